@@ -1,0 +1,101 @@
+/*
+ * FP64 CPU oracle of the two-way continuous collision handling step.
+ *
+ * TEST INFRASTRUCTURE. Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark load this library. The HIP product path never
+ * includes this header, links this library, or shares code with it.
+ *
+ * What it computes: Alg. 1 of the paper (the two-way method) with the backward
+ * step of Sec. 4 (LCP of Eq. eqn:LCP, linearised at x^(l), one projected
+ * multi-colour Gauss-Seidel sweep, volume-based contact constraints of
+ * Sec. 4.1, soft unilateral edge-length constraints of Sec. 4.2) and the forward
+ * step of Sec. 5 (Eq. eq:forward2 with per-vertex bounds D_i). Readings where the
+ * paper is silent are listed in the design notes of the repository and in the
+ * comments of cc_oracle.c.
+ *
+ * Arrays are row-major: x[3*i+k], tris[3*f+k], edges[2*e+k].
+ * Parity unpinned: the edge-edge volume constraint, the degenerate fallbacks and
+ * the colouring priority are readings, not formulas printed in the paper.
+ */
+#ifndef CC_ORACLE_H
+#define CC_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orc_params {
+  double delta;      /* activation threshold (Table 2: 1 mm) */
+  double d_min;      /* proximity search lower bound (Table 2: 2 mm) */
+  double d_max;      /* proximity search upper bound (Table 2: 4 mm) */
+  double sigma;      /* edge violation ratio limit (Table 2: 1.1) */
+  double gamma;      /* damping factor on movement (Table 2: 0.9) */
+  double eps;        /* termination threshold on ||r||_inf (Table 2: 1e-4) */
+  double kappa;      /* near-degenerate test for the volume form (reading) */
+  int32_t max_iters; /* L */
+  int32_t gs_sweeps; /* Gauss-Seidel sweeps per backward step (Sec. 4.3.1: 1) */
+  int32_t max_colors;/* colour palette size (<= 1024) */
+  int32_t edge_len;  /* 1: edge-length constraints on (Sec. 4.2) */
+  uint64_t seed;     /* colouring priority seed */
+} orc_params;
+
+typedef struct orc_iter {
+  int32_t searched;      /* proximity search ran this iteration */
+  int32_t n_colors;      /* colours of the contact rows */
+  int64_t n_p;           /* |P| evaluated by the pair pass */
+  int64_t n_pf;          /* |P'| = pairs with d < D^(l) */
+  int64_t n_a;           /* |A| = pairs with d < delta */
+  int64_t ccd_fail;      /* pairs in P' whose motion bound did not certify the piece */
+  double d_before;       /* D^(l) used by the pair pass */
+  double d_after;        /* D^(l+1) */
+  double move_max;       /* max_i ||x_i^(l+1) - x_i^(l)|| */
+  double r_inf;          /* ||r^(l+1)||_inf */
+  uint64_t fp_pf, fp_a, fp_col; /* order-independent set fingerprints */
+} orc_iter;
+
+typedef struct orc_scene orc_scene;
+
+/* Create a scene. w: inverse masses (N); tris (F,3); edges (E,2). Copies all. */
+orc_scene* orc_create(int32_t n, const double* w, const int32_t* tris, int32_t nt,
+                      const int32_t* edges, int32_t ne, const orc_params* p);
+void orc_destroy(orc_scene* s);
+/* Alg. 1 initialisation: x <- x^[k], y <- y^[k+1], D <- 0, r <- 1, P <- empty. */
+int orc_begin(orc_scene* s, const double* x_prev, const double* x_tilde);
+/* One iteration of the loop of Alg. 1. Returns 1 if the stop test holds, 0 if not,
+ * <0 on error. */
+int orc_iterate(orc_scene* s, orc_iter* info);
+/* Full step: iterate until the stop test or max_iters. Returns iterations run. */
+int orc_run(orc_scene* s, double* x_out, orc_iter* trace, int32_t trace_cap);
+
+/* State access (lockstep checks). */
+void orc_get_state(const orc_scene* s, double* x, double* y, double* r, double* D);
+int orc_set_state(orc_scene* s, const double* x, const double* y, const double* r,
+                  double D, const uint64_t* P, int64_t nP);
+int64_t orc_get_P(const orc_scene* s, uint64_t* out, int64_t cap);
+int64_t orc_get_A(const orc_scene* s, uint64_t* keys, int32_t* colors, int64_t cap);
+void orc_get_Di(const orc_scene* s, double* out);
+
+/* Building blocks (pinned individually by the tests). */
+double orc_pt_tri_d2(const double* p, const double* a, const double* b,
+                     const double* c, double* bary);
+double orc_seg_seg_d2(const double* a, const double* b, const double* c,
+                      const double* e, double* st);
+/* Contact row at state x for pair key: vertex ids v[4], c0, J[12], invA.
+ * Returns 0 for the volume form, 1 for the gap fallback, 2 if inactive. */
+int orc_contact_row(const orc_scene* s, const double* x, uint64_t key,
+                    int32_t* v, double* c0, double* J, double* inv_a);
+/* Proximity search: every pair of the universe with d < dmax at state x.
+ * brute != 0 uses the all-pairs loop instead of the grid. Result sorted by key. */
+int64_t orc_search(orc_scene* s, const double* x, double dmax, int brute,
+                   uint64_t* out, int64_t cap);
+/* Jones-Plassmann colouring of rows with vertex lists rv[4*r] (-1 = none);
+ * conflicts through vertices with w > 0. Returns the number of colours, <0 error. */
+int32_t orc_color_rows(const orc_scene* s, int64_t nrows, const int32_t* rv,
+                       const uint64_t* keys, int32_t* colors);
+uint64_t orc_mix64(uint64_t z);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

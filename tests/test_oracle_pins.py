@@ -1,0 +1,444 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself:
+exact rational minimisation, closed forms derived from the constraint
+definitions (Sec. 4.1, Sec. 4.2), the greedy-order characterisation of
+Jones-Plassmann colouring, brute-force sets, and the safety lemma of Sec. 5
+checked in exact arithmetic."""
+from fractions import Fraction as Fr
+import math
+
+import numpy as np
+import pytest
+
+import exact
+import oracle
+import scenes
+
+DELTA = 1e-3
+
+
+def rel_close(a, b, rtol=1e-12, atol=1e-30):
+    return abs(float(a) - float(b)) <= atol + rtol * abs(float(b))
+
+
+# ------------------------------------------------------------------ distances
+
+def _rand_pts(rng, k, scale=0.01):
+    return [rng.normal(size=3) * scale for _ in range(k)]
+
+
+def test_pt_tri_distance_matches_exact_rational():
+    rng = np.random.default_rng(1)
+    for trial in range(300):
+        p, a, b, c = _rand_pts(rng, 4)
+        if trial % 5 == 0:  # point close to the triangle plane
+            n = np.cross(b - a, c - a)
+            p = a + 0.3 * (b - a) + 0.2 * (c - a) + n / np.linalg.norm(n) * 1e-4
+        d2, bary = oracle.pt_tri_d2(p, a, b, c)
+        ex = exact.pt_tri_d2(p, a, b, c)
+        assert rel_close(d2, ex, rtol=1e-10, atol=1e-24), (trial, d2, float(ex))
+        q = bary[0] * a + bary[1] * b + bary[2] * c
+        assert abs(bary.sum() - 1) < 1e-12 and (bary >= -1e-15).all()
+        assert rel_close(np.dot(p - q, p - q), d2, rtol=1e-9, atol=1e-24)
+
+
+def test_pt_tri_degenerate_triangles():
+    p = np.array([0.3, 0.4, 0.1])
+    a = np.array([0.0, 0, 0])
+    b = np.array([1.0, 0, 0])
+    for c in (np.array([2.0, 0, 0]), a.copy(), np.array([0.5, 0, 0])):
+        d2, _ = oracle.pt_tri_d2(p, a, b, c)
+        assert rel_close(d2, exact.pt_tri_d2(p, a, b, c))
+    # all three corners coincide
+    d2, _ = oracle.pt_tri_d2(p, a, a, a)
+    assert rel_close(d2, np.dot(p, p))
+
+
+def test_vertex_over_triangle_interior_is_height():
+    a, b, c = np.array([0.0, 0, 0]), np.array([1.0, 0, 0]), np.array([0.0, 1, 0])
+    for h in (1e-3, 0.25, -0.5):
+        d2, bary = oracle.pt_tri_d2(np.array([0.25, 0.25, h]), a, b, c)
+        assert d2 == h * h
+        assert np.allclose(bary, [0.5, 0.25, 0.25])
+
+
+def test_seg_seg_distance_matches_exact_rational():
+    rng = np.random.default_rng(2)
+    for trial in range(300):
+        a, b, c, e = _rand_pts(rng, 4)
+        if trial % 7 == 0:  # parallel
+            e = c + (b - a) * 0.7
+        if trial % 11 == 0:  # collinear overlapping
+            c = a + 0.3 * (b - a)
+            e = a + 1.4 * (b - a)
+        if trial % 13 == 0:  # zero-length segment
+            e = c.copy()
+        d2, st = oracle.seg_seg_d2(a, b, c, e)
+        ex = exact.seg_seg_d2(a, b, c, e)
+        assert rel_close(d2, ex, rtol=1e-10, atol=1e-24), (trial, d2, float(ex))
+        p = a + st[0] * (b - a)
+        q = c + st[1] * (e - c)
+        assert rel_close(np.dot(p - q, p - q), d2, rtol=1e-9, atol=1e-24)
+
+
+def test_perpendicular_crossing_segments_offset():
+    d2, st = oracle.seg_seg_d2([-1.0, 0, 0], [1.0, 0, 0], [0.0, -1, 0.125], [0.0, 1, 0.125])
+    assert d2 == 0.125 ** 2 and np.allclose(st, [0.5, 0.5])
+
+
+# -------------------------------------------------------------- constraints
+
+def _scene(n, w=None, tris=(), edges=(), **kw):
+    w = np.ones(n) if w is None else np.asarray(w, float)
+    return oracle.Scene(w, np.asarray(tris, np.int32).reshape(-1, 3),
+                        np.asarray(edges, np.int32).reshape(-1, 2), **kw)
+
+
+def _fd_grad(f, x, idx, h=1e-9):
+    g = np.zeros((4, 3))
+    for i, v in enumerate(idx):
+        for k in range(3):
+            xp = x.copy(); xm = x.copy()
+            xp[v, k] += h; xm[v, k] -= h
+            g[i, k] = (f(xp) - f(xm)) / (2 * h)
+    return g
+
+
+def _ref_volume_ratio(xs_ref):
+    """V(y)/V(r) - 1 for fixed reference corners, via numpy's determinant."""
+    r = np.asarray(xs_ref)
+    vr = np.linalg.det(np.stack([r[1] - r[0], r[2] - r[0], r[3] - r[0]]))
+    return lambda ys: np.linalg.det(np.stack([ys[1] - ys[0], ys[2] - ys[0], ys[3] - ys[0]])) / vr - 1
+
+
+def test_vt_volume_constraint_closed_form_and_gradient():
+    rng = np.random.default_rng(3)
+    s = _scene(4, tris=[(1, 2, 3)], delta=DELTA)
+    checked = 0
+    for trial in range(200):
+        tri = rng.normal(size=(3, 3)) * 0.01
+        n = np.cross(tri[1] - tri[0], tri[2] - tri[0]); n /= np.linalg.norm(n)
+        bc = rng.dirichlet([1, 1, 1]) * (1.3 if trial % 3 == 0 else 1.0) - (0.1 if trial % 3 == 0 else 0)
+        p = bc @ tri + n * rng.uniform(-1, 1) * 0.8e-3
+        x = np.vstack([p, tri])
+        d = math.sqrt(exact.pt_tri_d2(p, *tri))
+        if not d < DELTA:
+            continue
+        row = s.contact_row(x, oracle.vt_key(0, 0))
+        assert row["kind"] == 0
+        h = abs(np.dot(p - tri[0], n))
+        # c0 = V(x)/V(r) - 1 = |h| / (|h| + delta - d) - 1 (derived from the definition of r)
+        assert rel_close(row["c0"] + 1, h / (h + DELTA - d), rtol=1e-7, atol=1e-12)
+        # gradient: finite differences of the volume ratio with the reference held fixed;
+        # r from the paper's definition with the closest point and side of x
+        side = 1.0 if np.dot(p - tri[0], n) >= 0 else -1.0
+        g = 0.5 * (DELTA - d)
+        ref = [p + g * side * n] + [t - g * side * n for t in tri]
+        fd = _fd_grad(_ref_volume_ratio(ref), x, [0, 1, 2, 3], h=1e-7)
+        assert np.allclose(row["J"], fd, rtol=1e-5, atol=1e-6 * np.abs(fd).max())
+        # the vertex is pushed to x's side of the triangle
+        assert np.dot(row["J"][0], side * n) > 0
+        # A = sum_v w_v |J_v|^2 with unit masses
+        assert rel_close(1 / row["inv_a"], (row["J"] ** 2).sum(), rtol=1e-12)
+        checked += 1
+    assert checked > 100
+
+
+def test_ee_volume_constraint_closed_form_and_gradient():
+    rng = np.random.default_rng(4)
+    s = _scene(4, edges=[(0, 1), (2, 3)], delta=DELTA)
+    checked = 0
+    for trial in range(200):
+        a = rng.normal(size=3) * 0.01
+        d1 = rng.normal(size=3) * 0.01
+        d2 = rng.normal(size=3) * 0.01
+        m = np.cross(d1, d2); m /= np.linalg.norm(m)
+        s0, t0 = rng.uniform(0, 1, 2)
+        off = m * rng.uniform(-1, 1) * 0.9e-3
+        c = a + s0 * d1 - t0 * d2 - off
+        x = np.vstack([a, a + d1, c, c + d2])
+        d = math.sqrt(exact.seg_seg_d2(*x))
+        if not d < DELTA:
+            continue
+        row = s.contact_row(x, oracle.ee_key(0, 1))
+        assert row["kind"] == 0
+        h = abs(np.dot(x[0] - x[2], m))
+        assert rel_close(row["c0"] + 1, h / (h + DELTA - d), rtol=1e-7, atol=1e-12)
+        side = 1.0 if np.dot(x[0] - x[2], m) >= 0 else -1.0
+        g = 0.5 * (DELTA - d)
+        ref = [x[0] + g * side * m, x[1] + g * side * m, x[2] - g * side * m, x[3] - g * side * m]
+        fd = _fd_grad(_ref_volume_ratio(ref), x, [0, 1, 2, 3], h=1e-7)
+        assert np.allclose(row["J"], fd, rtol=1e-5, atol=1e-6 * np.abs(fd).max())
+        checked += 1
+    assert checked > 100
+
+
+def test_gap_fallback_for_parallel_edges_and_static_triangle():
+    s = _scene(4, w=[1, 1, 0, 0], edges=[(0, 1), (2, 3)], delta=DELTA)
+    x = np.array([[0, 0, 0.4e-3], [0.01, 0, 0.4e-3], [0.002, 0, 0], [0.008, 0, 0]], float)
+    row = s.contact_row(x, oracle.ee_key(0, 1))
+    assert row["kind"] == 1
+    assert rel_close(row["c0"], 0.4e-3 / DELTA - 1)
+    u = np.array([0, 0, 1.0])
+    assert np.allclose(row["J"].sum(axis=0), 0, atol=1e-9)
+    assert np.dot(row["J"][0] + row["J"][1], u) > 0
+    # closed form: J_a + J_b = u/delta (the segment-1 weights sum to one)
+    assert np.allclose(row["J"][0] + row["J"][1], u / DELTA)
+
+
+def test_vt_static_triangle_interior_closed_form():
+    # free vertex above the interior of a static triangle: c0 = d/(d + delta - d) - 1 and
+    # J_a = n / (delta) * (|N| / |N|) ... i.e. J_a . n = 1/delta
+    s = _scene(4, w=[1, 0, 0, 0], tris=[(1, 2, 3)], delta=DELTA)
+    for hgt in (1e-5, 3e-4, 9e-4):
+        x = np.array([[0.2, 0.2, hgt], [0, 0, 0], [1, 0, 0], [0, 1, 0]], float)
+        row = s.contact_row(x, oracle.vt_key(0, 0))
+        assert rel_close(row["c0"], hgt / DELTA - 1, rtol=1e-9)
+        assert rel_close(row["J"][0, 2], 1 / DELTA, rtol=1e-9)
+        assert abs(row["J"][0, 0]) < 1e-9 and abs(row["J"][0, 1]) < 1e-9
+
+
+# ------------------------------------------------------------- search, colour
+
+def _two_patches(nx=3, spacing=5e-3, gap=3e-3, shift=(1.3e-3, 0.9e-3), move=8e-3,
+                 twist=0.0, seed=5):
+    xa, ta, ea = scenes.grid_cloth(nx, nx, spacing)
+    xb = xa.copy()
+    xb[:, 0] += shift[0]
+    xb[:, 1] += shift[1]
+    xb[:, 2] += gap
+    if twist:
+        c, s_ = math.cos(twist), math.sin(twist)
+        ctr = xb[:, :2].mean(axis=0)
+        d = xb[:, :2] - ctr
+        xb[:, :2] = ctr + d @ np.array([[c, s_], [-s_, c]])
+    x = np.vstack([xa, xb])
+    tris = np.vstack([ta, ta + len(xa)])
+    edges = np.vstack([ea, ea + len(xa)])
+    rng = np.random.default_rng(seed)
+    xt = x.copy()
+    xt[: len(xa), 2] += move
+    xt[len(xa):, 2] -= move
+    xt += rng.normal(size=xt.shape) * 2e-4
+    return x, xt, tris.astype(np.int32), edges.astype(np.int32)
+
+
+def _universe_keys(n, tris, edges):
+    keys = set()
+    for a in range(n):
+        for f, t in enumerate(tris):
+            if a not in t:
+                keys.add(oracle.vt_key(a, f))
+    for e in range(len(edges)):
+        for g in range(e + 1, len(edges)):
+            if not set(edges[e]) & set(edges[g]):
+                keys.add(oracle.ee_key(e, g))
+    return keys
+
+
+def test_search_grid_equals_brute_force_and_exact_threshold():
+    x, xt, tris, edges = _two_patches()
+    s = oracle.Scene(np.ones(len(x)), tris, edges)
+    for dmax in (2e-3, 4e-3, 6e-3):
+        g = set(int(k) for k in s.search(x, dmax))
+        b = set(int(k) for k in s.search(x, dmax, brute=True))
+        assert g == b
+        # independent check: universe built here, threshold decided in exact arithmetic
+        want = set()
+        for k in _universe_keys(len(x), tris, edges):
+            ee = k >> 63
+            a, f = (k >> 32) & 0x7FFFFFFF, k & 0xFFFFFFFF
+            v = [*edges[a], *edges[f]] if ee else [a, *tris[f]]
+            d2 = (exact.seg_seg_d2 if ee else exact.pt_tri_d2)(*(x[i] for i in v))
+            if d2 < Fr(dmax) * Fr(dmax):
+                want.add(k)
+        # sets may differ only on pairs whose distance is within rounding of dmax
+        for k in want ^ g:
+            ee = k >> 63
+            a, f = (k >> 32) & 0x7FFFFFFF, k & 0xFFFFFFFF
+            v = [*edges[a], *edges[f]] if ee else [a, *tris[f]]
+            d2 = float((exact.seg_seg_d2 if ee else exact.pt_tri_d2)(*(x[i] for i in v)))
+            assert abs(d2 - dmax * dmax) < 1e-12 * dmax * dmax
+
+
+def test_search_drops_all_static_pairs():
+    x, xt, tris, edges = _two_patches(gap=1e-3)
+    w = np.zeros(len(x))
+    s = oracle.Scene(w, tris, edges)
+    s.begin(x, x)
+    assert len(s.search(x, 4e-3)) == 0
+
+
+def _greedy_in_priority_order(rows, keys, w, seed):
+    """Sequential greedy colouring, rows taken in decreasing priority."""
+    prio = [oracle.mix64(int(k) ^ seed) for k in keys]
+    order = sorted(range(len(rows)), key=lambda r: -prio[r])
+    col = [-1] * len(rows)
+    used = {}
+    for r in order:
+        verts = [v for v in rows[r] if v >= 0 and w[v] > 0]
+        taken = set()
+        for v in verts:
+            taken |= used.get(v, set())
+        c = 0
+        while c in taken:
+            c += 1
+        col[r] = c
+        for v in verts:
+            used.setdefault(v, set()).add(c)
+    return col
+
+
+def test_jones_plassmann_equals_greedy_in_priority_order():
+    rng = np.random.default_rng(6)
+    n = 60
+    w = np.where(rng.uniform(size=n) < 0.8, 1.0, 0.0)
+    s = _scene(n, w=w)
+    for trial in range(20):
+        m = int(rng.integers(1, 400))
+        rows = rng.integers(0, n, size=(m, 4)).astype(np.int32)
+        rows[rng.uniform(size=(m, 4)) < 0.2] = -1
+        keys = rng.choice(2 ** 62, size=m, replace=False).astype(np.uint64)
+        col, nc = s.color(rows, keys)
+        ref = _greedy_in_priority_order(rows, keys, w, oracle.DEFAULTS["seed"])
+        assert list(col) == ref
+        assert nc == max(ref) + 1
+        # proper: rows sharing a free vertex differ
+        for v in range(n):
+            if w[v] == 0:
+                continue
+            cs = [col[r] for r in range(m) if v in rows[r]]
+            assert len(cs) == len(set(cs))
+
+
+# -------------------------------------------------------------- full step
+
+def test_vertex_through_static_triangle_settles_at_delta():
+    x = np.array([[0.2, 0.2, 0.005], [0, 0, 0], [1, 0, 0], [0, 1, 0]], float)
+    xt = x.copy()
+    xt[0, 2] = -0.005
+    s = oracle.Scene(np.array([1.0, 0, 0, 0]), [[1, 2, 3]], [[1, 2], [2, 3], [1, 3]], max_iters=100)
+    out, n, tr = s.run(x, xt, trace_cap=100)
+    assert abs(out[0, 2] - DELTA) < 1e-15  # the fixed point of the renewed linearisation
+    assert out[0, 2] > 0  # same side as x^t (Fig. fig:different_linearization)
+    assert np.array_equal(out[1:], x[1:])
+    assert tr[-1]["r_inf"] < 1e-4
+
+
+def test_free_flight_iteration_count_and_exact_target():
+    # one free vertex, nothing within D_max ever: every iteration moves 0.45 D_max
+    x = np.array([[0.0, 0, 0.5], [0, 0, 0], [1, 0, 0], [0, 1, 0]], float)
+    xt = x.copy()
+    S = 0.0137
+    xt[0, 0] += S
+    s = oracle.Scene(np.array([1.0, 0, 0, 0]), [[1, 2, 3]], [[1, 2], [2, 3], [1, 3]], max_iters=100)
+    out, n, tr = s.run(x, xt, trace_cap=100)
+    assert n == math.ceil(S / (0.45 * 4e-3))
+    assert np.array_equal(out, xt)
+    assert all(t["searched"] for t in tr)  # D drops to 0.1 D_max < D_min each time
+
+
+def test_static_input_returns_input_after_one_iteration():
+    x, xt, tris, edges = _two_patches(gap=3e-3)
+    s = oracle.Scene(np.ones(len(x)), tris, edges, max_iters=10)
+    out, n, tr = s.run(x, x, trace_cap=10)
+    assert n == 1 and np.array_equal(out, x)
+
+
+def test_single_row_projection_is_exact():
+    # one active row, static triangle: after the backward step the linearised
+    # constraint holds with equality (complementarity of the LCP, Eq. eqn:LCP)
+    x = np.array([[0.2, 0.2, 0.0005], [0, 0, 0], [1, 0, 0], [0, 1, 0]], float)
+    xt = x.copy()
+    xt[0, 2] = -0.004
+    s = oracle.Scene(np.array([1.0, 0, 0, 0]), [[1, 2, 3]], [[1, 2], [2, 3], [1, 3]], max_iters=1)
+    s.begin(x, xt)
+    s.iterate()
+    _, y, _, _ = s.state()
+    row = s.contact_row(x, oracle.vt_key(0, 0))
+    res = row["c0"] + sum(np.dot(row["J"][k], y[row["v"][k]] - x[row["v"][k]]) for k in range(4))
+    assert abs(res) < 1e-12
+    assert rel_close(y[0, 2], DELTA, rtol=1e-12)
+
+
+def test_edge_length_row_limits_stretch_to_sigma():
+    # vertex 0 pushed out of a static triangle; its short edge to free vertex 4 would
+    # stretch beyond sigma * L; the edge row pulls vertex 4 along
+    x = np.array([[0.2, 0.2, 0.0005], [0, 0, 0], [1, 0, 0], [0, 1, 0], [0.2, 0.2, 0.0015]], float)
+    xt = x.copy()
+    xt[0, 2] = -0.003
+    xt[4, 2] = -0.004  # target edge points along the coming push, L = 1 mm
+    s = oracle.Scene(np.array([1.0, 0, 0, 0, 1.0]), [[1, 2, 3]],
+                     [[1, 2], [2, 3], [1, 3], [0, 4]], max_iters=1)
+    s.begin(x, xt)
+    s.iterate()
+    _, y, _, _ = s.state()
+    e = xt[0] - xt[4]
+    g = e / np.dot(e, e)
+    assert rel_close(np.dot(g, y[0] - y[4]), 1.1, rtol=1e-12)
+
+
+def _safety_run(x, xt, tris, edges, w, iters, **kw):
+    s = oracle.Scene(w, tris, edges, max_iters=iters, **kw)
+    s.begin(x, xt)
+    U = _universe_keys(len(x), tris, edges)
+    traj = [x.copy()]
+    for l in range(iters):
+        X0, _, R0, D0 = s.state()
+        stop, it = s.iterate()
+        X1, _, R1, D1 = s.state()
+        Di = s.Di()
+        mv = np.linalg.norm(X1 - X0, axis=1)
+        # forward bound (Eq. eq:forward2) and r bookkeeping
+        assert (mv <= 0.45 * Di * (1 + 1e-12) + 1e-18).all()
+        assert ((R1 >= 0) & (R1 <= R0)).all()
+        assert D1 == it["d_before"] - 2 * it["move_max"]
+        # P' contains every pair below D^(l) (Sec. 3.1 reuse bound)
+        Pf = set(int(k) for k in s.P())
+        for k in U:
+            ee = k >> 63
+            a, f = (k >> 32) & 0x7FFFFFFF, k & 0xFFFFFFFF
+            v = [*edges[a], *edges[f]] if ee else [a, *tris[f]]
+            d2 = (exact.seg_seg_d2 if ee else exact.pt_tri_d2)(*(X0[i] for i in v))
+            D = Fr(it["d_before"])
+            if d2 < D * D * Fr(1 - 1e-12):
+                assert k in Pf
+            # the lemma of Sec. 5 in exact arithmetic: no vertex of the pair moved
+            # half the pair distance, so the linear piece stays in the free region
+            m2 = max(sum((Fr(float(X1[i, c])) - Fr(float(X0[i, c]))) ** 2 for c in range(3))
+                     for i in v)
+            assert 4 * m2 < d2
+        traj.append(X1)
+        if stop:
+            break
+    return traj, s
+
+
+@pytest.mark.parametrize("twist", [0.0, 0.7])
+def test_two_patches_pass_through_is_resolved_safely(twist):
+    x, xt, tris, edges = _two_patches(twist=twist)
+    traj, s = _safety_run(x, xt, tris, edges, np.ones(len(x)), iters=40)
+    xf = traj[-1]
+    assert not exact.mesh_self_intersects(xf, tris.tolist(), edges.tolist())
+    # the patches kept their order along z (linearisation at x, Sec. 4)
+    n = len(x) // 2
+    assert xf[:n, 2].mean() < xf[n:, 2].mean()
+
+
+def test_hair_like_polylines_stay_separated():
+    # two crossing polylines, one driven through the other
+    t = np.linspace(0, 1, 6)
+    la = np.stack([t * 0.02, np.zeros_like(t), np.zeros_like(t)], 1)
+    lb = np.stack([np.full_like(t, 0.01), t * 0.02 - 0.01, np.full_like(t, 2e-3)], 1)
+    x = np.vstack([la, lb])
+    edges = np.array([(i, i + 1) for i in range(5)] + [(6 + i, 7 + i) for i in range(5)], np.int32)
+    xt = x.copy()
+    xt[6:, 2] -= 6e-3
+    w = np.ones(len(x))
+    w[[0, 6]] = 0
+    xt[[0, 6]] = x[[0, 6]]
+    traj, s = _safety_run(x, xt, np.zeros((0, 3), np.int32), edges, w, iters=60)
+    xf = traj[-1]
+    for e in range(5):
+        for g in range(5, 10):
+            d2 = exact.seg_seg_d2(*(xf[i] for i in (*edges[e], *edges[g])))
+            assert d2 > 0
