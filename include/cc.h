@@ -1,0 +1,176 @@
+/*
+ * cc.h - C ABI of the MI355X two-way continuous collision handling step.
+ *
+ * The step (Alg. 1 of "Fast GPU-Based Two-Way Continuous Collision Handling")
+ * takes an intersection-free state x^t, a time-integrated target x~ and the mesh
+ * topology, and returns an intersection-free x^{t+1}. Inputs and output have the
+ * form the paper states for its collision handling module (an x^[k], y^[k+1]
+ * pair in, x^[k+1] out; Sec. 7.3). Every iteration runs:
+ *   - the proximity search when the reuse bound D has dropped below D_min
+ *     (Sec. 3.1): an LBVH over triangles and edges, boxes inflated by D_max/2,
+ *     exact FP64 distance filter d < D_max;
+ *   - the pair pass: distances at x^(l), P <- {d < D}, A <- {d < delta}, the
+ *     per-vertex bounds D_i (Sec. 5);
+ *   - the backward step: volume-based contact rows linearised at x^(l)
+ *     (Sec. 4, Sec. 4.1), coloured (Sec. 4.3), one projected Gauss-Seidel sweep,
+ *     then the soft unilateral edge-length rows (Sec. 4.2);
+ *   - the forward step (Eq. eq:forward2) and the reductions of Alg. 1;
+ *   - the path certificate of the new linear piece over P (lemma of Sec. 5).
+ *
+ * Conventions for every function below:
+ *   - Array arguments are DEVICE pointers unless the name ends in _host.
+ *     Positions are row-major xyz triples of float64 (x[3*i+k]); tris are int32
+ *     triples, edges int32 pairs. The caller owns every array it passes; the
+ *     library owns only the workspace inside cc_context / cc_solver.
+ *   - `stream` is a hipStream_t (NULL = the default stream). Work is stream
+ *     ordered; functions that return counts or statistics synchronise `stream`.
+ *   - Return value: CC_OK (0) or a negative error code (cc_strerror).
+ *     Reaching max_iters is not an error: the result is still safe (Sec. 3,
+ *     the method may always report x^(l+1)) and stats.status = CC_MAXITER.
+ *   - Not thread safe per context: one host thread per context at a time.
+ */
+#ifndef CC_H
+#define CC_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CC_OK = 0,
+  CC_EINVAL = -1,    /* bad argument: NULL pointer, negative size, out-of-range or
+                        repeated index in a primitive, NaN/Inf position, invalid
+                        parameter (d_min < delta, d_max <= d_min, gamma not in (0,1),
+                        sigma < 1, eps <= 0, max_iters < 1, gs_sweeps < 1) */
+  CC_ENOMEM = -2,    /* device allocation failed */
+  CC_EOVERFLOW = -3, /* pair capacity exceeded after regrowth */
+  CC_EHIP = -4,      /* HIP runtime error */
+  CC_ECOLOR = -5,    /* more colours needed than max_colors */
+  CC_ESTATE = -6     /* call out of order (e.g. iterate before begin) */
+};
+
+enum { CC_CONVERGED = 0, CC_MAXITER = 1 };
+
+/* flags */
+#define CC_EDGE_LEN 1u      /* edge-length constraints on (Sec. 4.2); default on */
+#define CC_TIME_KERNELS 2u  /* time kernel families with HIP events */
+#define CC_TRACE 4u         /* per-iteration set fingerprints */
+
+/* Parameters; defaults are Table 2 of the paper (cc_default_params). */
+typedef struct cc_params {
+  double delta;      /* activation threshold, 1e-3 m */
+  double d_min;      /* proximity search lower bound, 2e-3 m */
+  double d_max;      /* proximity search upper bound, 4e-3 m */
+  double sigma;      /* edge violation ratio limit, 1.1 */
+  double gamma;      /* damping factor on movement, 0.9 */
+  double eps;        /* termination threshold on ||r||_inf, 1e-4 */
+  double kappa;      /* near-parallel / near-degenerate threshold of the volume form */
+  int32_t max_iters; /* L: 512 (dt = 1/100 s) .. 2048 (dt = 1/20 s) */
+  int32_t gs_sweeps; /* Gauss-Seidel sweeps per backward step, 1 (Sec. 4.3.1) */
+  int32_t max_colors;/* colour palette, <= 1024 */
+  uint32_t flags;    /* CC_EDGE_LEN | CC_TIME_KERNELS | CC_TRACE */
+  uint64_t seed;     /* colouring priority seed */
+} cc_params;
+
+/* Per-iteration record (filled by cc_solver_iterate). Set fingerprints are
+ * wrapping sums of a 64-bit mix of each key, so they do not depend on order;
+ * they are computed only with CC_TRACE. */
+typedef struct cc_iter_info {
+  int32_t searched;
+  int32_t n_colors;
+  int64_t n_p;       /* |P| evaluated by the pair pass */
+  int64_t n_pf;      /* |P'| = {d < D} */
+  int64_t n_a;       /* |A| = {d < delta} */
+  int64_t ccd_fail;  /* pairs of P' whose motion bound did not certify the piece */
+  double d_before;
+  double d_after;
+  double move_max;
+  double r_inf;
+  uint64_t fp_pf, fp_a, fp_col;
+} cc_iter_info;
+
+/* Kernel families timed with CC_TIME_KERNELS. */
+enum {
+  CC_K_SEARCH = 0,   /* LBVH build + traversal */
+  CC_K_PAIR = 1,     /* pair pass */
+  CC_K_COLOR = 2,    /* colouring */
+  CC_K_GS = 3,       /* Gauss-Seidel colour passes (contacts and edges) */
+  CC_K_FORWARD = 4,  /* forward step + reductions */
+  CC_K_CERT = 5,     /* path certificate */
+  CC_K_COUNT = 6
+};
+
+typedef struct cc_stats {
+  int32_t iters;
+  int32_t searches;
+  int32_t status;        /* CC_CONVERGED or CC_MAXITER */
+  int32_t max_colors_used;
+  int64_t pair_updates;  /* sum over iterations of |P| in the pair pass */
+  int64_t row_updates;   /* sum over iterations of |A| + active edge rows, x sweeps */
+  int64_t ccd_fail;
+  double r_inf;
+  double kernel_ms[CC_K_COUNT];        /* with CC_TIME_KERNELS */
+  int64_t kernel_launches[CC_K_COUNT];
+  double kernel_bytes[CC_K_COUNT];     /* algorithmic bytes moved */
+} cc_stats;
+
+typedef struct cc_context cc_context;
+typedef struct cc_solver cc_solver;
+
+void cc_default_params(cc_params* p);
+const char* cc_strerror(int code);
+
+/* A context binds a device. Destroy releases every workspace. */
+int cc_context_create(int device, cc_context** out);
+void cc_context_destroy(cc_context* ctx);
+
+/* One collision-handling step: x_next <- TwoWay(x_prev, x_tilde). inv_mass (N)
+ * may be NULL (all ones); w = 0 marks static or pinned vertices (scaled lumped
+ * mass of Sec. 3; a global scale cancels). `edges` must list every triangle edge
+ * for complete edge-edge coverage. x_next must not alias an input. stats may be
+ * NULL. The context keeps its workspace between calls. */
+int cc_collide_step(cc_context* ctx, const double* x_prev, const double* x_tilde,
+                    const double* inv_mass, int32_t n_verts, const int32_t* tris,
+                    int32_t n_tris, const int32_t* edges, int32_t n_edges,
+                    const cc_params* params, double* x_next, cc_stats* stats,
+                    void* stream);
+
+/* ---- resident solver: the same step split into its phases ------------------
+ * A solver keeps one scene's topology, state (x, y, r, D, P) and workspace on
+ * the device. cc_collide_step is begin + iterate until stop + copy out. */
+int cc_solver_create(cc_context* ctx, int32_t n_verts, const double* inv_mass,
+                     const int32_t* tris, int32_t n_tris, const int32_t* edges,
+                     int32_t n_edges, const cc_params* params, cc_solver** out,
+                     void* stream);
+void cc_solver_destroy(cc_solver* s);
+/* Alg. 1 initialisation (x <- x^[k], y <- y^[k+1], D <- 0, r <- 1, P <- {}) and the
+ * edge-length rows at y^[k+1] with their colouring. */
+int cc_solver_begin(cc_solver* s, const double* x_prev, const double* x_tilde, void* stream);
+/* One loop iteration of Alg. 1. *stop = 1 when ||r||_inf < eps. info may be NULL. */
+int cc_solver_iterate(cc_solver* s, int32_t* stop, cc_iter_info* info, void* stream);
+/* Iterate until stop or max_iters; copy x to x_out (device). */
+int cc_solver_run(cc_solver* s, double* x_out, cc_stats* stats, void* stream);
+/* State access (device arrays of N*3, N*3, N; any may be NULL). */
+int cc_solver_get_state(cc_solver* s, double* x, double* y, double* r, double* D_host,
+                        void* stream);
+/* Replace the state and P (keys, device); used to check one iteration in lockstep. */
+int cc_solver_set_state(cc_solver* s, const double* x, const double* y, const double* r,
+                        double D, const uint64_t* P, int64_t n_p, void* stream);
+/* Sets of the last pair pass: P' keys, A keys with their colours, D_i. *n gets the
+ * size; nothing is written when cap is smaller. */
+int cc_solver_get_P(cc_solver* s, uint64_t* keys, int64_t cap, int64_t* n, void* stream);
+int cc_solver_get_A(cc_solver* s, uint64_t* keys, int32_t* colors, int64_t cap, int64_t* n,
+                    void* stream);
+int cc_solver_get_Di(cc_solver* s, double* out, void* stream);
+/* The proximity search alone at state x with bound dmax (LBVH + exact filter). */
+int cc_solver_search(cc_solver* s, const double* x, double dmax, uint64_t* keys, int64_t cap,
+                     int64_t* n, void* stream);
+/* Accumulated statistics since begin. */
+int cc_solver_stats(cc_solver* s, cc_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -29,8 +29,9 @@
  *    accumulated effect (Sec. 4: y initialised with y^(l)).
  *  - Constraints are coloured with Jones-Plassmann on the graph "shares a vertex
  *    with w > 0", priority = mix64(key ^ seed), smallest free colour (Sec. 4.3
- *    colours constraints, not vertices). Contacts are swept colour by colour,
- *    then edge-length rows colour by colour.
+ *    colours constraints, not vertices); the key of a contact is its pair key,
+ *    the key of an edge-length row its input edge index. Contacts are swept
+ *    colour by colour, then edge-length rows colour by colour.
  *  - Edge-edge contacts use the tetrahedron (a,b,c,e) in the volume form; near
  *    parallel edges and near degenerate triangles fall back to the gap
  *    constraint c = d/delta - 1 (the alternative named in Sec. 4.1).
@@ -68,6 +69,7 @@ struct orc_scene {
   double* move2;
   /* edge-length rows, fixed for the step */
   int32_t n_er;
+  int32_t* er_e;    /* input edge index of the row (its colouring key) */
   int32_t* er_v;    /* 2 per row */
   double* er_g;     /* 3 per row: (y_i - y_j)/L^2 at y^[k+1] */
   double* er_inv;   /* 1/A */
@@ -721,6 +723,7 @@ orc_scene* orc_create(int32_t n, const double* w, const int32_t* tris, int32_t n
   s->r = (double*)malloc(N * sizeof(double));
   s->Di = (double*)malloc(N * sizeof(double));
   s->move2 = (double*)malloc(N * sizeof(double));
+  s->er_e = (int32_t*)malloc((size_t)(ne > 0 ? ne : 1) * sizeof(int32_t));
   s->er_v = (int32_t*)malloc((size_t)(ne > 0 ? ne : 1) * 2 * sizeof(int32_t));
   s->er_g = (double*)malloc((size_t)(ne > 0 ? ne : 1) * 3 * sizeof(double));
   s->er_inv = (double*)malloc((size_t)(ne > 0 ? ne : 1) * sizeof(double));
@@ -733,7 +736,7 @@ void orc_destroy(orc_scene* s) {
   free(s->w); free(s->tris); free(s->edges); free(s->stat);
   free(s->x); free(s->y); free(s->xt); free(s->xold); free(s->r);
   free(s->Di); free(s->move2); free(s->P); free(s->A); free(s->acol);
-  free(s->er_v); free(s->er_g); free(s->er_inv); free(s->er_col);
+  free(s->er_e); free(s->er_v); free(s->er_g); free(s->er_inv); free(s->er_col);
   free(s);
 }
 
@@ -760,6 +763,7 @@ static int setup_edges(orc_scene* s) {
     double l2 = dot3(d, d);
     if (!(l2 > 0.0)) continue;
     int32_t r = s->n_er++;
+    s->er_e[r] = e;
     s->er_v[2 * r] = i;
     s->er_v[2 * r + 1] = j;
     double* g = s->er_g + 3 * r;
@@ -777,7 +781,7 @@ static int setup_edges(orc_scene* s) {
     rv[4 * r + 1] = s->er_v[2 * r + 1];
     rv[4 * r + 2] = -1;
     rv[4 * r + 3] = -1;
-    keys[r] = (uint64_t)r;
+    keys[r] = (uint64_t)s->er_e[r];
   }
   int32_t nc = orc_color_rows(s, s->n_er, rv, keys, s->er_col);
   free(rv);

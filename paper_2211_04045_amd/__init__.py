@@ -1,0 +1,208 @@
+"""MI355X two-way continuous collision handling (HIP, gfx950).
+
+The Python surface mirrors the C ABI of include/cc.h: a Context per device, a
+resident Solver per scene (begin / iterate / run / state access), and
+collide_step for one complete step. Arrays are torch tensors on the GPU:
+positions float64 (N,3), inverse masses float64 (N,), triangles int32 (F,3),
+edges int32 (E,2). All work runs in the HIP library on torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+from . import _lib
+from ._lib import CC_EDGE_LEN, CC_TIME_KERNELS, CC_TRACE, CCError, IterInfo, Params, Stats
+
+__all__ = ["Context", "Solver", "collide_step", "params", "CC_EDGE_LEN", "CC_TIME_KERNELS",
+           "CC_TRACE", "CCError"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check(rc, where):
+    if rc != 0:
+        raise CCError(rc, where)
+
+
+def _dev(t, dtype, shape_last=None, name="array"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(t)
+    if t.device.type != "cuda":
+        t = t.to("cuda")
+    t = t.to(dtype).contiguous()
+    if shape_last is not None and t.numel() and t.shape[-1] != shape_last:
+        raise ValueError(f"{name}: last dimension must be {shape_last}")
+    return t
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None and t.numel() else None
+
+
+def params(**over) -> Params:
+    """Defaults of Table 2 (cc_default_params) with keyword overrides."""
+    p = Params()
+    _lib.load().cc_default_params(C.byref(p))
+    for k, v in over.items():
+        if k == "edge_len":
+            p.flags = (p.flags | CC_EDGE_LEN) if v else (p.flags & ~CC_EDGE_LEN)
+        elif k == "time_kernels":
+            p.flags = (p.flags | CC_TIME_KERNELS) if v else (p.flags & ~CC_TIME_KERNELS)
+        elif k == "trace":
+            p.flags = (p.flags | CC_TRACE) if v else (p.flags & ~CC_TRACE)
+        else:
+            setattr(p, k, v)
+    return p
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.lib = _lib.load()
+        h = C.c_void_p()
+        _check(self.lib.cc_context_create(device, C.byref(h)), "cc_context_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.cc_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Solver:
+    """A resident scene: topology, state (x, y, r, D, P) and workspace on the GPU."""
+
+    def __init__(self, ctx: Context, w, tris, edges, **over):
+        torch = _torch()
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.w = _dev(w, torch.float64, name="w").reshape(-1)
+        self.tris = _dev(tris, torch.int32, 3, "tris").reshape(-1, 3)
+        self.edges = _dev(edges, torch.int32, 2, "edges").reshape(-1, 2)
+        self.n = self.w.numel()
+        self.p = params(**over)
+        h = C.c_void_p()
+        _check(self.lib.cc_solver_create(ctx.h, self.n, _ptr(self.w), _ptr(self.tris),
+                                         self.tris.shape[0], _ptr(self.edges),
+                                         self.edges.shape[0], C.byref(self.p), C.byref(h),
+                                         _stream()), "cc_solver_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.cc_solver_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def begin(self, x, xt):
+        torch = _torch()
+        self._x0 = _dev(x, torch.float64, 3, "x").reshape(-1, 3)
+        self._xt = _dev(xt, torch.float64, 3, "x_tilde").reshape(-1, 3)
+        _check(self.lib.cc_solver_begin(self.h, _ptr(self._x0), _ptr(self._xt), _stream()),
+               "cc_solver_begin")
+
+    def iterate(self):
+        stop = C.c_int32()
+        info = IterInfo()
+        _check(self.lib.cc_solver_iterate(self.h, C.byref(stop), C.byref(info), _stream()),
+               "cc_solver_iterate")
+        return bool(stop.value), info.as_dict()
+
+    def run(self, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty((self.n, 3), dtype=torch.float64, device="cuda")
+        st = Stats()
+        _check(self.lib.cc_solver_run(self.h, _ptr(out), C.byref(st), _stream()), "cc_solver_run")
+        return out, st.as_dict()
+
+    def stats(self):
+        st = Stats()
+        _check(self.lib.cc_solver_stats(self.h, C.byref(st)), "cc_solver_stats")
+        return st.as_dict()
+
+    def state(self):
+        torch = _torch()
+        x = torch.empty((self.n, 3), dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        r = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        D = C.c_double()
+        _check(self.lib.cc_solver_get_state(self.h, _ptr(x), _ptr(y), _ptr(r), C.byref(D),
+                                            _stream()), "cc_solver_get_state")
+        return x, y, r, D.value
+
+    def set_state(self, x, y, r, D, P):
+        torch = _torch()
+        x = _dev(x, torch.float64, 3, "x")
+        y = _dev(y, torch.float64, 3, "y")
+        r = _dev(r, torch.float64, name="r")
+        P = _dev(torch.as_tensor(P).view(torch.int64) if not isinstance(P, torch.Tensor) else P,
+                 torch.int64, name="P")
+        _check(self.lib.cc_solver_set_state(self.h, _ptr(x), _ptr(y), _ptr(r), float(D), _ptr(P),
+                                            P.numel(), _stream()), "cc_solver_set_state")
+
+    def P(self):
+        torch = _torch()
+        n = C.c_int64()
+        _check(self.lib.cc_solver_get_P(self.h, None, 0, C.byref(n), _stream()), "get_P")
+        out = torch.empty(n.value, dtype=torch.int64, device="cuda")
+        _check(self.lib.cc_solver_get_P(self.h, _ptr(out), n.value, C.byref(n), _stream()),
+               "get_P")
+        return out
+
+    def A(self):
+        torch = _torch()
+        n = C.c_int64()
+        _check(self.lib.cc_solver_get_A(self.h, None, None, 0, C.byref(n), _stream()), "get_A")
+        k = torch.empty(n.value, dtype=torch.int64, device="cuda")
+        c = torch.empty(n.value, dtype=torch.int32, device="cuda")
+        _check(self.lib.cc_solver_get_A(self.h, _ptr(k), _ptr(c), n.value, C.byref(n),
+                                        _stream()), "get_A")
+        return k, c
+
+    def Di(self):
+        torch = _torch()
+        out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        _check(self.lib.cc_solver_get_Di(self.h, _ptr(out), _stream()), "get_Di")
+        return out
+
+    def search(self, x, dmax):
+        torch = _torch()
+        x = _dev(x, torch.float64, 3, "x")
+        n = C.c_int64()
+        _check(self.lib.cc_solver_search(self.h, _ptr(x), float(dmax), None, 0, C.byref(n),
+                                         _stream()), "search")
+        out = torch.empty(n.value, dtype=torch.int64, device="cuda")
+        _check(self.lib.cc_solver_search(self.h, _ptr(x), float(dmax), _ptr(out), n.value,
+                                         C.byref(n), _stream()), "search")
+        return out
+
+
+def collide_step(ctx: Context, x, xt, w, tris, edges, **over):
+    """One complete two-way step; returns (x_next, stats)."""
+    torch = _torch()
+    x = _dev(x, torch.float64, 3, "x").reshape(-1, 3)
+    xt = _dev(xt, torch.float64, 3, "x_tilde").reshape(-1, 3)
+    w = _dev(w, torch.float64, name="w").reshape(-1)
+    tris = _dev(tris, torch.int32, 3, "tris").reshape(-1, 3)
+    edges = _dev(edges, torch.int32, 2, "edges").reshape(-1, 2)
+    p = params(**over)
+    out = torch.empty_like(x)
+    st = Stats()
+    _check(ctx.lib.cc_collide_step(ctx.h, _ptr(x), _ptr(xt), _ptr(w), x.shape[0], _ptr(tris),
+                                   tris.shape[0], _ptr(edges), edges.shape[0], C.byref(p),
+                                   _ptr(out), C.byref(st), _stream()), "cc_collide_step")
+    return out, st.as_dict()

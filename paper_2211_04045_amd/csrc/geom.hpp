@@ -1,0 +1,284 @@
+// Device geometry of the two-way collision step: distances, contact rows.
+//
+// Compiled with -ffp-contract=off: every expression below is evaluated as
+// written, left to right, in binary64 with correctly rounded sqrt and
+// division, so that the results do not depend on the compiler's choice of
+// fused operations. The operation order is the project's written geometry
+// specification; see the design notes.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cc {
+
+struct V3 {
+  double x, y, z;
+};
+
+__device__ __forceinline__ V3 ld3(const double* __restrict__ p, int32_t i) {
+  const double* q = p + 3 * (int64_t)i;
+  return V3{q[0], q[1], q[2]};
+}
+__device__ __forceinline__ void st3(double* __restrict__ p, int32_t i, V3 v) {
+  double* q = p + 3 * (int64_t)i;
+  q[0] = v.x;
+  q[1] = v.y;
+  q[2] = v.z;
+}
+__device__ __forceinline__ V3 vsub(V3 a, V3 b) { return V3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ double vdot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 vcross(V3 a, V3 b) {
+  return V3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+// u + s*v per component
+__device__ __forceinline__ V3 vaxpy(V3 u, double s, V3 v) {
+  return V3{u.x + s * v.x, u.y + s * v.y, u.z + s * v.z};
+}
+
+// |p - q|^2 for the closest point q of segment [u,v]; t its parameter.
+__device__ __forceinline__ double pt_seg_d2(V3 p, V3 u, V3 v, double& t) {
+  V3 uv = vsub(v, u);
+  V3 up = vsub(p, u);
+  double l2 = vdot(uv, uv);
+  double s = 0.0;
+  if (l2 > 0.0) {
+    s = vdot(up, uv) / l2;
+    if (s < 0.0) s = 0.0;
+    if (s > 1.0) s = 1.0;
+  }
+  V3 q = vaxpy(u, s, uv);
+  V3 d = vsub(p, q);
+  t = s;
+  return vdot(d, d);
+}
+
+// Point-triangle: interior projection candidate (when inside), then edges
+// (a,b), (b,c), (c,a); first strict minimum. bw = closest point weights.
+__device__ __forceinline__ double pt_tri_d2(V3 p, V3 a, V3 b, V3 c, double bw[3]) {
+  V3 ab = vsub(b, a), ac = vsub(c, a), ap = vsub(p, a);
+  V3 n = vcross(ab, ac);
+  double nn = vdot(n, n);
+  double best = __builtin_inf();
+  bw[0] = 1.0;
+  bw[1] = 0.0;
+  bw[2] = 0.0;
+  if (nn > 0.0) {
+    V3 t1 = vcross(ap, ac);
+    V3 t2 = vcross(ab, ap);
+    double wb = vdot(t1, n) / nn;
+    double wc = vdot(t2, n) / nn;
+    double wa = 1.0 - wb - wc;
+    if (wa >= 0.0 && wb >= 0.0 && wc >= 0.0) {
+      double h = vdot(ap, n);
+      best = h * h / nn;
+      bw[0] = wa;
+      bw[1] = wb;
+      bw[2] = wc;
+    }
+  }
+  double t, e2;
+  e2 = pt_seg_d2(p, a, b, t);
+  if (e2 < best) {
+    best = e2;
+    bw[0] = 1.0 - t;
+    bw[1] = t;
+    bw[2] = 0.0;
+  }
+  e2 = pt_seg_d2(p, b, c, t);
+  if (e2 < best) {
+    best = e2;
+    bw[0] = 0.0;
+    bw[1] = 1.0 - t;
+    bw[2] = t;
+  }
+  e2 = pt_seg_d2(p, c, a, t);
+  if (e2 < best) {
+    best = e2;
+    bw[0] = t;
+    bw[1] = 0.0;
+    bw[2] = 1.0 - t;
+  }
+  return best;
+}
+
+// Segment-segment: interior stationary point (non-parallel, inside the unit
+// square), then endpoint candidates a|ce, b|ce, c|ab, e|ab; first strict minimum.
+__device__ __forceinline__ double seg_seg_d2(V3 a, V3 b, V3 c, V3 e, double& bs, double& bt) {
+  V3 d1 = vsub(b, a), d2 = vsub(e, c), r = vsub(a, c);
+  double A = vdot(d1, d1), B = vdot(d1, d2), C = vdot(d2, d2);
+  double Dd = vdot(d1, r), Ee = vdot(d2, r);
+  double den = A * C - B * B;
+  double best = __builtin_inf();
+  bs = 0.0;
+  bt = 0.0;
+  if (den > 0.0) {
+    double s = (B * Ee - C * Dd) / den;
+    double t = (A * Ee - B * Dd) / den;
+    if (s >= 0.0 && s <= 1.0 && t >= 0.0 && t <= 1.0) {
+      V3 p = vaxpy(a, s, d1);
+      V3 q = vaxpy(c, t, d2);
+      V3 d = vsub(p, q);
+      best = vdot(d, d);
+      bs = s;
+      bt = t;
+    }
+  }
+  double u, e2;
+  e2 = pt_seg_d2(a, c, e, u);
+  if (e2 < best) { best = e2; bs = 0.0; bt = u; }
+  e2 = pt_seg_d2(b, c, e, u);
+  if (e2 < best) { best = e2; bs = 1.0; bt = u; }
+  e2 = pt_seg_d2(c, a, b, u);
+  if (e2 < best) { best = e2; bs = u; bt = 0.0; }
+  e2 = pt_seg_d2(e, a, b, u);
+  if (e2 < best) { best = e2; bs = u; bt = 1.0; }
+  return best;
+}
+
+// Pair keys: bit 63 = edge-edge; bits 62..32 = first primitive (vertex or
+// edge), bits 31..0 = second primitive (triangle or edge).
+constexpr uint64_t KEY_EE = 1ull << 63;
+__device__ __forceinline__ bool key_is_ee(uint64_t k) { return (k & KEY_EE) != 0; }
+__device__ __forceinline__ uint32_t key_a(uint64_t k) { return (uint32_t)((k >> 32) & 0x7fffffffu); }
+__device__ __forceinline__ uint32_t key_b(uint64_t k) { return (uint32_t)(k & 0xffffffffu); }
+
+struct Topo {
+  const int32_t* __restrict__ tris;
+  const int32_t* __restrict__ edges;
+};
+
+__device__ __forceinline__ void pair_verts(const Topo& T, uint64_t k, int32_t v[4]) {
+  uint32_t a = key_a(k), b = key_b(k);
+  if (key_is_ee(k)) {
+    v[0] = T.edges[2 * a];
+    v[1] = T.edges[2 * a + 1];
+    v[2] = T.edges[2 * b];
+    v[3] = T.edges[2 * b + 1];
+  } else {
+    v[0] = (int32_t)a;
+    v[1] = T.tris[3 * b];
+    v[2] = T.tris[3 * b + 1];
+    v[3] = T.tris[3 * b + 2];
+  }
+}
+
+__device__ __forceinline__ double pair_d2(bool ee, V3 p0, V3 p1, V3 p2, V3 p3) {
+  if (ee) {
+    double s, t;
+    return seg_seg_d2(p0, p1, p2, p3, s, t);
+  }
+  double bw[3];
+  return pt_tri_d2(p0, p1, p2, p3, bw);
+}
+
+// det[q1-q0, q2-q0, q3-q0]
+__device__ __forceinline__ double det4(V3 q0, V3 q1, V3 q2, V3 q3) {
+  V3 e1 = vsub(q1, q0), e2 = vsub(q2, q0), e3 = vsub(q3, q0);
+  return vdot(e1, vcross(e2, e3));
+}
+
+struct Row {
+  double c0;
+  double inv_a;  // 0 = inactive
+  V3 J[4];
+};
+
+// Contact row at x: volume form (Sec. 4.1: reference shape separated by delta,
+// c = V(x)/V(r) - 1, J = grad V(x) / V(r)), or the gap fallback
+// c = d/delta - 1, J_v = omega_v u / delta for near-parallel edges and near
+// degenerate triangles. w = inverse masses of the four vertices.
+__device__ __forceinline__ void contact_row(bool ee, const V3 xs[4], const double w[4],
+                                            double delta, double kappa2, Row& R) {
+  double om[4], d2, bw[3], s0 = 0.0, t0 = 0.0;
+  bool volume_ok;
+  V3 N;
+  double side;
+  if (ee) {
+    d2 = seg_seg_d2(xs[0], xs[1], xs[2], xs[3], s0, t0);
+    om[0] = 1.0 - s0;
+    om[1] = s0;
+    om[2] = -(1.0 - t0);
+    om[3] = -t0;
+    V3 d1v = vsub(xs[1], xs[0]), d2v = vsub(xs[3], xs[2]);
+    N = vcross(d1v, d2v);
+    double mm = vdot(N, N);
+    double l1 = vdot(d1v, d1v), l2 = vdot(d2v, d2v);
+    volume_ok = mm > kappa2 * (l1 * l2);
+    V3 ac = vsub(xs[0], xs[2]);
+    side = vdot(ac, N) >= 0.0 ? 1.0 : -1.0;
+  } else {
+    d2 = pt_tri_d2(xs[0], xs[1], xs[2], xs[3], bw);
+    om[0] = 1.0;
+    om[1] = -bw[0];
+    om[2] = -bw[1];
+    om[3] = -bw[2];
+    V3 e1 = vsub(xs[2], xs[1]), e2 = vsub(xs[3], xs[1]), e3 = vsub(xs[3], xs[2]);
+    N = vcross(e1, e2);
+    double nn = vdot(N, N);
+    double l = vdot(e1, e1), m2 = vdot(e2, e2), m3 = vdot(e3, e3);
+    if (m2 > l) l = m2;
+    if (m3 > l) l = m3;
+    volume_ok = nn > kappa2 * (l * l);
+    V3 ai = vsub(xs[0], xs[1]);
+    side = vdot(ai, N) >= 0.0 ? 1.0 : -1.0;
+  }
+  double d = sqrt(d2);
+  R.inv_a = 0.0;
+  if (volume_ok) {
+    double g = 0.5 * (delta - d);
+    double scale = side / sqrt(vdot(N, N));
+    V3 off = V3{g * (N.x * scale), g * (N.y * scale), g * (N.z * scale)};
+    V3 r0 = V3{xs[0].x + off.x, xs[0].y + off.y, xs[0].z + off.z};
+    V3 r1 = ee ? V3{xs[1].x + off.x, xs[1].y + off.y, xs[1].z + off.z}
+               : V3{xs[1].x - off.x, xs[1].y - off.y, xs[1].z - off.z};
+    V3 r2 = V3{xs[2].x - off.x, xs[2].y - off.y, xs[2].z - off.z};
+    V3 r3 = V3{xs[3].x - off.x, xs[3].y - off.y, xs[3].z - off.z};
+    double vr = det4(r0, r1, r2, r3);
+    if (vr == 0.0) return;
+    double vx = det4(xs[0], xs[1], xs[2], xs[3]);
+    R.c0 = vx / vr - 1.0;
+    V3 e1 = vsub(xs[1], xs[0]), e2 = vsub(xs[2], xs[0]), e3 = vsub(xs[3], xs[0]);
+    V3 G1 = vcross(e2, e3), G2 = vcross(e3, e1), G3 = vcross(e1, e2);
+    V3 G0 = V3{-((G1.x + G2.x) + G3.x), -((G1.y + G2.y) + G3.y), -((G1.z + G2.z) + G3.z)};
+    R.J[0] = V3{G0.x / vr, G0.y / vr, G0.z / vr};
+    R.J[1] = V3{G1.x / vr, G1.y / vr, G1.z / vr};
+    R.J[2] = V3{G2.x / vr, G2.y / vr, G2.z / vr};
+    R.J[3] = V3{G3.x / vr, G3.y / vr, G3.z / vr};
+  } else {
+    V3 diff;
+    if (ee) {
+      V3 d1v = vsub(xs[1], xs[0]), d2v = vsub(xs[3], xs[2]);
+      V3 p = vaxpy(xs[0], s0, d1v);
+      V3 q = vaxpy(xs[2], t0, d2v);
+      diff = vsub(p, q);
+    } else {
+      V3 p = V3{(bw[0] * xs[1].x + bw[1] * xs[2].x) + bw[2] * xs[3].x,
+                (bw[0] * xs[1].y + bw[1] * xs[2].y) + bw[2] * xs[3].y,
+                (bw[0] * xs[1].z + bw[1] * xs[2].z) + bw[2] * xs[3].z};
+      diff = vsub(xs[0], p);
+    }
+    double dd = sqrt(vdot(diff, diff));
+    if (dd == 0.0) return;
+    V3 u = V3{diff.x / dd, diff.y / dd, diff.z / dd};
+    R.c0 = d / delta - 1.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double co = om[i] / delta;
+      R.J[i] = V3{co * u.x, co * u.y, co * u.z};
+    }
+  }
+  double A = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) A = A + w[i] * vdot(R.J[i], R.J[i]);
+  R.inv_a = A > 0.0 ? 1.0 / A : 0.0;
+}
+
+// splitmix64 output function (Steele, Lea, Flood 2014); a bijection on 64 bits.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ uint64_t fp_key(uint64_t k) { return mix64(k ^ 0x6A09E667F3BCC909ull); }
+
+}  // namespace cc

@@ -234,15 +234,17 @@ def cloth_over_sphere(n: int = 33, spacing: float = 0.01, subdiv: int = 3,
 def folded_cloth(layer_rows: int = 64, cols: int | None = None,
                  spacing: float = 2.0 ** -8, gap: float = 2.0 ** -9,
                  amp_gaps: float = 5.0, wavelength: float = 0.08,
-                 seed: int = 1002):
+                 seed: int = 1002, noise_space: str = "world"):
     """A (4*layer_rows+1)-row cloth z-folded into 4 layers `gap` apart.
 
     Grid row r belongs to layer k = min(r // layer_rows, 3), u = r - k*layer_rows,
     at height z = k*gap and y = u*s (k even) or (layer_rows-u)*s (k odd).
-    x~ = x + A * (P_x, P_y, P_z), three independent seeded Perlin fields sampled in
-    the cloth's material (unfolded) coordinates at wavelength `wavelength`, so
-    stacked layers receive unrelated displacements and are driven through each
-    other. A = amp_gaps * gap.
+    x~ = x + A * (P_x, P_y, P_z), three independent seeded Perlin fields at
+    wavelength `wavelength`, A = amp_gaps * gap. noise_space "world" samples the
+    fields at the folded positions x (a smooth displacement field, the default);
+    "material" samples them at the unfolded grid coordinates, so stacked layers
+    receive unrelated displacements and are driven through each other (a stress
+    variant).
     """
     nv = 4 * layer_rows + 1
     nu = nv if cols is None else cols
@@ -257,8 +259,9 @@ def folded_cloth(layer_rows: int = 64, cols: int | None = None,
     offs = rng.uniform(0.0, 64.0, size=(3, 3))
     amp = amp_gaps * gap
     disp = np.zeros_like(x)
+    base = x if noise_space == "world" else uv
     for c in range(3):
-        q = uv / wavelength + offs[c]
+        q = base / wavelength + offs[c]
         disp[:, c] = amp * fields[c](q)
     xt = x + disp
     free = np.ones(len(x), bool)

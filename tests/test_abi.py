@@ -1,0 +1,46 @@
+"""The C-ABI library loads and exports every function include/cc.h declares
+(CPU only: nothing here launches a kernel)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "cc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(cc_\w+)\s*\(", src, re.M)))
+
+
+def test_header_declares_the_step_and_solver_api():
+    names = declared()
+    for n in ("cc_collide_step", "cc_context_create", "cc_solver_iterate", "cc_solver_search"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2211_04045_amd import _lib
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for n in declared():
+        assert hasattr(lib, n), n
+    assert sorted(_lib.EXPORTED) == declared()
+
+
+def test_default_params_are_table_2():
+    from paper_2211_04045_amd import params
+    p = params()
+    assert (p.delta, p.d_min, p.d_max, p.sigma, p.gamma, p.eps) == (1e-3, 2e-3, 4e-3, 1.1, 0.9, 1e-4)
+    assert p.gs_sweeps == 1 and p.max_colors == 1024
+    # the oracle's defaults are the same numbers (declared independently)
+    import oracle
+    for k in ("delta", "d_min", "d_max", "sigma", "gamma", "eps", "kappa", "gs_sweeps",
+              "max_colors", "seed"):
+        assert getattr(p, k) == oracle.DEFAULTS[k], k
+
+
+def test_strerror_names_every_code():
+    from paper_2211_04045_amd import _lib
+    lib = _lib.load()
+    for code in range(0, -7, -1):
+        assert lib.cc_strerror(code) != b"unknown error"
