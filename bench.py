@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # FETCH_SIZE / WRITE_SIZE scale from the plain copy kernel (see profiles/)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pair_pass.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_folded_cloth_257.json")
 
 
 def main():
@@ -36,11 +36,34 @@ def main():
     ap.add_argument("--small", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=3)
+    # serving stream (--config 5)
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--serve-steps", type=int, default=10)
+    ap.add_argument("--rate", type=float, default=None,
+                    help="Poisson arrival rate (requests/s); default: the frozen SERVE_RATE")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="measure the closed-batch capacity and print 0.7 of it as a rate")
+    ap.add_argument("--compare", type=int, default=24,
+                    help="requests served both one by one and as a closed batch")
+    ap.add_argument("--budget-gib", type=float, default=64.0)
+    # HBM traffic from rocprofv3 counters
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed steps, run one plain copy of known size (the "
+                         "scale reference for FETCH_SIZE / WRITE_SIZE)")
+    ap.add_argument("--digest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE) of "
+                         "a --copy-probe run into per-kernel HBM bytes per launch")
     args = ap.parse_args()
+    if args.digest_pmc:
+        digest_pmc(*args.digest_pmc)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; the multi-GPU sharding is a "
                                    "design note only", "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.config == 5:
+        serve_bench(args)
+        return
 
     import torch
 
@@ -82,6 +105,8 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     lat_ms = [a.elapsed_time(b) for a, b in lat]
+    if args.copy_probe:
+        copy_probe()
 
     iters = stats[-1]["iters"]
     pairs = sum(s["pair_updates"] for s in stats)
@@ -103,8 +128,10 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         try:
             tj = json.load(open(TRAFFIC_FILE))
-            if tj.get("kernel") == dom and tj.get("source_hash") == _src_hash():
-                traffic = tj.get("bytes_per_launch")
+            kname = {"pair": "k_pair_pass", "search": "k_traverse", "forward": "k_forward",
+                     "cert": "k_cert"}[dom]
+            if tj.get("source_hash") == _src_hash() and kname in tj.get("kernels", {}):
+                traffic = round(tj["kernels"][kname]["bytes_per_launch"])
         except Exception:
             traffic = None
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
@@ -149,10 +176,160 @@ def main():
     print(json.dumps(line))
 
 
+# Poisson arrival rate of the serving stream (requests/s), frozen from one
+# calibration run at 70% of the measured closed-batch capacity.
+SERVE_RATE = None
+
+
+def serve_bench(args):
+    """Serving stream: requests of mixed families and sizes (2K-150K triangles),
+    Poisson arrivals, admission by HBM budget, `serve_steps` consecutive steps per
+    request with the scene resident in between. Reports completed steps/s of the
+    stream, p50/p99 step latency (ready -> result back), and, on the first
+    `compare` requests, closed-batch served throughput against the plain
+    one-scene-at-a-time path."""
+    import torch
+
+    import paper_2211_04045_amd as cc
+    import scenes
+    from paper_2211_04045_amd import serve
+
+    torch.cuda.set_device(0)
+    ctx = cc.Context(0)
+    budget = int(args.budget_gib * (1 << 30))
+    t0 = time.perf_counter()
+    reqs = [scenes.serve_request(i) for i in range(args.requests)]
+    print(f"# generated {len(reqs)} requests in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    k = min(args.compare, len(reqs))
+    # warm-up: one small request through both paths
+    serve.run_alone(ctx, reqs[0], steps=1)
+    torch.cuda.synchronize()
+    # plain path: one scene after another, consecutive collide_step calls
+    t0 = time.perf_counter()
+    n_plain = 0
+    for i in range(k):
+        _, its = serve.run_alone(ctx, reqs[i], steps=args.serve_steps)
+        n_plain += len(its)
+    torch.cuda.synchronize()
+    plain = n_plain / (time.perf_counter() - t0)
+    print(f"# plain path: {plain:.2f} steps/s over {k} requests", file=sys.stderr, flush=True)
+    closed = serve.run_stream(ctx, reqs[:k], np.zeros(k), steps=args.serve_steps,
+                              budget_bytes=budget)
+    capacity = closed["steps"] / closed["wall"]
+    print(f"# closed batch: {capacity:.2f} steps/s", file=sys.stderr, flush=True)
+    if args.calibrate:
+        print(json.dumps({"calibrated_rate": round(0.7 * capacity / args.serve_steps, 4),
+                          "capacity_steps_per_s": round(capacity, 3)}))
+        return
+    rate = args.rate or SERVE_RATE or 0.7 * capacity / args.serve_steps
+    arr = scenes.poisson_arrivals(len(reqs), rate)
+    res = serve.run_stream(ctx, reqs, arr, steps=args.serve_steps, budget_bytes=budget)
+    lat = res["latency"] * 1e3
+    value = res["steps"] / res["wall"]
+    fam = np.bincount([r["family"] for r in reqs], minlength=4)[1:]
+    line = {
+        "metric": "collision-handling steps/sec + contact-pair updates/sec; p50/p99 step latency",
+        "value": round(value, 4),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": int(res["steps"]),
+        "warmup": 1,
+        "ms_per_step": round(1e3 * res["wall"] / res["steps"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"serving stream: {len(reqs)} requests x {args.serve_steps} "
+                               "steps, families cloth-over-sphere / folded cloth / stacked "
+                               "cubes, 2K-150K triangles log-uniform, Poisson arrivals",
+                   "requests_per_family": [int(v) for v in fam],
+                   "arrival_rate_per_s": round(rate, 4),
+                   "budget_gib": args.budget_gib,
+                   "parallelism": "single GPU"},
+        "pair_updates_per_s": round(float(res["pairs"].sum()) / res["wall"], 1),
+        "iterations_per_s": round(float(res["iters"].sum()) / res["wall"], 2),
+        "p50_ms": round(float(np.percentile(lat, 50)), 3),
+        "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "peak_resident_scenes": res["peak_resident"],
+        "peak_resident_gib": round(res["peak_bytes"] / (1 << 30), 3),
+        "closed_batch_steps_per_s": round(capacity, 3),
+        "plain_path_steps_per_s": round(plain, 3),
+        "served_over_plain": round(capacity / plain, 3),
+        "compare_requests": k,
+    }
+    print(json.dumps(line))
+
+
+COPY_PROBE_BYTES = 1 << 29  # bytes read (and written) by the copy probe
+
+
+def copy_probe():
+    """One plain elementwise copy, COPY_PROBE_BYTES read and written once."""
+    import torch
+    a = torch.rand(COPY_PROBE_BYTES // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+
+
+TRAFFIC_KERNELS = ("k_pair_pass", "k_traverse", "k_forward", "k_cert", "k_gs_contact")
+
+
+def digest_pmc(fetch_csv, write_csv):
+    """Per-kernel HBM bytes per launch from two counter runs of the same command.
+
+    FETCH_SIZE and WRITE_SIZE are read per dispatch (KiB) and summed over the
+    counter instances of each dispatch; each is divided by what the same counter
+    reads for the copy probe per byte it must move, so the result is in bytes of
+    the copy kernel's own accounting."""
+    import csv
+    from collections import defaultdict
+
+    def per_dispatch(path, counter):
+        vals = defaultdict(float)
+        names = {}
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name") != counter:
+                    continue
+                d = row["Dispatch_Id"]
+                vals[d] += float(row["Counter_Value"])
+                names[d] = row["Kernel_Name"]
+        return vals, names
+
+    out = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        vals, names = per_dispatch(path, counter)
+        copy = [vals[d] for d in vals if "elementwise" in names[d] or "mul" in names[d].lower()]
+        copy = [v for v in copy if v * 1024 > COPY_PROBE_BYTES / 2]
+        if not copy:
+            raise SystemExit(f"{path}: no copy-probe dispatch found")
+        scale = max(copy) * 1024 / COPY_PROBE_BYTES
+        for k in TRAFFIC_KERNELS:
+            ds = [d for d in vals if names[d].split("(")[0].strip().endswith(k)]
+            if not ds:
+                continue
+            e = out.setdefault(k, {"launches": len(ds)})
+            e[counter.lower() + "_bytes_per_launch"] = sum(vals[d] for d in ds) * 1024 / len(ds) / scale
+            e[counter.lower() + "_scale"] = scale
+    for k, e in out.items():
+        e["bytes_per_launch"] = e.get("fetch_size_bytes_per_launch", 0.0) + \
+            e.get("write_size_bytes_per_launch", 0.0)
+    res = {"source_hash": _src_hash(), "kernels": out,
+           "note": "rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, of bench.py --copy-probe; "
+                   "scaled by the copy probe's reading per byte moved"}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res))
+
+
 def _src_hash():
     import hashlib
     h = hashlib.sha1()
-    for f in ("step.hip", "geom.hpp"):
+    for f in ("step.hip", "geom.hpp", "lbvh.hip", "internal.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2211_04045_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:12]
 

@@ -15,7 +15,8 @@
  *     (Sec. 4, Sec. 4.1), coloured (Sec. 4.3), one projected Gauss-Seidel sweep,
  *     then the soft unilateral edge-length rows (Sec. 4.2);
  *   - the forward step (Eq. eq:forward2) and the reductions of Alg. 1;
- *   - the path certificate of the new linear piece over P (lemma of Sec. 5).
+ *   - the path certificate of the new linear piece over P (lemma of Sec. 5),
+ *     with a continuous test (coplanarity cubic) for pairs the bound misses.
  *
  * Conventions for every function below:
  *   - Array arguments are DEVICE pointers unless the name ends in _host.
@@ -48,7 +49,9 @@ enum {
   CC_EOVERFLOW = -3, /* pair capacity exceeded after regrowth */
   CC_EHIP = -4,      /* HIP runtime error */
   CC_ECOLOR = -5,    /* more colours needed than max_colors */
-  CC_ESTATE = -6     /* call out of order (e.g. iterate before begin) */
+  CC_ESTATE = -6,    /* call out of order (e.g. iterate before begin) */
+  CC_EAGAIN = -7,    /* admission would exceed the HBM budget; retry after a release */
+  CC_EBUSY = -8      /* the scene's step is still running */
 };
 
 enum { CC_CONVERGED = 0, CC_MAXITER = 1 };
@@ -84,6 +87,8 @@ typedef struct cc_iter_info {
   int64_t n_pf;      /* |P'| = {d < D} */
   int64_t n_a;       /* |A| = {d < delta} */
   int64_t ccd_fail;  /* pairs of P' whose motion bound did not certify the piece */
+  int64_t ccd_hits;  /* of those, pairs the continuous test (FP64 coplanarity cubic)
+                        finds within 1e-12 m along the piece */
   double d_before;
   double d_after;
   double move_max;
@@ -110,6 +115,7 @@ typedef struct cc_stats {
   int64_t pair_updates;  /* sum over iterations of |P| in the pair pass */
   int64_t row_updates;   /* sum over iterations of |A| + active edge rows, x sweeps */
   int64_t ccd_fail;
+  int64_t ccd_hits;
   double r_inf;
   double kernel_ms[CC_K_COUNT];        /* with CC_TIME_KERNELS */
   int64_t kernel_launches[CC_K_COUNT];
@@ -136,6 +142,53 @@ int cc_collide_step(cc_context* ctx, const double* x_prev, const double* x_tilde
                     int32_t n_tris, const int32_t* edges, int32_t n_edges,
                     const cc_params* params, double* x_next, cc_stats* stats,
                     void* stream);
+
+/* One scene of a batch (device pointers as in cc_collide_step). */
+typedef struct cc_scene {
+  const double* x_prev;
+  const double* x_tilde;
+  const double* inv_mass;  /* may be NULL (all ones) */
+  int32_t n_verts;
+  const int32_t* tris;
+  int32_t n_tris;
+  const int32_t* edges;
+  int32_t n_edges;
+  double* x_next;          /* output, must not alias the inputs */
+} cc_scene;
+
+/* One collision-handling step for each of n_scenes independent scenes of any
+ * sizes. Each scene's result equals the result of cc_collide_step on that scene
+ * alone. The scenes run concurrently on the device (one resident workspace and
+ * one library stream per scene slot, kept in the context between calls); the
+ * call returns when every scene is done, and `stream` is ordered after the work.
+ * stats (n_scenes entries) may be NULL. An error in any scene is returned (the
+ * first in scene order); the other scenes still complete. */
+int cc_collide_step_batched(cc_context* ctx, const cc_scene* scenes, int32_t n_scenes,
+                            const cc_params* params, cc_stats* stats, void* stream);
+
+/* ---- serving: resident scenes admitted by HBM budget ------------------------
+ * A resident scene keeps its topology, masses, current state x and workspace on
+ * the device between steps, so each step starts from the previous step's result.
+ * Steps of different scenes run concurrently (a worker pool with one stream per
+ * scene); a scene runs one step at a time. Handles are >= 0. */
+/* Budget in bytes for the workspaces of resident scenes (0 = unlimited). */
+int cc_context_set_budget(cc_context* ctx, size_t hbm_budget_bytes);
+/* Bytes a resident scene of this size reserves against the budget. */
+size_t cc_scene_bytes(int32_t n_verts, int32_t n_tris, int32_t n_edges);
+/* Admit a scene: copies x_prev (its state x^t), inverse masses and topology
+ * (scene->x_tilde and x_next are ignored). CC_EAGAIN when over budget. */
+int cc_scene_admit(cc_context* ctx, const cc_scene* scene, const cc_params* params,
+                   int32_t* handle);
+/* Start one step of the scene towards x_tilde (device, N*3) from its resident
+ * state. x_tilde must stay valid until cc_scene_poll reports completion.
+ * CC_EBUSY if the scene's previous step is still running. */
+int cc_scene_submit(cc_context* ctx, int32_t handle, const double* x_tilde);
+/* CC_OK when the last submitted step is done: x_next (device, may be NULL) gets the
+ * new state and stats (may be NULL) the step's statistics; CC_EBUSY while it runs;
+ * the step's error code if it failed. The resident state is the new x either way. */
+int cc_scene_poll(cc_context* ctx, int32_t handle, double* x_next, cc_stats* stats);
+/* Wait for the scene's step, then free its workspace and budget. */
+int cc_scene_release(cc_context* ctx, int32_t handle);
 
 /* ---- resident solver: the same step split into its phases ------------------
  * A solver keeps one scene's topology, state (x, y, r, D, P) and workspace on

@@ -33,7 +33,7 @@ class Params(C.Structure):
 class Iter(C.Structure):
     _fields_ = [("searched", C.c_int32), ("n_colors", C.c_int32), ("n_p", C.c_int64),
                 ("n_pf", C.c_int64), ("n_a", C.c_int64), ("ccd_fail", C.c_int64),
-                ("d_before", C.c_double), ("d_after", C.c_double),
+                ("ccd_hits", C.c_int64), ("d_before", C.c_double), ("d_after", C.c_double),
                 ("move_max", C.c_double), ("r_inf", C.c_double),
                 ("fp_pf", C.c_uint64), ("fp_a", C.c_uint64), ("fp_col", C.c_uint64)]
 
@@ -80,6 +80,8 @@ def _load():
     lib.orc_color_rows.restype = i32
     lib.orc_mix64.argtypes = [u64]
     lib.orc_mix64.restype = u64
+    lib.orc_ccd_hit.argtypes = [vp, vp, C.c_int, d, P(d)]
+    lib.orc_ccd_hit.restype = C.c_int
     _lib = lib
     return lib
 
@@ -114,6 +116,14 @@ def seg_seg_d2(a, b, c, e):
     d2 = _load().orc_seg_seg_d2(_ptr(_f64(a)), _ptr(_f64(b)), _ptr(_f64(c)),
                                 _ptr(_f64(e)), _ptr(st))
     return d2, st
+
+
+def ccd_hit(q, dq, ee: bool, eta: float = 1e-12):
+    """Continuous test of 4 points q (4,3) moving by dq (4,3) over t in [0,1]."""
+    t = C.c_double(-1.0)
+    hit = _load().orc_ccd_hit(_ptr(_f64(q).reshape(-1)), _ptr(_f64(dq).reshape(-1)), int(ee),
+                              eta, C.byref(t))
+    return bool(hit), t.value
 
 
 def vt_key(a: int, f: int) -> int:

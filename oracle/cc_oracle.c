@@ -48,6 +48,8 @@
 #include <string.h>
 
 #define KEY_EE (1ull << 63)
+/* distance at which the continuous test reports contact (metres) */
+#define ORC_CCD_ETA 1e-12
 
 struct orc_scene {
   int32_t n, nt, ne;
@@ -617,6 +619,103 @@ int64_t orc_search(orc_scene* s, const double* x, double dmax, int brute, uint64
   return kb.n;
 }
 
+/* ------------------------------------------------------------------- CCD */
+
+/* Continuous test of one pair along the linear piece q_k(t) = q_k + t dq_k,
+ * t in [0,1] (q in the tetrahedron order of the contact row: vertex then
+ * triangle, or edge 1 then edge 2). The four points are coplanar where
+ * V(t) = det[q1-q0, q2-q0, q3-q0](t) = 0, a cubic a3 t^3 + a2 t^2 + a1 t + a0.
+ * Its critical points split [0,1] into monotone pieces; a piece whose end values
+ * differ in sign is bisected to its root. At every root and critical point the
+ * primitives' distance is evaluated; the pair hits when it is <= eta.
+ * Returns 1 on a hit and stores the earliest such t. */
+static double cubic_at(const double* a, double t) { return ((a[3] * t + a[2]) * t + a[1]) * t + a[0]; }
+
+static int ccd_probe(const double* q, const double* dq, int ee, double t, double eta2) {
+  double p[4][3];
+  for (int k = 0; k < 4; ++k)
+    for (int m = 0; m < 3; ++m) p[k][m] = q[3 * k + m] + t * dq[3 * k + m];
+  double d2 = ee ? orc_seg_seg_d2(p[0], p[1], p[2], p[3], NULL)
+                 : orc_pt_tri_d2(p[0], p[1], p[2], p[3], NULL);
+  return d2 <= eta2;
+}
+
+int orc_ccd_hit(const double* q, const double* dq, int ee, double eta, double* t_hit) {
+  double e1[3], e2[3], e3[3], f1[3], f2[3], f3[3], c[3], a[4];
+  for (int m = 0; m < 3; ++m) {
+    e1[m] = q[3 + m] - q[m];
+    e2[m] = q[6 + m] - q[m];
+    e3[m] = q[9 + m] - q[m];
+    f1[m] = dq[3 + m] - dq[m];
+    f2[m] = dq[6 + m] - dq[m];
+    f3[m] = dq[9 + m] - dq[m];
+  }
+  double c23[3], f2e3[3], e2f3[3], f2f3[3];
+  cross3(c23, e2, e3);
+  cross3(f2e3, f2, e3);
+  cross3(e2f3, e2, f3);
+  cross3(f2f3, f2, f3);
+  a[0] = dot3(e1, c23);
+  a[1] = dot3(f1, c23) + dot3(e1, f2e3) + dot3(e1, e2f3);
+  a[2] = dot3(f1, f2e3) + dot3(f1, e2f3) + dot3(e1, f2f3);
+  a[3] = dot3(f1, f2f3);
+  (void)c;
+  /* knots: 0, critical points inside (0,1) in increasing order, 1 */
+  double knot[4];
+  int nk = 0;
+  knot[nk++] = 0.0;
+  double A = 3.0 * a[3], B = 2.0 * a[2], C = a[1];
+  double crit[2];
+  int nc = 0;
+  if (A == 0.0) {
+    if (B != 0.0) crit[nc++] = -C / B;
+  } else {
+    double disc = B * B - 4.0 * A * C;
+    if (disc >= 0.0) {
+      double sq = sqrt(disc);
+      double r1 = (-B - sq) / (2.0 * A), r2 = (-B + sq) / (2.0 * A);
+      crit[nc++] = r1 < r2 ? r1 : r2;
+      crit[nc++] = r1 < r2 ? r2 : r1;
+    }
+  }
+  for (int i = 0; i < nc; ++i)
+    if (crit[i] > 0.0 && crit[i] < 1.0 && crit[i] > knot[nk - 1]) knot[nk++] = crit[i];
+  knot[nk++] = 1.0;
+  const double eta2 = eta * eta;
+  for (int i = 0; i + 1 < nk; ++i) {
+    double lo = knot[i], hi = knot[i + 1];
+    double vlo = cubic_at(a, lo), vhi = cubic_at(a, hi);
+    double t = -1.0;
+    if (vlo == 0.0) {
+      t = lo;
+    } else if (vhi == 0.0) {
+      t = hi;
+    } else if ((vlo < 0.0) != (vhi < 0.0)) {
+      for (int it = 0; it < 64; ++it) {
+        double mid = 0.5 * (lo + hi);
+        double vm = cubic_at(a, mid);
+        if (vm == 0.0) {
+          lo = mid;
+          hi = mid;
+          break;
+        }
+        if ((vm < 0.0) == (vlo < 0.0)) lo = mid; else hi = mid;
+      }
+      t = 0.5 * (lo + hi);
+    }
+    if (t >= 0.0 && ccd_probe(q, dq, ee, t, eta2)) {
+      if (t_hit) *t_hit = t;
+      return 1;
+    }
+    /* a grazing contact leaves no sign change: probe the critical point too */
+    if (i + 2 < nk && ccd_probe(q, dq, ee, knot[i + 1], eta2)) {
+      if (t_hit) *t_hit = knot[i + 1];
+      return 1;
+    }
+  }
+  return 0;
+}
+
 /* ------------------------------------------------------------- colouring */
 
 /* Jones-Plassmann: in each round every uncoloured row whose priority is the
@@ -948,16 +1047,27 @@ int orc_iterate(orc_scene* s, orc_iter* info) {
 
   /* path certificate on P' along x^(l) -> x^(l+1): the piece is safe for a pair
    * when no vertex of it moved half the pair distance (lemma of Sec. 5) */
-  int64_t fail = 0;
+  int64_t fail = 0, hits = 0;
   for (int64_t q = 0; q < npf; ++q) {
     int32_t v[4];
     pair_verts(s, s->P[q], v);
     double mv = s->move2[v[0]];
     for (int k = 1; k < 4; ++k)
       if (s->move2[v[k]] > mv) mv = s->move2[v[k]];
-    if (!(4.0 * mv < dpf[q])) ++fail;
+    if (!(4.0 * mv < dpf[q])) {
+      /* not certified by the motion bound: continuous test of the piece */
+      ++fail;
+      double qq[12], dq[12];
+      for (int k = 0; k < 4; ++k)
+        for (int m = 0; m < 3; ++m) {
+          qq[3 * k + m] = s->xold[3 * v[k] + m];
+          dq[3 * k + m] = s->x[3 * v[k] + m] - s->xold[3 * v[k] + m];
+        }
+      if (orc_ccd_hit(qq, dq, (s->P[q] & KEY_EE) ? 1 : 0, ORC_CCD_ETA, NULL)) ++hits;
+    }
   }
   it.ccd_fail = fail;
+  it.ccd_hits = hits;
 
   s->D = D - 2.0 * mmax;
   it.d_after = s->D;

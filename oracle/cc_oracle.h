@@ -47,6 +47,7 @@ typedef struct orc_iter {
   int64_t n_pf;          /* |P'| = pairs with d < D^(l) */
   int64_t n_a;           /* |A| = pairs with d < delta */
   int64_t ccd_fail;      /* pairs in P' whose motion bound did not certify the piece */
+  int64_t ccd_hits;      /* of those, pairs the continuous test finds in contact */
   double d_before;       /* D^(l) used by the pair pass */
   double d_after;        /* D^(l+1) */
   double move_max;       /* max_i ||x_i^(l+1) - x_i^(l)|| */
@@ -94,6 +95,9 @@ int64_t orc_search(orc_scene* s, const double* x, double dmax, int brute,
 int32_t orc_color_rows(const orc_scene* s, int64_t nrows, const int32_t* rv,
                        const uint64_t* keys, int32_t* colors);
 uint64_t orc_mix64(uint64_t z);
+/* Continuous test of a pair along q_k + t dq_k, t in [0,1] (q, dq: 4 points in the
+ * contact-row order). Returns 1 when the primitives come within eta. */
+int orc_ccd_hit(const double* q, const double* dq, int ee, double eta, double* t_hit);
 
 #ifdef __cplusplus
 }

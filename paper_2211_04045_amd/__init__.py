@@ -11,9 +11,10 @@ from __future__ import annotations
 import ctypes as C
 
 from . import _lib
-from ._lib import CC_EDGE_LEN, CC_TIME_KERNELS, CC_TRACE, CCError, IterInfo, Params, Stats
+from ._lib import (CC_EDGE_LEN, CC_TIME_KERNELS, CC_TRACE, CCError, IterInfo, Params, SceneDesc,
+                   Stats)
 
-__all__ = ["Context", "Solver", "collide_step", "params", "CC_EDGE_LEN", "CC_TIME_KERNELS",
+__all__ = ["Context", "Solver", "Server", "collide_step", "collide_step_batched", "params", "CC_EDGE_LEN", "CC_TIME_KERNELS",
            "CC_TRACE", "CCError"]
 
 
@@ -206,3 +207,86 @@ def collide_step(ctx: Context, x, xt, w, tris, edges, **over):
                                    tris.shape[0], _ptr(edges), edges.shape[0], C.byref(p),
                                    _ptr(out), C.byref(st), _stream()), "cc_collide_step")
     return out, st.as_dict()
+
+
+def collide_step_batched(ctx: Context, scenes, **over):
+    """One step for each scene (dicts with x, xt, w, tris, edges); the scenes run
+    concurrently on the GPU. Returns a list of (x_next, stats)."""
+    torch = _torch()
+    keep, descs = [], (SceneDesc * max(len(scenes), 1))()
+    outs = []
+    for i, sc in enumerate(scenes):
+        x = _dev(sc["x"], torch.float64, 3, "x").reshape(-1, 3)
+        xt = _dev(sc["xt"], torch.float64, 3, "x_tilde").reshape(-1, 3)
+        w = _dev(sc["w"], torch.float64, name="w").reshape(-1)
+        tris = _dev(sc["tris"], torch.int32, 3, "tris").reshape(-1, 3)
+        edges = _dev(sc["edges"], torch.int32, 2, "edges").reshape(-1, 2)
+        out = torch.empty_like(x)
+        keep += [x, xt, w, tris, edges]
+        outs.append(out)
+        descs[i] = SceneDesc(_ptr(x), _ptr(xt), _ptr(w), x.shape[0], _ptr(tris), tris.shape[0],
+                             _ptr(edges), edges.shape[0], _ptr(out))
+    p = params(**over)
+    st = (Stats * max(len(scenes), 1))()
+    _check(ctx.lib.cc_collide_step_batched(ctx.h, descs, len(scenes), C.byref(p), st, _stream()),
+           "cc_collide_step_batched")
+    return [(outs[i], st[i].as_dict()) for i in range(len(scenes))]
+
+
+class Server:
+    """Resident scenes admitted against an HBM budget (cc_scene_* of the C ABI).
+
+    admit() returns a handle or None when the budget is full; submit() starts one
+    step towards x~ from the scene's resident state; poll() returns None while the
+    step runs, else (x_next, stats); release() frees the scene."""
+
+    def __init__(self, ctx: Context, budget_bytes: int = 0):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        _check(self.lib.cc_context_set_budget(ctx.h, int(budget_bytes)), "cc_context_set_budget")
+        self._keep = {}
+
+    def scene_bytes(self, n, nt, ne):
+        return int(self.lib.cc_scene_bytes(n, nt, ne))
+
+    def admit(self, x, w, tris, edges, **over):
+        torch = _torch()
+        x = _dev(x, torch.float64, 3, "x").reshape(-1, 3)
+        w = _dev(w, torch.float64, name="w").reshape(-1)
+        tris = _dev(tris, torch.int32, 3, "tris").reshape(-1, 3)
+        edges = _dev(edges, torch.int32, 2, "edges").reshape(-1, 2)
+        d = SceneDesc(_ptr(x), None, _ptr(w), x.shape[0], _ptr(tris), tris.shape[0],
+                      _ptr(edges), edges.shape[0], None)
+        p = params(**over)
+        h = C.c_int32()
+        rc = self.lib.cc_scene_admit(self.ctx.h, C.byref(d), C.byref(p), C.byref(h))
+        if rc == _lib.CC_EAGAIN:
+            return None
+        _check(rc, "cc_scene_admit")
+        self._keep[h.value] = [x.shape[0], None]
+        return h.value
+
+    def submit(self, h, xt):
+        torch = _torch()
+        xt = _dev(xt, torch.float64, 3, "x_tilde").reshape(-1, 3)
+        # the step reads x~ on the library's stream: finish torch's work first
+        torch.cuda.current_stream().synchronize()
+        self._keep[h][1] = xt
+        _check(self.lib.cc_scene_submit(self.ctx.h, h, _ptr(xt)), "cc_scene_submit")
+
+    def poll(self, h, out=None):
+        torch = _torch()
+        n = self._keep[h][0]
+        if out is None:
+            out = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+        torch.cuda.current_stream().synchronize()  # out may reuse memory torch still writes
+        st = Stats()
+        rc = self.lib.cc_scene_poll(self.ctx.h, h, _ptr(out), C.byref(st))
+        if rc == _lib.CC_EBUSY:
+            return None
+        _check(rc, "cc_scene_poll")
+        return out, st.as_dict()
+
+    def release(self, h):
+        _check(self.lib.cc_scene_release(self.ctx.h, h), "cc_scene_release")
+        self._keep.pop(h, None)

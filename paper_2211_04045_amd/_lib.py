@@ -20,7 +20,10 @@ K_NAMES = ["search", "pair", "color", "gs", "forward", "cert"]
 
 ERRORS = {0: "ok", -1: "invalid argument", -2: "device allocation failed",
           -3: "pair capacity exceeded", -4: "HIP runtime error",
-          -5: "colour palette exhausted", -6: "call out of order"}
+          -5: "colour palette exhausted", -6: "call out of order",
+          -7: "over the HBM budget", -8: "step still running"}
+CC_EAGAIN = -7
+CC_EBUSY = -8
 
 
 class CCError(RuntimeError):
@@ -39,7 +42,7 @@ class Params(C.Structure):
 class IterInfo(C.Structure):
     _fields_ = [("searched", C.c_int32), ("n_colors", C.c_int32), ("n_p", C.c_int64),
                 ("n_pf", C.c_int64), ("n_a", C.c_int64), ("ccd_fail", C.c_int64),
-                ("d_before", C.c_double), ("d_after", C.c_double), ("move_max", C.c_double),
+                ("ccd_hits", C.c_int64), ("d_before", C.c_double), ("d_after", C.c_double), ("move_max", C.c_double),
                 ("r_inf", C.c_double), ("fp_pf", C.c_uint64), ("fp_a", C.c_uint64),
                 ("fp_col", C.c_uint64)]
 
@@ -47,15 +50,22 @@ class IterInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class SceneDesc(C.Structure):
+    _fields_ = [("x_prev", C.c_void_p), ("x_tilde", C.c_void_p), ("inv_mass", C.c_void_p),
+                ("n_verts", C.c_int32), ("tris", C.c_void_p), ("n_tris", C.c_int32),
+                ("edges", C.c_void_p), ("n_edges", C.c_int32), ("x_next", C.c_void_p)]
+
+
 class Stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("searches", C.c_int32), ("status", C.c_int32),
                 ("max_colors_used", C.c_int32), ("pair_updates", C.c_int64),
-                ("row_updates", C.c_int64), ("ccd_fail", C.c_int64), ("r_inf", C.c_double),
+                ("row_updates", C.c_int64), ("ccd_fail", C.c_int64), ("ccd_hits", C.c_int64),
+                ("r_inf", C.c_double),
                 ("kernel_ms", C.c_double * 6), ("kernel_launches", C.c_int64 * 6),
                 ("kernel_bytes", C.c_double * 6)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_[:8]}
+        d = {k: getattr(self, k) for k, _ in self._fields_[:9]}
         d["kernels"] = {K_NAMES[i]: dict(ms=self.kernel_ms[i], launches=self.kernel_launches[i],
                                          bytes=self.kernel_bytes[i]) for i in range(6)}
         return d
@@ -82,6 +92,7 @@ def load():
         "cc_context_destroy": (None, [vp]),
         "cc_collide_step": (C.c_int, [vp, vp, vp, vp, i32, vp, i32, vp, i32, P(Params), vp,
                                       P(Stats), vp]),
+        "cc_collide_step_batched": (C.c_int, [vp, P(SceneDesc), i32, P(Params), P(Stats), vp]),
         "cc_solver_create": (C.c_int, [vp, i32, vp, vp, i32, vp, i32, P(Params), P(vp), vp]),
         "cc_solver_destroy": (None, [vp]),
         "cc_solver_begin": (C.c_int, [vp, vp, vp, vp]),
@@ -94,6 +105,12 @@ def load():
         "cc_solver_get_Di": (C.c_int, [vp, vp, vp]),
         "cc_solver_search": (C.c_int, [vp, vp, d, vp, i64, P(i64), vp]),
         "cc_solver_stats": (C.c_int, [vp, P(Stats)]),
+        "cc_context_set_budget": (C.c_int, [vp, C.c_size_t]),
+        "cc_scene_bytes": (C.c_size_t, [i32, i32, i32]),
+        "cc_scene_admit": (C.c_int, [vp, P(SceneDesc), P(Params), P(i32)]),
+        "cc_scene_submit": (C.c_int, [vp, i32, vp]),
+        "cc_scene_poll": (C.c_int, [vp, i32, vp, P(Stats)]),
+        "cc_scene_release": (C.c_int, [vp, i32]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -104,7 +121,8 @@ def load():
 
 
 EXPORTED = ["cc_default_params", "cc_strerror", "cc_context_create", "cc_context_destroy",
-            "cc_collide_step", "cc_solver_create", "cc_solver_destroy", "cc_solver_begin",
+            "cc_collide_step", "cc_collide_step_batched", "cc_solver_create", "cc_solver_destroy", "cc_solver_begin",
             "cc_solver_iterate", "cc_solver_run", "cc_solver_get_state",
             "cc_solver_set_state", "cc_solver_get_P", "cc_solver_get_A", "cc_solver_get_Di",
-            "cc_solver_search", "cc_solver_stats"]
+            "cc_solver_search", "cc_solver_stats", "cc_context_set_budget", "cc_scene_bytes",
+            "cc_scene_admit", "cc_scene_submit", "cc_scene_poll", "cc_scene_release"]

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcc.so")
-SOURCES = ["api.hip", "step.hip", "lbvh.hip"]
+SOURCES = ["api.hip", "step.hip", "lbvh.hip", "serve.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # every FP64 expression is evaluated as written (no fused multiply-add)
          "-ffp-contract=off",
@@ -29,7 +29,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     for p in procs:
         if p.wait() != 0:
             raise RuntimeError("hipcc failed")
-    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp", *objs]
+    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", LIB + ".tmp", *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -4,6 +4,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <thread>
 
 #include "internal.hpp"
 
@@ -66,12 +68,13 @@ int alloc_active(cc_solver* s, int64_t cap) {
 
 void solver_free(cc_solver* s) {
   dfree(s->w); dfree(s->tris); dfree(s->edges); dfree(s->stat);
-  dfree(s->x); dfree(s->y); dfree(s->xt); dfree(s->r); dfree(s->move2); dfree(s->Di);
+  dfree(s->x); dfree(s->y); dfree(s->xt); dfree(s->xold); dfree(s->r); dfree(s->move2); dfree(s->Di);
   free_pairs(s);
   free_active(s);
   dfree(s->eg); dfree(s->einv); dfree(s->ecol); dfree(s->eorder);
   dfree(s->elist0); dfree(s->elist1); dfree(s->elist2); dfree(s->lamE);
-  dfree(s->vmax0); dfree(s->vmax1); dfree(s->masks); dfree(s->col_cnt);
+  dfree(s->vmax0); dfree(s->vmax1); dfree(s->masks); dfree(s->col_cnt); dfree(s->rcnt);
+  dfree(s->coff_dev); dfree(s->ecoff_dev);
   bvh_free(s);
   dfree(s->dc);
   if (s->hc) hipHostFree(s->hc);
@@ -94,6 +97,7 @@ int solver_alloc(cc_solver* s) {
   CC_TRY(dalloc(&s->x, 3 * n));
   CC_TRY(dalloc(&s->y, 3 * n));
   CC_TRY(dalloc(&s->xt, 3 * n));
+  CC_TRY(dalloc(&s->xold, 3 * n));
   CC_TRY(dalloc(&s->r, n));
   CC_TRY(dalloc(&s->move2, n));
   CC_TRY(dalloc(&s->Di, n));
@@ -109,6 +113,9 @@ int solver_alloc(cc_solver* s) {
   CC_TRY(dalloc(&s->vmax1, n));
   CC_TRY(dalloc(&s->masks, n * kMaskWords));
   CC_TRY(dalloc(&s->col_cnt, kMaxColors + 1));
+  CC_TRY(dalloc(&s->rcnt, kMaxRounds + 1));
+  CC_TRY(dalloc(&s->coff_dev, kMaxColors + 1));
+  CC_TRY(dalloc(&s->ecoff_dev, kMaxColors + 1));
   CC_TRY(bvh_alloc(s));
   CC_TRY(dalloc(&s->dc, 1));
   if (hipHostMalloc((void**)&s->hc, sizeof(Counters), hipHostMallocDefault) != hipSuccess)
@@ -145,10 +152,37 @@ void resolve_timers(cc_solver* s) {
   s->timers.clear();
 }
 
+// Make `slot` a solver for this topology: reuse it when the sizes match (topology
+// and masses are copied in again), otherwise replace it.
+int bind_solver(cc_context* ctx, cc_solver*& slot, int32_t n, const double* inv_mass,
+                const int32_t* tris, int32_t nt, const int32_t* edges, int32_t ne,
+                const cc_params* params, void* stream) {
+  hipStream_t st = as_stream(stream);
+  cc_solver* s = slot;
+  if (s && s->n == n && s->nt == nt && s->ne == ne) {
+    s->p = *params;
+    s->kappa2 = params->kappa * params->kappa;
+    if (nt) CC_HIP(hipMemcpyAsync(s->tris, tris, sizeof(int32_t) * 3 * nt, hipMemcpyDefault, st));
+    if (ne) CC_HIP(hipMemcpyAsync(s->edges, edges, sizeof(int32_t) * 2 * ne, hipMemcpyDefault, st));
+    if (n) {
+      if (inv_mass)
+        CC_HIP(hipMemcpyAsync(s->w, inv_mass, sizeof(double) * n, hipMemcpyDefault, st));
+      else
+        CC_TRY(launch_fill_u64((unsigned long long*)s->w, n, d2bits(1.0), st));
+    }
+    return launch_validate(s, nullptr, nullptr, st);
+  }
+  if (s) cc_solver_destroy(s);
+  slot = nullptr;
+  CC_TRY(cc_solver_create(ctx, n, inv_mass, tris, nt, edges, ne, params, &s, stream));
+  slot = s;
+  return CC_OK;
+}
+
 int do_search(cc_solver* s, const double* x, double dmax, hipStream_t st) {
   for (int attempt = 0; attempt < 2; ++attempt) {
     int64_t n = 0;
-    CC_TRY(lbvh_search(s, x, dmax, s->P, nullptr, s->capP, &n, st));
+    CC_TRY(lbvh_search(s, x, dmax, s->P, s->capP, &n, st));
     if (n <= s->capP) {
       s->nP = n;
       return CC_OK;
@@ -217,6 +251,8 @@ const char* cc_strerror(int code) {
     case CC_EHIP: return "HIP runtime error";
     case CC_ECOLOR: return "colour palette exhausted";
     case CC_ESTATE: return "call out of order";
+    case CC_EAGAIN: return "over the HBM budget, retry after a release";
+    case CC_EBUSY: return "step still running";
     default: return "unknown error";
   }
 }
@@ -234,7 +270,11 @@ int cc_context_create(int device, cc_context** out) {
 
 void cc_context_destroy(cc_context* ctx) {
   if (!ctx) return;
+  server_destroy(ctx);
   if (ctx->cached) cc_solver_destroy(ctx->cached);
+  for (cc_solver* s : ctx->slots)
+    if (s) cc_solver_destroy(s);
+  for (hipStream_t s : ctx->slot_streams) (void)hipStreamDestroy(s);
   delete ctx;
 }
 
@@ -276,8 +316,7 @@ int cc_solver_create(cc_context* ctx, int32_t n, const double* inv_mass, const i
 
 void cc_solver_destroy(cc_solver* s) {
   if (!s) return;
-  hipDeviceSynchronize();
-  solver_free(s);
+  solver_free(s);  // hipFree waits for the work that uses the memory
   delete s;
 }
 
@@ -364,6 +403,7 @@ int cc_solver_iterate(cc_solver* s, int32_t* stop, cc_iter_info* info, void* str
   // forward step (Sec. 5) and the path certificate
   CC_HIP(hipMemsetAsync(&s->dc->mmax_bits, 0, 2 * sizeof(unsigned long long), st));
   CC_HIP(hipMemsetAsync(&s->dc->fail, 0, sizeof(unsigned long long), st));
+  CC_HIP(hipMemsetAsync(&s->dc->hits, 0, sizeof(unsigned long long), st));
   timer_begin(s, CC_K_FORWARD, st);
   CC_TRY(launch_forward(s, st));
   timer_end(s, st);
@@ -377,6 +417,7 @@ int cc_solver_iterate(cc_solver* s, int32_t* stop, cc_iter_info* info, void* str
   it.move_max = mmax;
   it.r_inf = rinf;
   it.ccd_fail = (int64_t)s->hc->fail;
+  it.ccd_hits = (int64_t)s->hc->hits;
   if (trace) it.fp_col = s->hc->fp_col;
   s->D = D - 2.0 * mmax;
   it.d_after = s->D;
@@ -386,6 +427,7 @@ int cc_solver_iterate(cc_solver* s, int32_t* stop, cc_iter_info* info, void* str
   s->st.pair_updates += it.n_p;
   s->st.row_updates += (na + s->n_erows) * (int64_t)p.gs_sweeps;
   s->st.ccd_fail += it.ccd_fail;
+  s->st.ccd_hits += it.ccd_hits;
   s->st.r_inf = rinf;
   if (it.n_colors > s->st.max_colors_used) s->st.max_colors_used = it.n_colors;
   if (done) s->st.status = CC_CONVERGED;
@@ -422,28 +464,62 @@ int cc_collide_step(cc_context* ctx, const double* x_prev, const double* x_tilde
   if (!ctx || (n > 0 && !x_next)) return CC_EINVAL;
   if (n > 0 && (x_next == x_prev || x_next == x_tilde)) return CC_EINVAL;
   CC_TRY(check_params(params));
-  hipStream_t st = as_stream(stream);
-  cc_solver* s = ctx->cached;
-  if (s && s->n == n && s->nt == nt && s->ne == ne) {
-    s->p = *params;
-    s->kappa2 = params->kappa * params->kappa;
-    if (nt) CC_HIP(hipMemcpyAsync(s->tris, tris, sizeof(int32_t) * 3 * nt, hipMemcpyDefault, st));
-    if (ne) CC_HIP(hipMemcpyAsync(s->edges, edges, sizeof(int32_t) * 2 * ne, hipMemcpyDefault, st));
-    if (n) {
-      if (inv_mass)
-        CC_HIP(hipMemcpyAsync(s->w, inv_mass, sizeof(double) * n, hipMemcpyDefault, st));
-      else
-        CC_TRY(launch_fill_u64((unsigned long long*)s->w, n, d2bits(1.0), st));
-    }
-    CC_TRY(launch_validate(s, nullptr, nullptr, st));
-  } else {
-    if (s) cc_solver_destroy(s);
-    ctx->cached = nullptr;
-    CC_TRY(cc_solver_create(ctx, n, inv_mass, tris, nt, edges, ne, params, &s, stream));
-    ctx->cached = s;
+  CC_TRY(bind_solver(ctx, ctx->cached, n, inv_mass, tris, nt, edges, ne, params, stream));
+  CC_TRY(cc_solver_begin(ctx->cached, x_prev, x_tilde, stream));
+  return cc_solver_run(ctx->cached, x_next, stats, stream);
+}
+
+int cc_collide_step_batched(cc_context* ctx, const cc_scene* scenes, int32_t ns,
+                            const cc_params* params, cc_stats* stats, void* stream) {
+  if (!ctx || ns < 0 || (ns > 0 && !scenes)) return CC_EINVAL;
+  CC_TRY(check_params(params));
+  for (int32_t i = 0; i < ns; ++i) {
+    const cc_scene& sc = scenes[i];
+    if (sc.n_verts < 0 || (sc.n_verts > 0 && !sc.x_next)) return CC_EINVAL;
+    if (sc.n_verts > 0 && (sc.x_next == sc.x_prev || sc.x_next == sc.x_tilde)) return CC_EINVAL;
   }
-  CC_TRY(cc_solver_begin(s, x_prev, x_tilde, stream));
-  return cc_solver_run(s, x_next, stats, stream);
+  if (ns == 0) return CC_OK;
+  if (hipSetDevice(ctx->device) != hipSuccess) return CC_EHIP;
+  hipStream_t cst = as_stream(stream);
+  while ((int32_t)ctx->slots.size() < ns) {
+    hipStream_t s = nullptr;
+    CC_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    ctx->slots.push_back(nullptr);
+    ctx->slot_streams.push_back(s);
+  }
+  // the inputs are produced on the caller's stream: every slot stream waits for it
+  hipEvent_t ready = nullptr;
+  CC_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  CC_HIP(hipEventRecord(ready, cst));
+  for (int32_t i = 0; i < ns; ++i) CC_HIP(hipStreamWaitEvent(ctx->slot_streams[i], ready, 0));
+  std::vector<int> rc(ns, CC_OK);
+  std::atomic<int32_t> next{0};
+  auto worker = [&]() {
+    if (hipSetDevice(ctx->device) != hipSuccess) return;
+    for (int32_t i = next++; i < ns; i = next++) {
+      const cc_scene& sc = scenes[i];
+      void* st = (void*)ctx->slot_streams[i];
+      int r = bind_solver(ctx, ctx->slots[i], sc.n_verts, sc.inv_mass, sc.tris, sc.n_tris,
+                          sc.edges, sc.n_edges, params, st);
+      if (r == CC_OK) r = cc_solver_begin(ctx->slots[i], sc.x_prev, sc.x_tilde, st);
+      if (r == CC_OK) r = cc_solver_run(ctx->slots[i], sc.x_next, stats ? &stats[i] : nullptr, st);
+      rc[i] = r;
+    }
+  };
+  const int32_t nthreads = std::min<int32_t>(ns, 16);
+  std::vector<std::thread> pool;
+  for (int32_t t = 1; t < nthreads; ++t) pool.emplace_back(worker);
+  worker();
+  for (auto& th : pool) th.join();
+  // order the caller's stream after every scene
+  for (int32_t i = 0; i < ns; ++i) {
+    CC_HIP(hipEventRecord(ready, ctx->slot_streams[i]));
+    CC_HIP(hipStreamWaitEvent(cst, ready, 0));
+  }
+  CC_HIP(hipEventDestroy(ready));
+  for (int32_t i = 0; i < ns; ++i)
+    if (rc[i] != CC_OK) return rc[i];
+  return CC_OK;
 }
 
 int cc_solver_get_state(cc_solver* s, double* x, double* y, double* r, double* D_host,
@@ -512,7 +588,7 @@ int cc_solver_search(cc_solver* s, const double* x, double dmax, uint64_t* keys,
   CC_TRY(launch_validate(s, x, nullptr, st));
   // the static flags come from the last begin; without one every vertex counts as free
   if (!s->begun && s->n) CC_HIP(hipMemsetAsync(s->stat, 0, s->n, st));
-  return lbvh_search(s, x, dmax, keys, nullptr, keys ? cap : 0, n, st);
+  return lbvh_search(s, x, dmax, keys, keys ? cap : 0, n, st);
 }
 
 int cc_solver_stats(cc_solver* s, cc_stats* out) {

@@ -273,6 +273,79 @@ __device__ __forceinline__ void contact_row(bool ee, const V3 xs[4], const doubl
   R.inv_a = A > 0.0 ? 1.0 / A : 0.0;
 }
 
+// Continuous test of one pair along the linear piece q_k(t) = q_k + t dq_k,
+// t in [0,1] (points in the contact-row order). Coplanarity V(t) =
+// det[q1-q0, q2-q0, q3-q0](t) is the cubic a3 t^3 + a2 t^2 + a1 t + a0; its
+// critical points split [0,1] into monotone pieces, a sign change is bisected to
+// the root, and the primitives' distance at every root and critical point decides
+// contact (<= eta). FP64 throughout.
+__device__ __forceinline__ double cubic_at(const double a[4], double t) {
+  return ((a[3] * t + a[2]) * t + a[1]) * t + a[0];
+}
+
+__device__ __forceinline__ bool ccd_probe(const V3 q[4], const V3 dq[4], bool ee, double t,
+                                          double eta2) {
+  V3 p0 = vaxpy(q[0], t, dq[0]), p1 = vaxpy(q[1], t, dq[1]);
+  V3 p2 = vaxpy(q[2], t, dq[2]), p3 = vaxpy(q[3], t, dq[3]);
+  return pair_d2(ee, p0, p1, p2, p3) <= eta2;
+}
+
+__device__ __noinline__ bool ccd_hit(const V3 q[4], const V3 dq[4], bool ee, double eta2) {
+  V3 e1 = vsub(q[1], q[0]), e2 = vsub(q[2], q[0]), e3 = vsub(q[3], q[0]);
+  V3 f1 = vsub(dq[1], dq[0]), f2 = vsub(dq[2], dq[0]), f3 = vsub(dq[3], dq[0]);
+  V3 c23 = vcross(e2, e3), f2e3 = vcross(f2, e3), e2f3 = vcross(e2, f3), f2f3 = vcross(f2, f3);
+  double a[4];
+  a[0] = vdot(e1, c23);
+  a[1] = vdot(f1, c23) + vdot(e1, f2e3) + vdot(e1, e2f3);
+  a[2] = vdot(f1, f2e3) + vdot(f1, e2f3) + vdot(e1, f2f3);
+  a[3] = vdot(f1, f2f3);
+  double knot[4];
+  int nk = 0;
+  knot[nk++] = 0.0;
+  double A = 3.0 * a[3], B = 2.0 * a[2], C = a[1];
+  double crit[2];
+  int nc = 0;
+  if (A == 0.0) {
+    if (B != 0.0) crit[nc++] = -C / B;
+  } else {
+    double disc = B * B - 4.0 * A * C;
+    if (disc >= 0.0) {
+      double sq = sqrt(disc);
+      double r1 = (-B - sq) / (2.0 * A), r2 = (-B + sq) / (2.0 * A);
+      crit[nc++] = r1 < r2 ? r1 : r2;
+      crit[nc++] = r1 < r2 ? r2 : r1;
+    }
+  }
+  for (int i = 0; i < nc; ++i)
+    if (crit[i] > 0.0 && crit[i] < 1.0 && crit[i] > knot[nk - 1]) knot[nk++] = crit[i];
+  knot[nk++] = 1.0;
+  for (int i = 0; i + 1 < nk; ++i) {
+    double lo = knot[i], hi = knot[i + 1];
+    double vlo = cubic_at(a, lo), vhi = cubic_at(a, hi);
+    double t = -1.0;
+    if (vlo == 0.0) {
+      t = lo;
+    } else if (vhi == 0.0) {
+      t = hi;
+    } else if ((vlo < 0.0) != (vhi < 0.0)) {
+      for (int it = 0; it < 64; ++it) {
+        double mid = 0.5 * (lo + hi);
+        double vm = cubic_at(a, mid);
+        if (vm == 0.0) {
+          lo = mid;
+          hi = mid;
+          break;
+        }
+        if ((vm < 0.0) == (vlo < 0.0)) lo = mid; else hi = mid;
+      }
+      t = 0.5 * (lo + hi);
+    }
+    if (t >= 0.0 && ccd_probe(q, dq, ee, t, eta2)) return true;
+    if (i + 2 < nk && ccd_probe(q, dq, ee, knot[i + 1], eta2)) return true;
+  }
+  return false;
+}
+
 // splitmix64 output function (Steele, Lea, Flood 2014); a bijection on 64 bits.
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;

@@ -5,11 +5,19 @@
 // D_max/2 and rounded outward to float, so box overlap of a query (also
 // inflated by D_max/2) is implied by distance < D_max; the exact FP64 filter
 // d^2 < D_max^2 then decides membership. Build: 30-bit Morton codes of box
-// centres (one key space for both trees, tree id in bit 30), a stable LSD
-// radix sort written here (8-bit digits, wave ballot ranking), the hierarchy
-// of Karras (2012) and a bottom-up refit with arrival counters. Traversal: one
-// thread per query, stack in registers, candidates appended through a
-// per-lane LDS buffer flushed with one atomic per wave.
+// centres and vertices (one key space, group id in bits 31..30), a stable LSD
+// radix sort written here (8-bit digits, wave ballot ranking) and the
+// hierarchy of Karras (2012). Node boxes need no bottom-up walk: an internal
+// node covers a contiguous range of sorted leaves, so its box is a range union,
+// taken from LDS inside a 256-leaf block or assembled from per-block prefix,
+// suffix and a sparse table of block boxes across blocks (no atomics, no
+// device-scope fences).
+// Each node record (64 B) holds both child boxes and child ids, leaves inline;
+// a 4-wide copy (128 B) collapses each node with its children for traversal.
+// Traversal: one thread per query, children tested at the parent, candidates
+// appended through a per-lane LDS buffer flushed with one atomic per wave.
+// Edge queries run in sorted order and visit only leaves after their own, so
+// each edge-edge pair is found once.
 #include "geom.hpp"
 #include "internal.hpp"
 
@@ -17,8 +25,10 @@ namespace cc {
 
 constexpr int kTile = 4096;      // radix sort tile per block
 constexpr int kRsThreads = 256;
-constexpr int kStack = 64;
-constexpr int kBuf = 8;          // per-lane pending pairs in the traversal
+constexpr int kStack = 100;     // 4-wide DFS: 3 pending entries per level, <= 32 levels
+constexpr int kBuf = 8;          // per-lane pending pairs in the traversal (>= 4 + 4)
+constexpr int kBlk = 256;        // leaves per refit block
+constexpr int32_t kLeaf = (int32_t)0x80000000;
 constexpr int kTravThreads = 256;
 
 __device__ __forceinline__ uint32_t f2ord(float f) {
@@ -35,11 +45,12 @@ __device__ __forceinline__ float hi_out(double v) {
   return nextafterf(__double2float_ru(v), __builtin_inff());
 }
 
-// Leaf boxes for all F triangles then E edges; box-centre bounds (ordered ints).
+// Leaf boxes for all F triangles then E edges; per-block bounds of the box
+// centres (order-preserving uint encoding), reduced by k_bounds_reduce.
 __global__ void k_boxes(const double* __restrict__ x, const int32_t* __restrict__ tris,
                         const int32_t* __restrict__ edges, int32_t nt, int32_t ne, double infl,
                         float4* __restrict__ blo, float4* __restrict__ bhi,
-                        uint32_t* __restrict__ bounds) {
+                        uint32_t* __restrict__ part) {
   __shared__ uint32_t sb[6];
   if (threadIdx.x < 6) sb[threadIdx.x] = (threadIdx.x < 3) ? 0xffffffffu : 0u;
   __syncthreads();
@@ -69,8 +80,24 @@ __global__ void k_boxes(const double* __restrict__ x, const int32_t* __restrict_
     atomicMax(&sb[5], f2ord(cz));
   }
   __syncthreads();
-  if (threadIdx.x < 3) atomicMin(&bounds[threadIdx.x], sb[threadIdx.x]);
-  else if (threadIdx.x < 6) atomicMax(&bounds[threadIdx.x], sb[threadIdx.x]);
+  if (threadIdx.x < 6) part[6 * blockIdx.x + threadIdx.x] = sb[threadIdx.x];
+}
+
+__global__ void k_bounds_reduce(const uint32_t* __restrict__ part, int32_t nb,
+                                uint32_t* __restrict__ bounds) {
+  __shared__ uint32_t sb[6];
+  if (threadIdx.x < 6) sb[threadIdx.x] = (threadIdx.x < 3) ? 0xffffffffu : 0u;
+  __syncthreads();
+  uint32_t v[6] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0u, 0u, 0u};
+  for (int32_t b = threadIdx.x; b < nb; b += blockDim.x)
+    for (int k = 0; k < 6; ++k) {
+      uint32_t u = part[6 * b + k];
+      v[k] = k < 3 ? (u < v[k] ? u : v[k]) : (u > v[k] ? u : v[k]);
+    }
+  for (int k = 0; k < 3; ++k) atomicMin(&sb[k], v[k]);
+  for (int k = 3; k < 6; ++k) atomicMax(&sb[k], v[k]);
+  __syncthreads();
+  if (threadIdx.x < 6) bounds[threadIdx.x] = sb[threadIdx.x];
 }
 
 __device__ __forceinline__ uint32_t spread10(uint32_t v) {
@@ -82,13 +109,29 @@ __device__ __forceinline__ uint32_t spread10(uint32_t v) {
   return v;
 }
 
+// Morton keys of the triangle boxes (group 0), edge boxes (group 1) and vertices
+// (group 2, used to order the vertex queries); group id in bits 31..30.
 __global__ void k_morton(const float4* __restrict__ blo, const float4* __restrict__ bhi,
-                         int32_t nt, int32_t ne, const uint32_t* __restrict__ bounds,
-                         uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+                         const double* __restrict__ x, int32_t nt, int32_t ne, int32_t n,
+                         const uint32_t* __restrict__ bounds, uint32_t* __restrict__ keys,
+                         uint32_t* __restrict__ vals) {
   int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nt + ne) return;
-  float4 l = blo[g], h = bhi[g];
-  float c[3] = {0.5f * (l.x + h.x), 0.5f * (l.y + h.y), 0.5f * (l.z + h.z)};
+  if (g >= nt + ne + n) return;
+  float c[3];
+  uint32_t grp;
+  if (g < nt + ne) {
+    float4 l = blo[g], h = bhi[g];
+    c[0] = 0.5f * (l.x + h.x);
+    c[1] = 0.5f * (l.y + h.y);
+    c[2] = 0.5f * (l.z + h.z);
+    grp = g < nt ? 0u : 1u;
+  } else {
+    V3 p = ld3(x, g - nt - ne);
+    c[0] = (float)p.x;
+    c[1] = (float)p.y;
+    c[2] = (float)p.z;
+    grp = 2u;
+  }
   uint32_t q[3];
   for (int k = 0; k < 3; ++k) {
     float lo = ord2f(bounds[k]), hi = ord2f(bounds[3 + k]);
@@ -99,7 +142,7 @@ __global__ void k_morton(const float4* __restrict__ blo, const float4* __restric
     q[k] = (uint32_t)v;
   }
   uint32_t code = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
-  keys[g] = code | ((g < nt ? 0u : 1u) << 30);
+  keys[g] = code | (grp << 30);
   vals[g] = (uint32_t)g;
 }
 
@@ -119,37 +162,59 @@ __global__ void k_rs_hist(const uint32_t* __restrict__ keys, int32_t n, int shif
   hist[threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
-// Exclusive scan of m counts in place, one block of 1024 threads.
-__global__ void k_scan_1block(uint32_t* __restrict__ a, int64_t m) {
-  __shared__ uint32_t part[1024];
-  int64_t per = (m + 1023) / 1024;
-  int64_t b = threadIdx.x * per, e = b + per < m ? b + per : m;
-  uint32_t sum = 0;
-  for (int64_t i = b; i < e; ++i) sum += a[i];
-  part[threadIdx.x] = sum;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+// Per digit (one block each): exclusive scan of the per-block counts of that
+// digit in place, and the digit's total.
+__global__ void __launch_bounds__(kRsThreads) k_rs_scan_digit(uint32_t* __restrict__ hist,
+                                                              int32_t nb,
+                                                              uint32_t* __restrict__ total) {
+  __shared__ uint32_t wsum[kRsThreads / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t* row = hist + (int64_t)blockIdx.x * nb;
+  uint32_t carry = 0;
+  for (int32_t b0 = 0; b0 < nb; b0 += kRsThreads) {
+    int32_t i = b0 + threadIdx.x;
+    uint32_t v = i < nb ? row[i] : 0u;
+    uint32_t incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      uint32_t t = __shfl_up(incl, o);
+      if (lane >= o) incl += t;
+    }
+    if (lane == 63) wsum[wv] = incl;
     __syncthreads();
-    part[threadIdx.x] += v;
+    uint32_t before = 0, chunk = 0;
+    for (int w = 0; w < kRsThreads / 64; ++w) {
+      if (w < wv) before += wsum[w];
+      chunk += wsum[w];
+    }
+    if (i < nb) row[i] = carry + before + incl - v;
+    carry += chunk;
     __syncthreads();
   }
-  uint32_t run = part[threadIdx.x] - sum;
-  for (int64_t i = b; i < e; ++i) {
-    uint32_t v = a[i];
-    a[i] = run;
-    run += v;
-  }
+  if (threadIdx.x == 0) total[blockIdx.x] = carry;
 }
 
 __global__ void k_rs_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                              uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, int32_t n,
-                             int shift, const uint32_t* __restrict__ hist, int32_t nb) {
+                             int shift, const uint32_t* __restrict__ hist, int32_t nb,
+                             const uint32_t* __restrict__ total) {
   constexpr int W = kRsThreads / 64;
   __shared__ uint32_t run[256];
   __shared__ uint32_t wc[W][256];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  run[threadIdx.x] = hist[threadIdx.x * nb + blockIdx.x];
+  {
+    // digit base = exclusive scan of the digit totals
+    uint32_t v = total[threadIdx.x], incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      uint32_t t = __shfl_up(incl, o);
+      if (lane >= o) incl += t;
+    }
+    if (lane == 63) wc[0][wave] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wave; ++w) before += wc[0][w];
+    run[threadIdx.x] = before + incl - v + hist[threadIdx.x * nb + blockIdx.x];
+    __syncthreads();
+  }
   const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
   int32_t base = blockIdx.x * kTile;
   for (int c = 0; c < kTile / kRsThreads; ++c) {
@@ -187,9 +252,11 @@ __global__ void k_rs_scatter(const uint32_t* __restrict__ kin, const uint32_t* _
 
 struct TreeView {
   int32_t n;
-  const uint32_t* keys;  // sorted codes of this tree
-  int32_t* child;
-  int32_t* parent;
+  const uint32_t* keys;     // sorted codes of this tree
+  const int32_t* leaf_prim;
+  float4* node;             // 4 float4 per internal node
+  int32_t* parent;          // internal nodes [0, n-1), then leaves: (parent << 1) | side
+  int2* range;
 };
 
 __device__ __forceinline__ int delta_fn(const uint32_t* __restrict__ k, int32_t n, int32_t i,
@@ -200,6 +267,8 @@ __device__ __forceinline__ int delta_fn(const uint32_t* __restrict__ k, int32_t 
   return 32 + __clz((uint32_t)i ^ (uint32_t)j);
 }
 
+// Internal node i of the radix tree over sorted keys (Karras 2012): its leaf
+// range, split position and children.
 __device__ void karras_node(const TreeView& T, int32_t i) {
   const uint32_t* k = T.keys;
   const int32_t n = T.n;
@@ -222,115 +291,313 @@ __device__ void karras_node(const TreeView& T, int32_t i) {
   } while (t > 1);
   int32_t gam = i + s * d + (d < 0 ? -1 : 0);
   int32_t lo = i < j ? i : j, hi = i < j ? j : i;
-  int32_t left = (lo == gam) ? (int32_t)(0x80000000u | (uint32_t)gam) : gam;
-  int32_t right = (hi == gam + 1) ? (int32_t)(0x80000000u | (uint32_t)(gam + 1)) : gam + 1;
-  T.child[2 * i] = left;
-  T.child[2 * i + 1] = right;
-  // parent: internal nodes at [0, n-1), leaves at [n-1, 2n-1)
-  T.parent[(left < 0) ? (n - 1 + (left & 0x7fffffff)) : left] = i;
-  T.parent[(right < 0) ? (n - 1 + (right & 0x7fffffff)) : right] = i;
+  int32_t cl, cr;
+  if (lo == gam) {
+    cl = kLeaf | T.leaf_prim[gam];
+    T.parent[n - 1 + gam] = (i << 1) | 0;
+  } else {
+    cl = gam;
+    T.parent[gam] = (i << 1) | 0;
+  }
+  if (hi == gam + 1) {
+    cr = kLeaf | T.leaf_prim[gam + 1];
+    T.parent[n - 1 + gam + 1] = (i << 1) | 1;
+  } else {
+    cr = gam + 1;
+    T.parent[gam + 1] = (i << 1) | 1;
+  }
+  T.node[4 * i + 3] = make_float4(__int_as_float(cl), __int_as_float(cr), __int_as_float(gam),
+                                  __int_as_float(hi));
+  T.range[i] = make_int2(lo, hi);
+  if (i == 0) T.parent[0] = -1;
 }
 
 __global__ void k_karras(TreeView ta, TreeView tb) {
   int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
   int32_t na = ta.n > 1 ? ta.n - 1 : 0, nb = tb.n > 1 ? tb.n - 1 : 0;
-  if (g < na) {
-    karras_node(ta, g);
-    if (g == 0) ta.parent[0] = -1;
-  } else if (g < na + nb) {
-    karras_node(tb, g - na);
-    if (g == na) tb.parent[0] = -1;
-  }
+  if (g < na) karras_node(ta, g);
+  else if (g < na + nb) karras_node(tb, g - na);
 }
 
-// Sorted leaf boxes and primitive ids of both trees.
+// Sorted leaf boxes, primitive ids and positions of both trees.
 __global__ void k_leaves(const uint32_t* __restrict__ sval, const float4* __restrict__ blo,
                          const float4* __restrict__ bhi, int32_t nt, int32_t ne,
                          float4* __restrict__ tlo, float4* __restrict__ thi,
-                         int32_t* __restrict__ tprim, float4* __restrict__ elo,
-                         float4* __restrict__ ehi, int32_t* __restrict__ eprim) {
+                         int32_t* __restrict__ tprim, int32_t* __restrict__ tpos,
+                         float4* __restrict__ elo, float4* __restrict__ ehi,
+                         int32_t* __restrict__ eprim, int32_t* __restrict__ epos, int32_t n,
+                         int32_t* __restrict__ vorder) {
   int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nt + ne) return;
+  if (g >= nt + ne + n) return;
   uint32_t p = sval[g];
-  if (g < nt) {
+  if (g >= nt + ne) {
+    vorder[g - nt - ne] = (int32_t)p - nt - ne;
+  } else if (g < nt) {
     tlo[g] = blo[p];
     thi[g] = bhi[p];
     tprim[g] = (int32_t)p;
+    tpos[p] = g;
   } else {
     int32_t i = g - nt;
     elo[i] = blo[p];
     ehi[i] = bhi[p];
     eprim[i] = (int32_t)p - nt;
+    epos[(int32_t)p - nt] = i;
   }
 }
 
-__device__ __forceinline__ float aload(const float* p) {
-  return __uint_as_float(
-      __hip_atomic_load((const uint32_t*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+// A tree of one leaf: node 0 holds the leaf on the left and an empty box on the right.
+__global__ void k_single(float4* __restrict__ node, float4* __restrict__ root,
+                         const float4* __restrict__ lo, const float4* __restrict__ hi,
+                         const int32_t* __restrict__ prim) {
+  float4 l = lo[0], h = hi[0];
+  const float inf = __builtin_inff();
+  node[0] = make_float4(l.x, l.y, l.z, h.x);
+  node[1] = make_float4(h.y, h.z, inf, inf);
+  node[2] = make_float4(inf, -inf, -inf, -inf);
+  node[3] = make_float4(__int_as_float(kLeaf | prim[0]), __int_as_float(kLeaf | prim[0]),
+                        __int_as_float(0), __int_as_float(0));
+  root[0] = l;
+  root[1] = h;
+}
+
+struct Box6 {
+  float lo[3], hi[3];
+};
+
+__device__ __forceinline__ Box6 box_empty() {
+  const float inf = __builtin_inff();
+  return Box6{{inf, inf, inf}, {-inf, -inf, -inf}};
+}
+__device__ __forceinline__ Box6 box_union(const Box6& a, const Box6& b) {
+  Box6 r;
+  for (int k = 0; k < 3; ++k) {
+    r.lo[k] = fminf(a.lo[k], b.lo[k]);
+    r.hi[k] = fmaxf(a.hi[k], b.hi[k]);
+  }
+  return r;
+}
+__device__ __forceinline__ Box6 box_ld(const float4* p) {
+  float4 l = p[0], h = p[1];
+  return Box6{{l.x, l.y, l.z}, {h.x, h.y, h.z}};
+}
+__device__ __forceinline__ void box_st(float4* p, const Box6& b) {
+  p[0] = make_float4(b.lo[0], b.lo[1], b.lo[2], 0.f);
+  p[1] = make_float4(b.hi[0], b.hi[1], b.hi[2], 0.f);
+}
+
+// Write a node's box into its parent's record (or the root box).
+__device__ __forceinline__ void box_to_parent(float4* __restrict__ node, float4* __restrict__ root,
+                                              int32_t par, const Box6& b) {
+  if (par < 0) {
+    box_st(root, b);
+    return;
+  }
+  float* rec = (float*)(node + 4 * (par >> 1)) + 6 * (par & 1);
+  rec[0] = b.lo[0];
+  rec[1] = b.lo[1];
+  rec[2] = b.lo[2];
+  rec[3] = b.hi[0];
+  rec[4] = b.hi[1];
+  rec[5] = b.hi[2];
 }
 
 struct RefitView {
   int32_t n;
-  const int32_t* child;
-  const int32_t* parent;
   const float4* leaf_lo;
   const float4* leaf_hi;
-  float4* node_lo;
-  float4* node_hi;
-  uint32_t* flag;
+  const int32_t* parent;
+  const int2* range;
+  float4* node;
+  float4* root;
+  float4* pre;  // 2 per leaf
+  float4* suf;  // 2 per leaf
+  float4* blk;  // 2 per block
 };
 
-__device__ void refit_leaf(const RefitView& T, int32_t leaf) {
-  int32_t node = T.parent[T.n - 1 + leaf];
-  while (node >= 0) {
-    __threadfence();
-    uint32_t old = atomicAdd(&T.flag[node], 1u);
-    if (old == 0) return;
-    __threadfence();
-    float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
-    float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
-    for (int c = 0; c < 2; ++c) {
-      int32_t ch = T.child[2 * node + c];
-      const float* L;
-      const float* H;
-      if (ch < 0) {
-        L = (const float*)&T.leaf_lo[ch & 0x7fffffff];
-        H = (const float*)&T.leaf_hi[ch & 0x7fffffff];
-      } else {
-        L = (const float*)&T.node_lo[ch];
-        H = (const float*)&T.node_hi[ch];
-      }
+// Refit, part 1 (one 256-leaf block): leaf boxes into their parents, prefix and
+// suffix unions inside the block, the block box, and every internal node whose
+// leaf range lies inside the block (range union read from LDS).
+__device__ void refit_block(const RefitView& T, int32_t b) {
+  __shared__ float slo[3][kBlk], shi[3][kBlk];
+  const int32_t B0 = b * kBlk;
+  const int32_t cnt = T.n - B0 < kBlk ? T.n - B0 : kBlk;
+  const int tid = threadIdx.x;
+  Box6 mine = box_empty();
+  if (tid < cnt) {
+    float4 l = T.leaf_lo[B0 + tid], h = T.leaf_hi[B0 + tid];
+    mine = Box6{{l.x, l.y, l.z}, {h.x, h.y, h.z}};
+    box_to_parent(T.node, T.root, T.parent[T.n - 1 + B0 + tid], mine);
+  }
+  for (int k = 0; k < 3; ++k) {
+    slo[k][tid] = mine.lo[k];
+    shi[k][tid] = mine.hi[k];
+  }
+  __syncthreads();
+  // inclusive prefix union (Hillis-Steele) in registers via LDS exchange
+  Box6 pre = mine;
+  for (int off = 1; off < kBlk; off <<= 1) {
+    Box6 other = box_empty();
+    if (tid >= off)
       for (int k = 0; k < 3; ++k) {
-        lo[k] = fminf(lo[k], aload(L + k));
-        hi[k] = fmaxf(hi[k], aload(H + k));
+        other.lo[k] = slo[k][tid - off];
+        other.hi[k] = shi[k][tid - off];
       }
+    __syncthreads();
+    pre = box_union(pre, other);
+    for (int k = 0; k < 3; ++k) {
+      slo[k][tid] = pre.lo[k];
+      shi[k][tid] = pre.hi[k];
     }
-    T.node_lo[node] = make_float4(lo[0], lo[1], lo[2], 0.f);
-    T.node_hi[node] = make_float4(hi[0], hi[1], hi[2], 0.f);
-    node = T.parent[node];
+    __syncthreads();
+  }
+  if (tid < cnt) box_st(T.pre + 2 * (B0 + tid), pre);
+  if (tid == cnt - 1) box_st(T.blk + 2 * b, pre);
+  // suffix union
+  for (int k = 0; k < 3; ++k) {
+    slo[k][tid] = mine.lo[k];
+    shi[k][tid] = mine.hi[k];
+  }
+  __syncthreads();
+  Box6 suf = mine;
+  for (int off = 1; off < kBlk; off <<= 1) {
+    Box6 other = box_empty();
+    if (tid + off < kBlk)
+      for (int k = 0; k < 3; ++k) {
+        other.lo[k] = slo[k][tid + off];
+        other.hi[k] = shi[k][tid + off];
+      }
+    __syncthreads();
+    suf = box_union(suf, other);
+    for (int k = 0; k < 3; ++k) {
+      slo[k][tid] = suf.lo[k];
+      shi[k][tid] = suf.hi[k];
+    }
+    __syncthreads();
+  }
+  if (tid < cnt) box_st(T.suf + 2 * (B0 + tid), suf);
+  // leaves again for range unions
+  for (int k = 0; k < 3; ++k) {
+    slo[k][tid] = mine.lo[k];
+    shi[k][tid] = mine.hi[k];
+  }
+  __syncthreads();
+  const int32_t i = B0 + tid;
+  if (i < T.n - 1) {
+    int2 r = T.range[i];
+    if (r.x >= B0 && r.y < B0 + kBlk) {
+      Box6 u = box_empty();
+      for (int32_t j = r.x - B0; j <= r.y - B0; ++j)
+        for (int k = 0; k < 3; ++k) {
+          u.lo[k] = fminf(u.lo[k], slo[k][j]);
+          u.hi[k] = fmaxf(u.hi[k], shi[k][j]);
+        }
+      box_to_parent(T.node, T.root, T.parent[i], u);
+    }
   }
 }
 
-__global__ void k_refit(RefitView ta, RefitView tb) {
-  int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < ta.n) {
-    if (ta.n > 1) refit_leaf(ta, g);
-  } else if (g < ta.n + tb.n) {
-    if (tb.n > 1) refit_leaf(tb, g - ta.n);
+__global__ void __launch_bounds__(kBlk) k_refit_block(RefitView ta, RefitView tb, int32_t nba) {
+  if ((int32_t)blockIdx.x < nba) refit_block(ta, blockIdx.x);
+  else refit_block(tb, blockIdx.x - nba);
+}
+
+// Sparse table over the block boxes: level k, entry b = union of blocks
+// b .. b + 2^k - 1 (level 0 is written by refit_block). One block per tree.
+__device__ void blk_sparse(const RefitView& T) {
+  const int32_t nb = (T.n + kBlk - 1) / kBlk;
+  for (int k = 1; (1 << k) <= nb; ++k) {
+    const int32_t half = 1 << (k - 1), cnt = nb - (1 << k) + 1;
+    const float4* src = T.blk + (int64_t)2 * nb * (k - 1);
+    float4* dst = T.blk + (int64_t)2 * nb * k;
+    for (int32_t b = threadIdx.x; b < cnt; b += blockDim.x)
+      box_st(dst + 2 * b, box_union(box_ld(src + 2 * b), box_ld(src + 2 * (b + half))));
+    __syncthreads();
   }
+}
+
+__global__ void __launch_bounds__(1024) k_blk_sparse(RefitView ta, RefitView tb) {
+  if (blockIdx.x == 0) blk_sparse(ta);
+  else blk_sparse(tb);
+}
+
+// Refit, part 2: internal nodes whose range crosses blocks: suffix of the first
+// block, the whole blocks between (two overlapping sparse-table entries), prefix
+// of the last block.
+__device__ void refit_top(const RefitView& T, int32_t i) {
+  int2 r = T.range[i];
+  int32_t b0 = r.x / kBlk, b1 = r.y / kBlk;
+  if (b0 == b1) return;
+  Box6 u = box_union(box_ld(T.suf + 2 * r.x), box_ld(T.pre + 2 * r.y));
+  const int32_t lo = b0 + 1, hi = b1 - 1;
+  if (lo <= hi) {
+    const int32_t nb = (T.n + kBlk - 1) / kBlk;
+    const int k = 31 - __clz((uint32_t)(hi - lo + 1));
+    const float4* lev = T.blk + (int64_t)2 * nb * k;
+    u = box_union(u, box_union(box_ld(lev + 2 * lo), box_ld(lev + 2 * (hi - (1 << k) + 1))));
+  }
+  box_to_parent(T.node, T.root, T.parent[i], u);
+}
+
+__global__ void k_refit_top(RefitView ta, RefitView tb) {
+  int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t na = ta.n > 1 ? ta.n - 1 : 0, nb = tb.n > 1 ? tb.n - 1 : 0;
+  if (g < na) refit_top(ta, g);
+  else if (g < na + nb) refit_top(tb, g - na);
 }
 
 // ---------------------------------------------------------------- traversal
 
 struct TravTree {
   int32_t n;
-  const int32_t* child;
-  const float4* node_lo;
-  const float4* node_hi;
-  const float4* leaf_lo;
-  const float4* leaf_hi;
+  const float4* wide;  // 8 float4 per internal node: four grandchild slots
+  const float4* root;
   const int32_t* leaf_prim;
 };
+
+// 4-wide records: node i with its children collapsed, so one visit tests up to
+// four boxes (the binary node's grandchildren, or a leaf child in place) and a
+// traversal takes half as many dependent steps. Slot layout: boxes (6 floats
+// each) in the first 6 float4, child ids, then the last leaf position of each slot.
+__global__ void k_wide(const float4* __restrict__ node, float4* __restrict__ wide, int32_t ni) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ni) return;
+  const float* rec = (const float*)(node + 4 * i);
+  float box[4][6];
+  int32_t id[4], hi[4];
+  const float inf = __builtin_inff();
+  for (int s = 0; s < 2; ++s) {
+    const int32_t c = __float_as_int(rec[12 + s]);
+    const int32_t chi = __float_as_int(rec[14 + s]);
+    if (c < 0) {
+      for (int k = 0; k < 6; ++k) box[2 * s][k] = rec[6 * s + k];
+      id[2 * s] = c;
+      hi[2 * s] = chi;
+      for (int k = 0; k < 3; ++k) {
+        box[2 * s + 1][k] = inf;
+        box[2 * s + 1][3 + k] = -inf;
+      }
+      id[2 * s + 1] = c;
+      hi[2 * s + 1] = chi;
+    } else {
+      const float* cr = (const float*)(node + 4 * c);
+      for (int t = 0; t < 2; ++t) {
+        for (int k = 0; k < 6; ++k) box[2 * s + t][k] = cr[6 * t + k];
+        id[2 * s + t] = __float_as_int(cr[12 + t]);
+        hi[2 * s + t] = __float_as_int(cr[14 + t]);
+      }
+    }
+  }
+  float out[32];
+  for (int s = 0; s < 4; ++s)
+    for (int k = 0; k < 6; ++k) out[6 * s + k] = box[s][k];
+  for (int s = 0; s < 4; ++s) {
+    out[24 + s] = __int_as_float(id[s]);
+    out[28 + s] = __int_as_float(hi[s]);
+  }
+  float4* w = wide + 8 * (int64_t)i;
+  for (int q = 0; q < 8; ++q) w[q] = make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
+}
 
 struct TravArgs {
   TravTree tt, te;
@@ -338,142 +605,128 @@ struct TravArgs {
   const int32_t* tris;
   const int32_t* edges;
   const uint8_t* stat;
+  const int32_t* vorder;  // vertex queries in Morton order
   int32_t n, ne;
   double infl, dmax2;
   uint64_t* out;
-  double* dout;
   int64_t cap;
   Counters* cnt;
 };
 
-__device__ __forceinline__ bool overlap(float4 al, float4 ah, float4 bl, float4 bh) {
-  return al.x <= bh.x && bl.x <= ah.x && al.y <= bh.y && bl.y <= ah.y && al.z <= bh.z &&
-         bl.z <= ah.z;
+__device__ __forceinline__ bool overlap6(float4 ql, float4 qh, float lx, float ly, float lz,
+                                         float hx, float hy, float hz) {
+  return ql.x <= hx && lx <= qh.x && ql.y <= hy && ly <= qh.y && ql.z <= hz && lz <= qh.z;
+}
+
+__device__ __forceinline__ void wave_flush(uint64_t* skey, int& cnt, const TravArgs& A) {
+  const int lane = __lane_id();
+  int incl = cnt;
+  for (int o = 1; o < 64; o <<= 1) {
+    int v = __shfl_up(incl, o);
+    if (lane >= o) incl += v;
+  }
+  int total = __shfl(incl, 63);
+  unsigned long long base = 0;
+  if (lane == 0 && total > 0) base = atomicAdd(&A.cnt->n_out, (unsigned long long)total);
+  base = __shfl(base, 0);
+  int64_t pos = (int64_t)base + (incl - cnt);
+  for (int i = 0; i < cnt; ++i)
+    if (pos + i < A.cap) A.out[pos + i] = skey[threadIdx.x * kBuf + i];
+  cnt = 0;
 }
 
 __global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
   __shared__ uint64_t skey[kTravThreads * kBuf];
-  __shared__ double sd2[kTravThreads * kBuf];
-  const int lane = threadIdx.x & 63;
   int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
   const bool is_vt = q < A.n;
   const bool active = q < A.n + A.ne;
-  const TravTree& T = is_vt ? A.tt : A.te;
+  const TravTree T = is_vt ? A.tt : A.te;
   float4 qlo = make_float4(0.f, 0.f, 0.f, 0.f), qhi = qlo;
-  int32_t qv[2] = {0, 0};
+  int32_t qv0 = 0, qv1 = 0, qid = 0, qpos = -1;
   V3 qx0{0, 0, 0}, qx1{0, 0, 0};
   int32_t stack[kStack];
   int sp = 0;
   if (active && T.n > 0) {
     if (is_vt) {
-      qv[0] = q;
-      qx0 = ld3(A.x, q);
+      qid = A.vorder[q];
+      qv0 = qid;
+      qx0 = ld3(A.x, qid);
       qlo = make_float4(lo_out(qx0.x - A.infl), lo_out(qx0.y - A.infl), lo_out(qx0.z - A.infl), 0.f);
       qhi = make_float4(hi_out(qx0.x + A.infl), hi_out(qx0.y + A.infl), hi_out(qx0.z + A.infl), 0.f);
     } else {
-      int32_t e = q - A.n;
-      qv[0] = A.edges[2 * e];
-      qv[1] = A.edges[2 * e + 1];
-      qx0 = ld3(A.x, qv[0]);
-      qx1 = ld3(A.x, qv[1]);
+      qpos = q - A.n;  // sorted position of the query edge in the edge tree
+      qid = T.leaf_prim[qpos];
+      qv0 = A.edges[2 * qid];
+      qv1 = A.edges[2 * qid + 1];
+      qx0 = ld3(A.x, qv0);
+      qx1 = ld3(A.x, qv1);
       qlo = make_float4(lo_out(fmin(qx0.x, qx1.x) - A.infl), lo_out(fmin(qx0.y, qx1.y) - A.infl),
                         lo_out(fmin(qx0.z, qx1.z) - A.infl), 0.f);
       qhi = make_float4(hi_out(fmax(qx0.x, qx1.x) + A.infl), hi_out(fmax(qx0.y, qx1.y) + A.infl),
                         hi_out(fmax(qx0.z, qx1.z) + A.infl), 0.f);
     }
-    stack[sp++] = T.n == 1 ? (int32_t)0x80000000u : 0;
+    float4 rl = T.root[0], rh = T.root[1];
+    if (overlap6(qlo, qhi, rl.x, rl.y, rl.z, rh.x, rh.y, rh.z)) stack[sp++] = 0;
   }
-  const int32_t qid = is_vt ? q : q - A.n;
   int cnt = 0;
   while (__any(sp > 0)) {
     if (sp > 0) {
-      int32_t node = stack[--sp];
-      if (node < 0) {
-        int32_t li = node & 0x7fffffff;
-        if (overlap(qlo, qhi, T.leaf_lo[li], T.leaf_hi[li])) {
-          int32_t prim = T.leaf_prim[li];
-          int32_t v1, v2, v3 = -1;
-          bool ok;
-          if (is_vt) {
-            v1 = A.tris[3 * prim];
-            v2 = A.tris[3 * prim + 1];
-            v3 = A.tris[3 * prim + 2];
-            ok = qv[0] != v1 && qv[0] != v2 && qv[0] != v3;
-            ok = ok && !(A.stat[qv[0]] && A.stat[v1] && A.stat[v2] && A.stat[v3]);
-          } else {
-            v1 = A.edges[2 * prim];
-            v2 = A.edges[2 * prim + 1];
-            ok = prim > qid && qv[0] != v1 && qv[0] != v2 && qv[1] != v1 && qv[1] != v2;
-            ok = ok && !(A.stat[qv[0]] && A.stat[qv[1]] && A.stat[v1] && A.stat[v2]);
-          }
-          if (ok) {
-            double d2;
-            uint64_t key;
-            if (is_vt) {
-              double bw[3];
-              d2 = pt_tri_d2(qx0, ld3(A.x, v1), ld3(A.x, v2), ld3(A.x, v3), bw);
-              key = ((uint64_t)(uint32_t)qid << 32) | (uint32_t)prim;
-            } else {
-              double s, t;
-              d2 = seg_seg_d2(qx0, qx1, ld3(A.x, v1), ld3(A.x, v2), s, t);
-              key = KEY_EE | ((uint64_t)(uint32_t)qid << 32) | (uint32_t)prim;
-            }
-            if (d2 < A.dmax2) {
-              skey[threadIdx.x * kBuf + cnt] = key;
-              sd2[threadIdx.x * kBuf + cnt] = d2;
-              ++cnt;
-            }
-          }
+      const int32_t i = stack[--sp];
+      const float4* rec = T.wide + 8 * i;
+      float f[32];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        float4 v = rec[q];
+        f[4 * q] = v.x;
+        f[4 * q + 1] = v.y;
+        f[4 * q + 2] = v.z;
+        f[4 * q + 3] = v.w;
+      }
+#pragma unroll
+      for (int slot = 0; slot < 4; ++slot) {
+        const float* b = f + 6 * slot;
+        if (!overlap6(qlo, qhi, b[0], b[1], b[2], b[3], b[4], b[5])) continue;
+        if (__float_as_int(f[28 + slot]) <= qpos) continue;
+        const int32_t c = __float_as_int(f[24 + slot]);
+        if (c >= 0) {
+          if (sp < kStack) stack[sp++] = c;
+          else atomicOr(&A.cnt->err, 2ull);
+          continue;
         }
-      } else if (overlap(qlo, qhi, T.node_lo[node], T.node_hi[node])) {
-        if (sp + 2 <= kStack) {
-          stack[sp++] = T.child[2 * node];
-          stack[sp++] = T.child[2 * node + 1];
+        const int32_t prim = c & 0x7fffffff;
+        double d2;
+        uint64_t key;
+        bool ok;
+        if (is_vt) {
+          int32_t v1 = A.tris[3 * prim], v2 = A.tris[3 * prim + 1], v3 = A.tris[3 * prim + 2];
+          ok = qv0 != v1 && qv0 != v2 && qv0 != v3 &&
+               !(A.stat[qv0] && A.stat[v1] && A.stat[v2] && A.stat[v3]);
+          if (!ok) continue;
+          double bw[3];
+          d2 = pt_tri_d2(qx0, ld3(A.x, v1), ld3(A.x, v2), ld3(A.x, v3), bw);
+          key = ((uint64_t)(uint32_t)qid << 32) | (uint32_t)prim;
         } else {
-          atomicOr(&A.cnt->err, 2ull);
-          sp = 0;
+          int32_t v1 = A.edges[2 * prim], v2 = A.edges[2 * prim + 1];
+          ok = qv0 != v1 && qv0 != v2 && qv1 != v1 && qv1 != v2 &&
+               !(A.stat[qv0] && A.stat[qv1] && A.stat[v1] && A.stat[v2]);
+          if (!ok) continue;
+          // the pair is reported once, under its canonical key (lower edge first);
+          // the distance is taken with that edge first as well
+          double s, t;
+          if (qid < prim) {
+            d2 = seg_seg_d2(qx0, qx1, ld3(A.x, v1), ld3(A.x, v2), s, t);
+            key = KEY_EE | ((uint64_t)(uint32_t)qid << 32) | (uint32_t)prim;
+          } else {
+            d2 = seg_seg_d2(ld3(A.x, v1), ld3(A.x, v2), qx0, qx1, s, t);
+            key = KEY_EE | ((uint64_t)(uint32_t)prim << 32) | (uint32_t)qid;
+          }
         }
+        if (d2 < A.dmax2) skey[threadIdx.x * kBuf + cnt++] = key;
       }
     }
-    if (__any(cnt == kBuf)) {
-      // wave-wide flush of every lane's pending pairs
-      int incl = cnt;
-      for (int o = 1; o < 64; o <<= 1) {
-        int v = __shfl_up(incl, o);
-        if (lane >= o) incl += v;
-      }
-      int total = __shfl(incl, 63);
-      unsigned long long base = 0;
-      if (lane == 0 && total > 0) base = atomicAdd(&A.cnt->n_out, (unsigned long long)total);
-      base = __shfl(base, 0);
-      int64_t pos = (int64_t)base + (incl - cnt);
-      for (int i = 0; i < cnt; ++i) {
-        if (pos + i < A.cap) {
-          A.out[pos + i] = skey[threadIdx.x * kBuf + i];
-          if (A.dout) A.dout[pos + i] = sd2[threadIdx.x * kBuf + i];
-        }
-      }
-      cnt = 0;
-    }
+    if (__any(cnt > kBuf - 4)) wave_flush(skey, cnt, A);
   }
-  {
-    int incl = cnt;
-    for (int o = 1; o < 64; o <<= 1) {
-      int v = __shfl_up(incl, o);
-      if (lane >= o) incl += v;
-    }
-    int total = __shfl(incl, 63);
-    unsigned long long base = 0;
-    if (lane == 0 && total > 0) base = atomicAdd(&A.cnt->n_out, (unsigned long long)total);
-    base = __shfl(base, 0);
-    int64_t pos = (int64_t)base + (incl - cnt);
-    for (int i = 0; i < cnt; ++i) {
-      if (pos + i < A.cap) {
-        A.out[pos + i] = skey[threadIdx.x * kBuf + i];
-        if (A.dout) A.dout[pos + i] = sd2[threadIdx.x * kBuf + i];
-      }
-    }
-  }
+  wave_flush(skey, cnt, A);
 }
 
 // ---------------------------------------------------------------- host side
@@ -488,37 +741,49 @@ static int dalloc(T** p, int64_t n) {
 static int bvh_alloc_one(Bvh& b, int32_t n) {
   b.n = n;
   int32_t ni = n > 1 ? n - 1 : 1;
+  int32_t nb = (n + kBlk - 1) / kBlk;
   CC_TRY(dalloc(&b.leaf_lo, n));
   CC_TRY(dalloc(&b.leaf_hi, n));
   CC_TRY(dalloc(&b.leaf_prim, n));
-  CC_TRY(dalloc(&b.child, 2 * ni));
-  CC_TRY(dalloc(&b.parent, ni + n));
-  CC_TRY(dalloc(&b.node_lo, ni));
-  CC_TRY(dalloc(&b.node_hi, ni));
-  CC_TRY(dalloc(&b.flag, ni));
+  CC_TRY(dalloc(&b.pos_of, n));
+  CC_TRY(dalloc(&b.node, 4 * (int64_t)ni));
+  CC_TRY(dalloc(&b.wide, 8 * (int64_t)ni));
+  CC_TRY(dalloc(&b.parent, (int64_t)ni + n));
+  CC_TRY(dalloc(&b.range, ni));
+  CC_TRY(dalloc(&b.pre, 2 * (int64_t)n));
+  CC_TRY(dalloc(&b.suf, 2 * (int64_t)n));
+  int nlev = 1;
+  while ((1 << nlev) <= nb) ++nlev;  // sparse-table levels over the block boxes
+  CC_TRY(dalloc(&b.blk, 2 * (int64_t)(nb > 0 ? nb : 1) * nlev));
+  CC_TRY(dalloc(&b.root, 2));
   return CC_OK;
 }
 
 static void bvh_free_one(Bvh& b) {
-  hipFree(b.leaf_lo); hipFree(b.leaf_hi); hipFree(b.leaf_prim); hipFree(b.child);
-  hipFree(b.parent); hipFree(b.node_lo); hipFree(b.node_hi); hipFree(b.flag);
+  hipFree(b.leaf_lo); hipFree(b.leaf_hi); hipFree(b.leaf_prim); hipFree(b.pos_of);
+  hipFree(b.node); hipFree(b.wide); hipFree(b.parent); hipFree(b.range); hipFree(b.pre); hipFree(b.suf);
+  hipFree(b.blk); hipFree(b.root);
   b = Bvh{};
 }
 
 int bvh_alloc(cc_solver* s) {
   int64_t m = (int64_t)s->nt + s->ne;
+  int64_t mall = m + s->n;  // triangles, edges and vertices share one sort
   CC_TRY(bvh_alloc_one(s->tree_t, s->nt));
   CC_TRY(bvh_alloc_one(s->tree_e, s->ne));
-  CC_TRY(dalloc(&s->sk0, m));
-  CC_TRY(dalloc(&s->sk1, m));
-  CC_TRY(dalloc(&s->sv0, m));
-  CC_TRY(dalloc(&s->sv1, m));
+  CC_TRY(dalloc(&s->sk0, mall));
+  CC_TRY(dalloc(&s->sk1, mall));
+  CC_TRY(dalloc(&s->sv0, mall));
+  CC_TRY(dalloc(&s->sv1, mall));
   CC_TRY(dalloc(&s->ubox_lo, m));
   CC_TRY(dalloc(&s->ubox_hi, m));
-  int64_t nb = (m + kTile - 1) / kTile;
+  CC_TRY(dalloc(&s->vorder, s->n));
+  int64_t nb = (mall + kTile - 1) / kTile;
   s->rs_hist_cap = 256 * (nb > 0 ? nb : 1);
   CC_TRY(dalloc(&s->rs_hist, s->rs_hist_cap));
+  CC_TRY(dalloc(&s->rs_total, 256));
   CC_TRY(dalloc(&s->bounds, 6));
+  CC_TRY(dalloc(&s->bounds_part, 6 * ((m + 255) / 256)));
   return CC_OK;
 }
 
@@ -527,71 +792,84 @@ void bvh_free(cc_solver* s) {
   bvh_free_one(s->tree_e);
   hipFree(s->sk0); hipFree(s->sk1); hipFree(s->sv0); hipFree(s->sv1);
   hipFree(s->ubox_lo); hipFree(s->ubox_hi); hipFree(s->rs_hist); hipFree(s->bounds);
+  hipFree(s->bounds_part); hipFree(s->vorder); hipFree(s->rs_total);
   s->sk0 = s->sk1 = s->sv0 = s->sv1 = nullptr;
 }
 
 static inline unsigned blocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-int lbvh_search(cc_solver* s, const double* x, double dmax, uint64_t* out, double* dout,
-                int64_t cap, int64_t* nfound, hipStream_t st) {
+static RefitView refit_view(Bvh& b) {
+  return RefitView{b.n, b.leaf_lo, b.leaf_hi, b.parent, b.range, b.node, b.root,
+                   b.pre, b.suf, b.blk};
+}
+
+int lbvh_search(cc_solver* s, const double* x, double dmax, uint64_t* out, int64_t cap,
+                int64_t* nfound, hipStream_t st) {
   const int32_t nt = s->nt, ne = s->ne;
   const int64_t m = (int64_t)nt + ne;
   const double infl = 0.5 * dmax;
   CC_HIP(hipMemsetAsync(&s->dc->n_out, 0, sizeof(unsigned long long), st));
   CC_HIP(hipMemsetAsync(&s->dc->err, 0, sizeof(unsigned long long), st));
   if (m > 0) {
-    // bounds init: min = 0xffffffff, max = 0
-    uint32_t init[6] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0u, 0u, 0u};
-    CC_HIP(hipMemcpyAsync(s->bounds, init, sizeof init, hipMemcpyHostToDevice, st));
-    k_boxes<<<blocks(m, 256), 256, 0, st>>>(x, s->tris, s->edges, nt, ne, infl, s->ubox_lo,
-                                           s->ubox_hi, s->bounds);
-    k_morton<<<blocks(m, 256), 256, 0, st>>>(s->ubox_lo, s->ubox_hi, nt, ne, s->bounds, s->sk0,
-                                             s->sv0);
-    const int32_t nb = (int32_t)((m + kTile - 1) / kTile);
+    const int64_t mall = m + s->n;
+    const unsigned nbx = blocks(m, 256);
+    k_boxes<<<nbx, 256, 0, st>>>(x, s->tris, s->edges, nt, ne, infl, s->ubox_lo, s->ubox_hi,
+                                 s->bounds_part);
+    k_bounds_reduce<<<1, 256, 0, st>>>(s->bounds_part, (int32_t)nbx, s->bounds);
+    k_morton<<<blocks(mall, 256), 256, 0, st>>>(s->ubox_lo, s->ubox_hi, x, nt, ne, s->n,
+                                                s->bounds, s->sk0, s->sv0);
+    const int32_t nb = (int32_t)((mall + kTile - 1) / kTile);
     uint32_t *ki = s->sk0, *vi = s->sv0, *ko = s->sk1, *vo = s->sv1;
     for (int shift = 0; shift < 32; shift += 8) {
-      k_rs_hist<<<nb, kRsThreads, 0, st>>>(ki, (int32_t)m, shift, s->rs_hist, nb);
-      k_scan_1block<<<1, 1024, 0, st>>>(s->rs_hist, (int64_t)256 * nb);
-      k_rs_scatter<<<nb, kRsThreads, 0, st>>>(ki, vi, ko, vo, (int32_t)m, shift, s->rs_hist, nb);
+      k_rs_hist<<<nb, kRsThreads, 0, st>>>(ki, (int32_t)mall, shift, s->rs_hist, nb);
+      k_rs_scan_digit<<<256, kRsThreads, 0, st>>>(s->rs_hist, nb, s->rs_total);
+      k_rs_scatter<<<nb, kRsThreads, 0, st>>>(ki, vi, ko, vo, (int32_t)mall, shift, s->rs_hist,
+                                              nb, s->rs_total);
       uint32_t* t;
       t = ki; ki = ko; ko = t;
       t = vi; vi = vo; vo = t;
     }
-    // after 4 passes the sorted data is back in sk0/sv0
-    k_leaves<<<blocks(m, 256), 256, 0, st>>>(ki == s->sk0 ? s->sv0 : s->sv1, s->ubox_lo,
-                                             s->ubox_hi, nt, ne, s->tree_t.leaf_lo,
-                                             s->tree_t.leaf_hi, s->tree_t.leaf_prim,
-                                             s->tree_e.leaf_lo, s->tree_e.leaf_hi,
-                                             s->tree_e.leaf_prim);
+    Bvh& bt = s->tree_t;
+    Bvh& be = s->tree_e;
+    k_leaves<<<blocks(mall, 256), 256, 0, st>>>(vi, s->ubox_lo, s->ubox_hi, nt, ne, bt.leaf_lo,
+                                                bt.leaf_hi, bt.leaf_prim, bt.pos_of, be.leaf_lo,
+                                                be.leaf_hi, be.leaf_prim, be.pos_of, s->n,
+                                                s->vorder);
     const uint32_t* sorted = ki;
-    TreeView ta{nt, sorted, s->tree_t.child, s->tree_t.parent};
-    TreeView tb{ne, sorted + nt, s->tree_e.child, s->tree_e.parent};
+    TreeView ta{nt, sorted, bt.leaf_prim, bt.node, bt.parent, bt.range};
+    TreeView tb{ne, sorted + nt, be.leaf_prim, be.node, be.parent, be.range};
     int64_t ninternal = (nt > 1 ? nt - 1 : 0) + (ne > 1 ? ne - 1 : 0);
-    if (ninternal > 0) {
-      k_karras<<<blocks(ninternal, 256), 256, 0, st>>>(ta, tb);
-      if (nt > 1) CC_HIP(hipMemsetAsync(s->tree_t.flag, 0, sizeof(uint32_t) * (nt - 1), st));
-      if (ne > 1) CC_HIP(hipMemsetAsync(s->tree_e.flag, 0, sizeof(uint32_t) * (ne - 1), st));
-      RefitView ra{nt, s->tree_t.child, s->tree_t.parent, s->tree_t.leaf_lo, s->tree_t.leaf_hi,
-                   s->tree_t.node_lo, s->tree_t.node_hi, s->tree_t.flag};
-      RefitView rb{ne, s->tree_e.child, s->tree_e.parent, s->tree_e.leaf_lo, s->tree_e.leaf_hi,
-                   s->tree_e.node_lo, s->tree_e.node_hi, s->tree_e.flag};
-      k_refit<<<blocks(m, 256), 256, 0, st>>>(ra, rb);
+    if (ninternal > 0) k_karras<<<blocks(ninternal, 256), 256, 0, st>>>(ta, tb);
+    if (nt == 1) k_single<<<1, 1, 0, st>>>(bt.node, bt.root, bt.leaf_lo, bt.leaf_hi, bt.leaf_prim);
+    if (ne == 1) k_single<<<1, 1, 0, st>>>(be.node, be.root, be.leaf_lo, be.leaf_hi, be.leaf_prim);
+    RefitView ra = refit_view(bt), rb = refit_view(be);
+    if (nt < 2) ra.n = 0;
+    if (ne < 2) rb.n = 0;
+    const int32_t nba = (ra.n + kBlk - 1) / kBlk, nbb = (rb.n + kBlk - 1) / kBlk;
+    if (nba + nbb > 0) {
+      k_refit_block<<<nba + nbb, kBlk, 0, st>>>(ra, rb, nba);
+      k_blk_sparse<<<2, 1024, 0, st>>>(ra, rb);
+      k_refit_top<<<blocks(ninternal, 256), 256, 0, st>>>(ra, rb);
     }
     TravArgs A;
-    A.tt = TravTree{nt, s->tree_t.child, s->tree_t.node_lo, s->tree_t.node_hi,
-                    s->tree_t.leaf_lo, s->tree_t.leaf_hi, s->tree_t.leaf_prim};
-    A.te = TravTree{ne, s->tree_e.child, s->tree_e.node_lo, s->tree_e.node_hi,
-                    s->tree_e.leaf_lo, s->tree_e.leaf_hi, s->tree_e.leaf_prim};
+    {
+      // 4-wide records (a tree of one leaf has the single record of k_single)
+      const int32_t wt = nt > 1 ? nt - 1 : nt, we = ne > 1 ? ne - 1 : ne;
+      if (wt > 0) k_wide<<<blocks(wt, 256), 256, 0, st>>>(bt.node, bt.wide, wt);
+      if (we > 0) k_wide<<<blocks(we, 256), 256, 0, st>>>(be.node, be.wide, we);
+    }
+    A.tt = TravTree{nt, bt.wide, bt.root, bt.leaf_prim};
+    A.te = TravTree{ne, be.wide, be.root, be.leaf_prim};
     A.x = x;
     A.tris = s->tris;
     A.edges = s->edges;
     A.stat = s->stat;
+    A.vorder = s->vorder;
     A.n = s->n;
     A.ne = ne;
     A.infl = infl;
     A.dmax2 = dmax * dmax;
     A.out = out;
-    A.dout = dout;
     A.cap = cap;
     A.cnt = s->dc;
     int64_t nq = (int64_t)s->n + ne;
@@ -606,9 +884,9 @@ int lbvh_search(cc_solver* s, const double* x, double dmax, uint64_t* out, doubl
   CC_HIP(hipStreamSynchronize(st));
   if (s->hc->err & 2ull) return CC_EOVERFLOW;
   *nfound = (int64_t)s->hc->n_out;
-  // algorithmic bytes of the traversal: queries, leaf and node boxes, output keys
-  s->st.kernel_bytes[CC_K_SEARCH] += 24.0 * s->n + 8.0 * ne + 36.0 * (double)m +
-                                     32.0 * (double)m + 8.0 * (double)*nfound;
+  // algorithmic bytes of the traversal: queries, node records, output keys
+  s->st.kernel_bytes[CC_K_SEARCH] += 24.0 * s->n + 8.0 * ne + 64.0 * (double)m +
+                                     8.0 * (double)*nfound;
   return CC_OK;
 }
 

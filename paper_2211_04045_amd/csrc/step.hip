@@ -176,36 +176,140 @@ struct PairPassArgs {
   int trace;
 };
 
+constexpr int kHash = 2048;         // LDS slots for the per-block D_i minimum
+constexpr int kPairsPerThread = 4;  // pairs per thread in the pair pass
+
+// Exclusive block-wide prefix sum of one int per thread; *total gets the sum.
+__device__ __forceinline__ int block_excl_scan(int v, int* sm, int* total) {
+  const int lane = __lane_id(), wv = threadIdx.x >> 6;
+  int incl = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    int t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) sm[wv] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int w = 0; w < kThreads / 64; ++w) {
+      int t = sm[w];
+      sm[w] = run;
+      run += t;
+    }
+    sm[kThreads / 64] = run;
+  }
+  __syncthreads();
+  int res = sm[wv] + incl - v;
+  *total = sm[kThreads / 64];
+  __syncthreads();
+  return res;
+}
+
+// Push the block's per-vertex minima to the global D_i and clear the table.
+__device__ __forceinline__ void flush_min_table(int32_t* hkey, unsigned long long* hval,
+                                                unsigned long long* Di) {
+  __syncthreads();
+  for (int t = threadIdx.x; t < kHash; t += kThreads) {
+    int32_t vv = hkey[t];
+    if (vv >= 0) {
+      unsigned long long b = hval[t];
+      if (b < Di[vv]) atomicMin(&Di[vv], b);
+      hkey[t] = -1;
+      hval[t] = ~0ull;
+    }
+  }
+  __syncthreads();
+}
+
 // Distances at x^(l) for every p in P; P' = {d^2 < D^2} (Sec. 3.1 filter),
 // A = {d^2 < delta^2} (Sec. 4.1 activation), D_i = min over P' of d (Sec. 5).
+// Each block handles kThreads*kPairsPerThread consecutive pairs. The minimum is
+// first taken in an LDS hash table keyed by vertex (flushed after every 256 pairs,
+// so it is never more than half full), then one global atomic per distinct vertex
+// (min is exact and order independent on the bit patterns of non-negative
+// doubles). P' and A are compacted with one counter atomic per block.
 __global__ void __launch_bounds__(kThreads) k_pair_pass(PairPassArgs a) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool valid = i < a.nP;
-  uint64_t key = valid ? a.P[i] : 0ull;
-  int32_t v[4] = {0, 0, 0, 0};
-  double d2 = __builtin_inf();
-  if (valid) {
-    pair_verts(a.T, key, v);
-    d2 = pair_d2(key_is_ee(key), ld3(a.x, v[0]), ld3(a.x, v[1]), ld3(a.x, v[2]), ld3(a.x, v[3]));
+  __shared__ int32_t hkey[kHash];
+  __shared__ unsigned long long hval[kHash];
+  __shared__ int ssc[kThreads / 64 + 1];
+  __shared__ unsigned long long sbase[2];
+  for (int t = threadIdx.x; t < kHash; t += kThreads) {
+    hkey[t] = -1;
+    hval[t] = ~0ull;
   }
-  bool keep = valid && d2 < a.D2;
-  bool act = keep && d2 < a.dl2;
-  unsigned long long pk = wave_append(keep, &a.c->n_out);
-  if (keep) {
-    a.Pout[pk] = key;
-    a.dPout[pk] = d2;
-    unsigned long long bits = (unsigned long long)__double_as_longlong(sqrt(d2));
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * (kThreads * kPairsPerThread);
+  uint64_t keys[kPairsPerThread];
+  double d2s[kPairsPerThread];
+  int4 vs[kPairsPerThread];
+  unsigned keepm = 0, actm = 0;
+  unsigned long long f1 = 0, f2 = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (bits < a.Di[v[k]]) atomicMin(&a.Di[v[k]], bits);
+  for (int k = 0; k < kPairsPerThread; ++k) {
+    const int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
+    keys[k] = 0;
+    d2s[k] = 0.0;
+    vs[k] = make_int4(0, 0, 0, 0);
+    if (i < a.nP) {
+      uint64_t key = a.P[i];
+      int32_t v[4];
+      pair_verts(a.T, key, v);
+      double d2 = pair_d2(key_is_ee(key), ld3(a.x, v[0]), ld3(a.x, v[1]), ld3(a.x, v[2]),
+                          ld3(a.x, v[3]));
+      keys[k] = key;
+      d2s[k] = d2;
+      vs[k] = make_int4(v[0], v[1], v[2], v[3]);
+      if (d2 < a.D2) {
+        keepm |= 1u << k;
+        if (a.trace) f1 += fp_key(key);
+        if (d2 < a.dl2) {
+          actm |= 1u << k;
+          if (a.trace) f2 += fp_key(key);
+        }
+        unsigned long long bits = (unsigned long long)__double_as_longlong(sqrt(d2));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          uint32_t h = ((uint32_t)v[q] * 2654435761u) >> 21;  // 11 bits
+          for (;;) {
+            int32_t prev = atomicCAS(&hkey[h], -1, v[q]);
+            if (prev == -1 || prev == v[q]) {
+              atomicMin(&hval[h], bits);
+              break;
+            }
+            h = (h + 1) & (kHash - 1);
+          }
+        }
+      }
+    }
+    flush_min_table(hkey, hval, a.Di);
   }
-  unsigned long long pa = wave_append(act, &a.c->n_act);
-  if (act && (int64_t)pa < a.capA) {
-    a.Akeys[pa] = key;
-    a.Averts[pa] = make_int4(v[0], v[1], v[2], v[3]);
+  // block-level compaction of P' and A
+  int nk = __popc(keepm), na = __popc(actm), tk = 0, ta = 0;
+  int ok = block_excl_scan(nk, ssc, &tk);
+  int oa = block_excl_scan(na, ssc, &ta);
+  if (threadIdx.x == 0) {
+    sbase[0] = tk ? atomicAdd(&a.c->n_out, (unsigned long long)tk) : 0ull;
+    sbase[1] = ta ? atomicAdd(&a.c->n_act, (unsigned long long)ta) : 0ull;
+  }
+  __syncthreads();
+  unsigned long long pk = sbase[0] + (unsigned long long)ok;
+  unsigned long long pa = sbase[1] + (unsigned long long)oa;
+#pragma unroll
+  for (int k = 0; k < kPairsPerThread; ++k) {
+    if (keepm & (1u << k)) {
+      a.Pout[pk] = keys[k];
+      a.dPout[pk] = d2s[k];
+      ++pk;
+    }
+    if (actm & (1u << k)) {
+      if ((int64_t)pa < a.capA) {
+        a.Akeys[pa] = keys[k];
+        a.Averts[pa] = vs[k];
+      }
+      ++pa;
+    }
   }
   if (a.trace) {
-    unsigned long long f1 = keep ? fp_key(key) : 0ull, f2 = act ? fp_key(key) : 0ull;
     f1 = wave_sum_u64(f1);
     f2 = wave_sum_u64(f2);
     if (__lane_id() == 0) {
@@ -231,7 +335,7 @@ int launch_pair_pass(cc_solver* s, double D2, double dl2, bool trace, hipStream_
   a.Di = s->Di;
   a.c = s->dc;
   a.trace = trace ? 1 : 0;
-  if (s->nP > 0) k_pair_pass<<<nblk(s->nP), kThreads, 0, st>>>(a);
+  if (s->nP > 0) k_pair_pass<<<nblk(s->nP, kThreads * kPairsPerThread), kThreads, 0, st>>>(a);
   CC_HIP(hipGetLastError());
   return CC_OK;
 }
@@ -263,85 +367,145 @@ struct RowSrc {
   }
 };
 
+constexpr int kRoundsPerSync = 8;  // colouring rounds launched between host reads
+constexpr int kTailRows = 4096;     // below this many rows one block finishes the rounds
+constexpr int kTailThreads = 1024;
+
 struct JpArgs {
   RowSrc src;
-  const int32_t* list;
-  int64_t nlist;
   const double* w;
   uint64_t seed;
-  unsigned long long* vcur;
-  unsigned long long* vnext;
   unsigned long long* masks;
   int maxc;
   int32_t* colors;
-  int32_t* list_out;
   Counters* c;
 };
 
 __device__ __forceinline__ bool is_free(const double* w, int32_t v) { return v >= 0 && w[v] > 0.0; }
 
-// Round part 1: every uncoloured row offers its priority to its free vertices.
-__global__ void __launch_bounds__(kThreads) k_jp_max(JpArgs a) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.nlist) return;
-  int32_t r = a.list[t];
+template <bool kAtomicLoads>
+__device__ __forceinline__ unsigned long long ld_u64(const unsigned long long* p) {
+  if (kAtomicLoads) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return *p;
+}
+
+// Round part 1: an uncoloured row offers its priority to its free vertices.
+// (The pre-check only skips atomics that cannot raise the value: in a fresh
+// kernel the buffer only grows; inside the single-block tail it is read with
+// atomic loads so that no stale cache line can hide a lower value.)
+template <bool kAtomicLoads>
+__device__ __forceinline__ void jp_offer(const JpArgs& a, int32_t r, unsigned long long* vcur) {
   uint64_t key;
   int32_t v[4];
   a.src.get(r, key, v);
   unsigned long long pr = (unsigned long long)mix64(key ^ a.seed);
 #pragma unroll
   for (int k = 0; k < 4; ++k)
-    if (is_free(a.w, v[k]) && pr > a.vcur[v[k]]) atomicMax(&a.vcur[v[k]], pr);
+    if (is_free(a.w, v[k]) && pr > ld_u64<kAtomicLoads>(&vcur[v[k]])) atomicMax(&vcur[v[k]], pr);
 }
 
 // Round part 2: a row holding the maximum at all its free vertices takes the
-// smallest colour not used at those vertices (Jones-Plassmann); the others go to
-// the next round's list. The other priority buffer is cleared for the next round.
-__global__ void __launch_bounds__(kThreads) k_jp_pick(JpArgs a) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool valid = t < a.nlist;
-  bool lose = false;
-  int32_t r = 0;
-  if (valid) {
-    r = a.list[t];
-    uint64_t key;
-    int32_t v[4];
-    a.src.get(r, key, v);
-    unsigned long long pr = (unsigned long long)mix64(key ^ a.seed);
-    bool win = true;
+// smallest colour not used at those vertices (Jones-Plassmann); it returns true
+// when the row stays uncoloured. The other priority buffer is cleared at the
+// row's vertices for the next round.
+template <bool kAtomicLoads>
+__device__ __forceinline__ bool jp_pick(const JpArgs& a, int32_t r,
+                                        const unsigned long long* vcur,
+                                        unsigned long long* vnext) {
+  uint64_t key;
+  int32_t v[4];
+  a.src.get(r, key, v);
+  unsigned long long pr = (unsigned long long)mix64(key ^ a.seed);
+  bool win = true;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (is_free(a.w, v[k])) {
+      if (ld_u64<kAtomicLoads>(&vcur[v[k]]) != pr) win = false;
+      vnext[v[k]] = 0ull;
+    }
+  if (!win) return true;
+  int col = -1;
+  const int W = (a.maxc + 63) / 64;
+  for (int wd = 0; wd < W && col < 0; ++wd) {
+    unsigned long long used = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-      if (is_free(a.w, v[k])) {
-        if (a.vcur[v[k]] != pr) win = false;
-        a.vnext[v[k]] = 0ull;
-      }
-    if (win) {
-      int col = -1;
-      const int W = (a.maxc + 63) / 64;
-      for (int wd = 0; wd < W && col < 0; ++wd) {
-        unsigned long long used = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-          if (is_free(a.w, v[k])) used |= a.masks[(int64_t)v[k] * kMaskWords + wd];
-        if (~used) col = 64 * wd + (__ffsll((long long)~used) - 1);
-      }
-      if (col < 0 || col >= a.maxc) {
-        atomicOr(&a.c->err, 1ull);
-        col = 0;
-      } else {
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-          if (is_free(a.w, v[k]))
-            atomicOr(&a.masks[(int64_t)v[k] * kMaskWords + col / 64], 1ull << (col % 64));
-      }
-      a.colors[r] = col;
-      atomicMax(&a.c->ncol, (unsigned long long)(col + 1));
-    } else {
-      lose = true;
-    }
+      if (is_free(a.w, v[k])) used |= ld_u64<kAtomicLoads>(&a.masks[(int64_t)v[k] * kMaskWords + wd]);
+    if (~used) col = 64 * wd + (__ffsll((long long)~used) - 1);
   }
-  unsigned long long pos = wave_append(lose, &a.c->n_left);
-  if (lose) a.list_out[pos] = r;
+  if (col < 0 || col >= a.maxc) {
+    atomicOr(&a.c->err, 1ull);
+    col = 0;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (is_free(a.w, v[k]))
+        atomicOr(&a.masks[(int64_t)v[k] * kMaskWords + col / 64], 1ull << (col % 64));
+  }
+  a.colors[r] = col;
+  atomicMax(&a.c->ncol, (unsigned long long)(col + 1));
+  return false;
+}
+
+// One round over a list whose length lives on the device (rounds are launched
+// ahead of the host knowing how many rows are left).
+__global__ void __launch_bounds__(kThreads) k_jp_max(JpArgs a, const int32_t* list,
+                                                     const unsigned long long* nlist,
+                                                     unsigned long long* vcur) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)*nlist) return;
+  jp_offer<false>(a, list[t], vcur);
+}
+
+__global__ void __launch_bounds__(kThreads) k_jp_pick(JpArgs a, const int32_t* list,
+                                                      const unsigned long long* nlist,
+                                                      const unsigned long long* vcur,
+                                                      unsigned long long* vnext,
+                                                      int32_t* list_out,
+                                                      unsigned long long* nout) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool valid = t < (int64_t)*nlist;
+  int32_t r = valid ? list[t] : 0;
+  bool lose = valid && jp_pick<false>(a, r, vcur, vnext);
+  unsigned long long pos = wave_append(lose, nout);
+  if (lose) list_out[pos] = r;
+}
+
+// The remaining rounds in one block: global atomics for the priorities and
+// masks, atomic loads to read them back, block barriers between the phases.
+__global__ void __launch_bounds__(kTailThreads) k_jp_tail(JpArgs a, int32_t* la, int32_t* lb,
+                                                          const unsigned long long* nlist,
+                                                          unsigned long long* v0,
+                                                          unsigned long long* v1, int parity) {
+  __shared__ int32_t ncur, nnext;
+  if (threadIdx.x == 0) {
+    ncur = (int32_t)*nlist;
+    nnext = 0;
+  }
+  __syncthreads();
+  int32_t* cur = la;
+  int32_t* nxt = lb;
+  int round = parity;
+  while (ncur > 0) {
+    unsigned long long* vcur = (round & 1) ? v1 : v0;
+    unsigned long long* vnext = (round & 1) ? v0 : v1;
+    for (int32_t t = threadIdx.x; t < ncur; t += kTailThreads) jp_offer<true>(a, cur[t], vcur);
+    __syncthreads();
+    for (int32_t t = threadIdx.x; t < ncur; t += kTailThreads) {
+      int32_t r = cur[t];
+      if (jp_pick<true>(a, r, vcur, vnext)) nxt[atomicAdd(&nnext, 1)] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      ncur = nnext;
+      nnext = 0;
+    }
+    int32_t* t = cur;
+    cur = nxt;
+    nxt = t;
+    ++round;
+    __syncthreads();
+  }
 }
 
 __global__ void k_iota(int32_t* p, int64_t n) {
@@ -349,20 +513,42 @@ __global__ void k_iota(int32_t* p, int64_t n) {
   if (i < n) p[i] = (int32_t)i;
 }
 
-__global__ void k_col_hist(const int32_t* __restrict__ list, int64_t n,
-                           const int32_t* __restrict__ colors, int32_t* __restrict__ cnt) {
+// Colour buckets: per-block histograms in LDS, one global atomic per block and colour.
+__global__ void __launch_bounds__(kThreads) k_bucket_count(const int32_t* __restrict__ list,
+                                                           int64_t n,
+                                                           const int32_t* __restrict__ colors,
+                                                           int32_t ncol, int32_t* __restrict__ cnt) {
+  __shared__ int32_t h[kMaxColors];
+  for (int c = threadIdx.x; c < ncol; c += kThreads) h[c] = 0;
+  __syncthreads();
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) atomicAdd(&cnt[colors[list ? list[i] : i]], 1);
+  if (i < n) atomicAdd(&h[colors[list ? list[i] : i]], 1);
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncol; c += kThreads)
+    if (h[c]) atomicAdd(&cnt[c], h[c]);
 }
 
-__global__ void k_col_scatter(const int32_t* __restrict__ list, int64_t n,
-                              const int32_t* __restrict__ colors, int32_t* __restrict__ cursor,
-                              int32_t* __restrict__ order) {
+__global__ void __launch_bounds__(kThreads) k_bucket_scatter(const int32_t* __restrict__ list,
+                                                             int64_t n,
+                                                             const int32_t* __restrict__ colors,
+                                                             int32_t ncol,
+                                                             int32_t* __restrict__ cursor,
+                                                             int32_t* __restrict__ order) {
+  __shared__ int32_t h[kMaxColors];
+  for (int c = threadIdx.x; c < ncol; c += kThreads) h[c] = 0;
+  __syncthreads();
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int32_t r = list ? list[i] : (int32_t)i;
-  int32_t pos = atomicAdd(&cursor[colors[r]], 1);
-  order[pos] = r;
+  int32_t r = 0, c = 0, rank = 0;
+  if (i < n) {
+    r = list ? list[i] : (int32_t)i;
+    c = colors[r];
+    rank = atomicAdd(&h[c], 1);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < ncol; k += kThreads)
+    if (h[k]) h[k] = atomicAdd(&cursor[k], h[k]);
+  __syncthreads();
+  if (i < n) order[h[c] + rank] = r;
 }
 
 // Colour the contact rows (A) or the edge-length rows and bucket them by colour.
@@ -393,6 +579,8 @@ int color_rows(cc_solver* s, bool edges, hipStream_t st) {
   CC_HIP(hipMemsetAsync(s->masks, 0, sizeof(unsigned long long) * s->n * kMaskWords, st));
   CC_HIP(hipMemsetAsync(&s->dc->ncol, 0, sizeof(unsigned long long), st));
   CC_HIP(hipMemsetAsync(&s->dc->err, 0, sizeof(unsigned long long), st));
+  CC_HIP(hipMemsetAsync(s->rcnt, 0, sizeof(unsigned long long) * (kMaxRounds + 1), st));
+  CC_TRY(launch_fill_u64(s->rcnt, 1, (unsigned long long)nrows, st));
   JpArgs a;
   a.src = RowSrc{s->Akeys, s->Averts, s->edges, edges ? 1 : 0};
   a.w = s->w;
@@ -401,39 +589,50 @@ int color_rows(cc_solver* s, bool edges, hipStream_t st) {
   a.maxc = s->p.max_colors;
   a.colors = colors;
   a.c = s->dc;
-  int64_t ncur = nrows;
+  int64_t known = nrows;  // upper bound of the current list length
   int round = 0;
-  while (ncur > 0) {
-    a.list = cur;
-    a.nlist = ncur;
-    a.vcur = (round & 1) ? s->vmax1 : s->vmax0;
-    a.vnext = (round & 1) ? s->vmax0 : s->vmax1;
-    a.list_out = nxt;
-    CC_HIP(hipMemsetAsync(&s->dc->n_left, 0, sizeof(unsigned long long), st));
-    k_jp_max<<<nblk(ncur), kThreads, 0, st>>>(a);
-    k_jp_pick<<<nblk(ncur), kThreads, 0, st>>>(a);
+  for (;;) {
+    if (known <= kTailRows) {
+      k_jp_tail<<<1, kTailThreads, 0, st>>>(a, cur, nxt, s->rcnt + round, s->vmax0, s->vmax1,
+                                            round & 1);
+      break;
+    }
+    if (round + kRoundsPerSync > kMaxRounds) return CC_ECOLOR;
+    for (int b = 0; b < kRoundsPerSync; ++b) {
+      unsigned long long* vcur = (round & 1) ? s->vmax1 : s->vmax0;
+      unsigned long long* vnext = (round & 1) ? s->vmax0 : s->vmax1;
+      k_jp_max<<<nblk(known), kThreads, 0, st>>>(a, cur, s->rcnt + round, vcur);
+      k_jp_pick<<<nblk(known), kThreads, 0, st>>>(a, cur, s->rcnt + round, vcur, vnext, nxt,
+                                                  s->rcnt + round + 1);
+      int32_t* t = cur;
+      cur = nxt;
+      nxt = t;
+      ++round;
+    }
     CC_HIP(hipGetLastError());
-    CC_HIP(hipMemcpyAsync(s->hc, s->dc, sizeof(Counters), hipMemcpyDeviceToHost, st));
+    CC_HIP(hipMemcpyAsync(&s->hc->n_left, s->rcnt + round, sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, st));
     CC_HIP(hipStreamSynchronize(st));
-    if (s->hc->err & 1ull) return CC_ECOLOR;
-    int64_t left = (int64_t)s->hc->n_left;
-    if (left >= ncur) return CC_EHIP;  // no progress is impossible for unique priorities
-    ncur = left;
-    int32_t* t = cur;
-    cur = nxt;
-    nxt = t;
-    ++round;
+    known = (int64_t)s->hc->n_left;
+    if (known == 0) break;
   }
+  CC_HIP(hipGetLastError());
+  CC_HIP(hipMemcpyAsync(s->hc, s->dc, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  CC_HIP(hipStreamSynchronize(st));
+  if (s->hc->err & 1ull) return CC_ECOLOR;
   const int32_t ncol = (int32_t)s->hc->ncol;
   CC_HIP(hipMemsetAsync(s->col_cnt, 0, sizeof(int32_t) * (ncol + 1), st));
-  k_col_hist<<<nblk(nrows), kThreads, 0, st>>>(base_list, nrows, colors, s->col_cnt);
+  k_bucket_count<<<nblk(nrows), kThreads, 0, st>>>(base_list, nrows, colors, ncol, s->col_cnt);
   std::vector<int32_t> cnt(ncol);
   CC_HIP(hipMemcpyAsync(cnt.data(), s->col_cnt, sizeof(int32_t) * ncol, hipMemcpyDeviceToHost, st));
   CC_HIP(hipStreamSynchronize(st));
   off.assign(ncol + 1, 0);
   for (int c = 0; c < ncol; ++c) off[c + 1] = off[c] + cnt[c];
   CC_HIP(hipMemcpyAsync(s->col_cnt, off.data(), sizeof(int32_t) * ncol, hipMemcpyHostToDevice, st));
-  k_col_scatter<<<nblk(nrows), kThreads, 0, st>>>(base_list, nrows, colors, s->col_cnt, order);
+  k_bucket_scatter<<<nblk(nrows), kThreads, 0, st>>>(base_list, nrows, colors, ncol, s->col_cnt,
+                                                    order);
+  CC_HIP(hipMemcpyAsync(edges ? s->ecoff_dev : s->coff_dev, off.data(), sizeof(int32_t) * (ncol + 1),
+                        hipMemcpyHostToDevice, st));
   CC_HIP(hipGetLastError());
   if (edges) s->n_ecolors = ncol; else s->n_colors = ncol;
   return CC_OK;
@@ -456,12 +655,13 @@ struct GsArgs {
   double delta, kappa2, sigma;
 };
 
-// One projected Gauss-Seidel update per contact row of this colour (Sec. 4.3):
-// residual w = c0 + sum J.(y - x), lambda <- max(0, lambda - w/A), y += w_v dl J_v.
-__global__ void __launch_bounds__(kThreads) k_gs_contact(GsArgs a) {
-  int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.cnt) return;
-  int32_t r = a.order[t];
+constexpr int kGsTailRows = 2048;   // colours smaller than this run in one block
+constexpr int kGsTailThreads = 1024;
+
+// One projected Gauss-Seidel update of a contact row (Sec. 4.3): the row is
+// linearised at x^(l) (Sec. 4), residual w = c0 + sum J.(y - x),
+// lambda <- max(0, lambda - w/A), y_v += w_v dl J_v at its free vertices.
+__device__ __forceinline__ void gs_contact_update(const GsArgs& a, int32_t r) {
   uint64_t key = a.Akeys[r];
   int4 q = a.Averts[r];
   int32_t v[4] = {q.x, q.y, q.z, q.w};
@@ -496,11 +696,8 @@ __global__ void __launch_bounds__(kThreads) k_gs_contact(GsArgs a) {
   }
 }
 
-// Edge-length rows of this colour (Sec. 4.2), same projected update.
-__global__ void __launch_bounds__(kThreads) k_gs_edge(GsArgs a) {
-  int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.cnt) return;
-  int32_t e = a.order[t];
+// Edge-length row (Sec. 4.2), same projected update.
+__device__ __forceinline__ void gs_edge_update(const GsArgs& a, int32_t e) {
   int32_t i = a.edges[2 * e], j = a.edges[2 * e + 1];
   V3 g = ld3(a.eg, e);
   V3 yi = ld3(a.y, i), yj = ld3(a.y, j);
@@ -522,6 +719,54 @@ __global__ void __launch_bounds__(kThreads) k_gs_edge(GsArgs a) {
   }
 }
 
+// One colour, one row per thread (rows of a colour share no free vertex).
+__global__ void __launch_bounds__(kThreads) k_gs_contact(GsArgs a) {
+  int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < a.cnt) gs_contact_update(a, a.order[t]);
+}
+
+__global__ void __launch_bounds__(kThreads) k_gs_edge(GsArgs a) {
+  int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < a.cnt) gs_edge_update(a, a.order[t]);
+}
+
+// A run of small colours [c0, c1) in one block, colour after colour with a block
+// barrier between them; `off` holds the colour bucket offsets on the device.
+__global__ void __launch_bounds__(kGsTailThreads) k_gs_tail(GsArgs a, const int32_t* off,
+                                                            int32_t c0, int32_t c1, int is_edge) {
+  for (int32_t c = c0; c < c1; ++c) {
+    const int32_t b = off[c], e = off[c + 1];
+    for (int32_t t = b + threadIdx.x; t < e; t += kGsTailThreads) {
+      if (is_edge) gs_edge_update(a, a.order[t]);
+      else gs_contact_update(a, a.order[t]);
+    }
+    __syncthreads();
+  }
+}
+
+static void gs_colours(const GsArgs& base, const int32_t* order, const std::vector<int32_t>& off,
+                       const int32_t* off_dev, int32_t ncol, bool edge, hipStream_t st) {
+  GsArgs a = base;
+  int32_t c = 0;
+  while (c < ncol) {
+    int32_t cnt = off[c + 1] - off[c];
+    if (cnt >= kGsTailRows) {
+      a.order = order + off[c];
+      a.cnt = cnt;
+      if (edge) k_gs_edge<<<nblk(cnt), kThreads, 0, st>>>(a);
+      else k_gs_contact<<<nblk(cnt), kThreads, 0, st>>>(a);
+      ++c;
+      continue;
+    }
+    int32_t c1 = c;
+    while (c1 < ncol && off[c1 + 1] - off[c1] < kGsTailRows) ++c1;
+    a.order = order;
+    a.cnt = 0;
+    k_gs_tail<<<1, kGsTailThreads, 0, st>>>(a, off_dev, c, c1, edge ? 1 : 0);
+    c = c1;
+  }
+}
+
 int launch_gs(cc_solver* s, hipStream_t st) {
   GsArgs a;
   a.Akeys = s->Akeys;
@@ -539,17 +784,9 @@ int launch_gs(cc_solver* s, hipStream_t st) {
   if (s->n_erows > 0) CC_HIP(hipMemsetAsync(s->lamE, 0, sizeof(double) * s->ne, st));
   for (int sw = 0; sw < s->p.gs_sweeps; ++sw) {
     a.lam = s->lamA;
-    for (int c = 0; c < s->n_colors; ++c) {
-      a.order = s->Aorder + s->col_off[c];
-      a.cnt = s->col_off[c + 1] - s->col_off[c];
-      if (a.cnt > 0) k_gs_contact<<<nblk(a.cnt), kThreads, 0, st>>>(a);
-    }
+    gs_colours(a, s->Aorder, s->col_off, s->coff_dev, s->n_colors, false, st);
     a.lam = s->lamE;
-    for (int c = 0; c < s->n_ecolors; ++c) {
-      a.order = s->eorder + s->ecol_off[c];
-      a.cnt = s->ecol_off[c + 1] - s->ecol_off[c];
-      if (a.cnt > 0) k_gs_edge<<<nblk(a.cnt), kThreads, 0, st>>>(a);
-    }
+    gs_colours(a, s->eorder, s->ecol_off, s->ecoff_dev, s->n_ecolors, true, st);
   }
   CC_HIP(hipGetLastError());
   return CC_OK;
@@ -561,6 +798,7 @@ int launch_gs(cc_solver* s, hipStream_t st) {
 // x_i <- y_i if alpha_i = 1 else x_i + alpha_i (y_i - x_i), r_i <- r_i (1 - alpha_i);
 // max ||x_i^(l+1) - x_i^(l)|| and ||r||_inf for Alg. 1.
 __global__ void __launch_bounds__(kThreads) k_forward(double* __restrict__ x,
+                                                      double* __restrict__ xold,
                                                       const double* __restrict__ y,
                                                       const unsigned long long* __restrict__ Di,
                                                       double* __restrict__ r,
@@ -582,6 +820,7 @@ __global__ void __launch_bounds__(kThreads) k_forward(double* __restrict__ x,
     V3 mv = vsub(xn, xi);
     double m2 = vdot(mv, mv);
     move2[i] = m2;
+    st3(xold, i, xi);
     st3(x, i, xn);
     double ri = r[i] * (1.0 - alpha);
     r[i] = ri;
@@ -611,7 +850,8 @@ __global__ void __launch_bounds__(kThreads) k_forward(double* __restrict__ x,
 int launch_forward(cc_solver* s, hipStream_t st) {
   const double hg = 0.5 * s->p.gamma;
   if (s->n > 0)
-    k_forward<<<nblk(s->n), kThreads, 0, st>>>(s->x, s->y, s->Di, s->r, s->move2, s->n, hg, s->dc);
+    k_forward<<<nblk(s->n), kThreads, 0, st>>>(s->x, s->xold, s->y, s->Di, s->r, s->move2, s->n, hg,
+                                                s->dc);
   CC_HIP(hipGetLastError());
   return CC_OK;
 }
@@ -619,16 +859,20 @@ int launch_forward(cc_solver* s, hipStream_t st) {
 // ------------------------------------------------------------- certificate
 
 // Lemma of Sec. 5: the linear piece x^(l) -> x^(l+1) stays free for pair p when
-// no vertex of p moved half its distance, i.e. 4 max_v |dx_v|^2 < d_p^2.
+// no vertex of p moved half its distance, i.e. 4 max_v |dx_v|^2 < d_p^2. A pair the
+// bound does not certify gets the continuous test of the piece (ccd_hit).
 __global__ void __launch_bounds__(kThreads) k_cert(const uint64_t* __restrict__ P,
                                                    const double* __restrict__ dP, int64_t nP,
                                                    Topo T, const double* __restrict__ move2,
+                                                   const double* __restrict__ xold,
+                                                   const double* __restrict__ x, double eta2,
                                                    Counters* c) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool bad = false;
+  bool bad = false, hit = false;
   if (i < nP) {
     int32_t v[4];
-    pair_verts(T, P[i], v);
+    uint64_t key = P[i];
+    pair_verts(T, key, v);
     double mv = move2[v[0]];
 #pragma unroll
     for (int k = 1; k < 4; ++k) {
@@ -636,16 +880,28 @@ __global__ void __launch_bounds__(kThreads) k_cert(const uint64_t* __restrict__ 
       if (m > mv) mv = m;
     }
     bad = !(4.0 * mv < dP[i]);
+    if (bad) {
+      V3 q[4], dq[4];
+      for (int k = 0; k < 4; ++k) {
+        q[k] = ld3(xold, v[k]);
+        dq[k] = vsub(ld3(x, v[k]), q[k]);
+      }
+      hit = ccd_hit(q, dq, key_is_ee(key), eta2);
+    }
   }
   uint64_t m = __ballot(bad);
   if (m && __lane_id() == __ffsll((long long)m) - 1)
     atomicAdd(&c->fail, (unsigned long long)__popcll(m));
+  uint64_t h = __ballot(hit);
+  if (h && __lane_id() == __ffsll((long long)h) - 1)
+    atomicAdd(&c->hits, (unsigned long long)__popcll(h));
 }
 
 int launch_cert(cc_solver* s, hipStream_t st) {
+  const double eta = kCcdEta;
   if (s->nP > 0)
     k_cert<<<nblk(s->nP), kThreads, 0, st>>>(s->P, s->dP, s->nP, Topo{s->tris, s->edges},
-                                              s->move2, s->dc);
+                                              s->move2, s->xold, s->x, eta * eta, s->dc);
   CC_HIP(hipGetLastError());
   return CC_OK;
 }

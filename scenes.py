@@ -356,3 +356,35 @@ def config(i: int, small: bool = False):
     if i == 4:
         return hair(n_strands=64 if small else 10000, segs=8 if small else 32)
     raise ValueError(i)
+
+
+def serve_request(i: int, t_min: float = 2000.0, t_max: float = 150000.0):
+    """Request i of the serving stream: family uniform in {cloth over sphere,
+    folded cloth, stacked cubes}, target triangle count log-uniform in
+    [t_min, t_max] rounded to the nearest size the family can realise; seed 1005+i.
+    Returns the scene dict with its time step h."""
+    rng = np.random.default_rng(1005 + i)
+    fam = int(rng.integers(1, 4))
+    T = float(np.exp(rng.uniform(np.log(t_min), np.log(t_max))))
+    if fam == 1:
+        n = max(3, int(round(1.0 + np.sqrt(T / 2.0))))
+        sc = cloth_over_sphere(n=n, seed=1005 + i)
+        h = 1.0 / 30.0
+    elif fam == 2:
+        rows = max(1, int(round(np.sqrt(T / 2.0) / 4.0)))
+        sc = folded_cloth(layer_rows=rows, seed=1005 + i)
+        h = 1.0 / 30.0
+    else:
+        c = max(1, int(round(np.sqrt(T / 96.0))))
+        sc = stacked_cubes(n_cubes=8, cells=c, seed=1005 + i)
+        h = 0.1
+    sc["family"] = fam
+    sc["h"] = h
+    sc["name"] = f"req{i}_" + sc["name"]
+    return sc
+
+
+def poisson_arrivals(n: int, rate: float, seed: int = 2005) -> np.ndarray:
+    """Arrival times (s) of n requests of a Poisson process of the given rate."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))

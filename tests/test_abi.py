@@ -10,7 +10,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared():
     src = open(os.path.join(ROOT, "include", "cc.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(cc_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|void|size_t|const char\*)\s+(cc_\w+)\s*\(", src, re.M)))
 
 
 def test_header_declares_the_step_and_solver_api():
@@ -42,5 +42,5 @@ def test_default_params_are_table_2():
 def test_strerror_names_every_code():
     from paper_2211_04045_amd import _lib
     lib = _lib.load()
-    for code in range(0, -7, -1):
+    for code in range(0, -9, -1):
         assert lib.cc_strerror(code) != b"unknown error"

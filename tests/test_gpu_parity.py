@@ -12,7 +12,7 @@ import scenes
 
 pytestmark = pytest.mark.gpu
 
-TRACE_KEYS = ["searched", "n_colors", "n_p", "n_pf", "n_a", "ccd_fail", "d_before", "d_after",
+TRACE_KEYS = ["searched", "n_colors", "n_p", "n_pf", "n_a", "ccd_fail", "ccd_hits", "d_before", "d_after",
               "move_max", "r_inf", "fp_pf", "fp_a", "fp_col"]
 
 
@@ -218,3 +218,101 @@ def test_errors_are_reported(cc, ctx):
     with pytest.raises(cc.CCError) as e:
         cc.collide_step(ctx, sc["x"], sc["xt"], sc["w"], sc["tris"], sc["edges"], max_colors=2)
     assert e.value.code == -5
+
+
+def test_batched_equals_solo_and_oracle(cc, ctx):
+    """Scenes of uneven sizes in one batched call: every result is bit-identical to
+    the scene run alone and to the oracle."""
+    batch = [scenes.config(2, small=True), scenes.config(3, small=True),
+             scenes.config(4, small=True), scenes.config(2, small=True),
+             scenes.folded_cloth(layer_rows=4)]
+    for sc in batch:
+        sc["params"] = dict(sc["params"], max_iters=300)
+    res = cc.collide_step_batched(ctx, batch, max_iters=300)
+    assert len(res) == len(batch)
+    for sc, (x_b, st_b) in zip(batch, res):
+        x_s, st_s = cc.collide_step(ctx, sc["x"], sc["xt"], sc["w"], sc["tris"], sc["edges"],
+                                    max_iters=300)
+        want, n, _ = oracle.collide_step(sc, max_iters=300)
+        assert np.array_equal(x_b.cpu().numpy(), x_s.cpu().numpy())
+        assert np.array_equal(x_b.cpu().numpy(), want)
+        assert st_b["iters"] == st_s["iters"] == n
+    # a second call reuses the slots
+    res2 = cc.collide_step_batched(ctx, batch, max_iters=300)
+    for (a, _), (b, _) in zip(res, res2):
+        assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+def _next_target(x_prev, x_new, h, w):
+    """x~_{n+1} = x_{n+1} + h v + h^2 g with v = (x_{n+1} - x_n)/h; pinned vertices stay."""
+    g = np.array([0.0, 0.0, -9.81])
+    v = (x_new - x_prev) / h
+    xt = x_new + h * v + h * h * g
+    xt[w == 0] = x_new[w == 0]
+    return xt
+
+
+def test_served_scenes_in_a_mix_equal_the_same_steps_alone(cc, ctx):
+    import time
+    srv = cc.Server(ctx, budget_bytes=0)
+    mix = [scenes.config(2, small=True), scenes.config(3, small=True),
+           scenes.config(4, small=True), scenes.folded_cloth(layer_rows=4)]
+    hs = [srv.admit(sc["x"], sc["w"], sc["tris"], sc["edges"], max_iters=400) for sc in mix]
+    prev = [sc["x"].copy() for sc in mix]
+    cur = [sc["x"].copy() for sc in mix]
+    xt = [sc["xt"].copy() for sc in mix]
+    for step in range(3):
+        for h, t in zip(hs, xt):
+            srv.submit(h, t)
+        done = [None] * len(mix)
+        t0 = time.time()
+        while any(d is None for d in done):
+            for i, h in enumerate(hs):
+                if done[i] is None:
+                    done[i] = srv.poll(h)
+            assert time.time() - t0 < 120
+        for i, sc in enumerate(mix):
+            got = done[i][0].cpu().numpy()
+            alone, _ = cc.collide_step(ctx, cur[i], xt[i], sc["w"], sc["tris"], sc["edges"],
+                                       max_iters=400)
+            assert np.array_equal(got, alone.cpu().numpy()), (i, step)
+            prev[i], cur[i] = cur[i], got
+            xt[i] = _next_target(prev[i], cur[i], 1.0 / 30.0, sc["w"])
+    for h in hs:
+        srv.release(h)
+
+
+def test_admission_respects_the_budget(cc, ctx):
+    srv = cc.Server(ctx)
+    sc = scenes.config(2, small=True)
+    need = srv.scene_bytes(len(sc["x"]), len(sc["tris"]), len(sc["edges"]))
+    srv2 = cc.Server(ctx, budget_bytes=int(need * 1.5))
+    h1 = srv2.admit(sc["x"], sc["w"], sc["tris"], sc["edges"])
+    assert h1 is not None
+    assert srv2.admit(sc["x"], sc["w"], sc["tris"], sc["edges"]) is None  # over budget
+    srv2.release(h1)
+    h2 = srv2.admit(sc["x"], sc["w"], sc["tris"], sc["edges"])
+    assert h2 is not None
+    srv2.release(h2)
+    cc.Server(ctx, budget_bytes=0)  # back to unlimited for later tests
+
+
+def test_stream_serving_results_equal_alone(cc, ctx):
+    """Requests of mixed families and sizes, staggered arrivals and a budget that
+    holds only some of them at once: every request's final state after 3 steps
+    equals the same 3 steps run alone with collide_step."""
+    import torch
+    from paper_2211_04045_amd import serve
+    reqs = [scenes.serve_request(i, t_min=300.0, t_max=3000.0) for i in range(6)]
+    need = [cc.Server(ctx).scene_bytes(len(r["x"]), len(r["tris"]), len(r["edges"])) for r in reqs]
+    budget = int(sum(sorted(need)[-3:]))  # at most about three resident at once
+    arrivals = np.array([0.0, 0.0, 0.01, 0.02, 0.02, 0.05])
+    res = serve.run_stream(ctx, reqs, arrivals, steps=3, budget_bytes=budget, keep_results=True,
+                           max_iters=300)
+    cc.Server(ctx, 0)
+    assert res["steps"] == 18 and len(res["latency"]) == 18
+    assert res["peak_bytes"] <= budget
+    for i, r in enumerate(reqs):
+        x_alone, its = serve.run_alone(ctx, r, steps=3, max_iters=300)
+        assert its == res["results"][i]["iters"], (i, r["name"])
+        assert torch.equal(x_alone, res["results"][i]["x"]), (i, r["name"])

@@ -442,3 +442,63 @@ def test_hair_like_polylines_stay_separated():
         for g in range(5, 10):
             d2 = exact.seg_seg_d2(*(xf[i] for i in (*edges[e], *edges[g])))
             assert d2 > 0
+
+
+# ------------------------------------------------------------ continuous test
+
+def _rand_frame(rng):
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    return q
+
+
+def test_ccd_vertex_through_triangle_hits_at_the_crossing_time():
+    rng = np.random.default_rng(11)
+    for trial in range(100):
+        R = _rand_frame(rng)
+        tri = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], float) * 0.01
+        bc = rng.dirichlet([2, 2, 2])
+        p_cross = bc @ tri
+        t_star = rng.uniform(0.1, 0.9)
+        vel = np.array([rng.uniform(-0.3, 0.3), rng.uniform(-0.3, 0.3), -1.0]) * 0.004
+        p0 = p_cross - t_star * vel
+        q = np.vstack([p0, tri]) @ R.T + rng.normal(size=3) * 0.02
+        dq = np.vstack([vel, np.zeros((3, 3))]) @ R.T
+        hit, t = oracle.ccd_hit(q, dq, ee=False)
+        assert hit and abs(t - t_star) < 1e-6, (trial, hit, t, t_star)
+
+
+def test_ccd_edges_crossing_hit_and_clear_misses_do_not():
+    rng = np.random.default_rng(12)
+    for trial in range(100):
+        R = _rand_frame(rng)
+        t_star = rng.uniform(0.1, 0.9)
+        e1 = np.array([[-1, 0, 0], [1, 0, 0]], float) * 0.005
+        e2 = np.array([[0, -1, 0], [0, 1, 0]], float) * 0.005
+        s = rng.uniform(-0.6, 0.6)
+        e2[:, 0] += s * 0.005
+        vel = np.array([0.0, 0.0, -0.004])
+        e1_0 = e1 - t_star * vel
+        q = np.vstack([e1_0, e2]) @ R.T
+        dq = np.vstack([vel, vel, [0, 0, 0], [0, 0, 0]]) @ R.T
+        hit, t = oracle.ccd_hit(q, dq, ee=True)
+        assert hit and abs(t - t_star) < 1e-6
+        # the same motion shifted sideways beyond the other edge's end never touches
+        q_miss = q.copy()
+        q_miss[2:] += (np.array([0.02, 0, 0]) @ R.T)
+        hit, _ = oracle.ccd_hit(q_miss, dq, ee=True)
+        ts = np.linspace(0, 1, 4001)
+        dmin = min(oracle.seg_seg_d2(*(q_miss + t_ * dq))[0] for t_ in ts) ** 0.5
+        assert dmin > 1e-3 and not hit
+
+
+def test_ccd_contact_at_the_end_of_the_piece():
+    # the vertex arrives exactly on the triangle at t = 1; stopping 0.1 mm short misses
+    tri = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], float) * 0.01
+    q = np.vstack([[0.004, 0.004, 0.002], tri])
+    dq = np.zeros((4, 3))
+    dq[0] = [0.0, 0.0, -0.002]
+    hit, t = oracle.ccd_hit(q, dq, ee=False)
+    assert hit and abs(t - 1.0) < 1e-12
+    dq[0] = [0.0, 0.0, -0.0019]
+    hit, _ = oracle.ccd_hit(q, dq, ee=False)
+    assert not hit
