@@ -60,6 +60,10 @@ enum { CC_CONVERGED = 0, CC_MAXITER = 1 };
 #define CC_EDGE_LEN 1u      /* edge-length constraints on (Sec. 4.2); default on */
 #define CC_TIME_KERNELS 2u  /* time kernel families with HIP events */
 #define CC_TRACE 4u         /* per-iteration set fingerprints */
+#define CC_MIXED 8u         /* mixed precision: the backward step (constraint values,
+                               Jacobians, multipliers and y - x) in FP32; every set
+                               decision, distance, D_i, x, the forward step and the
+                               continuous test stay FP64 */
 
 /* Parameters; defaults are Table 2 of the paper (cc_default_params). */
 typedef struct cc_params {
@@ -73,7 +77,7 @@ typedef struct cc_params {
   int32_t max_iters; /* L: 512 (dt = 1/100 s) .. 2048 (dt = 1/20 s) */
   int32_t gs_sweeps; /* Gauss-Seidel sweeps per backward step, 1 (Sec. 4.3.1) */
   int32_t max_colors;/* colour palette, <= 1024 */
-  uint32_t flags;    /* CC_EDGE_LEN | CC_TIME_KERNELS | CC_TRACE */
+  uint32_t flags;    /* CC_EDGE_LEN | CC_TIME_KERNELS | CC_TRACE | CC_MIXED */
   uint64_t seed;     /* colouring priority seed */
 } cc_params;
 

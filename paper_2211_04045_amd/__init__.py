@@ -11,11 +11,11 @@ from __future__ import annotations
 import ctypes as C
 
 from . import _lib
-from ._lib import (CC_EDGE_LEN, CC_TIME_KERNELS, CC_TRACE, CCError, IterInfo, Params, SceneDesc,
-                   Stats)
+from ._lib import (CC_EDGE_LEN, CC_MIXED, CC_TIME_KERNELS, CC_TRACE, CCError, IterInfo, Params,
+                   SceneDesc, Stats)
 
 __all__ = ["Context", "Solver", "Server", "collide_step", "collide_step_batched", "params", "CC_EDGE_LEN", "CC_TIME_KERNELS",
-           "CC_TRACE", "CCError"]
+           "CC_TRACE", "CC_MIXED", "CCError"]
 
 
 def _torch():
@@ -50,7 +50,8 @@ def _ptr(t):
 
 
 def params(**over) -> Params:
-    """Defaults of Table 2 (cc_default_params) with keyword overrides."""
+    """Defaults of Table 2 (cc_default_params) with keyword overrides; the flags
+    are set with edge_len=, time_kernels=, trace= and mixed= (booleans)."""
     p = Params()
     _lib.load().cc_default_params(C.byref(p))
     for k, v in over.items():
@@ -60,6 +61,8 @@ def params(**over) -> Params:
             p.flags = (p.flags | CC_TIME_KERNELS) if v else (p.flags & ~CC_TIME_KERNELS)
         elif k == "trace":
             p.flags = (p.flags | CC_TRACE) if v else (p.flags & ~CC_TRACE)
+        elif k == "mixed":
+            p.flags = (p.flags | CC_MIXED) if v else (p.flags & ~CC_MIXED)
         else:
             setattr(p, k, v)
     return p

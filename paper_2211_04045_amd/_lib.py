@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libcc.so")
 CC_EDGE_LEN = 1
 CC_TIME_KERNELS = 2
 CC_TRACE = 4
+CC_MIXED = 8
 K_NAMES = ["search", "pair", "color", "gs", "forward", "cert"]
 
 ERRORS = {0: "ok", -1: "invalid argument", -2: "device allocation failed",

@@ -1,10 +1,19 @@
-// C ABI of the two-way collision-handling step: contexts, resident solvers and
-// the host loop of Alg. 1 that sequences the HIP kernels on the caller's stream.
+// C ABI of the two-way collision-handling step: contexts, solvers and the host
+// loop of Alg. 1 that sequences the HIP kernels on the caller's stream.
+//
+// A solver is a multi-scene engine: scenes (segments) occupy disjoint index
+// ranges of one set of device arrays, and every kernel launch of an iteration
+// covers all iterating scenes at once. Each scene keeps its own D, its own stop
+// test and its own iteration count; its kernels read and write only its own
+// ranges (pairs, rows and colours never mix scenes, and colouring priorities use
+// scene-local keys), so a scene's result does not depend on which other scenes
+// share the engine. cc_collide_step is a one-scene engine.
 #include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
 #include <atomic>
+#include <climits>
 #include <thread>
 
 #include "internal.hpp"
@@ -21,9 +30,37 @@ int dalloc(T** p, int64_t n) {
 }
 template <class T>
 void dfree(T*& p) {
-  if (p) hipFree((void*)p);
+  if (p) (void)hipFree((void*)p);
   p = nullptr;
 }
+// Replace *p by an allocation of n elements holding its first `keep` elements.
+template <class T>
+int dregrow(T** p, int64_t n, int64_t keep, hipStream_t st) {
+  T* q = nullptr;
+  CC_TRY(dalloc(&q, n));
+  if (*p && keep > 0) CC_HIP(hipMemcpyAsync(q, *p, sizeof(T) * keep, hipMemcpyDeviceToDevice, st));
+  CC_HIP(hipStreamSynchronize(st));
+  dfree(*p);
+  *p = q;
+  return CC_OK;
+}
+
+hipStream_t as_stream(void* st) { return (hipStream_t)st; }
+
+double bits2d(unsigned long long b) {
+  double d;
+  memcpy(&d, &b, sizeof d);
+  return d;
+}
+unsigned long long d2bits(double d) {
+  unsigned long long b;
+  memcpy(&b, &d, sizeof b);
+  return b;
+}
+
+}  // namespace
+
+namespace cc {
 
 int check_params(const cc_params* p) {
   if (!p) return CC_EINVAL;
@@ -35,6 +72,52 @@ int check_params(const cc_params* p) {
   return CC_OK;
 }
 
+// ---------------------------------------------------------------- ranges
+
+int32_t RangeAlloc::take(int32_t len) {
+  if (len <= 0) return 0;
+  for (size_t i = 0; i < free_.size(); ++i) {
+    if (free_[i].second < len) continue;
+    const int32_t start = free_[i].first;
+    free_[i].first += len;
+    free_[i].second -= len;
+    if (free_[i].second == 0) free_.erase(free_.begin() + i);
+    return start;
+  }
+  return -1;
+}
+
+void RangeAlloc::give(int32_t start, int32_t len) {
+  if (len <= 0) return;
+  auto it = std::lower_bound(free_.begin(), free_.end(), std::make_pair(start, 0));
+  it = free_.insert(it, {start, len});
+  size_t i = it - free_.begin();
+  if (i + 1 < free_.size() && free_[i].first + free_[i].second == free_[i + 1].first) {
+    free_[i].second += free_[i + 1].second;
+    free_.erase(free_.begin() + i + 1);
+  }
+  if (i > 0 && free_[i - 1].first + free_[i - 1].second == free_[i].first) {
+    free_[i - 1].second += free_[i].second;
+    free_.erase(free_.begin() + i);
+  }
+}
+
+void RangeAlloc::grow(int32_t new_cap) {
+  if (new_cap <= cap) return;
+  const int32_t old = cap;
+  cap = new_cap;
+  give(old, new_cap - old);
+}
+
+int32_t RangeAlloc::extent() const {
+  if (!free_.empty() && free_.back().first + free_.back().second == cap) return free_.back().first;
+  return cap;
+}
+
+}  // namespace cc
+
+namespace {
+
 void free_pairs(cc_solver* s) {
   dfree(s->P); dfree(s->P2); dfree(s->dP); dfree(s->dP2);
 }
@@ -43,10 +126,11 @@ void free_active(cc_solver* s) {
   dfree(s->list0); dfree(s->list1); dfree(s->lamA);
 }
 
-int alloc_pairs(cc_solver* s, int64_t cap) {
-  free_pairs(s);
+// Pair buffers of capacity cap; the first `keep` keys of P survive.
+int alloc_pairs(cc_solver* s, int64_t cap, int64_t keep, hipStream_t st) {
+  CC_TRY(dregrow(&s->P, cap, keep, st));
+  dfree(s->P2); dfree(s->dP); dfree(s->dP2);
   s->capP = cap;
-  CC_TRY(dalloc(&s->P, cap));
   CC_TRY(dalloc(&s->P2, cap));
   CC_TRY(dalloc(&s->dP, cap));
   CC_TRY(dalloc(&s->dP2, cap));
@@ -66,77 +150,110 @@ int alloc_active(cc_solver* s, int64_t cap) {
   return CC_OK;
 }
 
+void free_vertex_arrays(cc_solver* s) {
+  dfree(s->w); dfree(s->stat); dfree(s->x); dfree(s->y); dfree(s->xt); dfree(s->xold);
+  dfree(s->r); dfree(s->move2); dfree(s->Di); dfree(s->vseg); dfree(s->dy);
+  dfree(s->vmax0); dfree(s->vmax1); dfree(s->masks);
+}
+void free_edge_arrays(cc_solver* s) {
+  dfree(s->edges); dfree(s->eseg); dfree(s->eg); dfree(s->einv); dfree(s->ecol); dfree(s->eorder);
+  dfree(s->elist0); dfree(s->elist1); dfree(s->elist2); dfree(s->lamE);
+}
+
 void solver_free(cc_solver* s) {
-  dfree(s->w); dfree(s->tris); dfree(s->edges); dfree(s->stat);
-  dfree(s->x); dfree(s->y); dfree(s->xt); dfree(s->xold); dfree(s->r); dfree(s->move2); dfree(s->Di);
+  free_vertex_arrays(s);
+  free_edge_arrays(s);
+  dfree(s->tris);
   free_pairs(s);
   free_active(s);
-  dfree(s->eg); dfree(s->einv); dfree(s->ecol); dfree(s->eorder);
-  dfree(s->elist0); dfree(s->elist1); dfree(s->elist2); dfree(s->lamE);
-  dfree(s->vmax0); dfree(s->vmax1); dfree(s->masks); dfree(s->col_cnt); dfree(s->rcnt);
-  dfree(s->coff_dev); dfree(s->ecoff_dev);
+  dfree(s->col_cnt); dfree(s->rcnt); dfree(s->coff_dev); dfree(s->ecoff_dev);
+  dfree(s->seg_dev);
+  if (s->seg_host) (void)hipHostFree(s->seg_host);
+  s->seg_host = nullptr;
   bvh_free(s);
+  if (s->sel_host) (void)hipHostFree(s->sel_host);
+  s->sel_host = nullptr;
   dfree(s->dc);
-  if (s->hc) hipHostFree(s->hc);
+  if (s->hc) (void)hipHostFree(s->hc);
   s->hc = nullptr;
   for (auto& t : s->timers) {
-    hipEventDestroy(t.a);
-    hipEventDestroy(t.b);
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
   }
   s->timers.clear();
-  for (auto e : s->event_pool) hipEventDestroy(e);
+  for (auto e : s->event_pool) (void)hipEventDestroy(e);
   s->event_pool.clear();
 }
 
-int solver_alloc(cc_solver* s) {
-  const int64_t n = s->n, nt = s->nt, ne = s->ne;
-  CC_TRY(dalloc(&s->w, n));
-  CC_TRY(dalloc(&s->tris, 3 * nt));
-  CC_TRY(dalloc(&s->edges, 2 * ne));
-  CC_TRY(dalloc(&s->stat, n));
-  CC_TRY(dalloc(&s->x, 3 * n));
-  CC_TRY(dalloc(&s->y, 3 * n));
-  CC_TRY(dalloc(&s->xt, 3 * n));
-  CC_TRY(dalloc(&s->xold, 3 * n));
-  CC_TRY(dalloc(&s->r, n));
-  CC_TRY(dalloc(&s->move2, n));
-  CC_TRY(dalloc(&s->Di, n));
-  CC_TRY(dalloc(&s->eg, 3 * ne));
-  CC_TRY(dalloc(&s->einv, ne));
-  CC_TRY(dalloc(&s->ecol, ne));
-  CC_TRY(dalloc(&s->eorder, ne));
-  CC_TRY(dalloc(&s->elist0, ne));
-  CC_TRY(dalloc(&s->elist1, ne));
-  CC_TRY(dalloc(&s->elist2, ne));
-  CC_TRY(dalloc(&s->lamE, ne));
-  CC_TRY(dalloc(&s->vmax0, n));
-  CC_TRY(dalloc(&s->vmax1, n));
-  CC_TRY(dalloc(&s->masks, n * kMaskWords));
+// Per-vertex, per-triangle and per-edge arrays at the given capacities; the
+// live contents (state, masses, topology, segment ids, edge rows) of the first
+// old-capacity elements are kept. Scratch arrays and the search tree are
+// reallocated empty.
+int resize_arrays(cc_solver* s, int32_t capV, int32_t capF, int32_t capE, hipStream_t st) {
+  const int64_t oV = s->capV, oF = s->capF, oE = s->capE;
+  if (capV != oV) {
+    CC_TRY(dregrow(&s->w, capV, oV, st));
+    CC_TRY(dregrow(&s->stat, capV, oV, st));
+    CC_TRY(dregrow(&s->x, 3 * (int64_t)capV, 3 * oV, st));
+    CC_TRY(dregrow(&s->y, 3 * (int64_t)capV, 3 * oV, st));
+    CC_TRY(dregrow(&s->xt, 3 * (int64_t)capV, 3 * oV, st));
+    CC_TRY(dregrow(&s->r, capV, oV, st));
+    CC_TRY(dregrow(&s->dy, 3 * (int64_t)capV, 3 * oV, st));
+    CC_TRY(dregrow(&s->vseg, capV, oV, st));
+    CC_TRY(launch_fill_i32(s->vseg + oV, capV - oV, -1, st));
+    dfree(s->xold); dfree(s->move2); dfree(s->Di); dfree(s->vmax0); dfree(s->vmax1); dfree(s->masks);
+    CC_TRY(dalloc(&s->xold, 3 * (int64_t)capV));
+    CC_TRY(dalloc(&s->move2, capV));
+    CC_TRY(dalloc(&s->Di, capV));
+    CC_TRY(dalloc(&s->vmax0, capV));
+    CC_TRY(dalloc(&s->vmax1, capV));
+    CC_TRY(dalloc(&s->masks, (int64_t)capV * kMaskWords));
+  }
+  if (capF != oF) CC_TRY(dregrow(&s->tris, 3 * (int64_t)capF, 3 * oF, st));
+  if (capE != oE) {
+    CC_TRY(dregrow(&s->edges, 2 * (int64_t)capE, 2 * oE, st));
+    CC_TRY(dregrow(&s->eseg, capE, oE, st));
+    CC_TRY(launch_fill_i32(s->eseg + oE, capE - oE, -1, st));
+    CC_TRY(dregrow(&s->eg, 3 * (int64_t)capE, 3 * oE, st));
+    CC_TRY(dregrow(&s->einv, capE, oE, st));
+    CC_TRY(dregrow(&s->ecol, capE, oE, st));
+    dfree(s->eorder); dfree(s->elist0); dfree(s->elist1); dfree(s->elist2); dfree(s->lamE);
+    CC_TRY(dalloc(&s->eorder, capE));
+    CC_TRY(dalloc(&s->elist0, capE));
+    CC_TRY(dalloc(&s->elist1, capE));
+    CC_TRY(dalloc(&s->elist2, capE));
+    CC_TRY(dalloc(&s->lamE, capE));
+    s->erows_dirty = true;
+  }
+  s->capV = capV;
+  s->capF = capF;
+  s->capE = capE;
+  bvh_free(s);
+  CC_TRY(bvh_alloc(s));
+  s->ra_v.grow(capV);
+  s->ra_f.grow(capF);
+  s->ra_e.grow(capE);
+  CC_HIP(hipStreamSynchronize(st));
+  return CC_OK;
+}
+
+int solver_alloc(cc_solver* s, int32_t capV, int32_t capF, int32_t capE, hipStream_t st) {
   CC_TRY(dalloc(&s->col_cnt, kMaxColors + 1));
   CC_TRY(dalloc(&s->rcnt, kMaxRounds + 1));
   CC_TRY(dalloc(&s->coff_dev, kMaxColors + 1));
   CC_TRY(dalloc(&s->ecoff_dev, kMaxColors + 1));
-  CC_TRY(bvh_alloc(s));
+  CC_TRY(dalloc(&s->seg_dev, kMaxSeg));
+  if (hipHostMalloc((void**)&s->seg_host, sizeof(SegDev) * kMaxSeg, hipHostMallocDefault) != hipSuccess)
+    return CC_ENOMEM;
+  memset(s->seg_host, 0, sizeof(SegDev) * kMaxSeg);
   CC_TRY(dalloc(&s->dc, 1));
   if (hipHostMalloc((void**)&s->hc, sizeof(Counters), hipHostMallocDefault) != hipSuccess)
     return CC_ENOMEM;
-  int64_t cap = std::max<int64_t>(4096, 32 * (n + ne));
-  CC_TRY(alloc_pairs(s, cap));
+  CC_TRY(resize_arrays(s, std::max(capV, 1), std::max(capF, 1), std::max(capE, 1), st));
+  const int64_t cap = std::max<int64_t>(4096, 32 * ((int64_t)capV + capE));
+  CC_TRY(alloc_pairs(s, cap, 0, st));
   CC_TRY(alloc_active(s, std::max<int64_t>(4096, cap / 8)));
   return CC_OK;
-}
-
-hipStream_t as_stream(void* st) { return (hipStream_t)st; }
-
-double bits2d(unsigned long long b) {
-  double d;
-  memcpy(&d, &b, sizeof d);
-  return d;
-}
-unsigned long long d2bits(double d) {
-  unsigned long long b;
-  memcpy(&b, &d, sizeof b);
-  return b;
 }
 
 void resolve_timers(cc_solver* s) {
@@ -152,46 +269,6 @@ void resolve_timers(cc_solver* s) {
   s->timers.clear();
 }
 
-// Make `slot` a solver for this topology: reuse it when the sizes match (topology
-// and masses are copied in again), otherwise replace it.
-int bind_solver(cc_context* ctx, cc_solver*& slot, int32_t n, const double* inv_mass,
-                const int32_t* tris, int32_t nt, const int32_t* edges, int32_t ne,
-                const cc_params* params, void* stream) {
-  hipStream_t st = as_stream(stream);
-  cc_solver* s = slot;
-  if (s && s->n == n && s->nt == nt && s->ne == ne) {
-    s->p = *params;
-    s->kappa2 = params->kappa * params->kappa;
-    if (nt) CC_HIP(hipMemcpyAsync(s->tris, tris, sizeof(int32_t) * 3 * nt, hipMemcpyDefault, st));
-    if (ne) CC_HIP(hipMemcpyAsync(s->edges, edges, sizeof(int32_t) * 2 * ne, hipMemcpyDefault, st));
-    if (n) {
-      if (inv_mass)
-        CC_HIP(hipMemcpyAsync(s->w, inv_mass, sizeof(double) * n, hipMemcpyDefault, st));
-      else
-        CC_TRY(launch_fill_u64((unsigned long long*)s->w, n, d2bits(1.0), st));
-    }
-    return launch_validate(s, nullptr, nullptr, st);
-  }
-  if (s) cc_solver_destroy(s);
-  slot = nullptr;
-  CC_TRY(cc_solver_create(ctx, n, inv_mass, tris, nt, edges, ne, params, &s, stream));
-  slot = s;
-  return CC_OK;
-}
-
-int do_search(cc_solver* s, const double* x, double dmax, hipStream_t st) {
-  for (int attempt = 0; attempt < 2; ++attempt) {
-    int64_t n = 0;
-    CC_TRY(lbvh_search(s, x, dmax, s->P, s->capP, &n, st));
-    if (n <= s->capP) {
-      s->nP = n;
-      return CC_OK;
-    }
-    CC_TRY(alloc_pairs(s, n + n / 4 + 1024));
-  }
-  return CC_EOVERFLOW;
-}
-
 }  // namespace
 
 namespace cc {
@@ -203,7 +280,7 @@ hipEvent_t pool_event(cc_solver* s) {
     return e;
   }
   hipEvent_t e = nullptr;
-  hipEventCreate(&e);
+  (void)hipEventCreate(&e);
   return e;
 }
 
@@ -213,16 +290,408 @@ void timer_begin(cc_solver* s, int kind, hipStream_t st) {
   t.kind = kind;
   t.a = pool_event(s);
   t.b = pool_event(s);
-  hipEventRecord(t.a, st);
+  (void)hipEventRecord(t.a, st);
   s->timers.push_back(t);
 }
 
 void timer_end(cc_solver* s, hipStream_t st) {
   if (!(s->p.flags & CC_TIME_KERNELS) || s->timers.empty()) return;
-  hipEventRecord(s->timers.back().b, st);
+  (void)hipEventRecord(s->timers.back().b, st);
+}
+
+// ---------------------------------------------------------------- engine
+
+int engine_create(cc_context* ctx, const cc_params* params, int32_t capV, int32_t capF,
+                  int32_t capE, cc_solver** out, hipStream_t st) {
+  CC_TRY(check_params(params));
+  if (hipSetDevice(ctx->device) != hipSuccess) return CC_EHIP;
+  cc_solver* s = new cc_solver();
+  s->ctx = ctx;
+  s->p = *params;
+  s->kappa2 = params->kappa * params->kappa;
+  int rc = solver_alloc(s, capV, capF, capE, st);
+  if (rc != CC_OK) {
+    solver_free(s);
+    delete s;
+    return rc;
+  }
+  *out = s;
+  return CC_OK;
+}
+
+void engine_set_params(cc_solver* s, const cc_params* params) {
+  s->p = *params;
+  s->kappa2 = params->kappa * params->kappa;
+}
+
+static void update_extents(cc_solver* s) {
+  s->n = s->ra_v.extent();
+  s->nt = s->ra_f.extent();
+  s->ne = s->ra_e.extent();
+}
+
+void release_pending(cc_solver* s) {
+  for (const auto& f : s->pending_free) {
+    if (f[0] == 0) s->ra_v.give(f[1], f[2]);
+    else if (f[0] == 1) s->ra_f.give(f[1], f[2]);
+    else s->ra_e.give(f[1], f[2]);
+  }
+  s->pending_free.clear();
+  update_extents(s);
+}
+
+int seg_add(cc_solver* s, int32_t nv, const double* inv_mass, const int32_t* tris, int32_t nf,
+            const int32_t* edges, int32_t ne, int32_t max_iters, int32_t* out, hipStream_t st) {
+  if (nv < 0 || nf < 0 || ne < 0 || !out) return CC_EINVAL;
+  if ((nf > 0 && !tris) || (ne > 0 && !edges)) return CC_EINVAL;
+  int32_t sg = -1;
+  for (int32_t i = 0; i < (int32_t)s->segs.size(); ++i)
+    if (!s->segs[i].live && !s->segs[i].pending) {
+      sg = i;
+      break;
+    }
+  if (sg < 0) {
+    if ((int32_t)s->segs.size() >= kMaxSeg) return CC_EAGAIN;
+    s->segs.push_back(Seg{});
+    sg = (int32_t)s->segs.size() - 1;
+  }
+  int32_t vb = s->ra_v.take(nv), fb = s->ra_f.take(nf), eb = s->ra_e.take(ne);
+  if (vb < 0 || fb < 0 || eb < 0) {
+    if (vb >= 0) s->ra_v.give(vb, nv);
+    if (fb >= 0) s->ra_f.give(fb, nf);
+    if (eb >= 0) s->ra_e.give(eb, ne);
+    const int32_t cv = vb < 0 ? std::max(s->capV + nv, 2 * s->capV) : s->capV;
+    const int32_t cf = fb < 0 ? std::max(s->capF + nf, 2 * s->capF) : s->capF;
+    const int32_t ce = eb < 0 ? std::max(s->capE + ne, 2 * s->capE) : s->capE;
+    CC_TRY(resize_arrays(s, cv, cf, ce, st));
+    vb = s->ra_v.take(nv);
+    fb = s->ra_f.take(nf);
+    eb = s->ra_e.take(ne);
+    if (vb < 0 || fb < 0 || eb < 0) return CC_ENOMEM;
+  }
+  Seg& g = s->segs[sg];
+  g = Seg{};
+  g.vb = vb;
+  g.nv = nv;
+  g.fb = fb;
+  g.nf = nf;
+  g.eb = eb;
+  g.ne = ne;
+  g.max_iters = max_iters;
+  g.live = true;
+  update_extents(s);
+  int rc = CC_OK;
+  if (nv > 0) {
+    if (inv_mass)
+      rc = hipMemcpyAsync(s->w + vb, inv_mass, sizeof(double) * nv, hipMemcpyDefault, st) == hipSuccess
+               ? CC_OK : CC_EHIP;
+    else
+      rc = launch_fill_u64((unsigned long long*)(s->w + vb), nv, d2bits(1.0), st);
+    if (rc == CC_OK) rc = launch_fill_i32(s->vseg + vb, nv, sg, st);
+  }
+  if (rc == CC_OK) rc = launch_topo_in(s, sg, tris, edges, st);
+  SegDev& d = s->seg_host[sg];
+  memset(&d, 0, sizeof d);
+  d.vb = vb;
+  d.fb = fb;
+  d.eb = eb;
+  if (rc == CC_OK)
+    rc = hipMemcpyAsync(s->seg_dev + sg, &d, sizeof d, hipMemcpyHostToDevice, st) == hipSuccess
+             ? CC_OK : CC_EHIP;
+  if (rc == CC_OK) rc = hipStreamSynchronize(st) == hipSuccess ? CC_OK : CC_EHIP;
+  if (rc != CC_OK) {
+    seg_remove(s, sg, st);
+    return rc;
+  }
+  *out = sg;
+  return CC_OK;
+}
+
+int seg_remove(cc_solver* s, int32_t sg, hipStream_t st) {
+  if (sg < 0 || sg >= (int32_t)s->segs.size() || !s->segs[sg].live) return CC_EINVAL;
+  Seg& g = s->segs[sg];
+  CC_TRY(launch_fill_i32(s->vseg + g.vb, g.nv, -1, st));
+  CC_TRY(launch_fill_i32(s->eseg + g.eb, g.ne, -1, st));
+  g.live = false;
+  g.active = false;
+  g.pending = true;
+  s->seg_host[sg].flags = 0;
+  CC_HIP(hipMemcpyAsync(s->seg_dev + sg, s->seg_host + sg, sizeof(SegDev), hipMemcpyHostToDevice, st));
+  // the ranges return to the allocator once no pair of P can refer to them
+  s->pending_free.push_back({0, g.vb, g.nv});
+  s->pending_free.push_back({1, g.fb, g.nf});
+  s->pending_free.push_back({2, g.eb, g.ne});
+  s->pending_segs.push_back(sg);
+  s->erows_dirty = true;
+  CC_HIP(hipStreamSynchronize(st));
+  if (s->nP == 0) {
+    release_pending(s);
+    for (int32_t q : s->pending_segs) s->segs[q].pending = false;
+    s->pending_segs.clear();
+  }
+  return CC_OK;
+}
+
+static void release_all_pending(cc_solver* s) {
+  release_pending(s);
+  for (int32_t q : s->pending_segs) s->segs[q].pending = false;
+  s->pending_segs.clear();
+}
+
+// Alg. 1 initialisation of k segments at once: x <- x^[k] (x_prev[i], or the
+// segment's resident x when NULL), y <- y^[k+1], D <- 0, r <- 1, the edge-length
+// rows at y^[k+1] and their colouring. rc[i] gets each segment's result.
+int seg_begin(cc_solver* s, const int32_t* sgs, int32_t k, const double* const* x_prev,
+              const double* const* x_tilde, int* rc, hipStream_t st) {
+  CC_HIP(hipMemsetAsync(&s->dc->n_rows, 0, sizeof(unsigned long long), st));
+  std::vector<int32_t> ok;
+  for (int32_t i = 0; i < k; ++i) {
+    const int32_t sg = sgs[i];
+    Seg& g = s->segs[sg];
+    if (!g.live || (g.nv > 0 && !x_tilde[i])) {
+      rc[i] = CC_EINVAL;
+      continue;
+    }
+    const double* xp = x_prev[i] ? x_prev[i] : s->x + 3 * (int64_t)g.vb;
+    rc[i] = launch_check_finite(s, xp, x_tilde[i], g.nv, st);
+    if (rc[i] != CC_OK) continue;
+    rc[i] = launch_setup(s, sg, xp, x_tilde[i], st);
+    if (rc[i] == CC_OK) ok.push_back(i);
+  }
+  CC_HIP(hipMemcpyAsync(&s->hc->n_rows, &s->dc->n_rows, sizeof(unsigned long long),
+                        hipMemcpyDeviceToHost, st));
+  CC_HIP(hipStreamSynchronize(st));
+  s->n_newrows = (int32_t)s->hc->n_rows;
+  timer_begin(s, CC_K_COLOR, st);
+  int crc = color_rows(s, true, st);
+  timer_end(s, st);
+  if (crc == CC_OK)
+    crc = hipMemcpyAsync(s->seg_host, s->seg_dev, sizeof(SegDev) * s->segs.size(),
+                         hipMemcpyDeviceToHost, st) == hipSuccess ? CC_OK : CC_EHIP;
+  if (crc == CC_OK) crc = hipStreamSynchronize(st) == hipSuccess ? CC_OK : CC_EHIP;
+  resolve_timers(s);
+  for (int32_t i : ok) {
+    if (crc != CC_OK) {
+      rc[i] = crc;
+      continue;
+    }
+    Seg& g = s->segs[sgs[i]];
+    g.D = 0.0;
+    g.begun = true;
+    g.active = true;
+    g.n_erows = (int32_t)s->seg_host[sgs[i]].n_rows;
+    memset(&g.st, 0, sizeof g.st);
+    g.st.status = CC_MAXITER;
+    memset(&g.last, 0, sizeof g.last);
+  }
+  s->erows_dirty = true;
+  return crc;
+}
+
+// One iteration of Alg. 1 for every iterating segment.
+int engine_iterate(cc_solver* s, hipStream_t st) {
+  const cc_params& p = s->p;
+  const bool trace = (p.flags & CC_TRACE) != 0;
+  const int32_t ns = (int32_t)s->segs.size();
+  std::vector<int32_t> act, sel;
+  std::vector<char> searched(ns, 0);
+  for (int32_t i = 0; i < ns; ++i) {
+    const Seg& g = s->segs[i];
+    if (!(g.live && g.active)) continue;
+    act.push_back(i);
+    if (g.D < p.d_min) sel.push_back(i);
+  }
+  if (act.empty()) {
+    s->nP = 0;
+    release_all_pending(s);
+    return CC_OK;
+  }
+  // proximity search of the segments whose reuse bound fell below D_min (Sec. 3.1)
+  int64_t n_old = s->nP;
+  int64_t n_search = 0;
+  if (!sel.empty()) {
+    if (sel.size() == act.size()) n_old = 0;  // every pair of P is replaced
+    for (size_t r = 0; r < sel.size(); ++r) s->sel_host[r].seg = sel[r];
+    for (int attempt = 0;; ++attempt) {
+      int64_t nf = 0;
+      CC_TRY(lbvh_search(s, (int32_t)sel.size(), s->x, p.d_max, s->P + n_old, s->capP - n_old,
+                         &nf, st));
+      if (n_old + nf <= s->capP) {
+        n_search = nf;
+        break;
+      }
+      if (attempt > 0) return CC_EOVERFLOW;
+      const int64_t need = n_old + nf;
+      CC_TRY(alloc_pairs(s, need + need / 4 + 1024, n_old, st));
+    }
+    s->nP = n_old + n_search;
+    for (int32_t sg : sel) {
+      s->segs[sg].D = p.d_max;
+      s->segs[sg].st.searches += 1;
+      s->segs[sg].last.searched = 1;
+      searched[sg] = 1;
+    }
+  }
+  // segment records
+  for (int32_t i = 0; i < ns; ++i) {
+    const Seg& g = s->segs[i];
+    SegDev& d = s->seg_host[i];
+    const unsigned long long rows = d.n_rows;
+    memset(&d, 0, sizeof d);
+    d.n_rows = rows;
+    d.D = g.D;
+    d.D2 = g.D * g.D;
+    d.vb = g.vb;
+    d.fb = g.fb;
+    d.eb = g.eb;
+    d.flags = ((g.live && g.active) ? kSegActive : 0) | (searched[i] ? kSegSearched : 0);
+  }
+  CC_HIP(hipMemcpyAsync(s->seg_dev, s->seg_host, sizeof(SegDev) * ns, hipMemcpyHostToDevice, st));
+  if (s->erows_dirty) CC_TRY(build_edge_buckets(s, st));
+  // pair pass; regrow the active set if it overflowed
+  for (int attempt = 0;; ++attempt) {
+    CC_HIP(hipMemsetAsync(s->dc, 0, sizeof(Counters), st));
+    CC_TRY(launch_di_init(s, st));
+    timer_begin(s, CC_K_PAIR, st);
+    CC_TRY(launch_pair_pass(s, n_old, p.delta * p.delta, trace, st));
+    timer_end(s, st);
+    CC_HIP(hipMemcpyAsync(s->hc, s->dc, sizeof(Counters), hipMemcpyDeviceToHost, st));
+    CC_HIP(hipMemcpyAsync(s->seg_host, s->seg_dev, sizeof(SegDev) * ns, hipMemcpyDeviceToHost, st));
+    CC_HIP(hipStreamSynchronize(st));
+    if ((int64_t)s->hc->n_act <= s->capA) break;
+    if (attempt > 0) return CC_EOVERFLOW;
+    CC_TRY(alloc_active(s, (int64_t)s->hc->n_act + (int64_t)s->hc->n_act / 4 + 1024));
+    // counters of the failed attempt start again from zero
+    for (int32_t i = 0; i < ns; ++i) s->seg_host[i].n_p = s->seg_host[i].n_pf = s->seg_host[i].n_a = 0;
+    CC_HIP(hipMemcpyAsync(s->seg_dev, s->seg_host, sizeof(SegDev) * ns, hipMemcpyHostToDevice, st));
+  }
+  const int64_t n_eval = s->nP;
+  const int64_t npf = (int64_t)s->hc->n_out, na = (int64_t)s->hc->n_act;
+  const uint64_t fp_pf = s->hc->fp_pf, fp_a = s->hc->fp_a;
+  std::swap(s->P, s->P2);
+  std::swap(s->dP, s->dP2);
+  s->nP = npf;
+  s->nA = na;
+  release_all_pending(s);  // no pair of a removed segment is left in P
+  for (int32_t sg : act) {
+    Seg& g = s->segs[sg];
+    g.last.d_before = g.D;
+    g.last.n_p = (int64_t)s->seg_host[sg].n_p;
+    g.last.n_pf = (int64_t)s->seg_host[sg].n_pf;
+    g.last.n_a = (int64_t)s->seg_host[sg].n_a;
+    if (!searched[sg]) g.last.searched = 0;
+  }
+  // backward step (Sec. 4)
+  timer_begin(s, CC_K_COLOR, st);
+  int rc = color_rows(s, false, st);
+  timer_end(s, st);
+  if (rc != CC_OK) return rc;
+  if (trace) {
+    CC_HIP(hipMemsetAsync(&s->dc->fp_col, 0, sizeof(unsigned long long), st));
+    CC_TRY(launch_fp_col(s, st));
+  }
+  timer_begin(s, CC_K_GS, st);
+  CC_TRY(launch_gs(s, st));
+  timer_end(s, st);
+  // forward step (Sec. 5) and the path certificate
+  timer_begin(s, CC_K_FORWARD, st);
+  CC_TRY(launch_forward(s, st));
+  timer_end(s, st);
+  timer_begin(s, CC_K_CERT, st);
+  CC_TRY(launch_cert(s, st));
+  timer_end(s, st);
+  CC_HIP(hipMemcpyAsync(s->seg_host, s->seg_dev, sizeof(SegDev) * ns, hipMemcpyDeviceToHost, st));
+  if (trace) CC_HIP(hipMemcpyAsync(&s->hc->fp_col, &s->dc->fp_col, sizeof(unsigned long long),
+                                   hipMemcpyDeviceToHost, st));
+  CC_HIP(hipStreamSynchronize(st));
+  resolve_timers(s);
+  bool changed = false;
+  for (int32_t sg : act) {
+    Seg& g = s->segs[sg];
+    const SegDev& d = s->seg_host[sg];
+    const double mmax = bits2d(d.mmax_bits), rinf = bits2d(d.rinf_bits);
+    cc_iter_info& it = g.last;
+    it.n_colors = s->n_colors;
+    it.move_max = mmax;
+    it.r_inf = rinf;
+    it.ccd_fail = (int64_t)d.fail;
+    it.ccd_hits = (int64_t)d.hits;
+    it.fp_pf = fp_pf;
+    it.fp_a = fp_a;
+    it.fp_col = trace ? s->hc->fp_col : 0;
+    g.D = g.D - 2.0 * mmax;
+    it.d_after = g.D;
+    g.st.iters += 1;
+    g.st.pair_updates += it.n_p;
+    g.st.row_updates += (it.n_a + g.n_erows) * (int64_t)p.gs_sweeps;
+    g.st.ccd_fail += it.ccd_fail;
+    g.st.ccd_hits += it.ccd_hits;
+    g.st.r_inf = rinf;
+    if (s->n_colors > g.st.max_colors_used) g.st.max_colors_used = s->n_colors;
+    if (rinf < p.eps) {
+      g.st.status = CC_CONVERGED;
+      g.active = false;
+      changed = true;
+    } else if (g.st.iters >= g.max_iters) {
+      g.active = false;
+      changed = true;
+    }
+  }
+  if (changed) s->erows_dirty = true;
+  // algorithmic bytes (engine totals)
+  {
+    const double N = s->n, F = s->nt, E = s->ne;
+    s->st.iters += 1;
+    s->st.pair_updates += n_eval;
+    s->st.kernel_bytes[CC_K_PAIR] += 8.0 * n_eval + 16.0 * npf + 24.0 * na + 32.0 * N + 12.0 * F + 8.0 * E;
+    s->st.kernel_bytes[CC_K_FORWARD] += 92.0 * N;
+    s->st.kernel_bytes[CC_K_CERT] += 16.0 * npf + 8.0 * N + 12.0 * F + 8.0 * E;
+  }
+  return CC_OK;
+}
+
+int engine_active(const cc_solver* s) {
+  int k = 0;
+  for (const Seg& g : s->segs) k += (g.live && g.active) ? 1 : 0;
+  return k;
+}
+
+// Statistics of a segment with the engine's kernel timings and bytes.
+void seg_stats(const cc_solver* s, int32_t sg, cc_stats* out) {
+  *out = s->segs[sg].st;
+  for (int k = 0; k < CC_K_COUNT; ++k) {
+    out->kernel_ms[k] = s->st.kernel_ms[k];
+    out->kernel_launches[k] = s->st.kernel_launches[k];
+    out->kernel_bytes[k] = s->st.kernel_bytes[k];
+  }
 }
 
 }  // namespace cc
+
+namespace {
+
+// Make ctx's one-scene engine hold exactly this scene, as segment 0 at base 0.
+int bind_single(cc_context* ctx, cc_solver*& slot, int32_t n, const double* inv_mass,
+                const int32_t* tris, int32_t nt, const int32_t* edges, int32_t ne,
+                const cc_params* params, hipStream_t st) {
+  if (!slot) CC_TRY(engine_create(ctx, params, n, nt, ne, &slot, st));
+  cc_solver* s = slot;
+  engine_set_params(s, params);
+  for (int32_t i = 0; i < (int32_t)s->segs.size(); ++i)
+    if (s->segs[i].live) CC_TRY(seg_remove(s, i, st));
+  s->nP = 0;
+  release_pending(s);
+  for (auto& g : s->segs) g.pending = false;
+  s->pending_segs.clear();
+  int32_t sg = -1;
+  CC_TRY(seg_add(s, n, inv_mass, tris, nt, edges, ne, INT_MAX, &sg, st));
+  if (sg != 0 || s->segs[0].vb != 0 || s->segs[0].fb != 0 || s->segs[0].eb != 0) return CC_ESTATE;
+  memset(&s->st, 0, sizeof s->st);
+  s->begun = false;
+  return CC_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -251,7 +720,7 @@ const char* cc_strerror(int code) {
     case CC_EHIP: return "HIP runtime error";
     case CC_ECOLOR: return "colour palette exhausted";
     case CC_ESTATE: return "call out of order";
-    case CC_EAGAIN: return "over the HBM budget, retry after a release";
+    case CC_EAGAIN: return "over the HBM budget or the scene limit, retry after a release";
     case CC_EBUSY: return "step still running";
     default: return "unknown error";
   }
@@ -272,9 +741,7 @@ void cc_context_destroy(cc_context* ctx) {
   if (!ctx) return;
   server_destroy(ctx);
   if (ctx->cached) cc_solver_destroy(ctx->cached);
-  for (cc_solver* s : ctx->slots)
-    if (s) cc_solver_destroy(s);
-  for (hipStream_t s : ctx->slot_streams) (void)hipStreamDestroy(s);
+  if (ctx->batched) cc_solver_destroy(ctx->batched);
   delete ctx;
 }
 
@@ -284,30 +751,10 @@ int cc_solver_create(cc_context* ctx, int32_t n, const double* inv_mass, const i
   if (!ctx || !out || n < 0 || nt < 0 || ne < 0) return CC_EINVAL;
   if ((nt > 0 && !tris) || (ne > 0 && !edges)) return CC_EINVAL;
   CC_TRY(check_params(params));
-  if (hipSetDevice(ctx->device) != hipSuccess) return CC_EHIP;
-  hipStream_t st = as_stream(stream);
-  cc_solver* s = new cc_solver();
-  s->ctx = ctx;
-  s->n = n;
-  s->nt = nt;
-  s->ne = ne;
-  s->p = *params;
-  s->kappa2 = params->kappa * params->kappa;
-  int rc = solver_alloc(s);
-  if (rc == CC_OK) {
-    if (nt) rc = hipMemcpyAsync(s->tris, tris, sizeof(int32_t) * 3 * nt, hipMemcpyDefault, st) == hipSuccess ? CC_OK : CC_EHIP;
-    if (rc == CC_OK && ne) rc = hipMemcpyAsync(s->edges, edges, sizeof(int32_t) * 2 * ne, hipMemcpyDefault, st) == hipSuccess ? CC_OK : CC_EHIP;
-    if (rc == CC_OK && n) {
-      if (inv_mass)
-        rc = hipMemcpyAsync(s->w, inv_mass, sizeof(double) * n, hipMemcpyDefault, st) == hipSuccess ? CC_OK : CC_EHIP;
-      else
-        rc = launch_fill_u64((unsigned long long*)s->w, n, d2bits(1.0), st);
-    }
-    if (rc == CC_OK) rc = launch_validate(s, nullptr, nullptr, st);
-  }
+  cc_solver* s = nullptr;
+  int rc = bind_single(ctx, s, n, inv_mass, tris, nt, edges, ne, params, as_stream(stream));
   if (rc != CC_OK) {
-    solver_free(s);
-    delete s;
+    if (s) cc_solver_destroy(s);
     return rc;
   }
   *out = s;
@@ -321,27 +768,17 @@ void cc_solver_destroy(cc_solver* s) {
 }
 
 int cc_solver_begin(cc_solver* s, const double* x_prev, const double* x_tilde, void* stream) {
-  if (!s || (s->n > 0 && (!x_prev || !x_tilde))) return CC_EINVAL;
-  hipStream_t st = as_stream(stream);
-  CC_TRY(launch_validate(s, x_prev, x_tilde, st));
-  CC_TRY(launch_setup(s, x_prev, x_tilde, st));
-  s->D = 0.0;
+  if (!s || s->segs.empty() || !s->segs[0].live) return CC_EINVAL;
+  if (s->segs[0].nv > 0 && (!x_prev || !x_tilde)) return CC_EINVAL;
+  int32_t sg = 0;
+  int rc = CC_OK;
+  memset(&s->st, 0, sizeof s->st);
+  CC_TRY(seg_begin(s, &sg, 1, &x_prev, &x_tilde, &rc, as_stream(stream)));
+  CC_TRY(rc);
   s->nP = 0;
   s->nA = 0;
   s->n_colors = 0;
-  memset(&s->st, 0, sizeof s->st);
-  s->st.status = CC_MAXITER;
-  for (auto& t : s->timers) {
-    s->event_pool.push_back(t.a);
-    s->event_pool.push_back(t.b);
-  }
-  s->timers.clear();
-  timer_begin(s, CC_K_COLOR, st);
-  int rc = color_rows(s, true, st);
-  timer_end(s, st);
-  if (rc != CC_OK) return rc;
-  CC_HIP(hipStreamSynchronize(st));
-  resolve_timers(s);
+  s->D = 0.0;
   s->begun = true;
   return CC_OK;
 }
@@ -349,96 +786,13 @@ int cc_solver_begin(cc_solver* s, const double* x_prev, const double* x_tilde, v
 int cc_solver_iterate(cc_solver* s, int32_t* stop, cc_iter_info* info, void* stream) {
   if (!s) return CC_EINVAL;
   if (!s->begun) return CC_ESTATE;
-  hipStream_t st = as_stream(stream);
-  const cc_params& p = s->p;
-  const bool trace = (p.flags & CC_TRACE) != 0;
-  cc_iter_info it;
-  memset(&it, 0, sizeof it);
-  // Alg. 1: proximity search when the reuse bound fell below D_min (Sec. 3.1)
-  if (s->D < p.d_min) {
-    int rc = do_search(s, s->x, p.d_max, st);
-    if (rc != CC_OK) return rc;
-    s->D = p.d_max;
-    it.searched = 1;
-    s->st.searches += 1;
-  }
-  it.d_before = s->D;
-  it.n_p = s->nP;
-  const double D = s->D;
-  // pair pass; regrow the active set if it overflowed
-  for (int attempt = 0;; ++attempt) {
-    CC_HIP(hipMemsetAsync(s->dc, 0, sizeof(Counters), st));
-    CC_TRY(launch_fill_u64(s->Di, s->n, d2bits(D), st));
-    timer_begin(s, CC_K_PAIR, st);
-    CC_TRY(launch_pair_pass(s, D * D, p.delta * p.delta, trace, st));
-    timer_end(s, st);
-    CC_HIP(hipMemcpyAsync(s->hc, s->dc, sizeof(Counters), hipMemcpyDeviceToHost, st));
-    CC_HIP(hipStreamSynchronize(st));
-    if ((int64_t)s->hc->n_act <= s->capA) break;
-    if (attempt > 0) return CC_EOVERFLOW;
-    CC_TRY(alloc_active(s, (int64_t)s->hc->n_act + (int64_t)s->hc->n_act / 4 + 1024));
-  }
-  const int64_t npf = (int64_t)s->hc->n_out, na = (int64_t)s->hc->n_act;
-  it.fp_pf = s->hc->fp_pf;
-  it.fp_a = s->hc->fp_a;
-  std::swap(s->P, s->P2);
-  std::swap(s->dP, s->dP2);
-  s->nP = npf;
-  s->nA = na;
-  it.n_pf = npf;
-  it.n_a = na;
-  // backward step (Sec. 4)
-  timer_begin(s, CC_K_COLOR, st);
-  int rc = color_rows(s, false, st);
-  timer_end(s, st);
-  if (rc != CC_OK) return rc;
-  it.n_colors = s->n_colors;
-  if (trace) {
-    CC_HIP(hipMemsetAsync(&s->dc->fp_col, 0, sizeof(unsigned long long), st));
-    CC_TRY(launch_fp_col(s, st));
-  }
-  timer_begin(s, CC_K_GS, st);
-  CC_TRY(launch_gs(s, st));
-  timer_end(s, st);
-  // forward step (Sec. 5) and the path certificate
-  CC_HIP(hipMemsetAsync(&s->dc->mmax_bits, 0, 2 * sizeof(unsigned long long), st));
-  CC_HIP(hipMemsetAsync(&s->dc->fail, 0, sizeof(unsigned long long), st));
-  CC_HIP(hipMemsetAsync(&s->dc->hits, 0, sizeof(unsigned long long), st));
-  timer_begin(s, CC_K_FORWARD, st);
-  CC_TRY(launch_forward(s, st));
-  timer_end(s, st);
-  timer_begin(s, CC_K_CERT, st);
-  CC_TRY(launch_cert(s, st));
-  timer_end(s, st);
-  CC_HIP(hipMemcpyAsync(s->hc, s->dc, sizeof(Counters), hipMemcpyDeviceToHost, st));
-  CC_HIP(hipStreamSynchronize(st));
-  resolve_timers(s);
-  const double mmax = bits2d(s->hc->mmax_bits), rinf = bits2d(s->hc->rinf_bits);
-  it.move_max = mmax;
-  it.r_inf = rinf;
-  it.ccd_fail = (int64_t)s->hc->fail;
-  it.ccd_hits = (int64_t)s->hc->hits;
-  if (trace) it.fp_col = s->hc->fp_col;
-  s->D = D - 2.0 * mmax;
-  it.d_after = s->D;
-  const int done = rinf < p.eps ? 1 : 0;
-  // statistics and algorithmic bytes
-  s->st.iters += 1;
-  s->st.pair_updates += it.n_p;
-  s->st.row_updates += (na + s->n_erows) * (int64_t)p.gs_sweeps;
-  s->st.ccd_fail += it.ccd_fail;
-  s->st.ccd_hits += it.ccd_hits;
-  s->st.r_inf = rinf;
-  if (it.n_colors > s->st.max_colors_used) s->st.max_colors_used = it.n_colors;
-  if (done) s->st.status = CC_CONVERGED;
-  {
-    const double N = s->n, F = s->nt, E = s->ne;
-    s->st.kernel_bytes[CC_K_PAIR] += 8.0 * it.n_p + 16.0 * npf + 24.0 * na + 32.0 * N + 12.0 * F + 8.0 * E;
-    s->st.kernel_bytes[CC_K_FORWARD] += 92.0 * N;
-    s->st.kernel_bytes[CC_K_CERT] += 16.0 * npf + 8.0 * N + 12.0 * F + 8.0 * E;
-  }
+  Seg& g = s->segs[0];
+  g.active = true;  // a converged scene may still be stepped by hand
+  CC_TRY(engine_iterate(s, as_stream(stream)));
+  s->D = g.D;
+  const int done = g.last.r_inf < s->p.eps ? 1 : 0;
   if (stop) *stop = done;
-  if (info) *info = it;
+  if (info) *info = g.last;
   return CC_OK;
 }
 
@@ -450,10 +804,11 @@ int cc_solver_run(cc_solver* s, double* x_out, cc_stats* stats, void* stream) {
     CC_TRY(cc_solver_iterate(s, &stop, nullptr, stream));
     if (stop) break;
   }
-  if (x_out && s->n)
-    CC_HIP(hipMemcpyAsync(x_out, s->x, sizeof(double) * 3 * s->n, hipMemcpyDefault, as_stream(stream)));
+  if (x_out && s->segs[0].nv)
+    CC_HIP(hipMemcpyAsync(x_out, s->x, sizeof(double) * 3 * s->segs[0].nv, hipMemcpyDefault,
+                          as_stream(stream)));
   CC_HIP(hipStreamSynchronize(as_stream(stream)));
-  if (stats) *stats = s->st;
+  if (stats) seg_stats(s, 0, stats);
   return CC_OK;
 }
 
@@ -461,10 +816,12 @@ int cc_collide_step(cc_context* ctx, const double* x_prev, const double* x_tilde
                     const double* inv_mass, int32_t n, const int32_t* tris, int32_t nt,
                     const int32_t* edges, int32_t ne, const cc_params* params, double* x_next,
                     cc_stats* stats, void* stream) {
-  if (!ctx || (n > 0 && !x_next)) return CC_EINVAL;
+  if (!ctx || n < 0 || nt < 0 || ne < 0 || (n > 0 && !x_next)) return CC_EINVAL;
+  if ((nt > 0 && !tris) || (ne > 0 && !edges)) return CC_EINVAL;
   if (n > 0 && (x_next == x_prev || x_next == x_tilde)) return CC_EINVAL;
   CC_TRY(check_params(params));
-  CC_TRY(bind_solver(ctx, ctx->cached, n, inv_mass, tris, nt, edges, ne, params, stream));
+  if (hipSetDevice(ctx->device) != hipSuccess) return CC_EHIP;
+  CC_TRY(bind_single(ctx, ctx->cached, n, inv_mass, tris, nt, edges, ne, params, as_stream(stream)));
   CC_TRY(cc_solver_begin(ctx->cached, x_prev, x_tilde, stream));
   return cc_solver_run(ctx->cached, x_next, stats, stream);
 }
@@ -472,51 +829,69 @@ int cc_collide_step(cc_context* ctx, const double* x_prev, const double* x_tilde
 int cc_collide_step_batched(cc_context* ctx, const cc_scene* scenes, int32_t ns,
                             const cc_params* params, cc_stats* stats, void* stream) {
   if (!ctx || ns < 0 || (ns > 0 && !scenes)) return CC_EINVAL;
+  if (ns > kMaxSeg) return CC_EINVAL;
   CC_TRY(check_params(params));
   for (int32_t i = 0; i < ns; ++i) {
     const cc_scene& sc = scenes[i];
-    if (sc.n_verts < 0 || (sc.n_verts > 0 && !sc.x_next)) return CC_EINVAL;
+    if (sc.n_verts < 0 || sc.n_tris < 0 || sc.n_edges < 0) return CC_EINVAL;
+    if (sc.n_verts > 0 && (!sc.x_next || !sc.x_prev || !sc.x_tilde)) return CC_EINVAL;
     if (sc.n_verts > 0 && (sc.x_next == sc.x_prev || sc.x_next == sc.x_tilde)) return CC_EINVAL;
   }
   if (ns == 0) return CC_OK;
   if (hipSetDevice(ctx->device) != hipSuccess) return CC_EHIP;
-  hipStream_t cst = as_stream(stream);
-  while ((int32_t)ctx->slots.size() < ns) {
-    hipStream_t s = nullptr;
-    CC_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-    ctx->slots.push_back(nullptr);
-    ctx->slot_streams.push_back(s);
-  }
-  // the inputs are produced on the caller's stream: every slot stream waits for it
-  hipEvent_t ready = nullptr;
-  CC_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
-  CC_HIP(hipEventRecord(ready, cst));
-  for (int32_t i = 0; i < ns; ++i) CC_HIP(hipStreamWaitEvent(ctx->slot_streams[i], ready, 0));
-  std::vector<int> rc(ns, CC_OK);
-  std::atomic<int32_t> next{0};
-  auto worker = [&]() {
-    if (hipSetDevice(ctx->device) != hipSuccess) return;
-    for (int32_t i = next++; i < ns; i = next++) {
-      const cc_scene& sc = scenes[i];
-      void* st = (void*)ctx->slot_streams[i];
-      int r = bind_solver(ctx, ctx->slots[i], sc.n_verts, sc.inv_mass, sc.tris, sc.n_tris,
-                          sc.edges, sc.n_edges, params, st);
-      if (r == CC_OK) r = cc_solver_begin(ctx->slots[i], sc.x_prev, sc.x_tilde, st);
-      if (r == CC_OK) r = cc_solver_run(ctx->slots[i], sc.x_next, stats ? &stats[i] : nullptr, st);
-      rc[i] = r;
-    }
-  };
-  const int32_t nthreads = std::min<int32_t>(ns, 16);
-  std::vector<std::thread> pool;
-  for (int32_t t = 1; t < nthreads; ++t) pool.emplace_back(worker);
-  worker();
-  for (auto& th : pool) th.join();
-  // order the caller's stream after every scene
+  hipStream_t st = as_stream(stream);
+  int64_t V = 0, F = 0, E = 0;
   for (int32_t i = 0; i < ns; ++i) {
-    CC_HIP(hipEventRecord(ready, ctx->slot_streams[i]));
-    CC_HIP(hipStreamWaitEvent(cst, ready, 0));
+    V += scenes[i].n_verts;
+    F += scenes[i].n_tris;
+    E += scenes[i].n_edges;
   }
-  CC_HIP(hipEventDestroy(ready));
+  if (V > INT_MAX / 4 || F > INT_MAX / 4 || E > INT_MAX / 4) return CC_EINVAL;
+  if (!ctx->batched)
+    CC_TRY(engine_create(ctx, params, (int32_t)V, (int32_t)F, (int32_t)E, &ctx->batched, st));
+  cc_solver* s = ctx->batched;
+  engine_set_params(s, params);
+  for (int32_t i = 0; i < (int32_t)s->segs.size(); ++i)
+    if (s->segs[i].live) CC_TRY(seg_remove(s, i, st));
+  s->nP = 0;
+  release_pending(s);
+  for (auto& g : s->segs) g.pending = false;
+  s->pending_segs.clear();
+  memset(&s->st, 0, sizeof s->st);
+  std::vector<int> rc(ns, CC_OK);
+  std::vector<int32_t> sg(ns, -1), begin_ids;
+  std::vector<const double*> xp, xt;
+  std::vector<int32_t> begin_of;
+  for (int32_t i = 0; i < ns; ++i) {
+    const cc_scene& sc = scenes[i];
+    rc[i] = seg_add(s, sc.n_verts, sc.inv_mass, sc.tris, sc.n_tris, sc.edges, sc.n_edges,
+                    params->max_iters, &sg[i], st);
+    if (rc[i] != CC_OK) continue;
+    begin_ids.push_back(sg[i]);
+    xp.push_back(sc.x_prev);
+    xt.push_back(sc.x_tilde);
+    begin_of.push_back(i);
+  }
+  if (!begin_ids.empty()) {
+    std::vector<int> brc(begin_ids.size(), CC_OK);
+    int r = seg_begin(s, begin_ids.data(), (int32_t)begin_ids.size(), xp.data(), xt.data(),
+                      brc.data(), st);
+    for (size_t k = 0; k < begin_ids.size(); ++k) {
+      if (brc[k] != CC_OK) rc[begin_of[k]] = brc[k];
+      if (brc[k] != CC_OK && s->segs[begin_ids[k]].live) s->segs[begin_ids[k]].active = false;
+    }
+    if (r != CC_OK) return r;
+    while (engine_active(s) > 0) CC_TRY(engine_iterate(s, st));
+  }
+  for (int32_t i = 0; i < ns; ++i) {
+    if (rc[i] != CC_OK) continue;
+    const Seg& g = s->segs[sg[i]];
+    if (g.nv)
+      CC_HIP(hipMemcpyAsync(scenes[i].x_next, s->x + 3 * (int64_t)g.vb, sizeof(double) * 3 * g.nv,
+                            hipMemcpyDefault, st));
+    if (stats) seg_stats(s, sg[i], &stats[i]);
+  }
+  CC_HIP(hipStreamSynchronize(st));
   for (int32_t i = 0; i < ns; ++i)
     if (rc[i] != CC_OK) return rc[i];
   return CC_OK;
@@ -524,14 +899,16 @@ int cc_collide_step_batched(cc_context* ctx, const cc_scene* scenes, int32_t ns,
 
 int cc_solver_get_state(cc_solver* s, double* x, double* y, double* r, double* D_host,
                         void* stream) {
-  if (!s) return CC_EINVAL;
+  if (!s || s->segs.empty()) return CC_EINVAL;
   hipStream_t st = as_stream(stream);
-  size_t n3 = sizeof(double) * 3 * s->n;
-  if (x && s->n) CC_HIP(hipMemcpyAsync(x, s->x, n3, hipMemcpyDefault, st));
-  if (y && s->n) CC_HIP(hipMemcpyAsync(y, s->y, n3, hipMemcpyDefault, st));
-  if (r && s->n) CC_HIP(hipMemcpyAsync(r, s->r, sizeof(double) * s->n, hipMemcpyDefault, st));
+  const int32_t n = s->segs[0].nv;
+  size_t n3 = sizeof(double) * 3 * n;
+  if (x && n) CC_HIP(hipMemcpyAsync(x, s->x, n3, hipMemcpyDefault, st));
+  if (y && n && (s->p.flags & CC_MIXED)) CC_TRY(launch_y_of_dy(s, y, n, st));
+  else if (y && n) CC_HIP(hipMemcpyAsync(y, s->y, n3, hipMemcpyDefault, st));
+  if (r && n) CC_HIP(hipMemcpyAsync(r, s->r, sizeof(double) * n, hipMemcpyDefault, st));
   CC_HIP(hipStreamSynchronize(st));
-  if (D_host) *D_host = s->D;
+  if (D_host) *D_host = s->segs[0].D;
   return CC_OK;
 }
 
@@ -540,14 +917,17 @@ int cc_solver_set_state(cc_solver* s, const double* x, const double* y, const do
   if (!s || n_p < 0 || (n_p > 0 && !P)) return CC_EINVAL;
   if (!s->begun) return CC_ESTATE;
   hipStream_t st = as_stream(stream);
-  size_t n3 = sizeof(double) * 3 * s->n;
-  if (n_p > s->capP) CC_TRY(alloc_pairs(s, n_p + n_p / 4 + 1024));
-  if (x && s->n) CC_HIP(hipMemcpyAsync(s->x, x, n3, hipMemcpyDefault, st));
-  if (y && s->n) CC_HIP(hipMemcpyAsync(s->y, y, n3, hipMemcpyDefault, st));
-  if (r && s->n) CC_HIP(hipMemcpyAsync(s->r, r, sizeof(double) * s->n, hipMemcpyDefault, st));
+  const int32_t n = s->segs[0].nv;
+  size_t n3 = sizeof(double) * 3 * n;
+  if (n_p > s->capP) CC_TRY(alloc_pairs(s, n_p + n_p / 4 + 1024, 0, st));
+  if (x && n) CC_HIP(hipMemcpyAsync(s->x, x, n3, hipMemcpyDefault, st));
+  if (y && n) CC_HIP(hipMemcpyAsync(s->y, y, n3, hipMemcpyDefault, st));
+  if (y && n && (s->p.flags & CC_MIXED)) CC_TRY(launch_dy_of_y(s, y, n, st));
+  if (r && n) CC_HIP(hipMemcpyAsync(s->r, r, sizeof(double) * n, hipMemcpyDefault, st));
   if (n_p) CC_HIP(hipMemcpyAsync(s->P, P, sizeof(uint64_t) * n_p, hipMemcpyDefault, st));
   CC_HIP(hipStreamSynchronize(st));
   s->nP = n_p;
+  s->segs[0].D = D;
   s->D = D;
   return CC_OK;
 }
@@ -575,25 +955,29 @@ int cc_solver_get_A(cc_solver* s, uint64_t* keys, int32_t* colors, int64_t cap, 
 }
 
 int cc_solver_get_Di(cc_solver* s, double* out, void* stream) {
-  if (!s || (!out && s->n)) return CC_EINVAL;
-  if (s->n) CC_HIP(hipMemcpyAsync(out, s->Di, sizeof(double) * s->n, hipMemcpyDefault, as_stream(stream)));
+  if (!s || s->segs.empty()) return CC_EINVAL;
+  const int32_t n = s->segs[0].nv;
+  if (!out && n) return CC_EINVAL;
+  if (n) CC_HIP(hipMemcpyAsync(out, s->Di, sizeof(double) * n, hipMemcpyDefault, as_stream(stream)));
   CC_HIP(hipStreamSynchronize(as_stream(stream)));
   return CC_OK;
 }
 
 int cc_solver_search(cc_solver* s, const double* x, double dmax, uint64_t* keys, int64_t cap,
                      int64_t* n, void* stream) {
-  if (!s || !x || !n || !(dmax > 0.0)) return CC_EINVAL;
+  if (!s || s->segs.empty() || !x || !n || !(dmax > 0.0)) return CC_EINVAL;
   hipStream_t st = as_stream(stream);
-  CC_TRY(launch_validate(s, x, nullptr, st));
+  const int32_t nv = s->segs[0].nv;
+  CC_TRY(launch_check_finite(s, x, nullptr, nv, st));
   // the static flags come from the last begin; without one every vertex counts as free
-  if (!s->begun && s->n) CC_HIP(hipMemsetAsync(s->stat, 0, s->n, st));
-  return lbvh_search(s, x, dmax, keys, keys ? cap : 0, n, st);
+  if (!s->begun && nv) CC_HIP(hipMemsetAsync(s->stat, 0, nv, st));
+  s->sel_host[0].seg = 0;
+  return lbvh_search(s, 1, x, dmax, keys, keys ? cap : 0, n, st);
 }
 
 int cc_solver_stats(cc_solver* s, cc_stats* out) {
-  if (!s || !out) return CC_EINVAL;
-  *out = s->st;
+  if (!s || !out || s->segs.empty()) return CC_EINVAL;
+  seg_stats(s, 0, out);
   return CC_OK;
 }
 

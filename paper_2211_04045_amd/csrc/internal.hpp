@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <array>
+#include <utility>
 #include <vector>
 
 #include "../../include/cc.h"
@@ -25,6 +27,29 @@ constexpr int kMaxColors = 1024;
 constexpr int kMaskWords = kMaxColors / 64;
 constexpr int kMaxRounds = 65536;  // Jones-Plassmann rounds per colouring
 constexpr double kCcdEta = 1e-12;  // distance at which the continuous test reports contact (m)
+constexpr int kMaxSeg = 1024;      // scenes (segments) resident in one solver
+constexpr int kSegBits = 10;       // bits of a segment's rank in a search's sort keys
+
+// Per-segment record on the device (one scene of a multi-scene solver). The host
+// writes D, D2, bases and flags before an iteration and reads the reductions back.
+struct SegDev {
+  double D;                     // D^(l) of the segment
+  double D2;                    // D^(l) squared (pair filter)
+  int32_t vb, fb, eb;           // first vertex, triangle and edge of the segment
+  int32_t flags;                // kSegActive | kSegSearched
+  unsigned long long mmax_bits; // max ||dx|| of the forward step (double bits)
+  unsigned long long rinf_bits; // max r after the forward step
+  unsigned long long fail;      // certificate failures
+  unsigned long long hits;      // continuous-test contacts
+  unsigned long long n_p;       // pairs evaluated by the pair pass
+  unsigned long long n_pf;      // |P'|
+  unsigned long long n_a;       // |A|
+  unsigned long long n_rows;    // valid edge-length rows (setup)
+  unsigned long long pad[4];
+};
+static_assert(sizeof(SegDev) == 128, "SegDev is one 128-byte record");
+constexpr int32_t kSegActive = 1;    // the segment iterates
+constexpr int32_t kSegSearched = 2;  // searched this iteration: its older pairs are dropped
 
 // Device-side counters, reset and read back by the host loop.
 struct Counters {
@@ -43,7 +68,8 @@ struct Counters {
   unsigned long long pad[3];
 };
 
-// Device buffers of a linear BVH over n leaves (n-1 internal nodes).
+// Device buffers of a linear BVH over n leaves (n-1 internal nodes), allocated
+// for the solver's capacity; n is the leaf count of the last search.
 // Node record (4 float4 = 64 B): left box (6 floats), right box (6 floats),
 // then child ids (bit 31 set = leaf, low bits = primitive id), the split
 // position and the last leaf position of the node's range.
@@ -52,7 +78,6 @@ struct Bvh {
   float4* leaf_lo = nullptr;     // sorted leaf boxes
   float4* leaf_hi = nullptr;
   int32_t* leaf_prim = nullptr;  // sorted position -> primitive id
-  int32_t* pos_of = nullptr;     // primitive id -> sorted position
   float4* node = nullptr;        // 4 per internal node
   float4* wide = nullptr;        // 8 per internal node: 4-wide traversal records
   int32_t* parent = nullptr;     // n-1 internal then n leaves: (parent << 1) | side
@@ -75,18 +100,66 @@ struct cc_server;  // resident-scene serving state (serve.hip)
 struct cc_context {
   int device = 0;
   cc_server* server = nullptr;
-  cc_solver* cached = nullptr;  // workspace reused by cc_collide_step
-  // batched steps: one solver and one stream per scene slot
-  std::vector<cc_solver*> slots;
-  std::vector<hipStream_t> slot_streams;
+  cc_solver* cached = nullptr;   // workspace reused by cc_collide_step
+  cc_solver* batched = nullptr;  // multi-scene workspace reused by cc_collide_step_batched
 };
+
+namespace cc {
+
+// Host view of one segment: a scene occupying index ranges of the solver's
+// vertex, triangle and edge arrays (topology stored with solver-wide vertex ids).
+struct Seg {
+  int32_t vb = 0, nv = 0, fb = 0, nf = 0, eb = 0, ne = 0;
+  int32_t max_iters = 0;
+  double D = 0.0;
+  bool live = false;     // holds a scene
+  bool active = false;   // iterating
+  bool begun = false;
+  bool pending = false;  // removed; its ranges are not yet free
+  int32_t n_erows = 0;
+  cc_stats st{};
+  cc_iter_info last{};
+};
+
+// One selected segment of a proximity search: its bases and the offsets of its
+// vertices, triangles and edges in the search's compact arrays.
+struct SelDev {
+  int32_t vb, fb, eb, seg;
+  int32_t voff, toff, eoff, pad;
+};
+
+// First-fit allocator of index ranges.
+struct RangeAlloc {
+  int32_t cap = 0;
+  std::vector<std::pair<int32_t, int32_t>> free_;  // (start, length), sorted, coalesced
+  int32_t take(int32_t len);                       // start or -1
+  void give(int32_t start, int32_t len);
+  void grow(int32_t new_cap);
+  int32_t extent() const;                          // one past the last used index
+};
+
+}  // namespace cc
 
 struct cc_solver {
   cc_context* ctx = nullptr;
+  // used extents (one past the highest index any segment holds) and capacities
   int32_t n = 0, nt = 0, ne = 0;
+  int32_t capV = 0, capF = 0, capE = 0;
   cc_params p{};
   double kappa2 = 0.0;
-  bool begun = false;
+  bool begun = false;  // single-scene interface: segment 0 begun
+  // segments
+  std::vector<cc::Seg> segs;
+  cc::SegDev* seg_dev = nullptr;   // kMaxSeg records
+  cc::SegDev* seg_host = nullptr;  // pinned mirror
+  cc::RangeAlloc ra_v, ra_f, ra_e;
+  // ranges of removed segments (kind 0 vertices, 1 triangles, 2 edges; start;
+  // length), freed after the next pair pass has dropped their pairs
+  std::vector<std::array<int32_t, 3>> pending_free;
+  std::vector<int32_t> pending_segs;
+  int32_t* vseg = nullptr;  // segment of each vertex (-1 = none)
+  int32_t* eseg = nullptr;  // segment of each edge (-1 = none)
+  bool erows_dirty = true;  // the union of edge-row colour buckets needs a rebuild
   // topology and masses
   double* w = nullptr;
   int32_t* tris = nullptr;
@@ -94,9 +167,10 @@ struct cc_solver {
   uint8_t* stat = nullptr;
   // state
   double *x = nullptr, *y = nullptr, *xt = nullptr, *r = nullptr, *move2 = nullptr;
+  float* dy = nullptr;  // mixed precision: y - x in FP32 (3 per vertex)
   double* xold = nullptr;  // x^(l) kept by the forward step for the continuous test
   unsigned long long* Di = nullptr;
-  double D = 0.0;
+  double D = 0.0;  // single-scene interface: D of segment 0
   // proximity set (double buffered for compaction) and distances of P'
   uint64_t *P = nullptr, *P2 = nullptr;
   double *dP = nullptr, *dP2 = nullptr;
@@ -111,14 +185,15 @@ struct cc_solver {
   int64_t nA = 0;
   int32_t n_colors = 0;
   std::vector<int32_t> col_off;  // host copy of colour bucket offsets (n_colors+1)
-  // edge-length rows (one per input edge; inv_a = 0 marks an unused edge)
+  // edge-length rows (one per edge; inv_a = 0 marks an unused edge)
   double* eg = nullptr;     // 3 per edge
   double* einv = nullptr;
   int32_t* ecol = nullptr;
   int32_t* eorder = nullptr;
   int32_t *elist0 = nullptr, *elist1 = nullptr, *elist2 = nullptr;
   double* lamE = nullptr;
-  int32_t n_erows = 0, n_ecolors = 0;
+  int32_t n_erows = 0, n_ecolors = 0;  // rows in the union buckets, their colours
+  int32_t n_newrows = 0;               // rows being coloured at a begin
   std::vector<int32_t> ecol_off;
   // colouring scratch
   unsigned long long *vmax0 = nullptr, *vmax1 = nullptr, *masks = nullptr;
@@ -127,14 +202,22 @@ struct cc_solver {
   int32_t *coff_dev = nullptr, *ecoff_dev = nullptr;  // colour bucket offsets on the device
   // broad phase
   cc::Bvh tree_t, tree_e;
-  uint32_t *sk0 = nullptr, *sk1 = nullptr, *sv0 = nullptr, *sv1 = nullptr;
+  uint64_t *sk0 = nullptr, *sk1 = nullptr;
+  uint32_t *sv0 = nullptr, *sv1 = nullptr;
   uint32_t* rs_hist = nullptr;
   uint32_t* rs_total = nullptr;  // per-digit totals of one radix pass
   int64_t rs_hist_cap = 0;
-  float4 *ubox_lo = nullptr, *ubox_hi = nullptr;  // unsorted leaf boxes (F then E)
+  float4 *ubox_lo = nullptr, *ubox_hi = nullptr;  // compact leaf boxes (F then E)
+  int32_t* gprim = nullptr;    // compact primitive -> triangle or edge id
   uint32_t* bounds = nullptr;  // box-centre bounds, order-preserving uint encoding
   uint32_t* bounds_part = nullptr;  // per-block partial bounds
-  int32_t* vorder = nullptr;   // vertices in Morton order (vertex-triangle queries)
+  int32_t* vorder = nullptr;   // vertex queries in Morton order (vertex ids)
+  int16_t* vrank = nullptr;    // selected-segment rank of each vertex query
+  int16_t* erank = nullptr;    // selected-segment rank of each sorted edge leaf
+  cc::SelDev* sel_dev = nullptr;   // kMaxSeg + 1
+  cc::SelDev* sel_host = nullptr;  // pinned
+  int32_t* root_t = nullptr;       // per selected segment: root of its triangle subtree
+  int32_t* root_e = nullptr;       // ... of its edge subtree
   // counters
   cc::Counters* dc = nullptr;
   cc::Counters* hc = nullptr;  // pinned host mirror
@@ -150,24 +233,58 @@ namespace cc {
 // broad phase (lbvh.hip)
 int bvh_alloc(cc_solver* s);
 void bvh_free(cc_solver* s);
-// Search at state x with bound dmax; appends pair keys to out (capacity cap);
-// *n gets the total number found (may exceed cap: caller regrows).
-int lbvh_search(cc_solver* s, const double* x, double dmax, uint64_t* out, int64_t cap,
-                int64_t* n, hipStream_t st);
+// Search of the segments listed in s->sel_host[0..nsel) at state x with bound
+// dmax; appends pair keys (solver-wide ids) to out (capacity cap); *n gets the
+// total number found (may exceed cap: caller regrows).
+int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64_t* out,
+                int64_t cap, int64_t* n, hipStream_t st);
 
 // per-iteration kernels (step.hip)
-int launch_validate(cc_solver* s, const double* xa, const double* xb, hipStream_t st);
-int launch_setup(cc_solver* s, const double* x_prev, const double* x_tilde, hipStream_t st);
+// Copy a scene's topology in (local vertex ids -> solver-wide) and check it;
+// CC_EINVAL on an out-of-range or repeated index.
+int launch_topo_in(cc_solver* s, int32_t seg, const int32_t* tris, const int32_t* edges,
+                   hipStream_t st);
+int launch_check_finite(cc_solver* s, const double* xa, const double* xb, int32_t n,
+                        hipStream_t st);
+int launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
+int launch_setup(cc_solver* s, int32_t seg, const double* x_prev, const double* x_tilde,
+                 hipStream_t st);
 int launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t st);
-int launch_pair_pass(cc_solver* s, double D2, double dl2, bool trace, hipStream_t st);
+int launch_di_init(cc_solver* s, hipStream_t st);
+// pairs [0, n_old) are last iteration's P'; [n_old, nP) were appended by a search
+int launch_pair_pass(cc_solver* s, int64_t n_old, double dl2, bool trace, hipStream_t st);
+// contacts: colour A; edges: colour the n_newrows rows listed in elist0
 int color_rows(cc_solver* s, bool edges, hipStream_t st);
+int build_edge_buckets(cc_solver* s, hipStream_t st);
 int launch_gs(cc_solver* s, hipStream_t st);
 int launch_forward(cc_solver* s, hipStream_t st);
 int launch_cert(cc_solver* s, hipStream_t st);
 int launch_fp_col(cc_solver* s, hipStream_t st);
+// mixed precision: y <-> x + dy for vertices [0, n)
+int launch_y_of_dy(cc_solver* s, double* y, int32_t n, hipStream_t st);
+int launch_dy_of_y(cc_solver* s, const double* y, int32_t n, hipStream_t st);
 
-// serving (serve.hip): stop the worker pool and free every resident scene
+// serving (serve.hip): stop the scheduler and free every resident scene
 void server_destroy(cc_context* ctx);
+
+// engine (api.hip)
+int check_params(const cc_params* p);
+int engine_create(cc_context* ctx, const cc_params* params, int32_t capV, int32_t capF,
+                  int32_t capE, cc_solver** out, hipStream_t st);
+void engine_set_params(cc_solver* s, const cc_params* params);
+// Add a scene (topology with its own vertex ids 0..nv-1, device pointers) as a
+// segment; the arrays grow when its ranges do not fit. *out = segment id.
+int seg_add(cc_solver* s, int32_t nv, const double* inv_mass, const int32_t* tris, int32_t nf,
+            const int32_t* edges, int32_t ne, int32_t max_iters, int32_t* out, hipStream_t st);
+int seg_remove(cc_solver* s, int32_t sg, hipStream_t st);
+void release_pending(cc_solver* s);
+// Begin k segments' steps (x_prev[i] NULL = the segment's resident x).
+int seg_begin(cc_solver* s, const int32_t* sgs, int32_t k, const double* const* x_prev,
+              const double* const* x_tilde, int* rc, hipStream_t st);
+// One Alg. 1 iteration of every iterating segment.
+int engine_iterate(cc_solver* s, hipStream_t st);
+int engine_active(const cc_solver* s);
+void seg_stats(const cc_solver* s, int32_t sg, cc_stats* out);
 
 // timing helpers (api.hip)
 void timer_begin(cc_solver* s, int kind, hipStream_t st);

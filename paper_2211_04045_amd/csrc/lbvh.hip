@@ -18,6 +18,9 @@
 // appended through a per-lane LDS buffer flushed with one atomic per wave.
 // Edge queries run in sorted order and visit only leaves after their own, so
 // each edge-edge pair is found once.
+// Several scenes (segments) are searched together: a segment's rank sits above
+// the Morton code in the sort key, so each segment's leaves form one subtree
+// of the radix tree, and its queries start at that subtree's root.
 #include "geom.hpp"
 #include "internal.hpp"
 
@@ -45,24 +48,48 @@ __device__ __forceinline__ float hi_out(double v) {
   return nextafterf(__double2float_ru(v), __builtin_inff());
 }
 
-// Leaf boxes for all F triangles then E edges; per-block bounds of the box
-// centres (order-preserving uint encoding), reduced by k_bounds_reduce.
+// Rank r of the selected segment holding compact index g of one kind
+// (0 vertices, 1 triangles, 2 edges): off(r) <= g < off(r + 1).
+__device__ __forceinline__ int32_t sel_off(const SelDev& d, int kind) {
+  return kind == 0 ? d.voff : (kind == 1 ? d.toff : d.eoff);
+}
+__device__ __forceinline__ int32_t find_sel(const SelDev* __restrict__ sel, int32_t nsel,
+                                            int kind, int32_t g) {
+  int32_t lo = 0, hi = nsel - 1;
+  while (lo < hi) {
+    int32_t mid = (lo + hi + 1) >> 1;
+    if (sel_off(sel[mid], kind) <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Leaf boxes of the selected segments' triangles (compact 0..mt) then edges
+// (mt..mt+me), their primitive ids, and per-block bounds of the box centres
+// (order-preserving uint encoding), reduced by k_bounds_reduce.
 __global__ void k_boxes(const double* __restrict__ x, const int32_t* __restrict__ tris,
-                        const int32_t* __restrict__ edges, int32_t nt, int32_t ne, double infl,
+                        const int32_t* __restrict__ edges, const SelDev* __restrict__ sel,
+                        int32_t nsel, int32_t mt, int32_t me, double infl,
                         float4* __restrict__ blo, float4* __restrict__ bhi,
-                        uint32_t* __restrict__ part) {
+                        int32_t* __restrict__ gprim, uint32_t* __restrict__ part) {
   __shared__ uint32_t sb[6];
   if (threadIdx.x < 6) sb[threadIdx.x] = (threadIdx.x < 3) ? 0xffffffffu : 0u;
   __syncthreads();
   int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < nt + ne) {
+  if (g < mt + me) {
     V3 lo, hi;
-    if (g < nt) {
-      V3 a = ld3(x, tris[3 * g]), b = ld3(x, tris[3 * g + 1]), c = ld3(x, tris[3 * g + 2]);
+    if (g < mt) {
+      const int32_t r = find_sel(sel, nsel, 1, g);
+      const int32_t f = sel[r].fb + (g - sel[r].toff);
+      gprim[g] = f;
+      V3 a = ld3(x, tris[3 * f]), b = ld3(x, tris[3 * f + 1]), c = ld3(x, tris[3 * f + 2]);
       lo = V3{fmin(fmin(a.x, b.x), c.x), fmin(fmin(a.y, b.y), c.y), fmin(fmin(a.z, b.z), c.z)};
       hi = V3{fmax(fmax(a.x, b.x), c.x), fmax(fmax(a.y, b.y), c.y), fmax(fmax(a.z, b.z), c.z)};
     } else {
-      int32_t e = g - nt;
+      const int32_t ge = g - mt;
+      const int32_t r = find_sel(sel, nsel, 2, ge);
+      const int32_t e = sel[r].eb + (ge - sel[r].eoff);
+      gprim[g] = e;
       V3 a = ld3(x, edges[2 * e]), b = ld3(x, edges[2 * e + 1]);
       lo = V3{fmin(a.x, b.x), fmin(a.y, b.y), fmin(a.z, b.z)};
       hi = V3{fmax(a.x, b.x), fmax(a.y, b.y), fmax(a.z, b.z)};
@@ -109,24 +136,30 @@ __device__ __forceinline__ uint32_t spread10(uint32_t v) {
   return v;
 }
 
-// Morton keys of the triangle boxes (group 0), edge boxes (group 1) and vertices
-// (group 2, used to order the vertex queries); group id in bits 31..30.
+// Sort keys: 30-bit Morton code of the triangle boxes (group 0), edge boxes
+// (group 1) and vertices (group 2, the order of the vertex queries), the
+// selected segment's rank in the rb bits above it and the group above that.
 __global__ void k_morton(const float4* __restrict__ blo, const float4* __restrict__ bhi,
-                         const double* __restrict__ x, int32_t nt, int32_t ne, int32_t n,
-                         const uint32_t* __restrict__ bounds, uint32_t* __restrict__ keys,
+                         const double* __restrict__ x, const SelDev* __restrict__ sel,
+                         int32_t nsel, int32_t mt, int32_t me, int32_t mv, int rb,
+                         const uint32_t* __restrict__ bounds, uint64_t* __restrict__ keys,
                          uint32_t* __restrict__ vals) {
   int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nt + ne + n) return;
+  if (g >= mt + me + mv) return;
   float c[3];
-  uint32_t grp;
-  if (g < nt + ne) {
+  uint64_t grp;
+  int32_t r;
+  if (g < mt + me) {
     float4 l = blo[g], h = bhi[g];
     c[0] = 0.5f * (l.x + h.x);
     c[1] = 0.5f * (l.y + h.y);
     c[2] = 0.5f * (l.z + h.z);
-    grp = g < nt ? 0u : 1u;
+    grp = g < mt ? 0u : 1u;
+    r = g < mt ? find_sel(sel, nsel, 1, g) : find_sel(sel, nsel, 2, g - mt);
   } else {
-    V3 p = ld3(x, g - nt - ne);
+    const int32_t gv = g - mt - me;
+    r = find_sel(sel, nsel, 0, gv);
+    V3 p = ld3(x, sel[r].vb + (gv - sel[r].voff));
     c[0] = (float)p.x;
     c[1] = (float)p.y;
     c[2] = (float)p.z;
@@ -142,13 +175,13 @@ __global__ void k_morton(const float4* __restrict__ blo, const float4* __restric
     q[k] = (uint32_t)v;
   }
   uint32_t code = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
-  keys[g] = code | (grp << 30);
+  keys[g] = (grp << (30 + rb)) | ((uint64_t)r << 30) | code;
   vals[g] = (uint32_t)g;
 }
 
 // ---------------------------------------------------------------- radix sort
 
-__global__ void k_rs_hist(const uint32_t* __restrict__ keys, int32_t n, int shift,
+__global__ void k_rs_hist(const uint64_t* __restrict__ keys, int32_t n, int shift,
                           uint32_t* __restrict__ hist, int32_t nb) {
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
@@ -156,7 +189,7 @@ __global__ void k_rs_hist(const uint32_t* __restrict__ keys, int32_t n, int shif
   int32_t base = blockIdx.x * kTile;
   for (int i = 0; i < kTile / kRsThreads; ++i) {
     int32_t idx = base + i * kRsThreads + threadIdx.x;
-    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 0xffu], 1u);
+    if (idx < n) atomicAdd(&h[(uint32_t)(keys[idx] >> shift) & 0xffu], 1u);
   }
   __syncthreads();
   hist[threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
@@ -193,8 +226,8 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scan_digit(uint32_t* __restri
   if (threadIdx.x == 0) total[blockIdx.x] = carry;
 }
 
-__global__ void k_rs_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-                             uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, int32_t n,
+__global__ void k_rs_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                             uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, int32_t n,
                              int shift, const uint32_t* __restrict__ hist, int32_t nb,
                              const uint32_t* __restrict__ total) {
   constexpr int W = kRsThreads / 64;
@@ -222,9 +255,9 @@ __global__ void k_rs_scatter(const uint32_t* __restrict__ kin, const uint32_t* _
     __syncthreads();
     int32_t idx = base + c * kRsThreads + threadIdx.x;
     bool valid = idx < n;
-    uint32_t key = valid ? kin[idx] : 0u;
+    uint64_t key = valid ? kin[idx] : 0ull;
     uint32_t val = valid ? vin[idx] : 0u;
-    uint32_t dig = (key >> shift) & 0xffu;
+    uint32_t dig = (uint32_t)(key >> shift) & 0xffu;
     uint64_t m = __ballot(valid);
     for (int b = 0; b < 8; ++b) {
       uint64_t bb = __ballot((dig >> b) & 1u);
@@ -252,41 +285,43 @@ __global__ void k_rs_scatter(const uint32_t* __restrict__ kin, const uint32_t* _
 
 struct TreeView {
   int32_t n;
-  const uint32_t* keys;     // sorted codes of this tree
+  const uint64_t* keys;     // sorted keys of this tree
+  uint64_t mask;            // key bits below the group (segment rank and Morton code)
   const int32_t* leaf_prim;
   float4* node;             // 4 float4 per internal node
   int32_t* parent;          // internal nodes [0, n-1), then leaves: (parent << 1) | side
   int2* range;
 };
 
-__device__ __forceinline__ int delta_fn(const uint32_t* __restrict__ k, int32_t n, int32_t i,
-                                        int32_t j) {
+__device__ __forceinline__ int delta_fn(const uint64_t* __restrict__ k, uint64_t mask, int32_t n,
+                                        int32_t i, int32_t j) {
   if (j < 0 || j >= n) return -1;
-  uint32_t a = k[i] & 0x3fffffffu, b = k[j] & 0x3fffffffu;
-  if (a != b) return __clz(a ^ b);
-  return 32 + __clz((uint32_t)i ^ (uint32_t)j);
+  uint64_t a = k[i] & mask, b = k[j] & mask;
+  if (a != b) return __clzll((long long)(a ^ b));
+  return 64 + __clz((uint32_t)i ^ (uint32_t)j);
 }
 
 // Internal node i of the radix tree over sorted keys (Karras 2012): its leaf
 // range, split position and children.
 __device__ void karras_node(const TreeView& T, int32_t i) {
-  const uint32_t* k = T.keys;
+  const uint64_t* k = T.keys;
+  const uint64_t mk = T.mask;
   const int32_t n = T.n;
-  int d = delta_fn(k, n, i, i + 1) - delta_fn(k, n, i, i - 1) > 0 ? 1 : -1;
-  int dmin = delta_fn(k, n, i, i - d);
+  int d = delta_fn(k, mk, n, i, i + 1) - delta_fn(k, mk, n, i, i - 1) > 0 ? 1 : -1;
+  int dmin = delta_fn(k, mk, n, i, i - d);
   int32_t lmax = 2;
-  while (delta_fn(k, n, i, i + lmax * d) > dmin) lmax *= 2;
+  while (delta_fn(k, mk, n, i, i + lmax * d) > dmin) lmax *= 2;
   int32_t l = 0;
   for (int32_t t = lmax / 2; t >= 1; t /= 2)
-    if (delta_fn(k, n, i, i + (l + t) * d) > dmin) l += t;
+    if (delta_fn(k, mk, n, i, i + (l + t) * d) > dmin) l += t;
   int32_t j = i + l * d;
-  int dnode = delta_fn(k, n, i, j);
+  int dnode = delta_fn(k, mk, n, i, j);
   int32_t s = 0;
   int32_t div = 2;
   int32_t t;
   do {
     t = (l + div - 1) / div;
-    if (delta_fn(k, n, i, i + (s + t) * d) > dnode) s += t;
+    if (delta_fn(k, mk, n, i, i + (s + t) * d) > dnode) s += t;
     div *= 2;
   } while (t > 1);
   int32_t gam = i + s * d + (d < 0 ? -1 : 0);
@@ -319,46 +354,64 @@ __global__ void k_karras(TreeView ta, TreeView tb) {
   else if (g < na + nb) karras_node(tb, g - na);
 }
 
-// Sorted leaf boxes, primitive ids and positions of both trees.
-__global__ void k_leaves(const uint32_t* __restrict__ sval, const float4* __restrict__ blo,
-                         const float4* __restrict__ bhi, int32_t nt, int32_t ne,
+// Sorted leaf boxes and primitive ids of both trees; the vertex queries in
+// Morton order with their segment ranks; the segment rank of each edge leaf.
+__global__ void k_leaves(const uint32_t* __restrict__ sval, const uint64_t* __restrict__ skey,
+                         const float4* __restrict__ blo, const float4* __restrict__ bhi,
+                         const int32_t* __restrict__ gprim, const SelDev* __restrict__ sel,
+                         int32_t mt, int32_t me, int32_t mv, uint32_t rmask,
                          float4* __restrict__ tlo, float4* __restrict__ thi,
-                         int32_t* __restrict__ tprim, int32_t* __restrict__ tpos,
-                         float4* __restrict__ elo, float4* __restrict__ ehi,
-                         int32_t* __restrict__ eprim, int32_t* __restrict__ epos, int32_t n,
-                         int32_t* __restrict__ vorder) {
+                         int32_t* __restrict__ tprim, float4* __restrict__ elo,
+                         float4* __restrict__ ehi, int32_t* __restrict__ eprim,
+                         int16_t* __restrict__ erank, int32_t* __restrict__ vorder,
+                         int16_t* __restrict__ vrank) {
   int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nt + ne + n) return;
-  uint32_t p = sval[g];
-  if (g >= nt + ne) {
-    vorder[g - nt - ne] = (int32_t)p - nt - ne;
-  } else if (g < nt) {
+  if (g >= mt + me + mv) return;
+  const uint32_t p = sval[g];
+  const int32_t r = (int32_t)((uint32_t)(skey[g] >> 30) & rmask);
+  if (g >= mt + me) {
+    const int32_t q = g - mt - me, gv = (int32_t)p - mt - me;
+    vorder[q] = sel[r].vb + (gv - sel[r].voff);
+    vrank[q] = (int16_t)r;
+  } else if (g < mt) {
     tlo[g] = blo[p];
     thi[g] = bhi[p];
-    tprim[g] = (int32_t)p;
-    tpos[p] = g;
+    tprim[g] = gprim[p];
   } else {
-    int32_t i = g - nt;
+    const int32_t i = g - mt;
     elo[i] = blo[p];
     ehi[i] = bhi[p];
-    eprim[i] = (int32_t)p - nt;
-    epos[(int32_t)p - nt] = i;
+    eprim[i] = gprim[p];
+    erank[i] = (int16_t)r;
   }
 }
 
-// A tree of one leaf: node 0 holds the leaf on the left and an empty box on the right.
-__global__ void k_single(float4* __restrict__ node, float4* __restrict__ root,
-                         const float4* __restrict__ lo, const float4* __restrict__ hi,
-                         const int32_t* __restrict__ prim) {
-  float4 l = lo[0], h = hi[0];
-  const float inf = __builtin_inff();
-  node[0] = make_float4(l.x, l.y, l.z, h.x);
-  node[1] = make_float4(h.y, h.z, inf, inf);
-  node[2] = make_float4(inf, -inf, -inf, -inf);
-  node[3] = make_float4(__int_as_float(kLeaf | prim[0]), __int_as_float(kLeaf | prim[0]),
-                        __int_as_float(0), __int_as_float(0));
-  root[0] = l;
-  root[1] = h;
+// Root of each selected segment's subtree: its leaves are the sorted positions
+// [off(r), off(r+1)); an internal node of a radix tree has one end of its range
+// at its own index, so the node covering exactly that range is `lo` or `hi`.
+// One leaf: the leaf itself (kLeaf | primitive); none: -1.
+__device__ __forceinline__ int32_t seg_root(int32_t lo, int32_t cnt, int32_t n,
+                                            const int2* __restrict__ range,
+                                            const int32_t* __restrict__ prim) {
+  if (cnt <= 0) return -1;
+  if (cnt == 1) return kLeaf | prim[lo];
+  const int32_t hi = lo + cnt - 1;
+  if (lo < n - 1) {
+    int2 rg = range[lo];
+    if (rg.x == lo && rg.y == hi) return lo;
+  }
+  return hi;
+}
+
+__global__ void k_seg_roots(const SelDev* __restrict__ sel, int32_t nsel, int32_t mt,
+                            int32_t me, const int2* __restrict__ trange,
+                            const int32_t* __restrict__ tprim, const int2* __restrict__ erange,
+                            const int32_t* __restrict__ eprim, int32_t* __restrict__ root_t,
+                            int32_t* __restrict__ root_e) {
+  int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nsel) return;
+  root_t[r] = seg_root(sel[r].toff, sel[r + 1].toff - sel[r].toff, mt, trange, tprim);
+  root_e[r] = seg_root(sel[r].eoff, sel[r + 1].eoff - sel[r].eoff, me, erange, eprim);
 }
 
 struct Box6 {
@@ -606,7 +659,11 @@ struct TravArgs {
   const int32_t* edges;
   const uint8_t* stat;
   const int32_t* vorder;  // vertex queries in Morton order
-  int32_t n, ne;
+  const int16_t* vrank;   // their selected-segment ranks
+  const int16_t* erank;   // selected-segment rank of each sorted edge leaf
+  const int32_t* root_t;  // per rank: subtree root in the triangle tree
+  const int32_t* root_e;  // ... in the edge tree
+  int32_t mv, me;         // vertex queries, edge queries
   double infl, dmax2;
   uint64_t* out;
   int64_t cap;
@@ -635,27 +692,65 @@ __device__ __forceinline__ void wave_flush(uint64_t* skey, int& cnt, const TravA
   cnt = 0;
 }
 
+// Exact test of one candidate primitive against the query: non-adjacent, not
+// all static, FP64 distance below D_max. Returns the pair's key (vertex-triangle:
+// vertex << 32 | triangle; edge-edge: canonical, lower edge first, with the
+// distance taken in that order) or 0.
+__device__ __forceinline__ uint64_t candidate(const TravArgs& A, bool is_vt, int32_t prim,
+                                              int32_t qid, int32_t qv0, int32_t qv1, V3 qx0,
+                                              V3 qx1) {
+  double d2;
+  uint64_t key;
+  if (is_vt) {
+    int32_t v1 = A.tris[3 * prim], v2 = A.tris[3 * prim + 1], v3 = A.tris[3 * prim + 2];
+    if (qv0 == v1 || qv0 == v2 || qv0 == v3 ||
+        (A.stat[qv0] && A.stat[v1] && A.stat[v2] && A.stat[v3]))
+      return 0;
+    double bw[3];
+    d2 = pt_tri_d2(qx0, ld3(A.x, v1), ld3(A.x, v2), ld3(A.x, v3), bw);
+    key = ((uint64_t)(uint32_t)qid << 32) | (uint32_t)prim;
+  } else {
+    int32_t v1 = A.edges[2 * prim], v2 = A.edges[2 * prim + 1];
+    if (qv0 == v1 || qv0 == v2 || qv1 == v1 || qv1 == v2 ||
+        (A.stat[qv0] && A.stat[qv1] && A.stat[v1] && A.stat[v2]))
+      return 0;
+    double s, t;
+    if (qid < prim) {
+      d2 = seg_seg_d2(qx0, qx1, ld3(A.x, v1), ld3(A.x, v2), s, t);
+      key = KEY_EE | ((uint64_t)(uint32_t)qid << 32) | (uint32_t)prim;
+    } else {
+      d2 = seg_seg_d2(ld3(A.x, v1), ld3(A.x, v2), qx0, qx1, s, t);
+      key = KEY_EE | ((uint64_t)(uint32_t)prim << 32) | (uint32_t)qid;
+    }
+  }
+  return d2 < A.dmax2 ? key : 0ull;
+}
+
 __global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
   __shared__ uint64_t skey[kTravThreads * kBuf];
   int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool is_vt = q < A.n;
-  const bool active = q < A.n + A.ne;
+  const bool is_vt = q < A.mv;
+  const bool active = q < A.mv + A.me;
   const TravTree T = is_vt ? A.tt : A.te;
   float4 qlo = make_float4(0.f, 0.f, 0.f, 0.f), qhi = qlo;
   int32_t qv0 = 0, qv1 = 0, qid = 0, qpos = -1;
   V3 qx0{0, 0, 0}, qx1{0, 0, 0};
   int32_t stack[kStack];
   int sp = 0;
-  if (active && T.n > 0) {
+  int cnt = 0;
+  if (active) {
+    int32_t root;
     if (is_vt) {
       qid = A.vorder[q];
+      root = A.root_t[A.vrank[q]];
       qv0 = qid;
       qx0 = ld3(A.x, qid);
       qlo = make_float4(lo_out(qx0.x - A.infl), lo_out(qx0.y - A.infl), lo_out(qx0.z - A.infl), 0.f);
       qhi = make_float4(hi_out(qx0.x + A.infl), hi_out(qx0.y + A.infl), hi_out(qx0.z + A.infl), 0.f);
     } else {
-      qpos = q - A.n;  // sorted position of the query edge in the edge tree
+      qpos = q - A.mv;  // sorted position of the query edge in the edge tree
       qid = T.leaf_prim[qpos];
+      root = A.root_e[A.erank[qpos]];
       qv0 = A.edges[2 * qid];
       qv1 = A.edges[2 * qid + 1];
       qx0 = ld3(A.x, qv0);
@@ -665,10 +760,14 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
       qhi = make_float4(hi_out(fmax(qx0.x, qx1.x) + A.infl), hi_out(fmax(qx0.y, qx1.y) + A.infl),
                         hi_out(fmax(qx0.z, qx1.z) + A.infl), 0.f);
     }
-    float4 rl = T.root[0], rh = T.root[1];
-    if (overlap6(qlo, qhi, rl.x, rl.y, rl.z, rh.x, rh.y, rh.z)) stack[sp++] = 0;
+    if (root >= 0) {
+      stack[sp++] = root;
+    } else if (root != -1 && is_vt) {
+      // a segment with one triangle: the leaf itself (one edge pairs with nothing)
+      uint64_t key = candidate(A, true, root & 0x7fffffff, qid, qv0, qv1, qx0, qx1);
+      if (key) skey[threadIdx.x * kBuf + cnt++] = key;
+    }
   }
-  int cnt = 0;
   while (__any(sp > 0)) {
     if (sp > 0) {
       const int32_t i = stack[--sp];
@@ -693,35 +792,8 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
           else atomicOr(&A.cnt->err, 2ull);
           continue;
         }
-        const int32_t prim = c & 0x7fffffff;
-        double d2;
-        uint64_t key;
-        bool ok;
-        if (is_vt) {
-          int32_t v1 = A.tris[3 * prim], v2 = A.tris[3 * prim + 1], v3 = A.tris[3 * prim + 2];
-          ok = qv0 != v1 && qv0 != v2 && qv0 != v3 &&
-               !(A.stat[qv0] && A.stat[v1] && A.stat[v2] && A.stat[v3]);
-          if (!ok) continue;
-          double bw[3];
-          d2 = pt_tri_d2(qx0, ld3(A.x, v1), ld3(A.x, v2), ld3(A.x, v3), bw);
-          key = ((uint64_t)(uint32_t)qid << 32) | (uint32_t)prim;
-        } else {
-          int32_t v1 = A.edges[2 * prim], v2 = A.edges[2 * prim + 1];
-          ok = qv0 != v1 && qv0 != v2 && qv1 != v1 && qv1 != v2 &&
-               !(A.stat[qv0] && A.stat[qv1] && A.stat[v1] && A.stat[v2]);
-          if (!ok) continue;
-          // the pair is reported once, under its canonical key (lower edge first);
-          // the distance is taken with that edge first as well
-          double s, t;
-          if (qid < prim) {
-            d2 = seg_seg_d2(qx0, qx1, ld3(A.x, v1), ld3(A.x, v2), s, t);
-            key = KEY_EE | ((uint64_t)(uint32_t)qid << 32) | (uint32_t)prim;
-          } else {
-            d2 = seg_seg_d2(ld3(A.x, v1), ld3(A.x, v2), qx0, qx1, s, t);
-            key = KEY_EE | ((uint64_t)(uint32_t)prim << 32) | (uint32_t)qid;
-          }
-        }
-        if (d2 < A.dmax2) skey[threadIdx.x * kBuf + cnt++] = key;
+        uint64_t key = candidate(A, is_vt, c & 0x7fffffff, qid, qv0, qv1, qx0, qx1);
+        if (key) skey[threadIdx.x * kBuf + cnt++] = key;
       }
     }
     if (__any(cnt > kBuf - 4)) wave_flush(skey, cnt, A);
@@ -737,21 +809,25 @@ static int dalloc(T** p, int64_t n) {
   if (hipMalloc((void**)p, (size_t)n * sizeof(T)) != hipSuccess) return CC_ENOMEM;
   return CC_OK;
 }
+template <class T>
+static void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
 
-static int bvh_alloc_one(Bvh& b, int32_t n) {
-  b.n = n;
-  int32_t ni = n > 1 ? n - 1 : 1;
-  int32_t nb = (n + kBlk - 1) / kBlk;
-  CC_TRY(dalloc(&b.leaf_lo, n));
-  CC_TRY(dalloc(&b.leaf_hi, n));
-  CC_TRY(dalloc(&b.leaf_prim, n));
-  CC_TRY(dalloc(&b.pos_of, n));
+static int bvh_alloc_one(Bvh& b, int32_t cap) {
+  b.n = 0;
+  int32_t ni = cap > 1 ? cap - 1 : 1;
+  int32_t nb = (cap + kBlk - 1) / kBlk;
+  CC_TRY(dalloc(&b.leaf_lo, cap));
+  CC_TRY(dalloc(&b.leaf_hi, cap));
+  CC_TRY(dalloc(&b.leaf_prim, cap));
   CC_TRY(dalloc(&b.node, 4 * (int64_t)ni));
   CC_TRY(dalloc(&b.wide, 8 * (int64_t)ni));
-  CC_TRY(dalloc(&b.parent, (int64_t)ni + n));
+  CC_TRY(dalloc(&b.parent, (int64_t)ni + cap));
   CC_TRY(dalloc(&b.range, ni));
-  CC_TRY(dalloc(&b.pre, 2 * (int64_t)n));
-  CC_TRY(dalloc(&b.suf, 2 * (int64_t)n));
+  CC_TRY(dalloc(&b.pre, 2 * (int64_t)cap));
+  CC_TRY(dalloc(&b.suf, 2 * (int64_t)cap));
   int nlev = 1;
   while ((1 << nlev) <= nb) ++nlev;  // sparse-table levels over the block boxes
   CC_TRY(dalloc(&b.blk, 2 * (int64_t)(nb > 0 ? nb : 1) * nlev));
@@ -760,40 +836,50 @@ static int bvh_alloc_one(Bvh& b, int32_t n) {
 }
 
 static void bvh_free_one(Bvh& b) {
-  hipFree(b.leaf_lo); hipFree(b.leaf_hi); hipFree(b.leaf_prim); hipFree(b.pos_of);
-  hipFree(b.node); hipFree(b.wide); hipFree(b.parent); hipFree(b.range); hipFree(b.pre); hipFree(b.suf);
-  hipFree(b.blk); hipFree(b.root);
+  dfree(b.leaf_lo); dfree(b.leaf_hi); dfree(b.leaf_prim);
+  dfree(b.node); dfree(b.wide); dfree(b.parent); dfree(b.range); dfree(b.pre); dfree(b.suf);
+  dfree(b.blk); dfree(b.root);
   b = Bvh{};
 }
 
 int bvh_alloc(cc_solver* s) {
-  int64_t m = (int64_t)s->nt + s->ne;
-  int64_t mall = m + s->n;  // triangles, edges and vertices share one sort
-  CC_TRY(bvh_alloc_one(s->tree_t, s->nt));
-  CC_TRY(bvh_alloc_one(s->tree_e, s->ne));
+  const int64_t m = (int64_t)s->capF + s->capE;
+  const int64_t mall = m + s->capV;  // triangles, edges and vertices share one sort
+  CC_TRY(bvh_alloc_one(s->tree_t, s->capF));
+  CC_TRY(bvh_alloc_one(s->tree_e, s->capE));
   CC_TRY(dalloc(&s->sk0, mall));
   CC_TRY(dalloc(&s->sk1, mall));
   CC_TRY(dalloc(&s->sv0, mall));
   CC_TRY(dalloc(&s->sv1, mall));
   CC_TRY(dalloc(&s->ubox_lo, m));
   CC_TRY(dalloc(&s->ubox_hi, m));
-  CC_TRY(dalloc(&s->vorder, s->n));
+  CC_TRY(dalloc(&s->gprim, m));
+  CC_TRY(dalloc(&s->vorder, s->capV));
+  CC_TRY(dalloc(&s->vrank, s->capV));
+  CC_TRY(dalloc(&s->erank, s->capE));
   int64_t nb = (mall + kTile - 1) / kTile;
   s->rs_hist_cap = 256 * (nb > 0 ? nb : 1);
   CC_TRY(dalloc(&s->rs_hist, s->rs_hist_cap));
   CC_TRY(dalloc(&s->rs_total, 256));
   CC_TRY(dalloc(&s->bounds, 6));
   CC_TRY(dalloc(&s->bounds_part, 6 * ((m + 255) / 256)));
+  CC_TRY(dalloc(&s->sel_dev, kMaxSeg + 1));
+  if (!s->sel_host &&
+      hipHostMalloc((void**)&s->sel_host, sizeof(SelDev) * (kMaxSeg + 1), hipHostMallocDefault) !=
+          hipSuccess)
+    return CC_ENOMEM;
+  CC_TRY(dalloc(&s->root_t, kMaxSeg));
+  CC_TRY(dalloc(&s->root_e, kMaxSeg));
   return CC_OK;
 }
 
 void bvh_free(cc_solver* s) {
   bvh_free_one(s->tree_t);
   bvh_free_one(s->tree_e);
-  hipFree(s->sk0); hipFree(s->sk1); hipFree(s->sv0); hipFree(s->sv1);
-  hipFree(s->ubox_lo); hipFree(s->ubox_hi); hipFree(s->rs_hist); hipFree(s->bounds);
-  hipFree(s->bounds_part); hipFree(s->vorder); hipFree(s->rs_total);
-  s->sk0 = s->sk1 = s->sv0 = s->sv1 = nullptr;
+  dfree(s->sk0); dfree(s->sk1); dfree(s->sv0); dfree(s->sv1);
+  dfree(s->ubox_lo); dfree(s->ubox_hi); dfree(s->gprim); dfree(s->rs_hist); dfree(s->bounds);
+  dfree(s->bounds_part); dfree(s->vorder); dfree(s->vrank); dfree(s->erank); dfree(s->rs_total);
+  dfree(s->sel_dev); dfree(s->root_t); dfree(s->root_e);
 }
 
 static inline unsigned blocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -803,76 +889,100 @@ static RefitView refit_view(Bvh& b) {
                    b.pre, b.suf, b.blk};
 }
 
-int lbvh_search(cc_solver* s, const double* x, double dmax, uint64_t* out, int64_t cap,
-                int64_t* nfound, hipStream_t st) {
-  const int32_t nt = s->nt, ne = s->ne;
-  const int64_t m = (int64_t)nt + ne;
+int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64_t* out,
+                int64_t cap, int64_t* nfound, hipStream_t st) {
+  // compact offsets of the selected segments' vertices, triangles and edges
+  int32_t mv = 0, mt = 0, me = 0;
+  for (int32_t r = 0; r < nsel; ++r) {
+    SelDev& d = s->sel_host[r];
+    const Seg& g = s->segs[d.seg];
+    d.vb = g.vb;
+    d.fb = g.fb;
+    d.eb = g.eb;
+    d.voff = mv;
+    d.toff = mt;
+    d.eoff = me;
+    mv += g.nv;
+    mt += g.nf;
+    me += g.ne;
+  }
+  s->sel_host[nsel] = SelDev{0, 0, 0, -1, mv, mt, me, 0};
+  int rb = 0;
+  while ((1 << rb) < nsel) ++rb;
   const double infl = 0.5 * dmax;
   CC_HIP(hipMemsetAsync(&s->dc->n_out, 0, sizeof(unsigned long long), st));
   CC_HIP(hipMemsetAsync(&s->dc->err, 0, sizeof(unsigned long long), st));
+  *nfound = 0;
+  const int64_t m = (int64_t)mt + me;
   if (m > 0) {
-    const int64_t mall = m + s->n;
+    CC_HIP(hipMemcpyAsync(s->sel_dev, s->sel_host, sizeof(SelDev) * (nsel + 1),
+                          hipMemcpyHostToDevice, st));
+    const int64_t mall = m + mv;
     const unsigned nbx = blocks(m, 256);
-    k_boxes<<<nbx, 256, 0, st>>>(x, s->tris, s->edges, nt, ne, infl, s->ubox_lo, s->ubox_hi,
-                                 s->bounds_part);
+    k_boxes<<<nbx, 256, 0, st>>>(x, s->tris, s->edges, s->sel_dev, nsel, mt, me, infl,
+                                 s->ubox_lo, s->ubox_hi, s->gprim, s->bounds_part);
     k_bounds_reduce<<<1, 256, 0, st>>>(s->bounds_part, (int32_t)nbx, s->bounds);
-    k_morton<<<blocks(mall, 256), 256, 0, st>>>(s->ubox_lo, s->ubox_hi, x, nt, ne, s->n,
-                                                s->bounds, s->sk0, s->sv0);
+    k_morton<<<blocks(mall, 256), 256, 0, st>>>(s->ubox_lo, s->ubox_hi, x, s->sel_dev, nsel, mt,
+                                                me, mv, rb, s->bounds, s->sk0, s->sv0);
     const int32_t nb = (int32_t)((mall + kTile - 1) / kTile);
-    uint32_t *ki = s->sk0, *vi = s->sv0, *ko = s->sk1, *vo = s->sv1;
-    for (int shift = 0; shift < 32; shift += 8) {
+    uint64_t *ki = s->sk0, *ko = s->sk1;
+    uint32_t *vi = s->sv0, *vo = s->sv1;
+    for (int shift = 0; shift < 32 + rb; shift += 8) {
       k_rs_hist<<<nb, kRsThreads, 0, st>>>(ki, (int32_t)mall, shift, s->rs_hist, nb);
       k_rs_scan_digit<<<256, kRsThreads, 0, st>>>(s->rs_hist, nb, s->rs_total);
       k_rs_scatter<<<nb, kRsThreads, 0, st>>>(ki, vi, ko, vo, (int32_t)mall, shift, s->rs_hist,
                                               nb, s->rs_total);
-      uint32_t* t;
-      t = ki; ki = ko; ko = t;
-      t = vi; vi = vo; vo = t;
+      std::swap(ki, ko);
+      std::swap(vi, vo);
     }
     Bvh& bt = s->tree_t;
     Bvh& be = s->tree_e;
-    k_leaves<<<blocks(mall, 256), 256, 0, st>>>(vi, s->ubox_lo, s->ubox_hi, nt, ne, bt.leaf_lo,
-                                                bt.leaf_hi, bt.leaf_prim, bt.pos_of, be.leaf_lo,
-                                                be.leaf_hi, be.leaf_prim, be.pos_of, s->n,
-                                                s->vorder);
-    const uint32_t* sorted = ki;
-    TreeView ta{nt, sorted, bt.leaf_prim, bt.node, bt.parent, bt.range};
-    TreeView tb{ne, sorted + nt, be.leaf_prim, be.node, be.parent, be.range};
-    int64_t ninternal = (nt > 1 ? nt - 1 : 0) + (ne > 1 ? ne - 1 : 0);
+    bt.n = mt;
+    be.n = me;
+    k_leaves<<<blocks(mall, 256), 256, 0, st>>>(vi, ki, s->ubox_lo, s->ubox_hi, s->gprim,
+                                                s->sel_dev, mt, me, mv, (1u << rb) - 1u,
+                                                bt.leaf_lo, bt.leaf_hi, bt.leaf_prim, be.leaf_lo,
+                                                be.leaf_hi, be.leaf_prim, s->erank, s->vorder,
+                                                s->vrank);
+    const uint64_t mask = (1ull << (30 + rb)) - 1ull;
+    TreeView ta{mt, ki, mask, bt.leaf_prim, bt.node, bt.parent, bt.range};
+    TreeView tb{me, ki + mt, mask, be.leaf_prim, be.node, be.parent, be.range};
+    int64_t ninternal = (mt > 1 ? mt - 1 : 0) + (me > 1 ? me - 1 : 0);
     if (ninternal > 0) k_karras<<<blocks(ninternal, 256), 256, 0, st>>>(ta, tb);
-    if (nt == 1) k_single<<<1, 1, 0, st>>>(bt.node, bt.root, bt.leaf_lo, bt.leaf_hi, bt.leaf_prim);
-    if (ne == 1) k_single<<<1, 1, 0, st>>>(be.node, be.root, be.leaf_lo, be.leaf_hi, be.leaf_prim);
-    RefitView ra = refit_view(bt), rb = refit_view(be);
-    if (nt < 2) ra.n = 0;
-    if (ne < 2) rb.n = 0;
-    const int32_t nba = (ra.n + kBlk - 1) / kBlk, nbb = (rb.n + kBlk - 1) / kBlk;
+    k_seg_roots<<<blocks(nsel, 256), 256, 0, st>>>(s->sel_dev, nsel, mt, me, bt.range,
+                                                   bt.leaf_prim, be.range, be.leaf_prim,
+                                                   s->root_t, s->root_e);
+    RefitView ra = refit_view(bt), rbv = refit_view(be);
+    if (mt < 2) ra.n = 0;
+    if (me < 2) rbv.n = 0;
+    const int32_t nba = (ra.n + kBlk - 1) / kBlk, nbb = (rbv.n + kBlk - 1) / kBlk;
     if (nba + nbb > 0) {
-      k_refit_block<<<nba + nbb, kBlk, 0, st>>>(ra, rb, nba);
-      k_blk_sparse<<<2, 1024, 0, st>>>(ra, rb);
-      k_refit_top<<<blocks(ninternal, 256), 256, 0, st>>>(ra, rb);
+      k_refit_block<<<nba + nbb, kBlk, 0, st>>>(ra, rbv, nba);
+      k_blk_sparse<<<2, 1024, 0, st>>>(ra, rbv);
+      k_refit_top<<<blocks(ninternal, 256), 256, 0, st>>>(ra, rbv);
     }
+    if (mt > 1) k_wide<<<blocks(mt - 1, 256), 256, 0, st>>>(bt.node, bt.wide, mt - 1);
+    if (me > 1) k_wide<<<blocks(me - 1, 256), 256, 0, st>>>(be.node, be.wide, me - 1);
     TravArgs A;
-    {
-      // 4-wide records (a tree of one leaf has the single record of k_single)
-      const int32_t wt = nt > 1 ? nt - 1 : nt, we = ne > 1 ? ne - 1 : ne;
-      if (wt > 0) k_wide<<<blocks(wt, 256), 256, 0, st>>>(bt.node, bt.wide, wt);
-      if (we > 0) k_wide<<<blocks(we, 256), 256, 0, st>>>(be.node, be.wide, we);
-    }
-    A.tt = TravTree{nt, bt.wide, bt.root, bt.leaf_prim};
-    A.te = TravTree{ne, be.wide, be.root, be.leaf_prim};
+    A.tt = TravTree{mt, bt.wide, bt.root, bt.leaf_prim};
+    A.te = TravTree{me, be.wide, be.root, be.leaf_prim};
     A.x = x;
     A.tris = s->tris;
     A.edges = s->edges;
     A.stat = s->stat;
     A.vorder = s->vorder;
-    A.n = s->n;
-    A.ne = ne;
+    A.vrank = s->vrank;
+    A.erank = s->erank;
+    A.root_t = s->root_t;
+    A.root_e = s->root_e;
+    A.mv = mt > 0 ? mv : 0;  // no triangles: no vertex-triangle queries
+    A.me = me;
     A.infl = infl;
     A.dmax2 = dmax * dmax;
     A.out = out;
     A.cap = cap;
     A.cnt = s->dc;
-    int64_t nq = (int64_t)s->n + ne;
+    int64_t nq = (int64_t)A.mv + me;
     if (nq > 0) {
       timer_begin(s, CC_K_SEARCH, st);
       k_traverse<<<blocks(nq, kTravThreads), kTravThreads, 0, st>>>(A);
@@ -885,7 +995,7 @@ int lbvh_search(cc_solver* s, const double* x, double dmax, uint64_t* out, int64
   if (s->hc->err & 2ull) return CC_EOVERFLOW;
   *nfound = (int64_t)s->hc->n_out;
   // algorithmic bytes of the traversal: queries, node records, output keys
-  s->st.kernel_bytes[CC_K_SEARCH] += 24.0 * s->n + 8.0 * ne + 64.0 * (double)m +
+  s->st.kernel_bytes[CC_K_SEARCH] += 24.0 * mv + 8.0 * me + 64.0 * (double)m +
                                      8.0 * (double)*nfound;
   return CC_OK;
 }

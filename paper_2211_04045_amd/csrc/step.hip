@@ -45,74 +45,147 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
   return v;
 }
 
+// ------------------------------------------------------------- segments
+
+// Scene-local key of a row, so that colouring priorities do not depend on where
+// a scene sits in the solver's arrays: vertex-triangle (v << 32 | f) and
+// edge-edge (e << 32 | g) pair keys and edge-row keys (e) lose their segment's
+// bases. A scene alone at base 0 keeps its keys.
+__device__ __forceinline__ uint64_t local_pair_key(uint64_t key, const SegDev& sg) {
+  const uint32_t hi = (uint32_t)(key >> 32) & 0x7fffffffu, lo = (uint32_t)key;
+  if (key_is_ee(key))
+    return KEY_EE | ((uint64_t)(hi - (uint32_t)sg.eb) << 32) | (uint32_t)(lo - (uint32_t)sg.eb);
+  return ((uint64_t)(hi - (uint32_t)sg.vb) << 32) | (uint32_t)(lo - (uint32_t)sg.fb);
+}
+
+// Small LDS table of per-segment counters for one block: slot keys are segment
+// ids (-1 = empty), linear probing; a segment that finds no slot adds straight
+// to the global record.
+constexpr int kSegSlots = 32;
+
+__device__ __forceinline__ int seg_slot(int32_t* skey, int32_t sg) {
+  uint32_t h = ((uint32_t)sg * 2654435761u) >> 27;  // 5 bits
+  for (int t = 0; t < kSegSlots; ++t) {
+    int32_t prev = atomicCAS(&skey[h], -1, sg);
+    if (prev == -1 || prev == sg) return (int)h;
+    h = (h + 1) & (kSegSlots - 1);
+  }
+  return -1;
+}
+
 // ------------------------------------------------------------- validation
 
-__global__ void k_validate(const int32_t* __restrict__ tris, int32_t nt,
-                           const int32_t* __restrict__ edges, int32_t ne, int32_t n,
-                           const double* __restrict__ xa, const double* __restrict__ xb,
-                           Counters* c) {
+// Topology of segment `sg` in: local vertex ids are checked against the scene's
+// vertex count and stored solver-wide (+ vb); edges record their segment.
+__global__ void k_topo_in(const int32_t* __restrict__ tin, const int32_t* __restrict__ ein,
+                          int32_t nf, int32_t ne, int32_t nv, int32_t vb, int32_t sg,
+                          int32_t* __restrict__ tris, int32_t* __restrict__ edges,
+                          int32_t* __restrict__ eseg, Counters* c) {
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long err = 0;
-  if (g < nt) {
-    int32_t i = tris[3 * g], j = tris[3 * g + 1], k = tris[3 * g + 2];
-    if (i < 0 || j < 0 || k < 0 || i >= n || j >= n || k >= n || i == j || j == k || i == k)
+  if (g < nf) {
+    int32_t i = tin[3 * g], j = tin[3 * g + 1], k = tin[3 * g + 2];
+    if (i < 0 || j < 0 || k < 0 || i >= nv || j >= nv || k >= nv || i == j || j == k || i == k)
       err |= 4ull;
-  } else if (g < (int64_t)nt + ne) {
-    int64_t e = g - nt;
-    int32_t i = edges[2 * e], j = edges[2 * e + 1];
-    if (i < 0 || j < 0 || i >= n || j >= n || i == j) err |= 4ull;
-  } else if (g < (int64_t)nt + ne + n) {
-    int64_t v = g - nt - ne;
-    if (xa)
-      for (int k = 0; k < 3; ++k)
-        if (!isfinite(xa[3 * v + k])) err |= 8ull;
-    if (xb)
-      for (int k = 0; k < 3; ++k)
-        if (!isfinite(xb[3 * v + k])) err |= 8ull;
+    tris[3 * g] = i + vb;
+    tris[3 * g + 1] = j + vb;
+    tris[3 * g + 2] = k + vb;
+  } else if (g < (int64_t)nf + ne) {
+    int64_t e = g - nf;
+    int32_t i = ein[2 * e], j = ein[2 * e + 1];
+    if (i < 0 || j < 0 || i >= nv || j >= nv || i == j) err |= 4ull;
+    edges[2 * e] = i + vb;
+    edges[2 * e + 1] = j + vb;
+    eseg[e] = sg;
   }
   if (err) atomicOr(&c->err, err);
 }
 
-int launch_validate(cc_solver* s, const double* xa, const double* xb, hipStream_t st) {
-  int64_t m = (int64_t)s->nt + s->ne + s->n;
-  CC_HIP(hipMemsetAsync(&s->dc->err, 0, sizeof(unsigned long long), st));
-  if (m > 0)
-    k_validate<<<nblk(m), kThreads, 0, st>>>(s->tris, s->nt, s->edges, s->ne, s->n, xa, xb, s->dc);
+__global__ void k_check_finite(const double* __restrict__ xa, const double* __restrict__ xb,
+                               int32_t n, Counters* c) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  unsigned long long err = 0;
+  for (int k = 0; k < 3; ++k) {
+    if (xa && !isfinite(xa[3 * v + k])) err |= 8ull;
+    if (xb && !isfinite(xb[3 * v + k])) err |= 8ull;
+  }
+  if (err) atomicOr(&c->err, err);
+}
+
+static int read_err(cc_solver* s, hipStream_t st) {
   CC_HIP(hipGetLastError());
   CC_HIP(hipMemcpyAsync(&s->hc->err, &s->dc->err, sizeof(unsigned long long),
                         hipMemcpyDeviceToHost, st));
   CC_HIP(hipStreamSynchronize(st));
-  if (s->hc->err & 12ull) return CC_EINVAL;
+  return (s->hc->err & 12ull) ? CC_EINVAL : CC_OK;
+}
+
+int launch_topo_in(cc_solver* s, int32_t sg, const int32_t* tris, const int32_t* edges,
+                   hipStream_t st) {
+  const Seg& g = s->segs[sg];
+  const int64_t m = (int64_t)g.nf + g.ne;
+  CC_HIP(hipMemsetAsync(&s->dc->err, 0, sizeof(unsigned long long), st));
+  if (m > 0)
+    k_topo_in<<<nblk(m), kThreads, 0, st>>>(tris, edges, g.nf, g.ne, g.nv, g.vb, sg,
+                                             s->tris + 3 * (int64_t)g.fb,
+                                             s->edges + 2 * (int64_t)g.eb, s->eseg + g.eb, s->dc);
+  return read_err(s, st);
+}
+
+int launch_check_finite(cc_solver* s, const double* xa, const double* xb, int32_t n,
+                        hipStream_t st) {
+  CC_HIP(hipMemsetAsync(&s->dc->err, 0, sizeof(unsigned long long), st));
+  if (n > 0) k_check_finite<<<nblk(n), kThreads, 0, st>>>(xa, xb, n, s->dc);
+  return read_err(s, st);
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+int launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
+  if (n > 0) k_fill_i32<<<nblk(n), kThreads, 0, st>>>(p, n, v);
+  CC_HIP(hipGetLastError());
   return CC_OK;
 }
 
 // ------------------------------------------------------------- setup (Alg. 1 init)
 
-__global__ void k_setup(const double* __restrict__ xp, const double* __restrict__ xt_in,
-                        const double* __restrict__ w, int32_t n, double* __restrict__ x,
+// One segment's vertices (pointers already offset to the segment): x <- x^[k],
+// y <- y^[k+1], r <- 1, static flag. x_prev may be the segment's own x.
+__global__ void k_setup(const double* xp, const double* __restrict__ xt_in,
+                        const double* __restrict__ w, int32_t n, double* x,
                         double* __restrict__ y, double* __restrict__ xt, double* __restrict__ r,
-                        uint8_t* __restrict__ stat) {
+                        uint8_t* __restrict__ stat, float* __restrict__ dy) {
   int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   V3 a = ld3(xp, i), b = ld3(xt_in, i);
   st3(x, i, a);
   st3(y, i, b);
   st3(xt, i, b);
+  dy[3 * (int64_t)i] = (float)(b.x - a.x);
+  dy[3 * (int64_t)i + 1] = (float)(b.y - a.y);
+  dy[3 * (int64_t)i + 2] = (float)(b.z - a.z);
   r[i] = 1.0;
   stat[i] = (w[i] == 0.0 && a.x == b.x && a.y == b.y && a.z == b.z) ? 1 : 0;
 }
 
-// Edge-length rows (Sec. 4.2): c = sigma - |x_i - x_j| / |y^_i - y^_j| linearised at
-// y^ = y^[k+1]: c_lin(y) = sigma - g.(y_i - y_j), g = (y^_i - y^_j)/L^2,
-// A = (w_i + w_j)|g|^2. Edges without a free end or with L = 0 carry no row.
-__global__ void k_edge_rows(const int32_t* __restrict__ edges, int32_t ne,
+// Edge-length rows (Sec. 4.2) of one segment's edges: c = sigma - |x_i - x_j| /
+// |y^_i - y^_j| linearised at y^ = y^[k+1]: c_lin(y) = sigma - g.(y_i - y_j),
+// g = (y^_i - y^_j)/L^2, A = (w_i + w_j)|g|^2. Edges without a free end or with
+// L = 0 carry no row. Valid rows are appended to `list` (to be coloured).
+__global__ void k_edge_rows(const int32_t* __restrict__ edges, int32_t eb, int32_t ne,
                             const double* __restrict__ w, const double* __restrict__ xt,
                             double* __restrict__ eg, double* __restrict__ einv,
-                            int32_t* __restrict__ list, Counters* c) {
+                            int32_t* __restrict__ list, Counters* c,
+                            unsigned long long* seg_rows) {
   int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   bool valid = false;
   if (e < ne) {
-    int32_t i = edges[2 * e], j = edges[2 * e + 1];
+    const int32_t ge = eb + e;
+    int32_t i = edges[2 * ge], j = edges[2 * ge + 1];
     double inv = 0.0;
     if (w[i] > 0.0 || w[j] > 0.0) {
       V3 d = vsub(ld3(xt, i), ld3(xt, j));
@@ -121,29 +194,38 @@ __global__ void k_edge_rows(const int32_t* __restrict__ edges, int32_t ne,
         V3 g = V3{d.x / l2, d.y / l2, d.z / l2};
         double A = (w[i] + w[j]) * vdot(g, g);
         inv = 1.0 / A;
-        st3(eg, e, g);
+        st3(eg, ge, g);
         valid = true;
       }
     }
-    einv[e] = inv;
+    einv[ge] = inv;
   }
   unsigned long long pos = wave_append(valid, &c->n_rows);
-  if (valid) list[pos] = e;
+  if (valid) list[pos] = eb + e;
+  uint64_t m = __ballot(valid);
+  if (m && __lane_id() == __ffsll((long long)m) - 1)
+    atomicAdd(seg_rows, (unsigned long long)__popcll(m));
 }
 
-int launch_setup(cc_solver* s, const double* x_prev, const double* x_tilde, hipStream_t st) {
-  if (s->n > 0)
-    k_setup<<<nblk(s->n), kThreads, 0, st>>>(x_prev, x_tilde, s->w, s->n, s->x, s->y, s->xt,
-                                              s->r, s->stat);
-  CC_HIP(hipMemsetAsync(&s->dc->n_rows, 0, sizeof(unsigned long long), st));
-  if (s->ne > 0 && (s->p.flags & CC_EDGE_LEN))
-    k_edge_rows<<<nblk(s->ne), kThreads, 0, st>>>(s->edges, s->ne, s->w, s->xt, s->eg, s->einv,
-                                                   s->elist0, s->dc);
+// Begin of one segment: state arrays and its edge-length rows (appended to
+// elist0 at the counter dc->n_rows, which the caller zeroes once per batch of
+// begins; the segment's own row count goes to its record).
+int launch_setup(cc_solver* s, int32_t sg, const double* x_prev, const double* x_tilde,
+                 hipStream_t st) {
+  const Seg& g = s->segs[sg];
+  const int64_t vb = g.vb;
+  if (g.nv > 0)
+    k_setup<<<nblk(g.nv), kThreads, 0, st>>>(x_prev, x_tilde, s->w + vb, g.nv, s->x + 3 * vb,
+                                              s->y + 3 * vb, s->xt + 3 * vb, s->r + vb,
+                                              s->stat + vb, s->dy + 3 * vb);
+  CC_HIP(hipMemsetAsync(&s->seg_dev[sg].n_rows, 0, sizeof(unsigned long long), st));
+  if (g.ne > 0 && (s->p.flags & CC_EDGE_LEN))
+    k_edge_rows<<<nblk(g.ne), kThreads, 0, st>>>(s->edges, g.eb, g.ne, s->w, s->xt, s->eg,
+                                                  s->einv, s->elist0, s->dc,
+                                                  &s->seg_dev[sg].n_rows);
+  else if (g.ne > 0)
+    CC_HIP(hipMemsetAsync(s->einv + g.eb, 0, sizeof(double) * g.ne, st));
   CC_HIP(hipGetLastError());
-  CC_HIP(hipMemcpyAsync(&s->hc->n_rows, &s->dc->n_rows, sizeof(unsigned long long),
-                        hipMemcpyDeviceToHost, st));
-  CC_HIP(hipStreamSynchronize(st));
-  s->n_erows = (int32_t)s->hc->n_rows;
   return CC_OK;
 }
 
@@ -158,14 +240,34 @@ int launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipS
   return CC_OK;
 }
 
+// D_i <- D^(l) of the vertex's segment (Sec. 5: a vertex in no pair moves at
+// most 0.45 D^(l)); vertices of segments that do not iterate are left alone.
+__global__ void k_di_init(const int32_t* __restrict__ vseg, const SegDev* __restrict__ seg,
+                          int32_t n, unsigned long long* __restrict__ Di) {
+  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int32_t sg = vseg[v];
+  if (sg < 0 || !(seg[sg].flags & kSegActive)) return;
+  Di[v] = (unsigned long long)__double_as_longlong(seg[sg].D);
+}
+
+int launch_di_init(cc_solver* s, hipStream_t st) {
+  if (s->n > 0) k_di_init<<<nblk(s->n), kThreads, 0, st>>>(s->vseg, s->seg_dev, s->n, s->Di);
+  CC_HIP(hipGetLastError());
+  return CC_OK;
+}
+
 // ------------------------------------------------------------- pair pass
 
 struct PairPassArgs {
   const uint64_t* P;
   int64_t nP;
+  int64_t n_old;  // [0, n_old): last P'; [n_old, nP): appended by this iteration's search
   const double* x;
   Topo T;
-  double D2, dl2;
+  const int32_t* vseg;
+  SegDev* seg;
+  double dl2;
   uint64_t* Pout;
   double* dPout;
   uint64_t* Akeys;
@@ -205,6 +307,25 @@ __device__ __forceinline__ int block_excl_scan(int v, int* sm, int* total) {
   return res;
 }
 
+// Add a thread's per-segment counts to the block's LDS table (or straight to
+// the segment's record when the table has no slot for it).
+__device__ __forceinline__ void seg_count_flush(int32_t* gkey, unsigned long long (*gcnt)[3],
+                                                SegDev* seg, int32_t sg,
+                                                unsigned long long* cnt) {
+  if (sg < 0 || cnt[0] == 0) return;
+  const int slot = seg_slot(gkey, sg);
+  if (slot >= 0) {
+    atomicAdd(&gcnt[slot][0], cnt[0]);
+    if (cnt[1]) atomicAdd(&gcnt[slot][1], cnt[1]);
+    if (cnt[2]) atomicAdd(&gcnt[slot][2], cnt[2]);
+  } else {
+    atomicAdd(&seg[sg].n_p, cnt[0]);
+    if (cnt[1]) atomicAdd(&seg[sg].n_pf, cnt[1]);
+    if (cnt[2]) atomicAdd(&seg[sg].n_a, cnt[2]);
+  }
+  cnt[0] = cnt[1] = cnt[2] = 0;
+}
+
 // Push the block's per-vertex minima to the global D_i and clear the table.
 __device__ __forceinline__ void flush_min_table(int32_t* hkey, unsigned long long* hval,
                                                 unsigned long long* Di) {
@@ -223,19 +344,28 @@ __device__ __forceinline__ void flush_min_table(int32_t* hkey, unsigned long lon
 
 // Distances at x^(l) for every p in P; P' = {d^2 < D^2} (Sec. 3.1 filter),
 // A = {d^2 < delta^2} (Sec. 4.1 activation), D_i = min over P' of d (Sec. 5).
+// D is the pair's segment's; pairs of segments that do not iterate, and pairs of
+// last iteration's P' whose segment was searched again, are dropped unevaluated.
 // Each block handles kThreads*kPairsPerThread consecutive pairs. The minimum is
 // first taken in an LDS hash table keyed by vertex (flushed after every 256 pairs,
 // so it is never more than half full), then one global atomic per distinct vertex
 // (min is exact and order independent on the bit patterns of non-negative
-// doubles). P' and A are compacted with one counter atomic per block.
+// doubles). P' and A are compacted with one counter atomic per block; the
+// per-segment counts go through a small LDS table.
 __global__ void __launch_bounds__(kThreads) k_pair_pass(PairPassArgs a) {
   __shared__ int32_t hkey[kHash];
   __shared__ unsigned long long hval[kHash];
   __shared__ int ssc[kThreads / 64 + 1];
   __shared__ unsigned long long sbase[2];
+  __shared__ int32_t gkey[kSegSlots];
+  __shared__ unsigned long long gcnt[kSegSlots][3];
   for (int t = threadIdx.x; t < kHash; t += kThreads) {
     hkey[t] = -1;
     hval[t] = ~0ull;
+  }
+  if (threadIdx.x < kSegSlots) {
+    gkey[threadIdx.x] = -1;
+    gcnt[threadIdx.x][0] = gcnt[threadIdx.x][1] = gcnt[threadIdx.x][2] = 0ull;
   }
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * (kThreads * kPairsPerThread);
@@ -244,6 +374,8 @@ __global__ void __launch_bounds__(kThreads) k_pair_pass(PairPassArgs a) {
   int4 vs[kPairsPerThread];
   unsigned keepm = 0, actm = 0;
   unsigned long long f1 = 0, f2 = 0;
+  int32_t csg = -1;                        // segment of the counts held in registers
+  unsigned long long cnt[3] = {0, 0, 0};  // evaluated, in P', in A
 #pragma unroll
   for (int k = 0; k < kPairsPerThread; ++k) {
     const int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
@@ -254,35 +386,50 @@ __global__ void __launch_bounds__(kThreads) k_pair_pass(PairPassArgs a) {
       uint64_t key = a.P[i];
       int32_t v[4];
       pair_verts(a.T, key, v);
-      double d2 = pair_d2(key_is_ee(key), ld3(a.x, v[0]), ld3(a.x, v[1]), ld3(a.x, v[2]),
-                          ld3(a.x, v[3]));
-      keys[k] = key;
-      d2s[k] = d2;
-      vs[k] = make_int4(v[0], v[1], v[2], v[3]);
-      if (d2 < a.D2) {
-        keepm |= 1u << k;
-        if (a.trace) f1 += fp_key(key);
-        if (d2 < a.dl2) {
-          actm |= 1u << k;
-          if (a.trace) f2 += fp_key(key);
+      const int32_t sg = a.vseg[v[0]];  // -1: a removed scene's pair
+      const int32_t fl = sg >= 0 ? a.seg[sg].flags : 0;
+      const bool live = (fl & kSegActive) && !(i < a.n_old && (fl & kSegSearched));
+      if (live) {
+        double d2 = pair_d2(key_is_ee(key), ld3(a.x, v[0]), ld3(a.x, v[1]), ld3(a.x, v[2]),
+                            ld3(a.x, v[3]));
+        keys[k] = key;
+        d2s[k] = d2;
+        vs[k] = make_int4(v[0], v[1], v[2], v[3]);
+        const bool keep = d2 < a.seg[sg].D2, act = keep && d2 < a.dl2;
+        if (sg != csg) {
+          seg_count_flush(gkey, gcnt, a.seg, csg, cnt);
+          csg = sg;
         }
-        unsigned long long bits = (unsigned long long)__double_as_longlong(sqrt(d2));
+        cnt[0] += 1;
+        cnt[1] += keep ? 1 : 0;
+        cnt[2] += act ? 1 : 0;
+        if (keep) {
+          keepm |= 1u << k;
+          if (a.trace) f1 += fp_key(key);
+          if (act) {
+            actm |= 1u << k;
+            if (a.trace) f2 += fp_key(key);
+          }
+          unsigned long long bits = (unsigned long long)__double_as_longlong(sqrt(d2));
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          uint32_t h = ((uint32_t)v[q] * 2654435761u) >> 21;  // 11 bits
-          for (;;) {
-            int32_t prev = atomicCAS(&hkey[h], -1, v[q]);
-            if (prev == -1 || prev == v[q]) {
-              atomicMin(&hval[h], bits);
-              break;
+          for (int q = 0; q < 4; ++q) {
+            uint32_t h = ((uint32_t)v[q] * 2654435761u) >> 21;  // 11 bits
+            for (;;) {
+              int32_t prev = atomicCAS(&hkey[h], -1, v[q]);
+              if (prev == -1 || prev == v[q]) {
+                atomicMin(&hval[h], bits);
+                break;
+              }
+              h = (h + 1) & (kHash - 1);
             }
-            h = (h + 1) & (kHash - 1);
           }
         }
       }
     }
     flush_min_table(hkey, hval, a.Di);
   }
+  seg_count_flush(gkey, gcnt, a.seg, csg, cnt);
+  __syncthreads();
   // block-level compaction of P' and A
   int nk = __popc(keepm), na = __popc(actm), tk = 0, ta = 0;
   int ok = block_excl_scan(nk, ssc, &tk);
@@ -290,6 +437,12 @@ __global__ void __launch_bounds__(kThreads) k_pair_pass(PairPassArgs a) {
   if (threadIdx.x == 0) {
     sbase[0] = tk ? atomicAdd(&a.c->n_out, (unsigned long long)tk) : 0ull;
     sbase[1] = ta ? atomicAdd(&a.c->n_act, (unsigned long long)ta) : 0ull;
+  }
+  if (threadIdx.x < kSegSlots && gkey[threadIdx.x] >= 0) {
+    SegDev& sd = a.seg[gkey[threadIdx.x]];
+    atomicAdd(&sd.n_p, gcnt[threadIdx.x][0]);
+    if (gcnt[threadIdx.x][1]) atomicAdd(&sd.n_pf, gcnt[threadIdx.x][1]);
+    if (gcnt[threadIdx.x][2]) atomicAdd(&sd.n_a, gcnt[threadIdx.x][2]);
   }
   __syncthreads();
   unsigned long long pk = sbase[0] + (unsigned long long)ok;
@@ -319,13 +472,15 @@ __global__ void __launch_bounds__(kThreads) k_pair_pass(PairPassArgs a) {
   }
 }
 
-int launch_pair_pass(cc_solver* s, double D2, double dl2, bool trace, hipStream_t st) {
+int launch_pair_pass(cc_solver* s, int64_t n_old, double dl2, bool trace, hipStream_t st) {
   PairPassArgs a;
   a.P = s->P;
   a.nP = s->nP;
+  a.n_old = n_old;
   a.x = s->x;
   a.T = Topo{s->tris, s->edges};
-  a.D2 = D2;
+  a.vseg = s->vseg;
+  a.seg = s->seg_dev;
   a.dl2 = dl2;
   a.Pout = s->P2;
   a.dPout = s->dP2;
@@ -343,26 +498,29 @@ int launch_pair_pass(cc_solver* s, double D2, double dl2, bool trace, hipStream_
 // ------------------------------------------------------------- colouring
 
 // A row source: contact rows (key = pair key, 4 vertices) or edge-length rows
-// (key = edge index, 2 vertices).
+// (key = edge index, 2 vertices). The key returned is the scene-local one.
 struct RowSrc {
   const uint64_t* keys;
   const int4* verts;
   const int32_t* edges;
+  const int32_t* vseg;
+  const int32_t* eseg;
+  const SegDev* seg;
   int is_edge;
   __device__ __forceinline__ void get(int32_t r, uint64_t& key, int32_t v[4]) const {
     if (is_edge) {
-      key = (uint64_t)(uint32_t)r;
+      key = (uint64_t)(uint32_t)(r - seg[eseg[r]].eb);
       v[0] = edges[2 * r];
       v[1] = edges[2 * r + 1];
       v[2] = -1;
       v[3] = -1;
     } else {
-      key = keys[r];
       int4 q = verts[r];
       v[0] = q.x;
       v[1] = q.y;
       v[2] = q.z;
       v[3] = q.w;
+      key = local_pair_key(keys[r], seg[vseg[q.x]]);
     }
   }
 };
@@ -551,26 +709,24 @@ __global__ void __launch_bounds__(kThreads) k_bucket_scatter(const int32_t* __re
   if (i < n) order[h[c] + rank] = r;
 }
 
-// Colour the contact rows (A) or the edge-length rows and bucket them by colour.
+// Colour the contact rows (A, then bucket them by colour) or the edge-length
+// rows listed in elist0[0, n_newrows) (the rows of segments being begun; their
+// buckets are built over every iterating segment by build_edge_buckets).
 int color_rows(cc_solver* s, bool edges, hipStream_t st) {
-  const int64_t nrows = edges ? s->n_erows : s->nA;
+  const int64_t nrows = edges ? s->n_newrows : s->nA;
   int32_t* colors = edges ? s->ecol : s->Acol;
-  int32_t* order = edges ? s->eorder : s->Aorder;
-  std::vector<int32_t>& off = edges ? s->ecol_off : s->col_off;
-  off.assign(1, 0);
-  if (edges) s->n_ecolors = 0; else s->n_colors = 0;
+  if (!edges) {
+    s->col_off.assign(1, 0);
+    s->n_colors = 0;
+  }
   if (nrows == 0) return CC_OK;
-  // contacts: rows 0..nA-1 (identity base list); edges: the valid-edge list of the
-  // step, kept intact in elist0 while elist1/elist2 carry the rounds
-  int32_t *cur, *nxt, *base_list;
+  int32_t *cur, *nxt;
   if (edges) {
     CC_HIP(hipMemcpyAsync(s->elist1, s->elist0, sizeof(int32_t) * nrows, hipMemcpyDeviceToDevice, st));
-    base_list = s->elist0;
     cur = s->elist1;
     nxt = s->elist2;
   } else {
     k_iota<<<nblk(nrows), kThreads, 0, st>>>(s->list0, nrows);
-    base_list = nullptr;
     cur = s->list0;
     nxt = s->list1;
   }
@@ -582,7 +738,7 @@ int color_rows(cc_solver* s, bool edges, hipStream_t st) {
   CC_HIP(hipMemsetAsync(s->rcnt, 0, sizeof(unsigned long long) * (kMaxRounds + 1), st));
   CC_TRY(launch_fill_u64(s->rcnt, 1, (unsigned long long)nrows, st));
   JpArgs a;
-  a.src = RowSrc{s->Akeys, s->Averts, s->edges, edges ? 1 : 0};
+  a.src = RowSrc{s->Akeys, s->Averts, s->edges, s->vseg, s->eseg, s->seg_dev, edges ? 1 : 0};
   a.w = s->w;
   a.seed = s->p.seed;
   a.masks = s->masks;
@@ -621,20 +777,100 @@ int color_rows(cc_solver* s, bool edges, hipStream_t st) {
   CC_HIP(hipStreamSynchronize(st));
   if (s->hc->err & 1ull) return CC_ECOLOR;
   const int32_t ncol = (int32_t)s->hc->ncol;
+  if (edges) return CC_OK;
+  std::vector<int32_t>& off = s->col_off;
   CC_HIP(hipMemsetAsync(s->col_cnt, 0, sizeof(int32_t) * (ncol + 1), st));
-  k_bucket_count<<<nblk(nrows), kThreads, 0, st>>>(base_list, nrows, colors, ncol, s->col_cnt);
+  k_bucket_count<<<nblk(nrows), kThreads, 0, st>>>(nullptr, nrows, colors, ncol, s->col_cnt);
   std::vector<int32_t> cnt(ncol);
   CC_HIP(hipMemcpyAsync(cnt.data(), s->col_cnt, sizeof(int32_t) * ncol, hipMemcpyDeviceToHost, st));
   CC_HIP(hipStreamSynchronize(st));
   off.assign(ncol + 1, 0);
   for (int c = 0; c < ncol; ++c) off[c + 1] = off[c] + cnt[c];
   CC_HIP(hipMemcpyAsync(s->col_cnt, off.data(), sizeof(int32_t) * ncol, hipMemcpyHostToDevice, st));
-  k_bucket_scatter<<<nblk(nrows), kThreads, 0, st>>>(base_list, nrows, colors, ncol, s->col_cnt,
-                                                    order);
-  CC_HIP(hipMemcpyAsync(edges ? s->ecoff_dev : s->coff_dev, off.data(), sizeof(int32_t) * (ncol + 1),
+  k_bucket_scatter<<<nblk(nrows), kThreads, 0, st>>>(nullptr, nrows, colors, ncol, s->col_cnt,
+                                                    s->Aorder);
+  CC_HIP(hipMemcpyAsync(s->coff_dev, off.data(), sizeof(int32_t) * (ncol + 1),
                         hipMemcpyHostToDevice, st));
   CC_HIP(hipGetLastError());
-  if (edges) s->n_ecolors = ncol; else s->n_colors = ncol;
+  s->n_colors = ncol;
+  return CC_OK;
+}
+
+// Edge rows of every iterating segment, bucketed by colour (rows of one colour
+// share no free vertex, so the order inside a bucket is free).
+__device__ __forceinline__ bool erow_live(int32_t e, const int32_t* eseg, const SegDev* seg,
+                                          const double* einv) {
+  const int32_t sg = eseg[e];
+  return sg >= 0 && (seg[sg].flags & kSegActive) && einv[e] > 0.0;
+}
+
+__global__ void __launch_bounds__(kThreads) k_ebucket_count(const int32_t* __restrict__ eseg,
+                                                            const SegDev* __restrict__ seg,
+                                                            const double* __restrict__ einv,
+                                                            const int32_t* __restrict__ colors,
+                                                            int32_t ne, int32_t* __restrict__ cnt) {
+  __shared__ int32_t h[kMaxColors];
+  for (int c = threadIdx.x; c < kMaxColors; c += kThreads) h[c] = 0;
+  __syncthreads();
+  int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < ne && erow_live(e, eseg, seg, einv)) atomicAdd(&h[colors[e]], 1);
+  __syncthreads();
+  for (int c = threadIdx.x; c < kMaxColors; c += kThreads)
+    if (h[c]) atomicAdd(&cnt[c], h[c]);
+}
+
+__global__ void __launch_bounds__(kThreads) k_ebucket_scatter(const int32_t* __restrict__ eseg,
+                                                              const SegDev* __restrict__ seg,
+                                                              const double* __restrict__ einv,
+                                                              const int32_t* __restrict__ colors,
+                                                              int32_t ne,
+                                                              int32_t* __restrict__ cursor,
+                                                              int32_t* __restrict__ order) {
+  __shared__ int32_t h[kMaxColors];
+  for (int c = threadIdx.x; c < kMaxColors; c += kThreads) h[c] = 0;
+  __syncthreads();
+  int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = e < ne && erow_live(e, eseg, seg, einv);
+  int32_t c = 0, rank = 0;
+  if (live) {
+    c = colors[e];
+    rank = atomicAdd(&h[c], 1);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < kMaxColors; k += kThreads)
+    if (h[k]) h[k] = atomicAdd(&cursor[k], h[k]);
+  __syncthreads();
+  if (live) order[h[c] + rank] = e;
+}
+
+int build_edge_buckets(cc_solver* s, hipStream_t st) {
+  s->ecol_off.assign(1, 0);
+  s->n_ecolors = 0;
+  s->n_erows = 0;
+  s->erows_dirty = false;
+  if (s->ne == 0 || !(s->p.flags & CC_EDGE_LEN)) return CC_OK;
+  CC_HIP(hipMemsetAsync(s->col_cnt, 0, sizeof(int32_t) * kMaxColors, st));
+  k_ebucket_count<<<nblk(s->ne), kThreads, 0, st>>>(s->eseg, s->seg_dev, s->einv, s->ecol, s->ne,
+                                                     s->col_cnt);
+  std::vector<int32_t> cnt(kMaxColors);
+  CC_HIP(hipMemcpyAsync(cnt.data(), s->col_cnt, sizeof(int32_t) * kMaxColors,
+                        hipMemcpyDeviceToHost, st));
+  CC_HIP(hipStreamSynchronize(st));
+  int32_t ncol = 0;
+  for (int c = 0; c < kMaxColors; ++c)
+    if (cnt[c]) ncol = c + 1;
+  std::vector<int32_t>& off = s->ecol_off;
+  off.assign(ncol + 1, 0);
+  for (int c = 0; c < ncol; ++c) off[c + 1] = off[c] + cnt[c];
+  if (ncol == 0) return CC_OK;
+  CC_HIP(hipMemcpyAsync(s->col_cnt, off.data(), sizeof(int32_t) * ncol, hipMemcpyHostToDevice, st));
+  k_ebucket_scatter<<<nblk(s->ne), kThreads, 0, st>>>(s->eseg, s->seg_dev, s->einv, s->ecol,
+                                                       s->ne, s->col_cnt, s->eorder);
+  CC_HIP(hipMemcpyAsync(s->ecoff_dev, off.data(), sizeof(int32_t) * (ncol + 1),
+                        hipMemcpyHostToDevice, st));
+  CC_HIP(hipGetLastError());
+  s->n_ecolors = ncol;
+  s->n_erows = off[ncol];
   return CC_OK;
 }
 
@@ -650,17 +886,36 @@ struct GsArgs {
   const double* einv;
   const double* x;
   double* y;
+  float* dy;  // mixed precision: y - x
   const double* w;
   double* lam;
+  float* lamf;  // mixed precision multipliers
   double delta, kappa2, sigma;
 };
 
 constexpr int kGsTailRows = 2048;   // colours smaller than this run in one block
 constexpr int kGsTailThreads = 1024;
 
+struct F3 {
+  float x, y, z;
+};
+__device__ __forceinline__ F3 ldf3(const float* p, int32_t i) {
+  const float* q = p + 3 * (int64_t)i;
+  return F3{q[0], q[1], q[2]};
+}
+__device__ __forceinline__ void stf3(float* p, int32_t i, F3 v) {
+  float* q = p + 3 * (int64_t)i;
+  q[0] = v.x;
+  q[1] = v.y;
+  q[2] = v.z;
+}
+
 // One projected Gauss-Seidel update of a contact row (Sec. 4.3): the row is
 // linearised at x^(l) (Sec. 4), residual w = c0 + sum J.(y - x),
 // lambda <- max(0, lambda - w/A), y_v += w_v dl J_v at its free vertices.
+// Mixed precision: the row is assembled in FP64 (closest point, normal,
+// volume sign) and rounded; the projection runs in FP32 on y - x.
+template <bool kMixed>
 __device__ __forceinline__ void gs_contact_update(const GsArgs& a, int32_t r) {
   uint64_t key = a.Akeys[r];
   int4 q = a.Averts[r];
@@ -675,6 +930,30 @@ __device__ __forceinline__ void gs_contact_update(const GsArgs& a, int32_t r) {
   Row R;
   contact_row(key_is_ee(key), xs, ws, a.delta, a.kappa2, R);
   if (!(R.inv_a > 0.0)) return;
+  if (kMixed) {
+    F3 J[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) J[k] = F3{(float)R.J[k].x, (float)R.J[k].y, (float)R.J[k].z};
+    float wr = (float)R.c0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      F3 d = ldf3(a.dy, v[k]);
+      wr = wr + (J[k].x * d.x + J[k].y * d.y + J[k].z * d.z);
+    }
+    const float lam = a.lamf[r];
+    float ln = lam - wr * (float)R.inv_a;
+    if (ln < 0.f) ln = 0.f;
+    const float dl = ln - lam;
+    a.lamf[r] = ln;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (!(ws[k] > 0.0)) continue;
+      const float co = (float)ws[k] * dl;
+      F3 d = ldf3(a.dy, v[k]);
+      stf3(a.dy, v[k], F3{d.x + co * J[k].x, d.y + co * J[k].y, d.z + co * J[k].z});
+    }
+    return;
+  }
   double wr = R.c0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -696,10 +975,33 @@ __device__ __forceinline__ void gs_contact_update(const GsArgs& a, int32_t r) {
   }
 }
 
-// Edge-length row (Sec. 4.2), same projected update.
+// Edge-length row (Sec. 4.2), same projected update. Mixed precision: the part
+// sigma - g.(x_i - x_j) in FP64, the rest on y - x in FP32.
+template <bool kMixed>
 __device__ __forceinline__ void gs_edge_update(const GsArgs& a, int32_t e) {
   int32_t i = a.edges[2 * e], j = a.edges[2 * e + 1];
   V3 g = ld3(a.eg, e);
+  const double wi = a.w[i], wj = a.w[j];
+  if (kMixed) {
+    const double base = a.sigma - vdot(g, vsub(ld3(a.x, i), ld3(a.x, j)));
+    const F3 gf{(float)g.x, (float)g.y, (float)g.z};
+    F3 di = ldf3(a.dy, i), dj = ldf3(a.dy, j);
+    const float wr = (float)base - (gf.x * (di.x - dj.x) + gf.y * (di.y - dj.y) + gf.z * (di.z - dj.z));
+    const float lam = a.lamf[e];
+    float ln = lam - wr * (float)a.einv[e];
+    if (ln < 0.f) ln = 0.f;
+    const float dl = ln - lam;
+    a.lamf[e] = ln;
+    if (wi > 0.0) {
+      const float co = (float)wi * dl;
+      stf3(a.dy, i, F3{di.x - co * gf.x, di.y - co * gf.y, di.z - co * gf.z});
+    }
+    if (wj > 0.0) {
+      const float co = (float)wj * dl;
+      stf3(a.dy, j, F3{dj.x + co * gf.x, dj.y + co * gf.y, dj.z + co * gf.z});
+    }
+    return;
+  }
   V3 yi = ld3(a.y, i), yj = ld3(a.y, j);
   V3 dy = vsub(yi, yj);
   double wr = a.sigma - vdot(g, dy);
@@ -708,7 +1010,6 @@ __device__ __forceinline__ void gs_edge_update(const GsArgs& a, int32_t e) {
   if (ln < 0.0) ln = 0.0;
   double dl = ln - lam;
   a.lam[e] = ln;
-  double wi = a.w[i], wj = a.w[j];
   if (wi > 0.0) {
     double co = wi * dl;
     st3(a.y, i, V3{yi.x - co * g.x, yi.y - co * g.y, yi.z - co * g.z});
@@ -720,30 +1021,34 @@ __device__ __forceinline__ void gs_edge_update(const GsArgs& a, int32_t e) {
 }
 
 // One colour, one row per thread (rows of a colour share no free vertex).
+template <bool kMixed>
 __global__ void __launch_bounds__(kThreads) k_gs_contact(GsArgs a) {
   int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < a.cnt) gs_contact_update(a, a.order[t]);
+  if (t < a.cnt) gs_contact_update<kMixed>(a, a.order[t]);
 }
 
+template <bool kMixed>
 __global__ void __launch_bounds__(kThreads) k_gs_edge(GsArgs a) {
   int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < a.cnt) gs_edge_update(a, a.order[t]);
+  if (t < a.cnt) gs_edge_update<kMixed>(a, a.order[t]);
 }
 
 // A run of small colours [c0, c1) in one block, colour after colour with a block
 // barrier between them; `off` holds the colour bucket offsets on the device.
+template <bool kMixed>
 __global__ void __launch_bounds__(kGsTailThreads) k_gs_tail(GsArgs a, const int32_t* off,
                                                             int32_t c0, int32_t c1, int is_edge) {
   for (int32_t c = c0; c < c1; ++c) {
     const int32_t b = off[c], e = off[c + 1];
     for (int32_t t = b + threadIdx.x; t < e; t += kGsTailThreads) {
-      if (is_edge) gs_edge_update(a, a.order[t]);
-      else gs_contact_update(a, a.order[t]);
+      if (is_edge) gs_edge_update<kMixed>(a, a.order[t]);
+      else gs_contact_update<kMixed>(a, a.order[t]);
     }
     __syncthreads();
   }
 }
 
+template <bool kMixed>
 static void gs_colours(const GsArgs& base, const int32_t* order, const std::vector<int32_t>& off,
                        const int32_t* off_dev, int32_t ncol, bool edge, hipStream_t st) {
   GsArgs a = base;
@@ -753,8 +1058,8 @@ static void gs_colours(const GsArgs& base, const int32_t* order, const std::vect
     if (cnt >= kGsTailRows) {
       a.order = order + off[c];
       a.cnt = cnt;
-      if (edge) k_gs_edge<<<nblk(cnt), kThreads, 0, st>>>(a);
-      else k_gs_contact<<<nblk(cnt), kThreads, 0, st>>>(a);
+      if (edge) k_gs_edge<kMixed><<<nblk(cnt), kThreads, 0, st>>>(a);
+      else k_gs_contact<kMixed><<<nblk(cnt), kThreads, 0, st>>>(a);
       ++c;
       continue;
     }
@@ -762,8 +1067,20 @@ static void gs_colours(const GsArgs& base, const int32_t* order, const std::vect
     while (c1 < ncol && off[c1 + 1] - off[c1] < kGsTailRows) ++c1;
     a.order = order;
     a.cnt = 0;
-    k_gs_tail<<<1, kGsTailThreads, 0, st>>>(a, off_dev, c, c1, edge ? 1 : 0);
+    k_gs_tail<kMixed><<<1, kGsTailThreads, 0, st>>>(a, off_dev, c, c1, edge ? 1 : 0);
     c = c1;
+  }
+}
+
+template <bool kMixed>
+static void gs_sweeps(cc_solver* s, GsArgs a, hipStream_t st) {
+  for (int sw = 0; sw < s->p.gs_sweeps; ++sw) {
+    a.lam = s->lamA;
+    a.lamf = (float*)s->lamA;
+    gs_colours<kMixed>(a, s->Aorder, s->col_off, s->coff_dev, s->n_colors, false, st);
+    a.lam = s->lamE;
+    a.lamf = (float*)s->lamE;
+    gs_colours<kMixed>(a, s->eorder, s->ecol_off, s->ecoff_dev, s->n_ecolors, true, st);
   }
 }
 
@@ -776,18 +1093,16 @@ int launch_gs(cc_solver* s, hipStream_t st) {
   a.einv = s->einv;
   a.x = s->x;
   a.y = s->y;
+  a.dy = s->dy;
   a.w = s->w;
   a.delta = s->p.delta;
   a.kappa2 = s->kappa2;
   a.sigma = s->p.sigma;
+  // multipliers start at zero in every backward step (0.0 and 0.0f are both all-zero bits)
   if (s->nA > 0) CC_HIP(hipMemsetAsync(s->lamA, 0, sizeof(double) * s->nA, st));
   if (s->n_erows > 0) CC_HIP(hipMemsetAsync(s->lamE, 0, sizeof(double) * s->ne, st));
-  for (int sw = 0; sw < s->p.gs_sweeps; ++sw) {
-    a.lam = s->lamA;
-    gs_colours(a, s->Aorder, s->col_off, s->coff_dev, s->n_colors, false, st);
-    a.lam = s->lamE;
-    gs_colours(a, s->eorder, s->ecol_off, s->ecoff_dev, s->n_ecolors, true, st);
-  }
+  if (s->p.flags & CC_MIXED) gs_sweeps<true>(s, a, st);
+  else gs_sweeps<false>(s, a, st);
   CC_HIP(hipGetLastError());
   return CC_OK;
 }
@@ -796,20 +1111,40 @@ int launch_gs(cc_solver* s, hipStream_t st) {
 
 // Eq. eq:forward2: alpha_i = min(0.5 gamma D_i / |y_i - x_i|, 1) (1 when y_i = x_i),
 // x_i <- y_i if alpha_i = 1 else x_i + alpha_i (y_i - x_i), r_i <- r_i (1 - alpha_i);
-// max ||x_i^(l+1) - x_i^(l)|| and ||r||_inf for Alg. 1.
+// per segment max ||x_i^(l+1) - x_i^(l)|| and ||r||_inf for Alg. 1 (bit patterns of
+// non-negative doubles, block-combined in a small LDS table, then atomicMax).
+// Vertices of segments that do not iterate are left alone.
+// Mixed precision: y = x + dy with dy in FP32; the step itself is FP64 and the
+// new dy is y - x^(l+1) rounded (0 when the vertex reached y).
+template <bool kMixed>
 __global__ void __launch_bounds__(kThreads) k_forward(double* __restrict__ x,
                                                       double* __restrict__ xold,
                                                       const double* __restrict__ y,
+                                                      float* __restrict__ dyf,
                                                       const unsigned long long* __restrict__ Di,
                                                       double* __restrict__ r,
                                                       double* __restrict__ move2, int32_t n,
-                                                      double hg, Counters* c) {
-  __shared__ unsigned long long sm[2][kThreads / 64];
+                                                      double hg, const int32_t* __restrict__ vseg,
+                                                      SegDev* seg) {
+  __shared__ int32_t gkey[kSegSlots];
+  __shared__ unsigned long long gmax[kSegSlots][2];
+  if (threadIdx.x < kSegSlots) {
+    gkey[threadIdx.x] = -1;
+    gmax[threadIdx.x][0] = gmax[threadIdx.x][1] = 0ull;
+  }
+  __syncthreads();
   int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long mb = 0, rb = 0;
-  if (i < n) {
-    V3 xi = ld3(x, i), yi = ld3(y, i);
-    V3 dx = vsub(yi, xi);
+  const int32_t sg = i < n ? vseg[i] : -1;
+  if (sg >= 0 && (seg[sg].flags & kSegActive)) {
+    V3 xi = ld3(x, i), yi, dx;
+    if (kMixed) {
+      const float* d = dyf + 3 * (int64_t)i;
+      dx = V3{(double)d[0], (double)d[1], (double)d[2]};
+      yi = V3{xi.x + dx.x, xi.y + dx.y, xi.z + dx.z};
+    } else {
+      yi = ld3(y, i);
+      dx = vsub(yi, xi);
+    }
     double n2 = vdot(dx, dx);
     double alpha = 1.0;
     if (n2 > 0.0) {
@@ -817,6 +1152,12 @@ __global__ void __launch_bounds__(kThreads) k_forward(double* __restrict__ x,
       if (a < 1.0) alpha = a;
     }
     V3 xn = (alpha == 1.0) ? yi : vaxpy(xi, alpha, dx);
+    if (kMixed) {
+      float* d = dyf + 3 * (int64_t)i;
+      d[0] = (float)(yi.x - xn.x);
+      d[1] = (float)(yi.y - xn.y);
+      d[2] = (float)(yi.z - xn.z);
+    }
     V3 mv = vsub(xn, xi);
     double m2 = vdot(mv, mv);
     move2[i] = m2;
@@ -824,34 +1165,33 @@ __global__ void __launch_bounds__(kThreads) k_forward(double* __restrict__ x,
     st3(x, i, xn);
     double ri = r[i] * (1.0 - alpha);
     r[i] = ri;
-    mb = (unsigned long long)__double_as_longlong(sqrt(m2));
-    rb = (unsigned long long)__double_as_longlong(ri);
-  }
-  mb = wave_max_u64(mb);
-  rb = wave_max_u64(rb);
-  const int wv = threadIdx.x >> 6;
-  if (__lane_id() == 0) {
-    sm[0][wv] = mb;
-    sm[1][wv] = rb;
+    const unsigned long long mb = (unsigned long long)__double_as_longlong(sqrt(m2));
+    const unsigned long long rb = (unsigned long long)__double_as_longlong(ri);
+    const int slot = seg_slot(gkey, sg);
+    if (slot >= 0) {
+      if (mb) atomicMax(&gmax[slot][0], mb);
+      if (rb) atomicMax(&gmax[slot][1], rb);
+    } else {
+      if (mb) atomicMax(&seg[sg].mmax_bits, mb);
+      if (rb) atomicMax(&seg[sg].rinf_bits, rb);
+    }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int k = 1; k < kThreads / 64; ++k) {
-      mb = sm[0][k] > mb ? sm[0][k] : mb;
-      rb = sm[1][k] > rb ? sm[1][k] : rb;
-    }
-    mb = sm[0][0] > mb ? sm[0][0] : mb;
-    rb = sm[1][0] > rb ? sm[1][0] : rb;
-    if (mb) atomicMax(&c->mmax_bits, mb);
-    if (rb) atomicMax(&c->rinf_bits, rb);
+  if (threadIdx.x < kSegSlots && gkey[threadIdx.x] >= 0) {
+    SegDev& sd = seg[gkey[threadIdx.x]];
+    if (gmax[threadIdx.x][0]) atomicMax(&sd.mmax_bits, gmax[threadIdx.x][0]);
+    if (gmax[threadIdx.x][1]) atomicMax(&sd.rinf_bits, gmax[threadIdx.x][1]);
   }
 }
 
 int launch_forward(cc_solver* s, hipStream_t st) {
   const double hg = 0.5 * s->p.gamma;
-  if (s->n > 0)
-    k_forward<<<nblk(s->n), kThreads, 0, st>>>(s->x, s->xold, s->y, s->Di, s->r, s->move2, s->n, hg,
-                                                s->dc);
+  if (s->n > 0 && (s->p.flags & CC_MIXED))
+    k_forward<true><<<nblk(s->n), kThreads, 0, st>>>(s->x, s->xold, s->y, s->dy, s->Di, s->r,
+                                                      s->move2, s->n, hg, s->vseg, s->seg_dev);
+  else if (s->n > 0)
+    k_forward<false><<<nblk(s->n), kThreads, 0, st>>>(s->x, s->xold, s->y, s->dy, s->Di, s->r,
+                                                       s->move2, s->n, hg, s->vseg, s->seg_dev);
   CC_HIP(hipGetLastError());
   return CC_OK;
 }
@@ -866,42 +1206,37 @@ __global__ void __launch_bounds__(kThreads) k_cert(const uint64_t* __restrict__ 
                                                    Topo T, const double* __restrict__ move2,
                                                    const double* __restrict__ xold,
                                                    const double* __restrict__ x, double eta2,
-                                                   Counters* c) {
+                                                   const int32_t* __restrict__ vseg, SegDev* seg) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool bad = false, hit = false;
-  if (i < nP) {
-    int32_t v[4];
-    uint64_t key = P[i];
-    pair_verts(T, key, v);
-    double mv = move2[v[0]];
+  if (i >= nP) return;
+  int32_t v[4];
+  uint64_t key = P[i];
+  pair_verts(T, key, v);
+  double mv = move2[v[0]];
 #pragma unroll
-    for (int k = 1; k < 4; ++k) {
-      double m = move2[v[k]];
-      if (m > mv) mv = m;
-    }
-    bad = !(4.0 * mv < dP[i]);
-    if (bad) {
-      V3 q[4], dq[4];
-      for (int k = 0; k < 4; ++k) {
-        q[k] = ld3(xold, v[k]);
-        dq[k] = vsub(ld3(x, v[k]), q[k]);
-      }
-      hit = ccd_hit(q, dq, key_is_ee(key), eta2);
-    }
+  for (int k = 1; k < 4; ++k) {
+    double m = move2[v[k]];
+    if (m > mv) mv = m;
   }
-  uint64_t m = __ballot(bad);
-  if (m && __lane_id() == __ffsll((long long)m) - 1)
-    atomicAdd(&c->fail, (unsigned long long)__popcll(m));
-  uint64_t h = __ballot(hit);
-  if (h && __lane_id() == __ffsll((long long)h) - 1)
-    atomicAdd(&c->hits, (unsigned long long)__popcll(h));
+  if (4.0 * mv < dP[i]) return;
+  // not certified by the motion bound: continuous test of the piece (rare)
+  V3 q[4], dq[4];
+  for (int k = 0; k < 4; ++k) {
+    q[k] = ld3(xold, v[k]);
+    dq[k] = vsub(ld3(x, v[k]), q[k]);
+  }
+  const bool hit = ccd_hit(q, dq, key_is_ee(key), eta2);
+  SegDev& sd = seg[vseg[v[0]]];
+  atomicAdd(&sd.fail, 1ull);
+  if (hit) atomicAdd(&sd.hits, 1ull);
 }
 
 int launch_cert(cc_solver* s, hipStream_t st) {
   const double eta = kCcdEta;
   if (s->nP > 0)
     k_cert<<<nblk(s->nP), kThreads, 0, st>>>(s->P, s->dP, s->nP, Topo{s->tris, s->edges},
-                                              s->move2, s->xold, s->x, eta * eta, s->dc);
+                                              s->move2, s->xold, s->x, eta * eta, s->vseg,
+                                              s->seg_dev);
   CC_HIP(hipGetLastError());
   return CC_OK;
 }
@@ -912,6 +1247,32 @@ __global__ void k_fp_col(const uint64_t* __restrict__ keys, const int32_t* __res
   unsigned long long f = i < n ? mix64(fp_key(keys[i]) ^ (uint64_t)col[i]) : 0ull;
   f = wave_sum_u64(f);
   if (__lane_id() == 0 && f) atomicAdd(&c->fp_col, f);
+}
+
+__global__ void k_y_of_dy(const double* __restrict__ x, const float* __restrict__ dy,
+                          double* __restrict__ y, int32_t n) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = 0; k < 3; ++k) y[3 * (int64_t)i + k] = x[3 * (int64_t)i + k] + (double)dy[3 * (int64_t)i + k];
+}
+
+__global__ void k_dy_of_y(const double* __restrict__ x, const double* __restrict__ y,
+                          float* __restrict__ dy, int32_t n) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = 0; k < 3; ++k) dy[3 * (int64_t)i + k] = (float)(y[3 * (int64_t)i + k] - x[3 * (int64_t)i + k]);
+}
+
+int launch_y_of_dy(cc_solver* s, double* y, int32_t n, hipStream_t st) {
+  if (n > 0) k_y_of_dy<<<nblk(n), kThreads, 0, st>>>(s->x, s->dy, y, n);
+  CC_HIP(hipGetLastError());
+  return CC_OK;
+}
+
+int launch_dy_of_y(cc_solver* s, const double* y, int32_t n, hipStream_t st) {
+  if (n > 0) k_dy_of_y<<<nblk(n), kThreads, 0, st>>>(s->x, y, s->dy, n);
+  CC_HIP(hipGetLastError());
+  return CC_OK;
 }
 
 int launch_fp_col(cc_solver* s, hipStream_t st) {

@@ -316,3 +316,77 @@ def test_stream_serving_results_equal_alone(cc, ctx):
         x_alone, its = serve.run_alone(ctx, r, steps=3, max_iters=300)
         assert its == res["results"][i]["iters"], (i, r["name"])
         assert torch.equal(x_alone, res["results"][i]["x"]), (i, r["name"])
+
+
+def _intersection_free(x, tris, edges):
+    """Exact check of a final state: no edge meets a triangle it shares no vertex
+    with (FP64 box prefilter with a margin, then exact rational tests)."""
+    import exact
+    x = np.asarray(x)
+    tris = np.asarray(tris)
+    edges = np.asarray(edges)
+    if len(tris) == 0:
+        return True
+    tlo, thi = x[tris].min(axis=1) - 1e-9, x[tris].max(axis=1) + 1e-9
+    elo, ehi = x[edges].min(axis=1), x[edges].max(axis=1)
+    for e0 in range(0, len(edges), 256):
+        sl = slice(e0, e0 + 256)
+        ov = np.all((elo[sl, None, :] <= thi[None]) & (tlo[None] <= ehi[sl, None, :]), axis=2)
+        for ei, ti in zip(*np.nonzero(ov)):
+            e = edges[e0 + ei]
+            t = tris[ti]
+            if set(e.tolist()) & set(t.tolist()):
+                continue
+            if exact.seg_tri_intersect(*(x[i] for i in (*e, *t))):
+                return False
+    return True
+
+
+@pytest.mark.parametrize("cfg,iters", [(2, 60), (3, 120), (4, 60), (1, 60)])
+def test_mixed_precision_lockstep(cc, ctx, cfg, iters):
+    """Mixed precision (FP32 backward step): every iteration starts the oracle from
+    the GPU's state (x, y, r, D, P'); the sets P', A and the colouring are decided
+    in FP64 at the same x and must be identical; x and y after the iteration must
+    agree within 1e-6 of the bounding-box diagonal; no continuous-test contact."""
+    sc = scenes.config(cfg, small=True)
+    p = dict(sc.get("params", {}))
+    p["max_iters"] = iters
+    ref = oracle.Scene(sc["w"], sc["tris"], sc["edges"], **p)
+    gpu = cc.Solver(ctx, sc["w"], sc["tris"], sc["edges"], trace=True, mixed=True, **p)
+    gpu.begin(sc["x"], sc["xt"])
+    ref.begin(sc["x"], sc["xt"])
+    tol = 1e-6 * _diag(sc["x"])
+    worst = 0.0
+    for l in range(iters):
+        xg, yg, rg, Dg = (t.cpu().numpy() if hasattr(t, "cpu") else t for t in gpu.state())
+        Pg = gpu.P().cpu().numpy().view(np.uint64)
+        ref.set_state(xg, yg, rg, Dg, Pg)
+        s_ref, it_ref = ref.iterate()
+        s_gpu, it_gpu = gpu.iterate()
+        for k in ("searched", "n_p", "n_pf", "n_a", "n_colors", "fp_pf", "fp_a", "fp_col"):
+            assert it_gpu[k] == it_ref[k], (cfg, l, k, it_gpu[k], it_ref[k])
+        assert it_gpu["ccd_hits"] == 0
+        xr, yr, _, _ = ref.state()
+        xg, yg, _, _ = (t.cpu().numpy() if hasattr(t, "cpu") else t for t in gpu.state())
+        err = max(np.abs(xg - xr).max(), np.abs(yg - yr).max())
+        worst = max(worst, err)
+        assert err <= tol, (cfg, l, err, tol)
+        if s_ref or s_gpu:
+            break
+    print(f"mixed lockstep config {cfg}: worst |x|,|y| difference {worst:.3e} m (tol {tol:.1e})")
+
+
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_mixed_precision_end_to_end(cc, ctx, cfg):
+    """A whole step in mixed precision ends intersection-free (exact test) with no
+    continuous-test contact; its distance from the FP64 oracle's result is printed."""
+    sc = scenes.config(cfg, small=True)
+    p = dict(sc.get("params", {}))
+    p["max_iters"] = 400
+    out, st = cc.collide_step(ctx, sc["x"], sc["xt"], sc["w"], sc["tris"], sc["edges"], mixed=True, **p)
+    x_mixed = out.cpu().numpy()
+    assert st["ccd_hits"] == 0
+    assert _intersection_free(x_mixed, sc["tris"], sc["edges"])
+    x_ref = oracle.collide_step(sc, **p)[0]
+    print(f"mixed end-to-end config {cfg}: iterations {st['iters']}, max |x - x_fp64| "
+          f"{np.abs(x_mixed - x_ref).max():.3e} m, bbox diagonal {_diag(sc['x']):.3e} m")
