@@ -646,6 +646,13 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
     s->st.kernel_bytes[CC_K_PAIR] += 8.0 * n_eval + 16.0 * npf + 24.0 * na + 32.0 * N + 12.0 * F + 8.0 * E;
     s->st.kernel_bytes[CC_K_FORWARD] += 92.0 * N;
     s->st.kernel_bytes[CC_K_CERT] += 16.0 * npf + 8.0 * N + 12.0 * F + 8.0 * E;
+    // projection: per contact row its key and vertex ids, x and w of its four
+    // vertices, y (or y - x) read and written, the multiplier; per edge row the
+    // ids, g, 1/A, w, y read and written (mixed: x as well, y - x in FP32)
+    const bool mixed = (p.flags & CC_MIXED) != 0;
+    const double row = mixed ? 8 + 16 + 96 + 32 + 48 + 48 + 8 : 8 + 16 + 96 + 32 + 96 + 96 + 16;
+    const double erow = mixed ? 8 + 24 + 8 + 16 + 48 + 24 + 24 + 8 : 8 + 24 + 8 + 16 + 48 + 48 + 16;
+    s->st.kernel_bytes[CC_K_GS] += (row * na + erow * s->n_erows) * p.gs_sweeps;
   }
   return CC_OK;
 }

@@ -693,19 +693,19 @@ __device__ __forceinline__ void wave_flush(uint64_t* skey, int& cnt, const TravA
 }
 
 // Exact test of one candidate primitive against the query: non-adjacent, not
-// all static, FP64 distance below D_max. Returns the pair's key (vertex-triangle:
-// vertex << 32 | triangle; edge-edge: canonical, lower edge first, with the
-// distance taken in that order) or 0.
-__device__ __forceinline__ uint64_t candidate(const TravArgs& A, bool is_vt, int32_t prim,
-                                              int32_t qid, int32_t qv0, int32_t qv1, V3 qx0,
-                                              V3 qx1) {
+// all static, FP64 distance below D_max. On success *out is the pair's key
+// (vertex-triangle: vertex << 32 | triangle; edge-edge: canonical, lower edge
+// first, with the distance taken in that order; 0 is a valid key).
+__device__ __forceinline__ bool candidate(const TravArgs& A, bool is_vt, int32_t prim,
+                                          int32_t qid, int32_t qv0, int32_t qv1, V3 qx0, V3 qx1,
+                                          uint64_t* out) {
   double d2;
   uint64_t key;
   if (is_vt) {
     int32_t v1 = A.tris[3 * prim], v2 = A.tris[3 * prim + 1], v3 = A.tris[3 * prim + 2];
     if (qv0 == v1 || qv0 == v2 || qv0 == v3 ||
         (A.stat[qv0] && A.stat[v1] && A.stat[v2] && A.stat[v3]))
-      return 0;
+      return false;
     double bw[3];
     d2 = pt_tri_d2(qx0, ld3(A.x, v1), ld3(A.x, v2), ld3(A.x, v3), bw);
     key = ((uint64_t)(uint32_t)qid << 32) | (uint32_t)prim;
@@ -713,7 +713,7 @@ __device__ __forceinline__ uint64_t candidate(const TravArgs& A, bool is_vt, int
     int32_t v1 = A.edges[2 * prim], v2 = A.edges[2 * prim + 1];
     if (qv0 == v1 || qv0 == v2 || qv1 == v1 || qv1 == v2 ||
         (A.stat[qv0] && A.stat[qv1] && A.stat[v1] && A.stat[v2]))
-      return 0;
+      return false;
     double s, t;
     if (qid < prim) {
       d2 = seg_seg_d2(qx0, qx1, ld3(A.x, v1), ld3(A.x, v2), s, t);
@@ -723,7 +723,8 @@ __device__ __forceinline__ uint64_t candidate(const TravArgs& A, bool is_vt, int
       key = KEY_EE | ((uint64_t)(uint32_t)prim << 32) | (uint32_t)qid;
     }
   }
-  return d2 < A.dmax2 ? key : 0ull;
+  *out = key;
+  return d2 < A.dmax2;
 }
 
 __global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
@@ -764,8 +765,9 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
       stack[sp++] = root;
     } else if (root != -1 && is_vt) {
       // a segment with one triangle: the leaf itself (one edge pairs with nothing)
-      uint64_t key = candidate(A, true, root & 0x7fffffff, qid, qv0, qv1, qx0, qx1);
-      if (key) skey[threadIdx.x * kBuf + cnt++] = key;
+      uint64_t key;
+      if (candidate(A, true, root & 0x7fffffff, qid, qv0, qv1, qx0, qx1, &key))
+        skey[threadIdx.x * kBuf + cnt++] = key;
     }
   }
   while (__any(sp > 0)) {
@@ -792,8 +794,9 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
           else atomicOr(&A.cnt->err, 2ull);
           continue;
         }
-        uint64_t key = candidate(A, is_vt, c & 0x7fffffff, qid, qv0, qv1, qx0, qx1);
-        if (key) skey[threadIdx.x * kBuf + cnt++] = key;
+        uint64_t key;
+        if (candidate(A, is_vt, c & 0x7fffffff, qid, qv0, qv1, qx0, qx1, &key))
+          skey[threadIdx.x * kBuf + cnt++] = key;
       }
     }
     if (__any(cnt > kBuf - 4)) wave_flush(skey, cnt, A);

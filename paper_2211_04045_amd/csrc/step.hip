@@ -709,6 +709,32 @@ __global__ void __launch_bounds__(kThreads) k_bucket_scatter(const int32_t* __re
   if (i < n) order[h[c] + rank] = r;
 }
 
+// Exclusive scan of the kMaxColors bucket counts (one block of kMaxColors
+// threads): offsets to `off` (kMaxColors + 1 entries) and, as the scatter's
+// cursors, back into `cnt`.
+__global__ void __launch_bounds__(kMaxColors) k_bucket_offsets(int32_t* __restrict__ cnt,
+                                                               int32_t* __restrict__ off) {
+  __shared__ int32_t wsum[kMaxColors / 64];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int32_t v = cnt[t];
+  int32_t incl = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    int32_t u = __shfl_up(incl, o);
+    if (lane >= o) incl += u;
+  }
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  int32_t before = 0, total = 0;
+  for (int w = 0; w < kMaxColors / 64; ++w) {
+    if (w < wv) before += wsum[w];
+    total += wsum[w];
+  }
+  const int32_t ex = before + incl - v;
+  off[t] = ex;
+  cnt[t] = ex;
+  if (t == 0) off[kMaxColors] = total;
+}
+
 // Colour the contact rows (A, then bucket them by colour) or the edge-length
 // rows listed in elist0[0, n_newrows) (the rows of segments being begun; their
 // buckets are built over every iterating segment by build_edge_buckets).
@@ -773,25 +799,28 @@ int color_rows(cc_solver* s, bool edges, hipStream_t st) {
     if (known == 0) break;
   }
   CC_HIP(hipGetLastError());
+  if (edges) {
+    CC_HIP(hipMemcpyAsync(s->hc, s->dc, sizeof(Counters), hipMemcpyDeviceToHost, st));
+    CC_HIP(hipStreamSynchronize(st));
+    return (s->hc->err & 1ull) ? CC_ECOLOR : CC_OK;
+  }
+  // contact buckets: counts, offsets (one-block scan) and the scatter are queued
+  // behind the colouring; one readback brings the colour count and the offsets
+  CC_HIP(hipMemsetAsync(s->col_cnt, 0, sizeof(int32_t) * (kMaxColors + 1), st));
+  k_bucket_count<<<nblk(nrows), kThreads, 0, st>>>(nullptr, nrows, colors, kMaxColors, s->col_cnt);
+  k_bucket_offsets<<<1, kMaxColors, 0, st>>>(s->col_cnt, s->coff_dev);
+  k_bucket_scatter<<<nblk(nrows), kThreads, 0, st>>>(nullptr, nrows, colors, kMaxColors,
+                                                    s->col_cnt, s->Aorder);
+  CC_HIP(hipGetLastError());
+  std::vector<int32_t>& off = s->col_off;
+  off.resize(kMaxColors + 1);
   CC_HIP(hipMemcpyAsync(s->hc, s->dc, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  CC_HIP(hipMemcpyAsync(off.data(), s->coff_dev, sizeof(int32_t) * (kMaxColors + 1),
+                        hipMemcpyDeviceToHost, st));
   CC_HIP(hipStreamSynchronize(st));
   if (s->hc->err & 1ull) return CC_ECOLOR;
   const int32_t ncol = (int32_t)s->hc->ncol;
-  if (edges) return CC_OK;
-  std::vector<int32_t>& off = s->col_off;
-  CC_HIP(hipMemsetAsync(s->col_cnt, 0, sizeof(int32_t) * (ncol + 1), st));
-  k_bucket_count<<<nblk(nrows), kThreads, 0, st>>>(nullptr, nrows, colors, ncol, s->col_cnt);
-  std::vector<int32_t> cnt(ncol);
-  CC_HIP(hipMemcpyAsync(cnt.data(), s->col_cnt, sizeof(int32_t) * ncol, hipMemcpyDeviceToHost, st));
-  CC_HIP(hipStreamSynchronize(st));
-  off.assign(ncol + 1, 0);
-  for (int c = 0; c < ncol; ++c) off[c + 1] = off[c] + cnt[c];
-  CC_HIP(hipMemcpyAsync(s->col_cnt, off.data(), sizeof(int32_t) * ncol, hipMemcpyHostToDevice, st));
-  k_bucket_scatter<<<nblk(nrows), kThreads, 0, st>>>(nullptr, nrows, colors, ncol, s->col_cnt,
-                                                    s->Aorder);
-  CC_HIP(hipMemcpyAsync(s->coff_dev, off.data(), sizeof(int32_t) * (ncol + 1),
-                        hipMemcpyHostToDevice, st));
-  CC_HIP(hipGetLastError());
+  off.resize(ncol + 1);
   s->n_colors = ncol;
   return CC_OK;
 }
