@@ -221,16 +221,20 @@ def serve_bench(args):
     serve.run_alone(ctx, reqs[0], steps=1)
     torch.cuda.synchronize()
     # plain path: one scene after another, consecutive collide_step calls
+    def say(msg):
+        print("# " + msg, file=sys.stderr, flush=True)
+
     t0 = time.perf_counter()
     n_plain = 0
     for i in range(k):
         _, its = serve.run_alone(ctx, reqs[i], steps=args.serve_steps)
         n_plain += len(its)
+        say(f"plain path: request {i} ({reqs[i]['name']}) iterations {its}")
     torch.cuda.synchronize()
     plain = n_plain / (time.perf_counter() - t0)
     print(f"# plain path: {plain:.2f} steps/s over {k} requests", file=sys.stderr, flush=True)
     closed = serve.run_stream(ctx, reqs[:k], np.zeros(k), steps=args.serve_steps,
-                              budget_bytes=budget)
+                              budget_bytes=budget, progress=say)
     capacity = closed["steps"] / closed["wall"]
     print(f"# closed batch: {capacity:.2f} steps/s", file=sys.stderr, flush=True)
     if args.calibrate:
@@ -239,7 +243,8 @@ def serve_bench(args):
         return
     rate = args.rate or SERVE_RATE or 0.7 * capacity / args.serve_steps
     arr = scenes.poisson_arrivals(len(reqs), rate)
-    res = serve.run_stream(ctx, reqs, arr, steps=args.serve_steps, budget_bytes=budget)
+    res = serve.run_stream(ctx, reqs, arr, steps=args.serve_steps, budget_bytes=budget,
+                           progress=say)
     lat = res["latency"] * 1e3
     value = res["steps"] / res["wall"]
     fam = np.bincount([r["family"] for r in reqs], minlength=4)[1:]

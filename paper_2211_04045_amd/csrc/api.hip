@@ -514,8 +514,8 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
     for (size_t r = 0; r < sel.size(); ++r) s->sel_host[r].seg = sel[r];
     for (int attempt = 0;; ++attempt) {
       int64_t nf = 0;
-      CC_TRY(lbvh_search(s, (int32_t)sel.size(), s->x, p.d_max, s->P + n_old, s->capP - n_old,
-                         &nf, st));
+      CC_TRY(lbvh_search(s, (int32_t)sel.size(), s->x, p.d_max, s->P + n_old, s->dP + n_old,
+                         s->capP - n_old, &nf, st));
       if (n_old + nf <= s->capP) {
         n_search = nf;
         break;
@@ -553,7 +553,8 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
     CC_HIP(hipMemsetAsync(s->dc, 0, sizeof(Counters), st));
     CC_TRY(launch_di_init(s, st));
     timer_begin(s, CC_K_PAIR, st);
-    CC_TRY(launch_pair_pass(s, n_old, p.delta * p.delta, trace, st));
+    // pairs the search just found carry their distance at this x already
+    CC_TRY(launch_pair_pass(s, n_old, sel.empty() ? s->nP : n_old, p.delta * p.delta, trace, st));
     timer_end(s, st);
     CC_HIP(hipMemcpyAsync(s->hc, s->dc, sizeof(Counters), hipMemcpyDeviceToHost, st));
     CC_HIP(hipMemcpyAsync(s->seg_host, s->seg_dev, sizeof(SegDev) * ns, hipMemcpyDeviceToHost, st));
@@ -979,7 +980,7 @@ int cc_solver_search(cc_solver* s, const double* x, double dmax, uint64_t* keys,
   // the static flags come from the last begin; without one every vertex counts as free
   if (!s->begun && nv) CC_HIP(hipMemsetAsync(s->stat, 0, nv, st));
   s->sel_host[0].seg = 0;
-  return lbvh_search(s, 1, x, dmax, keys, keys ? cap : 0, n, st);
+  return lbvh_search(s, 1, x, dmax, keys, nullptr, keys ? cap : 0, n, st);
 }
 
 int cc_solver_stats(cc_solver* s, cc_stats* out) {

@@ -234,10 +234,11 @@ namespace cc {
 int bvh_alloc(cc_solver* s);
 void bvh_free(cc_solver* s);
 // Search of the segments listed in s->sel_host[0..nsel) at state x with bound
-// dmax; appends pair keys (solver-wide ids) to out (capacity cap); *n gets the
-// total number found (may exceed cap: caller regrows).
+// dmax; appends pair keys (solver-wide ids) to out and their squared distances at
+// x to outd (if not NULL; capacity cap); *n gets the total number found (may
+// exceed cap: caller regrows).
 int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64_t* out,
-                int64_t cap, int64_t* n, hipStream_t st);
+                double* outd, int64_t cap, int64_t* n, hipStream_t st);
 
 // per-iteration kernels (step.hip)
 // Copy a scene's topology in (local vertex ids -> solver-wide) and check it;
@@ -251,8 +252,10 @@ int launch_setup(cc_solver* s, int32_t seg, const double* x_prev, const double* 
                  hipStream_t st);
 int launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t st);
 int launch_di_init(cc_solver* s, hipStream_t st);
-// pairs [0, n_old) are last iteration's P'; [n_old, nP) were appended by a search
-int launch_pair_pass(cc_solver* s, int64_t n_old, double dl2, bool trace, hipStream_t st);
+// pairs [0, n_old) are last iteration's P'; [n_old, nP) were appended by a search;
+// pairs from d_from on take their squared distance from dP (written by the search)
+int launch_pair_pass(cc_solver* s, int64_t n_old, int64_t d_from, double dl2, bool trace,
+                     hipStream_t st);
 // contacts: colour A; edges: colour the n_newrows rows listed in elist0
 int color_rows(cc_solver* s, bool edges, hipStream_t st);
 int build_edge_buckets(cc_solver* s, hipStream_t st);

@@ -610,8 +610,8 @@ struct TravTree {
 
 // 4-wide records: node i with its children collapsed, so one visit tests up to
 // four boxes (the binary node's grandchildren, or a leaf child in place) and a
-// traversal takes half as many dependent steps. Slot layout: boxes (6 floats
-// each) in the first 6 float4, child ids, then the last leaf position of each slot.
+// traversal takes half as many dependent steps. Each slot is two float4: its
+// box, child id and the last leaf position of its range.
 __global__ void k_wide(const float4* __restrict__ node, float4* __restrict__ wide, int32_t ni) {
   int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ni) return;
@@ -641,15 +641,12 @@ __global__ void k_wide(const float4* __restrict__ node, float4* __restrict__ wid
       }
     }
   }
-  float out[32];
-  for (int s = 0; s < 4; ++s)
-    for (int k = 0; k < 6; ++k) out[6 * s + k] = box[s][k];
-  for (int s = 0; s < 4; ++s) {
-    out[24 + s] = __int_as_float(id[s]);
-    out[28 + s] = __int_as_float(hi[s]);
-  }
+  // slot-major: per slot two float4 (box lo xyz, hi x | hi yz, child id, last leaf)
   float4* w = wide + 8 * (int64_t)i;
-  for (int q = 0; q < 8; ++q) w[q] = make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
+  for (int s = 0; s < 4; ++s) {
+    w[2 * s] = make_float4(box[s][0], box[s][1], box[s][2], box[s][3]);
+    w[2 * s + 1] = make_float4(box[s][4], box[s][5], __int_as_float(id[s]), __int_as_float(hi[s]));
+  }
 }
 
 struct TravArgs {
@@ -666,6 +663,7 @@ struct TravArgs {
   int32_t mv, me;         // vertex queries, edge queries
   double infl, dmax2;
   uint64_t* out;
+  double* outd;  // d^2 of each pair found (same function and operand order as the pair pass)
   int64_t cap;
   Counters* cnt;
 };
@@ -675,7 +673,8 @@ __device__ __forceinline__ bool overlap6(float4 ql, float4 qh, float lx, float l
   return ql.x <= hx && lx <= qh.x && ql.y <= hy && ly <= qh.y && ql.z <= hz && lz <= qh.z;
 }
 
-__device__ __forceinline__ void wave_flush(uint64_t* skey, int& cnt, const TravArgs& A) {
+__device__ __forceinline__ void wave_flush(uint64_t* skey, double* sd2, int& cnt,
+                                           const TravArgs& A) {
   const int lane = __lane_id();
   int incl = cnt;
   for (int o = 1; o < 64; o <<= 1) {
@@ -688,7 +687,10 @@ __device__ __forceinline__ void wave_flush(uint64_t* skey, int& cnt, const TravA
   base = __shfl(base, 0);
   int64_t pos = (int64_t)base + (incl - cnt);
   for (int i = 0; i < cnt; ++i)
-    if (pos + i < A.cap) A.out[pos + i] = skey[threadIdx.x * kBuf + i];
+    if (pos + i < A.cap) {
+      A.out[pos + i] = skey[threadIdx.x * kBuf + i];
+      if (A.outd) A.outd[pos + i] = sd2[threadIdx.x * kBuf + i];
+    }
   cnt = 0;
 }
 
@@ -698,7 +700,8 @@ __device__ __forceinline__ void wave_flush(uint64_t* skey, int& cnt, const TravA
 // first, with the distance taken in that order; 0 is a valid key).
 __device__ __forceinline__ bool candidate(const TravArgs& A, bool is_vt, int32_t prim,
                                           int32_t qid, int32_t qv0, int32_t qv1, V3 qx0, V3 qx1,
-                                          uint64_t* out) {
+                                          uint64_t* out, double* out_d2) {
+  // (out and out_d2 point at the lane's next LDS buffer slot; written on success)
   double d2;
   uint64_t key;
   if (is_vt) {
@@ -723,12 +726,15 @@ __device__ __forceinline__ bool candidate(const TravArgs& A, bool is_vt, int32_t
       key = KEY_EE | ((uint64_t)(uint32_t)prim << 32) | (uint32_t)qid;
     }
   }
+  if (!(d2 < A.dmax2)) return false;
   *out = key;
-  return d2 < A.dmax2;
+  *out_d2 = d2;
+  return true;
 }
 
 __global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
   __shared__ uint64_t skey[kTravThreads * kBuf];
+  __shared__ double sd2[kTravThreads * kBuf];
   int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
   const bool is_vt = q < A.mv;
   const bool active = q < A.mv + A.me;
@@ -765,43 +771,34 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
       stack[sp++] = root;
     } else if (root != -1 && is_vt) {
       // a segment with one triangle: the leaf itself (one edge pairs with nothing)
-      uint64_t key;
-      if (candidate(A, true, root & 0x7fffffff, qid, qv0, qv1, qx0, qx1, &key))
-        skey[threadIdx.x * kBuf + cnt++] = key;
+      if (candidate(A, true, root & 0x7fffffff, qid, qv0, qv1, qx0, qx1,
+                    &skey[threadIdx.x * kBuf + cnt], &sd2[threadIdx.x * kBuf + cnt]))
+        ++cnt;
     }
   }
   while (__any(sp > 0)) {
     if (sp > 0) {
       const int32_t i = stack[--sp];
       const float4* rec = T.wide + 8 * i;
-      float f[32];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        float4 v = rec[q];
-        f[4 * q] = v.x;
-        f[4 * q + 1] = v.y;
-        f[4 * q + 2] = v.z;
-        f[4 * q + 3] = v.w;
-      }
 #pragma unroll
       for (int slot = 0; slot < 4; ++slot) {
-        const float* b = f + 6 * slot;
-        if (!overlap6(qlo, qhi, b[0], b[1], b[2], b[3], b[4], b[5])) continue;
-        if (__float_as_int(f[28 + slot]) <= qpos) continue;
-        const int32_t c = __float_as_int(f[24 + slot]);
+        const float4 b0 = rec[2 * slot], b1 = rec[2 * slot + 1];
+        if (!overlap6(qlo, qhi, b0.x, b0.y, b0.z, b0.w, b1.x, b1.y)) continue;
+        if (__float_as_int(b1.w) <= qpos) continue;
+        const int32_t c = __float_as_int(b1.z);
         if (c >= 0) {
           if (sp < kStack) stack[sp++] = c;
           else atomicOr(&A.cnt->err, 2ull);
           continue;
         }
-        uint64_t key;
-        if (candidate(A, is_vt, c & 0x7fffffff, qid, qv0, qv1, qx0, qx1, &key))
-          skey[threadIdx.x * kBuf + cnt++] = key;
+        if (candidate(A, is_vt, c & 0x7fffffff, qid, qv0, qv1, qx0, qx1,
+                      &skey[threadIdx.x * kBuf + cnt], &sd2[threadIdx.x * kBuf + cnt]))
+          ++cnt;
       }
     }
-    if (__any(cnt > kBuf - 4)) wave_flush(skey, cnt, A);
+    if (__any(cnt > kBuf - 4)) wave_flush(skey, sd2, cnt, A);
   }
-  wave_flush(skey, cnt, A);
+  wave_flush(skey, sd2, cnt, A);
 }
 
 // ---------------------------------------------------------------- host side
@@ -893,7 +890,7 @@ static RefitView refit_view(Bvh& b) {
 }
 
 int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64_t* out,
-                int64_t cap, int64_t* nfound, hipStream_t st) {
+                double* outd, int64_t cap, int64_t* nfound, hipStream_t st) {
   // compact offsets of the selected segments' vertices, triangles and edges
   int32_t mv = 0, mt = 0, me = 0;
   for (int32_t r = 0; r < nsel; ++r) {
@@ -983,6 +980,7 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
     A.infl = infl;
     A.dmax2 = dmax * dmax;
     A.out = out;
+    A.outd = outd;
     A.cap = cap;
     A.cnt = s->dc;
     int64_t nq = (int64_t)A.mv + me;

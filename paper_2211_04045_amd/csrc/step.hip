@@ -263,6 +263,8 @@ struct PairPassArgs {
   const uint64_t* P;
   int64_t nP;
   int64_t n_old;  // [0, n_old): last P'; [n_old, nP): appended by this iteration's search
+  int64_t d_from;    // pairs i >= d_from read d^2 from dPin instead of computing it
+  const double* dPin;
   const double* x;
   Topo T;
   const int32_t* vseg;
@@ -376,22 +378,49 @@ __global__ void __launch_bounds__(kThreads) k_pair_pass(PairPassArgs a) {
   unsigned long long f1 = 0, f2 = 0;
   int32_t csg = -1;                        // segment of the counts held in registers
   unsigned long long cnt[3] = {0, 0, 0};  // evaluated, in P', in A
+  // Every load of the thread's pairs is issued before any distance is taken
+  // (keys, then topology, then segment ids and the four vertices' positions), so
+  // the dependent gathers of the pairs overlap instead of running one after the
+  // other.
+  int32_t pv[kPairsPerThread][4];
+  int32_t psg[kPairsPerThread];
+  V3 px[kPairsPerThread][4];
 #pragma unroll
   for (int k = 0; k < kPairsPerThread; ++k) {
     const int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
+    keys[k] = i < a.nP ? a.P[i] : 0ull;
+  }
+#pragma unroll
+  for (int k = 0; k < kPairsPerThread; ++k) {
+    const int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
+    if (i < a.nP) pair_verts(a.T, keys[k], pv[k]);
+    else pv[k][0] = pv[k][1] = pv[k][2] = pv[k][3] = 0;
+  }
+#pragma unroll
+  for (int k = 0; k < kPairsPerThread; ++k) {
+    const int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
+    psg[k] = a.vseg[pv[k][0]];
+    if (i < a.d_from) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) px[k][q] = ld3(a.x, pv[k][q]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kPairsPerThread; ++k) {
+    const int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
+    const uint64_t key = keys[k];
     keys[k] = 0;
     d2s[k] = 0.0;
     vs[k] = make_int4(0, 0, 0, 0);
     if (i < a.nP) {
-      uint64_t key = a.P[i];
-      int32_t v[4];
-      pair_verts(a.T, key, v);
-      const int32_t sg = a.vseg[v[0]];  // -1: a removed scene's pair
+      const int32_t* v = pv[k];
+      const int32_t sg = psg[k];  // -1: a removed scene's pair
       const int32_t fl = sg >= 0 ? a.seg[sg].flags : 0;
       const bool live = (fl & kSegActive) && !(i < a.n_old && (fl & kSegSearched));
       if (live) {
-        double d2 = pair_d2(key_is_ee(key), ld3(a.x, v[0]), ld3(a.x, v[1]), ld3(a.x, v[2]),
-                            ld3(a.x, v[3]));
+        const double d2 = i < a.d_from
+                              ? pair_d2(key_is_ee(key), px[k][0], px[k][1], px[k][2], px[k][3])
+                              : a.dPin[i];
         keys[k] = key;
         d2s[k] = d2;
         vs[k] = make_int4(v[0], v[1], v[2], v[3]);
@@ -472,11 +501,14 @@ __global__ void __launch_bounds__(kThreads) k_pair_pass(PairPassArgs a) {
   }
 }
 
-int launch_pair_pass(cc_solver* s, int64_t n_old, double dl2, bool trace, hipStream_t st) {
+int launch_pair_pass(cc_solver* s, int64_t n_old, int64_t d_from, double dl2, bool trace,
+                     hipStream_t st) {
   PairPassArgs a;
   a.P = s->P;
   a.nP = s->nP;
   a.n_old = n_old;
+  a.d_from = d_from;
+  a.dPin = s->dP;
   a.x = s->x;
   a.T = Topo{s->tris, s->edges};
   a.vseg = s->vseg;

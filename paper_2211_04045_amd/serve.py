@@ -7,8 +7,9 @@ order. The scene's state, pair set and tree then stay on the device between its
 steps. When a step completes, the next target is formed from the result by the
 caller's time integration (x~_{n+1} = 2 x_{n+1} - x_n + h^2 g for free vertices,
 the velocity being the step's own displacement over h), and the next step is
-submitted at once. Steps of different scenes run concurrently on the device, one
-stream per scene, drawn by the library's worker pool.
+submitted at once. The library's scheduler runs the steps of all running scenes
+together, in the same kernel launches; a new step joins at the next iteration
+boundary.
 
 Latency of a step: from the moment it could start (the request's arrival for its
 first step, the previous step's completion for the others) to the moment its
@@ -40,7 +41,7 @@ class _Live:
 
 def run_stream(ctx, requests, arrivals, steps: int = 10, budget_bytes: int = 0,
                max_resident: int = 64, keep_results: bool = False, poll_sleep: float = 2e-4,
-               **over):
+               progress=None, **over):
     """Serve `requests` (scene dicts with x, xt, w, tris, edges, h) arriving at
     `arrivals` (seconds from the start; all zero = a closed batch). Returns a dict
     with per-step latencies (s), the wall time, completed steps, and per-request
@@ -57,6 +58,7 @@ def run_stream(ctx, requests, arrivals, steps: int = 10, budget_bytes: int = 0,
     results = {} if keep_results else None
     done_steps = 0
     t0 = time.perf_counter()
+    t_report = t0
     try:
         while pending or live:
             now = time.perf_counter() - t0
@@ -115,6 +117,9 @@ def run_stream(ctx, requests, arrivals, steps: int = 10, budget_bytes: int = 0,
                 srv.submit(h, xt)
             if not progressed:
                 time.sleep(poll_sleep)
+            if progress is not None and time.perf_counter() - t_report > 10.0:
+                t_report = time.perf_counter()
+                progress(f"{done_steps} steps done, {len(live)} resident, {len(pending)} waiting")
     finally:
         for h in list(live):
             srv.release(h)
