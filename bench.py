@@ -48,6 +48,8 @@ def main():
     ap.add_argument("--compare", type=int, default=24,
                     help="requests served both one by one and as a closed batch")
     ap.add_argument("--budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-max-iters", type=int, default=200,
+                    help="iteration cap L of the served steps (the same in every path compared)")
     # HBM traffic from rocprofv3 counters
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, run one plain copy of known size (the "
@@ -217,8 +219,9 @@ def serve_bench(args):
     print(f"# generated {len(reqs)} requests in {time.perf_counter() - t0:.1f} s",
           file=sys.stderr, flush=True)
     k = min(args.compare, len(reqs))
-    # warm-up: one small request through both paths
-    serve.run_alone(ctx, reqs[0], steps=1)
+    L = args.serve_max_iters
+    # warm-up
+    serve.run_alone(ctx, reqs[0], steps=1, max_iters=L)
     torch.cuda.synchronize()
     # plain path: one scene after another, consecutive collide_step calls
     def say(msg):
@@ -227,14 +230,15 @@ def serve_bench(args):
     t0 = time.perf_counter()
     n_plain = 0
     for i in range(k):
-        _, its = serve.run_alone(ctx, reqs[i], steps=args.serve_steps)
+        _, its = serve.run_alone(ctx, reqs[i], steps=args.serve_steps, max_iters=L,
+                                 progress=say)
         n_plain += len(its)
         say(f"plain path: request {i} ({reqs[i]['name']}) iterations {its}")
     torch.cuda.synchronize()
     plain = n_plain / (time.perf_counter() - t0)
     print(f"# plain path: {plain:.2f} steps/s over {k} requests", file=sys.stderr, flush=True)
     closed = serve.run_stream(ctx, reqs[:k], np.zeros(k), steps=args.serve_steps,
-                              budget_bytes=budget, progress=say)
+                              budget_bytes=budget, progress=say, max_iters=L)
     capacity = closed["steps"] / closed["wall"]
     print(f"# closed batch: {capacity:.2f} steps/s", file=sys.stderr, flush=True)
     if args.calibrate:
@@ -244,7 +248,7 @@ def serve_bench(args):
     rate = args.rate or SERVE_RATE or 0.7 * capacity / args.serve_steps
     arr = scenes.poisson_arrivals(len(reqs), rate)
     res = serve.run_stream(ctx, reqs, arr, steps=args.serve_steps, budget_bytes=budget,
-                           progress=say)
+                           progress=say, max_iters=L)
     lat = res["latency"] * 1e3
     value = res["steps"] / res["wall"]
     fam = np.bincount([r["family"] for r in reqs], minlength=4)[1:]
@@ -266,6 +270,7 @@ def serve_bench(args):
                                "cubes, 2K-150K triangles log-uniform, Poisson arrivals",
                    "requests_per_family": [int(v) for v in fam],
                    "arrival_rate_per_s": round(rate, 4),
+                   "max_iters": L,
                    "budget_gib": args.budget_gib,
                    "parallelism": "single GPU"},
         "pair_updates_per_s": round(float(res["pairs"].sum()) / res["wall"], 1),

@@ -129,7 +129,7 @@ def run_stream(ctx, requests, arrivals, steps: int = 10, budget_bytes: int = 0,
                 results=results)
 
 
-def run_alone(ctx, sc, steps: int = 10, **over):
+def run_alone(ctx, sc, steps: int = 10, progress=None, **over):
     """The same request served by plain consecutive collide_step calls: the
     reference for results in the mix, and the per-scene throughput baseline."""
     import torch
@@ -147,6 +147,8 @@ def run_alone(ctx, sc, steps: int = 10, **over):
     for k in range(steps):
         out, st = collide_step(ctx, x, xt, w, tris, edges, **prm)
         its.append(st["iters"])
+        if progress is not None:
+            progress(f"{sc.get('name', 'scene')} step {k}: {st['iters']} iterations")
         prev, x = x, out
         if k + 1 < steps:
             xt = next_target(prev, x, w, sc["h"])
