@@ -334,7 +334,7 @@ def digest_pmc(fetch_csv, write_csv):
             raise SystemExit(f"{path}: no copy-probe dispatch found")
         scale = max(copy) * 1024 / COPY_PROBE_BYTES
         for k in TRAFFIC_KERNELS:
-            ds = [d for d in vals if names[d].split("(")[0].strip().endswith(k)]
+            ds = [d for d in vals if ("::" + k + "(") in names[d] or ("::" + k + "<") in names[d]]
             if not ds:
                 continue
             e = out.setdefault(k, {"launches": len(ds)})
