@@ -132,6 +132,16 @@ typedef struct cc_solver cc_solver;
 void cc_default_params(cc_params* p);
 const char* cc_strerror(int code);
 
+/* The edges of a triangle mesh (HOST arrays): every unordered vertex pair that is
+ * a side of some triangle, once, as (min, max), sorted. The edge-edge pairs of
+ * the step are drawn from the edge list, so for a triangle mesh it must hold
+ * every triangle side (Sec. 5: the pair types are vertex-triangle and
+ * edge-edge). *n_edges gets the count; edges_host (2 * cap int32) is written
+ * only when cap is large enough (call with cap = 0 to size it). CC_EINVAL on a
+ * negative index or a repeated vertex in a triangle. */
+int cc_edges_from_tris_host(const int32_t* tris_host, int32_t n_tris, int32_t* edges_host,
+                            int32_t cap, int32_t* n_edges);
+
 /* A context binds a device. Destroy releases every workspace. */
 int cc_context_create(int device, cc_context** out);
 void cc_context_destroy(cc_context* ctx);

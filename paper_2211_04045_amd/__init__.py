@@ -14,7 +14,8 @@ from . import _lib
 from ._lib import (CC_EDGE_LEN, CC_MIXED, CC_TIME_KERNELS, CC_TRACE, CCError, IterInfo, Params,
                    SceneDesc, Stats)
 
-__all__ = ["Context", "Solver", "Server", "collide_step", "collide_step_batched", "params", "CC_EDGE_LEN", "CC_TIME_KERNELS",
+__all__ = ["Context", "Solver", "Server", "collide_step", "collide_step_batched", "params",
+           "edges_from_tris", "CC_EDGE_LEN", "CC_TIME_KERNELS",
            "CC_TRACE", "CC_MIXED", "CCError"]
 
 
@@ -66,6 +67,22 @@ def params(**over) -> Params:
         else:
             setattr(p, k, v)
     return p
+
+
+def edges_from_tris(tris):
+    """Every side of every triangle once, as sorted (min, max) int32 pairs (host;
+    cc_edges_from_tris_host)."""
+    import numpy as np
+    lib = _lib.load()
+    t = np.ascontiguousarray(np.asarray(tris, dtype=np.int32).reshape(-1, 3))
+    n = C.c_int32()
+    tp = t.ctypes.data_as(C.c_void_p) if len(t) else None
+    _check(lib.cc_edges_from_tris_host(tp, len(t), None, 0, C.byref(n)), "cc_edges_from_tris_host")
+    out = np.zeros((n.value, 2), np.int32)
+    if n.value:
+        _check(lib.cc_edges_from_tris_host(tp, len(t), out.ctypes.data_as(C.c_void_p), n.value,
+                                           C.byref(n)), "cc_edges_from_tris_host")
+    return out
 
 
 class Context:

@@ -734,6 +734,32 @@ const char* cc_strerror(int code) {
   }
 }
 
+int cc_edges_from_tris_host(const int32_t* tris, int32_t nt, int32_t* edges, int32_t cap,
+                            int32_t* n_edges) {
+  if (nt < 0 || cap < 0 || !n_edges || (nt > 0 && !tris)) return CC_EINVAL;
+  std::vector<uint64_t> e;
+  e.reserve(3 * (size_t)nt);
+  for (int32_t t = 0; t < nt; ++t) {
+    const int32_t v[3] = {tris[3 * t], tris[3 * t + 1], tris[3 * t + 2]};
+    if (v[0] < 0 || v[1] < 0 || v[2] < 0 || v[0] == v[1] || v[1] == v[2] || v[0] == v[2])
+      return CC_EINVAL;
+    for (int k = 0; k < 3; ++k) {
+      const uint32_t a = (uint32_t)v[k], b = (uint32_t)v[(k + 1) % 3];
+      e.push_back(a < b ? ((uint64_t)a << 32) | b : ((uint64_t)b << 32) | a);
+    }
+  }
+  std::sort(e.begin(), e.end());
+  e.erase(std::unique(e.begin(), e.end()), e.end());
+  if ((int64_t)e.size() > INT_MAX) return CC_EINVAL;
+  *n_edges = (int32_t)e.size();
+  if (edges && cap >= (int32_t)e.size())
+    for (size_t i = 0; i < e.size(); ++i) {
+      edges[2 * i] = (int32_t)(e[i] >> 32);
+      edges[2 * i + 1] = (int32_t)(uint32_t)e[i];
+    }
+  return CC_OK;
+}
+
 int cc_context_create(int device, cc_context** out) {
   if (!out) return CC_EINVAL;
   int ndev = 0;

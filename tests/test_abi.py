@@ -4,6 +4,8 @@ import ctypes
 import os
 import re
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -44,3 +46,31 @@ def test_strerror_names_every_code():
     lib = _lib.load()
     for code in range(0, -9, -1):
         assert lib.cc_strerror(code) != b"unknown error"
+
+
+def test_edges_from_tris_host_matches_generator():
+    """The library's host edge builder against the input generator's numpy one
+    (two independent implementations) on a grid, an icosphere and a cube surface."""
+    import numpy as np
+    import paper_2211_04045_amd as cc
+    import scenes
+    for tris in (scenes.grid_cloth(7, 5, 0.01)[1], scenes.icosphere(2, 1.0)[1],
+                 scenes.box_surface(3, 1.0)[1]):
+        got = cc.edges_from_tris(tris)
+        want = scenes.edges_from_tris(np.asarray(tris))
+        want = np.sort(np.sort(want, axis=1).view([("a", want.dtype), ("b", want.dtype)]), axis=0)
+        assert np.array_equal(got, want.view(got.dtype).reshape(-1, 2))
+    assert cc.edges_from_tris(np.zeros((0, 3), np.int32)).shape == (0, 2)
+    with pytest.raises(cc.CCError):
+        cc.edges_from_tris(np.array([[0, 1, 1]], np.int32))
+
+
+def test_scene_bytes_grows_with_size():
+    import paper_2211_04045_amd as cc
+    lib = cc._lib.load()
+    a = lib.cc_scene_bytes(1000, 2000, 3000)
+    assert a > 0
+    assert lib.cc_scene_bytes(2000, 2000, 3000) > a
+    assert lib.cc_scene_bytes(1000, 4000, 3000) > a
+    assert lib.cc_scene_bytes(1000, 2000, 6000) > a
+    assert lib.cc_scene_bytes(-1, 0, 0) == 0
