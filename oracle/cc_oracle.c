@@ -908,6 +908,86 @@ int orc_begin(orc_scene* s, const double* x_prev, const double* x_tilde) {
 
 static uint64_t fp_key(uint64_t k) { return orc_mix64(k ^ 0x6A09E667F3BCC909ull); }
 
+/* Projected Jacobi backward step (Sec. 4.3.2: one projected Jacobi iteration in
+ * place of the Gauss-Seidel sweep, with an under-relaxation factor). Every row
+ * (contacts of A, then the edge-length rows; no colouring) is evaluated from the
+ * same y: w = c0 + J.(y - x) (contacts) or sigma - g.(y_i - y_j) (edges),
+ * lambda' = max(0, lambda - w/A), dl = lambda' - lambda, and the update w_v dl J_v of
+ * each of its free vertices is added to that vertex's sum; then y_v += omega * sum_v.
+ * Each update is rounded to an integer multiple of 2^-56 m before it is summed, so
+ * the sum is exact and does not depend on the order of the rows. gs_sweeps such
+ * iterations run per backward step, lambda carried between them. */
+#define JAC_SCALE 72057594037927936.0 /* 2^56: sums of up to 2^7 m, steps of 2^-56 m */
+static int jac_add(int64_t* acc, double v) {
+  if (!(fabs(v) < 64.0)) return -1;
+  *acc += llrint(v * JAC_SCALE);
+  return 0;
+}
+
+static int backward_jacobi(orc_scene* s, int64_t na, orc_iter* it) {
+  const orc_params* p = &s->p;
+  const int64_t NA = na > 0 ? na : 1;
+  int32_t* rv = (int32_t*)malloc((size_t)NA * 4 * sizeof(int32_t));
+  double* rc0 = (double*)malloc((size_t)NA * sizeof(double));
+  double* rJ = (double*)malloc((size_t)NA * 12 * sizeof(double));
+  double* rinv = (double*)malloc((size_t)NA * sizeof(double));
+  double* lam = (double*)calloc((size_t)NA, sizeof(double));
+  double* elam = (double*)calloc((size_t)(s->n_er > 0 ? s->n_er : 1), sizeof(double));
+  int64_t* acc = (int64_t*)calloc((size_t)(s->n > 0 ? s->n : 1) * 3, sizeof(int64_t));
+  int bad = 0;
+  for (int64_t q = 0; q < na; ++q)
+    orc_contact_row(s, s->x, s->A[q], rv + 4 * q, rc0 + q, rJ + 12 * q, rinv + q);
+  it->n_colors = 0;
+  for (int sw = 0; sw < p->gs_sweeps; ++sw) {
+    for (int64_t q = 0; q < na; ++q) {
+      if (!(rinv[q] > 0.0)) continue;
+      const double* J = rJ + 12 * q;
+      double wr = rc0[q];
+      for (int k = 0; k < 4; ++k) {
+        const int32_t vv = rv[4 * q + k];
+        double dy[3];
+        sub3(dy, s->y + 3 * vv, s->x + 3 * vv);
+        wr = wr + dot3(J + 3 * k, dy);
+      }
+      double ln = lam[q] - wr * rinv[q];
+      if (ln < 0.0) ln = 0.0;
+      double dl = ln - lam[q];
+      lam[q] = ln;
+      for (int k = 0; k < 4; ++k) {
+        const int32_t vv = rv[4 * q + k];
+        if (!(s->w[vv] > 0.0)) continue;
+        double co = s->w[vv] * dl;
+        for (int m = 0; m < 3; ++m) bad |= jac_add(acc + 3 * vv + m, co * J[3 * k + m]);
+      }
+    }
+    for (int32_t q = 0; q < s->n_er; ++q) {
+      const int32_t i = s->er_v[2 * q], j = s->er_v[2 * q + 1];
+      const double* g = s->er_g + 3 * q;
+      double dy[3];
+      sub3(dy, s->y + 3 * i, s->y + 3 * j);
+      double wr = p->sigma - dot3(g, dy);
+      double ln = elam[q] - wr * s->er_inv[q];
+      if (ln < 0.0) ln = 0.0;
+      double dl = ln - elam[q];
+      elam[q] = ln;
+      if (s->w[i] > 0.0) {
+        double co = s->w[i] * dl;
+        for (int m = 0; m < 3; ++m) bad |= jac_add(acc + 3 * i + m, -(co * g[m]));
+      }
+      if (s->w[j] > 0.0) {
+        double co = s->w[j] * dl;
+        for (int m = 0; m < 3; ++m) bad |= jac_add(acc + 3 * j + m, co * g[m]);
+      }
+    }
+    for (int64_t c = 0; c < 3 * (int64_t)s->n; ++c) {
+      s->y[c] = s->y[c] + p->omega * ((double)acc[c] * (1.0 / JAC_SCALE));
+      acc[c] = 0;
+    }
+  }
+  free(rv); free(rc0); free(rJ); free(rinv); free(lam); free(elam); free(acc);
+  return bad ? -3 : 0;
+}
+
 int orc_iterate(orc_scene* s, orc_iter* info) {
   const orc_params* p = &s->p;
   orc_iter it;
@@ -946,6 +1026,13 @@ int orc_iterate(orc_scene* s, orc_iter* info) {
   it.n_pf = npf;
   it.n_a = na;
 
+  if (p->backward == 1) {
+    int rc = backward_jacobi(s, na, &it);
+    if (rc != 0) {
+      free(dpf);
+      return rc;
+    }
+  } else {
   /* backward (Sec. 4): rows linearised at x^(l), coloured, one projected sweep */
   int32_t* rv = (int32_t*)malloc((size_t)(na > 0 ? na : 1) * 4 * sizeof(int32_t));
   double* rc0 = (double*)malloc((size_t)(na > 0 ? na : 1) * sizeof(double));
@@ -1005,6 +1092,9 @@ int orc_iterate(orc_scene* s, orc_iter* info) {
           for (int m = 0; m < 3; ++m) s->y[3 * j + m] = s->y[3 * j + m] + co * g[m];
         }
       }
+  }
+
+  free(rv); free(rc0); free(rJ); free(rinv); free(lam); free(elam);
   }
 
   /* forward (Sec. 5, Eq. eq:forward2) */
@@ -1078,7 +1168,7 @@ int orc_iterate(orc_scene* s, orc_iter* info) {
     it.fp_a += fp_key(s->A[q]);
     it.fp_col += orc_mix64(fp_key(s->A[q]) ^ (uint64_t)s->acol[q]);
   }
-  free(dpf); free(rv); free(rc0); free(rJ); free(rinv); free(lam); free(elam);
+  free(dpf);
   if (info) *info = it;
   return rinf < p->eps ? 1 : 0;
 }

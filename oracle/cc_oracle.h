@@ -38,6 +38,10 @@ typedef struct orc_params {
   int32_t max_colors;/* colour palette size (<= 1024) */
   int32_t edge_len;  /* 1: edge-length constraints on (Sec. 4.2) */
   uint64_t seed;     /* colouring priority seed */
+  double omega;      /* projected Jacobi: under-relaxation factor (Sec. 4.3.2 gives none) */
+  int32_t backward;  /* 0: projected Gauss-Seidel over colours (Sec. 4.3, the method);
+                        1: projected Jacobi (Sec. 4.3.2) */
+  int32_t pad_;
 } orc_params;
 
 typedef struct orc_iter {

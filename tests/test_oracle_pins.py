@@ -502,3 +502,73 @@ def test_ccd_contact_at_the_end_of_the_piece():
     dq[0] = [0.0, 0.0, -0.0019]
     hit, _ = oracle.ccd_hit(q, dq, ee=False)
     assert not hit
+
+
+# ---------------------------------------------------------------- projected Jacobi
+# (Sec. 4.3.2: one projected Jacobi iteration in place of the Gauss-Seidel sweep,
+# with an under-relaxation factor omega; the per-vertex sums are taken on a fixed
+# 2^-56 m grid, which makes them exact and independent of the order of the rows)
+
+def test_jacobi_single_row_settles_at_delta():
+    # one contact row: Jacobi with omega = 1 is the same projection, up to the
+    # 2^-56 m rounding of the update
+    x = np.array([[0.2, 0.2, 0.005], [0, 0, 0], [1, 0, 0], [0, 1, 0]], float)
+    xt = x.copy()
+    xt[0, 2] = -0.005
+    s = oracle.Scene(np.array([1.0, 0, 0, 0]), [[1, 2, 3]], [[1, 2], [2, 3], [1, 3]],
+                     max_iters=100, backward="jacobi", omega=1.0)
+    out, n, tr = s.run(x, xt, trace_cap=100)
+    assert abs(out[0, 2] - DELTA) < 1e-15
+    assert np.array_equal(out[1:], x[1:])
+    assert all(t["n_colors"] == 0 for t in tr)  # no colouring
+
+
+def test_jacobi_opposite_rows_cancel_exactly():
+    # a free vertex midway between two static parallel triangles, 0.5 mm from each:
+    # the two rows push with equal and opposite updates from the same y, their
+    # fixed-point sum is exactly zero, and the vertex stays where it is (Gauss-Seidel
+    # would move it: the second row sees the first row's push)
+    h = 0.5e-3
+    x = np.array([[0.2, 0.2, 0.0],
+                  [0, 0, -h], [1, 0, -h], [0, 1, -h],
+                  [0, 0, h], [1, 0, h], [0, 1, h]], float)
+    w = np.array([1.0, 0, 0, 0, 0, 0, 0])
+    tris = [[1, 2, 3], [4, 5, 6]]
+    jac = oracle.Scene(w, tris, [], max_iters=5, backward="jacobi", omega=1.0, edge_len=0)
+    out, n, tr = jac.run(x, x.copy(), trace_cap=5)
+    assert tr[0]["n_a"] == 2
+    assert np.array_equal(out, x)
+    gs = oracle.Scene(w, tris, [], max_iters=5, edge_len=0)
+    gs.begin(x, x.copy())
+    gs.iterate()
+    assert gs.state()[1][0, 2] != 0.0  # the sequential sweep is not symmetric
+
+
+def test_jacobi_result_does_not_depend_on_row_order():
+    # the same step with the pair list handed over in two different orders
+    x, xt, tris, edges = _two_patches()
+    w = np.ones(len(x))
+    outs = []
+    for order in (1, -1):
+        s = oracle.Scene(w, tris, edges, max_iters=30, backward="jacobi", omega=0.5)
+        s.begin(x, xt)
+        s.iterate()  # first iteration: search, then P' in the search's order
+        X, Y, R, D = s.state()
+        P = s.P()[::order].copy()
+        s.set_state(X, Y, R, D, P)
+        for _ in range(5):
+            s.iterate()
+        outs.append(s.state())
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(np.asarray(a), np.asarray(b))
+
+
+@pytest.mark.parametrize("omega", [0.5, 1.0])
+def test_jacobi_two_patches_pass_through_is_resolved_safely(omega):
+    x, xt, tris, edges = _two_patches()
+    traj, s = _safety_run(x, xt, tris, edges, np.ones(len(x)), iters=60, backward="jacobi",
+                          omega=omega)
+    xf = traj[-1]
+    assert not exact.mesh_self_intersects(xf, tris.tolist(), edges.tolist())
+    n = len(x) // 2
+    assert xf[:n, 2].mean() < xf[n:, 2].mean()
