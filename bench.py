@@ -36,6 +36,8 @@ def main():
     ap.add_argument("--small", action="store_true")
     ap.add_argument("--mixed", action="store_true",
                     help="FP32 backward step (sets, distances, x and CCD stay FP64)")
+    ap.add_argument("--jacobi", action="store_true",
+                    help="projected Jacobi backward step (Sec. 4.3.2) instead of Gauss-Seidel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=3)
     # serving stream (--config 5)
@@ -79,6 +81,8 @@ def main():
     prm = dict(sc["params"])
     if args.mixed:
         prm["mixed"] = True
+    if args.jacobi:
+        prm["backward"] = "jacobi"
     dev = "cuda"
     x = torch.as_tensor(sc["x"], device=dev)
     xt = torch.as_tensor(sc["xt"], device=dev)
@@ -176,7 +180,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": sc["name"] + " (self-contact folded cloth, 4 layers, "
                                "Perlin target, " + ("FP32 backward step, FP64 sets, x and "
-                                                     "CCD" if args.mixed else "FP64") + ")",
+                                                     "CCD" if args.mixed else "FP64") +
+                               (", projected Jacobi backward step" if args.jacobi else "") + ")",
                    "verts": int(len(sc["x"])), "tris": int(len(sc["tris"])),
                    "edges": int(len(sc["edges"])), "iterations_per_step": iters,
                    "parallelism": "single GPU"},

@@ -44,7 +44,8 @@ enum {
   CC_EINVAL = -1,    /* bad argument: NULL pointer, negative size, out-of-range or
                         repeated index in a primitive, NaN/Inf position, invalid
                         parameter (d_min < delta, d_max <= d_min, gamma not in (0,1),
-                        sigma < 1, eps <= 0, max_iters < 1, gs_sweeps < 1) */
+                        sigma < 1, eps <= 0, max_iters < 1, gs_sweeps < 1, omega not in
+                        (0,1], unknown backward solver, CC_JACOBI with CC_MIXED) */
   CC_ENOMEM = -2,    /* device allocation failed */
   CC_EOVERFLOW = -3, /* pair capacity exceeded after regrowth */
   CC_EHIP = -4,      /* HIP runtime error */
@@ -79,7 +80,19 @@ typedef struct cc_params {
   int32_t max_colors;/* colour palette, <= 1024 */
   uint32_t flags;    /* CC_EDGE_LEN | CC_TIME_KERNELS | CC_TRACE | CC_MIXED */
   uint64_t seed;     /* colouring priority seed */
+  double omega;      /* CC_JACOBI: under-relaxation factor in (0, 1] (Sec. 4.3.2 names the
+                        factor but gives no value; default 0.5) */
+  int32_t backward;  /* CC_GAUSS_SEIDEL (default, Sec. 4.3) or CC_JACOBI (Sec. 4.3.2) */
+  int32_t pad_;
 } cc_params;
+
+/* backward-step solvers */
+enum {
+  CC_GAUSS_SEIDEL = 0, /* one projected Gauss-Seidel sweep over the colours (the method) */
+  CC_JACOBI = 1        /* one projected Jacobi iteration: every row from the same y, the
+                          per-vertex updates summed on a 2^-56 m grid (exact, order
+                          independent), y += omega * sum; no colouring. FP64 only. */
+};
 
 /* Per-iteration record (filled by cc_solver_iterate). Set fingerprints are
  * wrapping sums of a 64-bit mix of each key, so they do not depend on order;

@@ -938,6 +938,7 @@ static int backward_jacobi(orc_scene* s, int64_t na, orc_iter* it) {
   for (int64_t q = 0; q < na; ++q)
     orc_contact_row(s, s->x, s->A[q], rv + 4 * q, rc0 + q, rJ + 12 * q, rinv + q);
   it->n_colors = 0;
+  for (int64_t q = 0; q < na; ++q) s->acol[q] = 0;  /* no colouring: every row in colour 0 */
   for (int sw = 0; sw < p->gs_sweeps; ++sw) {
     for (int64_t q = 0; q < na; ++q) {
       if (!(rinv[q] > 0.0)) continue;

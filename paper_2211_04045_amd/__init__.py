@@ -52,7 +52,8 @@ def _ptr(t):
 
 def params(**over) -> Params:
     """Defaults of Table 2 (cc_default_params) with keyword overrides; the flags
-    are set with edge_len=, time_kernels=, trace= and mixed= (booleans)."""
+    are set with edge_len=, time_kernels=, trace= and mixed= (booleans); backward= takes
+    "gs" (default) or "jacobi"."""
     p = Params()
     _lib.load().cc_default_params(C.byref(p))
     for k, v in over.items():
@@ -64,6 +65,8 @@ def params(**over) -> Params:
             p.flags = (p.flags | CC_TRACE) if v else (p.flags & ~CC_TRACE)
         elif k == "mixed":
             p.flags = (p.flags | CC_MIXED) if v else (p.flags & ~CC_MIXED)
+        elif k == "backward":
+            p.backward = {"gs": 0, "jacobi": 1}.get(v, v)
         else:
             setattr(p, k, v)
     return p

@@ -17,6 +17,8 @@ CC_EDGE_LEN = 1
 CC_TIME_KERNELS = 2
 CC_TRACE = 4
 CC_MIXED = 8
+CC_GAUSS_SEIDEL = 0
+CC_JACOBI = 1
 K_NAMES = ["search", "pair", "color", "gs", "forward", "cert"]
 
 ERRORS = {0: "ok", -1: "invalid argument", -2: "device allocation failed",
@@ -37,7 +39,8 @@ class Params(C.Structure):
     _fields_ = [("delta", C.c_double), ("d_min", C.c_double), ("d_max", C.c_double),
                 ("sigma", C.c_double), ("gamma", C.c_double), ("eps", C.c_double),
                 ("kappa", C.c_double), ("max_iters", C.c_int32), ("gs_sweeps", C.c_int32),
-                ("max_colors", C.c_int32), ("flags", C.c_uint32), ("seed", C.c_uint64)]
+                ("max_colors", C.c_int32), ("flags", C.c_uint32), ("seed", C.c_uint64),
+                ("omega", C.c_double), ("backward", C.c_int32), ("pad_", C.c_int32)]
 
 
 class IterInfo(C.Structure):

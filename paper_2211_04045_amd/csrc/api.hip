@@ -69,6 +69,9 @@ int check_params(const cc_params* p) {
   if (!(p->kappa >= 0.0)) return CC_EINVAL;
   if (p->max_iters < 1 || p->gs_sweeps < 1) return CC_EINVAL;
   if (p->max_colors < 1 || p->max_colors > kMaxColors) return CC_EINVAL;
+  if (p->backward != CC_GAUSS_SEIDEL && p->backward != CC_JACOBI) return CC_EINVAL;
+  if (p->backward == CC_JACOBI && (!(p->omega > 0.0 && p->omega <= 1.0) || (p->flags & CC_MIXED)))
+    return CC_EINVAL;
   return CC_OK;
 }
 
@@ -152,7 +155,7 @@ int alloc_active(cc_solver* s, int64_t cap) {
 
 void free_vertex_arrays(cc_solver* s) {
   dfree(s->w); dfree(s->stat); dfree(s->x); dfree(s->y); dfree(s->xt); dfree(s->xold);
-  dfree(s->r); dfree(s->move2); dfree(s->Di); dfree(s->vseg); dfree(s->dy);
+  dfree(s->r); dfree(s->move2); dfree(s->Di); dfree(s->vseg); dfree(s->dy); dfree(s->jacc);
   dfree(s->vmax0); dfree(s->vmax1); dfree(s->masks);
 }
 void free_edge_arrays(cc_solver* s) {
@@ -199,6 +202,9 @@ int resize_arrays(cc_solver* s, int32_t capV, int32_t capF, int32_t capE, hipStr
     CC_TRY(dregrow(&s->xt, 3 * (int64_t)capV, 3 * oV, st));
     CC_TRY(dregrow(&s->r, capV, oV, st));
     CC_TRY(dregrow(&s->dy, 3 * (int64_t)capV, 3 * oV, st));
+    dfree(s->jacc);
+    CC_TRY(dalloc(&s->jacc, 3 * (int64_t)capV));
+    CC_HIP(hipMemsetAsync(s->jacc, 0, sizeof(long long) * 3 * (size_t)capV, st));
     CC_TRY(dregrow(&s->vseg, capV, oV, st));
     CC_TRY(launch_fill_i32(s->vseg + oV, capV - oV, -1, st));
     dfree(s->xold); dfree(s->move2); dfree(s->Di); dfree(s->vmax0); dfree(s->vmax1); dfree(s->masks);
@@ -462,9 +468,12 @@ int seg_begin(cc_solver* s, const int32_t* sgs, int32_t k, const double* const* 
                         hipMemcpyDeviceToHost, st));
   CC_HIP(hipStreamSynchronize(st));
   s->n_newrows = (int32_t)s->hc->n_rows;
-  timer_begin(s, CC_K_COLOR, st);
-  int crc = color_rows(s, true, st);
-  timer_end(s, st);
+  int crc = CC_OK;
+  if (s->p.backward != CC_JACOBI) {  // the Jacobi step needs no colours
+    timer_begin(s, CC_K_COLOR, st);
+    crc = color_rows(s, true, st);
+    timer_end(s, st);
+  }
   if (crc == CC_OK)
     crc = hipMemcpyAsync(s->seg_host, s->seg_dev, sizeof(SegDev) * s->segs.size(),
                          hipMemcpyDeviceToHost, st) == hipSuccess ? CC_OK : CC_EHIP;
@@ -547,7 +556,8 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
     d.flags = ((g.live && g.active) ? kSegActive : 0) | (searched[i] ? kSegSearched : 0);
   }
   CC_HIP(hipMemcpyAsync(s->seg_dev, s->seg_host, sizeof(SegDev) * ns, hipMemcpyHostToDevice, st));
-  if (s->erows_dirty) CC_TRY(build_edge_buckets(s, st));
+  const bool jacobi = p.backward == CC_JACOBI;
+  if (s->erows_dirty && !jacobi) CC_TRY(build_edge_buckets(s, st));
   // pair pass; regrow the active set if it overflowed
   for (int attempt = 0;; ++attempt) {
     CC_HIP(hipMemsetAsync(s->dc, 0, sizeof(Counters), st));
@@ -582,17 +592,28 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
     g.last.n_a = (int64_t)s->seg_host[sg].n_a;
     if (!searched[sg]) g.last.searched = 0;
   }
-  // backward step (Sec. 4)
-  timer_begin(s, CC_K_COLOR, st);
-  int rc = color_rows(s, false, st);
-  timer_end(s, st);
-  if (rc != CC_OK) return rc;
+  // backward step (Sec. 4): coloured Gauss-Seidel, or the Jacobi variant of Sec. 4.3.2
+  if (jacobi) {
+    s->n_colors = 0;
+    s->col_off.assign(1, 0);
+    if (na > 0) CC_HIP(hipMemsetAsync(s->Acol, 0, sizeof(int32_t) * na, st));  // all in colour 0
+  } else {
+    timer_begin(s, CC_K_COLOR, st);
+    int rc = color_rows(s, false, st);
+    timer_end(s, st);
+    if (rc != CC_OK) return rc;
+  }
   if (trace) {
     CC_HIP(hipMemsetAsync(&s->dc->fp_col, 0, sizeof(unsigned long long), st));
     CC_TRY(launch_fp_col(s, st));
   }
   timer_begin(s, CC_K_GS, st);
-  CC_TRY(launch_gs(s, st));
+  if (jacobi) {
+    CC_HIP(hipMemsetAsync(&s->dc->err, 0, sizeof(unsigned long long), st));
+    CC_TRY(launch_jacobi(s, st));
+  } else {
+    CC_TRY(launch_gs(s, st));
+  }
   timer_end(s, st);
   // forward step (Sec. 5) and the path certificate
   timer_begin(s, CC_K_FORWARD, st);
@@ -604,7 +625,10 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
   CC_HIP(hipMemcpyAsync(s->seg_host, s->seg_dev, sizeof(SegDev) * ns, hipMemcpyDeviceToHost, st));
   if (trace) CC_HIP(hipMemcpyAsync(&s->hc->fp_col, &s->dc->fp_col, sizeof(unsigned long long),
                                    hipMemcpyDeviceToHost, st));
+  if (jacobi) CC_HIP(hipMemcpyAsync(&s->hc->err, &s->dc->err, sizeof(unsigned long long),
+                                    hipMemcpyDeviceToHost, st));
   CC_HIP(hipStreamSynchronize(st));
+  if (jacobi && (s->hc->err & 16ull)) return CC_EOVERFLOW;
   resolve_timers(s);
   bool changed = false;
   for (int32_t sg : act) {
@@ -717,6 +741,9 @@ void cc_default_params(cc_params* p) {
   p->max_colors = 1024;
   p->flags = CC_EDGE_LEN;
   p->seed = 0x221104045ull;
+  p->omega = 0.5;
+  p->backward = CC_GAUSS_SEIDEL;
+  p->pad_ = 0;
 }
 
 const char* cc_strerror(int code) {

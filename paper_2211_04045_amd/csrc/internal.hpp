@@ -168,6 +168,7 @@ struct cc_solver {
   // state
   double *x = nullptr, *y = nullptr, *xt = nullptr, *r = nullptr, *move2 = nullptr;
   float* dy = nullptr;  // mixed precision: y - x in FP32 (3 per vertex)
+  long long* jacc = nullptr;  // projected Jacobi: per-vertex update sums, 2^-56 m units
   double* xold = nullptr;  // x^(l) kept by the forward step for the continuous test
   unsigned long long* Di = nullptr;
   double D = 0.0;  // single-scene interface: D of segment 0
@@ -260,6 +261,7 @@ int launch_pair_pass(cc_solver* s, int64_t n_old, int64_t d_from, double dl2, bo
 int color_rows(cc_solver* s, bool edges, hipStream_t st);
 int build_edge_buckets(cc_solver* s, hipStream_t st);
 int launch_gs(cc_solver* s, hipStream_t st);
+int launch_jacobi(cc_solver* s, hipStream_t st);
 int launch_forward(cc_solver* s, hipStream_t st);
 int launch_cert(cc_solver* s, hipStream_t st);
 int launch_fp_col(cc_solver* s, hipStream_t st);

@@ -1168,6 +1168,140 @@ int launch_gs(cc_solver* s, hipStream_t st) {
   return CC_OK;
 }
 
+// ------------------------------------------------------------- projected Jacobi
+
+// Sec. 4.3.2 variant of the backward step: every row is evaluated from the same
+// y, its per-vertex updates w_v dl J_v are rounded to a multiple of 2^-56 m and
+// added (integer atomics: exact, so the sum does not depend on the order), then
+// y += omega * sum. An update of 64 m or more flags an error (bit 4).
+constexpr double kJacScale = 72057594037927936.0;  // 2^56
+
+__device__ __forceinline__ void jac_add(long long* acc, double v, Counters* c) {
+  if (!(fabs(v) < 64.0)) {
+    atomicOr(&c->err, 16ull);
+    return;
+  }
+  atomicAdd((unsigned long long*)acc, (unsigned long long)__double2ll_rn(v * kJacScale));
+}
+
+__global__ void __launch_bounds__(kThreads) k_jacobi_contact(GsArgs a, int64_t nA,
+                                                             long long* __restrict__ acc,
+                                                             Counters* c) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nA) return;
+  const uint64_t key = a.Akeys[r];
+  const int4 q = a.Averts[r];
+  const int32_t v[4] = {q.x, q.y, q.z, q.w};
+  V3 xs[4];
+  double ws[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    xs[k] = ld3(a.x, v[k]);
+    ws[k] = a.w[v[k]];
+  }
+  Row R;
+  contact_row(key_is_ee(key), xs, ws, a.delta, a.kappa2, R);
+  if (!(R.inv_a > 0.0)) return;
+  double wr = R.c0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) wr = wr + vdot(R.J[k], vsub(ld3(a.y, v[k]), xs[k]));
+  const double lam = a.lam[r];
+  double ln = lam - wr * R.inv_a;
+  if (ln < 0.0) ln = 0.0;
+  const double dl = ln - lam;
+  a.lam[r] = ln;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (!(ws[k] > 0.0)) continue;
+    const double co = ws[k] * dl;
+    long long* p = acc + 3 * (int64_t)v[k];
+    jac_add(p, co * R.J[k].x, c);
+    jac_add(p + 1, co * R.J[k].y, c);
+    jac_add(p + 2, co * R.J[k].z, c);
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_jacobi_edge(GsArgs a, int32_t ne,
+                                                          const int32_t* __restrict__ eseg,
+                                                          const SegDev* __restrict__ seg,
+                                                          long long* __restrict__ acc,
+                                                          Counters* c) {
+  const int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne || !erow_live(e, eseg, seg, a.einv)) return;
+  const int32_t i = a.edges[2 * e], j = a.edges[2 * e + 1];
+  const V3 g = ld3(a.eg, e);
+  const double wr = a.sigma - vdot(g, vsub(ld3(a.y, i), ld3(a.y, j)));
+  const double lam = a.lam[e];
+  double ln = lam - wr * a.einv[e];
+  if (ln < 0.0) ln = 0.0;
+  const double dl = ln - lam;
+  a.lam[e] = ln;
+  const double wi = a.w[i], wj = a.w[j];
+  if (wi > 0.0) {
+    const double co = wi * dl;
+    long long* p = acc + 3 * (int64_t)i;
+    jac_add(p, -(co * g.x), c);
+    jac_add(p + 1, -(co * g.y), c);
+    jac_add(p + 2, -(co * g.z), c);
+  }
+  if (wj > 0.0) {
+    const double co = wj * dl;
+    long long* p = acc + 3 * (int64_t)j;
+    jac_add(p, co * g.x, c);
+    jac_add(p + 1, co * g.y, c);
+    jac_add(p + 2, co * g.z, c);
+  }
+}
+
+// y += omega * sum (vertices of iterating segments), and the sums back to zero.
+__global__ void __launch_bounds__(kThreads) k_jacobi_apply(double* __restrict__ y,
+                                                           long long* __restrict__ acc,
+                                                           int32_t n, double omega,
+                                                           const int32_t* __restrict__ vseg,
+                                                           const SegDev* __restrict__ seg) {
+  const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int32_t sg = vseg[v];
+  if (sg < 0 || !(seg[sg].flags & kSegActive)) return;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {  // also for a zero sum (y + 0.0, as the definition reads)
+    const int64_t k = 3 * (int64_t)v + m;
+    y[k] = y[k] + omega * ((double)acc[k] * (1.0 / kJacScale));
+    acc[k] = 0;
+  }
+}
+
+int launch_jacobi(cc_solver* s, hipStream_t st) {
+  GsArgs a;
+  a.Akeys = s->Akeys;
+  a.Averts = s->Averts;
+  a.edges = s->edges;
+  a.eg = s->eg;
+  a.einv = s->einv;
+  a.x = s->x;
+  a.y = s->y;
+  a.dy = s->dy;
+  a.w = s->w;
+  a.delta = s->p.delta;
+  a.kappa2 = s->kappa2;
+  a.sigma = s->p.sigma;
+  if (s->nA > 0) CC_HIP(hipMemsetAsync(s->lamA, 0, sizeof(double) * s->nA, st));
+  if (s->ne > 0) CC_HIP(hipMemsetAsync(s->lamE, 0, sizeof(double) * s->ne, st));
+  const bool edges = s->ne > 0 && (s->p.flags & CC_EDGE_LEN);
+  for (int sw = 0; sw < s->p.gs_sweeps; ++sw) {
+    a.lam = s->lamA;
+    if (s->nA > 0) k_jacobi_contact<<<nblk(s->nA), kThreads, 0, st>>>(a, s->nA, s->jacc, s->dc);
+    a.lam = s->lamE;
+    if (edges)
+      k_jacobi_edge<<<nblk(s->ne), kThreads, 0, st>>>(a, s->ne, s->eseg, s->seg_dev, s->jacc, s->dc);
+    if (s->n > 0)
+      k_jacobi_apply<<<nblk(s->n), kThreads, 0, st>>>(s->y, s->jacc, s->n, s->p.omega, s->vseg,
+                                                      s->seg_dev);
+  }
+  CC_HIP(hipGetLastError());
+  return CC_OK;
+}
+
 // ------------------------------------------------------------- forward step
 
 // Eq. eq:forward2: alpha_i = min(0.5 gamma D_i / |y_i - x_i|, 1) (1 when y_i = x_i),

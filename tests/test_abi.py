@@ -37,7 +37,7 @@ def test_default_params_are_table_2():
     # the oracle's defaults are the same numbers (declared independently)
     import oracle
     for k in ("delta", "d_min", "d_max", "sigma", "gamma", "eps", "kappa", "gs_sweeps",
-              "max_colors", "seed"):
+              "max_colors", "seed", "omega", "backward"):
         assert getattr(p, k) == oracle.DEFAULTS[k], k
 
 

@@ -390,3 +390,26 @@ def test_mixed_precision_end_to_end(cc, ctx, cfg):
     x_ref = oracle.collide_step(sc, **p)[0]
     print(f"mixed end-to-end config {cfg}: iterations {st['iters']}, max |x - x_fp64| "
           f"{np.abs(x_mixed - x_ref).max():.3e} m, bbox diagonal {_diag(sc['x']):.3e} m")
+
+
+@pytest.mark.parametrize("cfg,iters", [(2, 200), (3, 300), (4, 150), (1, 100)])
+def test_jacobi_lockstep(cc, ctx, cfg, iters):
+    """Projected Jacobi backward step (Sec. 4.3.2): every iteration bit-identical to
+    the oracle (sets, fingerprints, x, y, r, D); no colouring."""
+    sc = scenes.config(cfg, small=True)
+    n, ref, gpu = _lockstep(cc, ctx, sc, iters, backward="jacobi")
+    assert n >= 1
+
+
+def test_jacobi_batched_equals_solo(cc, ctx):
+    mix = [scenes.config(2, small=True), scenes.config(3, small=True), scenes.config(4, small=True)]
+    res = cc.collide_step_batched(ctx, mix, backward="jacobi", max_iters=300)
+    for sc, (out, st) in zip(mix, res):
+        alone, st1 = cc.collide_step(ctx, sc["x"], sc["xt"], sc["w"], sc["tris"], sc["edges"],
+                                     backward="jacobi", max_iters=300)
+        assert torch_equal(out, alone) and st["iters"] == st1["iters"]
+
+
+def torch_equal(a, b):
+    import torch
+    return torch.equal(a, b)
