@@ -83,6 +83,10 @@ def _load():
     lib.orc_mix64.restype = u64
     lib.orc_ccd_hit.argtypes = [vp, vp, C.c_int, d, P(d)]
     lib.orc_ccd_hit.restype = C.c_int
+    lib.orc_seg_tri_meet.argtypes = [vp, vp, vp, vp, vp, d]
+    lib.orc_seg_tri_meet.restype = C.c_int
+    lib.orc_validate.argtypes = [vp, vp, d]
+    lib.orc_validate.restype = C.c_int
     _lib = lib
     return lib
 
@@ -129,6 +133,10 @@ def ccd_hit(q, dq, ee: bool, eta: float = 1e-12):
     hit = _load().orc_ccd_hit(_ptr(_f64(q).reshape(-1)), _ptr(_f64(dq).reshape(-1)), int(ee),
                               eta, C.byref(t))
     return bool(hit), t.value
+
+
+def seg_tri_meet(p, q, a, b, c, tol: float = 1e-9) -> bool:
+    return bool(_load().orc_seg_tri_meet(*(_ptr(_f64(v)) for v in (p, q, a, b, c)), float(tol)))
 
 
 def vt_key(a: int, f: int) -> int:
@@ -208,6 +216,10 @@ class Scene:
         out = np.zeros(self.n)
         self.lib.orc_get_Di(self.h, _ptr(out))
         return out
+
+    def validate(self, x, tol=1e-9):
+        """1 when x is not in the free space (see orc_validate), else 0."""
+        return int(self.lib.orc_validate(self.h, _ptr(_f64(x)), float(tol)))
 
     def search(self, x, dmax, brute=False):
         x = _f64(x)

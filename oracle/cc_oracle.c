@@ -524,20 +524,10 @@ static void test_pair(orc_scene* s, const double* x, uint64_t key, double dmax2,
   if (pair_d2(s, x, key, v) < dmax2) kb_push(kb, key);
 }
 
-int64_t orc_search(orc_scene* s, const double* x, double dmax, int brute, uint64_t* out,
-                   int64_t cap) {
-  keybuf kb = {out, 0, cap};
-  double dmax2 = dmax * dmax;
-  if (brute) {
-    for (int32_t a = 0; a < s->n; ++a)
-      for (int32_t f = 0; f < s->nt; ++f)
-        if (vt_ok(s, a, f)) test_pair(s, x, ((uint64_t)a << 32) | (uint32_t)f, dmax2, &kb);
-    for (int32_t e = 0; e < s->ne; ++e)
-      for (int32_t g = e + 1; g < s->ne; ++g)
-        if (ee_ok(s, e, g))
-          test_pair(s, x, KEY_EE | ((uint64_t)e << 32) | (uint32_t)g, dmax2, &kb);
-  } else {
-    /* grid: cell size >= dmax and >= the mean primitive extent */
+/* Grid over the scene at x: cell size >= dmax and >= the mean edge extent, the
+ * scene's box widened by 2 dmax, at most 4096 cells per axis. */
+static void grid_dims(const orc_scene* s, const double* x, double dmax, double* glo, double* h_out,
+                      int64_t* dim) {
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int32_t i = 0; i < s->n; ++i)
       for (int k = 0; k < 3; ++k) {
@@ -555,8 +545,6 @@ int64_t orc_search(orc_scene* s, const double* x, double dmax, int brute, uint64
     }
     double h = dmax;
     if (cnt && ext / (double)cnt > h) h = ext / (double)cnt;
-    int64_t dim[3];
-    double glo[3];
     for (int k = 0; k < 3; ++k) {
       glo[k] = lo[k] - 2.0 * dmax;
       double span = (hi[k] + 2.0 * dmax) - glo[k];
@@ -570,6 +558,118 @@ int64_t orc_search(orc_scene* s, const double* x, double dmax, int brute, uint64
       if (span / hh > (double)dim[k]) hh = span / (double)(dim[k] - 1);
     }
     h = hh;
+    *h_out = h;
+}
+
+/* --------------------------------------------------------------- validation */
+
+/* Sign of det[b-a, c-a, d-a] (d against the plane of a, b, c); 0 when the FP64
+ * value lies within 1e-12 of the sum of the absolute products (touching). */
+static int orient_band(const double* a, const double* b, const double* c, const double* d) {
+  double u[3], v[3], w[3], n[3];
+  sub3(u, b, a);
+  sub3(v, c, a);
+  sub3(w, d, a);
+  cross3(n, u, v);
+  double o = dot3(n, w);
+  double perm = (fabs(u[1] * v[2]) + fabs(u[2] * v[1])) * fabs(w[0]) +
+                (fabs(u[2] * v[0]) + fabs(u[0] * v[2])) * fabs(w[1]) +
+                (fabs(u[0] * v[1]) + fabs(u[1] * v[0])) * fabs(w[2]);
+  double band = 1e-12 * perm;
+  return o > band ? 1 : (o < -band ? -1 : 0);
+}
+
+/* Does segment pq meet triangle abc (crossing or touching)? Off the plane: the
+ * endpoints are not strictly on one side and the line pq passes through the
+ * closed triangle (the three orientations of pq against its sides agree). In the
+ * plane (both endpoints within the band): the FP64 distance is at most tol. */
+int orc_seg_tri_meet(const double* p, const double* q, const double* a, const double* b,
+                     const double* c, double tol) {
+  int sp = orient_band(a, b, c, p), sq = orient_band(a, b, c, q);
+  if (sp == 0 && sq == 0) {
+    double d2 = orc_seg_seg_d2(p, q, a, b, NULL), t;
+    t = orc_seg_seg_d2(p, q, b, c, NULL);
+    if (t < d2) d2 = t;
+    t = orc_seg_seg_d2(p, q, c, a, NULL);
+    if (t < d2) d2 = t;
+    t = orc_pt_tri_d2(p, a, b, c, NULL);
+    if (t < d2) d2 = t;
+    t = orc_pt_tri_d2(q, a, b, c, NULL);
+    if (t < d2) d2 = t;
+    return d2 <= tol * tol;
+  }
+  if (sp * sq > 0) return 0;
+  int s1 = orient_band(p, q, a, b), s2 = orient_band(p, q, b, c), s3 = orient_band(p, q, c, a);
+  return (s1 >= 0 && s2 >= 0 && s3 >= 0) || (s1 <= 0 && s2 <= 0 && s3 <= 0);
+}
+
+/* The input check (x^t must be in the free space, Sec. 3): 1 when some vertex-
+ * triangle or edge-edge pair of the universe is closer than tol, or some edge
+ * meets a triangle it shares no vertex with (pairs whose vertices are all static
+ * are skipped, as in the step); 0 otherwise. */
+int orc_validate(orc_scene* s, const double* x, double tol) {
+  if (orc_search(s, x, tol, 0, NULL, 0) > 0) return 1;
+  if (s->nt == 0 || s->ne == 0) return 0;
+  int64_t dim[3];
+  double glo[3], h;
+  grid_dims(s, x, tol, glo, &h, dim);
+  grid_t g;
+  grid_build(&g, x, s->tris, 3, s->nt, tol, glo, h, dim);
+  int32_t* seen = (int32_t*)malloc((size_t)s->nt * sizeof(int32_t));
+  for (int32_t f = 0; f < s->nt; ++f) seen[f] = -1;
+  int bad = 0;
+  for (int32_t e = 0; e < s->ne && !bad; ++e) {
+    const int32_t* ev = s->edges + 2 * e;
+    const double *p = x + 3 * ev[0], *q = x + 3 * ev[1];
+    double blo[3], bhi[3];
+    for (int k = 0; k < 3; ++k) {
+      blo[k] = p[k] < q[k] ? p[k] : q[k];
+      bhi[k] = p[k] < q[k] ? q[k] : p[k];
+    }
+    int64_t c0[3], c1[3];
+    cell_range(&g, blo, bhi, c0, c1);
+    for (int64_t i0 = c0[0]; i0 <= c1[0] && !bad; ++i0)
+      for (int64_t j0 = c0[1]; j0 <= c1[1] && !bad; ++j0)
+        for (int64_t k0 = c0[2]; k0 <= c1[2] && !bad; ++k0) {
+          int64_t cell = cell_of(&g, i0, j0, k0);
+          for (int64_t i = grid_lower(&g, cell); i < g.n && g.ent[i].cell == cell; ++i) {
+            int32_t f = g.ent[i].prim;
+            if (seen[f] == e) continue;
+            seen[f] = e;
+            const int32_t* t = s->tris + 3 * f;
+            if (ev[0] == t[0] || ev[0] == t[1] || ev[0] == t[2] || ev[1] == t[0] || ev[1] == t[1] ||
+                ev[1] == t[2])
+              continue;
+            if (s->stat[ev[0]] && s->stat[ev[1]] && s->stat[t[0]] && s->stat[t[1]] && s->stat[t[2]])
+              continue;
+            if (orc_seg_tri_meet(p, q, x + 3 * t[0], x + 3 * t[1], x + 3 * t[2], tol)) {
+              bad = 1;
+              break;
+            }
+          }
+        }
+  }
+  free(seen);
+  free(g.ent);
+  return bad;
+}
+
+int64_t orc_search(orc_scene* s, const double* x, double dmax, int brute, uint64_t* out,
+                   int64_t cap) {
+  keybuf kb = {out, 0, cap};
+  double dmax2 = dmax * dmax;
+  if (brute) {
+    for (int32_t a = 0; a < s->n; ++a)
+      for (int32_t f = 0; f < s->nt; ++f)
+        if (vt_ok(s, a, f)) test_pair(s, x, ((uint64_t)a << 32) | (uint32_t)f, dmax2, &kb);
+    for (int32_t e = 0; e < s->ne; ++e)
+      for (int32_t g = e + 1; g < s->ne; ++g)
+        if (ee_ok(s, e, g))
+          test_pair(s, x, KEY_EE | ((uint64_t)e << 32) | (uint32_t)g, dmax2, &kb);
+  } else {
+    int64_t dim[3];
+    double glo[3], h;
+    grid_dims(s, x, dmax, glo, &h, dim);
     if (s->nt > 0) {
       grid_t g;
       grid_build(&g, x, s->tris, 3, s->nt, dmax, glo, h, dim);

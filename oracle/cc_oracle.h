@@ -102,6 +102,15 @@ uint64_t orc_mix64(uint64_t z);
 /* Continuous test of a pair along q_k + t dq_k, t in [0,1] (q, dq: 4 points in the
  * contact-row order). Returns 1 when the primitives come within eta. */
 int orc_ccd_hit(const double* q, const double* dq, int ee, double eta, double* t_hit);
+/* Segment pq against triangle abc: 1 when they cross or touch (FP64 orientations;
+ * values within 1e-12 of their absolute products count as touching; a segment in
+ * the triangle's plane decides by its distance <= tol). */
+int orc_seg_tri_meet(const double* p, const double* q, const double* a, const double* b,
+                     const double* c, double tol);
+/* Input check at x (x^t of a step): 1 when a vertex-triangle or edge-edge pair is
+ * closer than tol or an edge meets a triangle it shares no vertex with (all-static
+ * pairs skipped; the static flags of the last begin are used). */
+int orc_validate(orc_scene* s, const double* x, double tol);
 
 #ifdef __cplusplus
 }

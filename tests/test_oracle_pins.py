@@ -572,3 +572,64 @@ def test_jacobi_two_patches_pass_through_is_resolved_safely(omega):
     assert not exact.mesh_self_intersects(xf, tris.tolist(), edges.tolist())
     n = len(x) // 2
     assert xf[:n, 2].mean() < xf[n:, 2].mean()
+
+
+# ---------------------------------------------------------------- input check
+# (x^t must lie in the free space, Sec. 3; the check is an option of the step)
+
+def test_seg_tri_meet_matches_exact_rational():
+    rng = np.random.default_rng(7)
+    n_meet = 0
+    for _ in range(3000):
+        a, b, c = rng.normal(size=(3, 3))
+        p, q = rng.normal(size=(2, 3)) * 0.8
+        want = exact.seg_tri_intersect(p, q, a, b, c)
+        got = oracle.seg_tri_meet(p, q, a, b, c)
+        assert got == want
+        n_meet += want
+    assert 100 < n_meet < 2900  # both outcomes well represented
+
+
+def test_seg_tri_meet_touching_and_coplanar_cases():
+    a, b, c = np.array([0.0, 0, 0]), np.array([1.0, 0, 0]), np.array([0.0, 1, 0])
+    # an endpoint on the triangle's interior: touching
+    assert oracle.seg_tri_meet([0.2, 0.2, 0.0], [0.2, 0.2, 1.0], a, b, c)
+    # an endpoint on a side
+    assert oracle.seg_tri_meet([0.5, 0.0, 0.0], [0.5, -1.0, 1.0], a, b, c)
+    # just above the plane, off the triangle
+    assert not oracle.seg_tri_meet([0.2, 0.2, 1e-6], [0.2, 0.2, 1.0], a, b, c)
+    # in the plane, crossing the triangle / far away in the plane
+    assert oracle.seg_tri_meet([-1.0, 0.3, 0.0], [2.0, 0.3, 0.0], a, b, c)
+    assert not oracle.seg_tri_meet([2.0, 2.0, 0.0], [3.0, 2.5, 0.0], a, b, c)
+
+
+def test_validate_scenes():
+    tol = 1e-9
+    # separated patches and the small folded cloth / cubes at x^t: free
+    x, xt, tris, edges = _two_patches()
+    s = oracle.Scene(np.ones(len(x)), tris, edges)
+    s.begin(x, xt)
+    assert s.validate(x, tol) == 0
+    for cfg in (2, 3):
+        sc = scenes.config(cfg, small=True)
+        s = oracle.Scene(sc["w"], sc["tris"], sc["edges"])
+        s.begin(sc["x"], sc["xt"])
+        assert s.validate(sc["x"], tol) == 0
+    # the upper patch tilted through the lower one: not free (the exact test agrees)
+    n = len(x) // 2
+    y = x.copy()
+    y[n:, 2] += (y[n:, 1] - y[n:, 1].mean()) * 1.5 - 1e-3
+    assert exact.mesh_self_intersects(y, tris.tolist(), edges.tolist())
+    s = oracle.Scene(np.ones(len(x)), tris, edges)
+    s.begin(y, y)
+    assert s.validate(y, tol) == 1
+    # a needle through a large triangle, far from its corners and sides: only the
+    # edge-triangle part of the check can see it
+    xn = np.array([[0.0, 0, 0], [1, 0, 0], [0, 1, 0], [0.25, 0.25, -0.5], [0.25, 0.25, 0.5]])
+    s = oracle.Scene(np.ones(5), [[0, 1, 2]], [[0, 1], [1, 2], [0, 2], [3, 4]])
+    s.begin(xn, xn)
+    assert s.search(xn, 0.2).size == 0  # no vertex-triangle or edge-edge pair nearby
+    assert s.validate(xn, tol) == 1
+    xn[4, 2] = -0.1  # now below the triangle: free
+    s.begin(xn, xn)
+    assert s.validate(xn, tol) == 0
