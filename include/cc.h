@@ -52,7 +52,8 @@ enum {
   CC_ECOLOR = -5,    /* more colours needed than max_colors */
   CC_ESTATE = -6,    /* call out of order (e.g. iterate before begin) */
   CC_EAGAIN = -7,    /* admission would exceed the HBM budget; retry after a release */
-  CC_EBUSY = -8      /* the scene's step is still running */
+  CC_EBUSY = -8,     /* the scene's step is still running */
+  CC_ENOTFREE = -9   /* CC_VALIDATE_INPUT: x_prev is not in the free space */
 };
 
 enum { CC_CONVERGED = 0, CC_MAXITER = 1 };
@@ -61,6 +62,12 @@ enum { CC_CONVERGED = 0, CC_MAXITER = 1 };
 #define CC_EDGE_LEN 1u      /* edge-length constraints on (Sec. 4.2); default on */
 #define CC_TIME_KERNELS 2u  /* time kernel families with HIP events */
 #define CC_TRACE 4u         /* per-iteration set fingerprints */
+#define CC_VALIDATE_INPUT 16u /* check at begin that x_prev is in the free space (the
+                               paper assumes it, Sec. 3): no vertex-triangle or edge-edge
+                               pair closer than 1e-9 m, no edge meeting a triangle it
+                               shares no vertex with (FP64 orientations; values within
+                               1e-12 of their absolute products count as touching);
+                               all-static pairs skipped. Fails with CC_ENOTFREE. */
 #define CC_MIXED 8u         /* mixed precision: the backward step (constraint values,
                                Jacobians, multipliers and y - x) in FP32; every set
                                decision, distance, D_i, x, the forward step and the
@@ -78,7 +85,7 @@ typedef struct cc_params {
   int32_t max_iters; /* L: 512 (dt = 1/100 s) .. 2048 (dt = 1/20 s) */
   int32_t gs_sweeps; /* Gauss-Seidel sweeps per backward step, 1 (Sec. 4.3.1) */
   int32_t max_colors;/* colour palette, <= 1024 */
-  uint32_t flags;    /* CC_EDGE_LEN | CC_TIME_KERNELS | CC_TRACE | CC_MIXED */
+  uint32_t flags;    /* CC_EDGE_LEN | CC_TIME_KERNELS | CC_TRACE | CC_MIXED | CC_VALIDATE_INPUT */
   uint64_t seed;     /* colouring priority seed */
   double omega;      /* CC_JACOBI: under-relaxation factor in (0, 1] (Sec. 4.3.2 names the
                         factor but gives no value; default 0.5) */

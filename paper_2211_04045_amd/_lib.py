@@ -17,6 +17,7 @@ CC_EDGE_LEN = 1
 CC_TIME_KERNELS = 2
 CC_TRACE = 4
 CC_MIXED = 8
+CC_VALIDATE_INPUT = 16
 CC_GAUSS_SEIDEL = 0
 CC_JACOBI = 1
 K_NAMES = ["search", "pair", "color", "gs", "forward", "cert"]
@@ -24,9 +25,11 @@ K_NAMES = ["search", "pair", "color", "gs", "forward", "cert"]
 ERRORS = {0: "ok", -1: "invalid argument", -2: "device allocation failed",
           -3: "pair capacity exceeded", -4: "HIP runtime error",
           -5: "colour palette exhausted", -6: "call out of order",
-          -7: "over the HBM budget", -8: "step still running"}
+          -7: "over the HBM budget", -8: "step still running",
+          -9: "x_prev is not in the free space"}
 CC_EAGAIN = -7
 CC_EBUSY = -8
+CC_ENOTFREE = -9
 
 
 class CCError(RuntimeError):

@@ -462,6 +462,14 @@ int seg_begin(cc_solver* s, const int32_t* sgs, int32_t k, const double* const* 
     rc[i] = launch_check_finite(s, xp, x_tilde[i], g.nv, st);
     if (rc[i] != CC_OK) continue;
     rc[i] = launch_setup(s, sg, xp, x_tilde[i], st);
+    if (rc[i] == CC_OK && (s->p.flags & CC_VALIDATE_INPUT)) {
+      // x^[k] must lie in the free space (Sec. 3): no pair within kFreeTol, no
+      // edge through a triangle
+      int bad = 0;
+      s->sel_host[0].seg = sg;
+      rc[i] = lbvh_validate(s, 1, s->x, kFreeTol, &bad, st);
+      if (rc[i] == CC_OK && bad) rc[i] = CC_ENOTFREE;
+    }
     if (rc[i] == CC_OK) ok.push_back(i);
   }
   CC_HIP(hipMemcpyAsync(&s->hc->n_rows, &s->dc->n_rows, sizeof(unsigned long long),
@@ -757,6 +765,7 @@ const char* cc_strerror(int code) {
     case CC_ESTATE: return "call out of order";
     case CC_EAGAIN: return "over the HBM budget or the scene limit, retry after a release";
     case CC_EBUSY: return "step still running";
+    case CC_ENOTFREE: return "x_prev is not in the free space";
     default: return "unknown error";
   }
 }

@@ -346,6 +346,41 @@ __device__ __noinline__ bool ccd_hit(const V3 q[4], const V3 dq[4], bool ee, dou
   return false;
 }
 
+// Sign of det[b-a, c-a, d-a] (d against the plane of a, b, c); 0 when the FP64
+// value lies within 1e-12 of the sum of the absolute products (touching).
+__device__ __forceinline__ int orient_band(V3 a, V3 b, V3 c, V3 d) {
+  const V3 u = vsub(b, a), v = vsub(c, a), w = vsub(d, a);
+  const double o = vdot(vcross(u, v), w);
+  const double perm = (fabs(u.y * v.z) + fabs(u.z * v.y)) * fabs(w.x) +
+                      (fabs(u.z * v.x) + fabs(u.x * v.z)) * fabs(w.y) +
+                      (fabs(u.x * v.y) + fabs(u.y * v.x)) * fabs(w.z);
+  const double band = 1e-12 * perm;
+  return o > band ? 1 : (o < -band ? -1 : 0);
+}
+
+// Does segment pq meet triangle abc (crossing or touching)? Off the plane: the
+// endpoints are not strictly on one side and the line pq passes through the closed
+// triangle; in the plane: the FP64 distance is at most tol.
+__device__ __forceinline__ bool seg_tri_meet(V3 p, V3 q, V3 a, V3 b, V3 c, double tol) {
+  const int sp = orient_band(a, b, c, p), sq = orient_band(a, b, c, q);
+  if (sp == 0 && sq == 0) {
+    double s_, t_, bw[3];
+    double d2 = seg_seg_d2(p, q, a, b, s_, t_), t;
+    t = seg_seg_d2(p, q, b, c, s_, t_);
+    if (t < d2) d2 = t;
+    t = seg_seg_d2(p, q, c, a, s_, t_);
+    if (t < d2) d2 = t;
+    t = pt_tri_d2(p, a, b, c, bw);
+    if (t < d2) d2 = t;
+    t = pt_tri_d2(q, a, b, c, bw);
+    if (t < d2) d2 = t;
+    return d2 <= tol * tol;
+  }
+  if (sp * sq > 0) return false;
+  const int s1 = orient_band(p, q, a, b), s2 = orient_band(p, q, b, c), s3 = orient_band(p, q, c, a);
+  return (s1 >= 0 && s2 >= 0 && s3 >= 0) || (s1 <= 0 && s2 <= 0 && s3 <= 0);
+}
+
 // splitmix64 output function (Steele, Lea, Flood 2014); a bijection on 64 bits.
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;

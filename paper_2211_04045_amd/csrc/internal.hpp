@@ -29,6 +29,7 @@ constexpr int kMaxRounds = 65536;  // Jones-Plassmann rounds per colouring
 constexpr double kCcdEta = 1e-12;  // distance at which the continuous test reports contact (m)
 constexpr int kMaxSeg = 1024;      // scenes (segments) resident in one solver
 constexpr int kSegBits = 10;       // bits of a segment's rank in a search's sort keys
+constexpr double kFreeTol = 1e-9;  // input check: closest allowed distance (m)
 
 // Per-segment record on the device (one scene of a multi-scene solver). The host
 // writes D, D2, bases and flags before an iteration and reads the reductions back.
@@ -65,7 +66,8 @@ struct Counters {
   unsigned long long ncol;      // colours used (max colour + 1)
   unsigned long long n_rows;    // edge rows in use
   unsigned long long hits;      // continuous-test contacts among the failures
-  unsigned long long pad[3];
+  unsigned long long et;        // input check: an edge meets a triangle
+  unsigned long long pad[2];
 };
 
 // Device buffers of a linear BVH over n leaves (n-1 internal nodes), allocated
@@ -240,6 +242,11 @@ void bvh_free(cc_solver* s);
 // exceed cap: caller regrows).
 int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64_t* out,
                 double* outd, int64_t cap, int64_t* n, hipStream_t st);
+// Input check of the selected segments at x (tolerance tol): *bad = 1 when a
+// vertex-triangle or edge-edge pair is closer than tol or an edge meets a
+// triangle it shares no vertex with.
+int lbvh_validate(cc_solver* s, int32_t nsel, const double* x, double tol, int* bad,
+                  hipStream_t st);
 
 // per-iteration kernels (step.hip)
 // Copy a scene's topology in (local vertex ids -> solver-wide) and check it;

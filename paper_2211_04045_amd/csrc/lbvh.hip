@@ -801,6 +801,73 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
   wave_flush(skey, sd2, cnt, A);
 }
 
+// ------------------------------------------------------- input check (edges)
+
+struct EtArgs {
+  TravTree tt;
+  const double* x;
+  const int32_t* tris;
+  const int32_t* edges;
+  const uint8_t* stat;
+  const int32_t* eprim;   // sorted edge leaves of the selected segments
+  const int16_t* erank;   // their selected-segment ranks
+  const int32_t* root_t;  // per rank: subtree root in the triangle tree
+  int32_t me;
+  double infl, tol;
+  Counters* cnt;
+};
+
+// Edge (e0, e1) at (p, q) against triangle f: skipped when they share a vertex or
+// all five vertices are static; otherwise the segment-triangle meeting test.
+__device__ __forceinline__ bool et_meet(const EtArgs& A, int32_t f, int32_t e0, int32_t e1, V3 p,
+                                        V3 q) {
+  const int32_t a = A.tris[3 * f], b = A.tris[3 * f + 1], c = A.tris[3 * f + 2];
+  if (e0 == a || e0 == b || e0 == c || e1 == a || e1 == b || e1 == c) return false;
+  if (A.stat[e0] && A.stat[e1] && A.stat[a] && A.stat[b] && A.stat[c]) return false;
+  return seg_tri_meet(p, q, ld3(A.x, a), ld3(A.x, b), ld3(A.x, c), A.tol);
+}
+
+// One lane per edge: walk its segment's triangle subtree (boxes inflated by
+// tol/2, the query box by tol/2: every triangle the edge can meet or come within
+// tol of is visited) and raise cnt->et on the first meeting.
+__global__ void __launch_bounds__(kTravThreads) k_validate_et(EtArgs A) {
+  const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= A.me) return;
+  const int32_t e = A.eprim[q];
+  const int32_t root = A.root_t[A.erank[q]];
+  if (root == -1) return;  // the segment has no triangle
+  const int32_t e0 = A.edges[2 * e], e1 = A.edges[2 * e + 1];
+  const V3 p = ld3(A.x, e0), r = ld3(A.x, e1);
+  bool bad = false;
+  if (root < 0) {
+    bad = et_meet(A, root & 0x7fffffff, e0, e1, p, r);
+  } else {
+    const float4 qlo = make_float4(lo_out(fmin(p.x, r.x) - A.infl), lo_out(fmin(p.y, r.y) - A.infl),
+                                   lo_out(fmin(p.z, r.z) - A.infl), 0.f);
+    const float4 qhi = make_float4(hi_out(fmax(p.x, r.x) + A.infl), hi_out(fmax(p.y, r.y) + A.infl),
+                                   hi_out(fmax(p.z, r.z) + A.infl), 0.f);
+    int32_t stack[kStack];
+    int sp = 0;
+    stack[sp++] = root;
+    while (sp > 0 && !bad) {
+      const int32_t i = stack[--sp];
+      const float4* rec = A.tt.wide + 8 * i;
+      for (int slot = 0; slot < 4 && !bad; ++slot) {
+        const float4 b0 = rec[2 * slot], b1 = rec[2 * slot + 1];
+        if (!overlap6(qlo, qhi, b0.x, b0.y, b0.z, b0.w, b1.x, b1.y)) continue;
+        const int32_t c = __float_as_int(b1.z);
+        if (c >= 0) {
+          if (sp < kStack) stack[sp++] = c;
+          else atomicOr(&A.cnt->err, 2ull);
+          continue;
+        }
+        bad = et_meet(A, c & 0x7fffffff, e0, e1, p, r);
+      }
+    }
+  }
+  if (bad) atomicOr(&A.cnt->et, 1ull);
+}
+
 // ---------------------------------------------------------------- host side
 
 template <class T>
@@ -998,6 +1065,46 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
   // algorithmic bytes of the traversal: queries, node records, output keys
   s->st.kernel_bytes[CC_K_SEARCH] += 24.0 * mv + 8.0 * me + 64.0 * (double)m +
                                      8.0 * (double)*nfound;
+  return CC_OK;
+}
+
+// The input check: a touching search at tol (vertex-triangle and edge-edge pairs
+// closer than tol, counted, not stored), then the edge-triangle meeting test over
+// the trees that search built.
+int lbvh_validate(cc_solver* s, int32_t nsel, const double* x, double tol, int* bad,
+                  hipStream_t st) {
+  *bad = 0;
+  const double kb = s->st.kernel_bytes[CC_K_SEARCH];
+  int64_t n = 0;
+  const int rc = lbvh_search(s, nsel, x, tol, nullptr, nullptr, 0, &n, st);
+  s->st.kernel_bytes[CC_K_SEARCH] = kb;  // not a step's search
+  CC_TRY(rc);
+  if (n > 0) {
+    *bad = 1;
+    return CC_OK;
+  }
+  const int32_t mt = s->sel_host[nsel].toff, me = s->sel_host[nsel].eoff;
+  if (mt == 0 || me == 0) return CC_OK;
+  CC_HIP(hipMemsetAsync(&s->dc->et, 0, sizeof(unsigned long long), st));
+  EtArgs A;
+  A.tt = TravTree{mt, s->tree_t.wide, s->tree_t.root, s->tree_t.leaf_prim};
+  A.x = x;
+  A.tris = s->tris;
+  A.edges = s->edges;
+  A.stat = s->stat;
+  A.eprim = s->tree_e.leaf_prim;
+  A.erank = s->erank;
+  A.root_t = s->root_t;
+  A.me = me;
+  A.infl = 0.5 * tol;
+  A.tol = tol;
+  A.cnt = s->dc;
+  k_validate_et<<<blocks(me, kTravThreads), kTravThreads, 0, st>>>(A);
+  CC_HIP(hipGetLastError());
+  CC_HIP(hipMemcpyAsync(s->hc, s->dc, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  CC_HIP(hipStreamSynchronize(st));
+  if (s->hc->err & 2ull) return CC_EOVERFLOW;
+  *bad = s->hc->et != 0;
   return CC_OK;
 }
 

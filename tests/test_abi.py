@@ -44,7 +44,7 @@ def test_default_params_are_table_2():
 def test_strerror_names_every_code():
     from paper_2211_04045_amd import _lib
     lib = _lib.load()
-    for code in range(0, -9, -1):
+    for code in range(0, -10, -1):
         assert lib.cc_strerror(code) != b"unknown error"
 
 

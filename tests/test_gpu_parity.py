@@ -413,3 +413,98 @@ def test_jacobi_batched_equals_solo(cc, ctx):
 def torch_equal(a, b):
     import torch
     return torch.equal(a, b)
+
+
+def _free_gpu(cc, ctx, x, xt, w, tris, edges):
+    """The library's input check at begin: True when x is accepted."""
+    s = cc.Solver(ctx, w, tris, edges, validate=True)
+    try:
+        s.begin(x, xt)
+        return True
+    except cc.CCError as e:
+        assert e.code == -9, e
+        return False
+    finally:
+        s.close()
+
+
+def _free_oracle(x, xt, w, tris, edges):
+    s = oracle.Scene(w, tris, edges)
+    s.begin(x, xt)
+    return s.validate(x, 1e-9) == 0
+
+
+def _check_cases():
+    out = []
+    xa, ta, ea = scenes.grid_cloth(4, 4, 5e-3)
+    xb = xa.copy()
+    xb[:, :2] += (1.3e-3, 0.9e-3)
+    xb[:, 2] += 3e-3
+    x = np.vstack([xa, xb])
+    tris = np.vstack([ta, ta + len(xa)]).astype(np.int32)
+    edges = np.vstack([ea, ea + len(xa)]).astype(np.int32)
+    w = np.ones(len(x))
+    out.append(("patches apart", x, x, w, tris, edges))
+    y = x.copy()
+    n = len(xa)
+    y[n:, 2] += (y[n:, 1] - y[n:, 1].mean()) * 1.5 - 1e-3
+    out.append(("patch tilted through", y, y, w, tris, edges))
+    # the same crossing with every vertex static: all-static pairs are skipped
+    out.append(("static crossing", y, y, np.zeros(len(y)), tris, edges))
+    tri = np.array([[0, 1, 2]], np.int32)
+    ned = np.array([[0, 1], [1, 2], [0, 2], [3, 4]], np.int32)
+    xn = np.array([[0.0, 0, 0], [1, 0, 0], [0, 1, 0], [0.25, 0.25, -0.5], [0.25, 0.25, 0.5]])
+    out.append(("needle through", xn, xn, np.ones(5), tri, ned))
+    xm = xn.copy()
+    xm[4, 2] = -0.1
+    out.append(("needle below", xm, xm, np.ones(5), tri, ned))
+    # a vertex hovering 0.5 nm / 2 nm above the triangle
+    for h, name in ((5e-10, "vertex at 0.5 nm"), (2e-9, "vertex at 2 nm")):
+        xv = np.array([[0.0, 0, 0], [1, 0, 0], [0, 1, 0], [0.2, 0.3, h]])
+        out.append((name, xv, xv, np.ones(4), tri, np.array([[0, 1], [1, 2], [0, 2]], np.int32)))
+    # soups of small random triangles: some seeds free, some not
+    for seed in range(24):
+        rng = np.random.default_rng(700 + seed)
+        nt = 40
+        c = rng.uniform(0, 1, size=(nt, 1, 3))
+        xs = (c + rng.normal(size=(nt, 3, 3)) * 0.035).reshape(-1, 3)
+        ts = np.arange(3 * nt, dtype=np.int32).reshape(nt, 3)
+        es = scenes.edges_from_tris(ts).astype(np.int32)
+        out.append((f"soup {seed}", xs, xs, np.ones(len(xs)), ts, es))
+    for cfg in (1, 2, 3, 4):
+        sc = scenes.config(cfg, small=True)
+        out.append((f"config {cfg}", sc["x"], sc["xt"], sc["w"], sc["tris"], sc["edges"]))
+    return out
+
+
+def test_input_check_agrees_with_oracle(cc, ctx):
+    """CC_VALIDATE_INPUT against the oracle's check on free, crossing, touching,
+    static and random-soup inputs: the same verdict on every case."""
+    verdicts = {}
+    for name, x, xt, w, tris, edges in _check_cases():
+        want = _free_oracle(x, xt, w, tris, edges)
+        got = _free_gpu(cc, ctx, x, xt, w, tris, edges)
+        assert got == want, name
+        verdicts[name] = got
+    assert verdicts["patches apart"] and not verdicts["patch tilted through"]
+    assert verdicts["static crossing"]
+    assert not verdicts["needle through"] and verdicts["needle below"]
+    assert not verdicts["vertex at 0.5 nm"] and verdicts["vertex at 2 nm"]
+    soups = [v for k, v in verdicts.items() if k.startswith("soup")]
+    assert any(soups) and not all(soups)
+    assert all(verdicts[f"config {c}"] for c in (1, 2, 3, 4))
+
+
+def test_input_check_in_a_batch_rejects_only_the_bad_scene(cc, ctx):
+    """In one multi-scene call a crossing scene fails with CC_ENOTFREE; the
+    others' results equal their solo runs."""
+    good = [scenes.config(2, small=True), scenes.config(3, small=True)]
+    (_, y, _, w, tris, edges) = _check_cases()[1]
+    bad = dict(x=y, xt=y, w=w, tris=tris, edges=edges, params={})
+    with pytest.raises(cc.CCError) as e:
+        cc.collide_step_batched(ctx, [good[0], bad, good[1]], validate=True)
+    assert e.value.code == -9
+    res = cc.collide_step_batched(ctx, good, validate=True)
+    for sc, (xb, _) in zip(good, res):
+        xs, _ = cc.collide_step(ctx, sc["x"], sc["xt"], sc["w"], sc["tris"], sc["edges"])
+        assert np.array_equal(xb.cpu().numpy(), xs.cpu().numpy())
