@@ -15,6 +15,7 @@ _LIB_PATH = os.path.join(_HERE, "liborcc.so")
 _lib = None
 
 KEY_EE = 1 << 63
+KEY_VV = 1 << 62
 
 # Table 2 defaults (L depends on the time step; the scene may override)
 DEFAULTS = dict(delta=1e-3, d_min=2e-3, d_max=4e-3, sigma=1.1, gamma=0.9, eps=1e-4,
@@ -87,6 +88,8 @@ def _load():
     lib.orc_seg_tri_meet.restype = C.c_int
     lib.orc_validate.argtypes = [vp, vp, d]
     lib.orc_validate.restype = C.c_int
+    lib.orc_particles.argtypes = [vp, vp]
+    lib.orc_particles.restype = i32
     _lib = lib
     return lib
 
@@ -127,11 +130,16 @@ def seg_seg_d2(a, b, c, e):
     return d2, st
 
 
-def ccd_hit(q, dq, ee: bool, eta: float = 1e-12):
-    """Continuous test of 4 points q (4,3) moving by dq (4,3) over t in [0,1]."""
+def ccd_hit(q, dq, ee, eta: float = 1e-12):
+    """Continuous test of points q moving by dq over t in [0,1]: ee False/0 vertex-
+    triangle (4,3), True/1 edge-edge (4,3), 2 vertex-vertex (2,3)."""
     t = C.c_double(-1.0)
-    hit = _load().orc_ccd_hit(_ptr(_f64(q).reshape(-1)), _ptr(_f64(dq).reshape(-1)), int(ee),
-                              eta, C.byref(t))
+    qq = np.zeros(12)
+    dd = np.zeros(12)
+    qf, df = _f64(q).reshape(-1), _f64(dq).reshape(-1)
+    qq[:len(qf)] = qf
+    dd[:len(df)] = df
+    hit = _load().orc_ccd_hit(_ptr(qq), _ptr(dd), int(ee), eta, C.byref(t))
     return bool(hit), t.value
 
 
@@ -145,6 +153,10 @@ def vt_key(a: int, f: int) -> int:
 
 def ee_key(e: int, g: int) -> int:
     return KEY_EE | (e << 32) | g
+
+
+def vv_key(a: int, b: int) -> int:
+    return KEY_VV | (min(a, b) << 32) | max(a, b)
 
 
 class Scene:
@@ -164,6 +176,13 @@ class Scene:
         if getattr(self, "h", None):
             self.lib.orc_destroy(self.h)
             self.h = None
+
+    def particles(self):
+        """Vertices in no triangle and no edge (the vertex-vertex pair universe)."""
+        n = self.lib.orc_particles(self.h, None)
+        out = np.zeros(n, np.int32)
+        self.lib.orc_particles(self.h, _ptr(out))
+        return out
 
     def begin(self, x, xt):
         rc = self.lib.orc_begin(self.h, _ptr(_f64(x)), _ptr(_f64(xt)))

@@ -40,6 +40,10 @@
  *  - Every vertex is a point primitive for vertex-triangle pairs; edge-edge
  *    pairs share no vertex; pairs whose vertices are all static (w = 0 and
  *    x~ = x) are dropped.
+ *  - Vertex-vertex pairs (the third pair type of Sec. 4.1, c = |x_i - x_a|/delta
+ *    - 1, for sand) join two particles: vertices that are a corner of no triangle
+ *    and an end of no edge. The row is that constraint linearised at x^(l); the
+ *    continuous test of such a pair is the closest approach of the two points.
  */
 #include "cc_oracle.h"
 
@@ -48,6 +52,7 @@
 #include <string.h>
 
 #define KEY_EE (1ull << 63)
+#define KEY_VV (1ull << 62)
 /* distance at which the continuous test reports contact (metres) */
 #define ORC_CCD_ETA 1e-12
 
@@ -56,6 +61,8 @@ struct orc_scene {
   double* w;
   int32_t* tris;
   int32_t* edges;
+  int32_t np;       /* particles: vertices in no triangle and no edge */
+  int32_t* part;    /* their ids, increasing */
   uint8_t* stat;
   orc_params p;
   /* state */
@@ -234,10 +241,17 @@ double orc_seg_seg_d2(const double* a, const double* b, const double* c,
 /* ------------------------------------------------------------------ pairs */
 
 /* Vertex ids of a pair: VT key (a<<32 | f) -> (a, tri f); EE key -> (edge e, edge g). */
+/* Vertices of a pair: vertex-triangle (a, i, j, k), edge-edge (a, b, c, e),
+ * vertex-vertex (a, b, -1, -1). */
 static void pair_verts(const orc_scene* s, uint64_t key, int32_t* v) {
-  uint32_t pa = (uint32_t)((key >> 32) & 0x7fffffffu);
+  uint32_t pa = (uint32_t)((key >> 32) & 0x3fffffffu);
   uint32_t pb = (uint32_t)(key & 0xffffffffu);
-  if (key & KEY_EE) {
+  if (key & KEY_VV) {
+    v[0] = (int32_t)pa;
+    v[1] = (int32_t)pb;
+    v[2] = -1;
+    v[3] = -1;
+  } else if (key & KEY_EE) {
     v[0] = s->edges[2 * pa];
     v[1] = s->edges[2 * pa + 1];
     v[2] = s->edges[2 * pb];
@@ -252,6 +266,11 @@ static void pair_verts(const orc_scene* s, uint64_t key, int32_t* v) {
 
 static double pair_d2(const orc_scene* s, const double* x, uint64_t key, int32_t* v) {
   pair_verts(s, key, v);
+  if (key & KEY_VV) {
+    double d[3];
+    sub3(d, x + 3 * v[0], x + 3 * v[1]);
+    return dot3(d, d);
+  }
   const double *x0 = x + 3 * v[0], *x1 = x + 3 * v[1], *x2 = x + 3 * v[2], *x3 = x + 3 * v[3];
   if (key & KEY_EE) return orc_seg_seg_d2(x0, x1, x2, x3, NULL);
   return orc_pt_tri_d2(x0, x1, x2, x3, NULL);
@@ -298,6 +317,29 @@ int orc_contact_row(const orc_scene* s, const double* x, uint64_t key, int32_t* 
                     double* c0, double* J, double* inv_a) {
   const double delta = s->p.delta, kappa2 = s->p.kappa * s->p.kappa;
   pair_verts(s, key, v);
+  if (key & KEY_VV) {
+    /* c = |x_a - x_b|/delta - 1 (Sec. 4.1) at x^(l): J_a = u/delta, J_b = -u/delta
+     * with u the unit vector from b to a; coincident points give no row */
+    double diff[3];
+    sub3(diff, x + 3 * v[0], x + 3 * v[1]);
+    double d = sqrt(dot3(diff, diff));
+    memset(J, 0, 12 * sizeof(double));
+    if (d == 0.0) {
+      *inv_a = 0.0;
+      return 2;
+    }
+    double u[3] = {diff[0] / d, diff[1] / d, diff[2] / d};
+    const double om[2] = {1.0, -1.0};
+    for (int i = 0; i < 2; ++i) {
+      double co = om[i] / delta;
+      for (int k = 0; k < 3; ++k) J[3 * i + k] = co * u[k];
+    }
+    double A = s->w[v[0]] * dot3(J, J);
+    A = A + s->w[v[1]] * dot3(J + 3, J + 3);
+    *c0 = d / delta - 1.0;
+    *inv_a = A > 0.0 ? 1.0 / A : 0.0;
+    return *inv_a > 0.0 ? 1 : 2;
+  }
   const double* xs[4] = {x + 3 * v[0], x + 3 * v[1], x + 3 * v[2], x + 3 * v[3]};
   double om[4], d2, bw[3], st[2];
   int volume_ok;
@@ -494,7 +536,9 @@ static int64_t grid_lower(const grid_t* g, int64_t cell) {
 }
 
 static int all_static(const orc_scene* s, const int32_t* v) {
-  return s->stat[v[0]] && s->stat[v[1]] && s->stat[v[2]] && s->stat[v[3]];
+  for (int k = 0; k < 4; ++k)
+    if (v[k] >= 0 && !s->stat[v[k]]) return 0;
+  return 1;
 }
 
 typedef struct {
@@ -507,7 +551,8 @@ static void kb_push(keybuf* b, uint64_t k) {
 }
 
 /* The pair universe (Sec. 5: two non-adjacent simplices): vertex-triangle (a,f)
- * with a not a corner of f, edge-edge (e,g) with e<g sharing no vertex. */
+ * with a not a corner of f, edge-edge (e,g) with e<g sharing no vertex, and
+ * vertex-vertex (a,b) with a<b, both particles. */
 static int vt_ok(const orc_scene* s, int32_t a, int32_t f) {
   const int32_t* t = s->tris + 3 * f;
   return a != t[0] && a != t[1] && a != t[2];
@@ -666,6 +711,9 @@ int64_t orc_search(orc_scene* s, const double* x, double dmax, int brute, uint64
       for (int32_t g = e + 1; g < s->ne; ++g)
         if (ee_ok(s, e, g))
           test_pair(s, x, KEY_EE | ((uint64_t)e << 32) | (uint32_t)g, dmax2, &kb);
+    for (int32_t i = 0; i < s->np; ++i)
+      for (int32_t j = i + 1; j < s->np; ++j)
+        test_pair(s, x, KEY_VV | ((uint64_t)s->part[i] << 32) | (uint32_t)s->part[j], dmax2, &kb);
   } else {
     int64_t dim[3];
     double glo[3], h;
@@ -714,6 +762,23 @@ int64_t orc_search(orc_scene* s, const double* x, double dmax, int brute, uint64
       free(seen);
       free(g.ent);
     }
+    if (s->np > 1) {
+      /* particles: each particle's cell against the particles whose box, widened
+       * by dmax, covers it; the pair is taken once, from its lower vertex */
+      grid_t g;
+      grid_build(&g, x, s->part, 1, s->np, dmax, glo, h, dim);
+      for (int32_t i = 0; i < s->np; ++i) {
+        const int32_t a = s->part[i];
+        int64_t c0[3], c1[3];
+        cell_range(&g, x + 3 * a, x + 3 * a, c0, c1);
+        int64_t cell = cell_of(&g, c0[0], c0[1], c0[2]);
+        for (int64_t k = grid_lower(&g, cell); k < g.n && g.ent[k].cell == cell; ++k) {
+          const int32_t b = s->part[g.ent[k].prim];
+          if (a < b) test_pair(s, x, KEY_VV | ((uint64_t)a << 32) | (uint32_t)b, dmax2, &kb);
+        }
+      }
+      free(g.ent);
+    }
   }
   if (out && kb.n <= cap) qsort(out, (size_t)kb.n, sizeof(uint64_t), cmp_u64);
   return kb.n;
@@ -731,6 +796,33 @@ int64_t orc_search(orc_scene* s, const double* x, double dmax, int brute, uint64
  * Returns 1 on a hit and stores the earliest such t. */
 static double cubic_at(const double* a, double t) { return ((a[3] * t + a[2]) * t + a[1]) * t + a[0]; }
 
+/* Vertex-vertex: the closest approach of two points moving linearly, at
+ * t* = clamp(-(p.dp)/(dp.dp), 0, 1) with p = q_a - q_b, dp = dq_a - dq_b (t* = 0
+ * when the points move together); contact when their distance there is <= eta. */
+static int ccd_hit_vv(const double* q, const double* dq, double eta, double* t_hit) {
+  double p[3], dp[3];
+  sub3(p, q, q + 3);
+  sub3(dp, dq, dq + 3);
+  double dd = dot3(dp, dp);
+  double t = 0.0;
+  if (dd > 0.0) {
+    t = -dot3(p, dp) / dd;
+    if (t < 0.0) t = 0.0;
+    if (t > 1.0) t = 1.0;
+  }
+  double a[3], b[3], e[3];
+  for (int m = 0; m < 3; ++m) {
+    a[m] = q[m] + t * dq[m];
+    b[m] = q[3 + m] + t * dq[3 + m];
+  }
+  sub3(e, a, b);
+  if (dot3(e, e) <= eta * eta) {
+    if (t_hit) *t_hit = t;
+    return 1;
+  }
+  return 0;
+}
+
 static int ccd_probe(const double* q, const double* dq, int ee, double t, double eta2) {
   double p[4][3];
   for (int k = 0; k < 4; ++k)
@@ -740,7 +832,9 @@ static int ccd_probe(const double* q, const double* dq, int ee, double t, double
   return d2 <= eta2;
 }
 
-int orc_ccd_hit(const double* q, const double* dq, int ee, double eta, double* t_hit) {
+int orc_ccd_hit(const double* q, const double* dq, int kind, double eta, double* t_hit) {
+  if (kind == 2) return ccd_hit_vv(q, dq, eta, t_hit);
+  const int ee = kind;
   double e1[3], e2[3], e3[3], f1[3], f2[3], f3[3], c[3], a[4];
   for (int m = 0; m < 3; ++m) {
     e1[m] = q[3 + m] - q[m];
@@ -915,6 +1009,14 @@ orc_scene* orc_create(int32_t n, const double* w, const int32_t* tris, int32_t n
   s->edges = (int32_t*)malloc((size_t)(ne > 0 ? ne : 1) * 2 * sizeof(int32_t));
   if (ne) memcpy(s->edges, edges, (size_t)ne * 2 * sizeof(int32_t));
   s->stat = (uint8_t*)calloc(N, 1);
+  /* particles: vertices no triangle or edge refers to */
+  for (int32_t f = 0; f < 3 * nt; ++f) s->stat[tris[f]] = 1;
+  for (int32_t e = 0; e < 2 * ne; ++e) s->stat[edges[e]] = 1;
+  s->part = (int32_t*)malloc(N * sizeof(int32_t));
+  s->np = 0;
+  for (int32_t i = 0; i < n; ++i)
+    if (!s->stat[i]) s->part[s->np++] = i;
+  memset(s->stat, 0, N);
   s->x = (double*)malloc(N * 3 * sizeof(double));
   s->y = (double*)malloc(N * 3 * sizeof(double));
   s->xt = (double*)malloc(N * 3 * sizeof(double));
@@ -930,9 +1032,14 @@ orc_scene* orc_create(int32_t n, const double* w, const int32_t* tris, int32_t n
   return s;
 }
 
+int32_t orc_particles(const orc_scene* s, int32_t* ids) {
+  if (ids) memcpy(ids, s->part, (size_t)s->np * sizeof(int32_t));
+  return s->np;
+}
+
 void orc_destroy(orc_scene* s) {
   if (!s) return;
-  free(s->w); free(s->tris); free(s->edges); free(s->stat);
+  free(s->w); free(s->tris); free(s->edges); free(s->part); free(s->stat);
   free(s->x); free(s->y); free(s->xt); free(s->xold); free(s->r);
   free(s->Di); free(s->move2); free(s->P); free(s->A); free(s->acol);
   free(s->er_e); free(s->er_v); free(s->er_g); free(s->er_inv); free(s->er_col);
@@ -1046,6 +1153,7 @@ static int backward_jacobi(orc_scene* s, int64_t na, orc_iter* it) {
       double wr = rc0[q];
       for (int k = 0; k < 4; ++k) {
         const int32_t vv = rv[4 * q + k];
+        if (vv < 0) continue;
         double dy[3];
         sub3(dy, s->y + 3 * vv, s->x + 3 * vv);
         wr = wr + dot3(J + 3 * k, dy);
@@ -1056,7 +1164,7 @@ static int backward_jacobi(orc_scene* s, int64_t na, orc_iter* it) {
       lam[q] = ln;
       for (int k = 0; k < 4; ++k) {
         const int32_t vv = rv[4 * q + k];
-        if (!(s->w[vv] > 0.0)) continue;
+        if (vv < 0 || !(s->w[vv] > 0.0)) continue;
         double co = s->w[vv] * dl;
         for (int m = 0; m < 3; ++m) bad |= jac_add(acc + 3 * vv + m, co * J[3 * k + m]);
       }
@@ -1119,7 +1227,7 @@ int orc_iterate(orc_scene* s, orc_iter* info) {
     s->P[npf++] = key;
     double d = sqrt(d2);
     for (int k = 0; k < 4; ++k)
-      if (d < s->Di[v[k]]) s->Di[v[k]] = d;
+      if (v[k] >= 0 && d < s->Di[v[k]]) s->Di[v[k]] = d;
     if (d2 < dl2) s->A[na++] = key;
   }
   s->nP = npf;
@@ -1157,6 +1265,7 @@ int orc_iterate(orc_scene* s, orc_iter* info) {
         double wr = rc0[q];
         for (int k = 0; k < 4; ++k) {
           const int32_t vv = rv[4 * q + k];
+          if (vv < 0) continue;
           double dy[3];
           sub3(dy, s->y + 3 * vv, s->x + 3 * vv);
           wr = wr + dot3(J + 3 * k, dy);
@@ -1167,7 +1276,7 @@ int orc_iterate(orc_scene* s, orc_iter* info) {
         lam[q] = ln;
         for (int k = 0; k < 4; ++k) {
           const int32_t vv = rv[4 * q + k];
-          if (!(s->w[vv] > 0.0)) continue;
+          if (vv < 0 || !(s->w[vv] > 0.0)) continue;
           double co = s->w[vv] * dl;
           for (int m = 0; m < 3; ++m) s->y[3 * vv + m] = s->y[3 * vv + m] + co * J[3 * k + m];
         }
@@ -1242,19 +1351,21 @@ int orc_iterate(orc_scene* s, orc_iter* info) {
   for (int64_t q = 0; q < npf; ++q) {
     int32_t v[4];
     pair_verts(s, s->P[q], v);
+    const int nv = (s->P[q] & KEY_VV) ? 2 : 4;
     double mv = s->move2[v[0]];
-    for (int k = 1; k < 4; ++k)
+    for (int k = 1; k < nv; ++k)
       if (s->move2[v[k]] > mv) mv = s->move2[v[k]];
     if (!(4.0 * mv < dpf[q])) {
       /* not certified by the motion bound: continuous test of the piece */
       ++fail;
       double qq[12], dq[12];
-      for (int k = 0; k < 4; ++k)
+      for (int k = 0; k < nv; ++k)
         for (int m = 0; m < 3; ++m) {
           qq[3 * k + m] = s->xold[3 * v[k] + m];
           dq[3 * k + m] = s->x[3 * v[k] + m] - s->xold[3 * v[k] + m];
         }
-      if (orc_ccd_hit(qq, dq, (s->P[q] & KEY_EE) ? 1 : 0, ORC_CCD_ETA, NULL)) ++hits;
+      const int kind = (s->P[q] & KEY_VV) ? 2 : ((s->P[q] & KEY_EE) ? 1 : 0);
+      if (orc_ccd_hit(qq, dq, kind, ORC_CCD_ETA, NULL)) ++hits;
     }
   }
   it.ccd_fail = fail;

@@ -86,7 +86,9 @@ double orc_pt_tri_d2(const double* p, const double* a, const double* b,
                      const double* c, double* bary);
 double orc_seg_seg_d2(const double* a, const double* b, const double* c,
                       const double* e, double* st);
-/* Contact row at state x for pair key: vertex ids v[4], c0, J[12], invA.
+/* Pair keys: vertex-triangle a << 32 | f; edge-edge 1 << 63 | e << 32 | g (e < g);
+ * vertex-vertex 1 << 62 | a << 32 | b (a < b, both particles). Ids below 2^30. */
+/* Contact row at state x for pair key: vertex ids v[4] (-1 = none), c0, J[12], invA.
  * Returns 0 for the volume form, 1 for the gap fallback, 2 if inactive. */
 int orc_contact_row(const orc_scene* s, const double* x, uint64_t key,
                     int32_t* v, double* c0, double* J, double* inv_a);
@@ -99,9 +101,13 @@ int64_t orc_search(orc_scene* s, const double* x, double dmax, int brute,
 int32_t orc_color_rows(const orc_scene* s, int64_t nrows, const int32_t* rv,
                        const uint64_t* keys, int32_t* colors);
 uint64_t orc_mix64(uint64_t z);
-/* Continuous test of a pair along q_k + t dq_k, t in [0,1] (q, dq: 4 points in the
- * contact-row order). Returns 1 when the primitives come within eta. */
-int orc_ccd_hit(const double* q, const double* dq, int ee, double eta, double* t_hit);
+/* Continuous test of a pair along q_k + t dq_k, t in [0,1] (q, dq: the points in
+ * the contact-row order). kind 0: vertex-triangle (4 points), 1: edge-edge (4),
+ * 2: vertex-vertex (2). Returns 1 when the primitives come within eta. */
+int orc_ccd_hit(const double* q, const double* dq, int kind, double eta, double* t_hit);
+/* Number of particles (vertices in no triangle and no edge: the vertex-vertex
+ * pair universe) and their ids, increasing (ids may be NULL). */
+int32_t orc_particles(const orc_scene* s, int32_t* ids);
 /* Segment pq against triangle abc: 1 when they cross or touch (FP64 orientations;
  * values within 1e-12 of their absolute products count as touching; a segment in
  * the triangle's plane decides by its distance <= tol). */

@@ -344,9 +344,45 @@ def hair(n_strands: int = 10000, segs: int = 32, seg_len: float = 0.005,
                 params=dict(max_iters=2048, delta=1e-3))
 
 
+def sand_pile(nx: int = 32, ny: int = 32, nz: int = 30, spacing: float = 2e-3,
+              jitter: float = 2e-4, h: float = 0.01, fall: float = 1.0, vstd: float = 0.5,
+              seed: int = 1006, ground: int = 9):
+    """A column of nx*ny*nz particles (vertices in no triangle or edge) on a jittered
+    lattice `spacing` apart, its lowest layer one spacing above a static ground grid
+    (ground x ground vertices, w = 0, x~ = x, 12 spacings beyond the column on every
+    side). Particles: w = 1, x~ = x + h(v + g h) with v = (0, 0, -fall) +
+    N(0, vstd^2) per component; the relative motion is several spacings per step, so
+    grains collide with each other and with the ground."""
+    rng = np.random.default_rng(seed)
+    ii, jj, kk = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    p = np.stack([ii, jj, kk], axis=-1).reshape(-1, 3).astype(np.float64) * spacing
+    p[:, 0] -= 0.5 * (nx - 1) * spacing
+    p[:, 1] -= 0.5 * (ny - 1) * spacing
+    p[:, 2] += spacing
+    p += rng.uniform(-jitter, jitter, size=p.shape)
+    ng = ground
+    gs = (max(nx, ny) + 24) * spacing / (ng - 1)
+    xg, tg, eg = grid_cloth(ng, ng, gs)
+    xg[:, 0] -= 0.5 * (ng - 1) * gs
+    xg[:, 1] -= 0.5 * (ng - 1) * gs
+    np_ = len(p)
+    x = np.concatenate([p, xg])
+    tris = (tg + np_).astype(np.int32)
+    edges = (eg + np_).astype(np.int32)
+    v = rng.normal(0.0, vstd, size=(np_, 3))
+    v[:, 2] -= fall
+    xt = x.copy()
+    xt[:np_] = p + h * (v + GRAVITY * h)
+    w = np.zeros(len(x))
+    w[:np_] = 1.0
+    return dict(name=f"sand_{nx}x{ny}x{nz}", x=x, xt=xt, w=w, tris=tris, edges=edges,
+                params=dict(max_iters=2048))
+
+
 def config(i: int, small: bool = False):
-    """The four single-scene workloads, full size or a small variant of the same
-    structure (the small variants finish in seconds on the oracle)."""
+    """The single-scene workloads (1-4, and 6: the particle pile), full size or a
+    small variant of the same structure (the small variants finish in seconds on the
+    oracle)."""
     if i == 1:
         return cloth_over_sphere(n=17 if small else 33)
     if i == 2:
@@ -355,6 +391,8 @@ def config(i: int, small: bool = False):
         return stacked_cubes(n_cubes=2 if small else 8, cells=4 if small else 16)
     if i == 4:
         return hair(n_strands=64 if small else 10000, segs=8 if small else 32)
+    if i == 6:
+        return sand_pile(*((6, 6, 5) if small else (32, 32, 30)))
     raise ValueError(i)
 
 

@@ -232,7 +232,26 @@ def _universe_keys(n, tris, edges):
         for g in range(e + 1, len(edges)):
             if not set(edges[e]) & set(edges[g]):
                 keys.add(oracle.ee_key(e, g))
+    # vertex-vertex: two vertices that no triangle and no edge refer to
+    used = set(int(v) for t in tris for v in t) | set(int(v) for e in edges for v in e)
+    part = [a for a in range(n) if a not in used]
+    for i, a in enumerate(part):
+        for b in part[i + 1:]:
+            keys.add(oracle.vv_key(a, b))
     return keys
+
+
+def _pair_exact(k, X, tris, edges):
+    """Vertices of pair key k and its squared distance at X in exact arithmetic."""
+    a, f = (k >> 32) & 0x3FFFFFFF, k & 0xFFFFFFFF
+    if k >> 63:
+        v = [*edges[a], *edges[f]]
+        return v, exact.seg_seg_d2(*(X[i] for i in v))
+    if (k >> 62) & 1:
+        v = [a, f]
+        return v, sum((Fr(float(X[a, c])) - Fr(float(X[f, c]))) ** 2 for c in range(3))
+    v = [a, *tris[f]]
+    return v, exact.pt_tri_d2(*(X[i] for i in v))
 
 
 def test_search_grid_equals_brute_force_and_exact_threshold():
@@ -395,10 +414,7 @@ def _safety_run(x, xt, tris, edges, w, iters, **kw):
         # P' contains every pair below D^(l) (Sec. 3.1 reuse bound)
         Pf = set(int(k) for k in s.P())
         for k in U:
-            ee = k >> 63
-            a, f = (k >> 32) & 0x7FFFFFFF, k & 0xFFFFFFFF
-            v = [*edges[a], *edges[f]] if ee else [a, *tris[f]]
-            d2 = (exact.seg_seg_d2 if ee else exact.pt_tri_d2)(*(X0[i] for i in v))
+            v, d2 = _pair_exact(k, X0, tris, edges)
             D = Fr(it["d_before"])
             if d2 < D * D * Fr(1 - 1e-12):
                 assert k in Pf
@@ -633,3 +649,115 @@ def test_validate_scenes():
     xn[4, 2] = -0.1  # now below the triangle: free
     s.begin(xn, xn)
     assert s.validate(xn, tol) == 0
+
+
+# ------------------------------------------------- vertex-vertex pairs (sand)
+
+def test_vv_search_grid_equals_brute_force_and_exact_threshold():
+    """Particles (vertices in no triangle or edge) pair with each other only; the
+    grid search equals the all-pairs loop and a threshold decided in exact
+    arithmetic over a universe built here."""
+    rng = np.random.default_rng(11)
+    xp = rng.uniform(0.0, 0.012, size=(60, 3))
+    xm, tm, em = scenes.grid_cloth(3, 3, 4e-3)
+    x = np.vstack([xp, xm + [0.002, 0.002, 0.006]])
+    tris, edges = tm + len(xp), em + len(xp)
+    s = oracle.Scene(np.ones(len(x)), tris, edges)
+    assert np.array_equal(s.particles(), np.arange(len(xp)))
+    U = _universe_keys(len(x), tris.tolist(), edges.tolist())
+    for dmax in (2e-3, 4e-3):
+        g = set(int(k) for k in s.search(x, dmax))
+        assert g == set(int(k) for k in s.search(x, dmax, brute=True))
+        want = set(k for k in U if _pair_exact(k, x, tris, edges)[1] < Fr(dmax) ** 2)
+        assert g == want
+        vv = [k for k in g if (k >> 62) & 1 and not k >> 63]
+        assert vv and all(((k >> 32) & 0x3FFFFFFF) < (k & 0xFFFFFFFF) < len(xp) for k in vv)
+
+
+def test_vv_row_closed_form_and_gradient():
+    """c = |x_a - x_b|/delta - 1 (Sec. 4.1) at x: c0, J = grad c by central
+    differences, A = (w_a + w_b)/delta^2 (|u| = 1)."""
+    rng = np.random.default_rng(12)
+    for _ in range(5):
+        x = rng.normal(size=(2, 3)) * 4e-4
+        w = rng.uniform(0.5, 2.0, size=2)
+        s = _scene(2, w=w)
+        k = oracle.vv_key(0, 1)
+        r = s.contact_row(x, k)
+        assert r["kind"] == 1 and list(r["v"]) == [0, 1, -1, -1]
+        d = np.linalg.norm(x[0] - x[1])
+        assert rel_close(r["c0"], d / DELTA - 1)
+        f = lambda y: np.linalg.norm(y[0] - y[1]) / DELTA - 1  # noqa: E731
+        g = _fd_grad(f, x, [0, 1], h=1e-10)
+        assert np.allclose(r["J"][:2], g[:2], rtol=1e-5, atol=1e-3)
+        assert np.array_equal(r["J"][2:], np.zeros((2, 3)))
+        assert rel_close(1.0 / r["inv_a"], (w[0] + w[1]) / DELTA ** 2, rtol=1e-12)
+    # coincident particles carry no row
+    assert _scene(2).contact_row(np.zeros((2, 3)), oracle.vv_key(0, 1))["kind"] == 2
+
+
+def test_particle_through_static_particle_settles_at_delta():
+    """A particle driven straight through a static one stops at distance delta on
+    its own side (the renewed linearisation's fixed point), like the vertex and the
+    static triangle."""
+    x = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 0.005]])
+    xt = x.copy()
+    xt[1, 2] = -0.005
+    s = oracle.Scene(np.array([0.0, 1.0]), np.zeros((0, 3), np.int32),
+                     np.zeros((0, 2), np.int32), max_iters=200)
+    out, n, tr = s.run(x, xt, trace_cap=200)
+    assert abs(out[1, 2] - DELTA) < 1e-15
+    assert out[1, 0] == 0.0 and out[1, 1] == 0.0
+    assert np.array_equal(out[0], x[0])
+    assert tr[-1]["r_inf"] < 1e-4
+
+
+def _vv_min_dist2_exact(q, dq):
+    """Exact minimum over t in [0,1] of |(q0 - q1) + t (dq0 - dq1)|^2."""
+    p = [Fr(float(q[0, c])) - Fr(float(q[1, c])) for c in range(3)]
+    d = [Fr(float(dq[0, c])) - Fr(float(dq[1, c])) for c in range(3)]
+    dd = sum(v * v for v in d)
+    t = Fr(0) if dd == 0 else min(max(-sum(a * b for a, b in zip(p, d)) / dd, Fr(0)), Fr(1))
+    return sum((a + t * b) ** 2 for a, b in zip(p, d)), t
+
+
+def test_ccd_vv_closest_approach():
+    """The vertex-vertex continuous test against the exact closest approach: head-on
+    crossings hit at the meeting time, passes 2 eta apart miss, eta/2 apart hit."""
+    rng = np.random.default_rng(13)
+    eta = 1e-12
+    for _ in range(20):
+        R = _rand_frame(rng)
+        c = rng.normal(size=3) * 1e-2
+        t0 = rng.uniform(0.1, 0.9)
+        for off, want in ((0.0, True), (2 * eta, False), (0.5 * eta, True), (1e-9, False)):
+            a0 = c + R @ np.array([-1e-3, off, 0.0])
+            b0 = c + R @ np.array([1e-3, 0.0, 0.0])
+            va = R @ np.array([1e-3 / t0, 0.0, 0.0])
+            q = np.stack([a0, b0])
+            dq = np.stack([va, -va])
+            d2, t = _vv_min_dist2_exact(q, dq)
+            hit, th = oracle.ccd_hit(q, dq, 2, eta)
+            if abs(float(d2) - eta * eta) > 1e-3 * eta * eta:
+                assert hit == (d2 <= Fr(eta) ** 2) == want
+            if hit:
+                assert abs(th - float(t)) < 1e-9
+    # parallel motion: t = 0
+    q = np.array([[0.0, 0, 0], [1e-3, 0, 0]])
+    assert oracle.ccd_hit(q, np.ones((2, 3)), 2)[0] is False
+
+
+def test_sand_pile_is_resolved_safely():
+    """A small particle pile falling on a static ground: every iteration keeps the
+    lemma of Sec. 5 and the reuse bound in exact arithmetic, and the end state has
+    no two particles coincident and every particle above the ground."""
+    sc = scenes.sand_pile(3, 3, 3, ground=3)
+    x, xt, w, tris, edges = sc["x"], sc["xt"], sc["w"], sc["tris"], sc["edges"]
+    traj, s = _safety_run(x, xt, tris, edges, w, iters=80)
+    assert len(traj) <= 80  # the stop test held before the cap
+    xf = traj[-1]
+    n = 27
+    for a in range(n):
+        for b in range(a + 1, n):
+            assert _pair_exact(oracle.vv_key(a, b), xf, tris, edges)[1] > 0
+        assert xf[a, 2] > 0
