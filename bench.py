@@ -27,6 +27,15 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_folded_cloth_257.json")
 
 
+WORKLOADS = {
+    1: "cloth over a static sphere, random velocities, ",
+    2: "self-contact folded cloth, 4 layers, Perlin target, ",
+    3: "8 stacked cube surfaces, rigid velocities, ",
+    4: "hair strands on a sphere, wind impulse, ",
+    6: "particle pile on a static ground: vertex-vertex and vertex-triangle pairs, ",
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,7 +144,7 @@ def main():
     bytes_per_launch = kd["bytes"] / max(kd["launches"], 1)
     achieved = bytes_per_launch / avg_s / 1e9
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
+    if args.config == 2 and not args.small and os.path.exists(TRAFFIC_FILE):
         try:
             tj = json.load(open(TRAFFIC_FILE))
             kname = {"pair": "k_pair_pass", "search": "k_traverse", "forward": "k_forward",
@@ -178,9 +187,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64+f32" if args.mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": sc["name"] + " (self-contact folded cloth, 4 layers, "
-                               "Perlin target, " + ("FP32 backward step, FP64 sets, x and "
-                                                     "CCD" if args.mixed else "FP64") +
+        "config": {"workload": sc["name"] + " (" + WORKLOADS.get(args.config, "") +
+                               ("FP32 backward step, FP64 sets, x and CCD" if args.mixed
+                                else "FP64") +
                                (", projected Jacobi backward step" if args.jacobi else "") + ")",
                    "verts": int(len(sc["x"])), "tris": int(len(sc["tris"])),
                    "edges": int(len(sc["edges"])), "iterations_per_step": iters,

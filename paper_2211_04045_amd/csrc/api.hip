@@ -155,7 +155,8 @@ int alloc_active(cc_solver* s, int64_t cap) {
 
 void free_vertex_arrays(cc_solver* s) {
   dfree(s->w); dfree(s->stat); dfree(s->x); dfree(s->y); dfree(s->xt); dfree(s->xold);
-  dfree(s->r); dfree(s->move2); dfree(s->Di); dfree(s->vseg); dfree(s->dy); dfree(s->jacc);
+  dfree(s->r); dfree(s->move2); dfree(s->Di); dfree(s->vseg); dfree(s->plist); dfree(s->dy);
+  dfree(s->jacc);
   dfree(s->vmax0); dfree(s->vmax1); dfree(s->masks);
 }
 void free_edge_arrays(cc_solver* s) {
@@ -194,6 +195,8 @@ void solver_free(cc_solver* s) {
 // reallocated empty.
 int resize_arrays(cc_solver* s, int32_t capV, int32_t capF, int32_t capE, hipStream_t st) {
   const int64_t oV = s->capV, oF = s->capF, oE = s->capE;
+  // pair keys hold primitive ids in 30 bits
+  if (capV > kMaxIds || capF > kMaxIds || capE > kMaxIds) return CC_ENOMEM;
   if (capV != oV) {
     CC_TRY(dregrow(&s->w, capV, oV, st));
     CC_TRY(dregrow(&s->stat, capV, oV, st));
@@ -207,6 +210,7 @@ int resize_arrays(cc_solver* s, int32_t capV, int32_t capF, int32_t capE, hipStr
     CC_HIP(hipMemsetAsync(s->jacc, 0, sizeof(long long) * 3 * (size_t)capV, st));
     CC_TRY(dregrow(&s->vseg, capV, oV, st));
     CC_TRY(launch_fill_i32(s->vseg + oV, capV - oV, -1, st));
+    CC_TRY(dregrow(&s->plist, capV, oV, st));
     dfree(s->xold); dfree(s->move2); dfree(s->Di); dfree(s->vmax0); dfree(s->vmax1); dfree(s->masks);
     CC_TRY(dalloc(&s->xold, 3 * (int64_t)capV));
     CC_TRY(dalloc(&s->move2, capV));
@@ -396,6 +400,18 @@ int seg_add(cc_solver* s, int32_t nv, const double* inv_mass, const int32_t* tri
     if (rc == CC_OK) rc = launch_fill_i32(s->vseg + vb, nv, sg, st);
   }
   if (rc == CC_OK) rc = launch_topo_in(s, sg, tris, edges, st);
+  if (rc == CC_OK) rc = launch_particles(s, sg, st);
+  if (rc == CC_OK) {
+    // the search arrays hold every live segment's particles
+    int64_t np = 0;
+    for (const Seg& o : s->segs)
+      if (o.live) np += o.np;
+    if (np > s->capPt) {
+      s->capPt = (int32_t)std::min<int64_t>(std::max<int64_t>(np, 2 * (int64_t)s->capPt), kMaxIds);
+      bvh_free(s);
+      rc = bvh_alloc(s);
+    }
+  }
   SegDev& d = s->seg_host[sg];
   memset(&d, 0, sizeof d);
   d.vb = vb;

@@ -135,11 +135,14 @@ __device__ __forceinline__ double seg_seg_d2(V3 a, V3 b, V3 c, V3 e, double& bs,
   return best;
 }
 
-// Pair keys: bit 63 = edge-edge; bits 62..32 = first primitive (vertex or
-// edge), bits 31..0 = second primitive (triangle or edge).
+// Pair keys: bit 63 = edge-edge, bit 62 = vertex-vertex; bits 61..32 = first
+// primitive (vertex or edge), bits 31..0 = second primitive (triangle, edge or
+// vertex). Primitive ids are below 2^30.
 constexpr uint64_t KEY_EE = 1ull << 63;
+constexpr uint64_t KEY_VV = 1ull << 62;
 __device__ __forceinline__ bool key_is_ee(uint64_t k) { return (k & KEY_EE) != 0; }
-__device__ __forceinline__ uint32_t key_a(uint64_t k) { return (uint32_t)((k >> 32) & 0x7fffffffu); }
+__device__ __forceinline__ bool key_is_vv(uint64_t k) { return (k & KEY_VV) != 0; }
+__device__ __forceinline__ uint32_t key_a(uint64_t k) { return (uint32_t)((k >> 32) & 0x3fffffffu); }
 __device__ __forceinline__ uint32_t key_b(uint64_t k) { return (uint32_t)(k & 0xffffffffu); }
 
 struct Topo {
@@ -147,9 +150,17 @@ struct Topo {
   const int32_t* __restrict__ edges;
 };
 
+// The pair's four vertices; a vertex-vertex pair (a, b) lists (a, b, a, b), so
+// that loads, minima and maxima over the four need no special case (sums and
+// updates take the first two only).
 __device__ __forceinline__ void pair_verts(const Topo& T, uint64_t k, int32_t v[4]) {
   uint32_t a = key_a(k), b = key_b(k);
-  if (key_is_ee(k)) {
+  if (key_is_vv(k)) {
+    v[0] = (int32_t)a;
+    v[1] = (int32_t)b;
+    v[2] = (int32_t)a;
+    v[3] = (int32_t)b;
+  } else if (key_is_ee(k)) {
     v[0] = T.edges[2 * a];
     v[1] = T.edges[2 * a + 1];
     v[2] = T.edges[2 * b];
@@ -162,8 +173,12 @@ __device__ __forceinline__ void pair_verts(const Topo& T, uint64_t k, int32_t v[
   }
 }
 
-__device__ __forceinline__ double pair_d2(bool ee, V3 p0, V3 p1, V3 p2, V3 p3) {
-  if (ee) {
+__device__ __forceinline__ double pair_d2(uint64_t key, V3 p0, V3 p1, V3 p2, V3 p3) {
+  if (key_is_vv(key)) {
+    const V3 d = vsub(p0, p1);
+    return vdot(d, d);
+  }
+  if (key_is_ee(key)) {
     double s, t;
     return seg_seg_d2(p0, p1, p2, p3, s, t);
   }
@@ -273,6 +288,27 @@ __device__ __forceinline__ void contact_row(bool ee, const V3 xs[4], const doubl
   R.inv_a = A > 0.0 ? 1.0 / A : 0.0;
 }
 
+// Vertex-vertex row (Sec. 4.1): c = |x_a - x_b|/delta - 1 at x, J_a = u/delta,
+// J_b = -u/delta with u the unit vector from b to a; slots 2 and 3 carry zero.
+// Coincident points give no row.
+__device__ __forceinline__ void contact_row_vv(const V3 xs[4], const double w[4], double delta,
+                                               Row& R) {
+  R.inv_a = 0.0;
+  const V3 diff = vsub(xs[0], xs[1]);
+  const double d = sqrt(vdot(diff, diff));
+  R.J[2] = V3{0.0, 0.0, 0.0};
+  R.J[3] = V3{0.0, 0.0, 0.0};
+  if (d == 0.0) return;
+  const V3 u = V3{diff.x / d, diff.y / d, diff.z / d};
+  const double c0 = 1.0 / delta, c1 = -1.0 / delta;
+  R.J[0] = V3{c0 * u.x, c0 * u.y, c0 * u.z};
+  R.J[1] = V3{c1 * u.x, c1 * u.y, c1 * u.z};
+  double A = w[0] * vdot(R.J[0], R.J[0]);
+  A = A + w[1] * vdot(R.J[1], R.J[1]);
+  R.c0 = d / delta - 1.0;
+  R.inv_a = A > 0.0 ? 1.0 / A : 0.0;
+}
+
 // Continuous test of one pair along the linear piece q_k(t) = q_k + t dq_k,
 // t in [0,1] (points in the contact-row order). Coplanarity V(t) =
 // det[q1-q0, q2-q0, q3-q0](t) is the cubic a3 t^3 + a2 t^2 + a1 t + a0; its
@@ -287,7 +323,7 @@ __device__ __forceinline__ bool ccd_probe(const V3 q[4], const V3 dq[4], bool ee
                                           double eta2) {
   V3 p0 = vaxpy(q[0], t, dq[0]), p1 = vaxpy(q[1], t, dq[1]);
   V3 p2 = vaxpy(q[2], t, dq[2]), p3 = vaxpy(q[3], t, dq[3]);
-  return pair_d2(ee, p0, p1, p2, p3) <= eta2;
+  return pair_d2(ee ? KEY_EE : 0ull, p0, p1, p2, p3) <= eta2;
 }
 
 __device__ __noinline__ bool ccd_hit(const V3 q[4], const V3 dq[4], bool ee, double eta2) {
@@ -379,6 +415,22 @@ __device__ __forceinline__ bool seg_tri_meet(V3 p, V3 q, V3 a, V3 b, V3 c, doubl
   if (sp * sq > 0) return false;
   const int s1 = orient_band(p, q, a, b), s2 = orient_band(p, q, b, c), s3 = orient_band(p, q, c, a);
   return (s1 >= 0 && s2 >= 0 && s3 >= 0) || (s1 <= 0 && s2 <= 0 && s3 <= 0);
+}
+
+// Vertex-vertex continuous test: the closest approach of two linearly moving
+// points, at t = clamp(-(p.dp)/(dp.dp), 0, 1) with p = qa - qb, dp = dqa - dqb
+// (t = 0 when they move together); contact when their distance there is <= eta.
+__device__ __forceinline__ bool ccd_hit_vv(V3 qa, V3 qb, V3 dqa, V3 dqb, double eta2) {
+  const V3 p = vsub(qa, qb), dp = vsub(dqa, dqb);
+  const double dd = vdot(dp, dp);
+  double t = 0.0;
+  if (dd > 0.0) {
+    t = -vdot(p, dp) / dd;
+    if (t < 0.0) t = 0.0;
+    if (t > 1.0) t = 1.0;
+  }
+  const V3 e = vsub(vaxpy(qa, t, dqa), vaxpy(qb, t, dqb));
+  return vdot(e, e) <= eta2;
 }
 
 // splitmix64 output function (Steele, Lea, Flood 2014); a bijection on 64 bits.

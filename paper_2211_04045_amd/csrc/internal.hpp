@@ -29,6 +29,7 @@ constexpr int kMaxRounds = 65536;  // Jones-Plassmann rounds per colouring
 constexpr double kCcdEta = 1e-12;  // distance at which the continuous test reports contact (m)
 constexpr int kMaxSeg = 1024;      // scenes (segments) resident in one solver
 constexpr int kSegBits = 10;       // bits of a segment's rank in a search's sort keys
+constexpr int32_t kMaxIds = 1 << 30;  // primitive ids of pair keys are 30-bit
 constexpr double kFreeTol = 1e-9;  // input check: closest allowed distance (m)
 
 // Per-segment record on the device (one scene of a multi-scene solver). The host
@@ -112,6 +113,7 @@ namespace cc {
 // vertex, triangle and edge arrays (topology stored with solver-wide vertex ids).
 struct Seg {
   int32_t vb = 0, nv = 0, fb = 0, nf = 0, eb = 0, ne = 0;
+  int32_t np = 0;  // particles (vertices in no triangle or edge), listed at plist[vb, vb+np)
   int32_t max_iters = 0;
   double D = 0.0;
   bool live = false;     // holds a scene
@@ -124,10 +126,10 @@ struct Seg {
 };
 
 // One selected segment of a proximity search: its bases and the offsets of its
-// vertices, triangles and edges in the search's compact arrays.
+// vertices, triangles, edges and particles in the search's compact arrays.
 struct SelDev {
   int32_t vb, fb, eb, seg;
-  int32_t voff, toff, eoff, pad;
+  int32_t voff, toff, eoff, poff;
 };
 
 // First-fit allocator of index ranges.
@@ -147,6 +149,7 @@ struct cc_solver {
   // used extents (one past the highest index any segment holds) and capacities
   int32_t n = 0, nt = 0, ne = 0;
   int32_t capV = 0, capF = 0, capE = 0;
+  int32_t capPt = 0;  // particle capacity of the search arrays (grows on demand)
   cc_params p{};
   double kappa2 = 0.0;
   bool begun = false;  // single-scene interface: segment 0 begun
@@ -161,6 +164,7 @@ struct cc_solver {
   std::vector<int32_t> pending_segs;
   int32_t* vseg = nullptr;  // segment of each vertex (-1 = none)
   int32_t* eseg = nullptr;  // segment of each edge (-1 = none)
+  int32_t* plist = nullptr; // per segment, at its vertex base: its particles' vertex ids
   bool erows_dirty = true;  // the union of edge-row colour buckets needs a rebuild
   // topology and masses
   double* w = nullptr;
@@ -204,7 +208,7 @@ struct cc_solver {
   int32_t* col_cnt = nullptr;  // kMaxColors + 1
   int32_t *coff_dev = nullptr, *ecoff_dev = nullptr;  // colour bucket offsets on the device
   // broad phase
-  cc::Bvh tree_t, tree_e;
+  cc::Bvh tree_t, tree_e, tree_p;  // triangles, edges, particles
   uint64_t *sk0 = nullptr, *sk1 = nullptr;
   uint32_t *sv0 = nullptr, *sv1 = nullptr;
   uint32_t* rs_hist = nullptr;
@@ -217,10 +221,12 @@ struct cc_solver {
   int32_t* vorder = nullptr;   // vertex queries in Morton order (vertex ids)
   int16_t* vrank = nullptr;    // selected-segment rank of each vertex query
   int16_t* erank = nullptr;    // selected-segment rank of each sorted edge leaf
+  int16_t* prank = nullptr;    // ... of each sorted particle leaf
   cc::SelDev* sel_dev = nullptr;   // kMaxSeg + 1
   cc::SelDev* sel_host = nullptr;  // pinned
   int32_t* root_t = nullptr;       // per selected segment: root of its triangle subtree
   int32_t* root_e = nullptr;       // ... of its edge subtree
+  int32_t* root_p = nullptr;       // ... of its particle subtree
   // counters
   cc::Counters* dc = nullptr;
   cc::Counters* hc = nullptr;  // pinned host mirror
@@ -256,6 +262,7 @@ int launch_topo_in(cc_solver* s, int32_t seg, const int32_t* tris, const int32_t
 int launch_check_finite(cc_solver* s, const double* xa, const double* xb, int32_t n,
                         hipStream_t st);
 int launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
+int launch_particles(cc_solver* s, int32_t sg, hipStream_t st);
 int launch_setup(cc_solver* s, int32_t seg, const double* x_prev, const double* x_tilde,
                  hipStream_t st);
 int launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t st);

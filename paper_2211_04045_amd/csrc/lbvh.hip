@@ -49,9 +49,9 @@ __device__ __forceinline__ float hi_out(double v) {
 }
 
 // Rank r of the selected segment holding compact index g of one kind
-// (0 vertices, 1 triangles, 2 edges): off(r) <= g < off(r + 1).
+// (0 vertices, 1 triangles, 2 edges, 3 particles): off(r) <= g < off(r + 1).
 __device__ __forceinline__ int32_t sel_off(const SelDev& d, int kind) {
-  return kind == 0 ? d.voff : (kind == 1 ? d.toff : d.eoff);
+  return kind == 0 ? d.voff : (kind == 1 ? d.toff : (kind == 2 ? d.eoff : d.poff));
 }
 __device__ __forceinline__ int32_t find_sel(const SelDev* __restrict__ sel, int32_t nsel,
                                             int kind, int32_t g) {
@@ -64,19 +64,21 @@ __device__ __forceinline__ int32_t find_sel(const SelDev* __restrict__ sel, int3
   return lo;
 }
 
-// Leaf boxes of the selected segments' triangles (compact 0..mt) then edges
-// (mt..mt+me), their primitive ids, and per-block bounds of the box centres
-// (order-preserving uint encoding), reduced by k_bounds_reduce.
+// Leaf boxes of the selected segments' triangles (compact 0..mt), edges
+// (mt..mt+me) and particles (mt+me..mt+me+mp), their primitive ids (particles:
+// vertex ids), and per-block bounds of the box centres (order-preserving uint
+// encoding), reduced by k_bounds_reduce.
 __global__ void k_boxes(const double* __restrict__ x, const int32_t* __restrict__ tris,
-                        const int32_t* __restrict__ edges, const SelDev* __restrict__ sel,
-                        int32_t nsel, int32_t mt, int32_t me, double infl,
-                        float4* __restrict__ blo, float4* __restrict__ bhi,
-                        int32_t* __restrict__ gprim, uint32_t* __restrict__ part) {
+                        const int32_t* __restrict__ edges, const int32_t* __restrict__ plist,
+                        const SelDev* __restrict__ sel, int32_t nsel, int32_t mt, int32_t me,
+                        int32_t mp, double infl, float4* __restrict__ blo,
+                        float4* __restrict__ bhi, int32_t* __restrict__ gprim,
+                        uint32_t* __restrict__ part) {
   __shared__ uint32_t sb[6];
   if (threadIdx.x < 6) sb[threadIdx.x] = (threadIdx.x < 3) ? 0xffffffffu : 0u;
   __syncthreads();
   int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < mt + me) {
+  if (g < mt + me + mp) {
     V3 lo, hi;
     if (g < mt) {
       const int32_t r = find_sel(sel, nsel, 1, g);
@@ -85,7 +87,7 @@ __global__ void k_boxes(const double* __restrict__ x, const int32_t* __restrict_
       V3 a = ld3(x, tris[3 * f]), b = ld3(x, tris[3 * f + 1]), c = ld3(x, tris[3 * f + 2]);
       lo = V3{fmin(fmin(a.x, b.x), c.x), fmin(fmin(a.y, b.y), c.y), fmin(fmin(a.z, b.z), c.z)};
       hi = V3{fmax(fmax(a.x, b.x), c.x), fmax(fmax(a.y, b.y), c.y), fmax(fmax(a.z, b.z), c.z)};
-    } else {
+    } else if (g < mt + me) {
       const int32_t ge = g - mt;
       const int32_t r = find_sel(sel, nsel, 2, ge);
       const int32_t e = sel[r].eb + (ge - sel[r].eoff);
@@ -93,6 +95,13 @@ __global__ void k_boxes(const double* __restrict__ x, const int32_t* __restrict_
       V3 a = ld3(x, edges[2 * e]), b = ld3(x, edges[2 * e + 1]);
       lo = V3{fmin(a.x, b.x), fmin(a.y, b.y), fmin(a.z, b.z)};
       hi = V3{fmax(a.x, b.x), fmax(a.y, b.y), fmax(a.z, b.z)};
+    } else {
+      const int32_t gp = g - mt - me;
+      const int32_t r = find_sel(sel, nsel, 3, gp);
+      const int32_t v = plist[sel[r].vb + (gp - sel[r].poff)];
+      gprim[g] = v;
+      lo = ld3(x, v);
+      hi = lo;
     }
     float4 l = make_float4(lo_out(lo.x - infl), lo_out(lo.y - infl), lo_out(lo.z - infl), 0.f);
     float4 h = make_float4(hi_out(hi.x + infl), hi_out(hi.y + infl), hi_out(hi.z + infl), 0.f);
@@ -137,33 +146,36 @@ __device__ __forceinline__ uint32_t spread10(uint32_t v) {
 }
 
 // Sort keys: 30-bit Morton code of the triangle boxes (group 0), edge boxes
-// (group 1) and vertices (group 2, the order of the vertex queries), the
-// selected segment's rank in the rb bits above it and the group above that.
+// (group 1), particle boxes (group 2) and vertices (group 3, the order of the
+// vertex queries), the selected segment's rank in the rb bits above it and the
+// group above that.
 __global__ void k_morton(const float4* __restrict__ blo, const float4* __restrict__ bhi,
                          const double* __restrict__ x, const SelDev* __restrict__ sel,
-                         int32_t nsel, int32_t mt, int32_t me, int32_t mv, int rb,
+                         int32_t nsel, int32_t mt, int32_t me, int32_t mp, int32_t mv, int rb,
                          const uint32_t* __restrict__ bounds, uint64_t* __restrict__ keys,
                          uint32_t* __restrict__ vals) {
   int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= mt + me + mv) return;
+  const int32_t m = mt + me + mp;
+  if (g >= m + mv) return;
   float c[3];
   uint64_t grp;
   int32_t r;
-  if (g < mt + me) {
+  if (g < m) {
     float4 l = blo[g], h = bhi[g];
     c[0] = 0.5f * (l.x + h.x);
     c[1] = 0.5f * (l.y + h.y);
     c[2] = 0.5f * (l.z + h.z);
-    grp = g < mt ? 0u : 1u;
-    r = g < mt ? find_sel(sel, nsel, 1, g) : find_sel(sel, nsel, 2, g - mt);
+    grp = g < mt ? 0u : (g < mt + me ? 1u : 2u);
+    r = g < mt ? find_sel(sel, nsel, 1, g)
+               : (g < mt + me ? find_sel(sel, nsel, 2, g - mt) : find_sel(sel, nsel, 3, g - mt - me));
   } else {
-    const int32_t gv = g - mt - me;
+    const int32_t gv = g - m;
     r = find_sel(sel, nsel, 0, gv);
     V3 p = ld3(x, sel[r].vb + (gv - sel[r].voff));
     c[0] = (float)p.x;
     c[1] = (float)p.y;
     c[2] = (float)p.z;
-    grp = 2u;
+    grp = 3u;
   }
   uint32_t q[3];
   for (int k = 0; k < 3; ++k) {
@@ -354,25 +366,39 @@ __global__ void k_karras(TreeView ta, TreeView tb) {
   else if (g < na + nb) karras_node(tb, g - na);
 }
 
-// Sorted leaf boxes and primitive ids of both trees; the vertex queries in
-// Morton order with their segment ranks; the segment rank of each edge leaf.
+struct LeafOut {
+  float4 *lo, *hi;
+  int32_t* prim;
+  int16_t* rank;
+};
+
+// Sorted leaf boxes and primitive ids of the three trees; the vertex queries in
+// Morton order with their segment ranks; the segment rank of each edge and
+// particle leaf.
 __global__ void k_leaves(const uint32_t* __restrict__ sval, const uint64_t* __restrict__ skey,
                          const float4* __restrict__ blo, const float4* __restrict__ bhi,
                          const int32_t* __restrict__ gprim, const SelDev* __restrict__ sel,
-                         int32_t mt, int32_t me, int32_t mv, uint32_t rmask,
+                         int32_t mt, int32_t me, int32_t mp, int32_t mv, uint32_t rmask,
                          float4* __restrict__ tlo, float4* __restrict__ thi,
                          int32_t* __restrict__ tprim, float4* __restrict__ elo,
                          float4* __restrict__ ehi, int32_t* __restrict__ eprim,
-                         int16_t* __restrict__ erank, int32_t* __restrict__ vorder,
+                         int16_t* __restrict__ erank, LeafOut po, int32_t* __restrict__ vorder,
                          int16_t* __restrict__ vrank) {
   int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= mt + me + mv) return;
+  const int32_t m = mt + me + mp;
+  if (g >= m + mv) return;
   const uint32_t p = sval[g];
   const int32_t r = (int32_t)((uint32_t)(skey[g] >> 30) & rmask);
-  if (g >= mt + me) {
-    const int32_t q = g - mt - me, gv = (int32_t)p - mt - me;
+  if (g >= m) {
+    const int32_t q = g - m, gv = (int32_t)p - m;
     vorder[q] = sel[r].vb + (gv - sel[r].voff);
     vrank[q] = (int16_t)r;
+  } else if (g >= mt + me) {
+    const int32_t i = g - mt - me;
+    po.lo[i] = blo[p];
+    po.hi[i] = bhi[p];
+    po.prim[i] = gprim[p];
+    po.rank[i] = (int16_t)r;
   } else if (g < mt) {
     tlo[g] = blo[p];
     thi[g] = bhi[p];
@@ -404,14 +430,16 @@ __device__ __forceinline__ int32_t seg_root(int32_t lo, int32_t cnt, int32_t n,
 }
 
 __global__ void k_seg_roots(const SelDev* __restrict__ sel, int32_t nsel, int32_t mt,
-                            int32_t me, const int2* __restrict__ trange,
+                            int32_t me, int32_t mp, const int2* __restrict__ trange,
                             const int32_t* __restrict__ tprim, const int2* __restrict__ erange,
-                            const int32_t* __restrict__ eprim, int32_t* __restrict__ root_t,
-                            int32_t* __restrict__ root_e) {
+                            const int32_t* __restrict__ eprim, const int2* __restrict__ prange,
+                            const int32_t* __restrict__ pprim, int32_t* __restrict__ root_t,
+                            int32_t* __restrict__ root_e, int32_t* __restrict__ root_p) {
   int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nsel) return;
   root_t[r] = seg_root(sel[r].toff, sel[r + 1].toff - sel[r].toff, mt, trange, tprim);
   root_e[r] = seg_root(sel[r].eoff, sel[r + 1].eoff - sel[r].eoff, me, erange, eprim);
+  root_p[r] = seg_root(sel[r].poff, sel[r + 1].poff - sel[r].poff, mp, prange, pprim);
 }
 
 struct Box6 {
@@ -650,7 +678,7 @@ __global__ void k_wide(const float4* __restrict__ node, float4* __restrict__ wid
 }
 
 struct TravArgs {
-  TravTree tt, te;
+  TravTree tt, te, tp;
   const double* x;
   const int32_t* tris;
   const int32_t* edges;
@@ -658,9 +686,11 @@ struct TravArgs {
   const int32_t* vorder;  // vertex queries in Morton order
   const int16_t* vrank;   // their selected-segment ranks
   const int16_t* erank;   // selected-segment rank of each sorted edge leaf
+  const int16_t* prank;   // ... of each sorted particle leaf
   const int32_t* root_t;  // per rank: subtree root in the triangle tree
   const int32_t* root_e;  // ... in the edge tree
-  int32_t mv, me;         // vertex queries, edge queries
+  const int32_t* root_p;  // ... in the particle tree
+  int32_t mv, me, mp;     // vertex, edge and particle queries
   double infl, dmax2;
   uint64_t* out;
   double* outd;  // d^2 of each pair found (same function and operand order as the pair pass)
@@ -694,17 +724,29 @@ __device__ __forceinline__ void wave_flush(uint64_t* skey, double* sd2, int& cnt
   cnt = 0;
 }
 
+// Query classes of the traversal: vertex against the triangle tree, edge against
+// the edge tree, particle against the particle tree.
+constexpr int kQVT = 0, kQEE = 1, kQVV = 2;
+
 // Exact test of one candidate primitive against the query: non-adjacent, not
 // all static, FP64 distance below D_max. On success *out is the pair's key
-// (vertex-triangle: vertex << 32 | triangle; edge-edge: canonical, lower edge
-// first, with the distance taken in that order; 0 is a valid key).
-__device__ __forceinline__ bool candidate(const TravArgs& A, bool is_vt, int32_t prim,
+// (vertex-triangle: vertex << 32 | triangle; edge-edge and vertex-vertex:
+// canonical, lower id first, with the distance taken in that order; 0 is a valid
+// key).
+__device__ __forceinline__ bool candidate(const TravArgs& A, int kind, int32_t prim,
                                           int32_t qid, int32_t qv0, int32_t qv1, V3 qx0, V3 qx1,
                                           uint64_t* out, double* out_d2) {
   // (out and out_d2 point at the lane's next LDS buffer slot; written on success)
   double d2;
   uint64_t key;
-  if (is_vt) {
+  if (kind == kQVV) {
+    if (A.stat[qv0] && A.stat[prim]) return false;
+    const V3 xb = ld3(A.x, prim);
+    const V3 d = qid < prim ? vsub(qx0, xb) : vsub(xb, qx0);
+    d2 = vdot(d, d);
+    key = qid < prim ? (KEY_VV | ((uint64_t)(uint32_t)qid << 32) | (uint32_t)prim)
+                     : (KEY_VV | ((uint64_t)(uint32_t)prim << 32) | (uint32_t)qid);
+  } else if (kind == kQVT) {
     int32_t v1 = A.tris[3 * prim], v2 = A.tris[3 * prim + 1], v3 = A.tris[3 * prim + 2];
     if (qv0 == v1 || qv0 == v2 || qv0 == v3 ||
         (A.stat[qv0] && A.stat[v1] && A.stat[v2] && A.stat[v3]))
@@ -736,9 +778,10 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
   __shared__ uint64_t skey[kTravThreads * kBuf];
   __shared__ double sd2[kTravThreads * kBuf];
   int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool is_vt = q < A.mv;
-  const bool active = q < A.mv + A.me;
-  const TravTree T = is_vt ? A.tt : A.te;
+  const int kind = q < A.mv ? kQVT : (q < A.mv + A.me ? kQEE : kQVV);
+  const bool is_vt = kind == kQVT;
+  const bool active = q < A.mv + A.me + A.mp;
+  const TravTree T = is_vt ? A.tt : (kind == kQEE ? A.te : A.tp);
   float4 qlo = make_float4(0.f, 0.f, 0.f, 0.f), qhi = qlo;
   int32_t qv0 = 0, qv1 = 0, qid = 0, qpos = -1;
   V3 qx0{0, 0, 0}, qx1{0, 0, 0};
@@ -750,6 +793,14 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
     if (is_vt) {
       qid = A.vorder[q];
       root = A.root_t[A.vrank[q]];
+      qv0 = qid;
+      qx0 = ld3(A.x, qid);
+      qlo = make_float4(lo_out(qx0.x - A.infl), lo_out(qx0.y - A.infl), lo_out(qx0.z - A.infl), 0.f);
+      qhi = make_float4(hi_out(qx0.x + A.infl), hi_out(qx0.y + A.infl), hi_out(qx0.z + A.infl), 0.f);
+    } else if (kind == kQVV) {
+      qpos = q - A.mv - A.me;  // sorted position of the query particle in its tree
+      qid = T.leaf_prim[qpos];
+      root = A.root_p[A.prank[qpos]];
       qv0 = qid;
       qx0 = ld3(A.x, qid);
       qlo = make_float4(lo_out(qx0.x - A.infl), lo_out(qx0.y - A.infl), lo_out(qx0.z - A.infl), 0.f);
@@ -771,7 +822,7 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
       stack[sp++] = root;
     } else if (root != -1 && is_vt) {
       // a segment with one triangle: the leaf itself (one edge pairs with nothing)
-      if (candidate(A, true, root & 0x7fffffff, qid, qv0, qv1, qx0, qx1,
+      if (candidate(A, kQVT, root & 0x7fffffff, qid, qv0, qv1, qx0, qx1,
                     &skey[threadIdx.x * kBuf + cnt], &sd2[threadIdx.x * kBuf + cnt]))
         ++cnt;
     }
@@ -791,7 +842,7 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
           else atomicOr(&A.cnt->err, 2ull);
           continue;
         }
-        if (candidate(A, is_vt, c & 0x7fffffff, qid, qv0, qv1, qx0, qx1,
+        if (candidate(A, kind, c & 0x7fffffff, qid, qv0, qv1, qx0, qx1,
                       &skey[threadIdx.x * kBuf + cnt], &sd2[threadIdx.x * kBuf + cnt]))
           ++cnt;
       }
@@ -910,10 +961,13 @@ static void bvh_free_one(Bvh& b) {
 }
 
 int bvh_alloc(cc_solver* s) {
-  const int64_t m = (int64_t)s->capF + s->capE;
-  const int64_t mall = m + s->capV;  // triangles, edges and vertices share one sort
+  const int64_t m = (int64_t)s->capF + s->capE + s->capPt;
+  const int64_t mall = m + s->capV;  // triangles, edges, particles and vertices share one sort
   CC_TRY(bvh_alloc_one(s->tree_t, s->capF));
   CC_TRY(bvh_alloc_one(s->tree_e, s->capE));
+  CC_TRY(bvh_alloc_one(s->tree_p, s->capPt));
+  CC_TRY(dalloc(&s->prank, s->capPt));
+  CC_TRY(dalloc(&s->root_p, kMaxSeg));
   CC_TRY(dalloc(&s->sk0, mall));
   CC_TRY(dalloc(&s->sk1, mall));
   CC_TRY(dalloc(&s->sv0, mall));
@@ -943,6 +997,8 @@ int bvh_alloc(cc_solver* s) {
 void bvh_free(cc_solver* s) {
   bvh_free_one(s->tree_t);
   bvh_free_one(s->tree_e);
+  bvh_free_one(s->tree_p);
+  dfree(s->prank); dfree(s->root_p);
   dfree(s->sk0); dfree(s->sk1); dfree(s->sv0); dfree(s->sv1);
   dfree(s->ubox_lo); dfree(s->ubox_hi); dfree(s->gprim); dfree(s->rs_hist); dfree(s->bounds);
   dfree(s->bounds_part); dfree(s->vorder); dfree(s->vrank); dfree(s->erank); dfree(s->rs_total);
@@ -958,8 +1014,8 @@ static RefitView refit_view(Bvh& b) {
 
 int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64_t* out,
                 double* outd, int64_t cap, int64_t* nfound, hipStream_t st) {
-  // compact offsets of the selected segments' vertices, triangles and edges
-  int32_t mv = 0, mt = 0, me = 0;
+  // compact offsets of the selected segments' vertices, triangles, edges and particles
+  int32_t mv = 0, mt = 0, me = 0, mp = 0;
   for (int32_t r = 0; r < nsel; ++r) {
     SelDev& d = s->sel_host[r];
     const Seg& g = s->segs[d.seg];
@@ -969,28 +1025,31 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
     d.voff = mv;
     d.toff = mt;
     d.eoff = me;
+    d.poff = mp;
     mv += g.nv;
     mt += g.nf;
     me += g.ne;
+    mp += g.np;
   }
-  s->sel_host[nsel] = SelDev{0, 0, 0, -1, mv, mt, me, 0};
+  s->sel_host[nsel] = SelDev{0, 0, 0, -1, mv, mt, me, mp};
+  if (mp > s->capPt) return CC_EINVAL;  // the particle capacity follows seg_add
   int rb = 0;
   while ((1 << rb) < nsel) ++rb;
   const double infl = 0.5 * dmax;
   CC_HIP(hipMemsetAsync(&s->dc->n_out, 0, sizeof(unsigned long long), st));
   CC_HIP(hipMemsetAsync(&s->dc->err, 0, sizeof(unsigned long long), st));
   *nfound = 0;
-  const int64_t m = (int64_t)mt + me;
+  const int64_t m = (int64_t)mt + me + mp;
   if (m > 0) {
     CC_HIP(hipMemcpyAsync(s->sel_dev, s->sel_host, sizeof(SelDev) * (nsel + 1),
                           hipMemcpyHostToDevice, st));
     const int64_t mall = m + mv;
     const unsigned nbx = blocks(m, 256);
-    k_boxes<<<nbx, 256, 0, st>>>(x, s->tris, s->edges, s->sel_dev, nsel, mt, me, infl,
-                                 s->ubox_lo, s->ubox_hi, s->gprim, s->bounds_part);
+    k_boxes<<<nbx, 256, 0, st>>>(x, s->tris, s->edges, s->plist, s->sel_dev, nsel, mt, me, mp,
+                                 infl, s->ubox_lo, s->ubox_hi, s->gprim, s->bounds_part);
     k_bounds_reduce<<<1, 256, 0, st>>>(s->bounds_part, (int32_t)nbx, s->bounds);
     k_morton<<<blocks(mall, 256), 256, 0, st>>>(s->ubox_lo, s->ubox_hi, x, s->sel_dev, nsel, mt,
-                                                me, mv, rb, s->bounds, s->sk0, s->sv0);
+                                                me, mp, mv, rb, s->bounds, s->sk0, s->sv0);
     const int32_t nb = (int32_t)((mall + kTile - 1) / kTile);
     uint64_t *ki = s->sk0, *ko = s->sk1;
     uint32_t *vi = s->sv0, *vo = s->sv1;
@@ -1004,21 +1063,28 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
     }
     Bvh& bt = s->tree_t;
     Bvh& be = s->tree_e;
+    Bvh& bp = s->tree_p;
     bt.n = mt;
     be.n = me;
+    bp.n = mp;
     k_leaves<<<blocks(mall, 256), 256, 0, st>>>(vi, ki, s->ubox_lo, s->ubox_hi, s->gprim,
-                                                s->sel_dev, mt, me, mv, (1u << rb) - 1u,
+                                                s->sel_dev, mt, me, mp, mv, (1u << rb) - 1u,
                                                 bt.leaf_lo, bt.leaf_hi, bt.leaf_prim, be.leaf_lo,
-                                                be.leaf_hi, be.leaf_prim, s->erank, s->vorder,
-                                                s->vrank);
+                                                be.leaf_hi, be.leaf_prim, s->erank,
+                                                LeafOut{bp.leaf_lo, bp.leaf_hi, bp.leaf_prim,
+                                                        s->prank},
+                                                s->vorder, s->vrank);
     const uint64_t mask = (1ull << (30 + rb)) - 1ull;
     TreeView ta{mt, ki, mask, bt.leaf_prim, bt.node, bt.parent, bt.range};
     TreeView tb{me, ki + mt, mask, be.leaf_prim, be.node, be.parent, be.range};
+    TreeView tc{mp, ki + mt + me, mask, bp.leaf_prim, bp.node, bp.parent, bp.range};
+    const TreeView tnone{0, nullptr, 0, nullptr, nullptr, nullptr, nullptr};
     int64_t ninternal = (mt > 1 ? mt - 1 : 0) + (me > 1 ? me - 1 : 0);
     if (ninternal > 0) k_karras<<<blocks(ninternal, 256), 256, 0, st>>>(ta, tb);
-    k_seg_roots<<<blocks(nsel, 256), 256, 0, st>>>(s->sel_dev, nsel, mt, me, bt.range,
-                                                   bt.leaf_prim, be.range, be.leaf_prim,
-                                                   s->root_t, s->root_e);
+    if (mp > 1) k_karras<<<blocks(mp - 1, 256), 256, 0, st>>>(tc, tnone);
+    k_seg_roots<<<blocks(nsel, 256), 256, 0, st>>>(s->sel_dev, nsel, mt, me, mp, bt.range,
+                                                   bt.leaf_prim, be.range, be.leaf_prim, bp.range,
+                                                   bp.leaf_prim, s->root_t, s->root_e, s->root_p);
     RefitView ra = refit_view(bt), rbv = refit_view(be);
     if (mt < 2) ra.n = 0;
     if (me < 2) rbv.n = 0;
@@ -1028,11 +1094,21 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
       k_blk_sparse<<<2, 1024, 0, st>>>(ra, rbv);
       k_refit_top<<<blocks(ninternal, 256), 256, 0, st>>>(ra, rbv);
     }
+    if (mp > 1) {  // the particle tree, refit on its own
+      RefitView rc = refit_view(bp), rnone = refit_view(bp);
+      rnone.n = 0;
+      const int32_t nbc = (mp + kBlk - 1) / kBlk;
+      k_refit_block<<<nbc, kBlk, 0, st>>>(rc, rnone, nbc);
+      k_blk_sparse<<<1, 1024, 0, st>>>(rc, rnone);
+      k_refit_top<<<blocks(mp - 1, 256), 256, 0, st>>>(rc, rnone);
+    }
     if (mt > 1) k_wide<<<blocks(mt - 1, 256), 256, 0, st>>>(bt.node, bt.wide, mt - 1);
     if (me > 1) k_wide<<<blocks(me - 1, 256), 256, 0, st>>>(be.node, be.wide, me - 1);
+    if (mp > 1) k_wide<<<blocks(mp - 1, 256), 256, 0, st>>>(bp.node, bp.wide, mp - 1);
     TravArgs A;
     A.tt = TravTree{mt, bt.wide, bt.root, bt.leaf_prim};
     A.te = TravTree{me, be.wide, be.root, be.leaf_prim};
+    A.tp = TravTree{mp, bp.wide, bp.root, bp.leaf_prim};
     A.x = x;
     A.tris = s->tris;
     A.edges = s->edges;
@@ -1040,17 +1116,20 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
     A.vorder = s->vorder;
     A.vrank = s->vrank;
     A.erank = s->erank;
+    A.prank = s->prank;
     A.root_t = s->root_t;
     A.root_e = s->root_e;
+    A.root_p = s->root_p;
     A.mv = mt > 0 ? mv : 0;  // no triangles: no vertex-triangle queries
     A.me = me;
+    A.mp = mp;
     A.infl = infl;
     A.dmax2 = dmax * dmax;
     A.out = out;
     A.outd = outd;
     A.cap = cap;
     A.cnt = s->dc;
-    int64_t nq = (int64_t)A.mv + me;
+    int64_t nq = (int64_t)A.mv + me + mp;
     if (nq > 0) {
       timer_begin(s, CC_K_SEARCH, st);
       k_traverse<<<blocks(nq, kTravThreads), kTravThreads, 0, st>>>(A);
@@ -1063,7 +1142,7 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
   if (s->hc->err & 2ull) return CC_EOVERFLOW;
   *nfound = (int64_t)s->hc->n_out;
   // algorithmic bytes of the traversal: queries, node records, output keys
-  s->st.kernel_bytes[CC_K_SEARCH] += 24.0 * mv + 8.0 * me + 64.0 * (double)m +
+  s->st.kernel_bytes[CC_K_SEARCH] += 24.0 * mv + 8.0 * me + 28.0 * mp + 64.0 * (double)m +
                                      8.0 * (double)*nfound;
   return CC_OK;
 }

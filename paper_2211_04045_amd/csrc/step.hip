@@ -49,10 +49,12 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 
 // Scene-local key of a row, so that colouring priorities do not depend on where
 // a scene sits in the solver's arrays: vertex-triangle (v << 32 | f) and
-// edge-edge (e << 32 | g) pair keys and edge-row keys (e) lose their segment's
-// bases. A scene alone at base 0 keeps its keys.
+// edge-edge (e << 32 | g), vertex-vertex (a << 32 | b) pair keys and edge-row
+// keys (e) lose their segment's bases. A scene alone at base 0 keeps its keys.
 __device__ __forceinline__ uint64_t local_pair_key(uint64_t key, const SegDev& sg) {
-  const uint32_t hi = (uint32_t)(key >> 32) & 0x7fffffffu, lo = (uint32_t)key;
+  const uint32_t hi = key_a(key), lo = (uint32_t)key;
+  if (key_is_vv(key))
+    return KEY_VV | ((uint64_t)(hi - (uint32_t)sg.vb) << 32) | (uint32_t)(lo - (uint32_t)sg.vb);
   if (key_is_ee(key))
     return KEY_EE | ((uint64_t)(hi - (uint32_t)sg.eb) << 32) | (uint32_t)(lo - (uint32_t)sg.eb);
   return ((uint64_t)(hi - (uint32_t)sg.vb) << 32) | (uint32_t)(lo - (uint32_t)sg.fb);
@@ -138,6 +140,44 @@ int launch_check_finite(cc_solver* s, const double* xa, const double* xb, int32_
   CC_HIP(hipMemsetAsync(&s->dc->err, 0, sizeof(unsigned long long), st));
   if (n > 0) k_check_finite<<<nblk(n), kThreads, 0, st>>>(xa, xb, n, s->dc);
   return read_err(s, st);
+}
+
+// Clear the flag of every vertex a triangle or edge of the segment refers to.
+__global__ void k_mark_refs(const int32_t* __restrict__ tris, int64_t n3,
+                            const int32_t* __restrict__ edges, int64_t n2,
+                            uint8_t* __restrict__ flag) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n3) flag[tris[g]] = 0;
+  else if (g < n3 + n2) flag[edges[g - n3]] = 0;
+}
+
+// Particles of segment sg (vertices in no triangle and no edge: the vertex-vertex
+// pair universe), listed in increasing order at plist[vb, vb + np). The static
+// flags of the segment's vertices serve as scratch (begin sets them).
+int launch_particles(cc_solver* s, int32_t sg, hipStream_t st) {
+  Seg& g = s->segs[sg];
+  g.np = 0;
+  if (g.nv == 0) return CC_OK;
+  CC_HIP(hipMemsetAsync(s->stat + g.vb, 1, (size_t)g.nv, st));
+  const int64_t m = 3 * (int64_t)g.nf + 2 * (int64_t)g.ne;
+  if (m > 0)
+    k_mark_refs<<<nblk(m), kThreads, 0, st>>>(s->tris + 3 * (int64_t)g.fb, 3 * (int64_t)g.nf,
+                                               s->edges + 2 * (int64_t)g.eb, 2 * (int64_t)g.ne,
+                                               s->stat);
+  CC_HIP(hipGetLastError());
+  std::vector<uint8_t> flag((size_t)g.nv);
+  CC_HIP(hipMemcpyAsync(flag.data(), s->stat + g.vb, (size_t)g.nv, hipMemcpyDeviceToHost, st));
+  CC_HIP(hipStreamSynchronize(st));
+  std::vector<int32_t> ids;
+  for (int32_t i = 0; i < g.nv; ++i)
+    if (flag[(size_t)i]) ids.push_back(g.vb + i);
+  g.np = (int32_t)ids.size();
+  if (g.np > 0) {
+    CC_HIP(hipMemcpyAsync(s->plist + g.vb, ids.data(), sizeof(int32_t) * ids.size(),
+                          hipMemcpyHostToDevice, st));
+    CC_HIP(hipStreamSynchronize(st));
+  }
+  return CC_OK;
 }
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
@@ -419,7 +459,7 @@ __global__ void __launch_bounds__(kThreads) k_pair_pass(PairPassArgs a) {
       const bool live = (fl & kSegActive) && !(i < a.n_old && (fl & kSegSearched));
       if (live) {
         const double d2 = i < a.d_from
-                              ? pair_d2(key_is_ee(key), px[k][0], px[k][1], px[k][2], px[k][3])
+                              ? pair_d2(key, px[k][0], px[k][1], px[k][2], px[k][3])
                               : a.dPin[i];
         keys[k] = key;
         d2s[k] = d2;
@@ -989,7 +1029,10 @@ __device__ __forceinline__ void gs_contact_update(const GsArgs& a, int32_t r) {
     ws[k] = a.w[v[k]];
   }
   Row R;
-  contact_row(key_is_ee(key), xs, ws, a.delta, a.kappa2, R);
+  const bool vv = key_is_vv(key);
+  const int nk = vv ? 2 : 4;  // a vertex-vertex row has two vertices
+  if (vv) contact_row_vv(xs, ws, a.delta, R);
+  else contact_row(key_is_ee(key), xs, ws, a.delta, a.kappa2, R);
   if (!(R.inv_a > 0.0)) return;
   if (kMixed) {
     F3 J[4];
@@ -998,6 +1041,7 @@ __device__ __forceinline__ void gs_contact_update(const GsArgs& a, int32_t r) {
     float wr = (float)R.c0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
+      if (k >= nk) continue;
       F3 d = ldf3(a.dy, v[k]);
       wr = wr + (J[k].x * d.x + J[k].y * d.y + J[k].z * d.z);
     }
@@ -1008,7 +1052,7 @@ __device__ __forceinline__ void gs_contact_update(const GsArgs& a, int32_t r) {
     a.lamf[r] = ln;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      if (!(ws[k] > 0.0)) continue;
+      if (k >= nk || !(ws[k] > 0.0)) continue;
       const float co = (float)ws[k] * dl;
       F3 d = ldf3(a.dy, v[k]);
       stf3(a.dy, v[k], F3{d.x + co * J[k].x, d.y + co * J[k].y, d.z + co * J[k].z});
@@ -1018,6 +1062,7 @@ __device__ __forceinline__ void gs_contact_update(const GsArgs& a, int32_t r) {
   double wr = R.c0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
+    if (k >= nk) continue;
     V3 dy = vsub(ld3(a.y, v[k]), xs[k]);
     wr = wr + vdot(R.J[k], dy);
   }
@@ -1028,7 +1073,7 @@ __device__ __forceinline__ void gs_contact_update(const GsArgs& a, int32_t r) {
   a.lam[r] = ln;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    if (!(ws[k] > 0.0)) continue;
+    if (k >= nk || !(ws[k] > 0.0)) continue;
     double co = ws[k] * dl;
     V3 yv = ld3(a.y, v[k]);
     yv = V3{yv.x + co * R.J[k].x, yv.y + co * R.J[k].y, yv.z + co * R.J[k].z};
@@ -1200,11 +1245,15 @@ __global__ void __launch_bounds__(kThreads) k_jacobi_contact(GsArgs a, int64_t n
     ws[k] = a.w[v[k]];
   }
   Row R;
-  contact_row(key_is_ee(key), xs, ws, a.delta, a.kappa2, R);
+  const bool vv = key_is_vv(key);
+  const int nk = vv ? 2 : 4;
+  if (vv) contact_row_vv(xs, ws, a.delta, R);
+  else contact_row(key_is_ee(key), xs, ws, a.delta, a.kappa2, R);
   if (!(R.inv_a > 0.0)) return;
   double wr = R.c0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) wr = wr + vdot(R.J[k], vsub(ld3(a.y, v[k]), xs[k]));
+  for (int k = 0; k < 4; ++k)
+    if (k < nk) wr = wr + vdot(R.J[k], vsub(ld3(a.y, v[k]), xs[k]));
   const double lam = a.lam[r];
   double ln = lam - wr * R.inv_a;
   if (ln < 0.0) ln = 0.0;
@@ -1212,7 +1261,7 @@ __global__ void __launch_bounds__(kThreads) k_jacobi_contact(GsArgs a, int64_t n
   a.lam[r] = ln;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    if (!(ws[k] > 0.0)) continue;
+    if (k >= nk || !(ws[k] > 0.0)) continue;
     const double co = ws[k] * dl;
     long long* p = acc + 3 * (int64_t)v[k];
     jac_add(p, co * R.J[k].x, c);
@@ -1420,7 +1469,8 @@ __global__ void __launch_bounds__(kThreads) k_cert(const uint64_t* __restrict__ 
     q[k] = ld3(xold, v[k]);
     dq[k] = vsub(ld3(x, v[k]), q[k]);
   }
-  const bool hit = ccd_hit(q, dq, key_is_ee(key), eta2);
+  const bool hit = key_is_vv(key) ? ccd_hit_vv(q[0], q[1], dq[0], dq[1], eta2)
+                                  : ccd_hit(q, dq, key_is_ee(key), eta2);
   SegDev& sd = seg[vseg[v[0]]];
   atomicAdd(&sd.fail, 1ull);
   if (hit) atomicAdd(&sd.hits, 1ull);

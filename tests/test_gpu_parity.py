@@ -68,7 +68,7 @@ def test_library_loads_on_gpu(cc, ctx):
     assert ctx.h
 
 
-@pytest.mark.parametrize("cfg", [1, 2, 3, 4])
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4, 6])
 def test_search_set_matches_oracle_small(cc, ctx, cfg):
     sc = scenes.config(cfg, small=True)
     ref = oracle.Scene(sc["w"], sc["tris"], sc["edges"])
@@ -93,7 +93,7 @@ def test_search_set_matches_oracle_full_folded_cloth(cc, ctx):
     assert np.array_equal(got, want)
 
 
-@pytest.mark.parametrize("cfg,iters", [(2, 200), (3, 400), (4, 200), (1, 120)])
+@pytest.mark.parametrize("cfg,iters", [(2, 200), (3, 400), (4, 200), (1, 120), (6, 200)])
 def test_end_to_end_lockstep_small(cc, ctx, cfg, iters):
     sc = scenes.config(cfg, small=True)
     _lockstep(cc, ctx, sc, iters)
@@ -342,7 +342,7 @@ def _intersection_free(x, tris, edges):
     return True
 
 
-@pytest.mark.parametrize("cfg,iters", [(2, 60), (3, 120), (4, 60), (1, 60)])
+@pytest.mark.parametrize("cfg,iters", [(2, 60), (3, 120), (4, 60), (1, 60), (6, 60)])
 def test_mixed_precision_lockstep(cc, ctx, cfg, iters):
     """Mixed precision (FP32 backward step): every iteration starts the oracle from
     the GPU's state (x, y, r, D, P'); the sets P', A and the colouring are decided
@@ -392,7 +392,7 @@ def test_mixed_precision_end_to_end(cc, ctx, cfg):
           f"{np.abs(x_mixed - x_ref).max():.3e} m, bbox diagonal {_diag(sc['x']):.3e} m")
 
 
-@pytest.mark.parametrize("cfg,iters", [(2, 200), (3, 300), (4, 150), (1, 100)])
+@pytest.mark.parametrize("cfg,iters", [(2, 200), (3, 300), (4, 150), (1, 100), (6, 200)])
 def test_jacobi_lockstep(cc, ctx, cfg, iters):
     """Projected Jacobi backward step (Sec. 4.3.2): every iteration bit-identical to
     the oracle (sets, fingerprints, x, y, r, D); no colouring."""
@@ -508,3 +508,66 @@ def test_input_check_in_a_batch_rejects_only_the_bad_scene(cc, ctx):
     for sc, (xb, _) in zip(good, res):
         xs, _ = cc.collide_step(ctx, sc["x"], sc["xt"], sc["w"], sc["tris"], sc["edges"])
         assert np.array_equal(xb.cpu().numpy(), xs.cpu().numpy())
+
+
+# --------------------------------------------------- vertex-vertex pairs (sand)
+
+def test_search_set_matches_oracle_full_sand_pile(cc, ctx):
+    """The full particle pile (30,720 particles on a static ground): every
+    vertex-vertex and vertex-triangle pair below D_max, identical to the oracle's."""
+    sc = scenes.config(6)
+    ref = oracle.Scene(sc["w"], sc["tris"], sc["edges"])
+    ref.begin(sc["x"], sc["xt"])
+    gpu = cc.Solver(ctx, sc["w"], sc["tris"], sc["edges"])
+    gpu.begin(sc["x"], sc["xt"])
+    want = np.sort(ref.search(sc["x"], 4e-3))
+    got = _u64(gpu.search(sc["x"], 4e-3))
+    assert (want >> np.uint64(62) == 1).sum() > 100_000  # vertex-vertex keys
+    assert np.array_equal(got, want)
+
+
+def test_full_size_sand_pile_step_matches_oracle(cc, ctx):
+    """One whole step of the full particle pile: iterations and result bit-identical
+    to the oracle; no two particles coincide and none is below the ground."""
+    sc = scenes.config(6)
+    want, n, _ = oracle.collide_step(sc)
+    got, st = cc.collide_step(ctx, sc["x"], sc["xt"], sc["w"], sc["tris"], sc["edges"],
+                              **sc["params"])
+    x = got.cpu().numpy()
+    assert st["iters"] == n and st["status"] == 0 and st["ccd_hits"] == 0
+    assert np.array_equal(x, want)
+    from scipy.spatial import cKDTree
+    npart = int((sc["w"] > 0).sum())
+    d, _ = cKDTree(x[:npart]).query(x[:npart], k=2)
+    assert d[:, 1].min() > 0.5e-3
+    inside = (np.abs(x[:npart, :2]) < 0.055).all(axis=1)
+    assert (x[:npart][inside, 2] > 0).all()
+
+
+def test_batched_particles_and_meshes_equal_solo_and_oracle(cc, ctx):
+    """Particle piles next to meshes in one multi-scene call: particle lists and the
+    particle tree are per scene (no pair across scenes), every result bit-identical
+    to the scene alone and to the oracle."""
+    batch = [scenes.config(6, small=True), scenes.config(2, small=True),
+             scenes.sand_pile(8, 8, 6, seed=77), scenes.config(4, small=True),
+             scenes.sand_pile(5, 4, 3, seed=78)]
+    res = cc.collide_step_batched(ctx, batch, max_iters=300)
+    for sc, (x_b, st_b) in zip(batch, res):
+        x_s, st_s = cc.collide_step(ctx, sc["x"], sc["xt"], sc["w"], sc["tris"], sc["edges"],
+                                    max_iters=300)
+        want, n, _ = oracle.collide_step(sc, max_iters=300)
+        assert np.array_equal(x_b.cpu().numpy(), x_s.cpu().numpy()), sc["name"]
+        assert np.array_equal(x_b.cpu().numpy(), want), sc["name"]
+        assert st_b["iters"] == st_s["iters"] == n
+
+
+def test_mixed_precision_sand_pile_end_to_end(cc, ctx):
+    sc = scenes.config(6, small=True)
+    out, st = cc.collide_step(ctx, sc["x"], sc["xt"], sc["w"], sc["tris"], sc["edges"],
+                              mixed=True, max_iters=400)
+    x = out.cpu().numpy()
+    assert st["ccd_hits"] == 0
+    assert _intersection_free(x, sc["tris"], sc["edges"])
+    npart = int((sc["w"] > 0).sum())
+    d = np.linalg.norm(x[:npart, None] - x[None, :npart], axis=-1)
+    assert d[np.triu_indices(npart, 1)].min() > 0.5e-3
