@@ -29,7 +29,6 @@ namespace cc {
 constexpr int kTile = 4096;      // radix sort tile per block
 constexpr int kRsThreads = 256;
 constexpr int kStack = 100;     // 4-wide DFS: 3 pending entries per level, <= 32 levels
-constexpr int kBuf = 8;          // per-lane pending pairs in the traversal (>= 4 + 4)
 constexpr int kBlk = 256;        // leaves per refit block
 constexpr int32_t kLeaf = (int32_t)0x80000000;
 constexpr int kTravThreads = 256;
@@ -691,6 +690,7 @@ struct TravArgs {
   const int32_t* root_e;  // ... in the edge tree
   const int32_t* root_p;  // ... in the particle tree
   int32_t mv, me, mp;     // vertex, edge and particle queries
+  int32_t mv_pad, me_pad; // the first two counts rounded up to whole waves
   double infl, dmax2;
   uint64_t* out;
   double* outd;  // d^2 of each pair found (same function and operand order as the pair pass)
@@ -703,25 +703,9 @@ __device__ __forceinline__ bool overlap6(float4 ql, float4 qh, float lx, float l
   return ql.x <= hx && lx <= qh.x && ql.y <= hy && ly <= qh.y && ql.z <= hz && lz <= qh.z;
 }
 
-__device__ __forceinline__ void wave_flush(uint64_t* skey, double* sd2, int& cnt,
-                                           const TravArgs& A) {
+__device__ __forceinline__ uint64_t lanes_below_tr() {
   const int lane = __lane_id();
-  int incl = cnt;
-  for (int o = 1; o < 64; o <<= 1) {
-    int v = __shfl_up(incl, o);
-    if (lane >= o) incl += v;
-  }
-  int total = __shfl(incl, 63);
-  unsigned long long base = 0;
-  if (lane == 0 && total > 0) base = atomicAdd(&A.cnt->n_out, (unsigned long long)total);
-  base = __shfl(base, 0);
-  int64_t pos = (int64_t)base + (incl - cnt);
-  for (int i = 0; i < cnt; ++i)
-    if (pos + i < A.cap) {
-      A.out[pos + i] = skey[threadIdx.x * kBuf + i];
-      if (A.outd) A.outd[pos + i] = sd2[threadIdx.x * kBuf + i];
-    }
-  cnt = 0;
+  return lane == 0 ? 0ull : ((~0ull) >> (64 - lane));
 }
 
 // Query classes of the traversal: vertex against the triangle tree, edge against
@@ -774,31 +758,117 @@ __device__ __forceinline__ bool candidate(const TravArgs& A, int kind, int32_t p
   return true;
 }
 
+constexpr int kWaves = kTravThreads / 64;  // waves per traversal block
+constexpr int kGroup = 16;                  // lanes sharing one traversal (a power of 2, <= 64)
+constexpr int kGroups = 64 / kGroup;        // traversals per wave
+constexpr int kGStack = 100;                // stack entries per traversal (4-wide DFS)
+constexpr int kQueue = 128;                 // candidate ring per wave (two rounds of 64)
+constexpr int kOut = 192;                   // found pairs held per wave (flushed from 128)
+
+struct WaveLds {
+  int32_t stack[kWaves][kGroups][kGStack];
+  int32_t qlane[kWaves][kQueue];  // candidate: query lane ...
+  int32_t qprim[kWaves][kQueue];  // ... and leaf primitive
+  double qx[kWaves][6][64];       // query positions per lane
+  int32_t qi[kWaves][3][64];      // query id and its vertices per lane
+  uint64_t okey[kWaves][kOut];    // found pairs not yet written out
+  double od2[kWaves][kOut];
+};
+
+// The wave's held pairs to the output, reserved with one atomic.
+__device__ __forceinline__ void flush_out(WaveLds& L, int wv, int& no, const TravArgs& A) {
+  const int lane = __lane_id();
+  unsigned long long base = 0;
+  if (lane == 0) base = atomicAdd(&A.cnt->n_out, (unsigned long long)no);
+  base = __shfl(base, 0);
+  for (int j = lane; j < no; j += 64) {
+    const int64_t pos = (int64_t)base + j;
+    if (pos < A.cap) {
+      A.out[pos] = L.okey[wv][j];
+      if (A.outd) A.outd[pos] = L.od2[wv][j];
+    }
+  }
+  no = 0;
+  __builtin_amdgcn_wave_barrier();
+}
+
+// The exact test of n <= 64 queued candidates, one per lane; found pairs join the
+// wave's held pairs (no, wave-uniform), written out from 128 on.
+__device__ __forceinline__ void drain(WaveLds& L, int wv, int head, int n, int kind, int& no,
+                                      const TravArgs& A) {
+  const int lane = __lane_id();
+  bool found = false;
+  uint64_t key = 0;
+  double d2 = 0.0;
+  if (lane < n) {
+    const int e = (head + lane) & (kQueue - 1);
+    const int ql = L.qlane[wv][e];
+    const int32_t prim = L.qprim[wv][e];
+    const V3 qx0{L.qx[wv][0][ql], L.qx[wv][1][ql], L.qx[wv][2][ql]};
+    const V3 qx1{L.qx[wv][3][ql], L.qx[wv][4][ql], L.qx[wv][5][ql]};
+    found = candidate(A, kind, prim, L.qi[wv][0][ql], L.qi[wv][1][ql], L.qi[wv][2][ql], qx0, qx1,
+                      &key, &d2);
+  }
+  __builtin_amdgcn_wave_barrier();
+  const uint64_t m = __ballot(found);
+  if (found) {
+    const int j = no + __popcll(m & lanes_below_tr());
+    L.okey[wv][j] = key;
+    L.od2[wv][j] = d2;
+  }
+  no += __popcll(m);
+  __builtin_amdgcn_wave_barrier();
+  if (no >= kOut - 64) flush_out(L, wv, no, A);
+}
+
+// Proximity search (Sec. 3.1). A wave takes 64 consecutive queries of one class
+// (vertices against the triangle tree, edges against the edge tree, particles
+// against the particle tree), in Morton order, and splits them into groups of
+// kGroup lanes. A group walks the union of its lanes' traversals: a node's
+// record is read once for the group, each lane tests the node's four children
+// against its own query box, a child is entered when some lane of the group
+// overlaps it, and the group's stack lives in LDS. A leaf that lanes overlap
+// becomes one candidate per such lane in a ring in LDS shared by the wave; every
+// 64 candidates the whole wave runs the exact FP64 tests together. Each lane sees
+// exactly the leaves its own box overlaps (their ancestors overlap it too), so
+// the pair set is that of independent per-query traversals. Lanes of different
+// scenes in one group walk their own subtrees in turn.
 __global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
-  __shared__ uint64_t skey[kTravThreads * kBuf];
-  __shared__ double sd2[kTravThreads * kBuf];
-  int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-  const int kind = q < A.mv ? kQVT : (q < A.mv + A.me ? kQEE : kQVV);
-  const bool is_vt = kind == kQVT;
-  const bool active = q < A.mv + A.me + A.mp;
-  const TravTree T = is_vt ? A.tt : (kind == kQEE ? A.te : A.tp);
+  __shared__ WaveLds L;
+  const int lane = __lane_id(), wv = threadIdx.x >> 6;
+  const int grp = lane / kGroup, gl = lane % kGroup;
+  const uint64_t gmask = (kGroup == 64 ? ~0ull : ((1ull << kGroup) - 1ull)) << (grp * kGroup);
+  const int32_t q0 = blockIdx.x * kTravThreads + wv * 64;  // the wave's first padded query
+  int kind;
+  int32_t idx, ncl;
+  if (q0 < A.mv_pad) {
+    kind = kQVT;
+    idx = q0 + lane;
+    ncl = A.mv;
+  } else if (q0 < A.mv_pad + A.me_pad) {
+    kind = kQEE;
+    idx = q0 - A.mv_pad + lane;
+    ncl = A.me;
+  } else {
+    kind = kQVV;
+    idx = q0 - A.mv_pad - A.me_pad + lane;
+    ncl = A.mp;
+  }
+  const bool active = idx < ncl;
+  const TravTree T = kind == kQVT ? A.tt : (kind == kQEE ? A.te : A.tp);
   float4 qlo = make_float4(0.f, 0.f, 0.f, 0.f), qhi = qlo;
-  int32_t qv0 = 0, qv1 = 0, qid = 0, qpos = -1;
+  int32_t qv0 = 0, qv1 = 0, qid = 0, qpos = -1, root = -1;
   V3 qx0{0, 0, 0}, qx1{0, 0, 0};
-  int32_t stack[kStack];
-  int sp = 0;
-  int cnt = 0;
   if (active) {
-    int32_t root;
-    if (is_vt) {
-      qid = A.vorder[q];
-      root = A.root_t[A.vrank[q]];
+    if (kind == kQVT) {
+      qid = A.vorder[idx];
+      root = A.root_t[A.vrank[idx]];
       qv0 = qid;
       qx0 = ld3(A.x, qid);
       qlo = make_float4(lo_out(qx0.x - A.infl), lo_out(qx0.y - A.infl), lo_out(qx0.z - A.infl), 0.f);
       qhi = make_float4(hi_out(qx0.x + A.infl), hi_out(qx0.y + A.infl), hi_out(qx0.z + A.infl), 0.f);
     } else if (kind == kQVV) {
-      qpos = q - A.mv - A.me;  // sorted position of the query particle in its tree
+      qpos = idx;  // sorted position of the query particle in its tree
       qid = T.leaf_prim[qpos];
       root = A.root_p[A.prank[qpos]];
       qv0 = qid;
@@ -806,7 +876,7 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
       qlo = make_float4(lo_out(qx0.x - A.infl), lo_out(qx0.y - A.infl), lo_out(qx0.z - A.infl), 0.f);
       qhi = make_float4(hi_out(qx0.x + A.infl), hi_out(qx0.y + A.infl), hi_out(qx0.z + A.infl), 0.f);
     } else {
-      qpos = q - A.mv;  // sorted position of the query edge in the edge tree
+      qpos = idx;  // sorted position of the query edge in the edge tree
       qid = T.leaf_prim[qpos];
       root = A.root_e[A.erank[qpos]];
       qv0 = A.edges[2 * qid];
@@ -818,38 +888,110 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
       qhi = make_float4(hi_out(fmax(qx0.x, qx1.x) + A.infl), hi_out(fmax(qx0.y, qx1.y) + A.infl),
                         hi_out(fmax(qx0.z, qx1.z) + A.infl), 0.f);
     }
-    if (root >= 0) {
-      stack[sp++] = root;
-    } else if (root != -1 && is_vt) {
-      // a segment with one triangle: the leaf itself (one edge pairs with nothing)
-      if (candidate(A, kQVT, root & 0x7fffffff, qid, qv0, qv1, qx0, qx1,
-                    &skey[threadIdx.x * kBuf + cnt], &sd2[threadIdx.x * kBuf + cnt]))
-        ++cnt;
-    }
   }
-  while (__any(sp > 0)) {
-    if (sp > 0) {
-      const int32_t i = stack[--sp];
-      const float4* rec = T.wide + 8 * i;
-#pragma unroll
-      for (int slot = 0; slot < 4; ++slot) {
-        const float4 b0 = rec[2 * slot], b1 = rec[2 * slot + 1];
-        if (!overlap6(qlo, qhi, b0.x, b0.y, b0.z, b0.w, b1.x, b1.y)) continue;
-        if (__float_as_int(b1.w) <= qpos) continue;
-        const int32_t c = __float_as_int(b1.z);
-        if (c >= 0) {
-          if (sp < kStack) stack[sp++] = c;
-          else atomicOr(&A.cnt->err, 2ull);
-          continue;
-        }
-        if (candidate(A, kind, c & 0x7fffffff, qid, qv0, qv1, qx0, qx1,
-                      &skey[threadIdx.x * kBuf + cnt], &sd2[threadIdx.x * kBuf + cnt]))
-          ++cnt;
+  L.qx[wv][0][lane] = qx0.x;
+  L.qx[wv][1][lane] = qx0.y;
+  L.qx[wv][2][lane] = qx0.z;
+  L.qx[wv][3][lane] = qx1.x;
+  L.qx[wv][4][lane] = qx1.y;
+  L.qx[wv][5][lane] = qx1.z;
+  L.qi[wv][0][lane] = qid;
+  L.qi[wv][1][lane] = qv0;
+  L.qi[wv][2][lane] = qv1;
+  int head = 0, qn = 0;  // candidate ring: first entry, entries queued (wave-uniform)
+  int no = 0;            // found pairs held (wave-uniform)
+  // a scene with one triangle: its vertices meet the leaf itself (one edge or one
+  // particle pairs with nothing)
+  {
+    const bool single = active && kind == kQVT && root < -1;
+    const uint64_t m = __ballot(single);
+    if (single) {
+      const int e = __popcll(m & lanes_below_tr());
+      L.qlane[wv][e] = lane;
+      L.qprim[wv][e] = root & 0x7fffffff;
+    }
+    qn = __popcll(m);
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (qn == 64) {
+    drain(L, wv, head, 64, kind, no, A);
+    qn = 0;
+    __builtin_amdgcn_wave_barrier();
+  }
+  bool todo = active && root >= 0;  // this lane's subtree still to walk
+  bool part = false;                // this lane takes part in its group's current walk
+  int sp = 0;                       // the group's stack depth (uniform in the group)
+  for (;;) {
+    // a group with an empty stack starts the next scene's subtree among its lanes
+    const uint64_t tm = __ballot(todo) & gmask;
+    if (sp == 0) {
+      part = false;
+      if (tm) {
+        const int32_t r = __shfl(root, __ffsll((long long)tm) - 1);
+        part = todo && root == r;
+        todo = todo && !part;
+        if (gl == 0) L.stack[wv][grp][0] = r;
+        sp = 1;
       }
     }
-    if (__any(cnt > kBuf - 4)) wave_flush(skey, sd2, cnt, A);
+    if (!__any(sp > 0)) break;
+    __builtin_amdgcn_wave_barrier();
+    const bool valid = sp > 0;
+    int32_t i = 0;
+    if (valid) {
+      --sp;
+      i = L.stack[wv][grp][sp];
+    }
+    float4 rb0[4], rb1[4];
+#pragma unroll
+    for (int slot = 0; slot < 4; ++slot) {
+      rb0[slot] = make_float4(0.f, 0.f, 0.f, 0.f);
+      rb1[slot] = rb0[slot];
+    }
+    if (valid) {
+      const float4* rec = T.wide + 8 * (int64_t)i;
+#pragma unroll
+      for (int slot = 0; slot < 4; ++slot) {
+        rb0[slot] = rec[2 * slot];
+        rb1[slot] = rec[2 * slot + 1];
+      }
+    }
+#pragma unroll
+    for (int slot = 0; slot < 4; ++slot) {
+      const float4 b0 = rb0[slot], b1 = rb1[slot];
+      const bool ov = valid && part && overlap6(qlo, qhi, b0.x, b0.y, b0.z, b0.w, b1.x, b1.y) &&
+                      __float_as_int(b1.w) > qpos;
+      const uint64_t m = __ballot(ov);
+      const int32_t c = __float_as_int(b1.z);
+      // internal child: the group enters it
+      if ((m & gmask) && c >= 0) {
+        if (sp < kGStack) {
+          if (gl == 0) L.stack[wv][grp][sp] = c;
+          ++sp;
+        } else if (gl == 0) {
+          atomicOr(&A.cnt->err, 2ull);
+        }
+      }
+      // leaf child: one candidate per overlapping lane
+      const bool leaf = ov && c < 0;
+      const uint64_t ml = __ballot(leaf);
+      if (leaf) {
+        const int e = (head + qn + __popcll(ml & lanes_below_tr())) & (kQueue - 1);
+        L.qlane[wv][e] = lane;
+        L.qprim[wv][e] = c & 0x7fffffff;
+      }
+      qn += __popcll(ml);
+      __builtin_amdgcn_wave_barrier();
+      while (qn >= 64) {
+        drain(L, wv, head, 64, kind, no, A);
+        head = (head + 64) & (kQueue - 1);
+        qn -= 64;
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
   }
-  wave_flush(skey, sd2, cnt, A);
+  if (qn > 0) drain(L, wv, head, qn, kind, no, A);
+  if (no > 0) flush_out(L, wv, no, A);
 }
 
 // ------------------------------------------------------- input check (edges)
@@ -1129,7 +1271,9 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
     A.outd = outd;
     A.cap = cap;
     A.cnt = s->dc;
-    int64_t nq = (int64_t)A.mv + me + mp;
+    A.mv_pad = (A.mv + 63) & ~63;
+    A.me_pad = (me + 63) & ~63;
+    int64_t nq = (int64_t)A.mv_pad + A.me_pad + mp;
     if (nq > 0) {
       timer_begin(s, CC_K_SEARCH, st);
       k_traverse<<<blocks(nq, kTravThreads), kTravThreads, 0, st>>>(A);
