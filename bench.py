@@ -36,6 +36,64 @@ WORKLOADS = {
 }
 
 
+def latency_table(reps: int, small: bool, budget_s: float):
+    """p50/p99 of the per-call time (HIP events on the calling stream) over `reps`
+    calls of collide_step, after one untimed call, for every single-scene workload;
+    a workload whose calls would take more than budget_s in all stops early (after
+    at least 5 calls) and reports how many calls it timed."""
+    import torch
+
+    import paper_2211_04045_amd as cc
+    import scenes
+    torch.cuda.set_device(0)
+    ctx = cc.Context(0)
+    for cfg in (1, 2, 3, 4, 6):
+        sc = scenes.config(cfg, small=small)
+        dev = "cuda"
+        x = torch.as_tensor(sc["x"], device=dev)
+        xt = torch.as_tensor(sc["xt"], device=dev)
+        w = torch.as_tensor(sc["w"], device=dev)
+        tris = torch.as_tensor(sc["tris"], dtype=torch.int32, device=dev)
+        edges = torch.as_tensor(sc["edges"], dtype=torch.int32, device=dev)
+        t_first = time.perf_counter()
+        out, st = cc.collide_step(ctx, x, xt, w, tris, edges, **sc["params"])
+        torch.cuda.synchronize()
+        t_first = time.perf_counter() - t_first
+        print(f"# config {cfg}: untimed call {t_first:.2f} s, {st['iters']} iterations",
+              file=sys.stderr, flush=True)
+        n = reps if t_first * reps <= budget_s else max(5, int(budget_s / max(t_first, 1e-9)))
+        n = min(n, reps)
+        stream = torch.cuda.current_stream()
+        ev = []
+        t0 = time.perf_counter()
+        for i in range(n):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            out, st = cc.collide_step(ctx, x, xt, w, tris, edges, **sc["params"])
+            e1.record(stream)
+            ev.append((e0, e1))
+            if t_first > 1.0 or (i + 1) % 10 == 0:
+                torch.cuda.synchronize()
+                print(f"# config {cfg}: {i + 1} calls", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = np.array([a.elapsed_time(b) for a, b in ev])
+        # resident set of the step: state, topology, pairs and trees (bytes, estimated
+        # by the library's own admission formula) against the 256 MB last-level cache
+        foot = int(cc._lib.load().cc_scene_bytes(len(sc["x"]), len(sc["tris"]), len(sc["edges"])))
+        print(json.dumps({
+            "workload": sc["name"], "config": cfg, "verts": int(len(sc["x"])),
+            "tris": int(len(sc["tris"])), "edges": int(len(sc["edges"])), "calls": n,
+            "iterations_per_step": st["iters"], "status": st["status"],
+            "p50_ms": round(float(np.percentile(ms, 50)), 3),
+            "p99_ms": round(float(np.percentile(ms, 99)), 3),
+            "steps_per_s": round(n / wall, 3),
+            "pair_updates_per_step": st["pair_updates"],
+            "workspace_bytes_estimate": foot, "fits_256MB_llc": foot < 256 * 2 ** 20}),
+            flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,9 +126,17 @@ def main():
     ap.add_argument("--digest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE) of "
                          "a --copy-probe run into per-kernel HBM bytes per launch")
+    ap.add_argument("--latency", type=int, default=0, metavar="R",
+                    help="per-call latency (HIP events) of R calls on each single-scene "
+                         "workload (configs 1, 2, 3, 4, 6): one JSON line per workload")
+    ap.add_argument("--latency-budget", type=float, default=90.0,
+                    help="seconds of timed calls per workload in --latency (at least 5 calls)")
     args = ap.parse_args()
     if args.digest_pmc:
         digest_pmc(*args.digest_pmc)
+        return
+    if args.latency:
+        latency_table(args.latency, args.small, args.latency_budget)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; the multi-GPU sharding is a "

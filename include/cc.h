@@ -67,7 +67,12 @@ enum { CC_CONVERGED = 0, CC_MAXITER = 1 };
                                pair closer than 1e-9 m, no edge meeting a triangle it
                                shares no vertex with (FP64 orientations; values within
                                1e-12 of their absolute products count as touching);
-                               all-static pairs skipped. Fails with CC_ENOTFREE. */
+                               all-static pairs skipped. Fails with CC_ENOTFREE. Also
+                               checks, when a scene is taken in, that its edges hold every
+                               side of every triangle (CC_EINVAL otherwise). */
+#define CC_CCD_ALL 32u      /* every pair of P' takes the continuous test of the piece, not
+                               only those the motion bound (lemma of Sec. 5) leaves
+                               uncertified: a check of the path, at its cost */
 #define CC_MIXED 8u         /* mixed precision: the backward step (constraint values,
                                Jacobians, multipliers and y - x) in FP32; every set
                                decision, distance, D_i, x, the forward step and the
@@ -85,7 +90,8 @@ typedef struct cc_params {
   int32_t max_iters; /* L: 512 (dt = 1/100 s) .. 2048 (dt = 1/20 s) */
   int32_t gs_sweeps; /* Gauss-Seidel sweeps per backward step, 1 (Sec. 4.3.1) */
   int32_t max_colors;/* colour palette, <= 1024 */
-  uint32_t flags;    /* CC_EDGE_LEN | CC_TIME_KERNELS | CC_TRACE | CC_MIXED | CC_VALIDATE_INPUT */
+  uint32_t flags;    /* CC_EDGE_LEN | CC_TIME_KERNELS | CC_TRACE | CC_MIXED | CC_VALIDATE_INPUT |
+                        CC_CCD_ALL */
   uint64_t seed;     /* colouring priority seed */
   double omega;      /* CC_JACOBI: under-relaxation factor in (0, 1] (Sec. 4.3.2 names the
                         factor but gives no value; default 0.5) */

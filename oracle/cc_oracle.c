@@ -1355,7 +1355,7 @@ int orc_iterate(orc_scene* s, orc_iter* info) {
     double mv = s->move2[v[0]];
     for (int k = 1; k < nv; ++k)
       if (s->move2[v[k]] > mv) mv = s->move2[v[k]];
-    if (!(4.0 * mv < dpf[q])) {
+    if (p->ccd_all || !(4.0 * mv < dpf[q])) {
       /* not certified by the motion bound: continuous test of the piece */
       ++fail;
       double qq[12], dq[12];

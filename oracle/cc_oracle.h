@@ -41,7 +41,8 @@ typedef struct orc_params {
   double omega;      /* projected Jacobi: under-relaxation factor (Sec. 4.3.2 gives none) */
   int32_t backward;  /* 0: projected Gauss-Seidel over colours (Sec. 4.3, the method);
                         1: projected Jacobi (Sec. 4.3.2) */
-  int32_t pad_;
+  int32_t ccd_all;   /* 1: every pair of P' takes the continuous test, not only those the
+                        motion bound leaves uncertified (a check of the lemma of Sec. 5) */
 } orc_params;
 
 typedef struct orc_iter {

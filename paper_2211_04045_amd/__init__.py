@@ -11,12 +11,12 @@ from __future__ import annotations
 import ctypes as C
 
 from . import _lib
-from ._lib import (CC_EDGE_LEN, CC_MIXED, CC_TIME_KERNELS, CC_TRACE, CC_VALIDATE_INPUT, CCError,
-                   IterInfo, Params, SceneDesc, Stats)
+from ._lib import (CC_CCD_ALL, CC_EDGE_LEN, CC_MIXED, CC_TIME_KERNELS, CC_TRACE,
+                   CC_VALIDATE_INPUT, CCError, IterInfo, Params, SceneDesc, Stats)
 
 __all__ = ["Context", "Solver", "Server", "collide_step", "collide_step_batched", "params",
            "edges_from_tris", "CC_EDGE_LEN", "CC_TIME_KERNELS",
-           "CC_TRACE", "CC_MIXED", "CC_VALIDATE_INPUT", "CCError"]
+           "CC_TRACE", "CC_MIXED", "CC_VALIDATE_INPUT", "CC_CCD_ALL", "CCError"]
 
 
 def _torch():
@@ -52,7 +52,8 @@ def _ptr(t):
 
 def params(**over) -> Params:
     """Defaults of Table 2 (cc_default_params) with keyword overrides; the flags
-    are set with edge_len=, time_kernels=, trace=, mixed= and validate= (booleans);
+    are set with edge_len=, time_kernels=, trace=, mixed=, validate= and ccd_all=
+    (booleans);
     backward= takes "gs" (default) or "jacobi"."""
     p = Params()
     _lib.load().cc_default_params(C.byref(p))
@@ -65,6 +66,8 @@ def params(**over) -> Params:
             p.flags = (p.flags | CC_TRACE) if v else (p.flags & ~CC_TRACE)
         elif k == "mixed":
             p.flags = (p.flags | CC_MIXED) if v else (p.flags & ~CC_MIXED)
+        elif k == "ccd_all":
+            p.flags = (p.flags | CC_CCD_ALL) if v else (p.flags & ~CC_CCD_ALL)
         elif k == "validate":
             p.flags = (p.flags | CC_VALIDATE_INPUT) if v else (p.flags & ~CC_VALIDATE_INPUT)
         elif k == "backward":

@@ -350,6 +350,32 @@ void release_pending(cc_solver* s) {
   update_extents(s);
 }
 
+// Every side of every triangle of segment sg must be one of its edges, or edge-edge
+// pairs would miss contacts; checked when the input check is on (CC_EINVAL).
+static int check_tri_edges(cc_solver* s, int32_t sg, hipStream_t st) {
+  const Seg& g = s->segs[sg];
+  if (g.nf == 0) return CC_OK;
+  std::vector<int32_t> t(3 * (size_t)g.nf), e(2 * (size_t)g.ne);
+  CC_HIP(hipMemcpyAsync(t.data(), s->tris + 3 * (int64_t)g.fb, sizeof(int32_t) * t.size(),
+                        hipMemcpyDeviceToHost, st));
+  if (g.ne > 0)
+    CC_HIP(hipMemcpyAsync(e.data(), s->edges + 2 * (int64_t)g.eb, sizeof(int32_t) * e.size(),
+                          hipMemcpyDeviceToHost, st));
+  CC_HIP(hipStreamSynchronize(st));
+  auto key = [](int32_t a, int32_t b) {
+    return a < b ? ((uint64_t)(uint32_t)a << 32) | (uint32_t)b : ((uint64_t)(uint32_t)b << 32) | (uint32_t)a;
+  };
+  std::vector<uint64_t> ek((size_t)g.ne);
+  for (int32_t i = 0; i < g.ne; ++i) ek[(size_t)i] = key(e[2 * (size_t)i], e[2 * (size_t)i + 1]);
+  std::sort(ek.begin(), ek.end());
+  for (int32_t f = 0; f < g.nf; ++f)
+    for (int k = 0; k < 3; ++k)
+      if (!std::binary_search(ek.begin(), ek.end(),
+                              key(t[3 * (size_t)f + k], t[3 * (size_t)f + (k + 1) % 3])))
+        return CC_EINVAL;
+  return CC_OK;
+}
+
 int seg_add(cc_solver* s, int32_t nv, const double* inv_mass, const int32_t* tris, int32_t nf,
             const int32_t* edges, int32_t ne, int32_t max_iters, int32_t* out, hipStream_t st) {
   if (nv < 0 || nf < 0 || ne < 0 || !out) return CC_EINVAL;
@@ -400,6 +426,7 @@ int seg_add(cc_solver* s, int32_t nv, const double* inv_mass, const int32_t* tri
     if (rc == CC_OK) rc = launch_fill_i32(s->vseg + vb, nv, sg, st);
   }
   if (rc == CC_OK) rc = launch_topo_in(s, sg, tris, edges, st);
+  if (rc == CC_OK && (s->p.flags & CC_VALIDATE_INPUT)) rc = check_tri_edges(s, sg, st);
   if (rc == CC_OK) rc = launch_particles(s, sg, st);
   if (rc == CC_OK) {
     // the search arrays hold every live segment's particles

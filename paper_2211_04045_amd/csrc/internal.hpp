@@ -68,7 +68,8 @@ struct Counters {
   unsigned long long n_rows;    // edge rows in use
   unsigned long long hits;      // continuous-test contacts among the failures
   unsigned long long et;        // input check: an edge meets a triangle
-  unsigned long long pad[2];
+  unsigned long long ncert;     // certificate: pairs queued for the continuous test
+  unsigned long long pad[1];
 };
 
 // Device buffers of a linear BVH over n leaves (n-1 internal nodes), allocated

@@ -1444,44 +1444,75 @@ int launch_forward(cc_solver* s, hipStream_t st) {
 
 // Lemma of Sec. 5: the linear piece x^(l) -> x^(l+1) stays free for pair p when
 // no vertex of p moved half its distance, i.e. 4 max_v |dx_v|^2 < d_p^2. A pair the
-// bound does not certify gets the continuous test of the piece (ccd_hit).
+// bound does not certify is counted for its scene and queued (its index in P) for
+// the continuous test of the piece, which runs in a kernel of its own: the test is
+// rare and large, and kept out of this pass it does not lower its occupancy.
 __global__ void __launch_bounds__(kThreads) k_cert(const uint64_t* __restrict__ P,
                                                    const double* __restrict__ dP, int64_t nP,
                                                    Topo T, const double* __restrict__ move2,
-                                                   const double* __restrict__ xold,
-                                                   const double* __restrict__ x, double eta2,
-                                                   const int32_t* __restrict__ vseg, SegDev* seg) {
+                                                   const int32_t* __restrict__ vseg, SegDev* seg,
+                                                   unsigned long long* __restrict__ queue,
+                                                   unsigned long long* nqueue, int all) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nP) return;
-  int32_t v[4];
-  uint64_t key = P[i];
-  pair_verts(T, key, v);
-  double mv = move2[v[0]];
+  bool fail = false;
+  int32_t v[4] = {0, 0, 0, 0};
+  if (i < nP) {
+    pair_verts(T, P[i], v);
+    double mv = move2[v[0]];
 #pragma unroll
-  for (int k = 1; k < 4; ++k) {
-    double m = move2[v[k]];
-    if (m > mv) mv = m;
+    for (int k = 1; k < 4; ++k) {
+      double m = move2[v[k]];
+      if (m > mv) mv = m;
+    }
+    fail = all || !(4.0 * mv < dP[i]);
   }
-  if (4.0 * mv < dP[i]) return;
-  // not certified by the motion bound: continuous test of the piece (rare)
-  V3 q[4], dq[4];
-  for (int k = 0; k < 4; ++k) {
-    q[k] = ld3(xold, v[k]);
-    dq[k] = vsub(ld3(x, v[k]), q[k]);
+  const unsigned long long pos = wave_append(fail, nqueue);
+  if (fail) {
+    queue[pos] = (unsigned long long)i;
+    atomicAdd(&seg[vseg[v[0]]].fail, 1ull);
   }
-  const bool hit = key_is_vv(key) ? ccd_hit_vv(q[0], q[1], dq[0], dq[1], eta2)
-                                  : ccd_hit(q, dq, key_is_ee(key), eta2);
-  SegDev& sd = seg[vseg[v[0]]];
-  atomicAdd(&sd.fail, 1ull);
-  if (hit) atomicAdd(&sd.hits, 1ull);
 }
 
+// The continuous test of every queued pair (a grid-stride loop over the queue,
+// whose length is read on the device); contacts are counted for the pair's scene.
+__global__ void __launch_bounds__(kThreads) k_cert_ccd(const uint64_t* __restrict__ P, Topo T,
+                                                       const double* __restrict__ xold,
+                                                       const double* __restrict__ x, double eta2,
+                                                       const int32_t* __restrict__ vseg,
+                                                       SegDev* seg,
+                                                       const unsigned long long* __restrict__ queue,
+                                                       const unsigned long long* nqueue) {
+  const int64_t n = (int64_t)*nqueue;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t key = P[queue[j]];
+    int32_t v[4];
+    pair_verts(T, key, v);
+    V3 q[4], dq[4];
+    for (int k = 0; k < 4; ++k) {
+      q[k] = ld3(xold, v[k]);
+      dq[k] = vsub(ld3(x, v[k]), q[k]);
+    }
+    const bool hit = key_is_vv(key) ? ccd_hit_vv(q[0], q[1], dq[0], dq[1], eta2)
+                                    : ccd_hit(q, dq, key_is_ee(key), eta2);
+    if (hit) atomicAdd(&seg[vseg[v[0]]].hits, 1ull);
+  }
+}
+
+// The certificate of the current P'. The pair buffer P2 is free between the pair
+// passes and holds the queue (at most |P'| entries).
 int launch_cert(cc_solver* s, hipStream_t st) {
   const double eta = kCcdEta;
-  if (s->nP > 0)
+  if (s->nP > 0) {
+    unsigned long long* queue = (unsigned long long*)s->P2;
+    CC_HIP(hipMemsetAsync(&s->dc->ncert, 0, sizeof(unsigned long long), st));
     k_cert<<<nblk(s->nP), kThreads, 0, st>>>(s->P, s->dP, s->nP, Topo{s->tris, s->edges},
-                                              s->move2, s->xold, s->x, eta * eta, s->vseg,
-                                              s->seg_dev);
+                                              s->move2, s->vseg, s->seg_dev, queue, &s->dc->ncert,
+                                              (s->p.flags & CC_CCD_ALL) ? 1 : 0);
+    const unsigned nb = std::min<unsigned>(nblk(s->nP), 1024u);
+    k_cert_ccd<<<nb, kThreads, 0, st>>>(s->P, Topo{s->tris, s->edges}, s->xold, s->x, eta * eta,
+                                         s->vseg, s->seg_dev, queue, &s->dc->ncert);
+  }
   CC_HIP(hipGetLastError());
   return CC_OK;
 }

@@ -571,3 +571,42 @@ def test_mixed_precision_sand_pile_end_to_end(cc, ctx):
     npart = int((sc["w"] > 0).sum())
     d = np.linalg.norm(x[:npart, None] - x[None, :npart], axis=-1)
     assert d[np.triu_indices(npart, 1)].min() > 0.5e-3
+
+
+@pytest.mark.parametrize("cfg,iters", [(2, 60), (4, 60), (6, 60)])
+def test_ccd_on_every_pair_lockstep(cc, ctx, cfg, iters):
+    """CC_CCD_ALL: every pair of P' takes the continuous test each iteration; counts
+    and state bit-identical to the oracle's, and no pair is ever in contact."""
+    sc = scenes.config(cfg, small=True)
+    p = dict(sc.get("params", {}), max_iters=iters, ccd_all=True)
+    ref = oracle.Scene(sc["w"], sc["tris"], sc["edges"], **p)
+    gpu = cc.Solver(ctx, sc["w"], sc["tris"], sc["edges"], trace=True, **p)
+    ref.begin(sc["x"], sc["xt"])
+    gpu.begin(sc["x"], sc["xt"])
+    tested = 0
+    for l in range(iters):
+        s_ref, it_ref = ref.iterate()
+        s_gpu, it_gpu = gpu.iterate()
+        for k in TRACE_KEYS:
+            assert it_gpu[k] == it_ref[k], (cfg, l, k)
+        assert it_gpu["ccd_fail"] == it_gpu["n_pf"] and it_gpu["ccd_hits"] == 0
+        tested += it_gpu["ccd_fail"]
+        xr = ref.state()[0]
+        xg = gpu.state()[0].cpu().numpy()
+        assert np.array_equal(xg, xr)
+        if s_ref:
+            break
+    assert tested > 0
+
+
+def test_input_check_rejects_missing_triangle_sides(cc, ctx):
+    """Under the input check a mesh whose edges miss a triangle side is rejected
+    when it is taken in (edge-edge pairs would be incomplete)."""
+    sc = scenes.config(2, small=True)
+    edges = sc["edges"][1:]
+    with pytest.raises(cc.CCError) as e:
+        cc.Solver(ctx, sc["w"], sc["tris"], edges, validate=True)
+    assert e.value.code == -1
+    s = cc.Solver(ctx, sc["w"], sc["tris"], sc["edges"], validate=True)
+    s.begin(sc["x"], sc["xt"])
+    s.close()

@@ -761,3 +761,17 @@ def test_sand_pile_is_resolved_safely():
         for b in range(a + 1, n):
             assert _pair_exact(oracle.vv_key(a, b), xf, tris, edges)[1] > 0
         assert xf[a, 2] > 0
+
+
+def test_ccd_all_checks_every_pair_and_changes_nothing():
+    """With the continuous test on every pair of P' (a check of the lemma of Sec. 5),
+    every pair is tested, none is in contact, and the path is the same."""
+    x, xt, tris, edges = _two_patches()
+    a = oracle.Scene(np.ones(len(x)), tris, edges, max_iters=60)
+    b = oracle.Scene(np.ones(len(x)), tris, edges, max_iters=60, ccd_all=1)
+    xa, na, ta = a.run(x, xt, trace_cap=60)
+    xb, nb, tb = b.run(x, xt, trace_cap=60)
+    assert na == nb and np.array_equal(xa, xb)
+    for ia, ib in zip(ta, tb):
+        assert ib["ccd_fail"] == ib["n_pf"] and ib["ccd_hits"] == 0
+        assert ia["ccd_fail"] <= ib["ccd_fail"]
