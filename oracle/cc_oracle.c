@@ -27,11 +27,12 @@
  *  - alpha_i = 1 when y_i = x_i; when alpha_i = 1 the vertex is set to y_i.
  *  - The multipliers start at zero in every backward step and y carries the
  *    accumulated effect (Sec. 4: y initialised with y^(l)).
- *  - Constraints are coloured with Jones-Plassmann on the graph "shares a vertex
- *    with w > 0", priority = mix64(key ^ seed), smallest free colour (Sec. 4.3
- *    colours constraints, not vertices); the key of a contact is its pair key,
- *    the key of an edge-length row its input edge index. Contacts are swept
- *    colour by colour, then edge-length rows colour by colour.
+ *  - Constraints are coloured on the graph "shares a vertex with w > 0" (Sec. 4.3
+ *    colours constraints, not vertices) by a randomised palette colouring whose
+ *    choices are hashes of the row key, the seed and the round (orc_color_rows);
+ *    the key of a contact is its pair key, the key of an edge-length row its
+ *    input edge index. Contacts are swept colour by colour, then edge-length rows
+ *    colour by colour.
  *  - Edge-edge contacts use the tetrahedron (a,b,c,e) in the volume form; near
  *    parallel edges and near degenerate triangles fall back to the gap
  *    constraint c = d/delta - 1 (the alternative named in Sec. 4.1).
@@ -912,83 +913,135 @@ int orc_ccd_hit(const double* q, const double* dq, int kind, double eta, double*
 
 /* ------------------------------------------------------------- colouring */
 
-/* Jones-Plassmann: in each round every uncoloured row whose priority is the
- * largest among the uncoloured rows sharing one of its free vertices takes the
- * smallest colour not used by already coloured rows at those vertices. */
+/* Randomised palette colouring, after the colouring the backward step of
+ * Sec. 4.3 takes (rows of one colour share no free vertex and are projected in
+ * parallel), with its random choices made functions of the row's key, the seed
+ * and the round so that the colours depend only on the row set. In round
+ * t = 1, 2, ... every uncoloured row r
+ *   - finds u_v, the number of uncoloured rows at each of its free vertices v
+ *     (r included), and its palette size m_r = max(1, max_v u_v) + f_r, where f_r
+ *     counts the rounds r has failed;
+ *   - picks the (h mod m_r)-th smallest colour (counting from 0) not used by the
+ *     coloured rows at its free vertices, h = mix64(mix64(key ^ seed) + t * phi),
+ *     phi = 0x9E3779B97F4A7C15 (wrapping arithmetic);
+ * then every row whose pick no other uncoloured row sharing a free vertex made in
+ * this round keeps it; the others fail and try again. A pick beyond the palette
+ * limit, or more than ORC_MAX_ROUNDS rounds, is an error. */
+#define ORC_MAX_ROUNDS 4096
+#define ORC_PHI 0x9E3779B97F4A7C15ull
+
+typedef struct {
+  int64_t key; /* vertex * 2048 + colour */
+  int64_t row;
+} claim_t;
+
+static int cmp_claim(const void* a, const void* b) {
+  const claim_t *x = (const claim_t*)a, *y = (const claim_t*)b;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  return (x->row > y->row) - (x->row < y->row);
+}
+
+static int free_vertex(const orc_scene* s, int32_t v) { return v >= 0 && s->w[v] > 0.0; }
+
 int32_t orc_color_rows(const orc_scene* s, int64_t nrows, const int32_t* rv,
                        const uint64_t* keys, int32_t* colors) {
   const int W = (s->p.max_colors + 63) / 64;
-  uint64_t* prio = (uint64_t*)malloc((size_t)(nrows > 0 ? nrows : 1) * sizeof(uint64_t));
-  uint64_t* vmax = (uint64_t*)calloc((size_t)s->n, sizeof(uint64_t));
+  const size_t NR = (size_t)(nrows > 0 ? nrows : 1);
+  uint64_t* prio = (uint64_t*)malloc(NR * sizeof(uint64_t));
+  int32_t* fails = (int32_t*)calloc(NR, sizeof(int32_t));
+  int32_t* pick = (int32_t*)malloc(NR * sizeof(int32_t));
+  uint8_t* lost = (uint8_t*)malloc(NR);
+  int32_t* unc = (int32_t*)calloc((size_t)s->n, sizeof(int32_t));
   uint64_t* mask = (uint64_t*)calloc((size_t)s->n * (size_t)W, sizeof(uint64_t));
-  uint8_t* win = (uint8_t*)malloc((size_t)(nrows > 0 ? nrows : 1));
+  claim_t* cl = (claim_t*)malloc(NR * 4 * sizeof(claim_t));
   int32_t ncol = 0, err = 0;
   for (int64_t r = 0; r < nrows; ++r) {
     prio[r] = orc_mix64(keys[r] ^ s->p.seed);
     colors[r] = -1;
   }
   int64_t left = nrows;
-  while (left > 0 && !err) {
+  for (uint64_t t = 1; left > 0 && !err; ++t) {
+    if (t > ORC_MAX_ROUNDS) {
+      err = 1;
+      break;
+    }
+    /* uncoloured rows at each free vertex */
+    for (int32_t v = 0; v < s->n; ++v) unc[v] = 0;
     for (int64_t r = 0; r < nrows; ++r) {
       if (colors[r] >= 0) continue;
-      for (int k = 0; k < 4; ++k) {
-        int32_t v = rv[4 * r + k];
-        if (v >= 0 && s->w[v] > 0.0) vmax[v] = 0;
-      }
+      for (int k = 0; k < 4; ++k)
+        if (free_vertex(s, rv[4 * r + k])) unc[rv[4 * r + k]] += 1;
     }
-    for (int64_t r = 0; r < nrows; ++r) {
+    /* picks */
+    int64_t ncl = 0;
+    for (int64_t r = 0; r < nrows && !err; ++r) {
       if (colors[r] >= 0) continue;
+      int32_t m = 1;
       for (int k = 0; k < 4; ++k) {
-        int32_t v = rv[4 * r + k];
-        if (v >= 0 && s->w[v] > 0.0 && prio[r] > vmax[v]) vmax[v] = prio[r];
+        const int32_t v = rv[4 * r + k];
+        if (free_vertex(s, v) && unc[v] > m) m = unc[v];
       }
-    }
-    for (int64_t r = 0; r < nrows; ++r) {
-      win[r] = 0;
-      if (colors[r] >= 0) continue;
-      int ok = 1;
-      for (int k = 0; k < 4; ++k) {
-        int32_t v = rv[4 * r + k];
-        if (v >= 0 && s->w[v] > 0.0 && vmax[v] != prio[r]) ok = 0;
-      }
-      win[r] = (uint8_t)ok;
-    }
-    for (int64_t r = 0; r < nrows; ++r) {
-      if (!win[r]) continue;
-      int c = -1;
-      for (int wd = 0; wd < W && c < 0; ++wd) {
-        uint64_t used = 0;
+      m += fails[r];
+      const uint64_t h = orc_mix64(prio[r] + t * ORC_PHI);
+      const int64_t want = (int64_t)(h % (uint64_t)m);
+      int32_t c = -1;
+      int64_t seen = 0;
+      for (int32_t q = 0; q < s->p.max_colors; ++q) {
+        int used = 0;
         for (int k = 0; k < 4; ++k) {
-          int32_t v = rv[4 * r + k];
-          if (v >= 0 && s->w[v] > 0.0) used |= mask[(size_t)v * W + wd];
+          const int32_t v = rv[4 * r + k];
+          if (free_vertex(s, v) && ((mask[(size_t)v * W + q / 64] >> (q % 64)) & 1ull)) used = 1;
         }
-        for (int b = 0; b < 64; ++b)
-          if (!((used >> b) & 1ull)) {
-            c = 64 * wd + b;
-            break;
-          }
+        if (used) continue;
+        if (seen == want) {
+          c = q;
+          break;
+        }
+        ++seen;
       }
-      if (c < 0 || c >= s->p.max_colors) {
+      if (c < 0) {
         err = 1;
         break;
       }
+      pick[r] = c;
+      for (int k = 0; k < 4; ++k) {
+        const int32_t v = rv[4 * r + k];
+        if (free_vertex(s, v)) {
+          cl[ncl].key = (int64_t)v * 2048 + c;
+          cl[ncl].row = r;
+          ++ncl;
+        }
+      }
+    }
+    if (err) break;
+    /* rows whose pick another row at a shared free vertex made too */
+    for (int64_t r = 0; r < nrows; ++r) lost[r] = 0;
+    qsort(cl, (size_t)ncl, sizeof(claim_t), cmp_claim);
+    for (int64_t i = 0; i < ncl;) {
+      int64_t j = i + 1;
+      while (j < ncl && cl[j].key == cl[i].key) ++j;
+      if (j - i > 1)
+        for (int64_t q = i; q < j; ++q) lost[cl[q].row] = 1;
+      i = j;
+    }
+    /* commit */
+    for (int64_t r = 0; r < nrows; ++r) {
+      if (colors[r] >= 0) continue;
+      if (lost[r]) {
+        fails[r] += 1;
+        continue;
+      }
+      const int32_t c = pick[r];
       colors[r] = c;
       if (c + 1 > ncol) ncol = c + 1;
-    }
-    for (int64_t r = 0; r < nrows && !err; ++r) {
-      if (!win[r]) continue;
-      int c = colors[r];
       for (int k = 0; k < 4; ++k) {
-        int32_t v = rv[4 * r + k];
-        if (v >= 0 && s->w[v] > 0.0) mask[(size_t)v * W + c / 64] |= 1ull << (c % 64);
+        const int32_t v = rv[4 * r + k];
+        if (free_vertex(s, v)) mask[(size_t)v * W + c / 64] |= 1ull << (c % 64);
       }
       --left;
     }
   }
-  free(prio);
-  free(vmax);
-  free(mask);
-  free(win);
+  free(prio); free(fails); free(pick); free(lost); free(unc); free(mask); free(cl);
   return err ? -1 : ncol;
 }
 

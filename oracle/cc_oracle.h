@@ -97,8 +97,10 @@ int orc_contact_row(const orc_scene* s, const double* x, uint64_t key,
  * brute != 0 uses the all-pairs loop instead of the grid. Result sorted by key. */
 int64_t orc_search(orc_scene* s, const double* x, double dmax, int brute,
                    uint64_t* out, int64_t cap);
-/* Jones-Plassmann colouring of rows with vertex lists rv[4*r] (-1 = none);
- * conflicts through vertices with w > 0. Returns the number of colours, <0 error. */
+/* Colouring of rows with vertex lists rv[4*r] (-1 = none, each vertex listed once):
+ * rows sharing a vertex with w > 0 get different colours; randomised palette
+ * rounds whose choices hash the row key, the seed and the round. Returns the
+ * number of colours, <0 on error. */
 int32_t orc_color_rows(const orc_scene* s, int64_t nrows, const int32_t* rv,
                        const uint64_t* keys, int32_t* colors);
 uint64_t orc_mix64(uint64_t z);

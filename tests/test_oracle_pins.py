@@ -287,46 +287,80 @@ def test_search_drops_all_static_pairs():
     assert len(s.search(x, 4e-3)) == 0
 
 
-def _greedy_in_priority_order(rows, keys, w, seed):
-    """Sequential greedy colouring, rows taken in decreasing priority."""
-    prio = [oracle.mix64(int(k) ^ seed) for k in keys]
-    order = sorted(range(len(rows)), key=lambda r: -prio[r])
-    col = [-1] * len(rows)
-    used = {}
-    for r in order:
-        verts = [v for v in rows[r] if v >= 0 and w[v] > 0]
-        taken = set()
-        for v in verts:
-            taken |= used.get(v, set())
-        c = 0
-        while c in taken:
-            c += 1
-        col[r] = c
-        for v in verts:
-            used.setdefault(v, set()).add(c)
-    return col
+PHI = 0x9E3779B97F4A7C15
+M64 = (1 << 64) - 1
 
 
-def test_jones_plassmann_equals_greedy_in_priority_order():
+def _random_rows(rng, n, m):
+    rows = rng.integers(0, n, size=(m, 4)).astype(np.int32)
+    rows[rng.uniform(size=(m, 4)) < 0.2] = -1
+    for r in rows:  # a constraint lists a vertex once
+        seen = set()
+        for k in range(4):
+            if r[k] in seen:
+                r[k] = -1
+            elif r[k] >= 0:
+                seen.add(int(r[k]))
+    return rows
+
+
+def _proper(rows, col, w):
+    at = {}
+    for r, vs in enumerate(rows):
+        for v in vs:
+            if v >= 0 and w[v] > 0:
+                at.setdefault(int(v), []).append(int(col[r]))
+    return all(len(cs) == len(set(cs)) for cs in at.values())
+
+
+def test_colouring_is_proper_and_independent_of_row_order():
+    """Rows sharing a free vertex get different colours; the colour of a row is a
+    function of the row set (permuting the rows permutes the colours)."""
     rng = np.random.default_rng(6)
     n = 60
     w = np.where(rng.uniform(size=n) < 0.8, 1.0, 0.0)
     s = _scene(n, w=w)
     for trial in range(20):
         m = int(rng.integers(1, 400))
-        rows = rng.integers(0, n, size=(m, 4)).astype(np.int32)
-        rows[rng.uniform(size=(m, 4)) < 0.2] = -1
+        rows = _random_rows(rng, n, m)
         keys = rng.choice(2 ** 62, size=m, replace=False).astype(np.uint64)
         col, nc = s.color(rows, keys)
-        ref = _greedy_in_priority_order(rows, keys, w, oracle.DEFAULTS["seed"])
-        assert list(col) == ref
-        assert nc == max(ref) + 1
-        # proper: rows sharing a free vertex differ
-        for v in range(n):
-            if w[v] == 0:
-                continue
-            cs = [col[r] for r in range(m) if v in rows[r]]
-            assert len(cs) == len(set(cs))
+        assert _proper(rows, col, w)
+        assert nc == col.max() + 1
+        perm = rng.permutation(m)
+        col2, nc2 = s.color(rows[perm], keys[perm])
+        assert np.array_equal(col2, col[perm]) and nc2 == nc
+
+
+def test_colouring_small_cases():
+    """Worked cases of the rule: a row alone, or at static vertices only, takes
+    colour 0; k rows at one free vertex take k different colours; two rows at one
+    free vertex whose first-round picks differ keep them (palette 2, pick
+    h mod 2 with h = mix64(mix64(key ^ seed) + 1 * phi))."""
+    seed = oracle.DEFAULTS["seed"]
+    w = np.array([1.0, 1.0, 1.0, 0.0, 0.0, 1.0, 1.0])
+    s = _scene(len(w), w=w)
+    col, _ = s.color(np.array([[0, 1, 2, -1]]), np.array([7], np.uint64))
+    assert list(col) == [0]
+    col, _ = s.color(np.array([[3, 4, -1, -1], [3, 4, -1, -1]]), np.array([1, 2], np.uint64))
+    assert list(col) == [0, 0]
+    k = 9
+    rows = np.array([[5, -1, -1, -1]] * k)
+    col, nc = s.color(rows, np.arange(1, k + 1, dtype=np.uint64))
+    assert sorted(col) == sorted(set(col)) and len(set(col)) == k
+    def first_pick(key):
+        h = oracle.mix64((oracle.mix64(key ^ seed) + PHI) & M64)
+        return h % 2
+    keys = None
+    for a in range(1, 200):
+        for b in range(a + 1, 200):
+            if first_pick(a) != first_pick(b):
+                keys = (a, b)
+                break
+        if keys:
+            break
+    col, _ = s.color(np.array([[6, 0, -1, -1], [6, 1, -1, -1]]), np.array(keys, np.uint64))
+    assert list(col) == [first_pick(keys[0]), first_pick(keys[1])]
 
 
 # -------------------------------------------------------------- full step
