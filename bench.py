@@ -105,6 +105,8 @@ def main():
                     help="FP32 backward step (sets, distances, x and CCD stay FP64)")
     ap.add_argument("--jacobi", action="store_true",
                     help="projected Jacobi backward step (Sec. 4.3.2) instead of Gauss-Seidel")
+    ap.add_argument("--max-iters", type=int, default=0,
+                    help="override the workload's iteration cap L (0: the workload's own)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=3)
     # serving stream (--config 5)
@@ -154,6 +156,8 @@ def main():
     torch.cuda.set_device(0)
     sc = scenes.config(args.config, small=args.small)
     prm = dict(sc["params"])
+    if args.max_iters > 0:
+        prm["max_iters"] = args.max_iters
     if args.mixed:
         prm["mixed"] = True
     if args.jacobi:

@@ -126,7 +126,7 @@ void free_pairs(cc_solver* s) {
 }
 void free_active(cc_solver* s) {
   dfree(s->Akeys); dfree(s->Averts); dfree(s->Acol); dfree(s->Aorder);
-  dfree(s->list0); dfree(s->list1); dfree(s->lamA);
+  dfree(s->list0); dfree(s->list1); dfree(s->lamA); dfree(s->afail); dfree(s->apick);
 }
 
 // Pair buffers of capacity cap; the first `keep` keys of P survive.
@@ -150,6 +150,8 @@ int alloc_active(cc_solver* s, int64_t cap) {
   CC_TRY(dalloc(&s->list0, cap));
   CC_TRY(dalloc(&s->list1, cap));
   CC_TRY(dalloc(&s->lamA, cap));
+  CC_TRY(dalloc(&s->afail, cap));
+  CC_TRY(dalloc(&s->apick, cap));
   return CC_OK;
 }
 
@@ -157,11 +159,12 @@ void free_vertex_arrays(cc_solver* s) {
   dfree(s->w); dfree(s->stat); dfree(s->x); dfree(s->y); dfree(s->xt); dfree(s->xold);
   dfree(s->r); dfree(s->move2); dfree(s->Di); dfree(s->vseg); dfree(s->plist); dfree(s->dy);
   dfree(s->jacc);
-  dfree(s->vmax0); dfree(s->vmax1); dfree(s->masks);
+  dfree(s->vmax0); dfree(s->claims); dfree(s->masks);
 }
 void free_edge_arrays(cc_solver* s) {
   dfree(s->edges); dfree(s->eseg); dfree(s->eg); dfree(s->einv); dfree(s->ecol); dfree(s->eorder);
   dfree(s->elist0); dfree(s->elist1); dfree(s->elist2); dfree(s->lamE);
+  dfree(s->efail); dfree(s->epick);
 }
 
 void solver_free(cc_solver* s) {
@@ -211,12 +214,13 @@ int resize_arrays(cc_solver* s, int32_t capV, int32_t capF, int32_t capE, hipStr
     CC_TRY(dregrow(&s->vseg, capV, oV, st));
     CC_TRY(launch_fill_i32(s->vseg + oV, capV - oV, -1, st));
     CC_TRY(dregrow(&s->plist, capV, oV, st));
-    dfree(s->xold); dfree(s->move2); dfree(s->Di); dfree(s->vmax0); dfree(s->vmax1); dfree(s->masks);
+    dfree(s->xold); dfree(s->move2); dfree(s->Di); dfree(s->vmax0); dfree(s->claims); dfree(s->masks);
     CC_TRY(dalloc(&s->xold, 3 * (int64_t)capV));
     CC_TRY(dalloc(&s->move2, capV));
     CC_TRY(dalloc(&s->Di, capV));
     CC_TRY(dalloc(&s->vmax0, capV));
-    CC_TRY(dalloc(&s->vmax1, capV));
+    CC_TRY(dalloc(&s->claims, (int64_t)capV * 2 * kMaskWords));
+    s->pc_dirty = true;
     CC_TRY(dalloc(&s->masks, (int64_t)capV * kMaskWords));
   }
   if (capF != oF) CC_TRY(dregrow(&s->tris, 3 * (int64_t)capF, 3 * oF, st));
@@ -233,6 +237,9 @@ int resize_arrays(cc_solver* s, int32_t capV, int32_t capF, int32_t capE, hipStr
     CC_TRY(dalloc(&s->elist1, capE));
     CC_TRY(dalloc(&s->elist2, capE));
     CC_TRY(dalloc(&s->lamE, capE));
+    dfree(s->efail); dfree(s->epick);
+    CC_TRY(dalloc(&s->efail, capE));
+    CC_TRY(dalloc(&s->epick, capE));
     s->erows_dirty = true;
   }
   s->capV = capV;

@@ -25,7 +25,7 @@ namespace cc {
 
 constexpr int kMaxColors = 1024;
 constexpr int kMaskWords = kMaxColors / 64;
-constexpr int kMaxRounds = 65536;  // Jones-Plassmann rounds per colouring
+constexpr int kMaxRounds = 4096;  // colouring rounds per colouring
 constexpr double kCcdEta = 1e-12;  // distance at which the continuous test reports contact (m)
 constexpr int kMaxSeg = 1024;      // scenes (segments) resident in one solver
 constexpr int kSegBits = 10;       // bits of a segment's rank in a search's sort keys
@@ -204,7 +204,11 @@ struct cc_solver {
   int32_t n_newrows = 0;               // rows being coloured at a begin
   std::vector<int32_t> ecol_off;
   // colouring scratch
-  unsigned long long *vmax0 = nullptr, *vmax1 = nullptr, *masks = nullptr;
+  unsigned long long *vmax0 = nullptr, *masks = nullptr;  // per vertex: row count, used colours
+  unsigned long long* claims = nullptr;  // per vertex: colours claimed this round, and clashes
+  int32_t *afail = nullptr, *apick = nullptr;  // per contact row: failed rounds, pick
+  int32_t *efail = nullptr, *epick = nullptr;  // per edge row
+  bool pc_dirty = true;                        // counts or claims may be non-zero
   unsigned long long* rcnt = nullptr;  // list length per colouring round (kMaxRounds + 1)
   int32_t* col_cnt = nullptr;  // kMaxColors + 1
   int32_t *coff_dev = nullptr, *ecoff_dev = nullptr;  // colour bucket offsets on the device

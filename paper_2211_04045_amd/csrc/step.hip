@@ -588,11 +588,12 @@ struct RowSrc {
       v[3] = -1;
     } else {
       int4 q = verts[r];
+      const uint64_t k = keys[r];
       v[0] = q.x;
       v[1] = q.y;
-      v[2] = q.z;
-      v[3] = q.w;
-      key = local_pair_key(keys[r], seg[vseg[q.x]]);
+      v[2] = key_is_vv(k) ? -1 : q.z;  // a vertex-vertex row has two vertices
+      v[3] = key_is_vv(k) ? -1 : q.w;
+      key = local_pair_key(k, seg[vseg[q.x]]);
     }
   }
 };
@@ -600,12 +601,27 @@ struct RowSrc {
 constexpr int kRoundsPerSync = 8;  // colouring rounds launched between host reads
 constexpr int kTailRows = 4096;     // below this many rows one block finishes the rounds
 constexpr int kTailThreads = 1024;
+constexpr uint64_t kPhi = 0x9E3779B97F4A7C15ull;  // round step of the colouring hash
 
-struct JpArgs {
+// Randomised palette colouring (Sec. 4.3 colours the constraints; the random
+// choices are hashes of the row key, the seed and the round, so the colours depend
+// only on the row set). A round over the uncoloured rows:
+//   count:   unc[v] = uncoloured rows at free vertex v;
+//   pick:    palette m = max(1, max_v unc[v]) + failed rounds of the row; the row
+//            picks the (h mod m)-th smallest colour its coloured neighbours leave
+//            free, h = mix64(mix64(key ^ seed) + t * phi), and claims it at its
+//            free vertices (a second claim of a colour at a vertex marks a clash);
+//   resolve: a row without a clash keeps its colour, the others fail and stay;
+//   clear:   the round's counts and claims are reset.
+struct PcArgs {
   RowSrc src;
   const double* w;
   uint64_t seed;
-  unsigned long long* masks;
+  unsigned long long* masks;   // colours used at each vertex (kMaskWords per vertex)
+  unsigned long long* claims;  // per vertex: kMaskWords words of claims, then of clashes
+  unsigned long long* unc;     // uncoloured rows per vertex (this round)
+  int32_t* fails;              // per row: failed rounds
+  int32_t* pick;               // per row: this round's pick
   int maxc;
   int32_t* colors;
   Counters* c;
@@ -619,41 +635,36 @@ __device__ __forceinline__ unsigned long long ld_u64(const unsigned long long* p
   return *p;
 }
 
-// Round part 1: an uncoloured row offers its priority to its free vertices.
-// (The pre-check only skips atomics that cannot raise the value: in a fresh
-// kernel the buffer only grows; inside the single-block tail it is read with
-// atomic loads so that no stale cache line can hide a lower value.)
-template <bool kAtomicLoads>
-__device__ __forceinline__ void jp_offer(const JpArgs& a, int32_t r, unsigned long long* vcur) {
-  uint64_t key;
-  int32_t v[4];
-  a.src.get(r, key, v);
-  unsigned long long pr = (unsigned long long)mix64(key ^ a.seed);
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-    if (is_free(a.w, v[k]) && pr > ld_u64<kAtomicLoads>(&vcur[v[k]])) atomicMax(&vcur[v[k]], pr);
+__device__ __forceinline__ unsigned long long* claim_word(const PcArgs& a, int32_t v, int which,
+                                                          int wd) {
+  return a.claims + ((int64_t)v * 2 + which) * kMaskWords + wd;
 }
 
-// Round part 2: a row holding the maximum at all its free vertices takes the
-// smallest colour not used at those vertices (Jones-Plassmann); it returns true
-// when the row stays uncoloured. The other priority buffer is cleared at the
-// row's vertices for the next round.
-template <bool kAtomicLoads>
-__device__ __forceinline__ bool jp_pick(const JpArgs& a, int32_t r,
-                                        const unsigned long long* vcur,
-                                        unsigned long long* vnext) {
+__device__ __forceinline__ void pc_count(const PcArgs& a, int32_t r) {
   uint64_t key;
   int32_t v[4];
   a.src.get(r, key, v);
-  unsigned long long pr = (unsigned long long)mix64(key ^ a.seed);
-  bool win = true;
+  a.colors[r] = 0;  // an uncoloured row reads as colour 0 should the rounds run out
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (is_free(a.w, v[k])) atomicAdd(&a.unc[v[k]], 1ull);
+}
+
+template <bool kAtomicLoads>
+__device__ __forceinline__ void pc_pick(const PcArgs& a, int32_t r, uint64_t t) {
+  uint64_t key;
+  int32_t v[4];
+  a.src.get(r, key, v);
+  unsigned long long m = 1;
 #pragma unroll
   for (int k = 0; k < 4; ++k)
     if (is_free(a.w, v[k])) {
-      if (ld_u64<kAtomicLoads>(&vcur[v[k]]) != pr) win = false;
-      vnext[v[k]] = 0ull;
+      const unsigned long long u = ld_u64<kAtomicLoads>(&a.unc[v[k]]);
+      if (u > m) m = u;
     }
-  if (!win) return true;
+  m += (unsigned long long)a.fails[r];
+  const uint64_t h = mix64(mix64(key ^ a.seed) + t * kPhi);
+  unsigned long long want = h % m;
   int col = -1;
   const int W = (a.maxc + 63) / 64;
   for (int wd = 0; wd < W && col < 0; ++wd) {
@@ -661,52 +672,108 @@ __device__ __forceinline__ bool jp_pick(const JpArgs& a, int32_t r,
 #pragma unroll
     for (int k = 0; k < 4; ++k)
       if (is_free(a.w, v[k])) used |= ld_u64<kAtomicLoads>(&a.masks[(int64_t)v[k] * kMaskWords + wd]);
-    if (~used) col = 64 * wd + (__ffsll((long long)~used) - 1);
+    unsigned long long fr = ~used;
+    const int lim = a.maxc - 64 * wd;  // palette limit inside this word
+    if (lim < 64) fr &= (1ull << lim) - 1ull;
+    const unsigned long long cnt = (unsigned long long)__popcll(fr);
+    if (want >= cnt) {
+      want -= cnt;
+      continue;
+    }
+    for (unsigned long long q = 0; q < want; ++q) fr &= fr - 1ull;  // drop the lowest `want`
+    col = 64 * wd + (__ffsll((long long)fr) - 1);
   }
-  if (col < 0 || col >= a.maxc) {
+  if (col < 0) {
     atomicOr(&a.c->err, 1ull);
     col = 0;
-  } else {
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (is_free(a.w, v[k]))
-        atomicOr(&a.masks[(int64_t)v[k] * kMaskWords + col / 64], 1ull << (col % 64));
   }
+  a.pick[r] = col;
+  const unsigned long long bit = 1ull << (col % 64);
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (is_free(a.w, v[k])) {
+      const unsigned long long old = atomicOr(claim_word(a, v[k], 0, col / 64), bit);
+      if (old & bit) atomicOr(claim_word(a, v[k], 1, col / 64), bit);
+    }
+}
+
+// Returns true when the row stays uncoloured.
+template <bool kAtomicLoads>
+__device__ __forceinline__ bool pc_resolve(const PcArgs& a, int32_t r) {
+  uint64_t key;
+  int32_t v[4];
+  a.src.get(r, key, v);
+  const int col = a.pick[r];
+  const unsigned long long bit = 1ull << (col % 64);
+  bool clash = false;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (is_free(a.w, v[k]) && (ld_u64<kAtomicLoads>(claim_word(a, v[k], 1, col / 64)) & bit))
+      clash = true;
+  if (clash) {
+    a.fails[r] += 1;
+    return true;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (is_free(a.w, v[k])) atomicOr(&a.masks[(int64_t)v[k] * kMaskWords + col / 64], bit);
   a.colors[r] = col;
   atomicMax(&a.c->ncol, (unsigned long long)(col + 1));
   return false;
 }
 
-// One round over a list whose length lives on the device (rounds are launched
-// ahead of the host knowing how many rows are left).
-__global__ void __launch_bounds__(kThreads) k_jp_max(JpArgs a, const int32_t* list,
-                                                     const unsigned long long* nlist,
-                                                     unsigned long long* vcur) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)*nlist) return;
-  jp_offer<false>(a, list[t], vcur);
+__device__ __forceinline__ void pc_clear(const PcArgs& a, int32_t r) {
+  uint64_t key;
+  int32_t v[4];
+  a.src.get(r, key, v);
+  const int wd = a.pick[r] / 64;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (is_free(a.w, v[k])) {
+      a.unc[v[k]] = 0ull;
+      *claim_word(a, v[k], 0, wd) = 0ull;
+      *claim_word(a, v[k], 1, wd) = 0ull;
+    }
 }
 
-__global__ void __launch_bounds__(kThreads) k_jp_pick(JpArgs a, const int32_t* list,
+// One phase of a round over a list whose length lives on the device (rounds are
+// launched ahead of the host knowing how many rows are left).
+__global__ void __launch_bounds__(kThreads) k_pc_count(PcArgs a, const int32_t* list,
+                                                       const unsigned long long* nlist) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < (int64_t)*nlist) pc_count(a, list[t]);
+}
+
+__global__ void __launch_bounds__(kThreads) k_pc_pick(PcArgs a, const int32_t* list,
                                                       const unsigned long long* nlist,
-                                                      const unsigned long long* vcur,
-                                                      unsigned long long* vnext,
-                                                      int32_t* list_out,
-                                                      unsigned long long* nout) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool valid = t < (int64_t)*nlist;
-  int32_t r = valid ? list[t] : 0;
-  bool lose = valid && jp_pick<false>(a, r, vcur, vnext);
-  unsigned long long pos = wave_append(lose, nout);
-  if (lose) list_out[pos] = r;
+                                                      uint64_t round) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < (int64_t)*nlist) pc_pick<false>(a, list[t], round);
 }
 
-// The remaining rounds in one block: global atomics for the priorities and
-// masks, atomic loads to read them back, block barriers between the phases.
-__global__ void __launch_bounds__(kTailThreads) k_jp_tail(JpArgs a, int32_t* la, int32_t* lb,
+__global__ void __launch_bounds__(kThreads) k_pc_resolve(PcArgs a, const int32_t* list,
+                                                         const unsigned long long* nlist,
+                                                         int32_t* list_out,
+                                                         unsigned long long* nout) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = t < (int64_t)*nlist;
+  const int32_t r = valid ? list[t] : 0;
+  const bool stay = valid && pc_resolve<false>(a, r);
+  const unsigned long long pos = wave_append(stay, nout);
+  if (stay) list_out[pos] = r;
+}
+
+__global__ void __launch_bounds__(kThreads) k_pc_clear(PcArgs a, const int32_t* list,
+                                                       const unsigned long long* nlist) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < (int64_t)*nlist) pc_clear(a, list[t]);
+}
+
+// The remaining rounds (from round t0) in one block: global atomics, atomic loads
+// to read what other threads wrote, block barriers between the phases.
+__global__ void __launch_bounds__(kTailThreads) k_pc_tail(PcArgs a, int32_t* la, int32_t* lb,
                                                           const unsigned long long* nlist,
-                                                          unsigned long long* v0,
-                                                          unsigned long long* v1, int parity) {
+                                                          uint64_t t0, uint64_t tmax) {
   __shared__ int32_t ncur, nnext;
   if (threadIdx.x == 0) {
     ncur = (int32_t)*nlist;
@@ -715,25 +782,29 @@ __global__ void __launch_bounds__(kTailThreads) k_jp_tail(JpArgs a, int32_t* la,
   __syncthreads();
   int32_t* cur = la;
   int32_t* nxt = lb;
-  int round = parity;
-  while (ncur > 0) {
-    unsigned long long* vcur = (round & 1) ? v1 : v0;
-    unsigned long long* vnext = (round & 1) ? v0 : v1;
-    for (int32_t t = threadIdx.x; t < ncur; t += kTailThreads) jp_offer<true>(a, cur[t], vcur);
-    __syncthreads();
-    for (int32_t t = threadIdx.x; t < ncur; t += kTailThreads) {
-      int32_t r = cur[t];
-      if (jp_pick<true>(a, r, vcur, vnext)) nxt[atomicAdd(&nnext, 1)] = r;
+  for (uint64_t t = t0; ncur > 0; ++t) {
+    if (t > tmax) {
+      if (threadIdx.x == 0) atomicOr(&a.c->err, 1ull);
+      break;
     }
+    for (int32_t i = threadIdx.x; i < ncur; i += kTailThreads) pc_count(a, cur[i]);
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < ncur; i += kTailThreads) pc_pick<true>(a, cur[i], t);
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < ncur; i += kTailThreads) {
+      const int32_t r = cur[i];
+      if (pc_resolve<true>(a, r)) nxt[atomicAdd(&nnext, 1)] = r;
+    }
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < ncur; i += kTailThreads) pc_clear(a, cur[i]);
     __syncthreads();
     if (threadIdx.x == 0) {
       ncur = nnext;
       nnext = 0;
     }
-    int32_t* t = cur;
+    int32_t* tmp = cur;
     cur = nxt;
-    nxt = t;
-    ++round;
+    nxt = tmp;
     __syncthreads();
   }
 }
@@ -828,36 +899,48 @@ int color_rows(cc_solver* s, bool edges, hipStream_t st) {
     cur = s->list0;
     nxt = s->list1;
   }
-  CC_HIP(hipMemsetAsync(s->vmax0, 0, sizeof(unsigned long long) * s->n, st));
-  CC_HIP(hipMemsetAsync(s->vmax1, 0, sizeof(unsigned long long) * s->n, st));
+  if (s->pc_dirty) {  // an aborted colouring left counts or claims behind
+    CC_HIP(hipMemsetAsync(s->vmax0, 0, sizeof(unsigned long long) * s->n, st));
+    CC_HIP(hipMemsetAsync(s->claims, 0, sizeof(unsigned long long) * s->n * 2 * kMaskWords, st));
+    s->pc_dirty = false;
+  }
   CC_HIP(hipMemsetAsync(s->masks, 0, sizeof(unsigned long long) * s->n * kMaskWords, st));
   CC_HIP(hipMemsetAsync(&s->dc->ncol, 0, sizeof(unsigned long long), st));
   CC_HIP(hipMemsetAsync(&s->dc->err, 0, sizeof(unsigned long long), st));
   CC_HIP(hipMemsetAsync(s->rcnt, 0, sizeof(unsigned long long) * (kMaxRounds + 1), st));
   CC_TRY(launch_fill_u64(s->rcnt, 1, (unsigned long long)nrows, st));
-  JpArgs a;
+  int32_t* fails = edges ? s->efail : s->afail;
+  int32_t* pick = edges ? s->epick : s->apick;
+  if (edges) CC_TRY(launch_fill_i32(fails, s->capE, 0, st));
+  else CC_TRY(launch_fill_i32(fails, nrows, 0, st));
+  PcArgs a;
   a.src = RowSrc{s->Akeys, s->Averts, s->edges, s->vseg, s->eseg, s->seg_dev, edges ? 1 : 0};
   a.w = s->w;
   a.seed = s->p.seed;
   a.masks = s->masks;
+  a.claims = s->claims;
+  a.unc = s->vmax0;
+  a.fails = fails;
+  a.pick = pick;
   a.maxc = s->p.max_colors;
   a.colors = colors;
   a.c = s->dc;
   int64_t known = nrows;  // upper bound of the current list length
-  int round = 0;
+  int round = 0;          // rounds done; round t = round + 1 is next
+  s->pc_dirty = true;
   for (;;) {
     if (known <= kTailRows) {
-      k_jp_tail<<<1, kTailThreads, 0, st>>>(a, cur, nxt, s->rcnt + round, s->vmax0, s->vmax1,
-                                            round & 1);
+      k_pc_tail<<<1, kTailThreads, 0, st>>>(a, cur, nxt, s->rcnt + round, (uint64_t)round + 1,
+                                            (uint64_t)kMaxRounds);
       break;
     }
     if (round + kRoundsPerSync > kMaxRounds) return CC_ECOLOR;
     for (int b = 0; b < kRoundsPerSync; ++b) {
-      unsigned long long* vcur = (round & 1) ? s->vmax1 : s->vmax0;
-      unsigned long long* vnext = (round & 1) ? s->vmax0 : s->vmax1;
-      k_jp_max<<<nblk(known), kThreads, 0, st>>>(a, cur, s->rcnt + round, vcur);
-      k_jp_pick<<<nblk(known), kThreads, 0, st>>>(a, cur, s->rcnt + round, vcur, vnext, nxt,
-                                                  s->rcnt + round + 1);
+      const unsigned g = nblk(known);
+      k_pc_count<<<g, kThreads, 0, st>>>(a, cur, s->rcnt + round);
+      k_pc_pick<<<g, kThreads, 0, st>>>(a, cur, s->rcnt + round, (uint64_t)round + 1);
+      k_pc_resolve<<<g, kThreads, 0, st>>>(a, cur, s->rcnt + round, nxt, s->rcnt + round + 1);
+      k_pc_clear<<<g, kThreads, 0, st>>>(a, cur, s->rcnt + round);
       int32_t* t = cur;
       cur = nxt;
       nxt = t;
@@ -874,7 +957,9 @@ int color_rows(cc_solver* s, bool edges, hipStream_t st) {
   if (edges) {
     CC_HIP(hipMemcpyAsync(s->hc, s->dc, sizeof(Counters), hipMemcpyDeviceToHost, st));
     CC_HIP(hipStreamSynchronize(st));
-    return (s->hc->err & 1ull) ? CC_ECOLOR : CC_OK;
+    if (s->hc->err & 1ull) return CC_ECOLOR;
+    s->pc_dirty = false;
+    return CC_OK;
   }
   // contact buckets: counts, offsets (one-block scan) and the scatter are queued
   // behind the colouring; one readback brings the colour count and the offsets
@@ -891,6 +976,7 @@ int color_rows(cc_solver* s, bool edges, hipStream_t st) {
                         hipMemcpyDeviceToHost, st));
   CC_HIP(hipStreamSynchronize(st));
   if (s->hc->err & 1ull) return CC_ECOLOR;
+  s->pc_dirty = false;
   const int32_t ncol = (int32_t)s->hc->ncol;
   off.resize(ncol + 1);
   s->n_colors = ncol;
