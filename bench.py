@@ -36,6 +36,48 @@ WORKLOADS = {
 }
 
 
+def ablation(reps: int):
+    """The backward-step ablations of Sec. 4.3.1 and Sec. 4.3.2 on the workloads that
+    converge (folded cloth, particle pile): Gauss-Seidel with 1, 2 and 4 sweeps,
+    projected Jacobi with omega 0.5 and 1.0. One JSON line per run: iterations to
+    the stop test and time per step (HIP events, `reps` calls after one untimed)."""
+    import torch
+
+    import paper_2211_04045_amd as cc
+    import scenes
+    torch.cuda.set_device(0)
+    ctx = cc.Context(0)
+    variants = [dict(backward="gs", gs_sweeps=1), dict(backward="gs", gs_sweeps=2),
+                dict(backward="gs", gs_sweeps=4), dict(backward="jacobi", omega=0.5),
+                dict(backward="jacobi", omega=1.0)]
+    for cfg in (2, 6):
+        sc = scenes.config(cfg)
+        dev = "cuda"
+        x = torch.as_tensor(sc["x"], device=dev)
+        xt = torch.as_tensor(sc["xt"], device=dev)
+        w = torch.as_tensor(sc["w"], device=dev)
+        tris = torch.as_tensor(sc["tris"], dtype=torch.int32, device=dev)
+        edges = torch.as_tensor(sc["edges"], dtype=torch.int32, device=dev)
+        for v in variants:
+            prm = dict(sc["params"], **v)
+            out, st = cc.collide_step(ctx, x, xt, w, tris, edges, **prm)
+            stream = torch.cuda.current_stream()
+            ms = []
+            for i in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                out, st = cc.collide_step(ctx, x, xt, w, tris, edges, **prm)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            print(json.dumps({"workload": sc["name"], "config": cfg, **v,
+                              "iterations_per_step": st["iters"], "status": st["status"],
+                              "ms_per_step": round(float(np.median(ms)), 3),
+                              "row_updates_per_step": st["row_updates"],
+                              "max_colors_used": st["max_colors_used"]}), flush=True)
+
+
 def latency_table(reps: int, small: bool, budget_s: float):
     """p50/p99 of the per-call time (HIP events on the calling stream) over `reps`
     calls of collide_step, after one untimed call, for every single-scene workload;
@@ -131,6 +173,9 @@ def main():
     ap.add_argument("--latency", type=int, default=0, metavar="R",
                     help="per-call latency (HIP events) of R calls on each single-scene "
                          "workload (configs 1, 2, 3, 4, 6): one JSON line per workload")
+    ap.add_argument("--ablation", type=int, default=0, metavar="R",
+                    help="backward-step ablations (sweeps, Jacobi) on the converging "
+                         "workloads, R timed calls each")
     ap.add_argument("--latency-budget", type=float, default=90.0,
                     help="seconds of timed calls per workload in --latency (at least 5 calls)")
     args = ap.parse_args()
@@ -139,6 +184,9 @@ def main():
         return
     if args.latency:
         latency_table(args.latency, args.small, args.latency_budget)
+        return
+    if args.ablation:
+        ablation(args.ablation)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; the multi-GPU sharding is a "

@@ -610,3 +610,13 @@ def test_input_check_rejects_missing_triangle_sides(cc, ctx):
     s = cc.Solver(ctx, sc["w"], sc["tris"], sc["edges"], validate=True)
     s.begin(sc["x"], sc["xt"])
     s.close()
+
+
+@pytest.mark.parametrize("cfg,backward,sweeps", [(2, "gs", 3), (3, "gs", 2), (2, "jacobi", 2),
+                                                 (6, "gs", 4)])
+def test_several_sweeps_lockstep(cc, ctx, cfg, backward, sweeps):
+    """More than one sweep per backward step (the ablation of Sec. 4.3.1; Jacobi
+    sweeps likewise): every iteration bit-identical to the oracle."""
+    sc = scenes.config(cfg, small=True)
+    n, ref, gpu = _lockstep(cc, ctx, sc, 150, gs_sweeps=sweeps, backward=backward)
+    assert n >= 1
