@@ -90,6 +90,8 @@ def _load():
     lib.orc_validate.restype = C.c_int
     lib.orc_particles.argtypes = [vp, vp]
     lib.orc_particles.restype = i32
+    lib.orc_normal_flow.argtypes = [i32, vp, vp, i32, d, d, i32, vp]
+    lib.orc_normal_flow.restype = C.c_int
     _lib = lib
     return lib
 
@@ -145,6 +147,18 @@ def ccd_hit(q, dq, ee, eta: float = 1e-12):
 
 def seg_tri_meet(p, q, a, b, c, tol: float = 1e-9) -> bool:
     return bool(_load().orc_seg_tri_meet(*(_ptr(_f64(v)) for v in (p, q, a, b, c)), float(tol)))
+
+
+def normal_flow(x, tris, beta: float, alpha: float, iters: int = 3):
+    """y^[k+1] of the globally injective normal flow (orc_normal_flow)."""
+    x = _f64(x)
+    tris = np.ascontiguousarray(tris, dtype=np.int32).reshape(-1, 3)
+    y = np.zeros_like(x)
+    rc = _load().orc_normal_flow(len(x), _ptr(x), _ptr(tris), len(tris), float(beta),
+                                 float(alpha), int(iters), _ptr(y))
+    if rc != 0:
+        raise ValueError("orc_normal_flow: bad argument")
+    return y
 
 
 def vt_key(a: int, f: int) -> int:

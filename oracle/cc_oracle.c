@@ -1489,3 +1489,108 @@ int64_t orc_get_A(const orc_scene* s, uint64_t* keys, int32_t* colors, int64_t c
 void orc_get_Di(const orc_scene* s, double* out) {
   memcpy(out, s->Di, (size_t)s->n * sizeof(double));
 }
+
+/* ----------------------------------------------------------- normal flow */
+
+/* Target of the globally injective normal flow (Sec. 7.4, Eq. eq:normal flow):
+ * y_0 = x + beta n with n the vertex normal field at x, then `iters` Jacobi steps
+ * y_{i+1}(v) = y_i(v) + alpha L y_i(v) with L the cotangent Laplace-Beltrami
+ * operator of the mesh at y_i. Readings: n_v = normalised sum, over the triangles
+ * at v in increasing index, of (x_b - x_a) x (x_c - x_a) (area weighted; 0 when the
+ * sum vanishes); L y(v) = (1 / (2 A_v)) sum over the triangles at v of
+ * [cot_r (y_q - y_v) + cot_q (y_r - y_v)], (v, q, r) the triangle rotated to start
+ * at v, cot_q the cotangent of its angle at q (0 for a degenerate triangle),
+ * A_v = sum of a third of those triangles' areas (barycentric area; a vertex with
+ * A_v = 0 does not move). */
+static void nf_rotate(const int32_t* t, int32_t v, int32_t* q, int32_t* r) {
+  if (t[0] == v) {
+    *q = t[1];
+    *r = t[2];
+  } else if (t[1] == v) {
+    *q = t[2];
+    *r = t[0];
+  } else {
+    *q = t[0];
+    *r = t[1];
+  }
+}
+
+/* cotangent of the angle at b of triangle (a, b, c) */
+static double nf_cot(const double* a, const double* b, const double* c) {
+  double u[3], w[3], k[3];
+  sub3(u, a, b);
+  sub3(w, c, b);
+  cross3(k, u, w);
+  double s = sqrt(dot3(k, k));
+  if (s == 0.0) return 0.0;
+  return dot3(u, w) / s;
+}
+
+int orc_normal_flow(int32_t n, const double* x, const int32_t* tris, int32_t nt, double beta,
+                    double alpha, int32_t iters, double* y_out) {
+  if (n < 0 || nt < 0 || iters < 0) return -1;
+  /* incident triangles of each vertex, in increasing index */
+  int32_t* cnt = (int32_t*)calloc((size_t)n + 1, sizeof(int32_t));
+  for (int32_t f = 0; f < 3 * nt; ++f) {
+    if (tris[f] < 0 || tris[f] >= n) {
+      free(cnt);
+      return -1;
+    }
+    cnt[tris[f] + 1] += 1;
+  }
+  for (int32_t v = 0; v < n; ++v) cnt[v + 1] += cnt[v];
+  int32_t* inc = (int32_t*)malloc((size_t)(3 * nt > 0 ? 3 * nt : 1) * sizeof(int32_t));
+  int32_t* cur = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  for (int32_t v = 0; v < n; ++v) cur[v] = cnt[v];
+  for (int32_t f = 0; f < nt; ++f)
+    for (int k = 0; k < 3; ++k) inc[cur[tris[3 * f + k]]++] = f;
+  double* ya = (double*)malloc((size_t)(n > 0 ? n : 1) * 3 * sizeof(double));
+  double* yb = (double*)malloc((size_t)(n > 0 ? n : 1) * 3 * sizeof(double));
+  /* y_0 = x + beta n */
+  for (int32_t v = 0; v < n; ++v) {
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int32_t i = cnt[v]; i < cnt[v + 1]; ++i) {
+      const int32_t* t = tris + 3 * inc[i];
+      double e1[3], e2[3], N[3];
+      sub3(e1, x + 3 * t[1], x + 3 * t[0]);
+      sub3(e2, x + 3 * t[2], x + 3 * t[0]);
+      cross3(N, e1, e2);
+      for (int k = 0; k < 3; ++k) s[k] = s[k] + N[k];
+    }
+    double len = sqrt(dot3(s, s));
+    for (int k = 0; k < 3; ++k) {
+      double nk = len > 0.0 ? s[k] / len : 0.0;
+      ya[3 * v + k] = x[3 * v + k] + beta * nk;
+    }
+  }
+  /* Jacobi smoothing steps */
+  for (int32_t it = 0; it < iters; ++it) {
+    for (int32_t v = 0; v < n; ++v) {
+      double L[3] = {0.0, 0.0, 0.0}, A = 0.0;
+      const double* p = ya + 3 * v;
+      for (int32_t i = cnt[v]; i < cnt[v + 1]; ++i) {
+        int32_t q, r;
+        nf_rotate(tris + 3 * inc[i], v, &q, &r);
+        const double *yq = ya + 3 * q, *yr = ya + 3 * r;
+        const double cq = nf_cot(p, yq, yr), cr = nf_cot(p, yr, yq);
+        double dq[3], dr[3], k3[3];
+        sub3(dq, yq, p);
+        sub3(dr, yr, p);
+        for (int k = 0; k < 3; ++k) {
+          L[k] = L[k] + cr * dq[k];
+          L[k] = L[k] + cq * dr[k];
+        }
+        cross3(k3, dq, dr);
+        A = A + (0.5 * sqrt(dot3(k3, k3))) / 3.0;
+      }
+      for (int k = 0; k < 3; ++k)
+        yb[3 * v + k] = A > 0.0 ? p[k] + alpha * (L[k] / (2.0 * A)) : p[k];
+    }
+    double* t = ya;
+    ya = yb;
+    yb = t;
+  }
+  memcpy(y_out, ya, (size_t)n * 3 * sizeof(double));
+  free(cnt); free(inc); free(cur); free(ya); free(yb);
+  return 0;
+}

@@ -120,6 +120,12 @@ int orc_seg_tri_meet(const double* p, const double* q, const double* a, const do
  * closer than tol or an edge meets a triangle it shares no vertex with (all-static
  * pairs skipped; the static flags of the last begin are used). */
 int orc_validate(orc_scene* s, const double* x, double tol);
+/* Target of the globally injective normal flow at x (Sec. 7.4, Eq. eq:normal flow):
+ * y_0 = x + beta n (area-weighted vertex normals), then `iters` Jacobi steps of the
+ * cotangent Laplacian at the current y with intensity alpha. Returns 0, or -1 on a
+ * bad argument. */
+int orc_normal_flow(int32_t n, const double* x, const int32_t* tris, int32_t nt, double beta,
+                    double alpha, int32_t iters, double* y_out);
 
 #ifdef __cplusplus
 }

@@ -809,3 +809,62 @@ def test_ccd_all_checks_every_pair_and_changes_nothing():
     for ia, ib in zip(ta, tb):
         assert ib["ccd_fail"] == ib["n_pf"] and ib["ccd_hits"] == 0
         assert ia["ccd_fail"] <= ib["ccd_fail"]
+
+
+# ------------------------------------------------------------ normal flow
+
+def test_normal_flow_flat_grid_moves_interior_by_beta_exactly():
+    """Flat dyadic grid: the vertex normals are (0, 0, 1) exactly and the cotangent
+    Laplacian of a flat interior vertex vanishes (linear precision), so vertices
+    three rings from the border move by exactly beta after three smoothing steps."""
+    n = 9
+    x, tris, _ = scenes.grid_cloth(n, n, 0.25)
+    beta, alpha = 2.0 ** -7, 2.0 ** -10
+    y = oracle.normal_flow(x, tris, beta, alpha, 3)
+    ij = np.arange(n * n)
+    i, j = ij // n, ij % n
+    deep = (i >= 3) & (i <= n - 4) & (j >= 3) & (j <= n - 4)
+    assert deep.sum() == 9
+    assert np.array_equal(y[deep], x[deep] + [0.0, 0.0, beta])
+    # the border is smoothed inwards (boundary vertices have a non-zero Laplacian)
+    assert np.abs(y[~deep][:, :2] - x[~deep][:, :2]).max() > 0
+
+
+def test_normal_flow_equilateral_triangle_closed_form():
+    """One equilateral triangle of side s: cot 60 = 1/sqrt(3), barycentric area
+    sqrt(3) s^2 / 12, so one step moves a corner by alpha * (2 / sqrt(3)) * (centroid
+    offset * 3) / (2 * area / 3)."""
+    s_ = 0.3
+    x = np.array([[0.0, 0.0, 0.0], [s_, 0.0, 0.0], [0.5 * s_, 0.5 * np.sqrt(3.0) * s_, 0.0]])
+    alpha = 1e-3
+    y = oracle.normal_flow(x, [[0, 1, 2]], 0.0, alpha, 1)
+    A = np.sqrt(3.0) * s_ * s_ / 4.0 / 3.0
+    for v in range(3):
+        q, r = [u for u in range(3) if u != v]
+        L = ((x[q] - x[v]) + (x[r] - x[v])) / np.sqrt(3.0)
+        want = x[v] + alpha * L / (2.0 * A)
+        assert np.allclose(y[v], want, rtol=0, atol=1e-15)
+
+
+def test_normal_flow_sphere_normals_and_mean_curvature():
+    """Icosphere of radius R: vertex normals are radial to within the mesh's
+    facet angle, y_0 sits beta outside, and the cotangent Laplacian of the positions
+    is the mean-curvature normal -2/R n (to discretisation error)."""
+    R = 0.1
+    xs, ts = scenes.icosphere(3, R)[:2]
+    nrm = xs / np.linalg.norm(xs, axis=1, keepdims=True)
+    beta = 2e-3
+    y0 = oracle.normal_flow(xs, ts, beta, 0.0, 0)
+    assert np.allclose(np.linalg.norm(y0, axis=1), R + beta, rtol=0, atol=2e-5)
+    d = y0 - xs
+    assert np.degrees(np.arccos(np.clip((d / beta * nrm).sum(1), -1, 1))).max() < 2.0
+    a = 1e-8
+    L = (oracle.normal_flow(xs, ts, 0.0, a, 1) - xs) / a
+    ln = (L * nrm).sum(1)
+    assert abs(ln.mean() - (-2.0 / R)) < 0.01 * (2.0 / R)
+    assert np.linalg.norm(L - ln[:, None] * nrm, axis=1).max() < 0.05 * (2.0 / R)
+
+
+def test_normal_flow_rejects_bad_index():
+    with pytest.raises(ValueError):
+        oracle.normal_flow(np.zeros((3, 3)), [[0, 1, 3]], 0.1, 0.1, 1)
