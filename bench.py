@@ -33,6 +33,8 @@ WORKLOADS = {
     3: "8 stacked cube surfaces, rigid velocities, ",
     4: "hair strands on a sphere, wind impulse, ",
     6: "particle pile on a static ground: vertex-vertex and vertex-triangle pairs, ",
+    7: "normal flow of two spheres 1 cm apart: target = outward offset of 1 cm along the "
+       "vertex normals and 3 cotangent smoothing steps, built on the device each step, ",
 }
 
 
@@ -212,14 +214,17 @@ def main():
         prm["backward"] = "jacobi"
     dev = "cuda"
     x = torch.as_tensor(sc["x"], device=dev)
-    xt = torch.as_tensor(sc["xt"], device=dev)
     w = torch.as_tensor(sc["w"], device=dev)
     tris = torch.as_tensor(sc["tris"], dtype=torch.int32, device=dev)
     edges = torch.as_tensor(sc["edges"], dtype=torch.int32, device=dev)
     ctx = cc.Context(0)
+    flow = sc.get("flow")
+    xt = None if flow else torch.as_tensor(sc["xt"], device=dev)
 
     def step():
-        return cc.collide_step(ctx, x, xt, w, tris, edges, time_kernels=True, **prm)
+        # a normal-flow frame builds its target on the device first (part of the step)
+        y = cc.normal_flow_target(ctx, x, tris, **flow) if flow else xt
+        return cc.collide_step(ctx, x, y, w, tris, edges, time_kernels=True, **prm)
 
     for i in range(args.warmup):
         out, st = step()
@@ -495,8 +500,14 @@ def cpu_baseline(sc, prm, iters_per_step, sample_iters):
     """The FP64 oracle, single-threaded on the host, over the first `sample_iters`
     iterations of the same step, scaled by the step's iteration count."""
     import oracle
+    t_flow = 0.0
+    xt = sc.get("xt")
+    if xt is None:  # a normal-flow frame: the oracle builds the target too
+        t_flow = time.perf_counter()
+        xt = oracle.normal_flow(sc["x"], sc["tris"], **sc["flow"])
+        t_flow = time.perf_counter() - t_flow
     s = oracle.Scene(sc["w"], sc["tris"], sc["edges"], **prm)
-    s.begin(sc["x"], sc["xt"])
+    s.begin(sc["x"], xt)
     t0 = time.perf_counter()
     done = 0
     pairs = 0
@@ -508,7 +519,8 @@ def cpu_baseline(sc, prm, iters_per_step, sample_iters):
             break
     dt = time.perf_counter() - t0
     per_iter = dt / done
-    return {"value": round(1.0 / (per_iter * iters_per_step), 6), "unit": "steps/s", "cores": 1,
+    return {"value": round(1.0 / (t_flow + per_iter * iters_per_step), 6), "unit": "steps/s",
+            "cores": 1,
             "kind": "oracle",
             "sample": f"first {done} of {iters_per_step} iterations of one step "
                       f"({dt:.1f} s, {pairs} pair updates), scaled to the full step",

@@ -206,6 +206,25 @@ typedef struct cc_scene {
 int cc_collide_step_batched(cc_context* ctx, const cc_scene* scenes, int32_t n_scenes,
                             const cc_params* params, cc_stats* stats, void* stream);
 
+/* ---- target of the globally injective normal flow ---------------------------
+ * Sec. 7.4, Eq. eq:normal flow: y = x + beta n, n the vertex normals at x (normalised
+ * sums of the cross products (x_b - x_a) x (x_c - x_a) of the vertex's triangles, an
+ * area weighting; 0 where that sum vanishes), then `iters` Jacobi steps
+ * y(v) <- y(v) + alpha (L y)(v) of the cotangent Laplace-Beltrami operator at the
+ * current y: (L y)(v) = 1/(2 A_v) sum over the triangles (v, q, r) at v of
+ * cot_r (y_q - y_v) + cot_q (y_r - y_v), A_v = a third of their areas (a vertex with
+ * A_v = 0 keeps its position). The paper uses three steps. The result is the target
+ * y^[k+1] that cc_collide_step then makes intersection free.
+ * x (n_verts x 3 FP64), tris (n_tris x 3 int32) and y (n_verts x 3, written) are
+ * device pointers; y must not alias x. Sums over a vertex's triangles run in
+ * increasing triangle index, so the result does not depend on the launch. The call
+ * returns when y is complete (it synchronises `stream`). Errors: CC_EINVAL (NULL
+ * pointer with a non-zero size, negative size or iters, non-finite beta or alpha,
+ * a vertex index outside [0, n_verts)), CC_ENOMEM, CC_EHIP. */
+int cc_normal_flow_target(cc_context* ctx, const double* x, int32_t n_verts,
+                          const int32_t* tris, int32_t n_tris, double beta, double alpha,
+                          int32_t iters, double* y, void* stream);
+
 /* ---- serving: resident scenes admitted by HBM budget ------------------------
  * A resident scene keeps its topology, masses, current state x and workspace on
  * the device between steps, so each step starts from the previous step's result.

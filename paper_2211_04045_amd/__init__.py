@@ -15,7 +15,7 @@ from ._lib import (CC_CCD_ALL, CC_EDGE_LEN, CC_MIXED, CC_TIME_KERNELS, CC_TRACE,
                    CC_VALIDATE_INPUT, CCError, IterInfo, Params, SceneDesc, Stats)
 
 __all__ = ["Context", "Solver", "Server", "collide_step", "collide_step_batched", "params",
-           "edges_from_tris", "CC_EDGE_LEN", "CC_TIME_KERNELS",
+           "edges_from_tris", "normal_flow_target", "CC_EDGE_LEN", "CC_TIME_KERNELS",
            "CC_TRACE", "CC_MIXED", "CC_VALIDATE_INPUT", "CC_CCD_ALL", "CCError"]
 
 
@@ -75,6 +75,20 @@ def params(**over) -> Params:
         else:
             setattr(p, k, v)
     return p
+
+
+def normal_flow_target(ctx: "Context", x, tris, beta: float, alpha: float, iters: int = 3):
+    """Target y^[k+1] of the globally injective normal flow at x (cc_normal_flow_target):
+    offset beta along the vertex normals, then `iters` cotangent-Laplacian Jacobi
+    steps of intensity alpha. Returns a new (N, 3) float64 tensor."""
+    torch = _torch()
+    x = _dev(x, torch.float64, 3, "x").reshape(-1, 3)
+    tris = _dev(tris, torch.int32, 3, "tris").reshape(-1, 3)
+    y = torch.empty_like(x)
+    _check(ctx.lib.cc_normal_flow_target(ctx.h, _ptr(x), x.shape[0], _ptr(tris), tris.shape[0],
+                                         float(beta), float(alpha), int(iters), _ptr(y),
+                                         _stream()), "cc_normal_flow_target")
+    return y
 
 
 def edges_from_tris(tris):

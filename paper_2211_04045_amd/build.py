@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcc.so")
-SOURCES = ["api.hip", "step.hip", "lbvh.hip", "serve.hip"]
+SOURCES = ["api.hip", "step.hip", "lbvh.hip", "serve.hip", "flow.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # every FP64 expression is evaluated as written (no fused multiply-add)
          "-ffp-contract=off",

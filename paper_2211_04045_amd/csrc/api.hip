@@ -862,7 +862,17 @@ void cc_context_destroy(cc_context* ctx) {
   server_destroy(ctx);
   if (ctx->cached) cc_solver_destroy(ctx->cached);
   if (ctx->batched) cc_solver_destroy(ctx->batched);
+  cc::flow_free(ctx->flow);
   delete ctx;
+}
+
+int cc_normal_flow_target(cc_context* ctx, const double* x, int32_t n_verts,
+                          const int32_t* tris, int32_t n_tris, double beta, double alpha,
+                          int32_t iters, double* y, void* stream) {
+  if (!ctx) return CC_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return CC_EHIP;
+  return cc::normal_flow_target(ctx, x, n_verts, tris, n_tris, beta, alpha, iters, y,
+                                as_stream(stream));
 }
 
 int cc_solver_create(cc_context* ctx, int32_t n, const double* inv_mass, const int32_t* tris,

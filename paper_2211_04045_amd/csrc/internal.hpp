@@ -100,12 +100,16 @@ struct Timer {
 }  // namespace cc
 
 struct cc_server;  // resident-scene serving state (serve.hip)
+namespace cc {
+struct FlowWork;  // normal-flow target workspace (flow.hip)
+}
 
 struct cc_context {
   int device = 0;
   cc_server* server = nullptr;
   cc_solver* cached = nullptr;   // workspace reused by cc_collide_step
   cc_solver* batched = nullptr;  // multi-scene workspace reused by cc_collide_step_batched
+  cc::FlowWork* flow = nullptr;  // normal-flow target workspace
 };
 
 namespace cc {
@@ -268,6 +272,10 @@ int launch_check_finite(cc_solver* s, const double* xa, const double* xb, int32_
                         hipStream_t st);
 int launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 int launch_particles(cc_solver* s, int32_t sg, hipStream_t st);
+int normal_flow_target(cc_context* ctx, const double* x, int32_t n, const int32_t* tris,
+                       int32_t nt, double beta, double alpha, int32_t iters, double* y,
+                       hipStream_t st);
+void flow_free(FlowWork* w);
 int launch_setup(cc_solver* s, int32_t seg, const double* x_prev, const double* x_tilde,
                  hipStream_t st);
 int launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t st);

@@ -379,8 +379,47 @@ def sand_pile(nx: int = 32, ny: int = 32, nz: int = 30, spacing: float = 2e-3,
                 params=dict(max_iters=2048))
 
 
+def torus(nu: int, nv: int, R: float, r: float):
+    """Torus surface: nu vertices around the ring, nv around the tube, two triangles
+    per quad, outward-facing (counter-clockwise seen from outside)."""
+    u = np.arange(nu) * (2.0 * np.pi / nu)
+    v = np.arange(nv) * (2.0 * np.pi / nv)
+    uu, vv = np.meshgrid(u, v, indexing="ij")
+    x = np.stack([(R + r * np.cos(vv)) * np.cos(uu), (R + r * np.cos(vv)) * np.sin(uu),
+                  r * np.sin(vv)], axis=-1).reshape(-1, 3)
+    i, j = np.meshgrid(np.arange(nu), np.arange(nv), indexing="ij")
+    a = (i * nv + j).ravel()
+    b = (((i + 1) % nu) * nv + j).ravel()
+    c = (((i + 1) % nu) * nv + (j + 1) % nv).ravel()
+    d = (i * nv + (j + 1) % nv).ravel()
+    tris = np.concatenate([np.stack([a, b, c], 1), np.stack([a, c, d], 1)]).astype(np.int32)
+    return x, tris, edges_from_tris(tris).astype(np.int32)
+
+
+def normal_flow_spheres(subdiv: int = 5, radius: float = 0.05, gap: float = 0.01,
+                        beta_gaps: float = 1.0, smooth: float = 0.1, iters: int = 3):
+    """Globally injective normal flow (a stand-in for the benchmark meshes of the
+    paper's normal-flow examples, which are not available): two icospheres `gap`
+    apart, a positive flow that moves both surfaces outward by beta = beta_gaps * gap,
+    so the spheres grow into each other and must stop face to face; then
+    alpha = smooth * (shortest edge)^2 and `iters` Jacobi smoothing steps (small
+    enough for the explicit steps not to overshoot). The target is computed by the flow
+    code (library or oracle) from these parameters."""
+    xs, ts = icosphere(subdiv, radius)[:2]
+    es = edges_from_tris(ts)
+    a = xs - [radius + 0.5 * gap, 0.0, 0.0]
+    b = xs + [radius + 0.5 * gap, 0.0, 0.0]
+    x, tris, edges = _merge([(a, ts, es), (b, ts, es)])
+    el = np.linalg.norm(x[edges[:, 0]] - x[edges[:, 1]], axis=1).min()
+    w = lumped_inverse_mass(x, tris, edges, np.ones(len(x), bool))
+    return dict(name=f"normal_flow_spheres_s{subdiv}", x=x, w=w, tris=tris, edges=edges,
+                flow=dict(beta=beta_gaps * gap, alpha=smooth * el * el, iters=iters),
+                params=dict(max_iters=2048))
+
+
 def config(i: int, small: bool = False):
-    """The single-scene workloads (1-4, and 6: the particle pile), full size or a
+    """The single-scene workloads (1-4; 6: the particle pile; 7: normal flow of two spheres,
+    whose target comes from the flow code), full size or a
     small variant of the same structure (the small variants finish in seconds on the
     oracle)."""
     if i == 1:
@@ -393,6 +432,8 @@ def config(i: int, small: bool = False):
         return hair(n_strands=64 if small else 10000, segs=8 if small else 32)
     if i == 6:
         return sand_pile(*((6, 6, 5) if small else (32, 32, 30)))
+    if i == 7:
+        return normal_flow_spheres(3 if small else 5)
     raise ValueError(i)
 
 

@@ -620,3 +620,68 @@ def test_several_sweeps_lockstep(cc, ctx, cfg, backward, sweeps):
     sc = scenes.config(cfg, small=True)
     n, ref, gpu = _lockstep(cc, ctx, sc, 150, gs_sweeps=sweeps, backward=backward)
     assert n >= 1
+
+
+# ------------------------------------------------------- normal-flow target
+
+def _flow_meshes():
+    xs, ts = scenes.icosphere(3, 0.1)[:2]
+    rng = np.random.default_rng(31)
+    xr = xs + rng.normal(size=xs.shape) * 2e-3
+    xg, tg, _ = scenes.grid_cloth(17, 9, 0.01)
+    xt_, tt_, _ = scenes.torus(48, 16, 0.1, 0.02)
+    return [("icosphere", xs, ts), ("rough icosphere", xr, ts), ("grid", xg, tg),
+            ("torus", xt_, tt_)]
+
+
+@pytest.mark.parametrize("beta,alpha,iters", [(0.004, 2e-6, 3), (-0.03, 1e-5, 3), (0.0, 5e-6, 1),
+                                              (0.01, 0.0, 0)])
+def test_normal_flow_target_matches_oracle(cc, ctx, beta, alpha, iters):
+    """The target of the globally injective normal flow, bit-identical to the oracle's on
+    spheres, a rough sphere, an open grid and a torus."""
+    for name, x, t in _flow_meshes():
+        got = cc.normal_flow_target(ctx, x, t, beta, alpha, iters).cpu().numpy()
+        want = oracle.normal_flow(x, t, beta, alpha, iters)
+        assert np.array_equal(got, want), name
+
+
+def test_normal_flow_target_rejects_bad_input(cc, ctx):
+    x, t = scenes.icosphere(1, 1.0)[:2]
+    bad = t.copy()
+    bad[0, 0] = len(x)
+    with pytest.raises(cc.CCError):
+        cc.normal_flow_target(ctx, x, bad, 0.1, 0.1, 3)
+    with pytest.raises(cc.CCError):
+        cc.normal_flow_target(ctx, x, t, float("nan"), 0.1, 3)
+
+
+def test_normal_flow_frame_matches_oracle(cc, ctx):
+    """One frame of the normal-flow workload (small torus, inward flow through the
+    tube): the target and the collision step's result bit-identical to the oracle's,
+    and the result intersection free."""
+    sc = scenes.config(7, small=True)
+    f = sc["flow"]
+    y = cc.normal_flow_target(ctx, sc["x"], sc["tris"], **f)
+    want_y = oracle.normal_flow(sc["x"], sc["tris"], **f)
+    assert np.array_equal(y.cpu().numpy(), want_y)
+    got, st = cc.collide_step(ctx, sc["x"], y, sc["w"], sc["tris"], sc["edges"], **sc["params"])
+    want, n, _ = oracle.collide_step(dict(sc, xt=want_y))
+    assert st["iters"] == n and np.array_equal(got.cpu().numpy(), want)
+    assert _intersection_free(got.cpu().numpy(), sc["tris"], sc["edges"])
+
+
+def test_normal_flow_frame_full_size_matches_oracle(cc, ctx):
+    """The full normal-flow frame (two icospheres of 10,242 vertices growing into each
+    other): target and result bit-identical to the oracle's; the spheres stop face to
+    face, about delta apart."""
+    sc = scenes.config(7)
+    f = sc["flow"]
+    y = cc.normal_flow_target(ctx, sc["x"], sc["tris"], **f)
+    want_y = oracle.normal_flow(sc["x"], sc["tris"], **f)
+    assert np.array_equal(y.cpu().numpy(), want_y)
+    got, st = cc.collide_step(ctx, sc["x"], y, sc["w"], sc["tris"], sc["edges"], **sc["params"])
+    want, n, _ = oracle.collide_step(dict(sc, xt=want_y))
+    x = got.cpu().numpy()
+    assert st["iters"] == n and st["status"] == 0 and np.array_equal(x, want)
+    h = len(x) // 2
+    assert 0.5e-3 < x[h:, 0].min() - x[:h, 0].max() < 2e-3
