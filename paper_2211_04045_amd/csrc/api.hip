@@ -387,6 +387,7 @@ int seg_add(cc_solver* s, int32_t nv, const double* inv_mass, const int32_t* tri
             const int32_t* edges, int32_t ne, int32_t max_iters, int32_t* out, hipStream_t st) {
   if (nv < 0 || nf < 0 || ne < 0 || !out) return CC_EINVAL;
   if ((nf > 0 && !tris) || (ne > 0 && !edges)) return CC_EINVAL;
+  ++s->gen;
   int32_t sg = -1;
   for (int32_t i = 0; i < (int32_t)s->segs.size(); ++i)
     if (!s->segs[i].live && !s->segs[i].pending) {
@@ -465,6 +466,7 @@ int seg_add(cc_solver* s, int32_t nv, const double* inv_mass, const int32_t* tri
 
 int seg_remove(cc_solver* s, int32_t sg, hipStream_t st) {
   if (sg < 0 || sg >= (int32_t)s->segs.size() || !s->segs[sg].live) return CC_EINVAL;
+  ++s->gen;
   Seg& g = s->segs[sg];
   CC_TRY(launch_fill_i32(s->vseg + g.vb, g.nv, -1, st));
   CC_TRY(launch_fill_i32(s->eseg + g.eb, g.ne, -1, st));
@@ -499,6 +501,7 @@ static void release_all_pending(cc_solver* s) {
 // rows at y^[k+1] and their colouring. rc[i] gets each segment's result.
 int seg_begin(cc_solver* s, const int32_t* sgs, int32_t k, const double* const* x_prev,
               const double* const* x_tilde, int* rc, hipStream_t st) {
+  ++s->gen;  // new positions: the next search builds its tree anew
   CC_HIP(hipMemsetAsync(&s->dc->n_rows, 0, sizeof(unsigned long long), st));
   std::vector<int32_t> ok;
   for (int32_t i = 0; i < k; ++i) {
@@ -582,7 +585,7 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
     for (int attempt = 0;; ++attempt) {
       int64_t nf = 0;
       CC_TRY(lbvh_search(s, (int32_t)sel.size(), s->x, p.d_max, s->P + n_old, s->dP + n_old,
-                         s->capP - n_old, &nf, st));
+                         s->capP - n_old, &nf, st, true));
       if (n_old + nf <= s->capP) {
         n_search = nf;
         break;
@@ -1046,6 +1049,7 @@ int cc_solver_set_state(cc_solver* s, const double* x, const double* y, const do
                         double D, const uint64_t* P, int64_t n_p, void* stream) {
   if (!s || n_p < 0 || (n_p > 0 && !P)) return CC_EINVAL;
   if (!s->begun) return CC_ESTATE;
+  ++s->gen;  // x set from outside: no tree reuse
   hipStream_t st = as_stream(stream);
   const int32_t n = s->segs[0].nv;
   size_t n3 = sizeof(double) * 3 * n;
@@ -1102,7 +1106,7 @@ int cc_solver_search(cc_solver* s, const double* x, double dmax, uint64_t* keys,
   // the static flags come from the last begin; without one every vertex counts as free
   if (!s->begun && nv) CC_HIP(hipMemsetAsync(s->stat, 0, nv, st));
   s->sel_host[0].seg = 0;
-  return lbvh_search(s, 1, x, dmax, keys, nullptr, keys ? cap : 0, n, st);
+  return lbvh_search(s, 1, x, dmax, keys, nullptr, keys ? cap : 0, n, st, false);
 }
 
 int cc_solver_stats(cc_solver* s, cc_stats* out) {

@@ -69,7 +69,7 @@ struct Counters {
   unsigned long long hits;      // continuous-test contacts among the failures
   unsigned long long et;        // input check: an edge meets a triangle
   unsigned long long ncert;     // certificate: pairs queued for the continuous test
-  unsigned long long pad[1];
+  unsigned long long ncand;     // search: node records read
 };
 
 // Device buffers of a linear BVH over n leaves (n-1 internal nodes), allocated
@@ -171,6 +171,11 @@ struct cc_solver {
   int32_t* eseg = nullptr;  // segment of each edge (-1 = none)
   int32_t* plist = nullptr; // per segment, at its vertex base: its particles' vertex ids
   bool erows_dirty = true;  // the union of edge-row colour buckets needs a rebuild
+  // tree reuse: gen changes with every change of the scenes or their state from
+  // outside the iteration; the last build's scene list and gen
+  uint64_t gen = 0, bvh_gen = ~0ull;
+  std::vector<int32_t> bvh_sel;
+  double bvh_q0 = 0.0;  // node records the traversal read right after the last build
   // topology and masses
   double* w = nullptr;
   int32_t* tris = nullptr;
@@ -255,8 +260,10 @@ void bvh_free(cc_solver* s);
 // dmax; appends pair keys (solver-wide ids) to out and their squared distances at
 // x to outd (if not NULL; capacity cap); *n gets the total number found (may
 // exceed cap: caller regrows).
+// refit_ok: the caller is the iteration loop, whose x only moves between searches;
+// the tree of its last build is refitted when the same scenes are searched again.
 int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64_t* out,
-                double* outd, int64_t cap, int64_t* n, hipStream_t st);
+                double* outd, int64_t cap, int64_t* n, hipStream_t st, bool refit_ok);
 // Input check of the selected segments at x (tolerance tol): *bad = 1 when a
 // vertex-triangle or edge-edge pair is closer than tol or an edge meets a
 // triangle it shares no vertex with.

@@ -758,6 +758,7 @@ __device__ __forceinline__ bool candidate(const TravArgs& A, int kind, int32_t p
   return true;
 }
 
+constexpr double kRefitSlack = 1.3;         // node reads allowed to a refitted tree
 constexpr int kWaves = kTravThreads / 64;  // waves per traversal block
 constexpr int kGroup = 16;                  // lanes sharing one traversal (a power of 2, <= 64)
 constexpr int kGroups = 64 / kGroup;        // traversals per wave
@@ -795,7 +796,8 @@ __device__ __forceinline__ void flush_out(WaveLds& L, int wv, int& no, const Tra
 // The exact test of n <= 64 queued candidates, one per lane; found pairs join the
 // wave's held pairs (no, wave-uniform), written out from 128 on.
 __device__ __forceinline__ void drain(WaveLds& L, int wv, int head, int n, int kind, int& no,
-                                      const TravArgs& A) {
+                                      unsigned& ntested, const TravArgs& A) {
+  ntested += (unsigned)n;
   const int lane = __lane_id();
   bool found = false;
   uint64_t key = 0;
@@ -900,6 +902,8 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
   L.qi[wv][2][lane] = qv1;
   int head = 0, qn = 0;  // candidate ring: first entry, entries queued (wave-uniform)
   int no = 0;            // found pairs held (wave-uniform)
+  unsigned ntested = 0;  // candidates tested by the wave
+  unsigned nvisit = 0;   // node records this lane's group read (counted by its first lane)
   // a scene with one triangle: its vertices meet the leaf itself (one edge or one
   // particle pairs with nothing)
   {
@@ -914,7 +918,7 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
   }
   __builtin_amdgcn_wave_barrier();
   if (qn == 64) {
-    drain(L, wv, head, 64, kind, no, A);
+    drain(L, wv, head, 64, kind, no, ntested, A);
     qn = 0;
     __builtin_amdgcn_wave_barrier();
   }
@@ -941,6 +945,7 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
     if (valid) {
       --sp;
       i = L.stack[wv][grp][sp];
+      if (gl == 0) ++nvisit;
     }
     float4 rb0[4], rb1[4];
 #pragma unroll
@@ -983,15 +988,19 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
       qn += __popcll(ml);
       __builtin_amdgcn_wave_barrier();
       while (qn >= 64) {
-        drain(L, wv, head, 64, kind, no, A);
+        drain(L, wv, head, 64, kind, no, ntested, A);
         head = (head + 64) & (kQueue - 1);
         qn -= 64;
         __builtin_amdgcn_wave_barrier();
       }
     }
   }
-  if (qn > 0) drain(L, wv, head, qn, kind, no, A);
+  if (qn > 0) drain(L, wv, head, qn, kind, no, ntested, A);
   if (no > 0) flush_out(L, wv, no, A);
+  // node records read by the wave's groups: the measure of the tree's quality
+  unsigned long long nv = nvisit;
+  for (int o = 32; o >= 1; o >>= 1) nv += __shfl_xor(nv, o);
+  if (lane == 0 && nv) atomicAdd(&A.cnt->ncand, nv);
 }
 
 // ------------------------------------------------------- input check (edges)
@@ -1061,6 +1070,44 @@ __global__ void __launch_bounds__(kTravThreads) k_validate_et(EtArgs A) {
   if (bad) atomicOr(&A.cnt->et, 1ull);
 }
 
+// Refit of a kept tree: the leaf boxes of the three trees at x, in their sorted
+// order (the sort, the hierarchy and the query orders of the last build stay).
+__global__ void k_leaf_refresh(const double* __restrict__ x, const int32_t* __restrict__ tris,
+                               const int32_t* __restrict__ edges, int32_t mt, int32_t me,
+                               int32_t mp, double infl, LeafOut lt, LeafOut le, LeafOut lp) {
+  const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  V3 lo, hi;
+  float4 *plo, *phi;
+  int32_t i;
+  if (g < mt) {
+    i = g;
+    const int32_t f = lt.prim[i];
+    V3 a = ld3(x, tris[3 * f]), b = ld3(x, tris[3 * f + 1]), c = ld3(x, tris[3 * f + 2]);
+    lo = V3{fmin(fmin(a.x, b.x), c.x), fmin(fmin(a.y, b.y), c.y), fmin(fmin(a.z, b.z), c.z)};
+    hi = V3{fmax(fmax(a.x, b.x), c.x), fmax(fmax(a.y, b.y), c.y), fmax(fmax(a.z, b.z), c.z)};
+    plo = lt.lo;
+    phi = lt.hi;
+  } else if (g < mt + me) {
+    i = g - mt;
+    const int32_t e = le.prim[i];
+    V3 a = ld3(x, edges[2 * e]), b = ld3(x, edges[2 * e + 1]);
+    lo = V3{fmin(a.x, b.x), fmin(a.y, b.y), fmin(a.z, b.z)};
+    hi = V3{fmax(a.x, b.x), fmax(a.y, b.y), fmax(a.z, b.z)};
+    plo = le.lo;
+    phi = le.hi;
+  } else if (g < mt + me + mp) {
+    i = g - mt - me;
+    lo = ld3(x, lp.prim[i]);
+    hi = lo;
+    plo = lp.lo;
+    phi = lp.hi;
+  } else {
+    return;
+  }
+  plo[i] = make_float4(lo_out(lo.x - infl), lo_out(lo.y - infl), lo_out(lo.z - infl), 0.f);
+  phi[i] = make_float4(hi_out(hi.x + infl), hi_out(hi.y + infl), hi_out(hi.z + infl), 0.f);
+}
+
 // ---------------------------------------------------------------- host side
 
 template <class T>
@@ -1103,6 +1150,7 @@ static void bvh_free_one(Bvh& b) {
 }
 
 int bvh_alloc(cc_solver* s) {
+  ++s->gen;  // fresh tree memory holds no tree
   const int64_t m = (int64_t)s->capF + s->capE + s->capPt;
   const int64_t mall = m + s->capV;  // triangles, edges, particles and vertices share one sort
   CC_TRY(bvh_alloc_one(s->tree_t, s->capF));
@@ -1154,8 +1202,38 @@ static RefitView refit_view(Bvh& b) {
                    b.pre, b.suf, b.blk};
 }
 
+// Node boxes from the leaf boxes (fence-free refit), then the 4-wide records.
+static int refit_and_widen(cc_solver* s, int32_t mt, int32_t me, int32_t mp, hipStream_t st) {
+  Bvh& bt = s->tree_t;
+  Bvh& be = s->tree_e;
+  Bvh& bp = s->tree_p;
+  RefitView ra = refit_view(bt), rbv = refit_view(be);
+  if (mt < 2) ra.n = 0;
+  if (me < 2) rbv.n = 0;
+  const int32_t nba = (ra.n + kBlk - 1) / kBlk, nbb = (rbv.n + kBlk - 1) / kBlk;
+  const int64_t ninternal = (mt > 1 ? mt - 1 : 0) + (me > 1 ? me - 1 : 0);
+  if (nba + nbb > 0) {
+    k_refit_block<<<nba + nbb, kBlk, 0, st>>>(ra, rbv, nba);
+    k_blk_sparse<<<2, 1024, 0, st>>>(ra, rbv);
+    k_refit_top<<<blocks(ninternal, 256), 256, 0, st>>>(ra, rbv);
+  }
+  if (mp > 1) {  // the particle tree, refit on its own
+    RefitView rc = refit_view(bp), rnone = refit_view(bp);
+    rnone.n = 0;
+    const int32_t nbc = (mp + kBlk - 1) / kBlk;
+    k_refit_block<<<nbc, kBlk, 0, st>>>(rc, rnone, nbc);
+    k_blk_sparse<<<1, 1024, 0, st>>>(rc, rnone);
+    k_refit_top<<<blocks(mp - 1, 256), 256, 0, st>>>(rc, rnone);
+  }
+  if (mt > 1) k_wide<<<blocks(mt - 1, 256), 256, 0, st>>>(bt.node, bt.wide, mt - 1);
+  if (me > 1) k_wide<<<blocks(me - 1, 256), 256, 0, st>>>(be.node, be.wide, me - 1);
+  if (mp > 1) k_wide<<<blocks(mp - 1, 256), 256, 0, st>>>(bp.node, bp.wide, mp - 1);
+  CC_HIP(hipGetLastError());
+  return CC_OK;
+}
+
 int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64_t* out,
-                double* outd, int64_t cap, int64_t* nfound, hipStream_t st) {
+                double* outd, int64_t cap, int64_t* nfound, hipStream_t st, bool refit_ok) {
   // compact offsets of the selected segments' vertices, triangles, edges and particles
   int32_t mv = 0, mt = 0, me = 0, mp = 0;
   for (int32_t r = 0; r < nsel; ++r) {
@@ -1180,9 +1258,30 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
   const double infl = 0.5 * dmax;
   CC_HIP(hipMemsetAsync(&s->dc->n_out, 0, sizeof(unsigned long long), st));
   CC_HIP(hipMemsetAsync(&s->dc->err, 0, sizeof(unsigned long long), st));
+  CC_HIP(hipMemsetAsync(&s->dc->ncand, 0, sizeof(unsigned long long), st));
   *nfound = 0;
   const int64_t m = (int64_t)mt + me + mp;
-  if (m > 0) {
+  // the tree of the last build serves again (refit) when the same scenes, in the same
+  // order, are searched and none of them changed since
+  bool refit = refit_ok && s->bvh_gen == s->gen && (int32_t)s->bvh_sel.size() == nsel;
+  for (int32_t r = 0; refit && r < nsel; ++r) refit = s->bvh_sel[r] == s->sel_host[r].seg;
+  if (refit_ok) {
+    s->bvh_gen = s->gen;
+    s->bvh_sel.resize(nsel);
+    for (int32_t r = 0; r < nsel; ++r) s->bvh_sel[r] = s->sel_host[r].seg;
+  } else {
+    s->bvh_gen = ~0ull;  // a build for another purpose: the next search builds anew
+  }
+  Bvh& bt = s->tree_t;
+  Bvh& be = s->tree_e;
+  Bvh& bp = s->tree_p;
+  if (m > 0 && refit) {
+    k_leaf_refresh<<<blocks(m, 256), 256, 0, st>>>(
+        x, s->tris, s->edges, mt, me, mp, infl, LeafOut{bt.leaf_lo, bt.leaf_hi, bt.leaf_prim, nullptr},
+        LeafOut{be.leaf_lo, be.leaf_hi, be.leaf_prim, nullptr},
+        LeafOut{bp.leaf_lo, bp.leaf_hi, bp.leaf_prim, nullptr});
+    CC_TRY(refit_and_widen(s, mt, me, mp, st));
+  } else if (m > 0) {
     CC_HIP(hipMemcpyAsync(s->sel_dev, s->sel_host, sizeof(SelDev) * (nsel + 1),
                           hipMemcpyHostToDevice, st));
     const int64_t mall = m + mv;
@@ -1203,9 +1302,6 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
       std::swap(ki, ko);
       std::swap(vi, vo);
     }
-    Bvh& bt = s->tree_t;
-    Bvh& be = s->tree_e;
-    Bvh& bp = s->tree_p;
     bt.n = mt;
     be.n = me;
     bp.n = mp;
@@ -1227,26 +1323,9 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
     k_seg_roots<<<blocks(nsel, 256), 256, 0, st>>>(s->sel_dev, nsel, mt, me, mp, bt.range,
                                                    bt.leaf_prim, be.range, be.leaf_prim, bp.range,
                                                    bp.leaf_prim, s->root_t, s->root_e, s->root_p);
-    RefitView ra = refit_view(bt), rbv = refit_view(be);
-    if (mt < 2) ra.n = 0;
-    if (me < 2) rbv.n = 0;
-    const int32_t nba = (ra.n + kBlk - 1) / kBlk, nbb = (rbv.n + kBlk - 1) / kBlk;
-    if (nba + nbb > 0) {
-      k_refit_block<<<nba + nbb, kBlk, 0, st>>>(ra, rbv, nba);
-      k_blk_sparse<<<2, 1024, 0, st>>>(ra, rbv);
-      k_refit_top<<<blocks(ninternal, 256), 256, 0, st>>>(ra, rbv);
-    }
-    if (mp > 1) {  // the particle tree, refit on its own
-      RefitView rc = refit_view(bp), rnone = refit_view(bp);
-      rnone.n = 0;
-      const int32_t nbc = (mp + kBlk - 1) / kBlk;
-      k_refit_block<<<nbc, kBlk, 0, st>>>(rc, rnone, nbc);
-      k_blk_sparse<<<1, 1024, 0, st>>>(rc, rnone);
-      k_refit_top<<<blocks(mp - 1, 256), 256, 0, st>>>(rc, rnone);
-    }
-    if (mt > 1) k_wide<<<blocks(mt - 1, 256), 256, 0, st>>>(bt.node, bt.wide, mt - 1);
-    if (me > 1) k_wide<<<blocks(me - 1, 256), 256, 0, st>>>(be.node, be.wide, me - 1);
-    if (mp > 1) k_wide<<<blocks(mp - 1, 256), 256, 0, st>>>(bp.node, bp.wide, mp - 1);
+    CC_TRY(refit_and_widen(s, mt, me, mp, st));
+  }
+  if (m > 0) {
     TravArgs A;
     A.tt = TravTree{mt, bt.wide, bt.root, bt.leaf_prim};
     A.te = TravTree{me, be.wide, be.root, be.leaf_prim};
@@ -1285,6 +1364,14 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
   CC_HIP(hipStreamSynchronize(st));
   if (s->hc->err & 2ull) return CC_EOVERFLOW;
   *nfound = (int64_t)s->hc->n_out;
+  // tree quality: node records read by the traversal; a refitted tree whose
+  // traversal reads 30 % more of them than right after its build is built anew at the
+  // next search
+  if (refit_ok && m > 0) {
+    const double q = (double)s->hc->ncand;
+    if (!refit) s->bvh_q0 = q;
+    else if (q > kRefitSlack * s->bvh_q0) s->bvh_gen = ~0ull;
+  }
   // algorithmic bytes of the traversal: queries, node records, output keys
   s->st.kernel_bytes[CC_K_SEARCH] += 24.0 * mv + 8.0 * me + 28.0 * mp + 64.0 * (double)m +
                                      8.0 * (double)*nfound;
@@ -1299,7 +1386,7 @@ int lbvh_validate(cc_solver* s, int32_t nsel, const double* x, double tol, int* 
   *bad = 0;
   const double kb = s->st.kernel_bytes[CC_K_SEARCH];
   int64_t n = 0;
-  const int rc = lbvh_search(s, nsel, x, tol, nullptr, nullptr, 0, &n, st);
+  const int rc = lbvh_search(s, nsel, x, tol, nullptr, nullptr, 0, &n, st, false);
   s->st.kernel_bytes[CC_K_SEARCH] = kb;  // not a step's search
   CC_TRY(rc);
   if (n > 0) {
