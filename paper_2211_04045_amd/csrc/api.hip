@@ -619,13 +619,16 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
   CC_HIP(hipMemcpyAsync(s->seg_dev, s->seg_host, sizeof(SegDev) * ns, hipMemcpyHostToDevice, st));
   const bool jacobi = p.backward == CC_JACOBI;
   if (s->erows_dirty && !jacobi) CC_TRY(build_edge_buckets(s, st));
-  // pair pass; regrow the active set if it overflowed
+  // pair pass; regrow the active set if it overflowed. After a search of every
+  // iterating scene each pair has d < D_max = D and stays in P': P' is P as it is.
+  const bool in_place = !sel.empty() && n_old == 0;
   for (int attempt = 0;; ++attempt) {
     CC_HIP(hipMemsetAsync(s->dc, 0, sizeof(Counters), st));
     CC_TRY(launch_di_init(s, st));
     timer_begin(s, CC_K_PAIR, st);
     // pairs the search just found carry their distance at this x already
-    CC_TRY(launch_pair_pass(s, n_old, sel.empty() ? s->nP : n_old, p.delta * p.delta, trace, st));
+    CC_TRY(launch_pair_pass(s, n_old, sel.empty() ? s->nP : n_old, p.delta * p.delta, trace,
+                            in_place, st));
     timer_end(s, st);
     CC_HIP(hipMemcpyAsync(s->hc, s->dc, sizeof(Counters), hipMemcpyDeviceToHost, st));
     CC_HIP(hipMemcpyAsync(s->seg_host, s->seg_dev, sizeof(SegDev) * ns, hipMemcpyDeviceToHost, st));
@@ -640,8 +643,11 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
   const int64_t n_eval = s->nP;
   const int64_t npf = (int64_t)s->hc->n_out, na = (int64_t)s->hc->n_act;
   const uint64_t fp_pf = s->hc->fp_pf, fp_a = s->hc->fp_a;
-  std::swap(s->P, s->P2);
-  std::swap(s->dP, s->dP2);
+  if (in_place && npf != n_eval) return CC_EHIP;  // cannot happen: the search kept d < D_max
+  if (!in_place) {
+    std::swap(s->P, s->P2);
+    std::swap(s->dP, s->dP2);
+  }
   s->nP = npf;
   s->nA = na;
   release_all_pending(s);  // no pair of a removed segment is left in P

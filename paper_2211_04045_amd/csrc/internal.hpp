@@ -290,7 +290,7 @@ int launch_di_init(cc_solver* s, hipStream_t st);
 // pairs [0, n_old) are last iteration's P'; [n_old, nP) were appended by a search;
 // pairs from d_from on take their squared distance from dP (written by the search)
 int launch_pair_pass(cc_solver* s, int64_t n_old, int64_t d_from, double dl2, bool trace,
-                     hipStream_t st);
+                     bool in_place, hipStream_t st);
 // contacts: colour A; edges: colour the n_newrows rows listed in elist0
 int color_rows(cc_solver* s, bool edges, hipStream_t st);
 int build_edge_buckets(cc_solver* s, hipStream_t st);

@@ -318,6 +318,7 @@ struct PairPassArgs {
   unsigned long long* Di;
   Counters* c;
   int trace;
+  int in_place;  // every pair is kept (fresh from a search of every scene): P' is P, unwritten
 };
 
 constexpr int kHash = 2048;         // LDS slots for the per-block D_i minimum
@@ -519,8 +520,10 @@ __global__ void __launch_bounds__(kThreads) k_pair_pass(PairPassArgs a) {
 #pragma unroll
   for (int k = 0; k < kPairsPerThread; ++k) {
     if (keepm & (1u << k)) {
-      a.Pout[pk] = keys[k];
-      a.dPout[pk] = d2s[k];
+      if (!a.in_place) {
+        a.Pout[pk] = keys[k];
+        a.dPout[pk] = d2s[k];
+      }
       ++pk;
     }
     if (actm & (1u << k)) {
@@ -542,7 +545,7 @@ __global__ void __launch_bounds__(kThreads) k_pair_pass(PairPassArgs a) {
 }
 
 int launch_pair_pass(cc_solver* s, int64_t n_old, int64_t d_from, double dl2, bool trace,
-                     hipStream_t st) {
+                     bool in_place, hipStream_t st) {
   PairPassArgs a;
   a.P = s->P;
   a.nP = s->nP;
@@ -562,6 +565,7 @@ int launch_pair_pass(cc_solver* s, int64_t n_old, int64_t d_from, double dl2, bo
   a.Di = s->Di;
   a.c = s->dc;
   a.trace = trace ? 1 : 0;
+  a.in_place = in_place ? 1 : 0;
   if (s->nP > 0) k_pair_pass<<<nblk(s->nP, kThreads * kPairsPerThread), kThreads, 0, st>>>(a);
   CC_HIP(hipGetLastError());
   return CC_OK;
