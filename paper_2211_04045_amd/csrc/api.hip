@@ -127,6 +127,7 @@ void free_pairs(cc_solver* s) {
 void free_active(cc_solver* s) {
   dfree(s->Akeys); dfree(s->Averts); dfree(s->Acol); dfree(s->Aorder);
   dfree(s->list0); dfree(s->list1); dfree(s->lamA); dfree(s->afail); dfree(s->apick);
+  dfree(s->Arow);
 }
 
 // Pair buffers of capacity cap; the first `keep` keys of P survive.
@@ -152,6 +153,7 @@ int alloc_active(cc_solver* s, int64_t cap) {
   CC_TRY(dalloc(&s->lamA, cap));
   CC_TRY(dalloc(&s->afail, cap));
   CC_TRY(dalloc(&s->apick, cap));
+  CC_TRY(dalloc(&s->Arow, cap * kRowWords));
   return CC_OK;
 }
 
@@ -159,7 +161,7 @@ void free_vertex_arrays(cc_solver* s) {
   dfree(s->w); dfree(s->stat); dfree(s->x); dfree(s->y); dfree(s->xt); dfree(s->xold);
   dfree(s->r); dfree(s->move2); dfree(s->Di); dfree(s->vseg); dfree(s->plist); dfree(s->dy);
   dfree(s->jacc);
-  dfree(s->vmax0); dfree(s->claims); dfree(s->masks);
+  dfree(s->vmax0); dfree(s->claims); dfree(s->masks); dfree(s->vloc);
 }
 void free_edge_arrays(cc_solver* s) {
   dfree(s->edges); dfree(s->eseg); dfree(s->eg); dfree(s->einv); dfree(s->ecol); dfree(s->eorder);
@@ -222,6 +224,9 @@ int resize_arrays(cc_solver* s, int32_t capV, int32_t capF, int32_t capE, hipStr
     CC_TRY(dalloc(&s->claims, (int64_t)capV * 2 * kMaskWords));
     s->pc_dirty = true;
     CC_TRY(dalloc(&s->masks, (int64_t)capV * kMaskWords));
+    dfree(s->vloc);
+    CC_TRY(dalloc(&s->vloc, capV));
+    CC_TRY(launch_fill_i32(s->vloc, capV, kNoLoc, st));
   }
   if (capF != oF) CC_TRY(dregrow(&s->tris, 3 * (int64_t)capF, 3 * oF, st));
   if (capE != oE) {
@@ -623,8 +628,7 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
   // iterating scene each pair has d < D_max = D and stays in P': P' is P as it is.
   const bool in_place = !sel.empty() && n_old == 0;
   for (int attempt = 0;; ++attempt) {
-    CC_HIP(hipMemsetAsync(s->dc, 0, sizeof(Counters), st));
-    CC_TRY(launch_di_init(s, st));
+    CC_TRY(launch_di_init(s, st));  // also clears the counters
     timer_begin(s, CC_K_PAIR, st);
     // pairs the search just found carry their distance at this x already
     CC_TRY(launch_pair_pass(s, n_old, sel.empty() ? s->nP : n_old, p.delta * p.delta, trace,
@@ -663,10 +667,13 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
   if (jacobi) {
     s->n_colors = 0;
     s->col_off.assign(1, 0);
+    s->col_small = false;
     if (na > 0) CC_HIP(hipMemsetAsync(s->Acol, 0, sizeof(int32_t) * na, st));  // all in colour 0
   } else {
+    // a small contact set is coloured and bucketed by one block, and the projection
+    // reads its colours on the device: no host round trip before the forward step
     timer_begin(s, CC_K_COLOR, st);
-    int rc = color_rows(s, false, st);
+    int rc = na <= kSmallRows ? color_small(s, st) : color_rows(s, false, st);
     timer_end(s, st);
     if (rc != CC_OK) return rc;
   }
@@ -690,12 +697,17 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
   CC_TRY(launch_cert(s, st));
   timer_end(s, st);
   CC_HIP(hipMemcpyAsync(s->seg_host, s->seg_dev, sizeof(SegDev) * ns, hipMemcpyDeviceToHost, st));
-  if (trace) CC_HIP(hipMemcpyAsync(&s->hc->fp_col, &s->dc->fp_col, sizeof(unsigned long long),
-                                   hipMemcpyDeviceToHost, st));
-  if (jacobi) CC_HIP(hipMemcpyAsync(&s->hc->err, &s->dc->err, sizeof(unsigned long long),
-                                    hipMemcpyDeviceToHost, st));
+  const bool small = s->col_small;
+  if (trace || jacobi || small)
+    CC_HIP(hipMemcpyAsync(s->hc, s->dc, sizeof(Counters), hipMemcpyDeviceToHost, st));
   CC_HIP(hipStreamSynchronize(st));
   if (jacobi && (s->hc->err & 16ull)) return CC_EOVERFLOW;
+  if (small) {
+    // the projection and the forward step did nothing if the colouring failed
+    if (s->hc->err & 1ull) return CC_ECOLOR;
+    s->pc_dirty = false;
+    s->n_colors = (int32_t)s->hc->ncol;
+  }
   resolve_timers(s);
   bool changed = false;
   for (int32_t sg : act) {

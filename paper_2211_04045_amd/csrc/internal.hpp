@@ -31,6 +31,9 @@ constexpr int kMaxSeg = 1024;      // scenes (segments) resident in one solver
 constexpr int kSegBits = 10;       // bits of a segment's rank in a search's sort keys
 constexpr int32_t kMaxIds = 1 << 30;  // primitive ids of pair keys are 30-bit
 constexpr double kFreeTol = 1e-9;  // input check: closest allowed distance (m)
+constexpr int kRowWords = 20;      // one linearised contact row: ids, c0, 1/A, w[4], J[4]
+constexpr int kSmallRows = 4096;   // contact sets up to this size are coloured by one block
+constexpr int32_t kNoLoc = 0x7fffffff;  // vloc entry of a vertex no colouring block holds
 
 // Per-segment record on the device (one scene of a multi-scene solver). The host
 // writes D, D2, bases and flags before an iteration and reads the reductions back.
@@ -199,9 +202,12 @@ struct cc_solver {
   int32_t* Aorder = nullptr;
   int32_t *list0 = nullptr, *list1 = nullptr;
   double* lamA = nullptr;
+  double* Arow = nullptr;  // contact rows linearised at x (kRowWords doubles each)
   int64_t nA = 0;
   int32_t n_colors = 0;
   std::vector<int32_t> col_off;  // host copy of colour bucket offsets (n_colors+1)
+  bool col_small = false;  // this step's contact colours and buckets live on the device only
+  int32_t* vloc = nullptr;  // per vertex: kNoLoc, or a block-local slot while one block colours
   // edge-length rows (one per edge; inv_a = 0 marks an unused edge)
   double* eg = nullptr;     // 3 per edge
   double* einv = nullptr;
@@ -287,6 +293,9 @@ int launch_setup(cc_solver* s, int32_t seg, const double* x_prev, const double* 
                  hipStream_t st);
 int launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t st);
 int launch_di_init(cc_solver* s, hipStream_t st);
+// Colouring of a contact set of at most kSmallRows rows in one block; colours,
+// buckets and the colour count stay on the device (s->col_small).
+int color_small(cc_solver* s, hipStream_t st);
 // pairs [0, n_old) are last iteration's P'; [n_old, nP) were appended by a search;
 // pairs from d_from on take their squared distance from dP (written by the search)
 int launch_pair_pass(cc_solver* s, int64_t n_old, int64_t d_from, double dl2, bool trace,

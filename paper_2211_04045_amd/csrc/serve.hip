@@ -251,15 +251,17 @@ extern "C" {
 size_t cc_scene_bytes(int32_t n, int32_t nt, int32_t ne) {
   if (n < 0 || nt < 0 || ne < 0) return 0;
   // per vertex: w, x, y, x~, x^(l), r, move, D_i, segment id, static flag,
-  // colouring counts, masks, claims and clashes, sort keys and values, query order;
+  // colouring counts, masks, claims, clashes and block slot, sort keys and values,
+  // query order;
   // per triangle: topology, boxes, tree records (binary and 4-wide), refit
   // unions, sort keys; per edge: the same plus the edge row and its colouring;
-  // pairs: 32 (N + E) of P, P' and their distances, an eighth of that active.
-  const size_t per_v = 8 + 4 * 24 + 8 + 8 + 8 + 4 + 1 + 8 + 16 * 8 + 32 * 8 + 2 * 12 + 4 + 2;
+  // pairs: 32 (N + E) of P, P' and their distances, an eighth of that active (with
+  // the linearised contact row).
+  const size_t per_v = 8 + 4 * 24 + 8 + 8 + 8 + 4 + 1 + 8 + 16 * 8 + 32 * 8 + 4 + 2 * 12 + 4 + 2;
   const size_t per_prim = 32 + 4 + 64 + 128 + 8 + 8 + 64 + 32 + 2 * 12;
   const size_t per_e = 8 + 4 + 24 + 8 + 4 + 4 + 12 + 8 + 2;
   const size_t pair_cap = 32 * ((size_t)n + (size_t)ne);
-  const size_t pairs = pair_cap * 32 + (pair_cap / 8) * (8 + 16 + 4 + 4 + 8 + 8);
+  const size_t pairs = pair_cap * 32 + (pair_cap / 8) * (8 + 16 + 4 + 4 + 8 + 8 + 8 * cc::kRowWords);
   // particles (vertices in no triangle or edge): at least n - 3F - 2E of them, each a
   // leaf of the particle tree and a search key
   const int64_t np = std::max<int64_t>(0, (int64_t)n - 3 * (int64_t)nt - 2 * (int64_t)ne);

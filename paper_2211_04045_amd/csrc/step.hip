@@ -282,9 +282,12 @@ int launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipS
 
 // D_i <- D^(l) of the vertex's segment (Sec. 5: a vertex in no pair moves at
 // most 0.45 D^(l)); vertices of segments that do not iterate are left alone.
+// The iteration's counters start from zero here as well.
 __global__ void k_di_init(const int32_t* __restrict__ vseg, const SegDev* __restrict__ seg,
-                          int32_t n, unsigned long long* __restrict__ Di) {
+                          int32_t n, unsigned long long* __restrict__ Di, Counters* c) {
   int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int kWords = (int)(sizeof(Counters) / sizeof(unsigned long long));
+  if (v < kWords) reinterpret_cast<unsigned long long*>(c)[v] = 0ull;
   if (v >= n) return;
   const int32_t sg = vseg[v];
   if (sg < 0 || !(seg[sg].flags & kSegActive)) return;
@@ -292,7 +295,11 @@ __global__ void k_di_init(const int32_t* __restrict__ vseg, const SegDev* __rest
 }
 
 int launch_di_init(cc_solver* s, hipStream_t st) {
-  if (s->n > 0) k_di_init<<<nblk(s->n), kThreads, 0, st>>>(s->vseg, s->seg_dev, s->n, s->Di);
+  static_assert(sizeof(Counters) % sizeof(unsigned long long) == 0 &&
+                    sizeof(Counters) / sizeof(unsigned long long) <= kThreads,
+                "one block clears the counters");
+  k_di_init<<<nblk(s->n > 0 ? s->n : 1), kThreads, 0, st>>>(s->vseg, s->seg_dev, s->n, s->Di,
+                                                             s->dc);
   CC_HIP(hipGetLastError());
   return CC_OK;
 }
@@ -773,8 +780,40 @@ __global__ void __launch_bounds__(kThreads) k_pc_clear(PcArgs a, const int32_t* 
   if (t < (int64_t)*nlist) pc_clear(a, list[t]);
 }
 
-// The remaining rounds (from round t0) in one block: global atomics, atomic loads
-// to read what other threads wrote, block barriers between the phases.
+// Rounds t0, t0 + 1, ... over the list cur[0, *ncur) in one block: global atomics,
+// atomic loads to read what other threads wrote, block barriers between the
+// phases (ncur and nnext live in LDS).
+__device__ void pc_rounds_block(const PcArgs& a, int32_t* cur, int32_t* nxt, int32_t* ncur,
+                                int32_t* nnext, uint64_t t0, uint64_t tmax) {
+  for (uint64_t t = t0; *ncur > 0; ++t) {
+    if (t > tmax) {
+      if (threadIdx.x == 0) atomicOr(&a.c->err, 1ull);
+      break;
+    }
+    const int32_t nc = *ncur;
+    for (int32_t i = threadIdx.x; i < nc; i += blockDim.x) pc_count(a, cur[i]);
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < nc; i += blockDim.x) pc_pick<true>(a, cur[i], t);
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < nc; i += blockDim.x) {
+      const int32_t r = cur[i];
+      if (pc_resolve<true>(a, r)) nxt[atomicAdd(nnext, 1)] = r;
+    }
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < nc; i += blockDim.x) pc_clear(a, cur[i]);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      *ncur = *nnext;
+      *nnext = 0;
+    }
+    int32_t* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+    __syncthreads();
+  }
+}
+
+// The remaining rounds (from round t0) of a list whose length lives on the device.
 __global__ void __launch_bounds__(kTailThreads) k_pc_tail(PcArgs a, int32_t* la, int32_t* lb,
                                                           const unsigned long long* nlist,
                                                           uint64_t t0, uint64_t tmax) {
@@ -784,32 +823,271 @@ __global__ void __launch_bounds__(kTailThreads) k_pc_tail(PcArgs a, int32_t* la,
     nnext = 0;
   }
   __syncthreads();
-  int32_t* cur = la;
-  int32_t* nxt = lb;
-  for (uint64_t t = t0; ncur > 0; ++t) {
-    if (t > tmax) {
-      if (threadIdx.x == 0) atomicOr(&a.c->err, 1ull);
-      break;
+  pc_rounds_block(a, la, lb, &ncur, &nnext, t0, tmax);
+}
+
+constexpr int kSmallPer = kSmallRows / kTailThreads;  // rows per thread
+constexpr int kLocCap = 2048;  // distinct free vertices whose colouring state fits in LDS
+constexpr int kLocWords = 2;   // colour words kept per vertex in LDS (colours below 128)
+static_assert(kSmallRows % kTailThreads == 0, "whole rows per thread");
+static_assert(kMaxColors == kTailThreads, "one thread per colour bucket in the scan");
+
+// The same rounds (from round 1) over every contact row [0, nrows) in one block,
+// with the per-vertex state in LDS. The rows' free vertices get block-local slots:
+// each (row, corner) names its vertex in vloc with an atomic minimum of its index,
+// the corner that holds the minimum takes the next slot and writes it back (as
+// -(slot + 1)), every corner reads it, and vloc returns to kNoLoc before the
+// rounds. A thread keeps its rows (row t + k * kTailThreads) in registers. When
+// more than kLocCap vertices take part, or a pick would need a colour beyond the
+// kLocWords words in LDS, the block runs the global-memory rounds from round 1
+// instead, with the same result (the colours depend only on the row set). Then
+// the colour buckets: counts, their exclusive scan to off (kMaxColors + 1
+// entries), the rows in colour order to order; the colour count goes to c->ncol.
+__global__ void __launch_bounds__(kTailThreads) k_pc_small(PcArgs a, int32_t nrows, int32_t* la,
+                                                           int32_t* lb, int32_t* __restrict__ vloc,
+                                                           int32_t* __restrict__ order,
+                                                           int32_t* __restrict__ off,
+                                                           uint64_t tmax) {
+  __shared__ unsigned s_unc[kLocCap];
+  __shared__ unsigned long long s_mask[kLocCap][kLocWords];
+  __shared__ unsigned long long s_claim[kLocCap][kLocWords];
+  __shared__ unsigned long long s_clash[kLocCap][kLocWords];
+  __shared__ int32_t s_cnt[kMaxColors];
+  __shared__ int32_t s_wsum[kTailThreads / 64];
+  __shared__ int32_t s_nloc, s_live, s_next, s_ncol, s_over, ncur, nnext;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_nloc = 0;
+    s_live = nrows;
+    s_next = 0;
+    s_ncol = 0;
+    s_over = 0;
+  }
+  s_cnt[tid] = 0;
+  uint64_t hk[kSmallPer];
+  int32_t vid[kSmallPer][4], lid[kSmallPer][4];
+  int32_t fails[kSmallPer], pick[kSmallPer], col[kSmallPer];
+#pragma unroll
+  for (int k = 0; k < kSmallPer; ++k) {
+    const int32_t r = tid + k * kTailThreads;
+    fails[k] = 0;
+    pick[k] = 0;
+    col[k] = -1;
+    hk[k] = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) vid[k][q] = lid[k][q] = -1;
+    if (r < nrows) {
+      uint64_t key;
+      int32_t v[4];
+      a.src.get(r, key, v);
+      hk[k] = mix64(key ^ a.seed);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (!is_free(a.w, v[q])) continue;
+        vid[k][q] = v[q];
+        atomicMin(&vloc[v[q]], r * 4 + q);
+      }
     }
-    for (int32_t i = threadIdx.x; i < ncur; i += kTailThreads) pc_count(a, cur[i]);
-    __syncthreads();
-    for (int32_t i = threadIdx.x; i < ncur; i += kTailThreads) pc_pick<true>(a, cur[i], t);
-    __syncthreads();
-    for (int32_t i = threadIdx.x; i < ncur; i += kTailThreads) {
-      const int32_t r = cur[i];
-      if (pc_resolve<true>(a, r)) nxt[atomicAdd(&nnext, 1)] = r;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kSmallPer; ++k) {
+    const int32_t r = tid + k * kTailThreads;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (vid[k][q] < 0) continue;
+      int32_t* slot = &vloc[vid[k][q]];
+      if (__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != r * 4 + q) continue;
+      const int32_t l = atomicAdd(&s_nloc, 1);
+      if (l < kLocCap) {
+        s_unc[l] = 0u;
+#pragma unroll
+        for (int wd = 0; wd < kLocWords; ++wd) s_mask[l][wd] = s_claim[l][wd] = s_clash[l][wd] = 0ull;
+      }
+      __hip_atomic_store(slot, -(l + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __syncthreads();
-    for (int32_t i = threadIdx.x; i < ncur; i += kTailThreads) pc_clear(a, cur[i]);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      ncur = nnext;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kSmallPer; ++k)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (vid[k][q] >= 0)
+        lid[k][q] = -__hip_atomic_load(&vloc[vid[k][q]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - 1;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kSmallPer; ++k)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (vid[k][q] >= 0) __hip_atomic_store(&vloc[vid[k][q]], kNoLoc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const bool in_lds = s_nloc <= kLocCap;
+  const int W = (a.maxc + 63) / 64;
+  if (in_lds) {
+    for (uint64_t t = 1; s_live > 0; ++t) {
+      if (t > tmax) {
+        if (tid == 0) atomicOr(&a.c->err, 1ull);
+        break;
+      }
+      unsigned live = 0;
+#pragma unroll
+      for (int k = 0; k < kSmallPer; ++k) {
+        if (tid + k * kTailThreads >= nrows || col[k] >= 0) continue;
+        live |= 1u << k;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (lid[k][q] >= 0) atomicAdd(&s_unc[lid[k][q]], 1u);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kSmallPer; ++k) {
+        if (!(live & (1u << k))) continue;
+        unsigned long long m = 1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (lid[k][q] >= 0 && (unsigned long long)s_unc[lid[k][q]] > m) m = s_unc[lid[k][q]];
+        m += (unsigned long long)fails[k];
+        unsigned long long want = mix64(hk[k] + t * kPhi) % m;
+        int c = -1;
+        bool over = false;
+        for (int wd = 0; wd < W && c < 0; ++wd) {
+          if (wd >= kLocWords) {
+            over = true;
+            break;
+          }
+          unsigned long long used = 0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (lid[k][q] >= 0) used |= s_mask[lid[k][q]][wd];
+          unsigned long long fr = ~used;
+          const int lim = a.maxc - 64 * wd;
+          if (lim < 64) fr &= (1ull << lim) - 1ull;
+          const unsigned long long cnt = (unsigned long long)__popcll(fr);
+          if (want >= cnt) {
+            want -= cnt;
+            continue;
+          }
+          for (unsigned long long z = 0; z < want; ++z) fr &= fr - 1ull;
+          c = 64 * wd + (__ffsll((long long)fr) - 1);
+        }
+        if (over) {
+          s_over = 1;
+          c = 0;  // the round is abandoned
+        } else if (c < 0) {
+          atomicOr(&a.c->err, 1ull);
+          c = 0;
+        }
+        pick[k] = c;
+        const unsigned long long bit = 1ull << (c % 64);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (lid[k][q] < 0) continue;
+          const unsigned long long old = atomicOr(&s_claim[lid[k][q]][c / 64], bit);
+          if (old & bit) atomicOr(&s_clash[lid[k][q]][c / 64], bit);
+        }
+      }
+      __syncthreads();
+      if (s_over) break;
+#pragma unroll
+      for (int k = 0; k < kSmallPer; ++k) {
+        if (!(live & (1u << k))) continue;
+        const int c = pick[k];
+        const unsigned long long bit = 1ull << (c % 64);
+        bool clash = false;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (lid[k][q] >= 0 && (s_clash[lid[k][q]][c / 64] & bit)) clash = true;
+        if (clash) {
+          fails[k] += 1;
+          atomicAdd(&s_next, 1);
+          continue;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (lid[k][q] >= 0) atomicOr(&s_mask[lid[k][q]][c / 64], bit);
+        col[k] = c;
+        atomicMax(&s_ncol, c + 1);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kSmallPer; ++k) {
+        if (!(live & (1u << k))) continue;
+        const int wd = pick[k] / 64;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (lid[k][q] < 0) continue;
+          s_unc[lid[k][q]] = 0u;
+          s_claim[lid[k][q]][wd] = 0ull;
+          s_clash[lid[k][q]][wd] = 0ull;
+        }
+      }
+      if (tid == 0) {
+        s_live = s_next;
+        s_next = 0;
+      }
+      __syncthreads();
+    }
+  }
+  const bool global_rounds = !in_lds || s_over;
+  if (global_rounds) {
+    // every row in the list, none failed yet, no colour at its vertices yet
+#pragma unroll
+    for (int k = 0; k < kSmallPer; ++k) {
+      const int32_t r = tid + k * kTailThreads;
+      if (r >= nrows) continue;
+      la[r] = r;
+      a.fails[r] = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (vid[k][q] >= 0)
+          for (int wd = 0; wd < kMaskWords; ++wd) a.masks[(int64_t)vid[k][q] * kMaskWords + wd] = 0ull;
+    }
+    if (tid == 0) {
+      ncur = nrows;
       nnext = 0;
     }
-    int32_t* tmp = cur;
-    cur = nxt;
-    nxt = tmp;
     __syncthreads();
+    pc_rounds_block(a, la, lb, &ncur, &nnext, 1, tmax);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSmallPer; ++k) {
+      const int32_t r = tid + k * kTailThreads;
+      if (r < nrows) col[k] = __hip_atomic_load(&a.colors[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  // colour buckets (a row left uncoloured by the round limit reads as colour 0)
+  int32_t rank[kSmallPer];
+#pragma unroll
+  for (int k = 0; k < kSmallPer; ++k) {
+    rank[k] = 0;
+    if (tid + k * kTailThreads >= nrows) continue;
+    if (col[k] < 0) col[k] = 0;
+    rank[k] = atomicAdd(&s_cnt[col[k]], 1);
+  }
+  __syncthreads();
+  const int lane = tid & 63, wv = tid >> 6;
+  const int32_t cv = s_cnt[tid];
+  int32_t incl = cv;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t u = __shfl_up(incl, o);
+    if (lane >= o) incl += u;
+  }
+  if (lane == 63) s_wsum[wv] = incl;
+  __syncthreads();
+  int32_t before = 0;
+  for (int w = 0; w < wv; ++w) before += s_wsum[w];
+  const int32_t ex = before + incl - cv;
+  __syncthreads();
+  s_cnt[tid] = ex;
+  off[tid] = ex;
+  if (tid == kTailThreads - 1) off[kMaxColors] = ex + cv;
+  if (tid == 0 && !global_rounds) a.c->ncol = (unsigned long long)s_ncol;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kSmallPer; ++k) {
+    const int32_t r = tid + k * kTailThreads;
+    if (r >= nrows) continue;
+    order[s_cnt[col[k]] + rank[k]] = r;
+    a.colors[r] = col[k];
   }
 }
 
@@ -882,6 +1160,40 @@ __global__ void __launch_bounds__(kMaxColors) k_bucket_offsets(int32_t* __restri
   if (t == 0) off[kMaxColors] = total;
 }
 
+static PcArgs pc_args(cc_solver* s, bool edges) {
+  PcArgs a;
+  a.src = RowSrc{s->Akeys, s->Averts, s->edges, s->vseg, s->eseg, s->seg_dev, edges ? 1 : 0};
+  a.w = s->w;
+  a.seed = s->p.seed;
+  a.masks = s->masks;
+  a.claims = s->claims;
+  a.unc = s->vmax0;
+  a.fails = edges ? s->efail : s->afail;
+  a.pick = edges ? s->epick : s->apick;
+  a.maxc = s->p.max_colors;
+  a.colors = edges ? s->ecol : s->Acol;
+  a.c = s->dc;
+  return a;
+}
+
+int color_small(cc_solver* s, hipStream_t st) {
+  s->col_off.assign(1, 0);
+  s->n_colors = 0;
+  s->col_small = true;
+  if (s->nA == 0) return CC_OK;
+  if (s->nA > kSmallRows) return CC_EINVAL;
+  if (s->pc_dirty) {  // an aborted colouring left counts or claims behind
+    CC_HIP(hipMemsetAsync(s->vmax0, 0, sizeof(unsigned long long) * s->n, st));
+    CC_HIP(hipMemsetAsync(s->claims, 0, sizeof(unsigned long long) * s->n * 2 * kMaskWords, st));
+  }
+  // clean again once the iteration's counters show no colouring error
+  s->pc_dirty = true;
+  k_pc_small<<<1, kTailThreads, 0, st>>>(pc_args(s, false), (int32_t)s->nA, s->list0, s->list1,
+                                          s->vloc, s->Aorder, s->coff_dev, (uint64_t)kMaxRounds);
+  CC_HIP(hipGetLastError());
+  return CC_OK;
+}
+
 // Colour the contact rows (A, then bucket them by colour) or the edge-length
 // rows listed in elist0[0, n_newrows) (the rows of segments being begun; their
 // buckets are built over every iterating segment by build_edge_buckets).
@@ -891,6 +1203,7 @@ int color_rows(cc_solver* s, bool edges, hipStream_t st) {
   if (!edges) {
     s->col_off.assign(1, 0);
     s->n_colors = 0;
+    s->col_small = false;
   }
   if (nrows == 0) return CC_OK;
   int32_t *cur, *nxt;
@@ -913,22 +1226,9 @@ int color_rows(cc_solver* s, bool edges, hipStream_t st) {
   CC_HIP(hipMemsetAsync(&s->dc->err, 0, sizeof(unsigned long long), st));
   CC_HIP(hipMemsetAsync(s->rcnt, 0, sizeof(unsigned long long) * (kMaxRounds + 1), st));
   CC_TRY(launch_fill_u64(s->rcnt, 1, (unsigned long long)nrows, st));
-  int32_t* fails = edges ? s->efail : s->afail;
-  int32_t* pick = edges ? s->epick : s->apick;
-  if (edges) CC_TRY(launch_fill_i32(fails, s->capE, 0, st));
-  else CC_TRY(launch_fill_i32(fails, nrows, 0, st));
-  PcArgs a;
-  a.src = RowSrc{s->Akeys, s->Averts, s->edges, s->vseg, s->eseg, s->seg_dev, edges ? 1 : 0};
-  a.w = s->w;
-  a.seed = s->p.seed;
-  a.masks = s->masks;
-  a.claims = s->claims;
-  a.unc = s->vmax0;
-  a.fails = fails;
-  a.pick = pick;
-  a.maxc = s->p.max_colors;
-  a.colors = colors;
-  a.c = s->dc;
+  if (edges) CC_TRY(launch_fill_i32(s->efail, s->capE, 0, st));
+  else CC_TRY(launch_fill_i32(s->afail, nrows, 0, st));
+  const PcArgs a = pc_args(s, edges);
   int64_t known = nrows;  // upper bound of the current list length
   int round = 0;          // rounds done; round t = round + 1 is next
   s->pc_dirty = true;
@@ -1067,9 +1367,22 @@ int build_edge_buckets(cc_solver* s, hipStream_t st) {
 
 // ------------------------------------------------------------- Gauss-Seidel
 
+// A contact row of A linearised at x^(l) (Sec. 4): x does not change during the
+// backward step, so the row is built once per step and every sweep reads it.
+// Slots 2 and 3 of a vertex-vertex row carry vertex id -1.
+struct RowRec {
+  int4 v;
+  double c0, inv_a;
+  double w[4];
+  V3 J[4];
+};
+static_assert(sizeof(RowRec) == 8 * kRowWords, "contact row record size");
+
 struct GsArgs {
   const int32_t* order;
   int32_t cnt;
+  const RowRec* rows;
+  const unsigned long long* err;  // bit 0 set: the colouring failed, the step does nothing
   const uint64_t* Akeys;
   const int4* Averts;
   const int32_t* edges;
@@ -1101,29 +1414,57 @@ __device__ __forceinline__ void stf3(float* p, int32_t i, F3 v) {
   q[2] = v.z;
 }
 
-// One projected Gauss-Seidel update of a contact row (Sec. 4.3): the row is
-// linearised at x^(l) (Sec. 4), residual w = c0 + sum J.(y - x),
-// lambda <- max(0, lambda - w/A), y_v += w_v dl J_v at its free vertices.
-// Mixed precision: the row is assembled in FP64 (closest point, normal,
-// volume sign) and rounded; the projection runs in FP32 on y - x.
-template <bool kMixed>
-__device__ __forceinline__ void gs_contact_update(const GsArgs& a, int32_t r) {
-  uint64_t key = a.Akeys[r];
-  int4 q = a.Averts[r];
-  int32_t v[4] = {q.x, q.y, q.z, q.w};
+// The contact rows of A at x^(l) (contact_row), and the step's multipliers set to
+// zero (contact rows and, with edge-length rows in use, the ne edge rows).
+__global__ void __launch_bounds__(kThreads) k_contact_rows(const uint64_t* __restrict__ Akeys,
+                                                           const int4* __restrict__ Averts,
+                                                           const double* __restrict__ x,
+                                                           const double* __restrict__ w,
+                                                           double delta, double kappa2,
+                                                           int64_t nA, RowRec* __restrict__ rows,
+                                                           double* __restrict__ lamA,
+                                                           double* __restrict__ lamE,
+                                                           int64_t ne) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ne) lamE[i] = 0.0;
+  if (i >= nA) return;
+  lamA[i] = 0.0;
+  const uint64_t key = Akeys[i];
+  const int4 q = Averts[i];
+  const int32_t v[4] = {q.x, q.y, q.z, q.w};
   V3 xs[4];
   double ws[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    xs[k] = ld3(a.x, v[k]);
-    ws[k] = a.w[v[k]];
+    xs[k] = ld3(x, v[k]);
+    ws[k] = w[v[k]];
   }
-  Row R;
+  Row R{};
   const bool vv = key_is_vv(key);
-  const int nk = vv ? 2 : 4;  // a vertex-vertex row has two vertices
-  if (vv) contact_row_vv(xs, ws, a.delta, R);
-  else contact_row(key_is_ee(key), xs, ws, a.delta, a.kappa2, R);
+  if (vv) contact_row_vv(xs, ws, delta, R);
+  else contact_row(key_is_ee(key), xs, ws, delta, kappa2, R);
+  RowRec o;
+  o.v = vv ? make_int4(q.x, q.y, -1, -1) : q;
+  o.c0 = R.c0;
+  o.inv_a = R.inv_a;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    o.w[k] = ws[k];
+    o.J[k] = R.J[k];
+  }
+  rows[i] = o;
+}
+
+// One projected Gauss-Seidel update of a contact row (Sec. 4.3) built by
+// k_contact_rows: residual w = c0 + sum J.(y - x), lambda <- max(0, lambda - w/A),
+// y_v += w_v dl J_v at its free vertices. Mixed precision: the row (FP64) is
+// rounded and the projection runs in FP32 on y - x.
+template <bool kMixed>
+__device__ __forceinline__ void gs_contact_update(const GsArgs& a, int32_t r) {
+  const RowRec R = a.rows[r];
   if (!(R.inv_a > 0.0)) return;
+  const int32_t v[4] = {R.v.x, R.v.y, R.v.z, R.v.w};
+  const int nk = v[2] < 0 ? 2 : 4;  // a vertex-vertex row has two vertices
   if (kMixed) {
     F3 J[4];
 #pragma unroll
@@ -1142,8 +1483,8 @@ __device__ __forceinline__ void gs_contact_update(const GsArgs& a, int32_t r) {
     a.lamf[r] = ln;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      if (k >= nk || !(ws[k] > 0.0)) continue;
-      const float co = (float)ws[k] * dl;
+      if (k >= nk || !(R.w[k] > 0.0)) continue;
+      const float co = (float)R.w[k] * dl;
       F3 d = ldf3(a.dy, v[k]);
       stf3(a.dy, v[k], F3{d.x + co * J[k].x, d.y + co * J[k].y, d.z + co * J[k].z});
     }
@@ -1153,7 +1494,7 @@ __device__ __forceinline__ void gs_contact_update(const GsArgs& a, int32_t r) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if (k >= nk) continue;
-    V3 dy = vsub(ld3(a.y, v[k]), xs[k]);
+    V3 dy = vsub(ld3(a.y, v[k]), ld3(a.x, v[k]));
     wr = wr + vdot(R.J[k], dy);
   }
   double lam = a.lam[r];
@@ -1163,8 +1504,8 @@ __device__ __forceinline__ void gs_contact_update(const GsArgs& a, int32_t r) {
   a.lam[r] = ln;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    if (k >= nk || !(ws[k] > 0.0)) continue;
-    double co = ws[k] * dl;
+    if (k >= nk || !(R.w[k] > 0.0)) continue;
+    double co = R.w[k] * dl;
     V3 yv = ld3(a.y, v[k]);
     yv = V3{yv.x + co * R.J[k].x, yv.y + co * R.J[k].y, yv.z + co * R.J[k].z};
     st3(a.y, v[k], yv);
@@ -1216,24 +1557,31 @@ __device__ __forceinline__ void gs_edge_update(const GsArgs& a, int32_t e) {
   }
 }
 
+__device__ __forceinline__ bool gs_off(const GsArgs& a) { return a.err && (*a.err & 1ull); }
+
 // One colour, one row per thread (rows of a colour share no free vertex).
 template <bool kMixed>
 __global__ void __launch_bounds__(kThreads) k_gs_contact(GsArgs a) {
   int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < a.cnt) gs_contact_update<kMixed>(a, a.order[t]);
+  if (t < a.cnt && !gs_off(a)) gs_contact_update<kMixed>(a, a.order[t]);
 }
 
 template <bool kMixed>
 __global__ void __launch_bounds__(kThreads) k_gs_edge(GsArgs a) {
   int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < a.cnt) gs_edge_update<kMixed>(a, a.order[t]);
+  if (t < a.cnt && !gs_off(a)) gs_edge_update<kMixed>(a, a.order[t]);
 }
 
 // A run of small colours [c0, c1) in one block, colour after colour with a block
-// barrier between them; `off` holds the colour bucket offsets on the device.
+// barrier between them; `off` holds the colour bucket offsets on the device. With
+// c1p set, the run ends at the colour count the device holds there (the colouring
+// of the same step wrote it).
 template <bool kMixed>
 __global__ void __launch_bounds__(kGsTailThreads) k_gs_tail(GsArgs a, const int32_t* off,
-                                                            int32_t c0, int32_t c1, int is_edge) {
+                                                            int32_t c0, int32_t c1, int is_edge,
+                                                            const unsigned long long* c1p) {
+  if (gs_off(a)) return;
+  if (c1p) c1 = (int32_t)*c1p;
   for (int32_t c = c0; c < c1; ++c) {
     const int32_t b = off[c], e = off[c + 1];
     for (int32_t t = b + threadIdx.x; t < e; t += kGsTailThreads) {
@@ -1263,7 +1611,7 @@ static void gs_colours(const GsArgs& base, const int32_t* order, const std::vect
     while (c1 < ncol && off[c1 + 1] - off[c1] < kGsTailRows) ++c1;
     a.order = order;
     a.cnt = 0;
-    k_gs_tail<kMixed><<<1, kGsTailThreads, 0, st>>>(a, off_dev, c, c1, edge ? 1 : 0);
+    k_gs_tail<kMixed><<<1, kGsTailThreads, 0, st>>>(a, off_dev, c, c1, edge ? 1 : 0, nullptr);
     c = c1;
   }
 }
@@ -1273,7 +1621,15 @@ static void gs_sweeps(cc_solver* s, GsArgs a, hipStream_t st) {
   for (int sw = 0; sw < s->p.gs_sweeps; ++sw) {
     a.lam = s->lamA;
     a.lamf = (float*)s->lamA;
-    gs_colours<kMixed>(a, s->Aorder, s->col_off, s->coff_dev, s->n_colors, false, st);
+    if (s->col_small) {
+      // colours of a small contact set are known on the device only: one block runs them all
+      a.order = s->Aorder;
+      a.cnt = 0;
+      if (s->nA > 0)
+        k_gs_tail<kMixed><<<1, kGsTailThreads, 0, st>>>(a, s->coff_dev, 0, 0, 0, &s->dc->ncol);
+    } else {
+      gs_colours<kMixed>(a, s->Aorder, s->col_off, s->coff_dev, s->n_colors, false, st);
+    }
     a.lam = s->lamE;
     a.lamf = (float*)s->lamE;
     gs_colours<kMixed>(a, s->eorder, s->ecol_off, s->ecoff_dev, s->n_ecolors, true, st);
@@ -1284,6 +1640,8 @@ int launch_gs(cc_solver* s, hipStream_t st) {
   GsArgs a;
   a.Akeys = s->Akeys;
   a.Averts = s->Averts;
+  a.rows = reinterpret_cast<const RowRec*>(s->Arow);
+  a.err = s->col_small ? &s->dc->err : nullptr;
   a.edges = s->edges;
   a.eg = s->eg;
   a.einv = s->einv;
@@ -1294,9 +1652,14 @@ int launch_gs(cc_solver* s, hipStream_t st) {
   a.delta = s->p.delta;
   a.kappa2 = s->kappa2;
   a.sigma = s->p.sigma;
-  // multipliers start at zero in every backward step (0.0 and 0.0f are both all-zero bits)
-  if (s->nA > 0) CC_HIP(hipMemsetAsync(s->lamA, 0, sizeof(double) * s->nA, st));
-  if (s->n_erows > 0) CC_HIP(hipMemsetAsync(s->lamE, 0, sizeof(double) * s->ne, st));
+  // contact rows at x, and the multipliers at zero (0.0 and 0.0f are both all-zero bits)
+  const int64_t ne = s->n_erows > 0 ? s->ne : 0;
+  const int64_t nz = s->nA > ne ? s->nA : ne;
+  if (nz > 0)
+    k_contact_rows<<<nblk(nz), kThreads, 0, st>>>(s->Akeys, s->Averts, s->x, s->w, s->p.delta,
+                                                  s->kappa2, s->nA,
+                                                  reinterpret_cast<RowRec*>(s->Arow), s->lamA,
+                                                  s->lamE, ne);
   if (s->p.flags & CC_MIXED) gs_sweeps<true>(s, a, st);
   else gs_sweeps<false>(s, a, st);
   CC_HIP(hipGetLastError());
@@ -1412,6 +1775,8 @@ __global__ void __launch_bounds__(kThreads) k_jacobi_apply(double* __restrict__ 
 
 int launch_jacobi(cc_solver* s, hipStream_t st) {
   GsArgs a;
+  a.rows = nullptr;
+  a.err = nullptr;
   a.Akeys = s->Akeys;
   a.Averts = s->Averts;
   a.edges = s->edges;
@@ -1459,7 +1824,9 @@ __global__ void __launch_bounds__(kThreads) k_forward(double* __restrict__ x,
                                                       double* __restrict__ r,
                                                       double* __restrict__ move2, int32_t n,
                                                       double hg, const int32_t* __restrict__ vseg,
-                                                      SegDev* seg) {
+                                                      SegDev* seg,
+                                                      const unsigned long long* err) {
+  if (err && (*err & 1ull)) return;  // the colouring of this step failed: x stays
   __shared__ int32_t gkey[kSegSlots];
   __shared__ unsigned long long gmax[kSegSlots][2];
   if (threadIdx.x < kSegSlots) {
@@ -1520,12 +1887,13 @@ __global__ void __launch_bounds__(kThreads) k_forward(double* __restrict__ x,
 
 int launch_forward(cc_solver* s, hipStream_t st) {
   const double hg = 0.5 * s->p.gamma;
+  const unsigned long long* err = s->col_small ? &s->dc->err : nullptr;
   if (s->n > 0 && (s->p.flags & CC_MIXED))
     k_forward<true><<<nblk(s->n), kThreads, 0, st>>>(s->x, s->xold, s->y, s->dy, s->Di, s->r,
-                                                      s->move2, s->n, hg, s->vseg, s->seg_dev);
+                                                      s->move2, s->n, hg, s->vseg, s->seg_dev, err);
   else if (s->n > 0)
     k_forward<false><<<nblk(s->n), kThreads, 0, st>>>(s->x, s->xold, s->y, s->dy, s->Di, s->r,
-                                                       s->move2, s->n, hg, s->vseg, s->seg_dev);
+                                                       s->move2, s->n, hg, s->vseg, s->seg_dev, err);
   CC_HIP(hipGetLastError());
   return CC_OK;
 }
@@ -1595,7 +1963,7 @@ int launch_cert(cc_solver* s, hipStream_t st) {
   const double eta = kCcdEta;
   if (s->nP > 0) {
     unsigned long long* queue = (unsigned long long*)s->P2;
-    CC_HIP(hipMemsetAsync(&s->dc->ncert, 0, sizeof(unsigned long long), st));
+    // dc->ncert starts at zero with the iteration's counters (k_di_init)
     k_cert<<<nblk(s->nP), kThreads, 0, st>>>(s->P, s->dP, s->nP, Topo{s->tris, s->edges},
                                               s->move2, s->vseg, s->seg_dev, queue, &s->dc->ncert,
                                               (s->p.flags & CC_CCD_ALL) ? 1 : 0);

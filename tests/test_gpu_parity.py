@@ -685,3 +685,52 @@ def test_normal_flow_frame_full_size_matches_oracle(cc, ctx):
     assert st["iters"] == n and st["status"] == 0 and np.array_equal(x, want)
     h = len(x) // 2
     assert 0.5e-3 < x[h:, 0].min() - x[:h, 0].max() < 2e-3
+
+
+def _particle_cluster(k, radius, seed):
+    """k particles in a ball of the given radius (pairwise more than 2e-5 m apart),
+    each heading 2e-4 m (std) in a random direction: every pair is a contact row."""
+    rng = np.random.default_rng(seed)
+    pts = []
+    while len(pts) < k:
+        p = rng.uniform(-radius, radius, 3)
+        if np.linalg.norm(p) <= radius and all(np.linalg.norm(p - q) > 2e-5 for q in pts):
+            pts.append(p)
+    x = np.array(pts)
+    return x, x + rng.normal(0.0, 2e-4, x.shape)
+
+
+def _particle_dimers(nd, seed, spacing=5e-3, gap=5e-4):
+    """nd particle pairs gap apart on a lattice spacing apart, moving 0.4 mm towards
+    each other: nd contact rows over 2 nd vertices."""
+    rng = np.random.default_rng(seed)
+    m = int(np.ceil(nd ** (1 / 3)))
+    c = np.stack(np.meshgrid(*[np.arange(m)] * 3, indexing="ij"), -1).reshape(-1, 3)[:nd] * spacing
+    u = rng.normal(size=(nd, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    x = np.concatenate([c + 0.5 * gap * u, c - 0.5 * gap * u])
+    xt = x.copy()
+    xt[:nd] -= 4e-4 * u
+    xt[nd:] += 4e-4 * u
+    return x, xt
+
+
+@pytest.mark.parametrize("kind", ["cluster", "dimers_lds", "dimers_many"])
+def test_small_contact_set_colouring_paths_lockstep(cc, ctx, kind):
+    # Contact sets of at most 4096 rows are coloured by one block with the vertex
+    # state in LDS; a set whose colours pass 127 (the 90-particle cluster needs
+    # about 136) or that touches more than 2048 free vertices (1500 dimers) is
+    # coloured by the same block with the global-memory rounds instead.
+    if kind == "cluster":
+        x, xt = _particle_cluster(90, 4.5e-4, 5)
+    else:
+        x, xt = _particle_dimers(900 if kind == "dimers_lds" else 1500, 7)
+    sc = {"name": kind, "x": x, "xt": xt, "w": np.ones(len(x)),
+          "tris": np.zeros((0, 3), np.int32), "edges": np.zeros((0, 2), np.int32), "params": {}}
+    n, ref, gpu = _lockstep(cc, ctx, sc, 6)
+    assert n >= 2
+    if kind == "cluster":
+        # the first iteration's colouring needed more than the 128 colours kept in LDS
+        ref2 = oracle.Scene(sc["w"], sc["tris"], sc["edges"], max_iters=1)
+        ref2.begin(x, xt)
+        assert ref2.iterate()[1]["n_colors"] > 128
