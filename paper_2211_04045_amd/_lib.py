@@ -19,6 +19,7 @@ CC_TRACE = 4
 CC_MIXED = 8
 CC_VALIDATE_INPUT = 16
 CC_CCD_ALL = 32
+CC_TIME_SEARCH = 64
 CC_GAUSS_SEIDEL = 0
 CC_JACOBI = 1
 K_NAMES = ["search", "pair", "color", "gs", "forward", "cert"]

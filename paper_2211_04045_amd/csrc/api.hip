@@ -307,18 +307,23 @@ hipEvent_t pool_event(cc_solver* s) {
 }
 
 void timer_begin(cc_solver* s, int kind, hipStream_t st) {
-  if (!(s->p.flags & CC_TIME_KERNELS)) return;
+  s->timer_open = false;
+  if (!(s->p.flags & CC_TIME_KERNELS) &&
+      !((s->p.flags & CC_TIME_SEARCH) && kind == CC_K_SEARCH))
+    return;
   Timer t;
   t.kind = kind;
   t.a = pool_event(s);
   t.b = pool_event(s);
   (void)hipEventRecord(t.a, st);
   s->timers.push_back(t);
+  s->timer_open = true;
 }
 
 void timer_end(cc_solver* s, hipStream_t st) {
-  if (!(s->p.flags & CC_TIME_KERNELS) || s->timers.empty()) return;
+  if (!s->timer_open || s->timers.empty()) return;
   (void)hipEventRecord(s->timers.back().b, st);
+  s->timer_open = false;
 }
 
 // ---------------------------------------------------------------- engine

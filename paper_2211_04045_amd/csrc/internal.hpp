@@ -67,12 +67,12 @@ struct Counters {
   unsigned long long fp_pf, fp_a, fp_col;
   unsigned long long err;       // bit 0: palette exhausted, bit 1: stack overflow,
                                 // bit 2: bad index, bit 3: non-finite input
+  unsigned long long ncand;     // search: node records read
   unsigned long long ncol;      // colours used (max colour + 1)
   unsigned long long n_rows;    // edge rows in use
   unsigned long long hits;      // continuous-test contacts among the failures
   unsigned long long et;        // input check: an edge meets a triangle
   unsigned long long ncert;     // certificate: pairs queued for the continuous test
-  unsigned long long ncand;     // search: node records read
 };
 
 // Device buffers of a linear BVH over n leaves (n-1 internal nodes), allocated
@@ -253,6 +253,7 @@ struct cc_solver {
   // statistics and timing
   cc_stats st{};
   std::vector<cc::Timer> timers;
+  bool timer_open = false;  // the last timer_begin recorded its start event
   std::vector<hipEvent_t> event_pool;
 };
 

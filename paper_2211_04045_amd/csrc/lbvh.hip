@@ -21,6 +21,8 @@
 // Several scenes (segments) are searched together: a segment's rank sits above
 // the Morton code in the sort key, so each segment's leaves form one subtree
 // of the radix tree, and its queries start at that subtree's root.
+#include <cstddef>
+
 #include "geom.hpp"
 #include "internal.hpp"
 
@@ -1256,9 +1258,14 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
   int rb = 0;
   while ((1 << rb) < nsel) ++rb;
   const double infl = 0.5 * dmax;
-  CC_HIP(hipMemsetAsync(&s->dc->n_out, 0, sizeof(unsigned long long), st));
-  CC_HIP(hipMemsetAsync(&s->dc->err, 0, sizeof(unsigned long long), st));
-  CC_HIP(hipMemsetAsync(&s->dc->ncand, 0, sizeof(unsigned long long), st));
+  // the search counts into n_out, err and ncand: one fill clears the counters from
+  // n_out to ncand (none of those between is pending when a search starts; the
+  // colour, edge-row and input-check counters after them are left alone)
+  static_assert(offsetof(Counters, n_out) == 0 && offsetof(Counters, ncand) > offsetof(Counters, err) &&
+                    offsetof(Counters, n_rows) > offsetof(Counters, ncand) &&
+                    offsetof(Counters, et) > offsetof(Counters, ncand),
+                "search counters first");
+  CC_HIP(hipMemsetAsync(s->dc, 0, offsetof(Counters, ncand) + sizeof(unsigned long long), st));
   *nfound = 0;
   const int64_t m = (int64_t)mt + me + mp;
   // the tree of the last build serves again (refit) when the same scenes, in the same
