@@ -244,7 +244,7 @@ def main():
     # the timed steps carry HIP events around the dominant kernel's launches only
     # (events around every family cost host time the step would not spend)
     dom = dominant(warm) if warm else "search"
-    timed = {"time_search": True} if dom == "search" else ALL
+    timed = {"time_one": dom}
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     lat, stats = [], []

@@ -45,7 +45,8 @@ enum {
                         repeated index in a primitive, NaN/Inf position, invalid
                         parameter (d_min < delta, d_max <= d_min, gamma not in (0,1),
                         sigma < 1, eps <= 0, max_iters < 1, gs_sweeps < 1, omega not in
-                        (0,1], unknown backward solver, CC_JACOBI with CC_MIXED) */
+                        (0,1], unknown backward solver, CC_JACOBI with CC_MIXED,
+                        CC_TIME_ONE with time_kind outside 0..CC_K_COUNT-1) */
   CC_ENOMEM = -2,    /* device allocation failed */
   CC_EOVERFLOW = -3, /* pair capacity exceeded after regrowth */
   CC_EHIP = -4,      /* HIP runtime error */
@@ -73,8 +74,8 @@ enum { CC_CONVERGED = 0, CC_MAXITER = 1 };
 #define CC_CCD_ALL 32u      /* every pair of P' takes the continuous test of the piece, not
                                only those the motion bound (lemma of Sec. 5) leaves
                                uncertified: a check of the path, at its cost */
-#define CC_TIME_SEARCH 64u  /* time the search family (CC_K_SEARCH) alone with HIP events:
-                               the other families run without events around them */
+#define CC_TIME_ONE 64u     /* time one kernel family alone (cc_params.time_kind) with HIP
+                               events: the other families run without events around them */
 #define CC_MIXED 8u         /* mixed precision: the backward step (constraint values,
                                Jacobians, multipliers and y - x) in FP32; every set
                                decision, distance, D_i, x, the forward step and the
@@ -92,13 +93,13 @@ typedef struct cc_params {
   int32_t max_iters; /* L: 512 (dt = 1/100 s) .. 2048 (dt = 1/20 s) */
   int32_t gs_sweeps; /* Gauss-Seidel sweeps per backward step, 1 (Sec. 4.3.1) */
   int32_t max_colors;/* colour palette, <= 1024 */
-  uint32_t flags;    /* CC_EDGE_LEN | CC_TIME_KERNELS | CC_TIME_SEARCH | CC_TRACE | CC_MIXED |
+  uint32_t flags;    /* CC_EDGE_LEN | CC_TIME_KERNELS | CC_TIME_ONE | CC_TRACE | CC_MIXED |
                         CC_VALIDATE_INPUT | CC_CCD_ALL */
   uint64_t seed;     /* colouring priority seed */
   double omega;      /* CC_JACOBI: under-relaxation factor in (0, 1] (Sec. 4.3.2 names the
                         factor but gives no value; default 0.5) */
   int32_t backward;  /* CC_GAUSS_SEIDEL (default, Sec. 4.3) or CC_JACOBI (Sec. 4.3.2) */
-  int32_t pad_;
+  int32_t time_kind; /* CC_TIME_ONE: the family timed (CC_K_SEARCH .. CC_K_CERT; default 0) */
 } cc_params;
 
 /* backward-step solvers */
@@ -149,7 +150,7 @@ typedef struct cc_stats {
   int64_t ccd_fail;
   int64_t ccd_hits;
   double r_inf;
-  double kernel_ms[CC_K_COUNT];        /* with CC_TIME_KERNELS (CC_TIME_SEARCH: the search) */
+  double kernel_ms[CC_K_COUNT];        /* with CC_TIME_KERNELS (CC_TIME_ONE: that family) */
   int64_t kernel_launches[CC_K_COUNT];
   double kernel_bytes[CC_K_COUNT];     /* algorithmic bytes moved */
 } cc_stats;

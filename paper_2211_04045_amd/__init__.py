@@ -11,12 +11,12 @@ from __future__ import annotations
 import ctypes as C
 
 from . import _lib
-from ._lib import (CC_CCD_ALL, CC_EDGE_LEN, CC_MIXED, CC_TIME_KERNELS, CC_TIME_SEARCH, CC_TRACE,
+from ._lib import (CC_CCD_ALL, CC_EDGE_LEN, CC_MIXED, CC_TIME_KERNELS, CC_TIME_ONE, CC_TRACE,
                    CC_VALIDATE_INPUT, CCError, IterInfo, Params, SceneDesc, Stats)
 
 __all__ = ["Context", "Solver", "Server", "collide_step", "collide_step_batched", "params",
            "edges_from_tris", "normal_flow_target", "CC_EDGE_LEN", "CC_TIME_KERNELS",
-           "CC_TIME_SEARCH", "CC_TRACE", "CC_MIXED", "CC_VALIDATE_INPUT", "CC_CCD_ALL", "CCError"]
+           "CC_TIME_ONE", "CC_TRACE", "CC_MIXED", "CC_VALIDATE_INPUT", "CC_CCD_ALL", "CCError"]
 
 
 def _torch():
@@ -52,8 +52,8 @@ def _ptr(t):
 
 def params(**over) -> Params:
     """Defaults of Table 2 (cc_default_params) with keyword overrides; the flags
-    are set with edge_len=, time_kernels=, time_search=, trace=, mixed=, validate= and ccd_all=
-    (booleans);
+    are set with edge_len=, time_kernels=, trace=, mixed=, validate= and ccd_all=
+    (booleans) and time_one= (a family name of K_NAMES: that family alone is timed);
     backward= takes "gs" (default) or "jacobi"."""
     p = Params()
     _lib.load().cc_default_params(C.byref(p))
@@ -62,8 +62,12 @@ def params(**over) -> Params:
             p.flags = (p.flags | CC_EDGE_LEN) if v else (p.flags & ~CC_EDGE_LEN)
         elif k == "time_kernels":
             p.flags = (p.flags | CC_TIME_KERNELS) if v else (p.flags & ~CC_TIME_KERNELS)
-        elif k == "time_search":
-            p.flags = (p.flags | CC_TIME_SEARCH) if v else (p.flags & ~CC_TIME_SEARCH)
+        elif k == "time_one":
+            if v is None:
+                p.flags &= ~CC_TIME_ONE
+            else:
+                p.flags |= CC_TIME_ONE
+                p.time_kind = _lib.K_NAMES.index(v) if isinstance(v, str) else int(v)
         elif k == "trace":
             p.flags = (p.flags | CC_TRACE) if v else (p.flags & ~CC_TRACE)
         elif k == "mixed":

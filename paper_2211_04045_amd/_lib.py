@@ -19,7 +19,7 @@ CC_TRACE = 4
 CC_MIXED = 8
 CC_VALIDATE_INPUT = 16
 CC_CCD_ALL = 32
-CC_TIME_SEARCH = 64
+CC_TIME_ONE = 64
 CC_GAUSS_SEIDEL = 0
 CC_JACOBI = 1
 K_NAMES = ["search", "pair", "color", "gs", "forward", "cert"]
@@ -45,7 +45,7 @@ class Params(C.Structure):
                 ("sigma", C.c_double), ("gamma", C.c_double), ("eps", C.c_double),
                 ("kappa", C.c_double), ("max_iters", C.c_int32), ("gs_sweeps", C.c_int32),
                 ("max_colors", C.c_int32), ("flags", C.c_uint32), ("seed", C.c_uint64),
-                ("omega", C.c_double), ("backward", C.c_int32), ("pad_", C.c_int32)]
+                ("omega", C.c_double), ("backward", C.c_int32), ("time_kind", C.c_int32)]
 
 
 class IterInfo(C.Structure):

@@ -70,6 +70,7 @@ int check_params(const cc_params* p) {
   if (p->max_iters < 1 || p->gs_sweeps < 1) return CC_EINVAL;
   if (p->max_colors < 1 || p->max_colors > kMaxColors) return CC_EINVAL;
   if (p->backward != CC_GAUSS_SEIDEL && p->backward != CC_JACOBI) return CC_EINVAL;
+  if ((p->flags & CC_TIME_ONE) && (p->time_kind < 0 || p->time_kind >= CC_K_COUNT)) return CC_EINVAL;
   if (p->backward == CC_JACOBI && (!(p->omega > 0.0 && p->omega <= 1.0) || (p->flags & CC_MIXED)))
     return CC_EINVAL;
   return CC_OK;
@@ -132,6 +133,7 @@ void free_active(cc_solver* s) {
 
 // Pair buffers of capacity cap; the first `keep` keys of P survive.
 int alloc_pairs(cc_solver* s, int64_t cap, int64_t keep, hipStream_t st) {
+  s->mv_gen = ~0ull;  // the stored distances do not survive
   CC_TRY(dregrow(&s->P, cap, keep, st));
   dfree(s->P2); dfree(s->dP); dfree(s->dP2);
   s->capP = cap;
@@ -159,7 +161,7 @@ int alloc_active(cc_solver* s, int64_t cap) {
 
 void free_vertex_arrays(cc_solver* s) {
   dfree(s->w); dfree(s->stat); dfree(s->x); dfree(s->y); dfree(s->xt); dfree(s->xold);
-  dfree(s->r); dfree(s->move2); dfree(s->Di); dfree(s->vseg); dfree(s->plist); dfree(s->dy);
+  dfree(s->r); dfree(s->move2); dfree(s->mvd); dfree(s->Di); dfree(s->vseg); dfree(s->plist); dfree(s->dy);
   dfree(s->jacc);
   dfree(s->vmax0); dfree(s->claims); dfree(s->masks); dfree(s->vloc);
 }
@@ -219,6 +221,9 @@ int resize_arrays(cc_solver* s, int32_t capV, int32_t capF, int32_t capE, hipStr
     dfree(s->xold); dfree(s->move2); dfree(s->Di); dfree(s->vmax0); dfree(s->claims); dfree(s->masks);
     CC_TRY(dalloc(&s->xold, 3 * (int64_t)capV));
     CC_TRY(dalloc(&s->move2, capV));
+    dfree(s->mvd);
+    CC_TRY(dalloc(&s->mvd, capV));
+    s->mv_gen = ~0ull;
     CC_TRY(dalloc(&s->Di, capV));
     CC_TRY(dalloc(&s->vmax0, capV));
     CC_TRY(dalloc(&s->claims, (int64_t)capV * 2 * kMaskWords));
@@ -309,7 +314,7 @@ hipEvent_t pool_event(cc_solver* s) {
 void timer_begin(cc_solver* s, int kind, hipStream_t st) {
   s->timer_open = false;
   if (!(s->p.flags & CC_TIME_KERNELS) &&
-      !((s->p.flags & CC_TIME_SEARCH) && kind == CC_K_SEARCH))
+      !((s->p.flags & CC_TIME_ONE) && kind == s->p.time_kind))
     return;
   Timer t;
   t.kind = kind;
@@ -651,6 +656,7 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
   }
   const int64_t n_eval = s->nP;
   const int64_t npf = (int64_t)s->hc->n_out, na = (int64_t)s->hc->n_act;
+  s->mv_gen = ~0ull;  // valid again once this iteration's forward step has completed
   const uint64_t fp_pf = s->hc->fp_pf, fp_a = s->hc->fp_a;
   if (in_place && npf != n_eval) return CC_EHIP;  // cannot happen: the search kept d < D_max
   if (!in_place) {
@@ -713,6 +719,9 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
     s->pc_dirty = false;
     s->n_colors = (int32_t)s->hc->ncol;
   }
+  // the forward step wrote every iterating vertex's moved flag, and P' holds the
+  // distances at the x it started from
+  s->mv_gen = s->gen;
   resolve_timers(s);
   bool changed = false;
   for (int32_t sg : act) {
@@ -827,7 +836,7 @@ void cc_default_params(cc_params* p) {
   p->seed = 0x221104045ull;
   p->omega = 0.5;
   p->backward = CC_GAUSS_SEIDEL;
-  p->pad_ = 0;
+  p->time_kind = CC_K_SEARCH;
 }
 
 const char* cc_strerror(int code) {

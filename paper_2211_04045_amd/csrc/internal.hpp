@@ -186,6 +186,11 @@ struct cc_solver {
   uint8_t* stat = nullptr;
   // state
   double *x = nullptr, *y = nullptr, *xt = nullptr, *r = nullptr, *move2 = nullptr;
+  // per vertex: the last forward step changed x; valid for the pairs' stored distances
+  // while mv_gen equals gen (set when an iteration completes, cleared by anything that
+  // moves x or drops the distances from outside)
+  uint8_t* mvd = nullptr;
+  uint64_t mv_gen = ~0ull;
   float* dy = nullptr;  // mixed precision: y - x in FP32 (3 per vertex)
   long long* jacc = nullptr;  // projected Jacobi: per-vertex update sums, 2^-56 m units
   double* xold = nullptr;  // x^(l) kept by the forward step for the continuous test

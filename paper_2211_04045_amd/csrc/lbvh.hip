@@ -694,6 +694,7 @@ struct TravArgs {
   int32_t mv, me, mp;     // vertex, edge and particle queries
   int32_t mv_pad, me_pad; // the first two counts rounded up to whole waves
   double infl, dmax2;
+  float fdmax;  // dmax rounded up to FP32 (the Euclidean box test below)
   uint64_t* out;
   double* outd;  // d^2 of each pair found (same function and operand order as the pair pass)
   int64_t cap;
@@ -703,6 +704,21 @@ struct TravArgs {
 __device__ __forceinline__ bool overlap6(float4 ql, float4 qh, float lx, float ly, float lz,
                                          float hx, float hy, float hz) {
   return ql.x <= hx && lx <= qh.x && ql.y <= hy && ly <= qh.y && ql.z <= hz && lz <= qh.z;
+}
+
+// Boxes that overlap6 accepts but whose un-inflated boxes lie farther apart than
+// dmax in the Euclidean norm hold no pair within dmax (a primitive lies in its box,
+// and the FP32 boxes contain the FP64 ones). Both boxes carry half of dmax, so the
+// separation on an axis is max(0, gap + dmax); r2 is (dmax + m)^2 with m =
+// 1e-6 (1 + |query|_inf) m, far above the FP32 rounding of these few operations
+// (about 2.4e-7 |query|_inf + 1.5e-7 dmax), so a box is dropped only when the exact
+// FP64 test would reject every primitive in it.
+__device__ __forceinline__ bool far6(float4 ql, float4 qh, float lx, float ly, float lz, float hx,
+                                     float hy, float hz, float fdmax, float r2) {
+  const float sx = fmaxf(0.f, fmaxf(ql.x - hx, lx - qh.x) + fdmax);
+  const float sy = fmaxf(0.f, fmaxf(ql.y - hy, ly - qh.y) + fdmax);
+  const float sz = fmaxf(0.f, fmaxf(ql.z - hz, lz - qh.z) + fdmax);
+  return sx * sx + sy * sy + sz * sz > r2;
 }
 
 __device__ __forceinline__ uint64_t lanes_below_tr() {
@@ -924,6 +940,14 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
     qn = 0;
     __builtin_amdgcn_wave_barrier();
   }
+  // (dmax + m)^2 of the Euclidean box test, m = 1e-6 (1 + |query|_inf)
+  float qr2;
+  {
+    const float qm = fmaxf(fmaxf(fmaxf(fabsf(qlo.x), fabsf(qhi.x)), fmaxf(fabsf(qlo.y), fabsf(qhi.y))),
+                           fmaxf(fabsf(qlo.z), fabsf(qhi.z)));
+    const float r = A.fdmax + 1e-6f * (1.f + qm);
+    qr2 = r * r;
+  }
   bool todo = active && root >= 0;  // this lane's subtree still to walk
   bool part = false;                // this lane takes part in its group's current walk
   int sp = 0;                       // the group's stack depth (uniform in the group)
@@ -967,7 +991,8 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
     for (int slot = 0; slot < 4; ++slot) {
       const float4 b0 = rb0[slot], b1 = rb1[slot];
       const bool ov = valid && part && overlap6(qlo, qhi, b0.x, b0.y, b0.z, b0.w, b1.x, b1.y) &&
-                      __float_as_int(b1.w) > qpos;
+                      __float_as_int(b1.w) > qpos &&
+                      !far6(qlo, qhi, b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, A.fdmax, qr2);
       const uint64_t m = __ballot(ov);
       const int32_t c = __float_as_int(b1.z);
       // internal child: the group enters it
@@ -1353,6 +1378,8 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
     A.mp = mp;
     A.infl = infl;
     A.dmax2 = dmax * dmax;
+    A.fdmax = (float)dmax;
+    if ((double)A.fdmax < dmax) A.fdmax = nextafterf(A.fdmax, __builtin_inff());
     A.out = out;
     A.outd = outd;
     A.cap = cap;

@@ -65,8 +65,8 @@ bool same_params(const cc_params& a, const cc_params& b) {
   return a.delta == b.delta && a.d_min == b.d_min && a.d_max == b.d_max && a.sigma == b.sigma &&
          a.gamma == b.gamma && a.eps == b.eps && a.kappa == b.kappa &&
          a.gs_sweeps == b.gs_sweeps && a.max_colors == b.max_colors &&
-         (a.flags & ~(CC_TIME_KERNELS | CC_TIME_SEARCH)) ==
-             (b.flags & ~(CC_TIME_KERNELS | CC_TIME_SEARCH)) &&
+         (a.flags & ~(CC_TIME_KERNELS | CC_TIME_ONE)) ==
+             (b.flags & ~(CC_TIME_KERNELS | CC_TIME_ONE)) &&
          a.seed == b.seed;
 }
 

@@ -312,6 +312,7 @@ struct PairPassArgs {
   int64_t n_old;  // [0, n_old): last P'; [n_old, nP): appended by this iteration's search
   int64_t d_from;    // pairs i >= d_from read d^2 from dPin instead of computing it
   const double* dPin;
+  const uint8_t* mvd;  // moved flags of the last forward step (null: every distance is taken)
   const double* x;
   Topo T;
   const int32_t* vseg;
@@ -427,16 +428,21 @@ __global__ void __launch_bounds__(kThreads) k_pair_pass(PairPassArgs a) {
   int32_t csg = -1;                        // segment of the counts held in registers
   unsigned long long cnt[3] = {0, 0, 0};  // evaluated, in P', in A
   // Every load of the thread's pairs is issued before any distance is taken
-  // (keys, then topology, then segment ids and the four vertices' positions), so
-  // the dependent gathers of the pairs overlap instead of running one after the
-  // other.
+  // (keys and stored distances, then topology, then segment ids, moved flags and
+  // the four vertices' positions), so the dependent gathers of the pairs overlap
+  // instead of running one after the other. A pair of last iteration's P' none of
+  // whose vertices the forward step moved keeps its stored distance: the same
+  // function of the same positions.
   int32_t pv[kPairsPerThread][4];
   int32_t psg[kPairsPerThread];
   V3 px[kPairsPerThread][4];
+  double dst[kPairsPerThread];
+  bool fresh[kPairsPerThread];  // the distance is taken from the positions
 #pragma unroll
   for (int k = 0; k < kPairsPerThread; ++k) {
     const int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
     keys[k] = i < a.nP ? a.P[i] : 0ull;
+    dst[k] = i < a.nP && (a.mvd || i >= a.d_from) ? a.dPin[i] : 0.0;
   }
 #pragma unroll
   for (int k = 0; k < kPairsPerThread; ++k) {
@@ -448,7 +454,10 @@ __global__ void __launch_bounds__(kThreads) k_pair_pass(PairPassArgs a) {
   for (int k = 0; k < kPairsPerThread; ++k) {
     const int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
     psg[k] = a.vseg[pv[k][0]];
-    if (i < a.d_from) {
+    fresh[k] = i < a.d_from;
+    if (fresh[k] && a.mvd)
+      fresh[k] = (a.mvd[pv[k][0]] | a.mvd[pv[k][1]] | a.mvd[pv[k][2]] | a.mvd[pv[k][3]]) != 0;
+    if (fresh[k]) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) px[k][q] = ld3(a.x, pv[k][q]);
     }
@@ -466,9 +475,8 @@ __global__ void __launch_bounds__(kThreads) k_pair_pass(PairPassArgs a) {
       const int32_t fl = sg >= 0 ? a.seg[sg].flags : 0;
       const bool live = (fl & kSegActive) && !(i < a.n_old && (fl & kSegSearched));
       if (live) {
-        const double d2 = i < a.d_from
-                              ? pair_d2(key, px[k][0], px[k][1], px[k][2], px[k][3])
-                              : a.dPin[i];
+        const double d2 =
+            fresh[k] ? pair_d2(key, px[k][0], px[k][1], px[k][2], px[k][3]) : dst[k];
         keys[k] = key;
         d2s[k] = d2;
         vs[k] = make_int4(v[0], v[1], v[2], v[3]);
@@ -559,6 +567,7 @@ int launch_pair_pass(cc_solver* s, int64_t n_old, int64_t d_from, double dl2, bo
   a.n_old = n_old;
   a.d_from = d_from;
   a.dPin = s->dP;
+  a.mvd = s->mv_gen == s->gen ? s->mvd : nullptr;
   a.x = s->x;
   a.T = Topo{s->tris, s->edges};
   a.vseg = s->vseg;
@@ -1825,7 +1834,8 @@ __global__ void __launch_bounds__(kThreads) k_forward(double* __restrict__ x,
                                                       double* __restrict__ move2, int32_t n,
                                                       double hg, const int32_t* __restrict__ vseg,
                                                       SegDev* seg,
-                                                      const unsigned long long* err) {
+                                                      const unsigned long long* err,
+                                                      uint8_t* __restrict__ mvd) {
   if (err && (*err & 1ull)) return;  // the colouring of this step failed: x stays
   __shared__ int32_t gkey[kSegSlots];
   __shared__ unsigned long long gmax[kSegSlots][2];
@@ -1862,6 +1872,7 @@ __global__ void __launch_bounds__(kThreads) k_forward(double* __restrict__ x,
     V3 mv = vsub(xn, xi);
     double m2 = vdot(mv, mv);
     move2[i] = m2;
+    mvd[i] = (xn.x != xi.x || xn.y != xi.y || xn.z != xi.z) ? 1 : 0;
     st3(xold, i, xi);
     st3(x, i, xn);
     double ri = r[i] * (1.0 - alpha);
@@ -1890,10 +1901,12 @@ int launch_forward(cc_solver* s, hipStream_t st) {
   const unsigned long long* err = s->col_small ? &s->dc->err : nullptr;
   if (s->n > 0 && (s->p.flags & CC_MIXED))
     k_forward<true><<<nblk(s->n), kThreads, 0, st>>>(s->x, s->xold, s->y, s->dy, s->Di, s->r,
-                                                      s->move2, s->n, hg, s->vseg, s->seg_dev, err);
+                                                      s->move2, s->n, hg, s->vseg, s->seg_dev, err,
+                                                      s->mvd);
   else if (s->n > 0)
     k_forward<false><<<nblk(s->n), kThreads, 0, st>>>(s->x, s->xold, s->y, s->dy, s->Di, s->r,
-                                                       s->move2, s->n, hg, s->vseg, s->seg_dev, err);
+                                                       s->move2, s->n, hg, s->vseg, s->seg_dev, err,
+                                                       s->mvd);
   CC_HIP(hipGetLastError());
   return CC_OK;
 }
