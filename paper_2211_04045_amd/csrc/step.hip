@@ -327,6 +327,7 @@ struct PairPassArgs {
   Counters* c;
   int trace;
   int in_place;  // every pair is kept (fresh from a search of every scene): P' is P, unwritten
+  int32_t one_seg;  // >= 0: every pair of P belongs to this (the only) segment
 };
 
 constexpr int kHash = 2048;         // LDS slots for the per-block D_i minimum
@@ -385,7 +386,7 @@ __device__ __forceinline__ void flush_min_table(int32_t* hkey, unsigned long lon
     int32_t vv = hkey[t];
     if (vv >= 0) {
       unsigned long long b = hval[t];
-      if (b < Di[vv]) atomicMin(&Di[vv], b);
+      atomicMin(&Di[vv], b);  // no read first: the wave does not wait on it
       hkey[t] = -1;
       hval[t] = ~0ull;
     }
@@ -453,7 +454,7 @@ __global__ void __launch_bounds__(kThreads) k_pair_pass(PairPassArgs a) {
 #pragma unroll
   for (int k = 0; k < kPairsPerThread; ++k) {
     const int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
-    psg[k] = a.vseg[pv[k][0]];
+    psg[k] = a.one_seg >= 0 ? a.one_seg : a.vseg[pv[k][0]];
     fresh[k] = i < a.d_from;
     if (fresh[k] && a.mvd)
       fresh[k] = (a.mvd[pv[k][0]] | a.mvd[pv[k][1]] | a.mvd[pv[k][2]] | a.mvd[pv[k][3]]) != 0;
@@ -582,6 +583,9 @@ int launch_pair_pass(cc_solver* s, int64_t n_old, int64_t d_from, double dl2, bo
   a.c = s->dc;
   a.trace = trace ? 1 : 0;
   a.in_place = in_place ? 1 : 0;
+  // one scene and no removed scene's pairs left in P: the segment of a pair is known
+  // without its vertex's segment id
+  a.one_seg = (s->segs.size() == 1 && s->segs[0].live && s->pending_segs.empty()) ? 0 : -1;
   if (s->nP > 0) k_pair_pass<<<nblk(s->nP, kThreads * kPairsPerThread), kThreads, 0, st>>>(a);
   CC_HIP(hipGetLastError());
   return CC_OK;
