@@ -741,32 +741,36 @@ __device__ __forceinline__ bool candidate(const TravArgs& A, int kind, int32_t p
   // (out and out_d2 point at the lane's next LDS buffer slot; written on success)
   double d2;
   uint64_t key;
+  // (positions are loaded before the static flags are tested, so both loads follow
+  // the topology together)
   if (kind == kQVV) {
-    if (A.stat[qv0] && A.stat[prim]) return false;
     const V3 xb = ld3(A.x, prim);
+    if (A.stat[qv0] && A.stat[prim]) return false;
     const V3 d = qid < prim ? vsub(qx0, xb) : vsub(xb, qx0);
     d2 = vdot(d, d);
     key = qid < prim ? (KEY_VV | ((uint64_t)(uint32_t)qid << 32) | (uint32_t)prim)
                      : (KEY_VV | ((uint64_t)(uint32_t)prim << 32) | (uint32_t)qid);
   } else if (kind == kQVT) {
     int32_t v1 = A.tris[3 * prim], v2 = A.tris[3 * prim + 1], v3 = A.tris[3 * prim + 2];
+    const V3 xa = ld3(A.x, v1), xb = ld3(A.x, v2), xc = ld3(A.x, v3);
     if (qv0 == v1 || qv0 == v2 || qv0 == v3 ||
         (A.stat[qv0] && A.stat[v1] && A.stat[v2] && A.stat[v3]))
       return false;
     double bw[3];
-    d2 = pt_tri_d2(qx0, ld3(A.x, v1), ld3(A.x, v2), ld3(A.x, v3), bw);
+    d2 = pt_tri_d2(qx0, xa, xb, xc, bw);
     key = ((uint64_t)(uint32_t)qid << 32) | (uint32_t)prim;
   } else {
     int32_t v1 = A.edges[2 * prim], v2 = A.edges[2 * prim + 1];
+    const V3 xa = ld3(A.x, v1), xb = ld3(A.x, v2);
     if (qv0 == v1 || qv0 == v2 || qv1 == v1 || qv1 == v2 ||
         (A.stat[qv0] && A.stat[qv1] && A.stat[v1] && A.stat[v2]))
       return false;
     double s, t;
     if (qid < prim) {
-      d2 = seg_seg_d2(qx0, qx1, ld3(A.x, v1), ld3(A.x, v2), s, t);
+      d2 = seg_seg_d2(qx0, qx1, xa, xb, s, t);
       key = KEY_EE | ((uint64_t)(uint32_t)qid << 32) | (uint32_t)prim;
     } else {
-      d2 = seg_seg_d2(ld3(A.x, v1), ld3(A.x, v2), qx0, qx1, s, t);
+      d2 = seg_seg_d2(xa, xb, qx0, qx1, s, t);
       key = KEY_EE | ((uint64_t)(uint32_t)prim << 32) | (uint32_t)qid;
     }
   }
