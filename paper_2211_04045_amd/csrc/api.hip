@@ -227,7 +227,11 @@ int resize_arrays(cc_solver* s, int32_t capV, int32_t capF, int32_t capE, hipStr
     CC_TRY(dalloc(&s->Di, capV));
     CC_TRY(dalloc(&s->vmax0, capV));
     CC_TRY(dalloc(&s->claims, (int64_t)capV * 2 * kMaskWords));
-    s->pc_dirty = true;
+    // the colouring counts and claims start at zero over the whole capacity: a later
+    // scene may reach vertices beyond the extent in use now
+    CC_HIP(hipMemsetAsync(s->vmax0, 0, sizeof(unsigned long long) * (size_t)capV, st));
+    CC_HIP(hipMemsetAsync(s->claims, 0, sizeof(unsigned long long) * (size_t)capV * 2 * kMaskWords, st));
+    s->pc_dirty = false;
     CC_TRY(dalloc(&s->masks, (int64_t)capV * kMaskWords));
     dfree(s->vloc);
     CC_TRY(dalloc(&s->vloc, capV));

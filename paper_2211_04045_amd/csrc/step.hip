@@ -1195,9 +1195,10 @@ int color_small(cc_solver* s, hipStream_t st) {
   s->col_small = true;
   if (s->nA == 0) return CC_OK;
   if (s->nA > kSmallRows) return CC_EINVAL;
-  if (s->pc_dirty) {  // an aborted colouring left counts or claims behind
-    CC_HIP(hipMemsetAsync(s->vmax0, 0, sizeof(unsigned long long) * s->n, st));
-    CC_HIP(hipMemsetAsync(s->claims, 0, sizeof(unsigned long long) * s->n * 2 * kMaskWords, st));
+  if (s->pc_dirty) {  // an aborted colouring left counts or claims behind (over any extent)
+    CC_HIP(hipMemsetAsync(s->vmax0, 0, sizeof(unsigned long long) * (size_t)s->capV, st));
+    CC_HIP(hipMemsetAsync(s->claims, 0, sizeof(unsigned long long) * (size_t)s->capV * 2 * kMaskWords,
+                          st));
   }
   // clean again once the iteration's counters show no colouring error
   s->pc_dirty = true;
@@ -1229,9 +1230,10 @@ int color_rows(cc_solver* s, bool edges, hipStream_t st) {
     cur = s->list0;
     nxt = s->list1;
   }
-  if (s->pc_dirty) {  // an aborted colouring left counts or claims behind
-    CC_HIP(hipMemsetAsync(s->vmax0, 0, sizeof(unsigned long long) * s->n, st));
-    CC_HIP(hipMemsetAsync(s->claims, 0, sizeof(unsigned long long) * s->n * 2 * kMaskWords, st));
+  if (s->pc_dirty) {  // an aborted colouring left counts or claims behind (over any extent)
+    CC_HIP(hipMemsetAsync(s->vmax0, 0, sizeof(unsigned long long) * (size_t)s->capV, st));
+    CC_HIP(hipMemsetAsync(s->claims, 0, sizeof(unsigned long long) * (size_t)s->capV * 2 * kMaskWords,
+                          st));
     s->pc_dirty = false;
   }
   CC_HIP(hipMemsetAsync(s->masks, 0, sizeof(unsigned long long) * s->n * kMaskWords, st));
