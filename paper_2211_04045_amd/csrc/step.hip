@@ -1473,11 +1473,10 @@ __global__ void __launch_bounds__(kThreads) k_contact_rows(const uint64_t* __res
 // One projected Gauss-Seidel update of a contact row (Sec. 4.3) built by
 // k_contact_rows: residual w = c0 + sum J.(y - x), lambda <- max(0, lambda - w/A),
 // y_v += w_v dl J_v at its free vertices. Mixed precision: the row (FP64) is
-// rounded and the projection runs in FP32 on y - x.
+// rounded and the projection runs in FP32 on y - x. The caller holds the row's record
+// R (an active one: 1/A > 0); the positions at x^(l) are loaded with y.
 template <bool kMixed>
-__device__ __forceinline__ void gs_contact_update(const GsArgs& a, int32_t r) {
-  const RowRec R = a.rows[r];
-  if (!(R.inv_a > 0.0)) return;
+__device__ __forceinline__ void gs_contact_apply(const GsArgs& a, int32_t r, const RowRec& R) {
   const int32_t v[4] = {R.v.x, R.v.y, R.v.z, R.v.w};
   const int nk = v[2] < 0 ? 2 : 4;  // a vertex-vertex row has two vertices
   if (kMixed) {
@@ -1525,6 +1524,13 @@ __device__ __forceinline__ void gs_contact_update(const GsArgs& a, int32_t r) {
     yv = V3{yv.x + co * R.J[k].x, yv.y + co * R.J[k].y, yv.z + co * R.J[k].z};
     st3(a.y, v[k], yv);
   }
+}
+
+template <bool kMixed>
+__device__ __forceinline__ void gs_contact_update(const GsArgs& a, int32_t r) {
+  const RowRec R = a.rows[r];
+  if (!(R.inv_a > 0.0)) return;
+  gs_contact_apply<kMixed>(a, r, R);
 }
 
 // Edge-length row (Sec. 4.2), same projected update. Mixed precision: the part
@@ -1607,6 +1613,38 @@ __global__ void __launch_bounds__(kGsTailThreads) k_gs_tail(GsArgs a, const int3
   }
 }
 
+// Every colour of a small contact set (at most kSmallRows rows, colours and buckets on
+// the device) in one block. Position p of the colour order is updated by thread
+// p mod kGsTailThreads; the thread of position p < kGsTailThreads holds that row's
+// record from the start, so a colour costs it only the loads of x and y at the row's
+// vertices and the stores. The bucket offsets are staged in LDS.
+template <bool kMixed>
+__global__ void __launch_bounds__(kGsTailThreads) k_gs_contact_small(
+    GsArgs a, const int32_t* __restrict__ off, const unsigned long long* ncolp,
+    const unsigned long long* nAp) {
+  __shared__ int32_t s_off[kMaxColors + 1];
+  if (gs_off(a)) return;
+  const int32_t ncol = (int32_t)*ncolp;
+  const int32_t nA = (int32_t)*nAp;
+  for (int32_t c = threadIdx.x; c <= ncol; c += kGsTailThreads) s_off[c] = off[c];
+  const int32_t p0 = threadIdx.x;
+  int32_t r0 = -1;
+  RowRec R0;
+  if (p0 < nA) {
+    r0 = a.order[p0];
+    R0 = a.rows[r0];
+    if (!(R0.inv_a > 0.0)) r0 = -1;  // an inactive row does nothing
+  }
+  __syncthreads();
+  for (int32_t c = 0; c < ncol; ++c) {
+    const int32_t b = s_off[c], e = s_off[c + 1];
+    if (r0 >= 0 && p0 >= b && p0 < e) gs_contact_apply<kMixed>(a, r0, R0);
+    for (int32_t p = p0 + kGsTailThreads; p < e; p += kGsTailThreads)
+      if (p >= b) gs_contact_update<kMixed>(a, a.order[p]);
+    __syncthreads();
+  }
+}
+
 template <bool kMixed>
 static void gs_colours(const GsArgs& base, const int32_t* order, const std::vector<int32_t>& off,
                        const int32_t* off_dev, int32_t ncol, bool edge, hipStream_t st) {
@@ -1641,7 +1679,8 @@ static void gs_sweeps(cc_solver* s, GsArgs a, hipStream_t st) {
       a.order = s->Aorder;
       a.cnt = 0;
       if (s->nA > 0)
-        k_gs_tail<kMixed><<<1, kGsTailThreads, 0, st>>>(a, s->coff_dev, 0, 0, 0, &s->dc->ncol);
+        k_gs_contact_small<kMixed><<<1, kGsTailThreads, 0, st>>>(a, s->coff_dev, &s->dc->ncol,
+                                                                  &s->dc->n_act);
     } else {
       gs_colours<kMixed>(a, s->Aorder, s->col_off, s->coff_dev, s->n_colors, false, st);
     }
