@@ -191,8 +191,8 @@ def main():
         ablation(args.ablation)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; the multi-GPU sharding is a "
-                                   "design note only", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the library runs on one GPU: sharding the step over "
+                                   "several GPUs is not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
     if args.config == 5:
         serve_bench(args)

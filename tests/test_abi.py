@@ -74,3 +74,20 @@ def test_scene_bytes_grows_with_size():
     assert lib.cc_scene_bytes(1000, 4000, 3000) > a
     assert lib.cc_scene_bytes(1000, 2000, 6000) > a
     assert lib.cc_scene_bytes(-1, 0, 0) == 0
+
+
+def test_timing_flags_select_one_family():
+    """time_one= sets CC_TIME_ONE and the family index (cc_params.time_kind); the
+    default times nothing, and the flag's bit matches the header."""
+    import paper_2211_04045_amd as cc
+    from paper_2211_04045_amd import _lib
+    src = open(os.path.join(ROOT, "include", "cc.h")).read()
+    assert int(re.search(r"#define CC_TIME_ONE (\d+)u", src).group(1)) == _lib.CC_TIME_ONE
+    p = cc.params()
+    assert not (p.flags & _lib.CC_TIME_ONE) and not (p.flags & _lib.CC_TIME_KERNELS)
+    assert p.time_kind == 0
+    for i, name in enumerate(_lib.K_NAMES):
+        q = cc.params(time_one=name)
+        assert q.flags & _lib.CC_TIME_ONE and q.time_kind == i
+    assert not (cc.params(time_one="pair", **{}).flags & _lib.CC_TIME_KERNELS)
+    assert not (cc.params(time_one=None).flags & _lib.CC_TIME_ONE)
