@@ -722,6 +722,7 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
     if (s->hc->err & 1ull) return CC_ECOLOR;
     s->pc_dirty = false;
     s->n_colors = (int32_t)s->hc->ncol;
+    s->pc_wide = s->n_colors > 56;
   }
   // the forward step wrote every iterating vertex's moved flag, and P' holds the
   // distances at the x it started from

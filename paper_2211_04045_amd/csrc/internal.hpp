@@ -212,6 +212,7 @@ struct cc_solver {
   int32_t n_colors = 0;
   std::vector<int32_t> col_off;  // host copy of colour bucket offsets (n_colors+1)
   bool col_small = false;  // this step's contact colours and buckets live on the device only
+  bool pc_wide = false;    // the last one-block colouring used more than 56 colours
   int32_t* vloc = nullptr;  // per vertex: kNoLoc, or a block-local slot while one block colours
   // edge-length rows (one per edge; inv_a = 0 marks an unused edge)
   double* eg = nullptr;     // 3 per edge

@@ -840,8 +840,10 @@ __global__ void __launch_bounds__(kTailThreads) k_pc_tail(PcArgs a, int32_t* la,
 }
 
 constexpr int kSmallPer = kSmallRows / kTailThreads;  // rows per thread
-constexpr int kLocCap = 2048;  // distinct free vertices whose colouring state fits in LDS
-constexpr int kLocWords = 2;   // colour words kept per vertex in LDS (colours below 128)
+// LDS layouts of the one-block colouring: kLocWords colour words per vertex (colours
+// below 64 kLocWords) for at most kLocCap distinct free vertices. One word holds 4096
+// vertices, two words 2048 (about 110 KB of LDS either way).
+constexpr int kLocCap1 = 4096, kLocCap2 = 2048;
 static_assert(kSmallRows % kTailThreads == 0, "whole rows per thread");
 static_assert(kMaxColors == kTailThreads, "one thread per colour bucket in the scan");
 
@@ -856,6 +858,7 @@ static_assert(kMaxColors == kTailThreads, "one thread per colour bucket in the s
 // instead, with the same result (the colours depend only on the row set). Then
 // the colour buckets: counts, their exclusive scan to off (kMaxColors + 1
 // entries), the rows in colour order to order; the colour count goes to c->ncol.
+template <int kLocWords, int kLocCap>
 __global__ void __launch_bounds__(kTailThreads) k_pc_small(PcArgs a, int32_t nrows, int32_t* la,
                                                            int32_t* lb, int32_t* __restrict__ vloc,
                                                            int32_t* __restrict__ order,
@@ -1202,8 +1205,16 @@ int color_small(cc_solver* s, hipStream_t st) {
   }
   // clean again once the iteration's counters show no colouring error
   s->pc_dirty = true;
-  k_pc_small<<<1, kTailThreads, 0, st>>>(pc_args(s, false), (int32_t)s->nA, s->list0, s->list1,
-                                          s->vloc, s->Aorder, s->coff_dev, (uint64_t)kMaxRounds);
+  // one colour word (4096 vertices) unless the last such colouring used more than 56
+  // colours; either way a set that does not fit is still coloured, by the global rounds
+  if (s->pc_wide)
+    k_pc_small<2, kLocCap2><<<1, kTailThreads, 0, st>>>(pc_args(s, false), (int32_t)s->nA,
+                                                        s->list0, s->list1, s->vloc, s->Aorder,
+                                                        s->coff_dev, (uint64_t)kMaxRounds);
+  else
+    k_pc_small<1, kLocCap1><<<1, kTailThreads, 0, st>>>(pc_args(s, false), (int32_t)s->nA,
+                                                        s->list0, s->list1, s->vloc, s->Aorder,
+                                                        s->coff_dev, (uint64_t)kMaxRounds);
   CC_HIP(hipGetLastError());
   return CC_OK;
 }
