@@ -55,7 +55,9 @@
 #define KEY_EE (1ull << 63)
 #define KEY_VV (1ull << 62)
 /* distance at which the continuous test reports contact (metres) */
-#define ORC_CCD_ETA 1e-12
+/* eta: primitives closer than eta (metres) count as touching. Binary64 distances of
+ * scenes whose coordinates stay within +-10 m are exact to far better than eta. */
+#define ORC_ETA 1e-12
 
 struct orc_scene {
   int32_t n, nt, ne;
@@ -67,7 +69,8 @@ struct orc_scene {
   uint8_t* stat;
   orc_params p;
   /* state */
-  double *x, *y, *xt, *r, *xold;
+  double *x, *y, *xt, *r, *xold, *rold;
+  uint8_t* back; /* certificate: vertex returned to x^(l) in this iteration */
   double D;
   uint64_t* P;
   int64_t nP, capP;
@@ -137,8 +140,8 @@ static double pt_seg_d2(const double* p, const double* u, const double* v, doubl
  * is reached either at the orthogonal projection (when it falls inside) or on
  * one of the three edges; the candidate list is tried in this order and the
  * first strict minimum kept. bary = weights of the closest point on (a,b,c). */
-double orc_pt_tri_d2(const double* p, const double* a, const double* b,
-                     const double* c, double* bary) {
+static double pt_tri_d2w(const double* p, const double* a, const double* b,
+                         const double* c, double* bary, int* which) {
   double ab[3], ac[3], ap[3], n[3], t1[3], t2[3];
   sub3(ab, b, a);
   sub3(ac, c, a);
@@ -147,6 +150,7 @@ double orc_pt_tri_d2(const double* p, const double* a, const double* b,
   double nn = dot3(n, n);
   double best = INFINITY;
   double bw[3] = {1.0, 0.0, 0.0};
+  int win = -1;
   if (nn > 0.0) {
     cross3(t1, ap, ac);
     cross3(t2, ab, ap);
@@ -156,6 +160,7 @@ double orc_pt_tri_d2(const double* p, const double* a, const double* b,
     if (wa >= 0.0 && wb >= 0.0 && wc >= 0.0) {
       double h = dot3(ap, n);
       best = h * h / nn;
+      win = 0;
       bw[0] = wa;
       bw[1] = wb;
       bw[2] = wc;
@@ -165,6 +170,7 @@ double orc_pt_tri_d2(const double* p, const double* a, const double* b,
   e2 = pt_seg_d2(p, a, b, &t);
   if (e2 < best) {
     best = e2;
+    win = 1;
     bw[0] = 1.0 - t;
     bw[1] = t;
     bw[2] = 0.0;
@@ -172,6 +178,7 @@ double orc_pt_tri_d2(const double* p, const double* a, const double* b,
   e2 = pt_seg_d2(p, b, c, &t);
   if (e2 < best) {
     best = e2;
+    win = 2;
     bw[0] = 0.0;
     bw[1] = 1.0 - t;
     bw[2] = t;
@@ -179,6 +186,7 @@ double orc_pt_tri_d2(const double* p, const double* a, const double* b,
   e2 = pt_seg_d2(p, c, a, &t);
   if (e2 < best) {
     best = e2;
+    win = 3;
     bw[0] = t;
     bw[1] = 0.0;
     bw[2] = 1.0 - t;
@@ -188,7 +196,13 @@ double orc_pt_tri_d2(const double* p, const double* a, const double* b,
     bary[1] = bw[1];
     bary[2] = bw[2];
   }
+  if (which) *which = win;
   return best;
+}
+
+double orc_pt_tri_d2(const double* p, const double* a, const double* b, const double* c,
+                     double* bary) {
+  return pt_tri_d2w(p, a, b, c, bary, NULL);
 }
 
 /* Squared segment-segment distance between [a,b] and [c,e]. The minimum over
@@ -196,8 +210,8 @@ double orc_pt_tri_d2(const double* p, const double* a, const double* b,
  * parallel and it lies inside) or lies on the boundary of the square, i.e. is an
  * endpoint-to-segment distance; candidates in this order, first strict minimum.
  * st = (s, t) with closest points a + s(b-a) and c + t(e-c). */
-double orc_seg_seg_d2(const double* a, const double* b, const double* c,
-                      const double* e, double* st) {
+static double seg_seg_d2w(const double* a, const double* b, const double* c,
+                          const double* e, double* st, int* which) {
   double d1[3], d2[3], r[3];
   sub3(d1, b, a);
   sub3(d2, e, c);
@@ -206,6 +220,7 @@ double orc_seg_seg_d2(const double* a, const double* b, const double* c,
   double Dd = dot3(d1, r), Ee = dot3(d2, r);
   double den = A * C - B * B;
   double best = INFINITY, bs = 0.0, bt = 0.0;
+  int win = -1;
   if (den > 0.0) {
     double s = (B * Ee - C * Dd) / den;
     double t = (A * Ee - B * Dd) / den;
@@ -219,24 +234,31 @@ double orc_seg_seg_d2(const double* a, const double* b, const double* c,
       q[2] = c[2] + t * d2[2];
       sub3(d, p, q);
       best = dot3(d, d);
+      win = 0;
       bs = s;
       bt = t;
     }
   }
   double u, e2;
   e2 = pt_seg_d2(a, c, e, &u);
-  if (e2 < best) { best = e2; bs = 0.0; bt = u; }
+  if (e2 < best) { best = e2; bs = 0.0; bt = u; win = 1; }
   e2 = pt_seg_d2(b, c, e, &u);
-  if (e2 < best) { best = e2; bs = 1.0; bt = u; }
+  if (e2 < best) { best = e2; bs = 1.0; bt = u; win = 2; }
   e2 = pt_seg_d2(c, a, b, &u);
-  if (e2 < best) { best = e2; bs = u; bt = 0.0; }
+  if (e2 < best) { best = e2; bs = u; bt = 0.0; win = 3; }
   e2 = pt_seg_d2(e, a, b, &u);
-  if (e2 < best) { best = e2; bs = u; bt = 1.0; }
+  if (e2 < best) { best = e2; bs = u; bt = 1.0; win = 4; }
   if (st) {
     st[0] = bs;
     st[1] = bt;
   }
+  if (which) *which = win;
   return best;
+}
+
+double orc_seg_seg_d2(const double* a, const double* b, const double* c, const double* e,
+                      double* st) {
+  return seg_seg_d2w(a, b, c, e, st, NULL);
 }
 
 /* ------------------------------------------------------------------ pairs */
@@ -343,10 +365,10 @@ int orc_contact_row(const orc_scene* s, const double* x, uint64_t key, int32_t* 
   }
   const double* xs[4] = {x + 3 * v[0], x + 3 * v[1], x + 3 * v[2], x + 3 * v[3]};
   double om[4], d2, bw[3], st[2];
-  int volume_ok;
+  int volume_ok, which;
   double N[3], side;
   if (key & KEY_EE) {
-    d2 = orc_seg_seg_d2(xs[0], xs[1], xs[2], xs[3], st);
+    d2 = seg_seg_d2w(xs[0], xs[1], xs[2], xs[3], st, &which);
     om[0] = 1.0 - st[0];
     om[1] = st[0];
     om[2] = -(1.0 - st[1]);
@@ -361,7 +383,7 @@ int orc_contact_row(const orc_scene* s, const double* x, uint64_t key, int32_t* 
     sub3(ac, xs[0], xs[2]);
     side = dot3(ac, N) >= 0.0 ? 1.0 : -1.0;
   } else {
-    d2 = orc_pt_tri_d2(xs[0], xs[1], xs[2], xs[3], bw);
+    d2 = pt_tri_d2w(xs[0], xs[1], xs[2], xs[3], bw, &which);
     om[0] = 1.0;
     om[1] = -bw[0];
     om[2] = -bw[1];
@@ -379,6 +401,11 @@ int orc_contact_row(const orc_scene* s, const double* x, uint64_t key, int32_t* 
     sub3(ai, xs[0], xs[1]);
     side = dot3(ai, N) >= 0.0 ? 1.0 : -1.0;
   }
+  /* the reference shape separates the closest points along n, which is their
+   * separating direction only when both closest points are interior (the vertex
+   * over the face, or the common perpendicular of the edges); otherwise the gap
+   * form */
+  if (which != 0) volume_ok = 0;
   double d = sqrt(d2);
   double c = 0.0, Jl[12];
   int kind;
@@ -789,12 +816,14 @@ int64_t orc_search(orc_scene* s, const double* x, double dmax, int brute, uint64
 
 /* Continuous test of one pair along the linear piece q_k(t) = q_k + t dq_k,
  * t in [0,1] (q in the tetrahedron order of the contact row: vertex then
- * triangle, or edge 1 then edge 2). The four points are coplanar where
- * V(t) = det[q1-q0, q2-q0, q3-q0](t) = 0, a cubic a3 t^3 + a2 t^2 + a1 t + a0.
- * Its critical points split [0,1] into monotone pieces; a piece whose end values
- * differ in sign is bisected to its root. At every root and critical point the
- * primitives' distance is evaluated; the pair hits when it is <= eta.
- * Returns 1 on a hit and stores the earliest such t. */
+ * triangle, or edge 1 then edge 2); contact means a distance <= eta. The
+ * primitives' distance is probed at t = 0; then at the times where the four points
+ * are coplanar, V(t) = det[q1-q0, q2-q0, q3-q0](t) = 0, a cubic
+ * a3 t^3 + a2 t^2 + a1 t + a0 whose critical points split [0,1] into monotone
+ * pieces (a piece whose end values differ in sign is bisected to its root), and at
+ * those critical points; a piece with no contact at these times is then swept by
+ * conservative advancement (below), and probed at t = 1. Returns 1 on a contact
+ * and stores its time. */
 static double cubic_at(const double* a, double t) { return ((a[3] * t + a[2]) * t + a[1]) * t + a[0]; }
 
 /* Vertex-vertex: the closest approach of two points moving linearly, at
@@ -824,18 +853,30 @@ static int ccd_hit_vv(const double* q, const double* dq, double eta, double* t_h
   return 0;
 }
 
-static int ccd_probe(const double* q, const double* dq, int ee, double t, double eta2) {
+#define ORC_CA_STEPS 1024
+
+/* squared distance of the two primitives at time t of the piece */
+static double ccd_dist2(const double* q, const double* dq, int ee, double t) {
   double p[4][3];
   for (int k = 0; k < 4; ++k)
     for (int m = 0; m < 3; ++m) p[k][m] = q[3 * k + m] + t * dq[3 * k + m];
-  double d2 = ee ? orc_seg_seg_d2(p[0], p[1], p[2], p[3], NULL)
-                 : orc_pt_tri_d2(p[0], p[1], p[2], p[3], NULL);
-  return d2 <= eta2;
+  return ee ? orc_seg_seg_d2(p[0], p[1], p[2], p[3], NULL)
+            : orc_pt_tri_d2(p[0], p[1], p[2], p[3], NULL);
+}
+
+static int ccd_probe(const double* q, const double* dq, int ee, double t, double eta2) {
+  return ccd_dist2(q, dq, ee, t) <= eta2;
 }
 
 int orc_ccd_hit(const double* q, const double* dq, int kind, double eta, double* t_hit) {
   if (kind == 2) return ccd_hit_vv(q, dq, eta, t_hit);
   const int ee = kind;
+  const double eta2 = eta * eta;
+  /* the start of the piece */
+  if (ccd_probe(q, dq, ee, 0.0, eta2)) {
+    if (t_hit) *t_hit = 0.0;
+    return 1;
+  }
   double e1[3], e2[3], e3[3], f1[3], f2[3], f3[3], c[3], a[4];
   for (int m = 0; m < 3; ++m) {
     e1[m] = q[3 + m] - q[m];
@@ -876,7 +917,6 @@ int orc_ccd_hit(const double* q, const double* dq, int kind, double eta, double*
   for (int i = 0; i < nc; ++i)
     if (crit[i] > 0.0 && crit[i] < 1.0 && crit[i] > knot[nk - 1]) knot[nk++] = crit[i];
   knot[nk++] = 1.0;
-  const double eta2 = eta * eta;
   for (int i = 0; i + 1 < nk; ++i) {
     double lo = knot[i], hi = knot[i + 1];
     double vlo = cubic_at(a, lo), vhi = cubic_at(a, hi);
@@ -908,8 +948,46 @@ int orc_ccd_hit(const double* q, const double* dq, int kind, double eta, double*
       return 1;
     }
   }
+  /* Clearance by conservative advancement (Mirtich's method): the distance of the
+   * two primitives changes with t at most at rate Lc = max |dq| over the first
+   * primitive's points + max |dq| over the second's, so from a time t with distance
+   * d > eta no contact occurs before t + (d - eta) / Lc. This also covers a piece
+   * that stays coplanar (V(t) = 0 throughout), which the cubic does not see. A
+   * piece not cleared within ORC_CA_STEPS advances counts as a contact. */
+  double l1 = 0.0, l2 = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    const double mk = sqrt(dot3(dq + 3 * k, dq + 3 * k));
+    if (k < (ee ? 2 : 1)) {
+      if (mk > l1) l1 = mk;
+    } else if (mk > l2) {
+      l2 = mk;
+    }
+  }
+  const double lc = l1 + l2;
+  double t = 0.0;
+  int cleared = !(lc > 0.0);
+  for (int step = 0; step < ORC_CA_STEPS && !cleared; ++step) {
+    const double d = sqrt(ccd_dist2(q, dq, ee, t));
+    if (d <= eta) {
+      if (t_hit) *t_hit = t;
+      return 1;
+    }
+    t = t + (d - eta) / lc;
+    if (t >= 1.0) cleared = 1;
+  }
+  if (!cleared) {
+    if (t_hit) *t_hit = t;
+    return 1;
+  }
+  /* the end of the piece (the advancement leaves a distance of at least eta there) */
+  if (ccd_probe(q, dq, ee, 1.0, eta2)) {
+    if (t_hit) *t_hit = 1.0;
+    return 1;
+  }
   return 0;
 }
+
+
 
 /* ------------------------------------------------------------- colouring */
 
@@ -1075,6 +1153,8 @@ orc_scene* orc_create(int32_t n, const double* w, const int32_t* tris, int32_t n
   s->xt = (double*)malloc(N * 3 * sizeof(double));
   s->xold = (double*)malloc(N * 3 * sizeof(double));
   s->r = (double*)malloc(N * sizeof(double));
+  s->rold = (double*)malloc(N * sizeof(double));
+  s->back = (uint8_t*)malloc(N);
   s->Di = (double*)malloc(N * sizeof(double));
   s->move2 = (double*)malloc(N * sizeof(double));
   s->er_e = (int32_t*)malloc((size_t)(ne > 0 ? ne : 1) * sizeof(int32_t));
@@ -1093,7 +1173,8 @@ int32_t orc_particles(const orc_scene* s, int32_t* ids) {
 void orc_destroy(orc_scene* s) {
   if (!s) return;
   free(s->w); free(s->tris); free(s->edges); free(s->part); free(s->stat);
-  free(s->x); free(s->y); free(s->xt); free(s->xold); free(s->r);
+  free(s->x); free(s->y); free(s->xt); free(s->xold); free(s->r); free(s->rold);
+  free(s->back);
   free(s->Di); free(s->move2); free(s->P); free(s->A); free(s->acol);
   free(s->er_e); free(s->er_v); free(s->er_g); free(s->er_inv); free(s->er_col);
   free(s);
@@ -1173,17 +1254,9 @@ static uint64_t fp_key(uint64_t k) { return orc_mix64(k ^ 0x6A09E667F3BCC909ull)
  * (contacts of A, then the edge-length rows; no colouring) is evaluated from the
  * same y: w = c0 + J.(y - x) (contacts) or sigma - g.(y_i - y_j) (edges),
  * lambda' = max(0, lambda - w/A), dl = lambda' - lambda, and the update w_v dl J_v of
- * each of its free vertices is added to that vertex's sum; then y_v += omega * sum_v.
- * Each update is rounded to an integer multiple of 2^-56 m before it is summed, so
- * the sum is exact and does not depend on the order of the rows. gs_sweeps such
- * iterations run per backward step, lambda carried between them. */
-#define JAC_SCALE 72057594037927936.0 /* 2^56: sums of up to 2^7 m, steps of 2^-56 m */
-static int jac_add(int64_t* acc, double v) {
-  if (!(fabs(v) < 64.0)) return -1;
-  *acc += llrint(v * JAC_SCALE);
-  return 0;
-}
-
+ * each of its free vertices is added, in binary64 and in row order, to that
+ * vertex's sum; then y_v += omega * sum_v. gs_sweeps such iterations run per
+ * backward step, lambda carried between them. */
 static int backward_jacobi(orc_scene* s, int64_t na, orc_iter* it) {
   const orc_params* p = &s->p;
   const int64_t NA = na > 0 ? na : 1;
@@ -1193,8 +1266,7 @@ static int backward_jacobi(orc_scene* s, int64_t na, orc_iter* it) {
   double* rinv = (double*)malloc((size_t)NA * sizeof(double));
   double* lam = (double*)calloc((size_t)NA, sizeof(double));
   double* elam = (double*)calloc((size_t)(s->n_er > 0 ? s->n_er : 1), sizeof(double));
-  int64_t* acc = (int64_t*)calloc((size_t)(s->n > 0 ? s->n : 1) * 3, sizeof(int64_t));
-  int bad = 0;
+  double* acc = (double*)calloc((size_t)(s->n > 0 ? s->n : 1) * 3, sizeof(double));
   for (int64_t q = 0; q < na; ++q)
     orc_contact_row(s, s->x, s->A[q], rv + 4 * q, rc0 + q, rJ + 12 * q, rinv + q);
   it->n_colors = 0;
@@ -1219,7 +1291,7 @@ static int backward_jacobi(orc_scene* s, int64_t na, orc_iter* it) {
         const int32_t vv = rv[4 * q + k];
         if (vv < 0 || !(s->w[vv] > 0.0)) continue;
         double co = s->w[vv] * dl;
-        for (int m = 0; m < 3; ++m) bad |= jac_add(acc + 3 * vv + m, co * J[3 * k + m]);
+        for (int m = 0; m < 3; ++m) acc[3 * vv + m] = acc[3 * vv + m] + co * J[3 * k + m];
       }
     }
     for (int32_t q = 0; q < s->n_er; ++q) {
@@ -1234,20 +1306,20 @@ static int backward_jacobi(orc_scene* s, int64_t na, orc_iter* it) {
       elam[q] = ln;
       if (s->w[i] > 0.0) {
         double co = s->w[i] * dl;
-        for (int m = 0; m < 3; ++m) bad |= jac_add(acc + 3 * i + m, -(co * g[m]));
+        for (int m = 0; m < 3; ++m) acc[3 * i + m] = acc[3 * i + m] - co * g[m];
       }
       if (s->w[j] > 0.0) {
         double co = s->w[j] * dl;
-        for (int m = 0; m < 3; ++m) bad |= jac_add(acc + 3 * j + m, co * g[m]);
+        for (int m = 0; m < 3; ++m) acc[3 * j + m] = acc[3 * j + m] + co * g[m];
       }
     }
     for (int64_t c = 0; c < 3 * (int64_t)s->n; ++c) {
-      s->y[c] = s->y[c] + p->omega * ((double)acc[c] * (1.0 / JAC_SCALE));
-      acc[c] = 0;
+      s->y[c] = s->y[c] + p->omega * acc[c];
+      acc[c] = 0.0;
     }
   }
   free(rv); free(rc0); free(rJ); free(rinv); free(lam); free(elam); free(acc);
-  return bad ? -3 : 0;
+  return 0;
 }
 
 int orc_iterate(orc_scene* s, orc_iter* info) {
@@ -1362,8 +1434,9 @@ int orc_iterate(orc_scene* s, orc_iter* info) {
 
   /* forward (Sec. 5, Eq. eq:forward2) */
   const double hg = 0.5 * p->gamma;
-  double mmax = 0.0, rinf = 0.0;
+  double mmax = 0.0;
   memcpy(s->xold, s->x, (size_t)s->n * 3 * sizeof(double));
+  memcpy(s->rold, s->r, (size_t)s->n * sizeof(double));
   for (int32_t i = 0; i < s->n; ++i) {
     double* xi = s->x + 3 * i;
     const double* yi = s->y + 3 * i;
@@ -1388,6 +1461,18 @@ int orc_iterate(orc_scene* s, orc_iter* info) {
     double mv[3];
     sub3(mv, xn, xi);
     double m2 = dot3(mv, mv);
+    /* the lemma of Sec. 5 for the rounded move: the vertex advances only when
+     * 2 |x_new - x| < D_i - eta, eta = ORC_ETA covering the rounding of the
+     * distances; otherwise it stays (alpha = 0). In exact arithmetic with
+     * gamma < 1 the test fails only when D_i <= eta / (1 - gamma). */
+    const double sb = s->Di[i] - ORC_ETA;
+    if (!p->unguarded && !(sb > 0.0 && 4.0 * m2 < sb * sb)) {
+      xn[0] = xi[0];
+      xn[1] = xi[1];
+      xn[2] = xi[2];
+      m2 = 0.0;
+      alpha = 0.0;
+    }
     s->move2[i] = m2;
     double mvn = sqrt(m2);
     if (mvn > mmax) mmax = mvn;
@@ -1395,21 +1480,29 @@ int orc_iterate(orc_scene* s, orc_iter* info) {
     xi[1] = xn[1];
     xi[2] = xn[2];
     s->r[i] = s->r[i] * (1.0 - alpha);
-    if (s->r[i] > rinf) rinf = s->r[i];
   }
 
-  /* path certificate on P' along x^(l) -> x^(l+1): the piece is safe for a pair
-   * when no vertex of it moved half the pair distance (lemma of Sec. 5) */
-  int64_t fail = 0, hits = 0;
-  for (int64_t q = 0; q < npf; ++q) {
-    int32_t v[4];
-    pair_verts(s, s->P[q], v);
-    const int nv = (s->P[q] & KEY_VV) ? 2 : 4;
-    double mv = s->move2[v[0]];
-    for (int k = 1; k < nv; ++k)
-      if (s->move2[v[k]] > mv) mv = s->move2[v[k]];
-    if (p->ccd_all || !(4.0 * mv < dpf[q])) {
-      /* not certified by the motion bound: continuous test of the piece */
+  /* path certificate on P' along x^(l) -> x^(l+1) (Sec. 5 and Sec. 5.1). A pair
+   * is certified when no vertex of it moved half the pair distance (the lemma:
+   * 4 max_v |dx_v|^2 < d^2); the others take the continuous test of the piece.
+   * A pair the test does not clear sends its vertices back to x^(l) (alpha = 0,
+   * r unchanged). That changes the piece of every pair sharing those vertices, so
+   * the pass repeats until it returns no new vertex (the returned set only grows).
+   * With ccd_all every pair takes the continuous test in every pass; a pair the
+   * motion bound certifies is never sent back. */
+  int64_t fail = 0, hits = 0, nback = 0;
+  memset(s->back, 0, (size_t)s->n);
+  for (;;) {
+    int64_t newly = 0;
+    for (int64_t q = 0; q < npf; ++q) {
+      int32_t v[4];
+      pair_verts(s, s->P[q], v);
+      const int nv = (s->P[q] & KEY_VV) ? 2 : 4;
+      double mv = s->move2[v[0]];
+      for (int k = 1; k < nv; ++k)
+        if (s->move2[v[k]] > mv) mv = s->move2[v[k]];
+      const int bound_ok = 4.0 * mv < dpf[q];
+      if (bound_ok && !p->ccd_all) continue;
       ++fail;
       double qq[12], dq[12];
       for (int k = 0; k < nv; ++k)
@@ -1418,11 +1511,31 @@ int orc_iterate(orc_scene* s, orc_iter* info) {
           dq[3 * k + m] = s->x[3 * v[k] + m] - s->xold[3 * v[k] + m];
         }
       const int kind = (s->P[q] & KEY_VV) ? 2 : ((s->P[q] & KEY_EE) ? 1 : 0);
-      if (orc_ccd_hit(qq, dq, kind, ORC_CCD_ETA, NULL)) ++hits;
+      if (!orc_ccd_hit(qq, dq, kind, ORC_ETA, NULL)) continue;
+      ++hits;
+      if (bound_ok) continue;
+      for (int k = 0; k < nv; ++k)
+        if (!s->back[v[k]]) {
+          s->back[v[k]] = 2;
+          ++newly;
+        }
+    }
+    if (newly == 0) break;
+    nback += newly;
+    for (int32_t i = 0; i < s->n; ++i) {
+      if (s->back[i] != 2) continue;
+      s->back[i] = 1;
+      memcpy(s->x + 3 * i, s->xold + 3 * i, 3 * sizeof(double));
+      s->r[i] = s->rold[i];
+      s->move2[i] = 0.0;
     }
   }
   it.ccd_fail = fail;
   it.ccd_hits = hits;
+  it.n_back = nback;
+  double rinf = 0.0;
+  for (int32_t i = 0; i < s->n; ++i)
+    if (s->r[i] > rinf) rinf = s->r[i];
 
   s->D = D - 2.0 * mmax;
   it.d_after = s->D;

@@ -43,6 +43,9 @@ typedef struct orc_params {
                         1: projected Jacobi (Sec. 4.3.2) */
   int32_t ccd_all;   /* 1: every pair of P' takes the continuous test, not only those the
                         motion bound leaves uncertified (a check of the lemma of Sec. 5) */
+  int32_t unguarded; /* 1: the forward step exactly as Eq. eq:forward2, without the
+                        check of the rounded move; the certificate is then the only
+                        guard (a test of the certificate's response) */
 } orc_params;
 
 typedef struct orc_iter {
@@ -51,8 +54,11 @@ typedef struct orc_iter {
   int64_t n_p;           /* |P| evaluated by the pair pass */
   int64_t n_pf;          /* |P'| = pairs with d < D^(l) */
   int64_t n_a;           /* |A| = pairs with d < delta */
-  int64_t ccd_fail;      /* pairs in P' whose motion bound did not certify the piece */
-  int64_t ccd_hits;      /* of those, pairs the continuous test finds in contact */
+  int64_t ccd_fail;      /* pairs of P' that took the continuous test: those the motion
+                            bound does not certify, or all with ccd_all (summed over
+                            the certificate's passes) */
+  int64_t ccd_hits;      /* pairs the continuous test does not clear (all passes) */
+  int64_t n_back;        /* vertices the certificate returned to x^(l) */
   double d_before;       /* D^(l) used by the pair pass */
   double d_after;        /* D^(l+1) */
   double move_max;       /* max_i ||x_i^(l+1) - x_i^(l)|| */

@@ -132,3 +132,141 @@ def mesh_self_intersects(x, tris, edges):
         if seg_seg_d2(*(x[i] for i in (*edges[e], *edges[g]))) == 0:
             return True
     return False
+
+
+# ------------------------------------------------------------------ fast exact test
+#
+# The same exact predicate as mesh_self_intersects, for meshes of thousands of
+# elements: candidate pairs come from axis-aligned boxes on a uniform grid, each
+# orientation is evaluated in binary64 together with a bound on its rounding error,
+# and only pairs whose signs the bound leaves undecided are evaluated in Fractions.
+
+def _orient_fp(a, b, c, d):
+    """det[b-a, c-a, d-a] in binary64 and a bound on its rounding error (vectorised)."""
+    import numpy as np
+    u, v, w = b - a, c - a, d - a
+    det = (u[:, 0] * (v[:, 1] * w[:, 2] - v[:, 2] * w[:, 1])
+           + u[:, 1] * (v[:, 2] * w[:, 0] - v[:, 0] * w[:, 2])
+           + u[:, 2] * (v[:, 0] * w[:, 1] - v[:, 1] * w[:, 0]))
+    perm = (np.abs(u[:, 0]) * (np.abs(v[:, 1] * w[:, 2]) + np.abs(v[:, 2] * w[:, 1]))
+            + np.abs(u[:, 1]) * (np.abs(v[:, 2] * w[:, 0]) + np.abs(v[:, 0] * w[:, 2]))
+            + np.abs(u[:, 2]) * (np.abs(v[:, 0] * w[:, 1]) + np.abs(v[:, 1] * w[:, 0])))
+    # the differences b-a etc. are rounded too: bound the error by the magnitudes of
+    # the inputs as well (a generous multiple of the unit roundoff)
+    mag = np.maximum.reduce([np.abs(a).max(1), np.abs(b).max(1), np.abs(c).max(1),
+                             np.abs(d).max(1)])
+    err = 1e-14 * perm + 1e-14 * mag * (np.abs(u).max(1) + np.abs(v).max(1) +
+                                        np.abs(w).max(1)) ** 2
+    return det, err
+
+
+def _box_pairs(lo1, hi1, lo2, hi2, margin):
+    """Index pairs (i, j) whose boxes [lo1[i]-m, hi1[i]+m] and [lo2[j], hi2[j]] overlap."""
+    import numpy as np
+    if len(lo1) == 0 or len(lo2) == 0:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64)
+    lo1 = lo1 - margin
+    hi1 = hi1 + margin
+    ext = max(float((hi1 - lo1).max()), float((hi2 - lo2).max()), 1e-12)
+    h = ext
+    org = np.minimum(lo1.min(0), lo2.min(0))
+    dim = np.floor((np.maximum(hi1.max(0), hi2.max(0)) - org) / h).astype(np.int64) + 1
+
+    def cells(lo, hi):
+        c0 = np.floor((lo - org) / h).astype(np.int64)
+        c1 = np.floor((hi - org) / h).astype(np.int64)
+        ids, own = [], []
+        for dx in (0, 1):
+            for dy in (0, 1):
+                for dz in (0, 1):
+                    c = c0 + np.array([dx, dy, dz])
+                    ok = (c <= c1).all(1)
+                    cid = (c[:, 0] * dim[1] + c[:, 1]) * dim[2] + c[:, 2]
+                    ids.append(cid[ok])
+                    own.append(np.nonzero(ok)[0])
+        return np.concatenate(ids), np.concatenate(own)
+
+    c2, o2 = cells(lo2, hi2)
+    order = np.argsort(c2, kind="stable")
+    c2, o2 = c2[order], o2[order]
+    c1, o1 = cells(lo1, hi1)
+    start = np.searchsorted(c2, c1, "left")
+    stop = np.searchsorted(c2, c1, "right")
+    cnt = stop - start
+    ii = np.repeat(o1, cnt)
+    base = np.repeat(start - np.cumsum(cnt) + cnt, cnt)
+    jj = o2[base + np.arange(cnt.sum())]
+    key = np.unique(ii * len(lo2) + jj)
+    ii, jj = key // len(lo2), key % len(lo2)
+    ok = ((lo1[ii] <= hi2[jj]) & (lo2[jj] <= hi1[ii])).all(1)
+    return ii[ok], jj[ok]
+
+
+def touching_pairs(x, tris, edges, margin=1e-9):
+    """Exact edge-triangle touches (closed edge and closed triangle sharing no vertex)
+    and, for edges in no triangle, exact edge-edge touches. Returns two lists of
+    index pairs (edge, triangle) and (edge, edge). Same predicate as
+    mesh_self_intersects."""
+    import numpy as np
+    x = np.asarray(x, np.float64)
+    tris = np.asarray(tris, np.int64).reshape(-1, 3)
+    edges = np.asarray(edges, np.int64).reshape(-1, 2)
+    et = []
+    if len(tris) and len(edges):
+        P, Q = x[edges[:, 0]], x[edges[:, 1]]
+        A, B, C = x[tris[:, 0]], x[tris[:, 1]], x[tris[:, 2]]
+        ie, it = _box_pairs(np.minimum(P, Q), np.maximum(P, Q),
+                            np.minimum(np.minimum(A, B), C), np.maximum(np.maximum(A, B), C),
+                            margin)
+        share = np.zeros(len(ie), bool)
+        for k in range(2):
+            for m in range(3):
+                share |= edges[ie, k] == tris[it, m]
+        ie, it = ie[~share], it[~share]
+        p, q, a, b, c = P[ie], Q[ie], A[it], B[it], C[it]
+        sp, ep = _orient_fp(a, b, c, p)
+        sq, eq = _orient_fp(a, b, c, q)
+        sure_p, sure_q = np.abs(sp) > ep, np.abs(sq) > eq
+        apart = sure_p & sure_q & (np.sign(sp) == np.sign(sq))
+        o = [_orient_fp(p, q, a, b), _orient_fp(p, q, b, c), _orient_fp(p, q, c, a)]
+        sure_o = np.all([np.abs(d) > e for d, e in o], axis=0)
+        sg = np.stack([np.sign(d) for d, _ in o], 1)
+        mixed = sure_o & (sg.max(1) > 0) & (sg.min(1) < 0)
+        crossing = sure_p & sure_q & (np.sign(sp) != np.sign(sq)) & sure_o & ~mixed
+        undecided = ~(apart | mixed | crossing)
+        for k in np.nonzero(crossing)[0]:
+            et.append((int(ie[k]), int(it[k])))
+        for k in np.nonzero(undecided)[0]:
+            e, t = edges[ie[k]], tris[it[k]]
+            if seg_tri_intersect(x[e[0]], x[e[1]], x[t[0]], x[t[1]], x[t[2]]):
+                et.append((int(ie[k]), int(it[k])))
+    ee = []
+    if len(edges):
+        in_tri = np.zeros(len(x), bool)
+        if len(tris):
+            in_tri[tris.ravel()] = True
+        poly = np.nonzero(~(in_tri[edges[:, 0]] & in_tri[edges[:, 1]]))[0]
+        if len(poly) > 1:
+            pe = edges[poly]
+            P, Q = x[pe[:, 0]], x[pe[:, 1]]
+            lo, hi = np.minimum(P, Q), np.maximum(P, Q)
+            i1, i2 = _box_pairs(lo, hi, lo, hi, margin)
+            ok = i1 < i2
+            i1, i2 = i1[ok], i2[ok]
+            share = np.zeros(len(i1), bool)
+            for k in range(2):
+                for m in range(2):
+                    share |= pe[i1, k] == pe[i2, m]
+            i1, i2 = i1[~share], i2[~share]
+            for k in range(len(i1)):
+                e, g = pe[i1[k]], pe[i2[k]]
+                # a binary64 distance clearly above the rounding level cannot be 0
+                d1, d2, r = x[e[1]] - x[e[0]], x[g[1]] - x[g[0]], x[e[0]] - x[g[0]]
+                if np.linalg.norm(np.cross(d1, d2)) > 1e-12 * np.linalg.norm(d1) * \
+                        np.linalg.norm(d2):
+                    n = np.cross(d1, d2)
+                    if abs(np.dot(r, n)) / np.linalg.norm(n) > 1e-9:
+                        continue
+                if seg_seg_d2(x[e[0]], x[e[1]], x[g[0]], x[g[1]]) == 0:
+                    ee.append((int(poly[i1[k]]), int(poly[i2[k]])))
+    return et, ee

@@ -1,8 +1,10 @@
 """Pins of the FP64 oracle against facts that do not come from the oracle itself:
 exact rational minimisation, closed forms derived from the constraint
-definitions (Sec. 4.1, Sec. 4.2), the greedy-order characterisation of
-Jones-Plassmann colouring, brute-force sets, and the safety lemma of Sec. 5
-checked in exact arithmetic."""
+definitions (Sec. 4.1, Sec. 4.2), finite differences of exact distances, worked
+cases and invariants of the randomised palette colouring (proper, a function of
+the row set), brute-force sets, sampled minimum distances along a piece, the
+safety lemma of Sec. 5 checked in exact arithmetic, and exact intersection tests
+of whole steps' final states."""
 from fractions import Fraction as Fr
 import math
 
@@ -111,13 +113,15 @@ def _ref_volume_ratio(xs_ref):
 
 
 def test_vt_volume_constraint_closed_form_and_gradient():
+    # the volume form (Sec. 4.1, Fig. fig:vt) for a vertex over the face: its closest
+    # point is the interior projection, the separating direction is the normal
     rng = np.random.default_rng(3)
     s = _scene(4, tris=[(1, 2, 3)], delta=DELTA)
     checked = 0
     for trial in range(200):
         tri = rng.normal(size=(3, 3)) * 0.01
         n = np.cross(tri[1] - tri[0], tri[2] - tri[0]); n /= np.linalg.norm(n)
-        bc = rng.dirichlet([1, 1, 1]) * (1.3 if trial % 3 == 0 else 1.0) - (0.1 if trial % 3 == 0 else 0)
+        bc = rng.dirichlet([2, 2, 2]) * 0.9 + 0.1 / 3
         p = bc @ tri + n * rng.uniform(-1, 1) * 0.8e-3
         x = np.vstack([p, tri])
         d = math.sqrt(exact.pt_tri_d2(p, *tri))
@@ -139,6 +143,60 @@ def test_vt_volume_constraint_closed_form_and_gradient():
         assert np.dot(row["J"][0], side * n) > 0
         # A = sum_v w_v |J_v|^2 with unit masses
         assert rel_close(1 / row["inv_a"], (row["J"] ** 2).sum(), rtol=1e-12)
+        checked += 1
+    assert checked > 100
+
+
+def _exact_dist(kind, xs):
+    """Exact rational distance of a vertex-triangle (0) or edge-edge (1) pair, as a float."""
+    d2 = exact.pt_tri_d2(*xs) if kind == 0 else exact.seg_seg_d2(*xs)
+    return math.sqrt(float(d2))
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_gap_form_when_the_closest_point_is_on_the_boundary(kind):
+    # a vertex beside the face (closest point on an edge or a corner) or edges whose
+    # closest points include an endpoint: the separating direction is not the normal,
+    # and the row is the gap constraint c = d/delta - 1 (Sec. 4.1 names it), whose
+    # Jacobian is the gradient of the distance over delta: finite differences of the
+    # exact rational distance pin it independently
+    rng = np.random.default_rng(11 + kind)
+    s = _scene(4, tris=[(1, 2, 3)], edges=[(0, 1), (2, 3)], delta=DELTA)
+    checked = 0
+    for trial in range(300):
+        if kind == 0:
+            tri = rng.normal(size=(3, 3)) * 0.01
+            n = np.cross(tri[1] - tri[0], tri[2] - tri[0]); n /= np.linalg.norm(n)
+            e = rng.integers(3)
+            a, b = tri[e], tri[(e + 1) % 3]
+            c = tri[(e + 2) % 3]
+            t = rng.uniform(-0.2, 1.2)
+            q = a + t * (b - a)
+            # outward in the plane, away from the third corner, plus a normal offset
+            m = (q - c) - np.dot(q - c, b - a) / np.dot(b - a, b - a) * (b - a)
+            m /= np.linalg.norm(m)
+            p = q + m * rng.uniform(0.1, 0.7) * 1e-3 + n * rng.uniform(-0.5, 0.5) * 1e-3
+            x = np.vstack([p, tri])
+            key = oracle.vt_key(0, 0)
+        else:
+            a = rng.normal(size=3) * 0.01
+            d1 = rng.normal(size=3) * 0.01
+            d2 = rng.normal(size=3) * 0.01
+            u = rng.normal(size=3); u /= np.linalg.norm(u)
+            # the end of edge 1 near an interior point of edge 2
+            c = a + d1 + u * rng.uniform(0.1, 0.9) * 1e-3 - rng.uniform(0.2, 0.8) * d2
+            x = np.vstack([a, a + d1, c, c + d2])
+            key = oracle.ee_key(0, 1)
+        d = _exact_dist(kind, x)
+        if not d < DELTA:
+            continue
+        row = s.contact_row(x, key)
+        if row["kind"] == 0:
+            continue  # the closest points happen to be interior
+        assert row["kind"] == 1
+        assert rel_close(row["c0"], d / DELTA - 1, rtol=1e-9, atol=1e-12)
+        fd = _fd_grad(lambda ys: _exact_dist(kind, ys) / DELTA, x, [0, 1, 2, 3], h=1e-8)
+        assert np.allclose(row["J"], fd, rtol=1e-4, atol=1e-5 * np.abs(fd).max())
         checked += 1
     assert checked > 100
 
@@ -556,12 +614,11 @@ def test_ccd_contact_at_the_end_of_the_piece():
 
 # ---------------------------------------------------------------- projected Jacobi
 # (Sec. 4.3.2: one projected Jacobi iteration in place of the Gauss-Seidel sweep,
-# with an under-relaxation factor omega; the per-vertex sums are taken on a fixed
-# 2^-56 m grid, which makes them exact and independent of the order of the rows)
+# with an under-relaxation factor omega; the per-vertex sums are plain binary64 sums
+# in row order)
 
 def test_jacobi_single_row_settles_at_delta():
-    # one contact row: Jacobi with omega = 1 is the same projection, up to the
-    # 2^-56 m rounding of the update
+    # one contact row: Jacobi with omega = 1 is the same projection
     x = np.array([[0.2, 0.2, 0.005], [0, 0, 0], [1, 0, 0], [0, 1, 0]], float)
     xt = x.copy()
     xt[0, 2] = -0.005
@@ -594,8 +651,9 @@ def test_jacobi_opposite_rows_cancel_exactly():
     assert gs.state()[1][0, 2] != 0.0  # the sequential sweep is not symmetric
 
 
-def test_jacobi_result_does_not_depend_on_row_order():
-    # the same step with the pair list handed over in two different orders
+def test_jacobi_result_depends_on_row_order_only_by_rounding():
+    # the same step with the pair list handed over in two different orders: every row
+    # reads the same y, so the orders differ only in the rounding of the sums
     x, xt, tris, edges = _two_patches()
     w = np.ones(len(x))
     outs = []
@@ -610,7 +668,7 @@ def test_jacobi_result_does_not_depend_on_row_order():
             s.iterate()
         outs.append(s.state())
     for a, b in zip(outs[0], outs[1]):
-        assert np.array_equal(np.asarray(a), np.asarray(b))
+        assert np.allclose(np.asarray(a), np.asarray(b), rtol=0, atol=1e-15)
 
 
 @pytest.mark.parametrize("omega", [0.5, 1.0])
@@ -868,3 +926,152 @@ def test_normal_flow_sphere_normals_and_mean_curvature():
 def test_normal_flow_rejects_bad_index():
     with pytest.raises(ValueError):
         oracle.normal_flow(np.zeros((3, 3)), [[0, 1, 3]], 0.1, 0.1, 1)
+
+
+# ------------------------------------------------------ continuous test: ends, coplanar
+
+def test_ccd_contact_within_eta_at_either_end_of_the_piece():
+    # a vertex 0.5 pm above the face at t = 0 (below eta = 1 pm), moving away: a
+    # contact at t = 0; the mirrored motion arriving 0.5 pm above the face at t = 1
+    # reaches eta just before the end of the piece; V(t) keeps its sign on both
+    tri = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], float) * 0.01
+    q = np.vstack([[0.003, 0.003, 5e-13], tri])
+    dq = np.zeros((4, 3))
+    dq[0] = [0.0, 0.0, 1e-3]
+    hit, t = oracle.ccd_hit(q, dq, ee=False)
+    assert hit and t == 0.0
+    q2 = np.vstack([[0.003, 0.003, 1e-3 + 5e-13], tri])
+    dq[0] = [0.0, 0.0, -1e-3]
+    hit, t = oracle.ccd_hit(q2, dq, ee=False)
+    assert hit and 1.0 - 1e-9 < t <= 1.0
+    # 2 pm instead: no contact on either piece
+    q[0, 2] = 2e-12
+    dq[0] = [0.0, 0.0, 1e-3]
+    assert not oracle.ccd_hit(q, dq, ee=False)[0]
+
+
+def test_ccd_coplanar_pieces():
+    # the four points stay in one plane (V(t) = 0 for every t), so the coplanarity
+    # cubic carries no information: a vertex sliding in the face's plane across an
+    # edge into the face, and an edge sliding in the plane of another across it, are
+    # contacts; the same slides stopping 0.1 mm short are not
+    tri = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], float) * 0.01
+    q = np.vstack([[0.003, -0.002, 0.0], tri])
+    dq = np.zeros((4, 3))
+    dq[0] = [0.0, 0.004, 0.0]
+    hit, t = oracle.ccd_hit(q, dq, ee=False)
+    assert hit and abs(t - 0.5) < 1e-6
+    dq[0] = [0.0, 0.0019, 0.0]
+    assert not oracle.ccd_hit(q, dq, ee=False)[0]
+    e = np.array([[-0.005, 0.0, 0.0], [0.005, 0.0, 0.0], [0.0, -0.005, 0.0], [0.0, -0.003, 0.0]])
+    dq = np.zeros((4, 3))
+    dq[2] = dq[3] = [0.0, 0.006, 0.0]
+    hit, t = oracle.ccd_hit(e, dq, ee=True)
+    assert hit and abs(t - 0.5) < 1e-6
+    dq[2] = dq[3] = [0.0, 0.0029, 0.0]
+    assert not oracle.ccd_hit(e, dq, ee=True)[0]
+
+
+def test_ccd_clearance_matches_sampled_minimum_distance():
+    # random short pieces of random vertex-triangle and edge-edge pairs: a piece is
+    # cleared exactly when the distance stays above eta; the minimum over a fine
+    # sampling of t (an upper bound of the true minimum) must exceed eta on cleared
+    # pieces, and pieces whose sampled minimum is far below eta must hit
+    rng = np.random.default_rng(21)
+    for trial in range(300):
+        ee = bool(trial % 2)
+        q = rng.normal(size=(4, 3)) * 0.003
+        dq = rng.normal(size=(4, 3)) * 0.003
+        hit, t = oracle.ccd_hit(q, dq, ee=ee)
+        ts = np.linspace(0, 1, 2001)
+        f = oracle.seg_seg_d2 if ee else oracle.pt_tri_d2
+        d = np.array([f(*(q + t_ * dq))[0] for t_ in ts]) ** 0.5
+        if d.min() < 1e-13:
+            assert hit
+        if not hit:
+            assert d.min() > 1e-12
+
+
+# ------------------------------------------------------ whole steps: safety in FP64
+
+def _run_checked(sc, **over):
+    p = dict(sc["params"])
+    p.update(over)
+    s = oracle.Scene(sc["w"], sc["tris"], sc["edges"], **p)
+    out, n, tr = s.run(sc["x"], sc["xt"], trace_cap=p.get("max_iters", 512))
+    return s, out, n, tr
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4, 6])
+def test_small_configs_run_to_their_end_intersection_free(cfg):
+    # the whole step, to the stop test or L, on the small variant of each workload:
+    # no pair of P' is left uncertified by the motion bound in any iteration (the
+    # lemma of Sec. 5 holds for the rounded positions), nothing is sent back, and the
+    # final state is free in exact arithmetic with no pair within eta
+    sc = scenes.config(cfg, small=True)
+    s, out, n, tr = _run_checked(sc)
+    assert all(t["ccd_fail"] == 0 and t["ccd_hits"] == 0 and t["n_back"] == 0 for t in tr)
+    et, ee = exact.touching_pairs(out, sc["tris"], sc["edges"])
+    assert et == [] and ee == []
+    assert len(s.search(out, 1e-12)) == 0
+
+
+def test_mid_size_cube_scene_runs_to_its_end_intersection_free():
+    # 4 cubes of 8^3 cells: the scene whose former output met itself
+    sc = scenes.stacked_cubes(4, 8)
+    s, out, n, tr = _run_checked(sc)
+    assert all(t["ccd_fail"] == 0 and t["n_back"] == 0 for t in tr)
+    et, ee = exact.touching_pairs(out, sc["tris"], sc["edges"])
+    assert et == [] and ee == []
+
+
+def test_lemma_holds_exactly_near_contact_on_the_crumpling_cloth():
+    # cloth over the sphere (small): over the first 150 iterations, every pair whose
+    # distance fell below D^(l) satisfies the lemma of Sec. 5 in exact rational
+    # arithmetic for the rounded positions; this window covers pairs driven from
+    # millimetres down to the 1e-11 m scale where the forward step's check of the
+    # rounded move freezes their vertices
+    sc = scenes.config(1, small=True)
+    p = dict(sc["params"])
+    p["max_iters"] = 150
+    s = oracle.Scene(sc["w"], sc["tris"], sc["edges"], **p)
+    s.begin(sc["x"], sc["xt"])
+    tris, edges = sc["tris"], sc["edges"]
+    smallest = 1.0
+    for l in range(p["max_iters"]):
+        X0 = s.state()[0]
+        stop, it = s.iterate()
+        X1 = s.state()[0]
+        m = np.linalg.norm(X1 - X0, axis=1)
+        for k in s.P():
+            k = int(k)
+            a, b = (k >> 32) & 0x3FFFFFFF, k & 0xFFFFFFFF
+            if k & oracle.KEY_EE:
+                v = [*edges[a], *edges[b]]
+                d = oracle.seg_seg_d2(*X0[v])[0] ** 0.5
+            else:
+                v = [a, *tris[b]]
+                d = oracle.pt_tri_d2(*X0[v])[0] ** 0.5
+            smallest = min(smallest, d)
+            mm = max(m[i] for i in v)
+            if d > 1e-6 and 2.0 * mm < 0.999 * d:
+                continue  # far from the rounding level: the binary64 check is decisive
+            v, d2 = _pair_exact(k, X0, tris, edges)
+            m2 = max(sum((Fr(float(X1[i, c])) - Fr(float(X0[i, c]))) ** 2 for c in range(3))
+                     for i in v)
+            assert 4 * m2 < d2, (l, hex(k))
+        if stop:
+            break
+    assert smallest < 1e-9  # the window reaches the near-contact regime
+
+
+def test_unguarded_forward_step_is_caught_by_the_certificate():
+    # the forward step exactly as Eq. eq:forward2, without the check of the rounded
+    # move: on the crumpling cloth some rounded moves break the lemma; the certificate
+    # finds those pieces, sends their vertices back to x^(l), and the output is still
+    # free in exact arithmetic
+    sc = scenes.config(1, small=True)
+    s, out, n, tr = _run_checked(sc, max_iters=600, unguarded=1)
+    assert sum(t["n_back"] for t in tr) > 0
+    et, ee = exact.touching_pairs(out, sc["tris"], sc["edges"])
+    assert et == [] and ee == []
