@@ -152,7 +152,7 @@ def main():
     ap.add_argument("--max-iters", type=int, default=0,
                     help="override the workload's iteration cap L (0: the workload's own)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-iters", type=int, default=3)
+    ap.add_argument("--cpu-sample-iters", type=int, default=8)
     # serving stream (--config 5)
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--serve-steps", type=int, default=10)
@@ -546,7 +546,25 @@ def cpu_baseline(sc, prm, iters_per_step, sample_iters):
             "kind": "oracle",
             "sample": f"first {done} of {iters_per_step} iterations of one step "
                       f"({dt:.1f} s, {pairs} pair updates), scaled to the full step",
-            "pair_updates_per_s": round(pairs / dt, 1)}
+            "pair_updates_per_s": round(pair_rate(pairs, dt), 1),
+            "host_nproc": os.cpu_count(),
+            "host_cpu": host_cpu_model()}
+
+
+def pair_rate(pairs, dt):
+    return pairs / dt if dt > 0 else 0.0
+
+
+def host_cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 if __name__ == "__main__":

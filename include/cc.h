@@ -11,12 +11,17 @@
  *     exact FP64 distance filter d < D_max;
  *   - the pair pass: distances at x^(l), P <- {d < D}, A <- {d < delta}, the
  *     per-vertex bounds D_i (Sec. 5);
- *   - the backward step: volume-based contact rows linearised at x^(l)
- *     (Sec. 4, Sec. 4.1), coloured (Sec. 4.3), one projected Gauss-Seidel sweep,
+ *   - the backward step: contact rows linearised at x^(l) (Sec. 4, Sec. 4.1; the
+ *     volume form when both closest points are interior, the gap form the section
+ *     names otherwise), coloured (Sec. 4.3), one projected Gauss-Seidel sweep,
  *     then the soft unilateral edge-length rows (Sec. 4.2);
- *   - the forward step (Eq. eq:forward2) and the reductions of Alg. 1;
+ *   - the forward step (Eq. eq:forward2), with the lemma of Sec. 5 checked on the
+ *     rounded move (2 |x_new - x| < D_i - eta, else the vertex stays), and the
+ *     reductions of Alg. 1;
  *   - the path certificate of the new linear piece over P (lemma of Sec. 5),
- *     with a continuous test (coplanarity cubic) for pairs the bound misses.
+ *     with a continuous test (coplanarity cubic, end probes, conservative
+ *     advancement) for pairs the bound misses; a pair it does not clear sends its
+ *     vertices back to x^(l).
  *
  * Conventions for every function below:
  *   - Array arguments are DEVICE pointers unless the name ends in _host.
@@ -80,6 +85,10 @@ enum { CC_CONVERGED = 0, CC_MAXITER = 1 };
                                Jacobians, multipliers and y - x) in FP32; every set
                                decision, distance, D_i, x, the forward step and the
                                continuous test stay FP64 */
+#define CC_UNGUARDED 128u   /* the forward step exactly as Eq. eq:forward2, without the
+                               check of the rounded move (below): the certificate and its
+                               response are then the only guard. A test of the
+                               certificate; not for production use */
 
 /* Parameters; defaults are Table 2 of the paper (cc_default_params). */
 typedef struct cc_params {
@@ -94,7 +103,7 @@ typedef struct cc_params {
   int32_t gs_sweeps; /* Gauss-Seidel sweeps per backward step, 1 (Sec. 4.3.1) */
   int32_t max_colors;/* colour palette, <= 1024 */
   uint32_t flags;    /* CC_EDGE_LEN | CC_TIME_KERNELS | CC_TIME_ONE | CC_TRACE | CC_MIXED |
-                        CC_VALIDATE_INPUT | CC_CCD_ALL */
+                        CC_VALIDATE_INPUT | CC_CCD_ALL | CC_UNGUARDED */
   uint64_t seed;     /* colouring priority seed */
   double omega;      /* CC_JACOBI: under-relaxation factor in (0, 1] (Sec. 4.3.2 names the
                         factor but gives no value; default 0.5) */
@@ -107,7 +116,8 @@ enum {
   CC_GAUSS_SEIDEL = 0, /* one projected Gauss-Seidel sweep over the colours (the method) */
   CC_JACOBI = 1        /* one projected Jacobi iteration: every row from the same y, the
                           per-vertex updates summed on a 2^-56 m grid (exact, order
-                          independent), y += omega * sum; no colouring. FP64 only. */
+                          independent; within rounding of a plain binary64 sum),
+                          y += omega * sum; no colouring. FP64 only. */
 };
 
 /* Per-iteration record (filled by cc_solver_iterate). Set fingerprints are
@@ -119,9 +129,12 @@ typedef struct cc_iter_info {
   int64_t n_p;       /* |P| evaluated by the pair pass */
   int64_t n_pf;      /* |P'| = {d < D} */
   int64_t n_a;       /* |A| = {d < delta} */
-  int64_t ccd_fail;  /* pairs of P' whose motion bound did not certify the piece */
-  int64_t ccd_hits;  /* of those, pairs the continuous test (FP64 coplanarity cubic)
-                        finds within 1e-12 m along the piece */
+  int64_t ccd_fail;  /* pairs of P' that took the continuous test: those the motion
+                        bound did not certify (all pairs with CC_CCD_ALL), summed over
+                        the certificate's passes */
+  int64_t ccd_hits;  /* of those, pairs the continuous test does not clear (it finds
+                        them within eta = 1e-12 m along the piece) */
+  int64_t n_back;    /* vertices the certificate sent back to x^(l) */
   double d_before;
   double d_after;
   double move_max;
@@ -149,6 +162,7 @@ typedef struct cc_stats {
   int64_t row_updates;   /* sum over iterations of |A| + active edge rows, x sweeps */
   int64_t ccd_fail;
   int64_t ccd_hits;
+  int64_t n_back;
   double r_inf;
   double kernel_ms[CC_K_COUNT];        /* with CC_TIME_KERNELS (CC_TIME_ONE: that family) */
   int64_t kernel_launches[CC_K_COUNT];
@@ -201,11 +215,13 @@ typedef struct cc_scene {
 
 /* One collision-handling step for each of n_scenes independent scenes of any
  * sizes. Each scene's result equals the result of cc_collide_step on that scene
- * alone. The scenes run concurrently on the device (one resident workspace and
- * one library stream per scene slot, kept in the context between calls); the
- * call returns when every scene is done, and `stream` is ordered after the work.
- * stats (n_scenes entries) may be NULL. An error in any scene is returned (the
- * first in scene order); the other scenes still complete. */
+ * alone, bit for bit. The scenes are segments of one multi-scene engine (a
+ * workspace kept in the context between calls): every iteration runs Alg. 1 once
+ * for all scenes still iterating, in the same kernel launches, and a scene drops
+ * out when it stops (its own stop test or max_iters). The work is issued on
+ * `stream`; the call returns when every scene is done. stats (n_scenes entries)
+ * may be NULL. An error in any scene is returned (the first in scene order); the
+ * other scenes still complete. */
 int cc_collide_step_batched(cc_context* ctx, const cc_scene* scenes, int32_t n_scenes,
                             const cc_params* params, cc_stats* stats, void* stream);
 
@@ -229,10 +245,13 @@ int cc_normal_flow_target(cc_context* ctx, const double* x, int32_t n_verts,
                           int32_t iters, double* y, void* stream);
 
 /* ---- serving: resident scenes admitted by HBM budget ------------------------
- * A resident scene keeps its topology, masses, current state x and workspace on
- * the device between steps, so each step starts from the previous step's result.
- * Steps of different scenes run concurrently (a worker pool with one stream per
- * scene); a scene runs one step at a time. Handles are >= 0. */
+ * A resident scene keeps its topology, masses, current state x and its share of
+ * the workspace on the device between steps, so each step starts from the
+ * previous step's result. All resident scenes are segments of one multi-scene
+ * engine owned by a scheduler thread of the context (continuous batching): at
+ * each iteration boundary it applies admissions, releases and submitted steps,
+ * then runs one iteration for every scene with a step in flight, in shared kernel
+ * launches on its own stream. A scene runs one step at a time. Handles are >= 0. */
 /* Budget in bytes for the workspaces of resident scenes (0 = unlimited). */
 int cc_context_set_budget(cc_context* ctx, size_t hbm_budget_bytes);
 /* Bytes a resident scene of this size reserves against the budget. */

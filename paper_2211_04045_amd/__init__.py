@@ -12,11 +12,13 @@ import ctypes as C
 
 from . import _lib
 from ._lib import (CC_CCD_ALL, CC_EDGE_LEN, CC_MIXED, CC_TIME_KERNELS, CC_TIME_ONE, CC_TRACE,
-                   CC_VALIDATE_INPUT, CCError, IterInfo, Params, SceneDesc, Stats)
+                   CC_UNGUARDED, CC_VALIDATE_INPUT, CCError, IterInfo, Params, SceneDesc,
+                   Stats)
 
 __all__ = ["Context", "Solver", "Server", "collide_step", "collide_step_batched", "params",
            "edges_from_tris", "normal_flow_target", "CC_EDGE_LEN", "CC_TIME_KERNELS",
-           "CC_TIME_ONE", "CC_TRACE", "CC_MIXED", "CC_VALIDATE_INPUT", "CC_CCD_ALL", "CCError"]
+           "CC_TIME_ONE", "CC_TRACE", "CC_MIXED", "CC_VALIDATE_INPUT", "CC_CCD_ALL",
+           "CC_UNGUARDED", "CCError"]
 
 
 def _torch():
@@ -52,8 +54,9 @@ def _ptr(t):
 
 def params(**over) -> Params:
     """Defaults of Table 2 (cc_default_params) with keyword overrides; the flags
-    are set with edge_len=, time_kernels=, trace=, mixed=, validate= and ccd_all=
-    (booleans) and time_one= (a family name of K_NAMES: that family alone is timed);
+    are set with edge_len=, time_kernels=, trace=, mixed=, validate=, ccd_all= and
+    unguarded= (booleans) and time_one= (a family name of K_NAMES: that family alone
+    is timed);
     backward= takes "gs" (default) or "jacobi"."""
     p = Params()
     _lib.load().cc_default_params(C.byref(p))
@@ -74,6 +77,8 @@ def params(**over) -> Params:
             p.flags = (p.flags | CC_MIXED) if v else (p.flags & ~CC_MIXED)
         elif k == "ccd_all":
             p.flags = (p.flags | CC_CCD_ALL) if v else (p.flags & ~CC_CCD_ALL)
+        elif k == "unguarded":
+            p.flags = (p.flags | CC_UNGUARDED) if v else (p.flags & ~CC_UNGUARDED)
         elif k == "validate":
             p.flags = (p.flags | CC_VALIDATE_INPUT) if v else (p.flags & ~CC_VALIDATE_INPUT)
         elif k == "backward":

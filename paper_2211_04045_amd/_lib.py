@@ -20,6 +20,7 @@ CC_MIXED = 8
 CC_VALIDATE_INPUT = 16
 CC_CCD_ALL = 32
 CC_TIME_ONE = 64
+CC_UNGUARDED = 128
 CC_GAUSS_SEIDEL = 0
 CC_JACOBI = 1
 K_NAMES = ["search", "pair", "color", "gs", "forward", "cert"]
@@ -51,7 +52,8 @@ class Params(C.Structure):
 class IterInfo(C.Structure):
     _fields_ = [("searched", C.c_int32), ("n_colors", C.c_int32), ("n_p", C.c_int64),
                 ("n_pf", C.c_int64), ("n_a", C.c_int64), ("ccd_fail", C.c_int64),
-                ("ccd_hits", C.c_int64), ("d_before", C.c_double), ("d_after", C.c_double), ("move_max", C.c_double),
+                ("ccd_hits", C.c_int64), ("n_back", C.c_int64), ("d_before", C.c_double),
+                ("d_after", C.c_double), ("move_max", C.c_double),
                 ("r_inf", C.c_double), ("fp_pf", C.c_uint64), ("fp_a", C.c_uint64),
                 ("fp_col", C.c_uint64)]
 
@@ -69,12 +71,12 @@ class Stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("searches", C.c_int32), ("status", C.c_int32),
                 ("max_colors_used", C.c_int32), ("pair_updates", C.c_int64),
                 ("row_updates", C.c_int64), ("ccd_fail", C.c_int64), ("ccd_hits", C.c_int64),
-                ("r_inf", C.c_double),
+                ("n_back", C.c_int64), ("r_inf", C.c_double),
                 ("kernel_ms", C.c_double * 6), ("kernel_launches", C.c_int64 * 6),
                 ("kernel_bytes", C.c_double * 6)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_[:9]}
+        d = {k: getattr(self, k) for k, _ in self._fields_[:10]}
         d["kernels"] = {K_NAMES[i]: dict(ms=self.kernel_ms[i], launches=self.kernel_launches[i],
                                          bytes=self.kernel_bytes[i]) for i in range(6)}
         return d

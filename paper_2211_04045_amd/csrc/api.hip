@@ -161,6 +161,7 @@ int alloc_active(cc_solver* s, int64_t cap) {
 
 void free_vertex_arrays(cc_solver* s) {
   dfree(s->w); dfree(s->stat); dfree(s->x); dfree(s->y); dfree(s->xt); dfree(s->xold);
+  dfree(s->rold); dfree(s->dyold); dfree(s->back);
   dfree(s->r); dfree(s->move2); dfree(s->mvd); dfree(s->Di); dfree(s->vseg); dfree(s->plist); dfree(s->dy);
   dfree(s->jacc);
   dfree(s->vmax0); dfree(s->claims); dfree(s->masks); dfree(s->vloc);
@@ -219,6 +220,11 @@ int resize_arrays(cc_solver* s, int32_t capV, int32_t capF, int32_t capE, hipStr
     CC_TRY(launch_fill_i32(s->vseg + oV, capV - oV, -1, st));
     CC_TRY(dregrow(&s->plist, capV, oV, st));
     dfree(s->xold); dfree(s->move2); dfree(s->Di); dfree(s->vmax0); dfree(s->claims); dfree(s->masks);
+    dfree(s->rold); dfree(s->dyold); dfree(s->back);
+    CC_TRY(dalloc(&s->rold, capV));
+    CC_TRY(dalloc(&s->dyold, 3 * (int64_t)capV));
+    CC_TRY(dalloc(&s->back, capV));
+    CC_TRY(launch_fill_i32(s->back, capV, 0, st));
     CC_TRY(dalloc(&s->xold, 3 * (int64_t)capV));
     CC_TRY(dalloc(&s->move2, capV));
     dfree(s->mvd);
@@ -716,6 +722,22 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
   if (trace || jacobi || small)
     CC_HIP(hipMemcpyAsync(s->hc, s->dc, sizeof(Counters), hipMemcpyDeviceToHost, st));
   CC_HIP(hipStreamSynchronize(st));
+  // vertices of pieces the certificate did not clear go back to x^(l); that changes
+  // the pieces of the pairs sharing them, so the certificate runs again until it
+  // sends no new vertex back (the returned set only grows)
+  for (unsigned long long nb_seen = 0;;) {
+    unsigned long long nb = 0;
+    for (int32_t sg : act) nb += s->seg_host[sg].nback;
+    if (nb == nb_seen) break;
+    nb_seen = nb;
+    timer_begin(s, CC_K_CERT, st);
+    CC_TRY(launch_send_back(s, ns, st));
+    CC_TRY(launch_cert(s, st));
+    timer_end(s, st);
+    CC_HIP(hipMemcpyAsync(s->seg_host, s->seg_dev, sizeof(SegDev) * ns, hipMemcpyDeviceToHost,
+                          st));
+    CC_HIP(hipStreamSynchronize(st));
+  }
   if (jacobi && (s->hc->err & 16ull)) return CC_EOVERFLOW;
   if (small) {
     // the projection and the forward step did nothing if the colouring failed
@@ -739,6 +761,7 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
     it.r_inf = rinf;
     it.ccd_fail = (int64_t)d.fail;
     it.ccd_hits = (int64_t)d.hits;
+    it.n_back = (int64_t)d.nback;
     it.fp_pf = fp_pf;
     it.fp_a = fp_a;
     it.fp_col = trace ? s->hc->fp_col : 0;
@@ -749,6 +772,7 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
     g.st.row_updates += (it.n_a + g.n_erows) * (int64_t)p.gs_sweeps;
     g.st.ccd_fail += it.ccd_fail;
     g.st.ccd_hits += it.ccd_hits;
+    g.st.n_back += it.n_back;
     g.st.r_inf = rinf;
     if (s->n_colors > g.st.max_colors_used) g.st.max_colors_used = s->n_colors;
     if (rinf < p.eps) {

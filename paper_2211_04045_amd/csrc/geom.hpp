@@ -53,12 +53,14 @@ __device__ __forceinline__ double pt_seg_d2(V3 p, V3 u, V3 v, double& t) {
 }
 
 // Point-triangle: interior projection candidate (when inside), then edges
-// (a,b), (b,c), (c,a); first strict minimum. bw = closest point weights.
-__device__ __forceinline__ double pt_tri_d2(V3 p, V3 a, V3 b, V3 c, double bw[3]) {
+// (a,b), (b,c), (c,a); first strict minimum. bw = closest point weights; which =
+// the winning candidate (0 interior, 1..3 the edges, -1 none).
+__device__ __forceinline__ double pt_tri_d2(V3 p, V3 a, V3 b, V3 c, double bw[3], int& which) {
   V3 ab = vsub(b, a), ac = vsub(c, a), ap = vsub(p, a);
   V3 n = vcross(ab, ac);
   double nn = vdot(n, n);
   double best = __builtin_inf();
+  which = -1;
   bw[0] = 1.0;
   bw[1] = 0.0;
   bw[2] = 0.0;
@@ -71,6 +73,7 @@ __device__ __forceinline__ double pt_tri_d2(V3 p, V3 a, V3 b, V3 c, double bw[3]
     if (wa >= 0.0 && wb >= 0.0 && wc >= 0.0) {
       double h = vdot(ap, n);
       best = h * h / nn;
+      which = 0;
       bw[0] = wa;
       bw[1] = wb;
       bw[2] = wc;
@@ -80,6 +83,7 @@ __device__ __forceinline__ double pt_tri_d2(V3 p, V3 a, V3 b, V3 c, double bw[3]
   e2 = pt_seg_d2(p, a, b, t);
   if (e2 < best) {
     best = e2;
+    which = 1;
     bw[0] = 1.0 - t;
     bw[1] = t;
     bw[2] = 0.0;
@@ -87,6 +91,7 @@ __device__ __forceinline__ double pt_tri_d2(V3 p, V3 a, V3 b, V3 c, double bw[3]
   e2 = pt_seg_d2(p, b, c, t);
   if (e2 < best) {
     best = e2;
+    which = 2;
     bw[0] = 0.0;
     bw[1] = 1.0 - t;
     bw[2] = t;
@@ -94,21 +99,29 @@ __device__ __forceinline__ double pt_tri_d2(V3 p, V3 a, V3 b, V3 c, double bw[3]
   e2 = pt_seg_d2(p, c, a, t);
   if (e2 < best) {
     best = e2;
+    which = 3;
     bw[0] = t;
     bw[1] = 0.0;
     bw[2] = 1.0 - t;
   }
   return best;
 }
+__device__ __forceinline__ double pt_tri_d2(V3 p, V3 a, V3 b, V3 c, double bw[3]) {
+  int which;
+  return pt_tri_d2(p, a, b, c, bw, which);
+}
 
 // Segment-segment: interior stationary point (non-parallel, inside the unit
 // square), then endpoint candidates a|ce, b|ce, c|ab, e|ab; first strict minimum.
-__device__ __forceinline__ double seg_seg_d2(V3 a, V3 b, V3 c, V3 e, double& bs, double& bt) {
+// which = the winning candidate (0 interior, 1..4 the endpoint candidates).
+__device__ __forceinline__ double seg_seg_d2(V3 a, V3 b, V3 c, V3 e, double& bs, double& bt,
+                                             int& which) {
   V3 d1 = vsub(b, a), d2 = vsub(e, c), r = vsub(a, c);
   double A = vdot(d1, d1), B = vdot(d1, d2), C = vdot(d2, d2);
   double Dd = vdot(d1, r), Ee = vdot(d2, r);
   double den = A * C - B * B;
   double best = __builtin_inf();
+  which = -1;
   bs = 0.0;
   bt = 0.0;
   if (den > 0.0) {
@@ -119,20 +132,25 @@ __device__ __forceinline__ double seg_seg_d2(V3 a, V3 b, V3 c, V3 e, double& bs,
       V3 q = vaxpy(c, t, d2);
       V3 d = vsub(p, q);
       best = vdot(d, d);
+      which = 0;
       bs = s;
       bt = t;
     }
   }
   double u, e2;
   e2 = pt_seg_d2(a, c, e, u);
-  if (e2 < best) { best = e2; bs = 0.0; bt = u; }
+  if (e2 < best) { best = e2; bs = 0.0; bt = u; which = 1; }
   e2 = pt_seg_d2(b, c, e, u);
-  if (e2 < best) { best = e2; bs = 1.0; bt = u; }
+  if (e2 < best) { best = e2; bs = 1.0; bt = u; which = 2; }
   e2 = pt_seg_d2(c, a, b, u);
-  if (e2 < best) { best = e2; bs = u; bt = 0.0; }
+  if (e2 < best) { best = e2; bs = u; bt = 0.0; which = 3; }
   e2 = pt_seg_d2(e, a, b, u);
-  if (e2 < best) { best = e2; bs = u; bt = 1.0; }
+  if (e2 < best) { best = e2; bs = u; bt = 1.0; which = 4; }
   return best;
+}
+__device__ __forceinline__ double seg_seg_d2(V3 a, V3 b, V3 c, V3 e, double& bs, double& bt) {
+  int which;
+  return seg_seg_d2(a, b, c, e, bs, bt, which);
 }
 
 // Pair keys: bit 63 = edge-edge, bit 62 = vertex-vertex; bits 61..32 = first
@@ -198,18 +216,20 @@ struct Row {
   V3 J[4];
 };
 
-// Contact row at x: volume form (Sec. 4.1: reference shape separated by delta,
-// c = V(x)/V(r) - 1, J = grad V(x) / V(r)), or the gap fallback
-// c = d/delta - 1, J_v = omega_v u / delta for near-parallel edges and near
-// degenerate triangles. w = inverse masses of the four vertices.
+// Contact row at x: volume form (Sec. 4.1: reference shape separated by delta
+// along the normal, c = V(x)/V(r) - 1, J = grad V(x) / V(r)) when both closest
+// points are interior (the normal is then their separating direction) and the
+// tetrahedron is not near degenerate; otherwise the gap form c = d/delta - 1,
+// J_v = omega_v u / delta. w = inverse masses of the four vertices.
 __device__ __forceinline__ void contact_row(bool ee, const V3 xs[4], const double w[4],
                                             double delta, double kappa2, Row& R) {
   double om[4], d2, bw[3], s0 = 0.0, t0 = 0.0;
   bool volume_ok;
+  int which;
   V3 N;
   double side;
   if (ee) {
-    d2 = seg_seg_d2(xs[0], xs[1], xs[2], xs[3], s0, t0);
+    d2 = seg_seg_d2(xs[0], xs[1], xs[2], xs[3], s0, t0, which);
     om[0] = 1.0 - s0;
     om[1] = s0;
     om[2] = -(1.0 - t0);
@@ -222,7 +242,7 @@ __device__ __forceinline__ void contact_row(bool ee, const V3 xs[4], const doubl
     V3 ac = vsub(xs[0], xs[2]);
     side = vdot(ac, N) >= 0.0 ? 1.0 : -1.0;
   } else {
-    d2 = pt_tri_d2(xs[0], xs[1], xs[2], xs[3], bw);
+    d2 = pt_tri_d2(xs[0], xs[1], xs[2], xs[3], bw, which);
     om[0] = 1.0;
     om[1] = -bw[0];
     om[2] = -bw[1];
@@ -237,6 +257,7 @@ __device__ __forceinline__ void contact_row(bool ee, const V3 xs[4], const doubl
     V3 ai = vsub(xs[0], xs[1]);
     side = vdot(ai, N) >= 0.0 ? 1.0 : -1.0;
   }
+  if (which != 0) volume_ok = false;
   double d = sqrt(d2);
   R.inv_a = 0.0;
   if (volume_ok) {
@@ -310,23 +331,37 @@ __device__ __forceinline__ void contact_row_vv(const V3 xs[4], const double w[4]
 }
 
 // Continuous test of one pair along the linear piece q_k(t) = q_k + t dq_k,
-// t in [0,1] (points in the contact-row order). Coplanarity V(t) =
-// det[q1-q0, q2-q0, q3-q0](t) is the cubic a3 t^3 + a2 t^2 + a1 t + a0; its
-// critical points split [0,1] into monotone pieces, a sign change is bisected to
-// the root, and the primitives' distance at every root and critical point decides
-// contact (<= eta). FP64 throughout.
+// t in [0,1] (points in the contact-row order); contact means a distance <= eta.
+// The distance is probed at t = 0; at the times where the four points are
+// coplanar, V(t) = det[q1-q0, q2-q0, q3-q0](t) = 0, a cubic a3 t^3 + a2 t^2 + a1 t
+// + a0 whose critical points split [0,1] into monotone pieces (a sign change is
+// bisected to the root), and at those critical points; then the piece is swept by
+// conservative advancement (Mirtich's method: the distance changes at most at rate
+// Lc = max |dq| over the first primitive + max |dq| over the second, so from a time
+// t with distance d > eta no contact occurs before t + (d - eta) / Lc; this also
+// covers a piece that stays coplanar, which the cubic cannot see; a piece not
+// cleared within kCaSteps advances counts as a contact) and probed at t = 1.
+// FP64 throughout.
+constexpr int kCaSteps = 1024;
+
 __device__ __forceinline__ double cubic_at(const double a[4], double t) {
   return ((a[3] * t + a[2]) * t + a[1]) * t + a[0];
 }
 
-__device__ __forceinline__ bool ccd_probe(const V3 q[4], const V3 dq[4], bool ee, double t,
-                                          double eta2) {
+__device__ __forceinline__ double ccd_dist2(const V3 q[4], const V3 dq[4], bool ee, double t) {
   V3 p0 = vaxpy(q[0], t, dq[0]), p1 = vaxpy(q[1], t, dq[1]);
   V3 p2 = vaxpy(q[2], t, dq[2]), p3 = vaxpy(q[3], t, dq[3]);
-  return pair_d2(ee ? KEY_EE : 0ull, p0, p1, p2, p3) <= eta2;
+  return pair_d2(ee ? KEY_EE : 0ull, p0, p1, p2, p3);
 }
 
-__device__ __noinline__ bool ccd_hit(const V3 q[4], const V3 dq[4], bool ee, double eta2) {
+__device__ __forceinline__ bool ccd_probe(const V3 q[4], const V3 dq[4], bool ee, double t,
+                                          double eta2) {
+  return ccd_dist2(q, dq, ee, t) <= eta2;
+}
+
+__device__ __noinline__ bool ccd_hit(const V3 q[4], const V3 dq[4], bool ee, double eta) {
+  const double eta2 = eta * eta;
+  if (ccd_probe(q, dq, ee, 0.0, eta2)) return true;
   V3 e1 = vsub(q[1], q[0]), e2 = vsub(q[2], q[0]), e3 = vsub(q[3], q[0]);
   V3 f1 = vsub(dq[1], dq[0]), f2 = vsub(dq[2], dq[0]), f3 = vsub(dq[3], dq[0]);
   V3 c23 = vcross(e2, e3), f2e3 = vcross(f2, e3), e2f3 = vcross(e2, f3), f2f3 = vcross(f2, f3);
@@ -379,7 +414,28 @@ __device__ __noinline__ bool ccd_hit(const V3 q[4], const V3 dq[4], bool ee, dou
     if (t >= 0.0 && ccd_probe(q, dq, ee, t, eta2)) return true;
     if (i + 2 < nk && ccd_probe(q, dq, ee, knot[i + 1], eta2)) return true;
   }
-  return false;
+  // conservative advancement over the piece
+  double l1 = 0.0, l2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double mk = sqrt(vdot(dq[k], dq[k]));
+    if (k < (ee ? 2 : 1)) {
+      if (mk > l1) l1 = mk;
+    } else if (mk > l2) {
+      l2 = mk;
+    }
+  }
+  const double lc = l1 + l2;
+  double t = 0.0;
+  bool cleared = !(lc > 0.0);
+  for (int step = 0; step < kCaSteps && !cleared; ++step) {
+    const double d = sqrt(ccd_dist2(q, dq, ee, t));
+    if (d <= eta) return true;
+    t = t + (d - eta) / lc;
+    if (t >= 1.0) cleared = true;
+  }
+  if (!cleared) return true;
+  return ccd_probe(q, dq, ee, 1.0, eta2);
 }
 
 // Sign of det[b-a, c-a, d-a] (d against the plane of a, b, c); 0 when the FP64

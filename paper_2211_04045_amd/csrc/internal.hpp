@@ -26,7 +26,12 @@ namespace cc {
 constexpr int kMaxColors = 1024;
 constexpr int kMaskWords = kMaxColors / 64;
 constexpr int kMaxRounds = 4096;  // colouring rounds per colouring
-constexpr double kCcdEta = 1e-12;  // distance at which the continuous test reports contact (m)
+// eta (m): primitives closer than eta count as touching (continuous test), and the
+// forward step keeps a vertex's rounded move below (D_i - eta) / 2; binary64
+// distances of scenes with coordinates within +-10 m are exact to far better
+constexpr double kEta = 1e-12;
+// certificate queue entry: bit 63 set when the motion bound certified the pair
+constexpr unsigned long long kQueueCertified = 1ull << 63;
 constexpr int kMaxSeg = 1024;      // scenes (segments) resident in one solver
 constexpr int kSegBits = 10;       // bits of a segment's rank in a search's sort keys
 constexpr int32_t kMaxIds = 1 << 30;  // primitive ids of pair keys are 30-bit
@@ -50,7 +55,8 @@ struct SegDev {
   unsigned long long n_pf;      // |P'|
   unsigned long long n_a;       // |A|
   unsigned long long n_rows;    // valid edge-length rows (setup)
-  unsigned long long pad[4];
+  unsigned long long nback;     // vertices the certificate sent back to x^(l)
+  unsigned long long pad[3];
 };
 static_assert(sizeof(SegDev) == 128, "SegDev is one 128-byte record");
 constexpr int32_t kSegActive = 1;    // the segment iterates
@@ -194,6 +200,9 @@ struct cc_solver {
   float* dy = nullptr;  // mixed precision: y - x in FP32 (3 per vertex)
   long long* jacc = nullptr;  // projected Jacobi: per-vertex update sums, 2^-56 m units
   double* xold = nullptr;  // x^(l) kept by the forward step for the continuous test
+  double* rold = nullptr;  // r^(l), for vertices the certificate sends back
+  float* dyold = nullptr;  // mixed precision: y - x^(l), likewise
+  int32_t* back = nullptr; // certificate: 0, 2 = sent back in this pass, 1 = earlier
   unsigned long long* Di = nullptr;
   double D = 0.0;  // single-scene interface: D of segment 0
   // proximity set (double buffered for compaction) and distances of P'
@@ -313,7 +322,10 @@ int build_edge_buckets(cc_solver* s, hipStream_t st);
 int launch_gs(cc_solver* s, hipStream_t st);
 int launch_jacobi(cc_solver* s, hipStream_t st);
 int launch_forward(cc_solver* s, hipStream_t st);
+// one pass of the certificate over P'; vertices of pairs it does not clear are marked
 int launch_cert(cc_solver* s, hipStream_t st);
+// the marked vertices back to x^(l), ||r||_inf again, queue cleared (ns segments)
+int launch_send_back(cc_solver* s, int32_t ns, hipStream_t st);
 int launch_fp_col(cc_solver* s, hipStream_t st);
 // mixed precision: y <-> x + dy for vertices [0, n)
 int launch_y_of_dy(cc_solver* s, double* y, int32_t n, hipStream_t st);

@@ -1410,9 +1410,10 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
     if (!refit) s->bvh_q0 = q;
     else if (q > kRefitSlack * s->bvh_q0) s->bvh_gen = ~0ull;
   }
-  // algorithmic bytes of the traversal: queries, node records, output keys
+  // algorithmic bytes of the traversal: queries, node records, output keys and their
+  // squared distances (8 + 8 bytes per pair found)
   s->st.kernel_bytes[CC_K_SEARCH] += 24.0 * mv + 8.0 * me + 28.0 * mp + 64.0 * (double)m +
-                                     8.0 * (double)*nfound;
+                                     16.0 * (double)*nfound;
   return CC_OK;
 }
 

@@ -1877,6 +1877,12 @@ int launch_jacobi(cc_solver* s, hipStream_t st) {
 // x_i <- y_i if alpha_i = 1 else x_i + alpha_i (y_i - x_i), r_i <- r_i (1 - alpha_i);
 // per segment max ||x_i^(l+1) - x_i^(l)|| and ||r||_inf for Alg. 1 (bit patterns of
 // non-negative doubles, block-combined in a small LDS table, then atomicMax).
+// The lemma of Sec. 5 for the rounded move: unless `unguarded`, a vertex advances
+// only when 2 |x_new - x| < D_i - eta (eta covers the rounding of the distances);
+// otherwise it stays (alpha = 0). With gamma < 1 this differs from the equation
+// only below D_i = eta / (1 - gamma) and on rounding.
+// x^(l), r^(l) (and in mixed precision y - x^(l)) are kept for the certificate,
+// which may send a vertex back; its return flag is cleared here.
 // Vertices of segments that do not iterate are left alone.
 // Mixed precision: y = x + dy with dy in FP32; the step itself is FP64 and the
 // new dy is y - x^(l+1) rounded (0 when the vertex reached y).
@@ -1885,10 +1891,14 @@ __global__ void __launch_bounds__(kThreads) k_forward(double* __restrict__ x,
                                                       double* __restrict__ xold,
                                                       const double* __restrict__ y,
                                                       float* __restrict__ dyf,
+                                                      float* __restrict__ dyold,
                                                       const unsigned long long* __restrict__ Di,
                                                       double* __restrict__ r,
+                                                      double* __restrict__ rold,
+                                                      int32_t* __restrict__ back,
                                                       double* __restrict__ move2, int32_t n,
-                                                      double hg, const int32_t* __restrict__ vseg,
+                                                      double hg, int guard,
+                                                      const int32_t* __restrict__ vseg,
                                                       SegDev* seg,
                                                       const unsigned long long* err,
                                                       uint8_t* __restrict__ mvd) {
@@ -1905,33 +1915,47 @@ __global__ void __launch_bounds__(kThreads) k_forward(double* __restrict__ x,
   if (sg >= 0 && (seg[sg].flags & kSegActive)) {
     V3 xi = ld3(x, i), yi, dx;
     if (kMixed) {
-      const float* d = dyf + 3 * (int64_t)i;
+      float* d = dyf + 3 * (int64_t)i;
       dx = V3{(double)d[0], (double)d[1], (double)d[2]};
       yi = V3{xi.x + dx.x, xi.y + dx.y, xi.z + dx.z};
+      float* o = dyold + 3 * (int64_t)i;
+      o[0] = d[0];
+      o[1] = d[1];
+      o[2] = d[2];
     } else {
       yi = ld3(y, i);
       dx = vsub(yi, xi);
     }
+    const double di = __longlong_as_double((long long)Di[i]);
     double n2 = vdot(dx, dx);
     double alpha = 1.0;
     if (n2 > 0.0) {
-      double a = (hg * __longlong_as_double((long long)Di[i])) / sqrt(n2);
+      double a = (hg * di) / sqrt(n2);
       if (a < 1.0) alpha = a;
     }
     V3 xn = (alpha == 1.0) ? yi : vaxpy(xi, alpha, dx);
+    V3 mv = vsub(xn, xi);
+    double m2 = vdot(mv, mv);
+    const double sb = di - kEta;
+    if (guard && !(sb > 0.0 && 4.0 * m2 < sb * sb)) {
+      xn = xi;
+      m2 = 0.0;
+      alpha = 0.0;
+    }
     if (kMixed) {
       float* d = dyf + 3 * (int64_t)i;
       d[0] = (float)(yi.x - xn.x);
       d[1] = (float)(yi.y - xn.y);
       d[2] = (float)(yi.z - xn.z);
     }
-    V3 mv = vsub(xn, xi);
-    double m2 = vdot(mv, mv);
     move2[i] = m2;
     mvd[i] = (xn.x != xi.x || xn.y != xi.y || xn.z != xi.z) ? 1 : 0;
+    back[i] = 0;
     st3(xold, i, xi);
     st3(x, i, xn);
-    double ri = r[i] * (1.0 - alpha);
+    const double r0 = r[i];
+    rold[i] = r0;
+    double ri = r0 * (1.0 - alpha);
     r[i] = ri;
     const unsigned long long mb = (unsigned long long)__double_as_longlong(sqrt(m2));
     const unsigned long long rb = (unsigned long long)__double_as_longlong(ri);
@@ -1954,14 +1978,16 @@ __global__ void __launch_bounds__(kThreads) k_forward(double* __restrict__ x,
 
 int launch_forward(cc_solver* s, hipStream_t st) {
   const double hg = 0.5 * s->p.gamma;
+  const int guard = (s->p.flags & CC_UNGUARDED) ? 0 : 1;
   const unsigned long long* err = s->col_small ? &s->dc->err : nullptr;
   if (s->n > 0 && (s->p.flags & CC_MIXED))
-    k_forward<true><<<nblk(s->n), kThreads, 0, st>>>(s->x, s->xold, s->y, s->dy, s->Di, s->r,
-                                                      s->move2, s->n, hg, s->vseg, s->seg_dev, err,
-                                                      s->mvd);
+    k_forward<true><<<nblk(s->n), kThreads, 0, st>>>(s->x, s->xold, s->y, s->dy, s->dyold, s->Di,
+                                                      s->r, s->rold, s->back, s->move2, s->n, hg,
+                                                      guard, s->vseg, s->seg_dev, err, s->mvd);
   else if (s->n > 0)
-    k_forward<false><<<nblk(s->n), kThreads, 0, st>>>(s->x, s->xold, s->y, s->dy, s->Di, s->r,
-                                                       s->move2, s->n, hg, s->vseg, s->seg_dev, err,
+    k_forward<false><<<nblk(s->n), kThreads, 0, st>>>(s->x, s->xold, s->y, s->dy, s->dyold,
+                                                       s->Di, s->r, s->rold, s->back, s->move2,
+                                                       s->n, hg, guard, s->vseg, s->seg_dev, err,
                                                        s->mvd);
   CC_HIP(hipGetLastError());
   return CC_OK;
@@ -1971,9 +1997,10 @@ int launch_forward(cc_solver* s, hipStream_t st) {
 
 // Lemma of Sec. 5: the linear piece x^(l) -> x^(l+1) stays free for pair p when
 // no vertex of p moved half its distance, i.e. 4 max_v |dx_v|^2 < d_p^2. A pair the
-// bound does not certify is counted for its scene and queued (its index in P) for
-// the continuous test of the piece, which runs in a kernel of its own: the test is
-// rare and large, and kept out of this pass it does not lower its occupancy.
+// bound does not certify (or every pair with CC_CCD_ALL) is counted for its scene and
+// queued (its index in P, bit 63 set when the bound certified it) for the continuous
+// test of the piece, which runs in a kernel of its own: the test is rare and large,
+// and kept out of this pass it does not lower its occupancy.
 __global__ void __launch_bounds__(kThreads) k_cert(const uint64_t* __restrict__ P,
                                                    const double* __restrict__ dP, int64_t nP,
                                                    Topo T, const double* __restrict__ move2,
@@ -1981,7 +2008,7 @@ __global__ void __launch_bounds__(kThreads) k_cert(const uint64_t* __restrict__ 
                                                    unsigned long long* __restrict__ queue,
                                                    unsigned long long* nqueue, int all) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool fail = false;
+  bool fail = false, bound_ok = false;
   int32_t v[4] = {0, 0, 0, 0};
   if (i < nP) {
     pair_verts(T, P[i], v);
@@ -1991,28 +2018,34 @@ __global__ void __launch_bounds__(kThreads) k_cert(const uint64_t* __restrict__ 
       double m = move2[v[k]];
       if (m > mv) mv = m;
     }
-    fail = all || !(4.0 * mv < dP[i]);
+    bound_ok = 4.0 * mv < dP[i];
+    fail = all || !bound_ok;
   }
   const unsigned long long pos = wave_append(fail, nqueue);
   if (fail) {
-    queue[pos] = (unsigned long long)i;
+    queue[pos] = (unsigned long long)i | (bound_ok ? kQueueCertified : 0ull);
     atomicAdd(&seg[vseg[v[0]]].fail, 1ull);
   }
 }
 
 // The continuous test of every queued pair (a grid-stride loop over the queue,
 // whose length is read on the device); contacts are counted for the pair's scene.
+// A pair the motion bound did not certify and the test does not clear sends its
+// vertices back to x^(l): each vertex is marked once (2 = marked in this pass) and
+// counted as returned for its scene.
 __global__ void __launch_bounds__(kThreads) k_cert_ccd(const uint64_t* __restrict__ P, Topo T,
                                                        const double* __restrict__ xold,
-                                                       const double* __restrict__ x, double eta2,
+                                                       const double* __restrict__ x, double eta,
                                                        const int32_t* __restrict__ vseg,
                                                        SegDev* seg,
                                                        const unsigned long long* __restrict__ queue,
-                                                       const unsigned long long* nqueue) {
+                                                       const unsigned long long* nqueue,
+                                                       int32_t* __restrict__ back) {
   const int64_t n = (int64_t)*nqueue;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
        j += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t key = P[queue[j]];
+    const unsigned long long e = queue[j];
+    const uint64_t key = P[e & ~kQueueCertified];
     int32_t v[4];
     pair_verts(T, key, v);
     V3 q[4], dq[4];
@@ -2020,26 +2053,84 @@ __global__ void __launch_bounds__(kThreads) k_cert_ccd(const uint64_t* __restric
       q[k] = ld3(xold, v[k]);
       dq[k] = vsub(ld3(x, v[k]), q[k]);
     }
-    const bool hit = key_is_vv(key) ? ccd_hit_vv(q[0], q[1], dq[0], dq[1], eta2)
-                                    : ccd_hit(q, dq, key_is_ee(key), eta2);
-    if (hit) atomicAdd(&seg[vseg[v[0]]].hits, 1ull);
+    const bool hit = key_is_vv(key) ? ccd_hit_vv(q[0], q[1], dq[0], dq[1], eta * eta)
+                                    : ccd_hit(q, dq, key_is_ee(key), eta);
+    if (!hit) continue;
+    SegDev& sd = seg[vseg[v[0]]];
+    atomicAdd(&sd.hits, 1ull);
+    if (e & kQueueCertified) continue;
+    for (int k = 0; k < 4; ++k)
+      if (atomicCAS(&back[v[k]], 0, 2) == 0) atomicAdd(&sd.nback, 1ull);
   }
 }
 
-// The certificate of the current P'. The pair buffer P2 is free between the pair
-// passes and holds the queue (at most |P'| entries).
+// Vertices marked in the last pass go back to x^(l): x, r (and y - x) as before
+// the forward step, no move; then ||r||_inf of every iterating segment again.
+__global__ void __launch_bounds__(kThreads) k_send_back(double* __restrict__ x,
+                                                        const double* __restrict__ xold,
+                                                        double* __restrict__ r,
+                                                        const double* __restrict__ rold,
+                                                        float* __restrict__ dyf,
+                                                        const float* __restrict__ dyold,
+                                                        double* __restrict__ move2,
+                                                        uint8_t* __restrict__ mvd,
+                                                        int32_t* __restrict__ back, int32_t n) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || back[i] != 2) return;
+  back[i] = 1;
+  st3(x, i, ld3(xold, i));
+  r[i] = rold[i];
+  if (dyf) {
+    for (int k = 0; k < 3; ++k) dyf[3 * (int64_t)i + k] = dyold[3 * (int64_t)i + k];
+  }
+  move2[i] = 0.0;
+  mvd[i] = 0;
+}
+
+__global__ void k_seg_rinf_clear(SegDev* seg, int32_t ns) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ns && (seg[i].flags & kSegActive)) seg[i].rinf_bits = 0ull;
+}
+
+__global__ void __launch_bounds__(kThreads) k_seg_rinf(const double* __restrict__ r, int32_t n,
+                                                       const int32_t* __restrict__ vseg,
+                                                       SegDev* seg) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t sg = i < n ? vseg[i] : -1;
+  if (sg < 0 || !(seg[sg].flags & kSegActive)) return;
+  const unsigned long long rb = (unsigned long long)__double_as_longlong(r[i]);
+  if (rb) atomicMax(&seg[sg].rinf_bits, rb);
+}
+
+// One pass of the certificate over the current P'. The pair buffer P2 is free
+// between the pair passes and holds the queue (at most |P'| entries).
 int launch_cert(cc_solver* s, hipStream_t st) {
-  const double eta = kCcdEta;
   if (s->nP > 0) {
     unsigned long long* queue = (unsigned long long*)s->P2;
-    // dc->ncert starts at zero with the iteration's counters (k_di_init)
+    // dc->ncert starts at zero with the iteration's counters (k_di_init) and is
+    // cleared by launch_send_back before a further pass
     k_cert<<<nblk(s->nP), kThreads, 0, st>>>(s->P, s->dP, s->nP, Topo{s->tris, s->edges},
                                               s->move2, s->vseg, s->seg_dev, queue, &s->dc->ncert,
                                               (s->p.flags & CC_CCD_ALL) ? 1 : 0);
     const unsigned nb = std::min<unsigned>(nblk(s->nP), 1024u);
-    k_cert_ccd<<<nb, kThreads, 0, st>>>(s->P, Topo{s->tris, s->edges}, s->xold, s->x, eta * eta,
-                                         s->vseg, s->seg_dev, queue, &s->dc->ncert);
+    k_cert_ccd<<<nb, kThreads, 0, st>>>(s->P, Topo{s->tris, s->edges}, s->xold, s->x, kEta,
+                                         s->vseg, s->seg_dev, queue, &s->dc->ncert, s->back);
   }
+  CC_HIP(hipGetLastError());
+  return CC_OK;
+}
+
+// Send the marked vertices back, recompute ||r||_inf, clear the queue length.
+int launch_send_back(cc_solver* s, int32_t ns, hipStream_t st) {
+  if (s->n > 0) {
+    const bool mixed = (s->p.flags & CC_MIXED) != 0;
+    k_send_back<<<nblk(s->n), kThreads, 0, st>>>(s->x, s->xold, s->r, s->rold,
+                                                  mixed ? s->dy : nullptr, s->dyold, s->move2,
+                                                  s->mvd, s->back, s->n);
+    k_seg_rinf_clear<<<(ns + 255) / 256, 256, 0, st>>>(s->seg_dev, ns);
+    k_seg_rinf<<<nblk(s->n), kThreads, 0, st>>>(s->r, s->n, s->vseg, s->seg_dev);
+  }
+  k_fill_u64<<<1, 64, 0, st>>>(&s->dc->ncert, 1, 0ull);
   CC_HIP(hipGetLastError());
   return CC_OK;
 }

@@ -202,6 +202,33 @@ def _box_pairs(lo1, hi1, lo2, hi2, margin):
     return ii[ok], jj[ok]
 
 
+def _seg_seg_dist_fp(a, b, c, e):
+    """Binary64 segment-segment distances (vectorised): the minimum over the interior
+    stationary point (when it lies in the unit square) and the four endpoint-to-
+    segment distances."""
+    import numpy as np
+
+    def pt_seg(p, u, v):
+        uv = v - u
+        l2 = (uv * uv).sum(1)
+        t = np.where(l2 > 0, ((p - u) * uv).sum(1) / np.where(l2 > 0, l2, 1), 0.0)
+        t = np.clip(t, 0.0, 1.0)
+        return np.linalg.norm(p - (u + t[:, None] * uv), axis=1)
+
+    d1, d2, r = b - a, e - c, a - c
+    A, B, C = (d1 * d1).sum(1), (d1 * d2).sum(1), (d2 * d2).sum(1)
+    D, E = (d1 * r).sum(1), (d2 * r).sum(1)
+    den = A * C - B * B
+    ok = den > 0
+    dd = np.where(ok, den, 1.0)
+    s, t = (B * E - C * D) / dd, (A * E - B * D) / dd
+    inside = ok & (s >= 0) & (s <= 1) & (t >= 0) & (t <= 1)
+    dint = np.linalg.norm((a + s[:, None] * d1) - (c + t[:, None] * d2), axis=1)
+    best = np.minimum.reduce([pt_seg(a, c, e), pt_seg(b, c, e), pt_seg(c, a, b),
+                              pt_seg(e, a, b)])
+    return np.where(inside, np.minimum(best, dint), best)
+
+
 def touching_pairs(x, tris, edges, margin=1e-9):
     """Exact edge-triangle touches (closed edge and closed triangle sharing no vertex)
     and, for edges in no triangle, exact edge-edge touches. Returns two lists of
@@ -258,15 +285,12 @@ def touching_pairs(x, tris, edges, margin=1e-9):
                 for m in range(2):
                     share |= pe[i1, k] == pe[i2, m]
             i1, i2 = i1[~share], i2[~share]
-            for k in range(len(i1)):
-                e, g = pe[i1[k]], pe[i2[k]]
-                # a binary64 distance clearly above the rounding level cannot be 0
-                d1, d2, r = x[e[1]] - x[e[0]], x[g[1]] - x[g[0]], x[e[0]] - x[g[0]]
-                if np.linalg.norm(np.cross(d1, d2)) > 1e-12 * np.linalg.norm(d1) * \
-                        np.linalg.norm(d2):
-                    n = np.cross(d1, d2)
-                    if abs(np.dot(r, n)) / np.linalg.norm(n) > 1e-9:
-                        continue
-                if seg_seg_d2(x[e[0]], x[e[1]], x[g[0]], x[g[1]]) == 0:
+            # a binary64 distance clearly above the rounding level cannot be 0
+            a, b = x[pe[i1, 0]], x[pe[i1, 1]]
+            c, e = x[pe[i2, 0]], x[pe[i2, 1]]
+            near = _seg_seg_dist_fp(a, b, c, e) <= 1e-9
+            for k in np.nonzero(near)[0]:
+                e1, g1 = pe[i1[k]], pe[i2[k]]
+                if seg_seg_d2(x[e1[0]], x[e1[1]], x[g1[0]], x[g1[1]]) == 0:
                     ee.append((int(poly[i1[k]]), int(poly[i2[k]])))
     return et, ee
