@@ -244,6 +244,21 @@ int cc_normal_flow_target(cc_context* ctx, const double* x, int32_t n_verts,
                           const int32_t* tris, int32_t n_tris, double beta, double alpha,
                           int32_t iters, double* y, void* stream);
 
+/* The same target without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * it). Arguments, layout, result and errors as cc_normal_flow_target; the caller
+ * still provides x, tris and y. The work runs in a fixed scratch array compiled
+ * into the library (about 7 MiB on each device, held until the process ends), so
+ * sizes are limited: n_verts <= 131072 and n_tris <= 262144, else CC_EINVAL. The
+ * array's device address is looked up when a context for the device is created
+ * (CC_ESTATE if none was). Every call on one device shares that device's array:
+ * calls that overlap on one device (other streams or host threads) race. A triangle
+ * with an index outside [0, n_verts) is left out of the work and the call returns
+ * CC_EINVAL after the stream has synchronised (y is then unspecified). */
+int cc_normal_flow_target_noalloc(cc_context* ctx, const double* x, int32_t n_verts,
+                                  const int32_t* tris, int32_t n_tris, double beta,
+                                  double alpha, int32_t iters, double* y, void* stream);
+
 /* ---- serving: resident scenes admitted by HBM budget ------------------------
  * A resident scene keeps its topology, masses, current state x and its share of
  * the workspace on the device between steps, so each step starts from the

@@ -124,6 +124,7 @@ def load():
         "cc_scene_release": (C.c_int, [vp, i32]),
         "cc_edges_from_tris_host": (C.c_int, [vp, i32, vp, i32, P(i32)]),
         "cc_normal_flow_target": (C.c_int, [vp, vp, i32, vp, i32, d, d, i32, vp, vp]),
+        "cc_normal_flow_target_noalloc": (C.c_int, [vp, vp, i32, vp, i32, d, d, i32, vp, vp]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -139,4 +140,4 @@ EXPORTED = ["cc_default_params", "cc_strerror", "cc_context_create", "cc_context
             "cc_solver_set_state", "cc_solver_get_P", "cc_solver_get_A", "cc_solver_get_Di",
             "cc_solver_search", "cc_solver_stats", "cc_context_set_budget", "cc_scene_bytes",
             "cc_scene_admit", "cc_scene_submit", "cc_scene_poll", "cc_scene_release",
-            "cc_edges_from_tris_host", "cc_normal_flow_target"]
+            "cc_edges_from_tris_host", "cc_normal_flow_target", "cc_normal_flow_target_noalloc"]

@@ -915,6 +915,9 @@ int cc_context_create(int device, cc_context** out) {
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return CC_EINVAL;
   if (hipSetDevice(device) != hipSuccess) return CC_EHIP;
+  // the no-allocation target's scratch array on this device (its entry point reports
+  // CC_ESTATE if the lookup failed)
+  (void)cc::flow_scratch_init(device);
   cc_context* c = new cc_context();
   c->device = device;
   *out = c;
@@ -937,6 +940,15 @@ int cc_normal_flow_target(cc_context* ctx, const double* x, int32_t n_verts,
   if (hipSetDevice(ctx->device) != hipSuccess) return CC_EHIP;
   return cc::normal_flow_target(ctx, x, n_verts, tris, n_tris, beta, alpha, iters, y,
                                 as_stream(stream));
+}
+
+int cc_normal_flow_target_noalloc(cc_context* ctx, const double* x, int32_t n_verts,
+                                  const int32_t* tris, int32_t n_tris, double beta, double alpha,
+                                  int32_t iters, double* y, void* stream) {
+  if (!ctx) return CC_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return CC_EHIP;
+  return cc::normal_flow_target_static(ctx->device, x, n_verts, tris, n_tris, beta, alpha, iters,
+                                       y, as_stream(stream));
 }
 
 int cc_solver_create(cc_context* ctx, int32_t n, const double* inv_mass, const int32_t* tris,

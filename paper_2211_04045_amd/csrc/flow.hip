@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "geom.hpp"
@@ -194,6 +195,148 @@ int normal_flow_target(cc_context* ctx, const double* x, int32_t n, const int32_
   CC_HIP(hipGetLastError());
   CC_HIP(hipStreamSynchronize(st));  // the host offsets above must outlive their copy
   return CC_OK;
+}
+
+// ---- the target without allocation --------------------------------------------
+// For callers that cannot allocate device memory (HIP graph capture, tight serving
+// loops): the same kernels on a fixed scratch array compiled into the library, one
+// copy per device, sized for kNfStaticVerts vertices and kNfStaticTris triangles.
+// Its address on each device is looked up once, when a context for that device is
+// created, and only that address is handed to kernels and copies.
+
+namespace {
+
+constexpr int32_t kNfStaticVerts = 1 << 17;
+constexpr int32_t kNfStaticTris = 1 << 18;
+constexpr size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t kNfOffCnt = 0;
+constexpr size_t kNfOffCur = kNfOffCnt + al256(sizeof(int32_t) * ((size_t)kNfStaticVerts + 1));
+constexpr size_t kNfOffInc = kNfOffCur + al256(sizeof(int32_t) * (size_t)kNfStaticVerts);
+constexpr size_t kNfOffTmp = kNfOffInc + al256(sizeof(int32_t) * 3 * (size_t)kNfStaticTris);
+constexpr size_t kNfOffErr = kNfOffTmp + al256(sizeof(double) * 3 * (size_t)kNfStaticVerts);
+constexpr size_t kNfScratchBytes = kNfOffErr + 256;
+
+__global__ void k_nf_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Per triangle: a triangle with a vertex outside [0, n) sets the error flag and is
+// left out, so no later kernel reads through its indices.
+__device__ __forceinline__ bool nf_tri_ok(const int32_t* t, int32_t n) {
+  return t[0] >= 0 && t[0] < n && t[1] >= 0 && t[1] < n && t[2] >= 0 && t[2] < n;
+}
+
+__global__ void k_nf_count_tri(const int32_t* __restrict__ tris, int32_t nt, int32_t n,
+                               int32_t* __restrict__ cnt, int32_t* err) {
+  const int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nt) return;
+  const int32_t* t = tris + 3 * (int64_t)f;
+  if (!nf_tri_ok(t, n)) {
+    atomicOr(err, 1);
+    return;
+  }
+  for (int k = 0; k < 3; ++k) atomicAdd(&cnt[t[k] + 1], 1);
+}
+
+__global__ void k_nf_fill_tri(const int32_t* __restrict__ tris, int32_t nt, int32_t n,
+                              int32_t* __restrict__ cur, int32_t* __restrict__ inc) {
+  const int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nt) return;
+  const int32_t* t = tris + 3 * (int64_t)f;
+  if (!nf_tri_ok(t, n)) return;
+  for (int k = 0; k < 3; ++k) inc[atomicAdd(&cur[t[k]], 1)] = f;
+}
+
+// In-place inclusive prefix sum of cnt[0..m) (cnt[0] = 0: the offsets) by one block
+// of kFlowThreads threads, kFlowThreads entries at a time with a running carry; the
+// fill cursors cur[0..m-1) start as a copy of the offsets.
+__global__ void __launch_bounds__(kFlowThreads) k_nf_scan(int32_t* __restrict__ cnt, int32_t m,
+                                                          int32_t* __restrict__ cur) {
+  __shared__ int32_t part[kFlowThreads];
+  int32_t carry = 0;
+  for (int32_t b = 0; b < m; b += kFlowThreads) {
+    const int32_t i = b + (int32_t)threadIdx.x;
+    int32_t v = i < m ? cnt[i] : 0;
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < kFlowThreads; o <<= 1) {
+      const int32_t t = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+      __syncthreads();
+      part[threadIdx.x] += t;
+      __syncthreads();
+    }
+    v = part[threadIdx.x] + carry;
+    if (i < m) {
+      cnt[i] = v;
+      if (i + 1 < m) cur[i] = v;
+    }
+    const int32_t total = part[kFlowThreads - 1];
+    __syncthreads();
+    carry += total;
+  }
+}
+
+}  // namespace
+
+// file-scope device array (about 7 MiB per device, held until the process ends); in
+// host code its name is only a stand-in: kernels and copies get g_scratch[device]
+static __device__ __align__(256) unsigned char scratch[kNfScratchBytes];
+
+static constexpr int kMaxDevices = 64;
+static void* g_scratch[kMaxDevices] = {};  // device address of `scratch` on each device
+static std::mutex g_scratch_mu;
+
+int flow_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return CC_EINVAL;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[device]) return CC_OK;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CC_EHIP;
+  g_scratch[device] = p;
+  return CC_OK;
+}
+
+int normal_flow_target_static(int device, const double* x, int32_t n, const int32_t* tris,
+                              int32_t nt, double beta, double alpha, int32_t iters, double* y,
+                              hipStream_t st) {
+  if (n < 0 || nt < 0 || iters < 0 || (n > 0 && (!x || !y)) || (nt > 0 && !tris)) return CC_EINVAL;
+  if (!std::isfinite(beta) || !std::isfinite(alpha)) return CC_EINVAL;
+  if (n > kNfStaticVerts || nt > kNfStaticTris) return CC_EINVAL;
+  if (n == 0) return CC_OK;
+  void* base = nullptr;
+  if (device >= 0 && device < kMaxDevices) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    base = g_scratch[device];
+  }
+  if (!base) return CC_ESTATE;  // no context was created for this device
+  unsigned char* b = (unsigned char*)base;
+  int32_t* cnt = (int32_t*)(b + kNfOffCnt);
+  int32_t* cur = (int32_t*)(b + kNfOffCur);
+  int32_t* inc = (int32_t*)(b + kNfOffInc);
+  double* tmp = (double*)(b + kNfOffTmp);
+  int32_t* err = (int32_t*)(b + kNfOffErr);
+  // the array keeps the last call's contents: counts and the error flag start at 0
+  k_nf_fill_i32<<<fblk((int64_t)n + 1), kFlowThreads, 0, st>>>(cnt, (int64_t)n + 1, 0);
+  k_nf_fill_i32<<<1, kFlowThreads, 0, st>>>(err, 1, 0);
+  if (nt > 0) k_nf_count_tri<<<fblk(nt), kFlowThreads, 0, st>>>(tris, nt, n, cnt, err);
+  k_nf_scan<<<1, kFlowThreads, 0, st>>>(cnt, n + 1, cur);
+  if (nt > 0) {
+    k_nf_fill_tri<<<fblk(nt), kFlowThreads, 0, st>>>(tris, nt, n, cur, inc);
+    k_nf_sort<<<fblk(n), kFlowThreads, 0, st>>>(cnt, n, inc);
+  }
+  double* a = (iters % 2 == 0) ? y : tmp;
+  double* c = (iters % 2 == 0) ? tmp : y;
+  k_nf_offset<<<fblk(n), kFlowThreads, 0, st>>>(x, tris, cnt, inc, n, beta, a);
+  for (int32_t it = 0; it < iters; ++it) {
+    k_nf_smooth<<<fblk(n), kFlowThreads, 0, st>>>(a, tris, cnt, inc, n, alpha, c);
+    std::swap(a, c);
+  }
+  CC_HIP(hipGetLastError());
+  int32_t herr = 0;
+  CC_HIP(hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  CC_HIP(hipStreamSynchronize(st));
+  return herr ? CC_EINVAL : CC_OK;
 }
 
 }  // namespace cc

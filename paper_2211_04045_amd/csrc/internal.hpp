@@ -305,6 +305,12 @@ int normal_flow_target(cc_context* ctx, const double* x, int32_t n, const int32_
                        int32_t nt, double beta, double alpha, int32_t iters, double* y,
                        hipStream_t st);
 void flow_free(FlowWork* w);
+// The normal-flow target on the library's fixed scratch array (no allocation);
+// flow_scratch_init looks up that array's address on `device` (current) once.
+int flow_scratch_init(int device);
+int normal_flow_target_static(int device, const double* x, int32_t n, const int32_t* tris,
+                              int32_t nt, double beta, double alpha, int32_t iters, double* y,
+                              hipStream_t st);
 int launch_setup(cc_solver* s, int32_t seg, const double* x_prev, const double* x_tilde,
                  hipStream_t st);
 int launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t st);
