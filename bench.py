@@ -39,10 +39,11 @@ WORKLOADS = {
 
 
 def ablation(reps: int):
-    """The backward-step ablations of Sec. 4.3.1 and Sec. 4.3.2 on the workloads that
+    """The ablations of Sec. 4.3.1, Sec. 4.3.2 and Sec. 5.1 on the workloads that
     converge (folded cloth, particle pile): Gauss-Seidel with 1, 2 and 4 sweeps,
-    projected Jacobi with omega 0.5 and 1.0. One JSON line per run: iterations to
-    the stop test and time per step (HIP events, `reps` calls after one untimed)."""
+    projected Jacobi with omega 0.5 and 1.0, and the CCD-based step-size scheme in
+    place of the CCD-free forward step. One JSON line per run: iterations to the stop
+    test and time per step (HIP events, `reps` calls after one untimed)."""
     import torch
 
     import paper_2211_04045_amd as cc
@@ -51,7 +52,9 @@ def ablation(reps: int):
     ctx = cc.Context(0)
     variants = [dict(backward="gs", gs_sweeps=1), dict(backward="gs", gs_sweeps=2),
                 dict(backward="gs", gs_sweeps=4), dict(backward="jacobi", omega=0.5),
-                dict(backward="jacobi", omega=1.0)]
+                dict(backward="jacobi", omega=1.0),
+                # the CCD-based step-size scheme Sec. 5.1 compares the method with
+                dict(backward="gs", gs_sweeps=1, ccd_step=True)]
     for cfg in (2, 6):
         sc = scenes.config(cfg)
         dev = "cuda"
@@ -77,7 +80,9 @@ def ablation(reps: int):
                               "iterations_per_step": st["iters"], "status": st["status"],
                               "ms_per_step": round(float(np.median(ms)), 3),
                               "row_updates_per_step": st["row_updates"],
-                              "max_colors_used": st["max_colors_used"]}), flush=True)
+                              "max_colors_used": st["max_colors_used"],
+                              "continuous_tests_per_step": st["ccd_fail"],
+                              "scaled_steps_per_step": st["n_scaled"]}), flush=True)
 
 
 def latency_table(reps: int, small: bool, budget_s: float):
@@ -149,6 +154,9 @@ def main():
                     help="FP32 backward step (sets, distances, x and CCD stay FP64)")
     ap.add_argument("--jacobi", action="store_true",
                     help="projected Jacobi backward step (Sec. 4.3.2) instead of Gauss-Seidel")
+    ap.add_argument("--ccd-step", action="store_true",
+                    help="the CCD-based step-size scheme of Sec. 5.1 instead of the CCD-free "
+                         "forward step")
     ap.add_argument("--max-iters", type=int, default=0,
                     help="override the workload's iteration cap L (0: the workload's own)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -212,6 +220,8 @@ def main():
         prm["mixed"] = True
     if args.jacobi:
         prm["backward"] = "jacobi"
+    if args.ccd_step:
+        prm["ccd_step"] = True
     dev = "cuda"
     x = torch.as_tensor(sc["x"], device=dev)
     w = torch.as_tensor(sc["w"], device=dev)
@@ -335,7 +345,8 @@ def main():
         "config": {"workload": sc["name"] + " (" + WORKLOADS.get(args.config, "") +
                                ("FP32 backward step, FP64 sets, x and CCD" if args.mixed
                                 else "FP64") +
-                               (", projected Jacobi backward step" if args.jacobi else "") + ")",
+                               (", projected Jacobi backward step" if args.jacobi else "") +
+                               (", CCD-based step sizes" if args.ccd_step else "") + ")",
                    "verts": int(len(sc["x"])), "tris": int(len(sc["tris"])),
                    "edges": int(len(sc["edges"])), "iterations_per_step": iters,
                    "parallelism": "single GPU"},
@@ -347,6 +358,7 @@ def main():
         "roofline": roofline,
         "kernels_ms_per_step": {k: round(v["ms"] / fam_steps, 3) for k, v in kern.items()},
         "family_rooflines": families,
+        "autotune": cc.autotune_table(),
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -50,7 +50,8 @@ enum {
                         repeated index in a primitive, NaN/Inf position, invalid
                         parameter (d_min < delta, d_max <= d_min, gamma not in (0,1),
                         sigma < 1, eps <= 0, max_iters < 1, gs_sweeps < 1, omega not in
-                        (0,1], unknown backward solver, CC_JACOBI with CC_MIXED,
+                        (0,1], unknown backward solver, CC_JACOBI or CC_CCD_STEP
+                        with CC_MIXED,
                         CC_TIME_ONE with time_kind outside 0..CC_K_COUNT-1) */
   CC_ENOMEM = -2,    /* device allocation failed */
   CC_EOVERFLOW = -3, /* pair capacity exceeded after regrowth */
@@ -85,10 +86,25 @@ enum { CC_CONVERGED = 0, CC_MAXITER = 1 };
                                Jacobians, multipliers and y - x) in FP32; every set
                                decision, distance, D_i, x, the forward step and the
                                continuous test stay FP64 */
+#define CC_CCD_STEP 256u    /* the CCD-based step-size scheme that Sec. 5.1 compares the
+                               method with (the paper gives no rule; this one): every vertex
+                               takes alpha = min(1, 0.5 gamma D^(l) / |y - x|) (the global
+                               bound alone, so pairs outside P' cannot meet), then each pair
+                               of P' the motion bound does not certify takes the continuous
+                               test, and a contact at time t* of its piece scales the steps
+                               of its four vertices by gamma t* (a vertex takes the smallest
+                               factor; r follows the new alpha); up to 16 such passes while
+                               they find contacts, then the certificate's send-back. Not
+                               with CC_MIXED */
 #define CC_UNGUARDED 128u   /* the forward step exactly as Eq. eq:forward2, without the
                                check of the rounded move (below): the certificate and its
                                response are then the only guard. A test of the
                                certificate; not for production use */
+
+#define CC_NO_AUTOTUNE 512u /* launch shapes at their defaults; without this flag the
+                               autotuner measures the variants of a kernel's launch shape
+                               the first time a (device, size class) meets it and keeps the
+                               fastest for the process (results do not depend on it) */
 
 /* Parameters; defaults are Table 2 of the paper (cc_default_params). */
 typedef struct cc_params {
@@ -103,7 +119,8 @@ typedef struct cc_params {
   int32_t gs_sweeps; /* Gauss-Seidel sweeps per backward step, 1 (Sec. 4.3.1) */
   int32_t max_colors;/* colour palette, <= 1024 */
   uint32_t flags;    /* CC_EDGE_LEN | CC_TIME_KERNELS | CC_TIME_ONE | CC_TRACE | CC_MIXED |
-                        CC_VALIDATE_INPUT | CC_CCD_ALL | CC_UNGUARDED */
+                        CC_VALIDATE_INPUT | CC_CCD_ALL | CC_UNGUARDED | CC_CCD_STEP |
+                        CC_NO_AUTOTUNE */
   uint64_t seed;     /* colouring priority seed */
   double omega;      /* CC_JACOBI: under-relaxation factor in (0, 1] (Sec. 4.3.2 names the
                         factor but gives no value; default 0.5) */
@@ -135,6 +152,7 @@ typedef struct cc_iter_info {
   int64_t ccd_hits;  /* of those, pairs the continuous test does not clear (it finds
                         them within eta = 1e-12 m along the piece) */
   int64_t n_back;    /* vertices the certificate sent back to x^(l) */
+  int64_t n_scaled;  /* CC_CCD_STEP: vertex steps scaled by a contact */
   double d_before;
   double d_after;
   double move_max;
@@ -163,6 +181,7 @@ typedef struct cc_stats {
   int64_t ccd_fail;
   int64_t ccd_hits;
   int64_t n_back;
+  int64_t n_scaled;
   double r_inf;
   double kernel_ms[CC_K_COUNT];        /* with CC_TIME_KERNELS (CC_TIME_ONE: that family) */
   int64_t kernel_launches[CC_K_COUNT];
@@ -171,6 +190,26 @@ typedef struct cc_stats {
 
 typedef struct cc_context cc_context;
 typedef struct cc_solver cc_solver;
+
+/* ---- autotuner ---------------------------------------------------------------
+ * Kernels whose launch shape is tuned, and the record of one tuning: the device,
+ * the kernel, its size class (CC_TUNE_TRAVERSE: 4 floor(log2(queries)) + the
+ * dominant query class, 0 vertex-triangle, 1 edge-edge, 2 vertex-vertex), the
+ * choice (lanes per traversal group: 8, 16 or 32) and the measured time of each
+ * variant in milliseconds (in the order 8, 16, 32). */
+enum { CC_TUNE_TRAVERSE = 0 };
+typedef struct cc_tune_entry {
+  int32_t device, kernel, size_class, choice;
+  float ms[4];
+} cc_tune_entry;
+/* The process-wide tuning table (HOST array out_host, cap entries): *n gets the
+ * number of entries; nothing is written when cap is smaller. */
+int cc_autotune_entries(cc_tune_entry* out_host, int32_t cap, int32_t* n);
+/* Forget every tuning (the next launches measure again). */
+void cc_autotune_reset(void);
+/* Force a choice for every later launch of the kernel in this process (CC_TUNE_TRAVERSE:
+ * 8, 16 or 32 lanes per group; 0 returns to the tuned choices); CC_EINVAL otherwise. */
+int cc_autotune_force(int32_t kernel, int32_t choice);
 
 void cc_default_params(cc_params* p);
 const char* cc_strerror(int code);

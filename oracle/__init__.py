@@ -20,7 +20,7 @@ KEY_VV = 1 << 62
 # Table 2 defaults (L depends on the time step; the scene may override)
 DEFAULTS = dict(delta=1e-3, d_min=2e-3, d_max=4e-3, sigma=1.1, gamma=0.9, eps=1e-4,
                 kappa=1e-3, max_iters=512, gs_sweeps=1, max_colors=1024, edge_len=1,
-                seed=0x2211_04045, omega=0.5, backward=0, ccd_all=0, unguarded=0)
+                seed=0x2211_04045, omega=0.5, backward=0, ccd_all=0, unguarded=0, ccd_step=0)
 
 
 class Params(C.Structure):
@@ -30,13 +30,14 @@ class Params(C.Structure):
                 ("gs_sweeps", C.c_int32), ("max_colors", C.c_int32),
                 ("edge_len", C.c_int32), ("seed", C.c_uint64), ("omega", C.c_double),
                 ("backward", C.c_int32), ("ccd_all", C.c_int32),
-                ("unguarded", C.c_int32)]
+                ("unguarded", C.c_int32), ("ccd_step", C.c_int32)]
 
 
 class Iter(C.Structure):
     _fields_ = [("searched", C.c_int32), ("n_colors", C.c_int32), ("n_p", C.c_int64),
                 ("n_pf", C.c_int64), ("n_a", C.c_int64), ("ccd_fail", C.c_int64),
-                ("ccd_hits", C.c_int64), ("n_back", C.c_int64), ("d_before", C.c_double), ("d_after", C.c_double),
+                ("ccd_hits", C.c_int64), ("n_back", C.c_int64), ("n_scaled", C.c_int64),
+                ("d_before", C.c_double), ("d_after", C.c_double),
                 ("move_max", C.c_double), ("r_inf", C.c_double),
                 ("fp_pf", C.c_uint64), ("fp_a", C.c_uint64), ("fp_col", C.c_uint64)]
 

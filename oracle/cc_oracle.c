@@ -58,6 +58,8 @@
 /* eta: primitives closer than eta (metres) count as touching. Binary64 distances of
  * scenes whose coordinates stay within +-10 m are exact to far better than eta. */
 #define ORC_ETA 1e-12
+/* CCD-based step (Sec. 5.1): passes that scale steps before contacts send back */
+#define ORC_STEP_PASSES 16
 
 struct orc_scene {
   int32_t n, nt, ne;
@@ -71,6 +73,8 @@ struct orc_scene {
   /* state */
   double *x, *y, *xt, *r, *xold, *rold;
   uint8_t* back; /* certificate: vertex returned to x^(l) in this iteration */
+  double* alpha; /* the forward step's alpha of each vertex */
+  double* scale; /* CCD-based step: factor of a vertex's step from the pass's contacts */
   double D;
   uint64_t* P;
   int64_t nP, capP;
@@ -1155,6 +1159,8 @@ orc_scene* orc_create(int32_t n, const double* w, const int32_t* tris, int32_t n
   s->r = (double*)malloc(N * sizeof(double));
   s->rold = (double*)malloc(N * sizeof(double));
   s->back = (uint8_t*)malloc(N);
+  s->alpha = (double*)malloc(N * sizeof(double));
+  s->scale = (double*)malloc(N * sizeof(double));
   s->Di = (double*)malloc(N * sizeof(double));
   s->move2 = (double*)malloc(N * sizeof(double));
   s->er_e = (int32_t*)malloc((size_t)(ne > 0 ? ne : 1) * sizeof(int32_t));
@@ -1174,7 +1180,7 @@ void orc_destroy(orc_scene* s) {
   if (!s) return;
   free(s->w); free(s->tris); free(s->edges); free(s->part); free(s->stat);
   free(s->x); free(s->y); free(s->xt); free(s->xold); free(s->r); free(s->rold);
-  free(s->back);
+  free(s->back); free(s->alpha); free(s->scale);
   free(s->Di); free(s->move2); free(s->P); free(s->A); free(s->acol);
   free(s->er_e); free(s->er_v); free(s->er_g); free(s->er_inv); free(s->er_col);
   free(s);
@@ -1440,12 +1446,15 @@ int orc_iterate(orc_scene* s, orc_iter* info) {
   for (int32_t i = 0; i < s->n; ++i) {
     double* xi = s->x + 3 * i;
     const double* yi = s->y + 3 * i;
+    /* the CCD-based scheme bounds every vertex by D^(l) alone (the pairs it cannot
+     * meet in one step); its contacts along P' are found afterwards */
+    const double bound = p->ccd_step ? D : s->Di[i];
     double dx[3];
     sub3(dx, yi, xi);
     double n2 = dot3(dx, dx);
     double alpha = 1.0;
     if (n2 > 0.0) {
-      double a = (hg * s->Di[i]) / sqrt(n2);
+      double a = (hg * bound) / sqrt(n2);
       if (a < 1.0) alpha = a;
     }
     double xn[3];
@@ -1465,7 +1474,7 @@ int orc_iterate(orc_scene* s, orc_iter* info) {
      * 2 |x_new - x| < D_i - eta, eta = ORC_ETA covering the rounding of the
      * distances; otherwise it stays (alpha = 0). In exact arithmetic with
      * gamma < 1 the test fails only when D_i <= eta / (1 - gamma). */
-    const double sb = s->Di[i] - ORC_ETA;
+    const double sb = bound - ORC_ETA;
     if (!p->unguarded && !(sb > 0.0 && 4.0 * m2 < sb * sb)) {
       xn[0] = xi[0];
       xn[1] = xi[1];
@@ -1474,6 +1483,7 @@ int orc_iterate(orc_scene* s, orc_iter* info) {
       alpha = 0.0;
     }
     s->move2[i] = m2;
+    s->alpha[i] = alpha;
     double mvn = sqrt(m2);
     if (mvn > mmax) mmax = mvn;
     xi[0] = xn[0];
@@ -1489,10 +1499,17 @@ int orc_iterate(orc_scene* s, orc_iter* info) {
    * r unchanged). That changes the piece of every pair sharing those vertices, so
    * the pass repeats until it returns no new vertex (the returned set only grows).
    * With ccd_all every pair takes the continuous test in every pass; a pair the
-   * motion bound certifies is never sent back. */
-  int64_t fail = 0, hits = 0, nback = 0;
+   * motion bound certifies is never sent back.
+   * The CCD-based scheme of Sec. 5.1 (ccd_step) answers its first ORC_STEP_PASSES
+   * passes differently: a pair in contact at time t* of its piece scales the steps
+   * of its moving vertices by gamma t* (a vertex takes the smallest factor of its pairs;
+   * alpha <- alpha factor, x <- x^(l) + alpha (y - x^(l)), r <- r^(l) (1 - alpha)),
+   * and the passes go on while they find contacts. */
+  int64_t fail = 0, hits = 0, nback = 0, nscaled = 0;
   memset(s->back, 0, (size_t)s->n);
-  for (;;) {
+  for (int32_t i = 0; i < s->n; ++i) s->scale[i] = 1.0;
+  for (int pass = 0;; ++pass) {
+    const int scaling = p->ccd_step && pass < ORC_STEP_PASSES;
     int64_t newly = 0;
     for (int64_t q = 0; q < npf; ++q) {
       int32_t v[4];
@@ -1511,16 +1528,43 @@ int orc_iterate(orc_scene* s, orc_iter* info) {
           dq[3 * k + m] = s->x[3 * v[k] + m] - s->xold[3 * v[k] + m];
         }
       const int kind = (s->P[q] & KEY_VV) ? 2 : ((s->P[q] & KEY_EE) ? 1 : 0);
-      if (!orc_ccd_hit(qq, dq, kind, ORC_ETA, NULL)) continue;
+      double th = 0.0;
+      if (!orc_ccd_hit(qq, dq, kind, ORC_ETA, &th)) continue;
       ++hits;
       if (bound_ok) continue;
-      for (int k = 0; k < nv; ++k)
-        if (!s->back[v[k]]) {
-          s->back[v[k]] = 2;
-          ++newly;
-        }
+      if (scaling) {
+        const double f = p->gamma * th;
+        for (int k = 0; k < nv; ++k)
+          if (f < s->scale[v[k]]) s->scale[v[k]] = f;
+        ++newly;
+      } else {
+        for (int k = 0; k < nv; ++k)
+          if (!s->back[v[k]]) {
+            s->back[v[k]] = 2;
+            ++newly;
+          }
+      }
     }
     if (newly == 0) break;
+    if (scaling) {
+      for (int32_t i = 0; i < s->n; ++i) {
+        if (!(s->scale[i] < 1.0)) continue;
+        const double a = s->alpha[i] * s->scale[i];
+        s->scale[i] = 1.0;
+        if (s->move2[i] == 0.0) continue; /* no step to scale */
+        s->alpha[i] = a;
+        double* xi = s->x + 3 * i;
+        const double *x0 = s->xold + 3 * i, *yi = s->y + 3 * i;
+        double dx[3], mvv[3];
+        sub3(dx, yi, x0);
+        for (int m = 0; m < 3; ++m) xi[m] = x0[m] + a * dx[m];
+        sub3(mvv, xi, x0);
+        s->move2[i] = dot3(mvv, mvv);
+        s->r[i] = s->rold[i] * (1.0 - a);
+        ++nscaled;
+      }
+      continue;
+    }
     nback += newly;
     for (int32_t i = 0; i < s->n; ++i) {
       if (s->back[i] != 2) continue;
@@ -1533,6 +1577,7 @@ int orc_iterate(orc_scene* s, orc_iter* info) {
   it.ccd_fail = fail;
   it.ccd_hits = hits;
   it.n_back = nback;
+  it.n_scaled = nscaled;
   double rinf = 0.0;
   for (int32_t i = 0; i < s->n; ++i)
     if (s->r[i] > rinf) rinf = s->r[i];

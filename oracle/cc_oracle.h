@@ -46,6 +46,9 @@ typedef struct orc_params {
   int32_t unguarded; /* 1: the forward step exactly as Eq. eq:forward2, without the
                         check of the rounded move; the certificate is then the only
                         guard (a test of the certificate's response) */
+  int32_t ccd_step;  /* 1: the CCD-based step-size scheme that Sec. 5.1 compares with:
+                        every vertex bounded by D^(l) only, then contacts found by the
+                        continuous test along P' scale the steps */
 } orc_params;
 
 typedef struct orc_iter {
@@ -59,6 +62,7 @@ typedef struct orc_iter {
                             the certificate's passes) */
   int64_t ccd_hits;      /* pairs the continuous test does not clear (all passes) */
   int64_t n_back;        /* vertices the certificate returned to x^(l) */
+  int64_t n_scaled;      /* CCD-based step: vertex steps scaled by a contact */
   double d_before;       /* D^(l) used by the pair pass */
   double d_after;        /* D^(l+1) */
   double move_max;       /* max_i ||x_i^(l+1) - x_i^(l)|| */

@@ -12,13 +12,13 @@ import ctypes as C
 
 from . import _lib
 from ._lib import (CC_CCD_ALL, CC_EDGE_LEN, CC_MIXED, CC_TIME_KERNELS, CC_TIME_ONE, CC_TRACE,
-                   CC_UNGUARDED, CC_VALIDATE_INPUT, CCError, IterInfo, Params, SceneDesc,
-                   Stats)
+                   CC_CCD_STEP, CC_UNGUARDED, CC_VALIDATE_INPUT, CCError, IterInfo, Params,
+                   SceneDesc, Stats)
 
 __all__ = ["Context", "Solver", "Server", "collide_step", "collide_step_batched", "params",
            "edges_from_tris", "normal_flow_target", "CC_EDGE_LEN", "CC_TIME_KERNELS",
            "CC_TIME_ONE", "CC_TRACE", "CC_MIXED", "CC_VALIDATE_INPUT", "CC_CCD_ALL",
-           "CC_UNGUARDED", "CCError"]
+           "CC_UNGUARDED", "CC_CCD_STEP", "CCError"]
 
 
 def _torch():
@@ -54,8 +54,8 @@ def _ptr(t):
 
 def params(**over) -> Params:
     """Defaults of Table 2 (cc_default_params) with keyword overrides; the flags
-    are set with edge_len=, time_kernels=, trace=, mixed=, validate=, ccd_all= and
-    unguarded= (booleans) and time_one= (a family name of K_NAMES: that family alone
+    are set with edge_len=, time_kernels=, trace=, mixed=, validate=, ccd_all=,
+    unguarded= and ccd_step= (booleans) and time_one= (a family name of K_NAMES: that family alone
     is timed);
     backward= takes "gs" (default) or "jacobi"."""
     p = Params()
@@ -77,6 +77,10 @@ def params(**over) -> Params:
             p.flags = (p.flags | CC_MIXED) if v else (p.flags & ~CC_MIXED)
         elif k == "ccd_all":
             p.flags = (p.flags | CC_CCD_ALL) if v else (p.flags & ~CC_CCD_ALL)
+        elif k == "autotune":
+            p.flags = (p.flags & ~_lib.CC_NO_AUTOTUNE) if v else (p.flags | _lib.CC_NO_AUTOTUNE)
+        elif k == "ccd_step":
+            p.flags = (p.flags | CC_CCD_STEP) if v else (p.flags & ~CC_CCD_STEP)
         elif k == "unguarded":
             p.flags = (p.flags | CC_UNGUARDED) if v else (p.flags & ~CC_UNGUARDED)
         elif k == "validate":
@@ -100,6 +104,20 @@ def normal_flow_target(ctx: "Context", x, tris, beta: float, alpha: float, iters
                                          float(beta), float(alpha), int(iters), _ptr(y),
                                          _stream()), "cc_normal_flow_target")
     return y
+
+
+def autotune_table():
+    """The process-wide autotuner table: one dict per tuned (device, kernel, size
+    class) with the choice and the measured time of each variant (ms)."""
+    lib = _lib.load()
+    n = C.c_int32()
+    _check(lib.cc_autotune_entries(None, 0, C.byref(n)), "cc_autotune_entries")
+    rows = (_lib.TuneEntry * max(n.value, 1))()
+    _check(lib.cc_autotune_entries(rows, n.value, C.byref(n)), "cc_autotune_entries")
+    names = {0: "traverse"}
+    return [dict(device=r.device, kernel=names.get(r.kernel, r.kernel), size_class=r.size_class,
+                 choice=r.choice, ms=[round(float(v), 4) for v in r.ms[:3]])
+            for r in rows[:n.value]]
 
 
 def edges_from_tris(tris):

@@ -21,6 +21,8 @@ CC_VALIDATE_INPUT = 16
 CC_CCD_ALL = 32
 CC_TIME_ONE = 64
 CC_UNGUARDED = 128
+CC_CCD_STEP = 256
+CC_NO_AUTOTUNE = 512
 CC_GAUSS_SEIDEL = 0
 CC_JACOBI = 1
 K_NAMES = ["search", "pair", "color", "gs", "forward", "cert"]
@@ -52,7 +54,8 @@ class Params(C.Structure):
 class IterInfo(C.Structure):
     _fields_ = [("searched", C.c_int32), ("n_colors", C.c_int32), ("n_p", C.c_int64),
                 ("n_pf", C.c_int64), ("n_a", C.c_int64), ("ccd_fail", C.c_int64),
-                ("ccd_hits", C.c_int64), ("n_back", C.c_int64), ("d_before", C.c_double),
+                ("ccd_hits", C.c_int64), ("n_back", C.c_int64), ("n_scaled", C.c_int64),
+                ("d_before", C.c_double),
                 ("d_after", C.c_double), ("move_max", C.c_double),
                 ("r_inf", C.c_double), ("fp_pf", C.c_uint64), ("fp_a", C.c_uint64),
                 ("fp_col", C.c_uint64)]
@@ -67,16 +70,21 @@ class SceneDesc(C.Structure):
                 ("edges", C.c_void_p), ("n_edges", C.c_int32), ("x_next", C.c_void_p)]
 
 
+class TuneEntry(C.Structure):
+    _fields_ = [("device", C.c_int32), ("kernel", C.c_int32), ("size_class", C.c_int32),
+                ("choice", C.c_int32), ("ms", C.c_float * 4)]
+
+
 class Stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("searches", C.c_int32), ("status", C.c_int32),
                 ("max_colors_used", C.c_int32), ("pair_updates", C.c_int64),
                 ("row_updates", C.c_int64), ("ccd_fail", C.c_int64), ("ccd_hits", C.c_int64),
-                ("n_back", C.c_int64), ("r_inf", C.c_double),
+                ("n_back", C.c_int64), ("n_scaled", C.c_int64), ("r_inf", C.c_double),
                 ("kernel_ms", C.c_double * 6), ("kernel_launches", C.c_int64 * 6),
                 ("kernel_bytes", C.c_double * 6)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_[:10]}
+        d = {k: getattr(self, k) for k, _ in self._fields_[:11]}
         d["kernels"] = {K_NAMES[i]: dict(ms=self.kernel_ms[i], launches=self.kernel_launches[i],
                                          bytes=self.kernel_bytes[i]) for i in range(6)}
         return d
@@ -125,6 +133,9 @@ def load():
         "cc_edges_from_tris_host": (C.c_int, [vp, i32, vp, i32, P(i32)]),
         "cc_normal_flow_target": (C.c_int, [vp, vp, i32, vp, i32, d, d, i32, vp, vp]),
         "cc_normal_flow_target_noalloc": (C.c_int, [vp, vp, i32, vp, i32, d, d, i32, vp, vp]),
+        "cc_autotune_entries": (C.c_int, [P(TuneEntry), i32, P(i32)]),
+        "cc_autotune_reset": (None, []),
+        "cc_autotune_force": (C.c_int, [i32, i32]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -140,4 +151,5 @@ EXPORTED = ["cc_default_params", "cc_strerror", "cc_context_create", "cc_context
             "cc_solver_set_state", "cc_solver_get_P", "cc_solver_get_A", "cc_solver_get_Di",
             "cc_solver_search", "cc_solver_stats", "cc_context_set_budget", "cc_scene_bytes",
             "cc_scene_admit", "cc_scene_submit", "cc_scene_poll", "cc_scene_release",
-            "cc_edges_from_tris_host", "cc_normal_flow_target", "cc_normal_flow_target_noalloc"]
+            "cc_edges_from_tris_host", "cc_normal_flow_target", "cc_normal_flow_target_noalloc",
+            "cc_autotune_entries", "cc_autotune_reset", "cc_autotune_force"]

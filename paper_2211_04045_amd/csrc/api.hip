@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <atomic>
 #include <climits>
+#include <mutex>
 #include <thread>
 
 #include "internal.hpp"
@@ -73,7 +74,38 @@ int check_params(const cc_params* p) {
   if ((p->flags & CC_TIME_ONE) && (p->time_kind < 0 || p->time_kind >= CC_K_COUNT)) return CC_EINVAL;
   if (p->backward == CC_JACOBI && (!(p->omega > 0.0 && p->omega <= 1.0) || (p->flags & CC_MIXED)))
     return CC_EINVAL;
+  if ((p->flags & CC_CCD_STEP) && (p->flags & CC_MIXED)) return CC_EINVAL;
   return CC_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+
+// Launch shapes measured on the first launch of a (device, kernel, size class) and
+// kept for the process: every variant computes the same result, so the choice only
+// changes the time. Process-wide, shared by every context.
+namespace {
+std::mutex g_tune_mu;
+std::vector<cc_tune_entry> g_tune;
+int g_tune_force[1] = {0};  // per kernel: a forced choice (0: none)
+}  // namespace
+
+int tune_lookup(int device, int kernel, int32_t size_class) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (kernel >= 0 && kernel < 1 && g_tune_force[kernel] > 0) return g_tune_force[kernel];
+  for (const cc_tune_entry& e : g_tune)
+    if (e.device == device && e.kernel == kernel && e.size_class == size_class) return e.choice;
+  return -1;
+}
+
+void tune_store(int device, int kernel, int32_t size_class, int choice, const float ms[4]) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  cc_tune_entry e{};
+  e.device = device;
+  e.kernel = kernel;
+  e.size_class = size_class;
+  e.choice = choice;
+  for (int i = 0; i < 4; ++i) e.ms[i] = ms[i];
+  g_tune.push_back(e);
 }
 
 // ---------------------------------------------------------------- ranges
@@ -161,7 +193,7 @@ int alloc_active(cc_solver* s, int64_t cap) {
 
 void free_vertex_arrays(cc_solver* s) {
   dfree(s->w); dfree(s->stat); dfree(s->x); dfree(s->y); dfree(s->xt); dfree(s->xold);
-  dfree(s->rold); dfree(s->dyold); dfree(s->back);
+  dfree(s->rold); dfree(s->dyold); dfree(s->back); dfree(s->alph); dfree(s->scale);
   dfree(s->r); dfree(s->move2); dfree(s->mvd); dfree(s->Di); dfree(s->vseg); dfree(s->plist); dfree(s->dy);
   dfree(s->jacc);
   dfree(s->vmax0); dfree(s->claims); dfree(s->masks); dfree(s->vloc);
@@ -220,7 +252,10 @@ int resize_arrays(cc_solver* s, int32_t capV, int32_t capF, int32_t capE, hipStr
     CC_TRY(launch_fill_i32(s->vseg + oV, capV - oV, -1, st));
     CC_TRY(dregrow(&s->plist, capV, oV, st));
     dfree(s->xold); dfree(s->move2); dfree(s->Di); dfree(s->vmax0); dfree(s->claims); dfree(s->masks);
-    dfree(s->rold); dfree(s->dyold); dfree(s->back);
+    dfree(s->rold); dfree(s->dyold); dfree(s->back); dfree(s->alph); dfree(s->scale);
+    CC_TRY(dalloc(&s->alph, capV));
+    CC_TRY(dalloc(&s->scale, capV));
+    CC_TRY(launch_fill_u64(s->scale, capV, kOneBits, st));
     CC_TRY(dalloc(&s->rold, capV));
     CC_TRY(dalloc(&s->dyold, 3 * (int64_t)capV));
     CC_TRY(dalloc(&s->back, capV));
@@ -714,8 +749,9 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
   timer_begin(s, CC_K_FORWARD, st);
   CC_TRY(launch_forward(s, st));
   timer_end(s, st);
+  const bool ccd_step = (p.flags & CC_CCD_STEP) != 0;
   timer_begin(s, CC_K_CERT, st);
-  CC_TRY(launch_cert(s, st));
+  CC_TRY(launch_cert(s, ccd_step, st));
   timer_end(s, st);
   CC_HIP(hipMemcpyAsync(s->seg_host, s->seg_dev, sizeof(SegDev) * ns, hipMemcpyDeviceToHost, st));
   const bool small = s->col_small;
@@ -724,15 +760,25 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
   CC_HIP(hipStreamSynchronize(st));
   // vertices of pieces the certificate did not clear go back to x^(l); that changes
   // the pieces of the pairs sharing them, so the certificate runs again until it
-  // sends no new vertex back (the returned set only grows)
-  for (unsigned long long nb_seen = 0;;) {
-    unsigned long long nb = 0;
-    for (int32_t sg : act) nb += s->seg_host[sg].nback;
-    if (nb == nb_seen) break;
+  // sends no new vertex back (the returned set only grows). The CCD-based step
+  // answers its first kStepPasses passes by scaling the steps instead, as long as
+  // they find contacts.
+  unsigned long long nb_seen = 0, ns_seen = 0;
+  for (int pass = 0;; ++pass) {
+    const bool scaling = ccd_step && pass < kStepPasses;
+    unsigned long long nb = 0, nstep = 0;
+    for (int32_t sg : act) {
+      nb += s->seg_host[sg].nback;
+      nstep += s->seg_host[sg].nstep;
+    }
+    const bool more = scaling ? nstep != ns_seen : nb != nb_seen;
+    if (!more) break;
     nb_seen = nb;
+    ns_seen = nstep;
+    const bool next_scaling = ccd_step && pass + 1 < kStepPasses;
     timer_begin(s, CC_K_CERT, st);
-    CC_TRY(launch_send_back(s, ns, st));
-    CC_TRY(launch_cert(s, st));
+    CC_TRY(launch_send_back(s, ns, scaling, st));
+    CC_TRY(launch_cert(s, next_scaling, st));
     timer_end(s, st);
     CC_HIP(hipMemcpyAsync(s->seg_host, s->seg_dev, sizeof(SegDev) * ns, hipMemcpyDeviceToHost,
                           st));
@@ -762,6 +808,7 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
     it.ccd_fail = (int64_t)d.fail;
     it.ccd_hits = (int64_t)d.hits;
     it.n_back = (int64_t)d.nback;
+    it.n_scaled = (int64_t)d.nscaled;
     it.fp_pf = fp_pf;
     it.fp_a = fp_a;
     it.fp_col = trace ? s->hc->fp_col : 0;
@@ -773,6 +820,7 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
     g.st.ccd_fail += it.ccd_fail;
     g.st.ccd_hits += it.ccd_hits;
     g.st.n_back += it.n_back;
+    g.st.n_scaled += it.n_scaled;
     g.st.r_inf = rinf;
     if (s->n_colors > g.st.max_colors_used) g.st.max_colors_used = s->n_colors;
     if (rinf < p.eps) {
@@ -949,6 +997,28 @@ int cc_normal_flow_target_noalloc(cc_context* ctx, const double* x, int32_t n_ve
   if (hipSetDevice(ctx->device) != hipSuccess) return CC_EHIP;
   return cc::normal_flow_target_static(ctx->device, x, n_verts, tris, n_tris, beta, alpha, iters,
                                        y, as_stream(stream));
+}
+
+int cc_autotune_entries(cc_tune_entry* out_host, int32_t cap, int32_t* n) {
+  if (!n || cap < 0 || (cap > 0 && !out_host)) return CC_EINVAL;
+  std::lock_guard<std::mutex> lk(cc::g_tune_mu);
+  *n = (int32_t)cc::g_tune.size();
+  if (cap >= *n)
+    for (int32_t i = 0; i < *n; ++i) out_host[i] = cc::g_tune[(size_t)i];
+  return CC_OK;
+}
+
+void cc_autotune_reset(void) {
+  std::lock_guard<std::mutex> lk(cc::g_tune_mu);
+  cc::g_tune.clear();
+}
+
+int cc_autotune_force(int32_t kernel, int32_t choice) {
+  if (kernel != CC_TUNE_TRAVERSE) return CC_EINVAL;
+  if (choice != 0 && choice != 8 && choice != 16 && choice != 32) return CC_EINVAL;
+  std::lock_guard<std::mutex> lk(cc::g_tune_mu);
+  cc::g_tune_force[kernel] = choice;
+  return CC_OK;
 }
 
 int cc_solver_create(cc_context* ctx, int32_t n, const double* inv_mass, const int32_t* tris,

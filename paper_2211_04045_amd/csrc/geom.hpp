@@ -341,7 +341,8 @@ __device__ __forceinline__ void contact_row_vv(const V3 xs[4], const double w[4]
 // t with distance d > eta no contact occurs before t + (d - eta) / Lc; this also
 // covers a piece that stays coplanar, which the cubic cannot see; a piece not
 // cleared within kCaSteps advances counts as a contact) and probed at t = 1.
-// FP64 throughout.
+// Returns the time of the contact found (the earliest probe or advance that found
+// it), or -1 when the piece is clear. FP64 throughout.
 constexpr int kCaSteps = 1024;
 
 __device__ __forceinline__ double cubic_at(const double a[4], double t) {
@@ -359,9 +360,9 @@ __device__ __forceinline__ bool ccd_probe(const V3 q[4], const V3 dq[4], bool ee
   return ccd_dist2(q, dq, ee, t) <= eta2;
 }
 
-__device__ __noinline__ bool ccd_hit(const V3 q[4], const V3 dq[4], bool ee, double eta) {
+__device__ __noinline__ double ccd_hit(const V3 q[4], const V3 dq[4], bool ee, double eta) {
   const double eta2 = eta * eta;
-  if (ccd_probe(q, dq, ee, 0.0, eta2)) return true;
+  if (ccd_probe(q, dq, ee, 0.0, eta2)) return 0.0;
   V3 e1 = vsub(q[1], q[0]), e2 = vsub(q[2], q[0]), e3 = vsub(q[3], q[0]);
   V3 f1 = vsub(dq[1], dq[0]), f2 = vsub(dq[2], dq[0]), f3 = vsub(dq[3], dq[0]);
   V3 c23 = vcross(e2, e3), f2e3 = vcross(f2, e3), e2f3 = vcross(e2, f3), f2f3 = vcross(f2, f3);
@@ -411,8 +412,8 @@ __device__ __noinline__ bool ccd_hit(const V3 q[4], const V3 dq[4], bool ee, dou
       }
       t = 0.5 * (lo + hi);
     }
-    if (t >= 0.0 && ccd_probe(q, dq, ee, t, eta2)) return true;
-    if (i + 2 < nk && ccd_probe(q, dq, ee, knot[i + 1], eta2)) return true;
+    if (t >= 0.0 && ccd_probe(q, dq, ee, t, eta2)) return t;
+    if (i + 2 < nk && ccd_probe(q, dq, ee, knot[i + 1], eta2)) return knot[i + 1];
   }
   // conservative advancement over the piece
   double l1 = 0.0, l2 = 0.0;
@@ -430,12 +431,12 @@ __device__ __noinline__ bool ccd_hit(const V3 q[4], const V3 dq[4], bool ee, dou
   bool cleared = !(lc > 0.0);
   for (int step = 0; step < kCaSteps && !cleared; ++step) {
     const double d = sqrt(ccd_dist2(q, dq, ee, t));
-    if (d <= eta) return true;
+    if (d <= eta) return t;
     t = t + (d - eta) / lc;
     if (t >= 1.0) cleared = true;
   }
-  if (!cleared) return true;
-  return ccd_probe(q, dq, ee, 1.0, eta2);
+  if (!cleared) return t;
+  return ccd_probe(q, dq, ee, 1.0, eta2) ? 1.0 : -1.0;
 }
 
 // Sign of det[b-a, c-a, d-a] (d against the plane of a, b, c); 0 when the FP64
@@ -476,7 +477,8 @@ __device__ __forceinline__ bool seg_tri_meet(V3 p, V3 q, V3 a, V3 b, V3 c, doubl
 // Vertex-vertex continuous test: the closest approach of two linearly moving
 // points, at t = clamp(-(p.dp)/(dp.dp), 0, 1) with p = qa - qb, dp = dqa - dqb
 // (t = 0 when they move together); contact when their distance there is <= eta.
-__device__ __forceinline__ bool ccd_hit_vv(V3 qa, V3 qb, V3 dqa, V3 dqb, double eta2) {
+// Returns that time on a contact, else -1.
+__device__ __forceinline__ double ccd_hit_vv(V3 qa, V3 qb, V3 dqa, V3 dqb, double eta2) {
   const V3 p = vsub(qa, qb), dp = vsub(dqa, dqb);
   const double dd = vdot(dp, dp);
   double t = 0.0;
@@ -486,7 +488,7 @@ __device__ __forceinline__ bool ccd_hit_vv(V3 qa, V3 qb, V3 dqa, V3 dqb, double 
     if (t > 1.0) t = 1.0;
   }
   const V3 e = vsub(vaxpy(qa, t, dqa), vaxpy(qb, t, dqb));
-  return vdot(e, e) <= eta2;
+  return vdot(e, e) <= eta2 ? t : -1.0;
 }
 
 // splitmix64 output function (Steele, Lea, Flood 2014); a bijection on 64 bits.

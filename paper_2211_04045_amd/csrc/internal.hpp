@@ -32,6 +32,8 @@ constexpr int kMaxRounds = 4096;  // colouring rounds per colouring
 constexpr double kEta = 1e-12;
 // certificate queue entry: bit 63 set when the motion bound certified the pair
 constexpr unsigned long long kQueueCertified = 1ull << 63;
+constexpr unsigned long long kOneBits = 0x3FF0000000000000ull;  // bits of 1.0
+constexpr int kStepPasses = 16;  // CCD-based step: passes that scale steps
 constexpr int kMaxSeg = 1024;      // scenes (segments) resident in one solver
 constexpr int kSegBits = 10;       // bits of a segment's rank in a search's sort keys
 constexpr int32_t kMaxIds = 1 << 30;  // primitive ids of pair keys are 30-bit
@@ -56,7 +58,9 @@ struct SegDev {
   unsigned long long n_a;       // |A|
   unsigned long long n_rows;    // valid edge-length rows (setup)
   unsigned long long nback;     // vertices the certificate sent back to x^(l)
-  unsigned long long pad[3];
+  unsigned long long nstep;     // CCD-based step: uncertified pairs in contact (all passes)
+  unsigned long long nscaled;   // CCD-based step: vertex steps scaled
+  unsigned long long pad[1];
 };
 static_assert(sizeof(SegDev) == 128, "SegDev is one 128-byte record");
 constexpr int32_t kSegActive = 1;    // the segment iterates
@@ -203,6 +207,8 @@ struct cc_solver {
   double* rold = nullptr;  // r^(l), for vertices the certificate sends back
   float* dyold = nullptr;  // mixed precision: y - x^(l), likewise
   int32_t* back = nullptr; // certificate: 0, 2 = sent back in this pass, 1 = earlier
+  double* alph = nullptr;  // CCD-based step: the forward step's alpha per vertex
+  unsigned long long* scale = nullptr;  // ... and the factor of its step (bits of a double)
   unsigned long long* Di = nullptr;
   double D = 0.0;  // single-scene interface: D of segment 0
   // proximity set (double buffered for compaction) and distances of P'
@@ -329,9 +335,11 @@ int launch_gs(cc_solver* s, hipStream_t st);
 int launch_jacobi(cc_solver* s, hipStream_t st);
 int launch_forward(cc_solver* s, hipStream_t st);
 // one pass of the certificate over P'; vertices of pairs it does not clear are marked
-int launch_cert(cc_solver* s, hipStream_t st);
-// the marked vertices back to x^(l), ||r||_inf again, queue cleared (ns segments)
-int launch_send_back(cc_solver* s, int32_t ns, hipStream_t st);
+// (scaling: a contact scales the steps of the pair's vertices, the CCD-based step)
+int launch_cert(cc_solver* s, bool scaling, hipStream_t st);
+// the marked vertices back to x^(l) (scaling: their steps scaled), ||r||_inf again,
+// queue cleared (ns segments)
+int launch_send_back(cc_solver* s, int32_t ns, bool scaling, hipStream_t st);
 int launch_fp_col(cc_solver* s, hipStream_t st);
 // mixed precision: y <-> x + dy for vertices [0, n)
 int launch_y_of_dy(cc_solver* s, double* y, int32_t n, hipStream_t st);
@@ -358,6 +366,11 @@ int seg_begin(cc_solver* s, const int32_t* sgs, int32_t k, const double* const* 
 int engine_iterate(cc_solver* s, hipStream_t st);
 int engine_active(const cc_solver* s);
 void seg_stats(const cc_solver* s, int32_t sg, cc_stats* out);
+
+// autotuner of launch shapes (api.hip): the choice stored for (device, kernel, size
+// class), or -1; tune_store records a measured choice with the times of its variants
+int tune_lookup(int device, int kernel, int32_t size_class);
+void tune_store(int device, int kernel, int32_t size_class, int choice, const float ms[4]);
 
 // timing helpers (api.hip)
 void timer_begin(cc_solver* s, int kind, hipStream_t st);

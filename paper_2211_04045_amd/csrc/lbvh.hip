@@ -21,6 +21,7 @@
 // Several scenes (segments) are searched together: a segment's rank sits above
 // the Morton code in the sort key, so each segment's leaves form one subtree
 // of the radix tree, and its queries start at that subtree's root.
+#include <cmath>
 #include <cstddef>
 
 #include "geom.hpp"
@@ -782,14 +783,16 @@ __device__ __forceinline__ bool candidate(const TravArgs& A, int kind, int32_t p
 
 constexpr double kRefitSlack = 1.3;         // node reads allowed to a refitted tree
 constexpr int kWaves = kTravThreads / 64;  // waves per traversal block
-constexpr int kGroup = 16;                  // lanes sharing one traversal (a power of 2, <= 64)
-constexpr int kGroups = 64 / kGroup;        // traversals per wave
+// lanes sharing one traversal (a power of 2 in [8, 32]): a template argument of the
+// traversal, picked per device and query count by the autotuner (16 without it)
+constexpr int kGroupDefault = 16;
 constexpr int kGStack = 100;                // stack entries per traversal (4-wide DFS)
 constexpr int kQueue = 128;                 // candidate ring per wave (two rounds of 64)
 constexpr int kOut = 192;                   // found pairs held per wave (flushed from 128)
 
+template <int G>
 struct WaveLds {
-  int32_t stack[kWaves][kGroups][kGStack];
+  int32_t stack[kWaves][64 / G][kGStack];
   int32_t qlane[kWaves][kQueue];  // candidate: query lane ...
   int32_t qprim[kWaves][kQueue];  // ... and leaf primitive
   double qx[kWaves][6][64];       // query positions per lane
@@ -799,7 +802,8 @@ struct WaveLds {
 };
 
 // The wave's held pairs to the output, reserved with one atomic.
-__device__ __forceinline__ void flush_out(WaveLds& L, int wv, int& no, const TravArgs& A) {
+template <class LT>
+__device__ __forceinline__ void flush_out(LT& L, int wv, int& no, const TravArgs& A) {
   const int lane = __lane_id();
   unsigned long long base = 0;
   if (lane == 0) base = atomicAdd(&A.cnt->n_out, (unsigned long long)no);
@@ -817,7 +821,8 @@ __device__ __forceinline__ void flush_out(WaveLds& L, int wv, int& no, const Tra
 
 // The exact test of n <= 64 queued candidates, one per lane; found pairs join the
 // wave's held pairs (no, wave-uniform), written out from 128 on.
-__device__ __forceinline__ void drain(WaveLds& L, int wv, int head, int n, int kind, int& no,
+template <class LT>
+__device__ __forceinline__ void drain(LT& L, int wv, int head, int n, int kind, int& no,
                                       unsigned& ntested, const TravArgs& A) {
   ntested += (unsigned)n;
   const int lane = __lane_id();
@@ -855,10 +860,11 @@ __device__ __forceinline__ void drain(WaveLds& L, int wv, int head, int n, int k
 // becomes one candidate per such lane in a ring in LDS shared by the wave; every
 // 64 candidates the whole wave runs the exact FP64 tests together. Each lane sees
 // exactly the leaves its own box overlaps (their ancestors overlap it too), so
-// the pair set is that of independent per-query traversals. Lanes of different
-// scenes in one group walk their own subtrees in turn.
+// the pair set is that of independent per-query traversals, whatever kGroup is.
+// Lanes of different scenes in one group walk their own subtrees in turn.
+template <int kGroup>
 __global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
-  __shared__ WaveLds L;
+  __shared__ WaveLds<kGroup> L;
   const int lane = __lane_id(), wv = threadIdx.x >> 6;
   const int grp = lane / kGroup, gl = lane % kGroup;
   const uint64_t gmask = (kGroup == 64 ? ~0ull : ((1ull << kGroup) - 1ull)) << (grp * kGroup);
@@ -1263,6 +1269,17 @@ static int refit_and_widen(cc_solver* s, int32_t mt, int32_t me, int32_t mp, hip
   return CC_OK;
 }
 
+int launch_traverse(int group, const TravArgs& A, int64_t nq, hipStream_t st) {
+  const unsigned nb = blocks(nq, kTravThreads);
+  switch (group) {
+    case 8: k_traverse<8><<<nb, kTravThreads, 0, st>>>(A); break;
+    case 32: k_traverse<32><<<nb, kTravThreads, 0, st>>>(A); break;
+    default: k_traverse<16><<<nb, kTravThreads, 0, st>>>(A); break;
+  }
+  CC_HIP(hipGetLastError());
+  return CC_OK;
+}
+
 int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64_t* out,
                 double* outd, int64_t cap, int64_t* nfound, hipStream_t st, bool refit_ok) {
   // compact offsets of the selected segments' vertices, triangles, edges and particles
@@ -1392,8 +1409,43 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
     A.me_pad = (me + 63) & ~63;
     int64_t nq = (int64_t)A.mv_pad + A.me_pad + mp;
     if (nq > 0) {
+      // lanes per traversal group: the autotuner's choice for this device and query
+      // count, measured on this search's own queries the first time (every variant
+      // finds the same pair set; the counters restart before each)
+      int group = kGroupDefault;
+      if (!(s->p.flags & CC_NO_AUTOTUNE)) {
+        const int cls = A.mv >= A.me && A.mv >= A.mp ? 0 : (A.me >= A.mp ? 1 : 2);
+        const int32_t size_class = 4 * (int32_t)std::ilogb((double)nq) + cls;
+        int dev = 0;
+        CC_HIP(hipGetDevice(&dev));
+        group = tune_lookup(dev, CC_TUNE_TRAVERSE, size_class);
+        if (group < 0) {
+          const int cand[3] = {8, 16, 32};
+          float ms[4] = {0.f, 0.f, 0.f, 0.f};
+          int best = 1;
+          hipEvent_t e0, e1;
+          CC_HIP(hipEventCreate(&e0));
+          CC_HIP(hipEventCreate(&e1));
+          for (int c = 0; c < 3; ++c) {
+            CC_HIP(hipMemsetAsync(s->dc, 0, offsetof(Counters, ncand) + sizeof(unsigned long long),
+                                  st));
+            CC_HIP(hipEventRecord(e0, st));
+            CC_TRY(launch_traverse(cand[c], A, nq, st));
+            CC_HIP(hipEventRecord(e1, st));
+            CC_HIP(hipEventSynchronize(e1));
+            CC_HIP(hipEventElapsedTime(&ms[c], e0, e1));
+            if (ms[c] < ms[best]) best = c;
+          }
+          (void)hipEventDestroy(e0);
+          (void)hipEventDestroy(e1);
+          group = cand[best];
+          tune_store(dev, CC_TUNE_TRAVERSE, size_class, group, ms);
+          CC_HIP(hipMemsetAsync(s->dc, 0, offsetof(Counters, ncand) + sizeof(unsigned long long),
+                                st));
+        }
+      }
       timer_begin(s, CC_K_SEARCH, st);
-      k_traverse<<<blocks(nq, kTravThreads), kTravThreads, 0, st>>>(A);
+      CC_TRY(launch_traverse(group, A, nq, st));
       timer_end(s, st);
     }
   }

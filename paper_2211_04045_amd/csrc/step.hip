@@ -1896,8 +1896,10 @@ __global__ void __launch_bounds__(kThreads) k_forward(double* __restrict__ x,
                                                       double* __restrict__ r,
                                                       double* __restrict__ rold,
                                                       int32_t* __restrict__ back,
+                                                      double* __restrict__ alph,
+                                                      unsigned long long* __restrict__ scale,
                                                       double* __restrict__ move2, int32_t n,
-                                                      double hg, int guard,
+                                                      double hg, int guard, int ccd_step,
                                                       const int32_t* __restrict__ vseg,
                                                       SegDev* seg,
                                                       const unsigned long long* err,
@@ -1926,7 +1928,9 @@ __global__ void __launch_bounds__(kThreads) k_forward(double* __restrict__ x,
       yi = ld3(y, i);
       dx = vsub(yi, xi);
     }
-    const double di = __longlong_as_double((long long)Di[i]);
+    // the CCD-based scheme bounds every vertex by D^(l) alone; its contacts along P'
+    // are found by the certificate's passes
+    const double di = ccd_step ? seg[sg].D : __longlong_as_double((long long)Di[i]);
     double n2 = vdot(dx, dx);
     double alpha = 1.0;
     if (n2 > 0.0) {
@@ -1951,6 +1955,10 @@ __global__ void __launch_bounds__(kThreads) k_forward(double* __restrict__ x,
     move2[i] = m2;
     mvd[i] = (xn.x != xi.x || xn.y != xi.y || xn.z != xi.z) ? 1 : 0;
     back[i] = 0;
+    if (ccd_step) {
+      alph[i] = alpha;
+      scale[i] = kOneBits;
+    }
     st3(xold, i, xi);
     st3(x, i, xn);
     const double r0 = r[i];
@@ -1979,15 +1987,18 @@ __global__ void __launch_bounds__(kThreads) k_forward(double* __restrict__ x,
 int launch_forward(cc_solver* s, hipStream_t st) {
   const double hg = 0.5 * s->p.gamma;
   const int guard = (s->p.flags & CC_UNGUARDED) ? 0 : 1;
+  const int ccd_step = (s->p.flags & CC_CCD_STEP) ? 1 : 0;
   const unsigned long long* err = s->col_small ? &s->dc->err : nullptr;
   if (s->n > 0 && (s->p.flags & CC_MIXED))
     k_forward<true><<<nblk(s->n), kThreads, 0, st>>>(s->x, s->xold, s->y, s->dy, s->dyold, s->Di,
-                                                      s->r, s->rold, s->back, s->move2, s->n, hg,
-                                                      guard, s->vseg, s->seg_dev, err, s->mvd);
+                                                      s->r, s->rold, s->back, s->alph, s->scale,
+                                                      s->move2, s->n, hg, guard, ccd_step,
+                                                      s->vseg, s->seg_dev, err, s->mvd);
   else if (s->n > 0)
     k_forward<false><<<nblk(s->n), kThreads, 0, st>>>(s->x, s->xold, s->y, s->dy, s->dyold,
-                                                       s->Di, s->r, s->rold, s->back, s->move2,
-                                                       s->n, hg, guard, s->vseg, s->seg_dev, err,
+                                                       s->Di, s->r, s->rold, s->back, s->alph,
+                                                       s->scale, s->move2, s->n, hg, guard,
+                                                       ccd_step, s->vseg, s->seg_dev, err,
                                                        s->mvd);
   CC_HIP(hipGetLastError());
   return CC_OK;
@@ -2040,7 +2051,9 @@ __global__ void __launch_bounds__(kThreads) k_cert_ccd(const uint64_t* __restric
                                                        SegDev* seg,
                                                        const unsigned long long* __restrict__ queue,
                                                        const unsigned long long* nqueue,
-                                                       int32_t* __restrict__ back) {
+                                                       int32_t* __restrict__ back,
+                                                       unsigned long long* __restrict__ scale,
+                                                       double gamma) {
   const int64_t n = (int64_t)*nqueue;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
        j += (int64_t)gridDim.x * blockDim.x) {
@@ -2053,15 +2066,52 @@ __global__ void __launch_bounds__(kThreads) k_cert_ccd(const uint64_t* __restric
       q[k] = ld3(xold, v[k]);
       dq[k] = vsub(ld3(x, v[k]), q[k]);
     }
-    const bool hit = key_is_vv(key) ? ccd_hit_vv(q[0], q[1], dq[0], dq[1], eta * eta)
-                                    : ccd_hit(q, dq, key_is_ee(key), eta);
-    if (!hit) continue;
+    const double th = key_is_vv(key) ? ccd_hit_vv(q[0], q[1], dq[0], dq[1], eta * eta)
+                                     : ccd_hit(q, dq, key_is_ee(key), eta);
+    if (!(th >= 0.0)) continue;
     SegDev& sd = seg[vseg[v[0]]];
     atomicAdd(&sd.hits, 1ull);
     if (e & kQueueCertified) continue;
-    for (int k = 0; k < 4; ++k)
-      if (atomicCAS(&back[v[k]], 0, 2) == 0) atomicAdd(&sd.nback, 1ull);
+    if (scale) {
+      // CCD-based step: the pair's vertices take at most gamma t* of their step
+      const unsigned long long fb = (unsigned long long)__double_as_longlong(gamma * th);
+      for (int k = 0; k < 4; ++k) atomicMin(&scale[v[k]], fb);
+      atomicAdd(&sd.nstep, 1ull);
+    } else {
+      for (int k = 0; k < 4; ++k)
+        if (atomicCAS(&back[v[k]], 0, 2) == 0) atomicAdd(&sd.nback, 1ull);
+    }
   }
+}
+
+// CCD-based step: every moving vertex whose factor fell below 1 in the last pass takes
+// alpha <- alpha * factor, x <- x^(l) + alpha (y - x^(l)) (y itself when alpha is 1),
+// r <- r^(l) (1 - alpha), and is counted for its scene.
+__global__ void __launch_bounds__(kThreads) k_step_apply(double* __restrict__ x,
+                                                         const double* __restrict__ xold,
+                                                         const double* __restrict__ y,
+                                                         double* __restrict__ r,
+                                                         const double* __restrict__ rold,
+                                                         double* __restrict__ alph,
+                                                         unsigned long long* __restrict__ scale,
+                                                         double* __restrict__ move2,
+                                                         uint8_t* __restrict__ mvd, int32_t n,
+                                                         const int32_t* __restrict__ vseg,
+                                                         SegDev* seg) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !(scale[i] < kOneBits)) return;
+  const double a = alph[i] * __longlong_as_double((long long)scale[i]);
+  scale[i] = kOneBits;
+  if (move2[i] == 0.0) return;  // no step to scale
+  alph[i] = a;
+  const V3 x0 = ld3(xold, i), yi = ld3(y, i);
+  const V3 xn = vaxpy(x0, a, vsub(yi, x0));
+  const V3 mv = vsub(xn, x0);
+  move2[i] = vdot(mv, mv);
+  mvd[i] = (xn.x != x0.x || xn.y != x0.y || xn.z != x0.z) ? 1 : 0;
+  st3(x, i, xn);
+  r[i] = rold[i] * (1.0 - a);
+  atomicAdd(&seg[vseg[i]].nscaled, 1ull);
 }
 
 // Vertices marked in the last pass go back to x^(l): x, r (and y - x) as before
@@ -2104,7 +2154,7 @@ __global__ void __launch_bounds__(kThreads) k_seg_rinf(const double* __restrict_
 
 // One pass of the certificate over the current P'. The pair buffer P2 is free
 // between the pair passes and holds the queue (at most |P'| entries).
-int launch_cert(cc_solver* s, hipStream_t st) {
+int launch_cert(cc_solver* s, bool scaling, hipStream_t st) {
   if (s->nP > 0) {
     unsigned long long* queue = (unsigned long long*)s->P2;
     // dc->ncert starts at zero with the iteration's counters (k_di_init) and is
@@ -2114,19 +2164,26 @@ int launch_cert(cc_solver* s, hipStream_t st) {
                                               (s->p.flags & CC_CCD_ALL) ? 1 : 0);
     const unsigned nb = std::min<unsigned>(nblk(s->nP), 1024u);
     k_cert_ccd<<<nb, kThreads, 0, st>>>(s->P, Topo{s->tris, s->edges}, s->xold, s->x, kEta,
-                                         s->vseg, s->seg_dev, queue, &s->dc->ncert, s->back);
+                                         s->vseg, s->seg_dev, queue, &s->dc->ncert, s->back,
+                                         scaling ? s->scale : nullptr, s->p.gamma);
   }
   CC_HIP(hipGetLastError());
   return CC_OK;
 }
 
-// Send the marked vertices back, recompute ||r||_inf, clear the queue length.
-int launch_send_back(cc_solver* s, int32_t ns, hipStream_t st) {
+// Send the marked vertices back (or, scaling, scale their steps), recompute
+// ||r||_inf, clear the queue length.
+int launch_send_back(cc_solver* s, int32_t ns, bool scaling, hipStream_t st) {
   if (s->n > 0) {
     const bool mixed = (s->p.flags & CC_MIXED) != 0;
-    k_send_back<<<nblk(s->n), kThreads, 0, st>>>(s->x, s->xold, s->r, s->rold,
-                                                  mixed ? s->dy : nullptr, s->dyold, s->move2,
-                                                  s->mvd, s->back, s->n);
+    if (scaling)
+      k_step_apply<<<nblk(s->n), kThreads, 0, st>>>(s->x, s->xold, s->y, s->r, s->rold, s->alph,
+                                                     s->scale, s->move2, s->mvd, s->n, s->vseg,
+                                                     s->seg_dev);
+    else
+      k_send_back<<<nblk(s->n), kThreads, 0, st>>>(s->x, s->xold, s->r, s->rold,
+                                                    mixed ? s->dy : nullptr, s->dyold, s->move2,
+                                                    s->mvd, s->back, s->n);
     k_seg_rinf_clear<<<(ns + 255) / 256, 256, 0, st>>>(s->seg_dev, ns);
     k_seg_rinf<<<nblk(s->n), kThreads, 0, st>>>(s->r, s->n, s->vseg, s->seg_dev);
   }

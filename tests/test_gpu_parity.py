@@ -15,7 +15,7 @@ import scenes
 pytestmark = pytest.mark.gpu
 
 TRACE_KEYS = ["searched", "n_colors", "n_p", "n_pf", "n_a", "ccd_fail", "ccd_hits", "n_back",
-              "d_before", "d_after", "move_max", "r_inf", "fp_pf", "fp_a", "fp_col"]
+              "n_scaled", "d_before", "d_after", "move_max", "r_inf", "fp_pf", "fp_a", "fp_col"]
 SET_KEYS = ("searched", "n_p", "n_pf", "n_a", "n_colors", "fp_pf", "fp_a", "fp_col")
 
 
@@ -159,6 +159,41 @@ def test_unguarded_forward_step_lockstep(cc, ctx):
     n, ref, gpu = _lockstep(cc, ctx, sc, 600, unguarded=True)
     assert sum(t["n_back"] for t in gpu.trace) > 0
     assert _intersection_free(gpu.state()[0].cpu().numpy(), sc["tris"], sc["edges"])
+
+
+@pytest.mark.parametrize("group", [8, 16, 32])
+def test_every_traversal_group_size_finds_the_oracle_set(cc, ctx, group):
+    """The traversal's launch shapes the autotuner chooses between (lanes per group):
+    each, forced, finds exactly the oracle's pair set on the full folded cloth and on
+    the small workloads; the tuning table records what was measured."""
+    lib = cc._lib.load()
+    assert lib.cc_autotune_force(0, group) == 0
+    try:
+        for sc in [scenes.config(2)] + [scenes.config(c, small=True) for c in (1, 3, 4, 6)]:
+            ref = oracle.Scene(sc["w"], sc["tris"], sc["edges"])
+            ref.begin(sc["x"], sc["xt"])
+            gpu = cc.Solver(ctx, sc["w"], sc["tris"], sc["edges"])
+            gpu.begin(sc["x"], sc["xt"])
+            want = np.sort(ref.search(sc["x"], 4e-3))
+            got = _u64(gpu.search(sc["x"], 4e-3))
+            assert np.array_equal(got, want), (group, sc["name"])
+    finally:
+        lib.cc_autotune_force(0, 0)
+    table = cc.autotune_table()
+    assert all(e["choice"] in (8, 16, 32) and min(e["ms"]) > 0 for e in table)
+
+
+@pytest.mark.parametrize("cfg", [2, 3, 4, 6])
+def test_ccd_step_lockstep_small(cc, ctx, cfg):
+    """The CCD-based step-size scheme (Sec. 5.1's comparison; CC_CCD_STEP) in lockstep
+    to its end: every iteration bit-identical (the passes, the contacts, the scaled
+    steps); the final state free in exact arithmetic."""
+    sc = scenes.config(cfg, small=True)
+    n, ref, gpu = _lockstep(cc, ctx, sc, sc["params"]["max_iters"], ccd_step=True)
+    assert all(t["n_back"] == 0 for t in gpu.trace)
+    assert _intersection_free(gpu.state()[0].cpu().numpy(), sc["tris"], sc["edges"])
+    print(f"ccd step config {cfg} small: {n} iterations, "
+          f"{sum(t['n_scaled'] for t in gpu.trace)} scaled steps")
 
 
 def test_sets_and_colours_explicit(cc, ctx):

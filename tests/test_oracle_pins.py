@@ -1075,3 +1075,42 @@ def test_unguarded_forward_step_is_caught_by_the_certificate():
     assert sum(t["n_back"] for t in tr) > 0
     et, ee = exact.touching_pairs(out, sc["tris"], sc["edges"])
     assert et == [] and ee == []
+
+
+# ------------------------------------------- CCD-based step-size scheme (Sec. 5.1)
+
+def test_ccd_step_stops_a_vertex_short_of_the_contact():
+    # a free vertex 1.5 mm above a static triangle, its target 2 mm below it; the row
+    # is not active (d > delta), so y stays the target. The CCD-based step bounds the
+    # vertex by 0.45 D^(l) = 1.8 mm, finds the contact at 1.5 mm of that piece and
+    # scales the step by gamma t*: the vertex stops at (1 - gamma) 1.5 mm above the
+    # face. The CCD-free step moves it by 0.45 D_i = 0.675 mm.
+    h0 = 1.5e-3
+    x = np.array([[0.002, 0.002, h0], [0, 0, 0], [0.01, 0, 0], [0, 0.01, 0]], float)
+    xt = x.copy()
+    xt[0, 2] = -2e-3
+    w = np.array([1.0, 0, 0, 0])
+    ccd = oracle.Scene(w, [[1, 2, 3]], [], max_iters=1, ccd_step=1, edge_len=0)
+    ccd.begin(x, xt)
+    _, it = ccd.iterate()
+    z = ccd.state()[0][0, 2]
+    assert it["n_scaled"] == 1 and it["ccd_hits"] == 1 and it["n_back"] == 0
+    assert abs(z - (1.0 - 0.9) * h0) < 1e-9
+    free = oracle.Scene(w, [[1, 2, 3]], [], max_iters=1, edge_len=0)
+    free.begin(x, xt)
+    free.iterate()
+    assert abs(free.state()[0][0, 2] - (h0 - 0.45 * h0)) < 1e-15
+
+
+@pytest.mark.parametrize("cfg", [2, 3, 4, 6])
+def test_ccd_step_small_configs_end_intersection_free(cfg):
+    # the CCD-based scheme on the small workloads: its final states are free in exact
+    # arithmetic, nothing had to be sent back, and it needs no more iterations than
+    # the CCD-free scheme (its steps are bounded by D^(l), not by D_i)
+    sc = scenes.config(cfg, small=True)
+    s, out, n, tr = _run_checked(sc, ccd_step=1)
+    assert all(t["n_back"] == 0 for t in tr)
+    et, ee = exact.touching_pairs(out, sc["tris"], sc["edges"])
+    assert et == [] and ee == []
+    n_free = _run_checked(sc)[2]
+    assert n <= n_free
