@@ -365,8 +365,10 @@ def main():
 
 
 # Poisson arrival rate of the serving stream (requests/s), frozen from one
-# calibration run at 70% of the measured closed-batch capacity.
-SERVE_RATE = None
+# calibration run at 70% of the measured closed-batch capacity
+# (`bench.py --config 5 --requests 6 --compare 6 --calibrate`, MI355X: the first 6
+# requests, 10 steps each at L = 200, closed batch 3.99 steps/s, plain path 1.80).
+SERVE_RATE = 0.2796
 
 
 def serve_bench(args):

@@ -828,22 +828,36 @@ def _particle_dimers(nd, seed, spacing=5e-3, gap=5e-4):
     return x, xt
 
 
-@pytest.mark.parametrize("kind", ["cluster", "dimers_lds", "dimers_many"])
+@pytest.mark.parametrize("kind", ["cluster", "cluster_wide", "dimers_lds", "dimers_many",
+                                  "dimers_overflow"])
 def test_small_contact_set_colouring_paths_lockstep(cc, ctx, kind):
-    # Contact sets of at most 4096 rows are coloured by one block with the vertex
-    # state in LDS; a set whose colours pass 127 (the 90-particle cluster needs
-    # about 136) or that touches more than 2048 free vertices (1500 dimers) is
-    # coloured by the same block with the global-memory rounds instead.
+    # Contact sets of at most 4096 rows are coloured by one block with the vertex state
+    # in LDS: one colour word per vertex (64 colours) for up to 4096 vertices, or, after
+    # a colouring of more than 56 colours, two words (128 colours) for up to 2048. A set
+    # that needs more colours than the words hold, or touches more free vertices than
+    # fit, is finished by the same block with the global-memory rounds. The cases:
+    # - cluster: 90 particles, about 136 colours: beyond both layouts;
+    # - cluster_wide: 50 particles, 80 colours: the first iteration overflows the one-word
+    #   layout (global rounds), the next ones complete in LDS with two words;
+    # - dimers_lds, dimers_many: 900 and 1500 dimers (1800 and 3000 free vertices, one
+    #   colour) complete in LDS with one word;
+    # - dimers_overflow: 2100 dimers, 4200 free vertices: more than 4096 fit, so the block
+    #   colours them with the global-memory rounds.
     if kind == "cluster":
         x, xt = _particle_cluster(90, 4.5e-4, 5)
+    elif kind == "cluster_wide":
+        x, xt = _particle_cluster(50, 4.5e-4, 5)
     else:
-        x, xt = _particle_dimers(900 if kind == "dimers_lds" else 1500, 7)
+        nd = {"dimers_lds": 900, "dimers_many": 1500, "dimers_overflow": 2100}[kind]
+        x, xt = _particle_dimers(nd, 7)
     sc = {"name": kind, "x": x, "xt": xt, "w": np.ones(len(x)),
           "tris": np.zeros((0, 3), np.int32), "edges": np.zeros((0, 2), np.int32), "params": {}}
     n, ref, gpu = _lockstep(cc, ctx, sc, 6)
     assert n >= 2
+    cols = [t["n_colors"] for t in gpu.trace]
     if kind == "cluster":
-        # the first iteration's colouring needed more than the 128 colours kept in LDS
-        ref2 = oracle.Scene(sc["w"], sc["tris"], sc["edges"], max_iters=1)
-        ref2.begin(x, xt)
-        assert ref2.iterate()[1]["n_colors"] > 128
+        assert cols[0] > 128
+    elif kind == "cluster_wide":
+        assert 64 < cols[0] <= 127 and all(56 < c <= 127 for c in cols[1:3])
+    elif kind == "dimers_overflow":
+        assert len(x) > 4096 and gpu.trace[0]["n_a"] <= 4096
