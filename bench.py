@@ -452,6 +452,7 @@ def serve_bench(args):
         "p99_ms": round(float(np.percentile(lat, 99)), 3),
         "peak_resident_scenes": res["peak_resident"],
         "peak_resident_gib": round(res["peak_bytes"] / (1 << 30), 3),
+        "failed_steps": res["failed"],
         "closed_batch_steps_per_s": round(capacity, 3),
         "plain_path_steps_per_s": round(plain, 3),
         "served_over_plain": round(capacity / plain, 3),

@@ -195,12 +195,14 @@ typedef struct cc_solver cc_solver;
  * Kernels whose launch shape is tuned, and the record of one tuning: the device,
  * the kernel, its size class (CC_TUNE_TRAVERSE: 4 floor(log2(queries)) + the
  * dominant query class, 0 vertex-triangle, 1 edge-edge, 2 vertex-vertex), the
- * choice (lanes per traversal group: 8, 16 or 32) and the measured time of each
- * variant in milliseconds (in the order 8, 16, 32). */
+ * choice and the measured time of each variant in milliseconds. CC_TUNE_TRAVERSE
+ * variants, in the order of ms[]: 8, 16, 32 lanes per traversal group taking one
+ * node per step, then 108, 116, 132: the same group sizes taking two nodes per step
+ * (their records loaded together). */
 enum { CC_TUNE_TRAVERSE = 0 };
 typedef struct cc_tune_entry {
   int32_t device, kernel, size_class, choice;
-  float ms[4];
+  float ms[8];
 } cc_tune_entry;
 /* The process-wide tuning table (HOST array out_host, cap entries): *n gets the
  * number of entries; nothing is written when cap is smaller. */
@@ -208,7 +210,8 @@ int cc_autotune_entries(cc_tune_entry* out_host, int32_t cap, int32_t* n);
 /* Forget every tuning (the next launches measure again). */
 void cc_autotune_reset(void);
 /* Force a choice for every later launch of the kernel in this process (CC_TUNE_TRAVERSE:
- * 8, 16 or 32 lanes per group; 0 returns to the tuned choices); CC_EINVAL otherwise. */
+ * 8, 16, 32, 108, 116 or 132 as above; 0 returns to the tuned choices); CC_EINVAL
+ * otherwise. */
 int cc_autotune_force(int32_t kernel, int32_t choice);
 
 void cc_default_params(cc_params* p);

@@ -116,7 +116,7 @@ def autotune_table():
     _check(lib.cc_autotune_entries(rows, n.value, C.byref(n)), "cc_autotune_entries")
     names = {0: "traverse"}
     return [dict(device=r.device, kernel=names.get(r.kernel, r.kernel), size_class=r.size_class,
-                 choice=r.choice, ms=[round(float(v), 4) for v in r.ms[:3]])
+                 choice=r.choice, ms=[round(float(v), 4) for v in r.ms[:6]])
             for r in rows[:n.value]]
 
 

@@ -72,7 +72,7 @@ class SceneDesc(C.Structure):
 
 class TuneEntry(C.Structure):
     _fields_ = [("device", C.c_int32), ("kernel", C.c_int32), ("size_class", C.c_int32),
-                ("choice", C.c_int32), ("ms", C.c_float * 4)]
+                ("choice", C.c_int32), ("ms", C.c_float * 8)]
 
 
 class Stats(C.Structure):

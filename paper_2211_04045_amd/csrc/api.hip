@@ -97,14 +97,14 @@ int tune_lookup(int device, int kernel, int32_t size_class) {
   return -1;
 }
 
-void tune_store(int device, int kernel, int32_t size_class, int choice, const float ms[4]) {
+void tune_store(int device, int kernel, int32_t size_class, int choice, const float ms[8]) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   cc_tune_entry e{};
   e.device = device;
   e.kernel = kernel;
   e.size_class = size_class;
   e.choice = choice;
-  for (int i = 0; i < 4; ++i) e.ms[i] = ms[i];
+  for (int i = 0; i < 8; ++i) e.ms[i] = ms[i];
   g_tune.push_back(e);
 }
 
@@ -1015,7 +1015,9 @@ void cc_autotune_reset(void) {
 
 int cc_autotune_force(int32_t kernel, int32_t choice) {
   if (kernel != CC_TUNE_TRAVERSE) return CC_EINVAL;
-  if (choice != 0 && choice != 8 && choice != 16 && choice != 32) return CC_EINVAL;
+  if (choice != 0 && choice != 8 && choice != 16 && choice != 32 && choice != 108 &&
+      choice != 116 && choice != 132)
+    return CC_EINVAL;
   std::lock_guard<std::mutex> lk(cc::g_tune_mu);
   cc::g_tune_force[kernel] = choice;
   return CC_OK;

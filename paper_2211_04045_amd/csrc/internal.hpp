@@ -370,7 +370,7 @@ void seg_stats(const cc_solver* s, int32_t sg, cc_stats* out);
 // autotuner of launch shapes (api.hip): the choice stored for (device, kernel, size
 // class), or -1; tune_store records a measured choice with the times of its variants
 int tune_lookup(int device, int kernel, int32_t size_class);
-void tune_store(int device, int kernel, int32_t size_class, int choice, const float ms[4]);
+void tune_store(int device, int kernel, int32_t size_class, int choice, const float ms[8]);
 
 // timing helpers (api.hip)
 void timer_begin(cc_solver* s, int kind, hipStream_t st);

@@ -793,6 +793,7 @@ constexpr int kOut = 192;                   // found pairs held per wave (flushe
 template <int G>
 struct WaveLds {
   int32_t stack[kWaves][64 / G][kGStack];
+  float4 nrec[kWaves][64 / G][8];  // two-node steps: the second node's record
   int32_t qlane[kWaves][kQueue];  // candidate: query lane ...
   int32_t qprim[kWaves][kQueue];  // ... and leaf primitive
   double qx[kWaves][6][64];       // query positions per lane
@@ -862,8 +863,9 @@ __device__ __forceinline__ void drain(LT& L, int wv, int head, int n, int kind, 
 // exactly the leaves its own box overlaps (their ancestors overlap it too), so
 // the pair set is that of independent per-query traversals, whatever kGroup is.
 // Lanes of different scenes in one group walk their own subtrees in turn.
-template <int kGroup>
-__global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
+// (occupancy target: 4 waves per SIMD; 3 for 8-lane groups, whose LDS allows no more)
+template <int kGroup, int kPop>
+__global__ void __launch_bounds__(kTravThreads, kGroup == 8 ? 3 : 4) k_traverse(TravArgs A) {
   __shared__ WaveLds<kGroup> L;
   const int lane = __lane_id(), wv = threadIdx.x >> 6;
   const int grp = lane / kGroup, gl = lane % kGroup;
@@ -976,31 +978,56 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(TravArgs A) {
     }
     if (!__any(sp > 0)) break;
     __builtin_amdgcn_wave_barrier();
-    const bool valid = sp > 0;
-    int32_t i = 0;
-    if (valid) {
-      --sp;
-      i = L.stack[wv][grp][sp];
-      if (gl == 0) ++nvisit;
+    // kPop nodes leave the group's stack per step, their records loaded together so
+    // that their latencies overlap (kPop = 2 halves the chain of dependent loads of a
+    // deep walk; the set of nodes visited is the same)
+    bool valid[kPop];
+    int32_t ni[kPop];
+#pragma unroll
+    for (int k = 0; k < kPop; ++k) {
+      valid[k] = sp > 0;
+      ni[k] = 0;
+      if (valid[k]) {
+        --sp;
+        ni[k] = L.stack[wv][grp][sp];
+        if (gl == 0) ++nvisit;
+      }
     }
+    // both records are loaded together; the second goes to LDS (each lane of the
+    // group stores one of its eight float4), so that registers hold one record while
+    // the first node's children are tested and candidates drained
     float4 rb0[4], rb1[4];
 #pragma unroll
     for (int slot = 0; slot < 4; ++slot) {
       rb0[slot] = make_float4(0.f, 0.f, 0.f, 0.f);
       rb1[slot] = rb0[slot];
     }
-    if (valid) {
-      const float4* rec = T.wide + 8 * (int64_t)i;
+    if (valid[0]) {
+      const float4* rec = T.wide + 8 * (int64_t)ni[0];
 #pragma unroll
       for (int slot = 0; slot < 4; ++slot) {
         rb0[slot] = rec[2 * slot];
         rb1[slot] = rec[2 * slot + 1];
       }
     }
+    if (kPop > 1) {
+      float4 r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (valid[kPop - 1] && gl < 8) r2 = T.wide[8 * (int64_t)ni[kPop - 1] + gl];
+      if (gl < 8) L.nrec[wv][grp][gl] = r2;
+      __builtin_amdgcn_wave_barrier();
+    }
 #pragma unroll
-    for (int slot = 0; slot < 4; ++slot) {
-      const float4 b0 = rb0[slot], b1 = rb1[slot];
-      const bool ov = valid && part && overlap6(qlo, qhi, b0.x, b0.y, b0.z, b0.w, b1.x, b1.y) &&
+    for (int slot = 0; slot < 4 * kPop; ++slot) {
+      float4 b0, b1;
+      if (slot < 4) {
+        b0 = rb0[slot];
+        b1 = rb1[slot];
+      } else {
+        b0 = L.nrec[wv][grp][2 * (slot - 4)];
+        b1 = L.nrec[wv][grp][2 * (slot - 4) + 1];
+      }
+      const bool ov = valid[slot / 4] && part &&
+                      overlap6(qlo, qhi, b0.x, b0.y, b0.z, b0.w, b1.x, b1.y) &&
                       __float_as_int(b1.w) > qpos &&
                       !far6(qlo, qhi, b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, A.fdmax, qr2);
       const uint64_t m = __ballot(ov);
@@ -1272,9 +1299,12 @@ static int refit_and_widen(cc_solver* s, int32_t mt, int32_t me, int32_t mp, hip
 int launch_traverse(int group, const TravArgs& A, int64_t nq, hipStream_t st) {
   const unsigned nb = blocks(nq, kTravThreads);
   switch (group) {
-    case 8: k_traverse<8><<<nb, kTravThreads, 0, st>>>(A); break;
-    case 32: k_traverse<32><<<nb, kTravThreads, 0, st>>>(A); break;
-    default: k_traverse<16><<<nb, kTravThreads, 0, st>>>(A); break;
+    case 8: k_traverse<8, 1><<<nb, kTravThreads, 0, st>>>(A); break;
+    case 32: k_traverse<32, 1><<<nb, kTravThreads, 0, st>>>(A); break;
+    case 108: k_traverse<8, 2><<<nb, kTravThreads, 0, st>>>(A); break;
+    case 116: k_traverse<16, 2><<<nb, kTravThreads, 0, st>>>(A); break;
+    case 132: k_traverse<32, 2><<<nb, kTravThreads, 0, st>>>(A); break;
+    default: k_traverse<16, 1><<<nb, kTravThreads, 0, st>>>(A); break;
   }
   CC_HIP(hipGetLastError());
   return CC_OK;
@@ -1420,13 +1450,13 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
         CC_HIP(hipGetDevice(&dev));
         group = tune_lookup(dev, CC_TUNE_TRAVERSE, size_class);
         if (group < 0) {
-          const int cand[3] = {8, 16, 32};
-          float ms[4] = {0.f, 0.f, 0.f, 0.f};
+          const int cand[6] = {8, 16, 32, 108, 116, 132};
+          float ms[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
           int best = 1;
           hipEvent_t e0, e1;
           CC_HIP(hipEventCreate(&e0));
           CC_HIP(hipEventCreate(&e1));
-          for (int c = 0; c < 3; ++c) {
+          for (int c = 0; c < 6; ++c) {
             CC_HIP(hipMemsetAsync(s->dc, 0, offsetof(Counters, ncand) + sizeof(unsigned long long),
                                   st));
             CC_HIP(hipEventRecord(e0, st));

@@ -14,6 +14,10 @@ boundary.
 Latency of a step: from the moment it could start (the request's arrival for its
 first step, the previous step's completion for the others) to the moment its
 result is back.
+
+A step that fails (the library returns an error for it, e.g. a colour palette too
+small for its contact set) ends its request: the scene is released, the error is
+recorded with the request and step, and the other requests go on.
 """
 from __future__ import annotations
 
@@ -53,7 +57,8 @@ def run_stream(ctx, requests, arrivals, steps: int = 10, budget_bytes: int = 0,
     order = np.argsort(np.asarray(arrivals), kind="stable")
     pending = deque(int(i) for i in order)
     live: dict[int, _Live] = {}
-    lat, iters, pairs = [], [], []
+    from . import CCError
+    lat, iters, pairs, failed = [], [], [], []
     peak_resident, peak_bytes, used = 0, 0, 0
     results = {} if keep_results else None
     done_steps = 0
@@ -90,7 +95,18 @@ def run_stream(ctx, requests, arrivals, steps: int = 10, budget_bytes: int = 0,
             # completions
             for h in list(live):
                 L = live[h]
-                r = srv.poll(h, out=L.out)
+                try:
+                    r = srv.poll(h, out=L.out)
+                except CCError as e:
+                    failed.append(dict(request=L.req, step=L.step, code=e.code))
+                    srv.release(h)
+                    sc = requests[L.req]
+                    used -= srv.scene_bytes(len(sc["x"]), len(sc["tris"]), len(sc["edges"]))
+                    del live[h]
+                    progressed = True
+                    if progress is not None:
+                        progress(f"request {L.req} ({sc.get('name', '')}) step {L.step} failed: {e}")
+                    continue
                 if r is None:
                     continue
                 t_done = time.perf_counter() - t0
@@ -126,7 +142,7 @@ def run_stream(ctx, requests, arrivals, steps: int = 10, budget_bytes: int = 0,
     wall = time.perf_counter() - t0
     return dict(latency=np.asarray(lat), wall=wall, steps=done_steps, iters=np.asarray(iters),
                 pairs=np.asarray(pairs), peak_resident=peak_resident, peak_bytes=peak_bytes,
-                results=results)
+                results=results, failed=failed)
 
 
 def run_alone(ctx, sc, steps: int = 10, progress=None, **over):

@@ -161,11 +161,12 @@ def test_unguarded_forward_step_lockstep(cc, ctx):
     assert _intersection_free(gpu.state()[0].cpu().numpy(), sc["tris"], sc["edges"])
 
 
-@pytest.mark.parametrize("group", [8, 16, 32])
+@pytest.mark.parametrize("group", [8, 16, 32, 108, 116, 132])
 def test_every_traversal_group_size_finds_the_oracle_set(cc, ctx, group):
-    """The traversal's launch shapes the autotuner chooses between (lanes per group):
-    each, forced, finds exactly the oracle's pair set on the full folded cloth and on
-    the small workloads; the tuning table records what was measured."""
+    """The traversal's launch shapes the autotuner chooses between (lanes per group,
+    one or two nodes per step): each, forced, finds exactly the oracle's pair set on
+    the full folded cloth and on the small workloads; the tuning table records what
+    was measured."""
     lib = cc._lib.load()
     assert lib.cc_autotune_force(0, group) == 0
     try:
@@ -180,7 +181,7 @@ def test_every_traversal_group_size_finds_the_oracle_set(cc, ctx, group):
     finally:
         lib.cc_autotune_force(0, 0)
     table = cc.autotune_table()
-    assert all(e["choice"] in (8, 16, 32) and min(e["ms"]) > 0 for e in table)
+    assert all(e["choice"] in (8, 16, 32, 108, 116, 132) and min(e["ms"]) > 0 for e in table)
 
 
 @pytest.mark.parametrize("cfg", [2, 3, 4, 6])
