@@ -217,6 +217,8 @@ void solver_free(cc_solver* s) {
   bvh_free(s);
   if (s->sel_host) (void)hipHostFree(s->sel_host);
   s->sel_host = nullptr;
+  if (s->hstripe) (void)hipHostFree(s->hstripe);
+  s->hstripe = nullptr;
   dfree(s->dc);
   if (s->hc) (void)hipHostFree(s->hc);
   s->hc = nullptr;
@@ -701,6 +703,12 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
   }
   const int64_t n_eval = s->nP;
   const int64_t npf = (int64_t)s->hc->n_out, na = (int64_t)s->hc->n_act;
+  if (single_live_seg(s)) {  // the pair pass kept no per-segment counts
+    SegDev& d = s->seg_host[0];
+    d.n_p = (d.flags & kSegActive) ? (unsigned long long)n_eval : 0ull;
+    d.n_pf = (unsigned long long)npf;
+    d.n_a = (unsigned long long)na;
+  }
   s->mv_gen = ~0ull;  // valid again once this iteration's forward step has completed
   const uint64_t fp_pf = s->hc->fp_pf, fp_a = s->hc->fp_a;
   if (in_place && npf != n_eval) return CC_EHIP;  // cannot happen: the search kept d < D_max

@@ -268,6 +268,14 @@ struct cc_solver {
   int32_t* root_t = nullptr;       // per selected segment: root of its triangle subtree
   int32_t* root_e = nullptr;       // ... of its edge subtree
   int32_t* root_p = nullptr;       // ... of its particle subtree
+  // search output in kStripes stripes (see lbvh.hip): per stripe its count and the
+  // node records its waves read (kStripeWords words apart), a pinned host mirror,
+  // and the stripes' keys and squared distances, capS entries each
+  unsigned long long* stripe = nullptr;
+  unsigned long long* hstripe = nullptr;
+  uint64_t* skeys = nullptr;
+  double* sd2 = nullptr;
+  int64_t capS = 0;
   // counters
   cc::Counters* dc = nullptr;
   cc::Counters* hc = nullptr;  // pinned host mirror
@@ -324,6 +332,12 @@ int launch_di_init(cc_solver* s, hipStream_t st);
 // Colouring of a contact set of at most kSmallRows rows in one block; colours,
 // buckets and the colour count stay on the device (s->col_small).
 int color_small(cc_solver* s, hipStream_t st);
+// The solver holds one live scene and no removed scene's pairs are left in P: every
+// pair belongs to segment 0, and the pair pass leaves the per-segment counts to the
+// host (evaluated = |P|, kept = |P'|, active = |A|).
+inline bool single_live_seg(const cc_solver* s) {
+  return s->segs.size() == 1 && s->segs[0].live && s->pending_segs.empty();
+}
 // pairs [0, n_old) are last iteration's P'; [n_old, nP) were appended by a search;
 // pairs from d_from on take their squared distance from dP (written by the search)
 int launch_pair_pass(cc_solver* s, int64_t n_old, int64_t d_from, double dl2, bool trace,

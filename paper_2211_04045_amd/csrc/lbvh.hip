@@ -21,6 +21,7 @@
 // Several scenes (segments) are searched together: a segment's rank sits above
 // the Morton code in the sort key, so each segment's leaves form one subtree
 // of the radix tree, and its queries start at that subtree's root.
+#include <algorithm>
 #include <cmath>
 #include <cstddef>
 
@@ -696,9 +697,12 @@ struct TravArgs {
   int32_t mv_pad, me_pad; // the first two counts rounded up to whole waves
   double infl, dmax2;
   float fdmax;  // dmax rounded up to FP32 (the Euclidean box test below)
+  // found pairs go to kStripes stripes of capS entries (keys, and d^2 in the same
+  // function and operand order as the pair pass); null: counted only
   uint64_t* out;
-  double* outd;  // d^2 of each pair found (same function and operand order as the pair pass)
-  int64_t cap;
+  double* outd;
+  int64_t capS;
+  unsigned long long* stripe;  // per stripe: [0] pairs found, [1] node records read
   Counters* cnt;
 };
 
@@ -789,6 +793,8 @@ constexpr int kGroupDefault = 16;
 constexpr int kGStack = 100;                // stack entries per traversal (4-wide DFS)
 constexpr int kQueue = 128;                 // candidate ring per wave (two rounds of 64)
 constexpr int kOut = 192;                   // found pairs held per wave (flushed from 128)
+constexpr int kStripes = 64;                // output stripes of the search
+constexpr int kStripeWords = 16;            // their counters 128 B apart
 
 template <int G>
 struct WaveLds {
@@ -802,18 +808,27 @@ struct WaveLds {
   double od2[kWaves][kOut];
 };
 
-// The wave's held pairs to the output, reserved with one atomic.
+// The wave's held pairs to the output, reserved with one atomic on the count of the
+// wave's next stripe. A device-wide atomic on one address is serialised over the
+// whole GPU (about 12 ns each on MI355X); a wave's flushes rotate over the stripes,
+// so each count takes about 1/kStripes of them and the stripes fill evenly.
 template <class LT>
-__device__ __forceinline__ void flush_out(LT& L, int wv, int& no, const TravArgs& A) {
+__device__ __forceinline__ void flush_out(LT& L, int wv, int& no, unsigned& sidx,
+                                          const TravArgs& A) {
   const int lane = __lane_id();
+  const unsigned sid = sidx & (kStripes - 1);
+  ++sidx;
   unsigned long long base = 0;
-  if (lane == 0) base = atomicAdd(&A.cnt->n_out, (unsigned long long)no);
+  if (lane == 0) base = atomicAdd(&A.stripe[sid * kStripeWords], (unsigned long long)no);
   base = __shfl(base, 0);
-  for (int j = lane; j < no; j += 64) {
-    const int64_t pos = (int64_t)base + j;
-    if (pos < A.cap) {
-      A.out[pos] = L.okey[wv][j];
-      if (A.outd) A.outd[pos] = L.od2[wv][j];
+  if (A.out) {
+    const int64_t s0 = (int64_t)sid * A.capS;
+    for (int j = lane; j < no; j += 64) {
+      const int64_t pos = (int64_t)base + j;
+      if (pos < A.capS) {
+        A.out[s0 + pos] = L.okey[wv][j];
+        if (A.outd) A.outd[s0 + pos] = L.od2[wv][j];
+      }
     }
   }
   no = 0;
@@ -824,7 +839,7 @@ __device__ __forceinline__ void flush_out(LT& L, int wv, int& no, const TravArgs
 // wave's held pairs (no, wave-uniform), written out from 128 on.
 template <class LT>
 __device__ __forceinline__ void drain(LT& L, int wv, int head, int n, int kind, int& no,
-                                      unsigned& ntested, const TravArgs& A) {
+                                      unsigned& sidx, unsigned& ntested, const TravArgs& A) {
   ntested += (unsigned)n;
   const int lane = __lane_id();
   bool found = false;
@@ -848,7 +863,7 @@ __device__ __forceinline__ void drain(LT& L, int wv, int head, int n, int kind, 
   }
   no += __popcll(m);
   __builtin_amdgcn_wave_barrier();
-  if (no >= kOut - 64) flush_out(L, wv, no, A);
+  if (no >= kOut - 64) flush_out(L, wv, no, sidx, A);
 }
 
 // Proximity search (Sec. 3.1). A wave takes 64 consecutive queries of one class
@@ -932,6 +947,7 @@ __global__ void __launch_bounds__(kTravThreads, kGroup == 8 ? 3 : 4) k_traverse(
   L.qi[wv][2][lane] = qv1;
   int head = 0, qn = 0;  // candidate ring: first entry, entries queued (wave-uniform)
   int no = 0;            // found pairs held (wave-uniform)
+  unsigned sidx = blockIdx.x * kWaves + wv;  // the stripe of the wave's next flush
   unsigned ntested = 0;  // candidates tested by the wave
   unsigned nvisit = 0;   // node records this lane's group read (counted by its first lane)
   // a scene with one triangle: its vertices meet the leaf itself (one edge or one
@@ -948,7 +964,7 @@ __global__ void __launch_bounds__(kTravThreads, kGroup == 8 ? 3 : 4) k_traverse(
   }
   __builtin_amdgcn_wave_barrier();
   if (qn == 64) {
-    drain(L, wv, head, 64, kind, no, ntested, A);
+    drain(L, wv, head, 64, kind, no, sidx, ntested, A);
     qn = 0;
     __builtin_amdgcn_wave_barrier();
   }
@@ -1052,19 +1068,52 @@ __global__ void __launch_bounds__(kTravThreads, kGroup == 8 ? 3 : 4) k_traverse(
       qn += __popcll(ml);
       __builtin_amdgcn_wave_barrier();
       while (qn >= 64) {
-        drain(L, wv, head, 64, kind, no, ntested, A);
+        drain(L, wv, head, 64, kind, no, sidx, ntested, A);
         head = (head + 64) & (kQueue - 1);
         qn -= 64;
         __builtin_amdgcn_wave_barrier();
       }
     }
   }
-  if (qn > 0) drain(L, wv, head, qn, kind, no, ntested, A);
-  if (no > 0) flush_out(L, wv, no, A);
+  if (qn > 0) drain(L, wv, head, qn, kind, no, sidx, ntested, A);
+  if (no > 0) flush_out(L, wv, no, sidx, A);
   // node records read by the wave's groups: the measure of the tree's quality
   unsigned long long nv = nvisit;
   for (int o = 32; o >= 1; o >>= 1) nv += __shfl_xor(nv, o);
-  if (lane == 0 && nv) atomicAdd(&A.cnt->ncand, nv);
+  if (lane == 0 && nv) atomicAdd(&A.stripe[(sidx & (kStripes - 1)) * kStripeWords + 1], nv);
+}
+
+// The stripes' pairs, concatenated in stripe order, to out[0, total): offsets from
+// the stripe counts (each at most capS), one wave's scan per block.
+__global__ void __launch_bounds__(256) k_stripe_gather(const unsigned long long* stripe,
+                                                       int64_t capS, const uint64_t* skeys,
+                                                       const double* sd2, uint64_t* out,
+                                                       double* outd, int64_t total) {
+  static_assert(kStripes == 64, "one lane per stripe");
+  __shared__ long long off[kStripes + 1];
+  if (threadIdx.x < 64) {
+    const long long c = (long long)stripe[threadIdx.x * kStripeWords];
+    long long incl = c;
+    for (int o = 1; o < 64; o <<= 1) {
+      const long long t = __shfl_up(incl, o);
+      if ((int)threadIdx.x >= o) incl += t;
+    }
+    off[threadIdx.x + 1] = incl;
+    if (threadIdx.x == 0) off[0] = 0;
+  }
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * 256) {
+    int lo = 0, hi = kStripes;  // off[lo] <= i < off[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (off[mid] <= i) lo = mid;
+      else hi = mid;
+    }
+    const int64_t src = (int64_t)lo * capS + (i - off[lo]);
+    out[i] = skeys[src];
+    if (outd) outd[i] = sd2[src];
+  }
 }
 
 // ------------------------------------------------------- input check (edges)
@@ -1245,6 +1294,13 @@ int bvh_alloc(cc_solver* s) {
     return CC_ENOMEM;
   CC_TRY(dalloc(&s->root_t, kMaxSeg));
   CC_TRY(dalloc(&s->root_e, kMaxSeg));
+  CC_TRY(dalloc(&s->stripe, kStripes * kStripeWords));
+  if (!s->hstripe && hipHostMalloc((void**)&s->hstripe,
+                                   sizeof(unsigned long long) * kStripes * kStripeWords,
+                                   hipHostMallocDefault) != hipSuccess) {
+    s->hstripe = nullptr;
+    return CC_ENOMEM;
+  }
   return CC_OK;
 }
 
@@ -1257,6 +1313,8 @@ void bvh_free(cc_solver* s) {
   dfree(s->ubox_lo); dfree(s->ubox_hi); dfree(s->gprim); dfree(s->rs_hist); dfree(s->bounds);
   dfree(s->bounds_part); dfree(s->vorder); dfree(s->vrank); dfree(s->erank); dfree(s->rs_total);
   dfree(s->sel_dev); dfree(s->root_t); dfree(s->root_e);
+  dfree(s->stripe); dfree(s->skeys); dfree(s->sd2);
+  s->capS = 0;
 }
 
 static inline unsigned blocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -1293,6 +1351,19 @@ static int refit_and_widen(cc_solver* s, int32_t mt, int32_t me, int32_t mp, hip
   if (me > 1) k_wide<<<blocks(me - 1, 256), 256, 0, st>>>(be.node, be.wide, me - 1);
   if (mp > 1) k_wide<<<blocks(mp - 1, 256), 256, 0, st>>>(bp.node, bp.wide, mp - 1);
   CC_HIP(hipGetLastError());
+  return CC_OK;
+}
+
+constexpr size_t kStripeBytes = sizeof(unsigned long long) * kStripes * kStripeWords;
+
+// Stripes of capS entries each (keys and squared distances); the contents go.
+static int grow_stripes(cc_solver* s, int64_t capS) {
+  dfree(s->skeys);
+  dfree(s->sd2);
+  s->capS = 0;
+  CC_TRY(dalloc(&s->skeys, capS * kStripes));
+  CC_TRY(dalloc(&s->sd2, capS * kStripes));
+  s->capS = capS;
   return CC_OK;
 }
 
@@ -1343,6 +1414,8 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
                 "search counters first");
   CC_HIP(hipMemsetAsync(s->dc, 0, offsetof(Counters, ncand) + sizeof(unsigned long long), st));
   *nfound = 0;
+  int64_t nfd = 0;     // pairs found (the stripes' counts)
+  double ncand = 0.0;  // node records read by the traversal
   const int64_t m = (int64_t)mt + me + mp;
   // the tree of the last build serves again (refit) when the same scenes, in the same
   // order, are searched and none of them changed since
@@ -1431,9 +1504,16 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
     A.dmax2 = dmax * dmax;
     A.fdmax = (float)dmax;
     if ((double)A.fdmax < dmax) A.fdmax = nextafterf(A.fdmax, __builtin_inff());
-    A.out = out;
-    A.outd = outd;
-    A.cap = cap;
+    // the stripes: about cap / kStripes each to start with (a quarter more, for the
+    // spread of the stripes' counts), grown below when one overflows
+    if (out && s->capS == 0) {
+      const int64_t c0 = (cap > 0 ? cap : 1) / kStripes;
+      CC_TRY(grow_stripes(s, c0 + c0 / 4 + 1024));
+    }
+    A.out = out ? s->skeys : nullptr;
+    A.outd = out && outd ? s->sd2 : nullptr;
+    A.capS = s->capS;
+    A.stripe = s->stripe;
     A.cnt = s->dc;
     A.mv_pad = (A.mv + 63) & ~63;
     A.me_pad = (me + 63) & ~63;
@@ -1459,6 +1539,7 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
           for (int c = 0; c < 6; ++c) {
             CC_HIP(hipMemsetAsync(s->dc, 0, offsetof(Counters, ncand) + sizeof(unsigned long long),
                                   st));
+            CC_HIP(hipMemsetAsync(s->stripe, 0, kStripeBytes, st));
             CC_HIP(hipEventRecord(e0, st));
             CC_TRY(launch_traverse(cand[c], A, nq, st));
             CC_HIP(hipEventRecord(e1, st));
@@ -1474,21 +1555,48 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
                                 st));
         }
       }
-      timer_begin(s, CC_K_SEARCH, st);
-      CC_TRY(launch_traverse(group, A, nq, st));
-      timer_end(s, st);
+      // a stripe that overflowed is grown to its count and the traversal runs again:
+      // it fills every stripe exactly as before (each wave's flushes, and the stripe
+      // each goes to, depend on its own queries only)
+      for (int attempt = 0;; ++attempt) {
+        CC_HIP(hipMemsetAsync(s->stripe, 0, kStripeBytes, st));
+        timer_begin(s, CC_K_SEARCH, st);
+        CC_TRY(launch_traverse(group, A, nq, st));
+        timer_end(s, st);
+        CC_HIP(hipMemcpyAsync(s->hstripe, s->stripe, kStripeBytes, hipMemcpyDeviceToHost, st));
+        CC_HIP(hipStreamSynchronize(st));
+        unsigned long long mx = 0, tot = 0, nvis = 0;
+        for (int k = 0; k < kStripes; ++k) {
+          mx = std::max(mx, s->hstripe[k * kStripeWords]);
+          tot += s->hstripe[k * kStripeWords];
+          nvis += s->hstripe[k * kStripeWords + 1];
+        }
+        nfd = (int64_t)tot;
+        ncand = (double)nvis;
+        if (!out || (int64_t)mx <= A.capS) break;
+        if (attempt > 0) return CC_EOVERFLOW;  // cannot happen: the counts repeat
+        CC_TRY(grow_stripes(s, (int64_t)mx + (int64_t)mx / 4 + 1024));
+        A.out = s->skeys;
+        A.outd = outd ? s->sd2 : nullptr;
+        A.capS = s->capS;
+      }
+      if (out && nfd > 0 && nfd <= cap) {
+        const int64_t nbg = std::min<int64_t>((nfd + 255) / 256, 8192);
+        k_stripe_gather<<<(unsigned)nbg, 256, 0, st>>>(s->stripe, s->capS, s->skeys, s->sd2, out,
+                                                       outd, nfd);
+      }
     }
   }
   CC_HIP(hipGetLastError());
   CC_HIP(hipMemcpyAsync(s->hc, s->dc, sizeof(Counters), hipMemcpyDeviceToHost, st));
   CC_HIP(hipStreamSynchronize(st));
   if (s->hc->err & 2ull) return CC_EOVERFLOW;
-  *nfound = (int64_t)s->hc->n_out;
+  *nfound = nfd;
   // tree quality: node records read by the traversal; a refitted tree whose
   // traversal reads 30 % more of them than right after its build is built anew at the
   // next search
   if (refit_ok && m > 0) {
-    const double q = (double)s->hc->ncand;
+    const double q = ncand;
     if (!refit) s->bvh_q0 = q;
     else if (q > kRefitSlack * s->bvh_q0) s->bvh_gen = ~0ull;
   }

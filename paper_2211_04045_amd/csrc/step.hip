@@ -327,7 +327,8 @@ struct PairPassArgs {
   Counters* c;
   int trace;
   int in_place;  // every pair is kept (fresh from a search of every scene): P' is P, unwritten
-  int32_t one_seg;  // >= 0: every pair of P belongs to this (the only) segment
+  int32_t one_seg;  // >= 0: every pair of P belongs to this (the only) segment, whose
+                    // counts the host takes from n_out and n_act (none are kept here)
 };
 
 constexpr int kHash = 2048;         // LDS slots for the per-block D_i minimum
@@ -482,13 +483,15 @@ __global__ void __launch_bounds__(kThreads) k_pair_pass(PairPassArgs a) {
         d2s[k] = d2;
         vs[k] = make_int4(v[0], v[1], v[2], v[3]);
         const bool keep = d2 < a.seg[sg].D2, act = keep && d2 < a.dl2;
-        if (sg != csg) {
+        if (sg != csg && a.one_seg < 0) {
           seg_count_flush(gkey, gcnt, a.seg, csg, cnt);
           csg = sg;
         }
-        cnt[0] += 1;
-        cnt[1] += keep ? 1 : 0;
-        cnt[2] += act ? 1 : 0;
+        if (a.one_seg < 0) {
+          cnt[0] += 1;
+          cnt[1] += keep ? 1 : 0;
+          cnt[2] += act ? 1 : 0;
+        }
         if (keep) {
           keepm |= 1u << k;
           if (a.trace) f1 += fp_key(key);
@@ -521,7 +524,13 @@ __global__ void __launch_bounds__(kThreads) k_pair_pass(PairPassArgs a) {
   int ok = block_excl_scan(nk, ssc, &tk);
   int oa = block_excl_scan(na, ssc, &ta);
   if (threadIdx.x == 0) {
-    sbase[0] = tk ? atomicAdd(&a.c->n_out, (unsigned long long)tk) : 0ull;
+    // P' kept in place needs no offsets: its count goes out without a return
+    if (a.in_place) {
+      if (tk) atomicAdd(&a.c->n_out, (unsigned long long)tk);
+      sbase[0] = 0ull;
+    } else {
+      sbase[0] = tk ? atomicAdd(&a.c->n_out, (unsigned long long)tk) : 0ull;
+    }
     sbase[1] = ta ? atomicAdd(&a.c->n_act, (unsigned long long)ta) : 0ull;
   }
   if (threadIdx.x < kSegSlots && gkey[threadIdx.x] >= 0) {
@@ -585,7 +594,7 @@ int launch_pair_pass(cc_solver* s, int64_t n_old, int64_t d_from, double dl2, bo
   a.in_place = in_place ? 1 : 0;
   // one scene and no removed scene's pairs left in P: the segment of a pair is known
   // without its vertex's segment id
-  a.one_seg = (s->segs.size() == 1 && s->segs[0].live && s->pending_segs.empty()) ? 0 : -1;
+  a.one_seg = single_live_seg(s) ? 0 : -1;
   if (s->nP > 0) k_pair_pass<<<nblk(s->nP, kThreads * kPairsPerThread), kThreads, 0, st>>>(a);
   CC_HIP(hipGetLastError());
   return CC_OK;
