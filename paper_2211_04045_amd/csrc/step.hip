@@ -379,20 +379,26 @@ __device__ __forceinline__ void seg_count_flush(int32_t* gkey, unsigned long lon
   cnt[0] = cnt[1] = cnt[2] = 0;
 }
 
-// Push the block's per-vertex minima to the global D_i and clear the table.
-__device__ __forceinline__ void flush_min_table(int32_t* hkey, unsigned long long* hval,
-                                                unsigned long long* Di) {
-  __syncthreads();
-  for (int t = threadIdx.x; t < kHash; t += kThreads) {
-    int32_t vv = hkey[t];
-    if (vv >= 0) {
-      unsigned long long b = hval[t];
-      atomicMin(&Di[vv], b);  // no read first: the wave does not wait on it
-      hkey[t] = -1;
-      hval[t] = ~0ull;
+// The block's minimum of d for vertex v in its LDS table (open addressing over kHash
+// slots, the slots taken listed in occ); past kProbe probes it goes straight to the
+// global D_i. Minima of the bit patterns of non-negative doubles are exact and
+// independent of order, so either path gives the same D_i.
+constexpr int kProbe = 32;
+__device__ __forceinline__ void min_insert(int32_t* hkey, unsigned long long* hval,
+                                           int16_t* occ, int* nocc, unsigned long long* Di,
+                                           int32_t v, unsigned long long bits) {
+  uint32_t h = ((uint32_t)v * 2654435761u) >> 21;  // 11 bits
+#pragma unroll 1
+  for (int p = 0; p < kProbe; ++p) {
+    const int32_t prev = atomicCAS(&hkey[h], -1, v);
+    if (prev == -1 || prev == v) {
+      if (prev == -1) occ[atomicAdd(nocc, 1)] = (int16_t)h;
+      atomicMin(&hval[h], bits);
+      return;
     }
+    h = (h + 1) & (kHash - 1);
   }
-  __syncthreads();
+  atomicMin(&Di[v], bits);
 }
 
 // Distances at x^(l) for every p in P; P' = {d^2 < D^2} (Sec. 3.1 filter),
@@ -400,14 +406,16 @@ __device__ __forceinline__ void flush_min_table(int32_t* hkey, unsigned long lon
 // D is the pair's segment's; pairs of segments that do not iterate, and pairs of
 // last iteration's P' whose segment was searched again, are dropped unevaluated.
 // Each block handles kThreads*kPairsPerThread consecutive pairs. The minimum is
-// first taken in an LDS hash table keyed by vertex (flushed after every 256 pairs,
-// so it is never more than half full), then one global atomic per distinct vertex
-// (min is exact and order independent on the bit patterns of non-negative
-// doubles). P' and A are compacted with one counter atomic per block; the
-// per-segment counts go through a small LDS table.
+// first taken in an LDS hash table keyed by vertex, then one global atomic per
+// distinct vertex of the block, at its end, over the list of slots taken (min is
+// exact and order independent on the bit patterns of non-negative doubles). P' and
+// A are compacted with one counter atomic per block; the per-segment counts go
+// through a small LDS table.
 __global__ void __launch_bounds__(kThreads) k_pair_pass(PairPassArgs a) {
   __shared__ int32_t hkey[kHash];
   __shared__ unsigned long long hval[kHash];
+  __shared__ int16_t occ[kHash];
+  __shared__ int nocc;
   __shared__ int ssc[kThreads / 64 + 1];
   __shared__ unsigned long long sbase[2];
   __shared__ int32_t gkey[kSegSlots];
@@ -416,6 +424,7 @@ __global__ void __launch_bounds__(kThreads) k_pair_pass(PairPassArgs a) {
     hkey[t] = -1;
     hval[t] = ~0ull;
   }
+  if (threadIdx.x == 0) nocc = 0;
   if (threadIdx.x < kSegSlots) {
     gkey[threadIdx.x] = -1;
     gcnt[threadIdx.x][0] = gcnt[threadIdx.x][1] = gcnt[threadIdx.x][2] = 0ull;
@@ -501,24 +510,17 @@ __global__ void __launch_bounds__(kThreads) k_pair_pass(PairPassArgs a) {
           }
           unsigned long long bits = (unsigned long long)__double_as_longlong(sqrt(d2));
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            uint32_t h = ((uint32_t)v[q] * 2654435761u) >> 21;  // 11 bits
-            for (;;) {
-              int32_t prev = atomicCAS(&hkey[h], -1, v[q]);
-              if (prev == -1 || prev == v[q]) {
-                atomicMin(&hval[h], bits);
-                break;
-              }
-              h = (h + 1) & (kHash - 1);
-            }
-          }
+          for (int q = 0; q < 4; ++q) min_insert(hkey, hval, occ, &nocc, a.Di, v[q], bits);
         }
       }
     }
-    flush_min_table(hkey, hval, a.Di);
   }
   seg_count_flush(gkey, gcnt, a.seg, csg, cnt);
   __syncthreads();
+  for (int t = threadIdx.x; t < nocc; t += kThreads) {
+    const int h = occ[t];
+    atomicMin(&a.Di[hkey[h]], hval[h]);  // no read first: the wave does not wait on it
+  }
   // block-level compaction of P' and A
   int nk = __popc(keepm), na = __popc(actm), tk = 0, ta = 0;
   int ok = block_excl_scan(nk, ssc, &tk);
