@@ -882,7 +882,8 @@ __device__ __forceinline__ void drain(LT& L, int wv, int head, int n, int kind, 
 template <int kGroup, int kPop>
 __global__ void __launch_bounds__(kTravThreads, kGroup == 8 ? 3 : 4) k_traverse(TravArgs A) {
   __shared__ WaveLds<kGroup> L;
-  const int lane = __lane_id(), wv = threadIdx.x >> 6;
+  // the wave index is uniform over the wave: held in a scalar register
+  const int lane = __lane_id(), wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int grp = lane / kGroup, gl = lane % kGroup;
   const uint64_t gmask = (kGroup == 64 ? ~0ull : ((1ull << kGroup) - 1ull)) << (grp * kGroup);
   const int32_t q0 = blockIdx.x * kTravThreads + wv * 64;  // the wave's first padded query
