@@ -219,6 +219,7 @@ void solver_free(cc_solver* s) {
   s->sel_host = nullptr;
   if (s->hstripe) (void)hipHostFree(s->hstripe);
   s->hstripe = nullptr;
+  ecache_free(s);
   dfree(s->dc);
   if (s->hc) (void)hipHostFree(s->hc);
   s->hc = nullptr;
@@ -237,6 +238,7 @@ void solver_free(cc_solver* s) {
 // reallocated empty.
 int resize_arrays(cc_solver* s, int32_t capV, int32_t capF, int32_t capE, hipStream_t st) {
   const int64_t oV = s->capV, oF = s->capF, oE = s->capE;
+  s->ecache.ok = false;
   // pair keys hold primitive ids in 30 bits
   if (capV > kMaxIds || capF > kMaxIds || capE > kMaxIds) return CC_ENOMEM;
   if (capV != oV) {
@@ -587,15 +589,30 @@ int seg_begin(cc_solver* s, const int32_t* sgs, int32_t k, const double* const* 
     }
     if (rc[i] == CC_OK) ok.push_back(i);
   }
+  // a lone scene whose edges, rows, free vertices, seed and palette repeat those of
+  // its last edge colouring keeps that colouring (checked element by element)
+  const bool lone = k == 1 && ok.size() == 1 && sgs[0] == 0 && s->segs.size() == 1 &&
+                    s->segs[0].vb == 0 && s->segs[0].eb == 0 && s->pending_segs.empty();
+  const cc_solver::EdgeColourCache& ec = s->ecache;
+  const bool ec_try = lone && ec.ok && ec.seed == s->p.seed && ec.maxc == s->p.max_colors &&
+                      ec.ne == s->segs[0].ne && ec.nv == s->segs[0].nv;
+  if (ec_try) CC_TRY(ecache_compare(s, st));
   CC_HIP(hipMemcpyAsync(&s->hc->n_rows, &s->dc->n_rows, sizeof(unsigned long long),
                         hipMemcpyDeviceToHost, st));
+  if (ec_try)
+    CC_HIP(hipMemcpyAsync(&s->hc->ecmis, &s->dc->ecmis, sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, st));
   CC_HIP(hipStreamSynchronize(st));
   s->n_newrows = (int32_t)s->hc->n_rows;
   int crc = CC_OK;
   if (s->p.backward != CC_JACOBI) {  // the Jacobi step needs no colours
-    timer_begin(s, CC_K_COLOR, st);
-    crc = color_rows(s, true, st);
-    timer_end(s, st);
+    const bool reuse = ec_try && s->hc->ecmis == 0 && s->n_newrows == ec.rows;
+    if (!reuse) {
+      timer_begin(s, CC_K_COLOR, st);
+      crc = color_rows(s, true, st);
+      timer_end(s, st);
+      if (crc == CC_OK && lone) crc = ecache_store(s, st);
+    }
   }
   if (crc == CC_OK)
     crc = hipMemcpyAsync(s->seg_host, s->seg_dev, sizeof(SegDev) * s->segs.size(),
@@ -702,7 +719,7 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
     CC_HIP(hipMemcpyAsync(s->seg_dev, s->seg_host, sizeof(SegDev) * ns, hipMemcpyHostToDevice, st));
   }
   const int64_t n_eval = s->nP;
-  const int64_t npf = (int64_t)s->hc->n_out, na = (int64_t)s->hc->n_act;
+  const int64_t npf = in_place ? n_eval : (int64_t)s->hc->n_out, na = (int64_t)s->hc->n_act;
   if (single_live_seg(s)) {  // the pair pass kept no per-segment counts
     SegDev& d = s->seg_host[0];
     d.n_p = (d.flags & kSegActive) ? (unsigned long long)n_eval : 0ull;
@@ -711,7 +728,6 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
   }
   s->mv_gen = ~0ull;  // valid again once this iteration's forward step has completed
   const uint64_t fp_pf = s->hc->fp_pf, fp_a = s->hc->fp_a;
-  if (in_place && npf != n_eval) return CC_EHIP;  // cannot happen: the search kept d < D_max
   if (!in_place) {
     std::swap(s->P, s->P2);
     std::swap(s->dP, s->dP2);

@@ -83,6 +83,7 @@ struct Counters {
   unsigned long long hits;      // continuous-test contacts among the failures
   unsigned long long et;        // input check: an edge meets a triangle
   unsigned long long ncert;     // certificate: pairs queued for the continuous test
+  unsigned long long ecmis;     // edge colouring cache: inputs differing from the last
 };
 
 // Device buffers of a linear BVH over n leaves (n-1 internal nodes), allocated
@@ -239,6 +240,18 @@ struct cc_solver {
   int32_t n_erows = 0, n_ecolors = 0;  // rows in the union buckets, their colours
   int32_t n_newrows = 0;               // rows being coloured at a begin
   std::vector<int32_t> ecol_off;
+  // the last edge-row colouring of a lone scene, reused while its inputs repeat:
+  // the colouring is a function of the edges, the rows present, the free vertices,
+  // the seed and the palette alone
+  struct EdgeColourCache {
+    bool ok = false;
+    uint64_t seed = 0;
+    int32_t maxc = 0, ne = 0, nv = 0, rows = 0;
+    int32_t* edges = nullptr;   // 2 per edge
+    uint8_t* row = nullptr;     // per edge: 1 = carries a row
+    uint8_t* freev = nullptr;   // per vertex: 1 = free (w > 0)
+    int32_t cap_e = 0, cap_v = 0;
+  } ecache;
   // colouring scratch
   unsigned long long *vmax0 = nullptr, *masks = nullptr;  // per vertex: row count, used colours
   unsigned long long* claims = nullptr;  // per vertex: colours claimed this round, and clashes
@@ -344,6 +357,11 @@ int launch_pair_pass(cc_solver* s, int64_t n_old, int64_t d_from, double dl2, bo
                      bool in_place, hipStream_t st);
 // contacts: colour A; edges: colour the n_newrows rows listed in elist0
 int color_rows(cc_solver* s, bool edges, hipStream_t st);
+// Edge colouring cache of a lone scene (segment 0 at offset 0): compare the inputs
+// with the cached ones (counted into dc->ecmis, cleared here), or store them.
+int ecache_compare(cc_solver* s, hipStream_t st);
+int ecache_store(cc_solver* s, hipStream_t st);
+void ecache_free(cc_solver* s);
 int build_edge_buckets(cc_solver* s, hipStream_t st);
 int launch_gs(cc_solver* s, hipStream_t st);
 int launch_jacobi(cc_solver* s, hipStream_t st);

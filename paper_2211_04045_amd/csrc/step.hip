@@ -33,6 +33,38 @@ __device__ __forceinline__ unsigned long long wave_append(bool pred, unsigned lo
   return base + (unsigned long long)__popcll(m & lanes_below());
 }
 
+// The block-wide form of wave_append, for kernels whose every thread reaches it:
+// one global atomic per block. A device-wide atomic on one address is serialised
+// over the whole GPU (about 12 ns each on MI355X), so one per wave over a grid of
+// a few thousand waves costs tens of microseconds. *total gets the block's count.
+__device__ __forceinline__ unsigned long long block_append(bool pred,
+                                                           unsigned long long* counter,
+                                                           int* total) {
+  __shared__ int s_cnt[kThreads / 64];
+  __shared__ unsigned long long s_base;
+  const uint64_t m = __ballot(pred);
+  const int wv = threadIdx.x >> 6;
+  if (__lane_id() == 0) s_cnt[wv] = __popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int w = 0; w < kThreads / 64; ++w) {
+      const int t = s_cnt[w];
+      s_cnt[w] = run;
+      run += t;
+    }
+    s_base = run ? atomicAdd(counter, (unsigned long long)run) : 0ull;
+    s_cnt[0] = run;  // wave 0's offset is 0: the slot carries the total meanwhile
+  }
+  __syncthreads();
+  const int off = wv == 0 ? 0 : s_cnt[wv];
+  *total = s_cnt[0];
+  const unsigned long long pos = s_base + (unsigned long long)off +
+                                 (unsigned long long)__popcll(m & lanes_below());
+  __syncthreads();  // the slots are free again when the function returns
+  return pos;
+}
+
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
   return v;
@@ -240,11 +272,10 @@ __global__ void k_edge_rows(const int32_t* __restrict__ edges, int32_t eb, int32
     }
     einv[ge] = inv;
   }
-  unsigned long long pos = wave_append(valid, &c->n_rows);
+  int nblock = 0;
+  const unsigned long long pos = block_append(valid, &c->n_rows, &nblock);
   if (valid) list[pos] = eb + e;
-  uint64_t m = __ballot(valid);
-  if (m && __lane_id() == __ffsll((long long)m) - 1)
-    atomicAdd(seg_rows, (unsigned long long)__popcll(m));
+  if (threadIdx.x == 0 && nblock) atomicAdd(seg_rows, (unsigned long long)nblock);
 }
 
 // Begin of one segment: state arrays and its edge-length rows (appended to
@@ -526,13 +557,9 @@ __global__ void __launch_bounds__(kThreads) k_pair_pass(PairPassArgs a) {
   int ok = block_excl_scan(nk, ssc, &tk);
   int oa = block_excl_scan(na, ssc, &ta);
   if (threadIdx.x == 0) {
-    // P' kept in place needs no offsets: its count goes out without a return
-    if (a.in_place) {
-      if (tk) atomicAdd(&a.c->n_out, (unsigned long long)tk);
-      sbase[0] = 0ull;
-    } else {
-      sbase[0] = tk ? atomicAdd(&a.c->n_out, (unsigned long long)tk) : 0ull;
-    }
+    // P' kept in place is P (each pair's stored d^2 came from the search, which kept
+    // d^2 < D_max^2 by the same comparison): neither offsets nor a count
+    sbase[0] = (!a.in_place && tk) ? atomicAdd(&a.c->n_out, (unsigned long long)tk) : 0ull;
     sbase[1] = ta ? atomicAdd(&a.c->n_act, (unsigned long long)ta) : 0ull;
   }
   if (threadIdx.x < kSegSlots && gkey[threadIdx.x] >= 0) {
@@ -732,9 +759,11 @@ __device__ __forceinline__ void pc_pick(const PcArgs& a, int32_t r, uint64_t t) 
     }
 }
 
-// Returns true when the row stays uncoloured.
+// Returns true when the row stays uncoloured; *colored gets the colour it took
+// (-1 when it stays). The caller raises c->ncol to the colours taken.
 template <bool kAtomicLoads>
-__device__ __forceinline__ bool pc_resolve(const PcArgs& a, int32_t r) {
+__device__ __forceinline__ bool pc_resolve(const PcArgs& a, int32_t r, int* colored) {
+  *colored = -1;
   uint64_t key;
   int32_t v[4];
   a.src.get(r, key, v);
@@ -753,7 +782,7 @@ __device__ __forceinline__ bool pc_resolve(const PcArgs& a, int32_t r) {
   for (int k = 0; k < 4; ++k)
     if (is_free(a.w, v[k])) atomicOr(&a.masks[(int64_t)v[k] * kMaskWords + col / 64], bit);
   a.colors[r] = col;
-  atomicMax(&a.c->ncol, (unsigned long long)(col + 1));
+  *colored = col;
   return false;
 }
 
@@ -790,12 +819,24 @@ __global__ void __launch_bounds__(kThreads) k_pc_resolve(PcArgs a, const int32_t
                                                          const unsigned long long* nlist,
                                                          int32_t* list_out,
                                                          unsigned long long* nout) {
+  __shared__ int s_max[kThreads / 64];
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = t < (int64_t)*nlist;
   const int32_t r = valid ? list[t] : 0;
-  const bool stay = valid && pc_resolve<false>(a, r);
-  const unsigned long long pos = wave_append(stay, nout);
+  int col = -1;
+  const bool stay = valid && pc_resolve<false>(a, r, &col);
+  int nblock = 0;
+  const unsigned long long pos = block_append(stay, nout, &nblock);
   if (stay) list_out[pos] = r;
+  // the block's largest colour taken: one atomic per block
+  for (int o = 32; o >= 1; o >>= 1) col = max(col, __shfl_xor(col, o));
+  if (__lane_id() == 0) s_max[threadIdx.x >> 6] = col;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int mx = s_max[0];
+    for (int w = 1; w < kThreads / 64; ++w) mx = max(mx, s_max[w]);
+    if (mx >= 0) atomicMax(&a.c->ncol, (unsigned long long)(mx + 1));
+  }
 }
 
 __global__ void __launch_bounds__(kThreads) k_pc_clear(PcArgs a, const int32_t* list,
@@ -821,7 +862,9 @@ __device__ void pc_rounds_block(const PcArgs& a, int32_t* cur, int32_t* nxt, int
     __syncthreads();
     for (int32_t i = threadIdx.x; i < nc; i += blockDim.x) {
       const int32_t r = cur[i];
-      if (pc_resolve<true>(a, r)) nxt[atomicAdd(nnext, 1)] = r;
+      int col;
+      if (pc_resolve<true>(a, r, &col)) nxt[atomicAdd(nnext, 1)] = r;
+      else atomicMax(&a.c->ncol, (unsigned long long)(col + 1));
     }
     __syncthreads();
     for (int32_t i = threadIdx.x; i < nc; i += blockDim.x) pc_clear(a, cur[i]);
@@ -1236,6 +1279,7 @@ int color_small(cc_solver* s, hipStream_t st) {
 int color_rows(cc_solver* s, bool edges, hipStream_t st) {
   const int64_t nrows = edges ? s->n_newrows : s->nA;
   int32_t* colors = edges ? s->ecol : s->Acol;
+  if (edges) s->ecache.ok = false;  // the cached colours are overwritten from here on
   if (!edges) {
     s->col_off.assign(1, 0);
     s->n_colors = 0;
@@ -1322,6 +1366,88 @@ int color_rows(cc_solver* s, bool edges, hipStream_t st) {
   off.resize(ncol + 1);
   s->n_colors = ncol;
   return CC_OK;
+}
+
+// ------------------------------------------------------------- edge colouring cache
+
+__global__ void k_ecache(const int32_t* __restrict__ edges, const double* __restrict__ einv,
+                         const double* __restrict__ w, int32_t ne, int32_t nv,
+                         int32_t* __restrict__ cedges, uint8_t* __restrict__ crow,
+                         uint8_t* __restrict__ cfree, int store, unsigned long long* mis) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool diff = false;
+  if (i < ne) {
+    const int32_t a = edges[2 * i], b = edges[2 * i + 1];
+    const uint8_t r = einv[i] != 0.0 ? 1 : 0;
+    if (store) {
+      cedges[2 * i] = a;
+      cedges[2 * i + 1] = b;
+      crow[i] = r;
+    } else {
+      diff = cedges[2 * i] != a || cedges[2 * i + 1] != b || crow[i] != r;
+    }
+  }
+  if (i < nv) {
+    const uint8_t f = w[i] > 0.0 ? 1 : 0;
+    if (store) cfree[i] = f;
+    else diff = diff || cfree[i] != f;
+  }
+  if (__any(diff) && __lane_id() == 0) atomicAdd(mis, 1ull);  // only on a difference
+}
+
+int ecache_compare(cc_solver* s, hipStream_t st) {
+  auto& c = s->ecache;
+  CC_HIP(hipMemsetAsync(&s->dc->ecmis, 0, sizeof(unsigned long long), st));
+  const int32_t n = std::max(c.ne, c.nv);
+  if (n > 0)
+    k_ecache<<<nblk(n), kThreads, 0, st>>>(s->edges, s->einv, s->w, c.ne, c.nv, c.edges, c.row,
+                                           c.freev, 0, &s->dc->ecmis);
+  CC_HIP(hipGetLastError());
+  return CC_OK;
+}
+
+int ecache_store(cc_solver* s, hipStream_t st) {
+  auto& c = s->ecache;
+  c.ok = false;
+  const Seg& g = s->segs[0];
+  if (g.ne > c.cap_e) {
+    if (c.edges) (void)hipFree(c.edges);
+    if (c.row) (void)hipFree(c.row);
+    c.edges = nullptr;
+    c.row = nullptr;
+    c.cap_e = 0;
+    if (hipMalloc((void**)&c.edges, sizeof(int32_t) * 2 * (size_t)g.ne) != hipSuccess ||
+        hipMalloc((void**)&c.row, (size_t)g.ne) != hipSuccess)
+      return CC_OK;  // no cache: the next begin colours again
+    c.cap_e = g.ne;
+  }
+  if (g.nv > c.cap_v) {
+    if (c.freev) (void)hipFree(c.freev);
+    c.freev = nullptr;
+    c.cap_v = 0;
+    if (hipMalloc((void**)&c.freev, (size_t)g.nv) != hipSuccess) return CC_OK;
+    c.cap_v = g.nv;
+  }
+  const int32_t n = std::max(g.ne, g.nv);
+  if (n > 0)
+    k_ecache<<<nblk(n), kThreads, 0, st>>>(s->edges, s->einv, s->w, g.ne, g.nv, c.edges, c.row,
+                                           c.freev, 1, &s->dc->ecmis);
+  CC_HIP(hipGetLastError());
+  c.ok = true;
+  c.seed = s->p.seed;
+  c.maxc = s->p.max_colors;
+  c.ne = g.ne;
+  c.nv = g.nv;
+  c.rows = s->n_newrows;
+  return CC_OK;
+}
+
+void ecache_free(cc_solver* s) {
+  auto& c = s->ecache;
+  if (c.edges) (void)hipFree(c.edges);
+  if (c.row) (void)hipFree(c.row);
+  if (c.freev) (void)hipFree(c.freev);
+  c = cc_solver::EdgeColourCache{};
 }
 
 // Edge rows of every iterating segment, bucketed by colour (rows of one colour

@@ -223,6 +223,27 @@ def test_collide_step_matches_oracle_run(cc, ctx):
     assert np.array_equal(got2.cpu().numpy(), want)
 
 
+def test_edge_colouring_reuse_follows_its_inputs(cc, ctx):
+    # Steps of one scene keep their edge-row colouring while the edges, the rows,
+    # the free vertices, the seed and the palette repeat; each change below must
+    # colour again and still give the oracle's step.
+    base = scenes.config(2, small=True)
+    pinned_w = base["w"].copy()
+    pinned_w[0] = 0.0
+    swapped = base["edges"].copy()
+    swapped[5] = swapped[5][::-1]
+    cases = [("first", {}, {}), ("repeat", {}, {}), ("pinned vertex", {"w": pinned_w}, {}),
+             ("back", {}, {}), ("seed", {}, {"seed": 12345}), ("swapped edge", {"edges": swapped}, {}),
+             ("palette", {}, {"max_colors": 512}), ("repeat again", {}, {})]
+    for name, sc_over, p_over in cases:
+        sc = dict(base, **sc_over)
+        prm = dict(sc["params"], **p_over)
+        want, n, _ = oracle.collide_step(sc, **p_over)
+        got, st = cc.collide_step(ctx, sc["x"], sc["xt"], sc["w"], sc["tris"], sc["edges"], **prm)
+        assert st["iters"] == n and st["status"] == 0, name
+        assert np.array_equal(got.cpu().numpy(), want), name
+
+
 def _full_step_sampled(cc, ctx, sc, samples, **over):
     """A full-size workload in the benchmark's launch configuration: the GPU runs the
     whole step (to the stop test or L); at the sampled iterations and at the last one
