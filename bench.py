@@ -474,7 +474,7 @@ def copy_probe():
     torch.cuda.synchronize()
 
 
-TRAFFIC_KERNELS = ("k_pair_pass", "k_traverse", "k_forward", "k_cert", "k_gs_contact")
+TRAFFIC_KERNELS = ("k_pair_pass", "k_traverse", "k_stripe_gather", "k_forward", "k_cert", "k_gs_contact")
 
 
 def digest_pmc(fetch_csv, write_csv):
@@ -511,7 +511,13 @@ def digest_pmc(fetch_csv, write_csv):
             ds = [d for d in vals if ("::" + k + "(") in names[d] or ("::" + k + "<") in names[d]]
             if not ds:
                 continue
-            e = out.setdefault(k, {"launches": len(ds)})
+            # a template kernel: the instance launched most (the autotuner's choice;
+            # the other launch shapes run once each on the first search)
+            inst = {}
+            for d in ds:
+                inst.setdefault(names[d].split("(")[0], []).append(d)
+            name, ds = max(inst.items(), key=lambda kv: len(kv[1]))
+            e = out.setdefault(k, {"launches": len(ds), "instance": name})
             e[counter.lower() + "_bytes_per_launch"] = sum(vals[d] for d in ds) * 1024 / len(ds) / scale
             e[counter.lower() + "_scale"] = scale
     for k, e in out.items():
