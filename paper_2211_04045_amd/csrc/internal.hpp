@@ -281,14 +281,20 @@ struct cc_solver {
   int32_t* root_t = nullptr;       // per selected segment: root of its triangle subtree
   int32_t* root_e = nullptr;       // ... of its edge subtree
   int32_t* root_p = nullptr;       // ... of its particle subtree
-  // search output in kStripes stripes (see lbvh.hip): per stripe its count and the
-  // node records its waves read (kStripeWords words apart), a pinned host mirror,
-  // and the stripes' keys and squared distances, capS entries each
+  // search output in kStripes stripes (see lbvh.hip): per stripe its counts (runs
+  // << 40 | pairs) and the node records its waves read (kStripeWords words apart), a
+  // pinned host mirror, and the stripes' keys and squared distances, capS entries each
   unsigned long long* stripe = nullptr;
   unsigned long long* hstripe = nullptr;
   uint64_t* skeys = nullptr;
   double* sd2 = nullptr;
   int64_t capS = 0;
+  // the runs written into the stripes (capC per stripe: wave, offset in the wave's
+  // output, length, start in the stripe), and per wave its pair count, then offset
+  int4* chunks = nullptr;
+  int64_t capC = 0;
+  long long* wtot = nullptr;
+  int64_t capW = 0;
   // counters
   cc::Counters* dc = nullptr;
   cc::Counters* hc = nullptr;  // pinned host mirror

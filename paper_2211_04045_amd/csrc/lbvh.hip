@@ -702,7 +702,10 @@ struct TravArgs {
   uint64_t* out;
   double* outd;
   int64_t capS;
-  unsigned long long* stripe;  // per stripe: [0] pairs found, [1] node records read
+  unsigned long long* stripe;  // per stripe: [0] runs << 40 | pairs, [1] node records read
+  int4* chunks;                // per stripe capC runs: wave, offset in its output, length, start
+  int64_t capC;
+  long long* wtot;             // per wave: pairs found
   Counters* cnt;
 };
 
@@ -795,6 +798,8 @@ constexpr int kQueue = 128;                 // candidate ring per wave (two roun
 constexpr int kOut = 192;                   // found pairs held per wave (flushed from 128)
 constexpr int kStripes = 64;                // output stripes of the search
 constexpr int kStripeWords = 16;            // their counters 128 B apart
+constexpr int kRunShift = 40;               // a stripe counter: runs << 40 | pairs
+constexpr unsigned long long kPairMask = (1ull << kRunShift) - 1ull;
 
 template <int G>
 struct WaveLds {
@@ -808,19 +813,24 @@ struct WaveLds {
   double od2[kWaves][kOut];
 };
 
-// The wave's held pairs to the output, reserved with one atomic on the count of the
-// wave's next stripe. A device-wide atomic on one address is serialised over the
-// whole GPU (about 12 ns each on MI355X); a wave's flushes rotate over the stripes,
-// so each count takes about 1/kStripes of them and the stripes fill evenly.
+// The wave's held pairs to the output as one run, reserved with one atomic on the
+// counts of the wave's next stripe. A device-wide atomic on one address is
+// serialised over the whole GPU (about 12 ns each on MI355X); a wave's flushes
+// rotate over the stripes, so each count takes about 1/kStripes of them and the
+// stripes fill evenly. The run is recorded (wave, its offset in the wave's output,
+// length, start) so that the gather can lay out P wave by wave.
 template <class LT>
 __device__ __forceinline__ void flush_out(LT& L, int wv, int& no, unsigned& sidx,
-                                          const TravArgs& A) {
+                                          long long& wrun, const TravArgs& A) {
   const int lane = __lane_id();
   const unsigned sid = sidx & (kStripes - 1);
   ++sidx;
-  unsigned long long base = 0;
-  if (lane == 0) base = atomicAdd(&A.stripe[sid * kStripeWords], (unsigned long long)no);
-  base = __shfl(base, 0);
+  unsigned long long old = 0;
+  if (lane == 0)
+    old = atomicAdd(&A.stripe[sid * kStripeWords],
+                    (1ull << kRunShift) | (unsigned long long)no);
+  old = __shfl(old, 0);
+  const unsigned long long base = old & kPairMask;
   if (A.out) {
     const int64_t s0 = (int64_t)sid * A.capS;
     for (int j = lane; j < no; j += 64) {
@@ -830,7 +840,12 @@ __device__ __forceinline__ void flush_out(LT& L, int wv, int& no, unsigned& sidx
         if (A.outd) A.outd[s0 + pos] = L.od2[wv][j];
       }
     }
+    const int64_t run = (int64_t)(old >> kRunShift);
+    if (lane == 0 && run < A.capC)
+      A.chunks[(int64_t)sid * A.capC + run] =
+          make_int4((int)(blockIdx.x * kWaves + wv), (int)wrun, no, (int)base);
   }
+  wrun += no;
   no = 0;
   __builtin_amdgcn_wave_barrier();
 }
@@ -839,7 +854,8 @@ __device__ __forceinline__ void flush_out(LT& L, int wv, int& no, unsigned& sidx
 // wave's held pairs (no, wave-uniform), written out from 128 on.
 template <class LT>
 __device__ __forceinline__ void drain(LT& L, int wv, int head, int n, int kind, int& no,
-                                      unsigned& sidx, unsigned& ntested, const TravArgs& A) {
+                                      unsigned& sidx, long long& wrun, unsigned& ntested,
+                                      const TravArgs& A) {
   ntested += (unsigned)n;
   const int lane = __lane_id();
   bool found = false;
@@ -863,7 +879,7 @@ __device__ __forceinline__ void drain(LT& L, int wv, int head, int n, int kind, 
   }
   no += __popcll(m);
   __builtin_amdgcn_wave_barrier();
-  if (no >= kOut - 64) flush_out(L, wv, no, sidx, A);
+  if (no >= kOut - 64) flush_out(L, wv, no, sidx, wrun, A);
 }
 
 // Proximity search (Sec. 3.1). A wave takes 64 consecutive queries of one class
@@ -949,6 +965,7 @@ __global__ void __launch_bounds__(kTravThreads, kGroup == 8 ? 3 : 4) k_traverse(
   int head = 0, qn = 0;  // candidate ring: first entry, entries queued (wave-uniform)
   int no = 0;            // found pairs held (wave-uniform)
   unsigned sidx = blockIdx.x * kWaves + wv;  // the stripe of the wave's next flush
+  long long wrun = 0;                         // pairs the wave has written out
   unsigned ntested = 0;  // candidates tested by the wave
   unsigned nvisit = 0;   // node records this lane's group read (counted by its first lane)
   // a scene with one triangle: its vertices meet the leaf itself (one edge or one
@@ -965,7 +982,7 @@ __global__ void __launch_bounds__(kTravThreads, kGroup == 8 ? 3 : 4) k_traverse(
   }
   __builtin_amdgcn_wave_barrier();
   if (qn == 64) {
-    drain(L, wv, head, 64, kind, no, sidx, ntested, A);
+    drain(L, wv, head, 64, kind, no, sidx, wrun, ntested, A);
     qn = 0;
     __builtin_amdgcn_wave_barrier();
   }
@@ -1069,51 +1086,82 @@ __global__ void __launch_bounds__(kTravThreads, kGroup == 8 ? 3 : 4) k_traverse(
       qn += __popcll(ml);
       __builtin_amdgcn_wave_barrier();
       while (qn >= 64) {
-        drain(L, wv, head, 64, kind, no, sidx, ntested, A);
+        drain(L, wv, head, 64, kind, no, sidx, wrun, ntested, A);
         head = (head + 64) & (kQueue - 1);
         qn -= 64;
         __builtin_amdgcn_wave_barrier();
       }
     }
   }
-  if (qn > 0) drain(L, wv, head, qn, kind, no, sidx, ntested, A);
-  if (no > 0) flush_out(L, wv, no, sidx, A);
+  if (qn > 0) drain(L, wv, head, qn, kind, no, sidx, wrun, ntested, A);
+  if (no > 0) flush_out(L, wv, no, sidx, wrun, A);
+  if (A.out && lane == 0) A.wtot[blockIdx.x * kWaves + wv] = wrun;
   // node records read by the wave's groups: the measure of the tree's quality
   unsigned long long nv = nvisit;
   for (int o = 32; o >= 1; o >>= 1) nv += __shfl_xor(nv, o);
   if (lane == 0 && nv) atomicAdd(&A.stripe[(sidx & (kStripes - 1)) * kStripeWords + 1], nv);
 }
 
-// The stripes' pairs, concatenated in stripe order, to out[0, total): offsets from
-// the stripe counts (each at most capS), one wave's scan per block.
-__global__ void __launch_bounds__(256) k_stripe_gather(const unsigned long long* stripe,
-                                                       int64_t capS, const uint64_t* skeys,
-                                                       const double* sd2, uint64_t* out,
-                                                       double* outd, int64_t total) {
+// Exclusive prefix sum of the waves' pair counts, in place (one block).
+__global__ void __launch_bounds__(1024) k_wave_offsets(long long* w, int32_t n) {
+  __shared__ long long part[1024];
+  const int t = threadIdx.x;
+  const int32_t per = (n + 1023) / 1024, b = t * per, e = b + per < n ? b + per : n;
+  long long sum = 0;
+  for (int32_t i = b; i < e; ++i) sum += w[i];
+  part[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const long long v = t >= o ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  long long run = part[t] - sum;
+  for (int32_t i = b; i < e; ++i) {
+    const long long c = w[i];
+    w[i] = run;
+    run += c;
+  }
+}
+
+// The stripes' runs to out, wave by wave: P holds each wave's pairs together, in
+// the order the wave found them (a wave's 64 queries are neighbours in Morton order,
+// so the pairs of one pair-pass block share most of their vertices). One wave per
+// run; the run's stripe from the stripes' run counts (one wave's scan per block).
+__global__ void __launch_bounds__(64) k_stripe_gather(const unsigned long long* stripe,
+                                                      int64_t capS, int64_t capC,
+                                                      const int4* chunks,
+                                                      const long long* woff,
+                                                      const uint64_t* skeys,
+                                                      const double* sd2, uint64_t* out,
+                                                      double* outd) {
   static_assert(kStripes == 64, "one lane per stripe");
   __shared__ long long off[kStripes + 1];
-  if (threadIdx.x < 64) {
-    const long long c = (long long)stripe[threadIdx.x * kStripeWords];
+  const int lane = threadIdx.x;
+  {
+    const long long c = (long long)(stripe[lane * kStripeWords] >> kRunShift);
     long long incl = c;
     for (int o = 1; o < 64; o <<= 1) {
       const long long t = __shfl_up(incl, o);
-      if ((int)threadIdx.x >= o) incl += t;
+      if (lane >= o) incl += t;
     }
-    off[threadIdx.x + 1] = incl;
-    if (threadIdx.x == 0) off[0] = 0;
+    off[lane + 1] = incl;
+    if (lane == 0) off[0] = 0;
   }
   __syncthreads();
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * 256) {
-    int lo = 0, hi = kStripes;  // off[lo] <= i < off[hi]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (off[mid] <= i) lo = mid;
-      else hi = mid;
-    }
-    const int64_t src = (int64_t)lo * capS + (i - off[lo]);
-    out[i] = skeys[src];
-    if (outd) outd[i] = sd2[src];
+  const long long r = blockIdx.x;
+  int lo = 0, hi = kStripes;  // off[lo] <= r < off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= r) lo = mid;
+    else hi = mid;
+  }
+  const int4 c = chunks[(int64_t)lo * capC + (r - off[lo])];
+  const int64_t dst = woff[c.x] + c.y, src = (int64_t)lo * capS + c.w;
+  for (int j = lane; j < c.z; j += 64) {
+    out[dst + j] = skeys[src + j];
+    if (outd) outd[dst + j] = sd2[src + j];
   }
 }
 
@@ -1314,8 +1362,10 @@ void bvh_free(cc_solver* s) {
   dfree(s->ubox_lo); dfree(s->ubox_hi); dfree(s->gprim); dfree(s->rs_hist); dfree(s->bounds);
   dfree(s->bounds_part); dfree(s->vorder); dfree(s->vrank); dfree(s->erank); dfree(s->rs_total);
   dfree(s->sel_dev); dfree(s->root_t); dfree(s->root_e);
-  dfree(s->stripe); dfree(s->skeys); dfree(s->sd2);
+  dfree(s->stripe); dfree(s->skeys); dfree(s->sd2); dfree(s->chunks); dfree(s->wtot);
   s->capS = 0;
+  s->capC = 0;
+  s->capW = 0;
 }
 
 static inline unsigned blocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -1357,16 +1407,23 @@ static int refit_and_widen(cc_solver* s, int32_t mt, int32_t me, int32_t mp, hip
 
 constexpr size_t kStripeBytes = sizeof(unsigned long long) * kStripes * kStripeWords;
 
-// Stripes of capS entries each (keys and squared distances); the contents go.
-static int grow_stripes(cc_solver* s, int64_t capS) {
+// Stripes of capS pairs (keys and squared distances) and capC runs each; the
+// contents go.
+static int grow_stripes(cc_solver* s, int64_t capS, int64_t capC) {
   dfree(s->skeys);
   dfree(s->sd2);
+  dfree(s->chunks);
   s->capS = 0;
+  s->capC = 0;
   CC_TRY(dalloc(&s->skeys, capS * kStripes));
   CC_TRY(dalloc(&s->sd2, capS * kStripes));
+  CC_TRY(dalloc(&s->chunks, capC * kStripes));
   s->capS = capS;
+  s->capC = capC;
   return CC_OK;
 }
+// runs of a stripe of capS pairs: all but a wave's last hold at least kOut - 64
+static inline int64_t runs_for(int64_t capS) { return capS / 64 + 1024; }
 
 int launch_traverse(int group, const TravArgs& A, int64_t nq, hipStream_t st) {
   const unsigned nb = blocks(nq, kTravThreads);
@@ -1416,6 +1473,7 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
   CC_HIP(hipMemsetAsync(s->dc, 0, offsetof(Counters, ncand) + sizeof(unsigned long long), st));
   *nfound = 0;
   int64_t nfd = 0;     // pairs found (the stripes' counts)
+  int64_t nruns = 0;   // runs written into the stripes
   double ncand = 0.0;  // node records read by the traversal
   const int64_t m = (int64_t)mt + me + mp;
   // the tree of the last build serves again (refit) when the same scenes, in the same
@@ -1509,16 +1567,26 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
     // spread of the stripes' counts), grown below when one overflows
     if (out && s->capS == 0) {
       const int64_t c0 = (cap > 0 ? cap : 1) / kStripes;
-      CC_TRY(grow_stripes(s, c0 + c0 / 4 + 1024));
+      CC_TRY(grow_stripes(s, c0 + c0 / 4 + 1024, runs_for(c0 + c0 / 4 + 1024)));
     }
     A.out = out ? s->skeys : nullptr;
     A.outd = out && outd ? s->sd2 : nullptr;
     A.capS = s->capS;
     A.stripe = s->stripe;
+    A.chunks = s->chunks;
+    A.capC = s->capC;
     A.cnt = s->dc;
     A.mv_pad = (A.mv + 63) & ~63;
     A.me_pad = (me + 63) & ~63;
     int64_t nq = (int64_t)A.mv_pad + A.me_pad + mp;
+    const int64_t nwaves = (int64_t)blocks(nq, kTravThreads) * kWaves;
+    if (out && nwaves > s->capW) {
+      dfree(s->wtot);
+      s->capW = 0;
+      CC_TRY(dalloc(&s->wtot, nwaves));
+      s->capW = nwaves;
+    }
+    A.wtot = s->wtot;
     if (nq > 0) {
       // lanes per traversal group: the autotuner's choice for this device and query
       // count, measured on this search's own queries the first time (every variant
@@ -1566,25 +1634,32 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
         timer_end(s, st);
         CC_HIP(hipMemcpyAsync(s->hstripe, s->stripe, kStripeBytes, hipMemcpyDeviceToHost, st));
         CC_HIP(hipStreamSynchronize(st));
-        unsigned long long mx = 0, tot = 0, nvis = 0;
+        unsigned long long mx = 0, mr = 0, tot = 0, nvis = 0;
+        nruns = 0;
         for (int k = 0; k < kStripes; ++k) {
-          mx = std::max(mx, s->hstripe[k * kStripeWords]);
-          tot += s->hstripe[k * kStripeWords];
+          const unsigned long long v = s->hstripe[k * kStripeWords];
+          mx = std::max(mx, v & kPairMask);
+          mr = std::max(mr, v >> kRunShift);
+          tot += v & kPairMask;
+          nruns += (int64_t)(v >> kRunShift);
           nvis += s->hstripe[k * kStripeWords + 1];
         }
         nfd = (int64_t)tot;
         ncand = (double)nvis;
-        if (!out || (int64_t)mx <= A.capS) break;
+        if (!out || ((int64_t)mx <= A.capS && (int64_t)mr <= A.capC)) break;
         if (attempt > 0) return CC_EOVERFLOW;  // cannot happen: the counts repeat
-        CC_TRY(grow_stripes(s, (int64_t)mx + (int64_t)mx / 4 + 1024));
+        const int64_t ns = std::max<int64_t>(s->capS, (int64_t)mx + (int64_t)mx / 4 + 1024);
+        CC_TRY(grow_stripes(s, ns, std::max<int64_t>(runs_for(ns), (int64_t)mr + (int64_t)mr / 4 + 1024)));
         A.out = s->skeys;
         A.outd = outd ? s->sd2 : nullptr;
         A.capS = s->capS;
+        A.chunks = s->chunks;
+        A.capC = s->capC;
       }
       if (out && nfd > 0 && nfd <= cap) {
-        const int64_t nbg = std::min<int64_t>((nfd + 255) / 256, 8192);
-        k_stripe_gather<<<(unsigned)nbg, 256, 0, st>>>(s->stripe, s->capS, s->skeys, s->sd2, out,
-                                                       outd, nfd);
+        k_wave_offsets<<<1, 1024, 0, st>>>(s->wtot, (int32_t)nwaves);
+        k_stripe_gather<<<(unsigned)nruns, 64, 0, st>>>(s->stripe, s->capS, s->capC, s->chunks,
+                                                       s->wtot, s->skeys, s->sd2, out, outd);
       }
     }
   }
