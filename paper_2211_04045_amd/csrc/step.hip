@@ -442,6 +442,11 @@ __device__ __forceinline__ void min_insert(int32_t* hkey, unsigned long long* hv
 // exact and order independent on the bit patterns of non-negative doubles). P' and
 // A are compacted with one counter atomic per block; the per-segment counts go
 // through a small LDS table.
+// kCompute = false when every pair carries its distance (d_from = 0: a pair pass
+// right after a search of every scene): no positions are loaded and no distance is
+// taken, and the kernel needs far fewer registers (more waves per SIMD to cover the
+// key -> topology chain).
+template <bool kCompute>
 __global__ void __launch_bounds__(kThreads) k_pair_pass(PairPassArgs a) {
   __shared__ int32_t hkey[kHash];
   __shared__ unsigned long long hval[kHash];
@@ -496,10 +501,10 @@ __global__ void __launch_bounds__(kThreads) k_pair_pass(PairPassArgs a) {
   for (int k = 0; k < kPairsPerThread; ++k) {
     const int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
     psg[k] = a.one_seg >= 0 ? a.one_seg : a.vseg[pv[k][0]];
-    fresh[k] = i < a.d_from;
+    fresh[k] = kCompute && i < a.d_from;
     if (fresh[k] && a.mvd)
       fresh[k] = (a.mvd[pv[k][0]] | a.mvd[pv[k][1]] | a.mvd[pv[k][2]] | a.mvd[pv[k][3]]) != 0;
-    if (fresh[k]) {
+    if (kCompute && fresh[k]) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) px[k][q] = ld3(a.x, pv[k][q]);
     }
@@ -518,7 +523,7 @@ __global__ void __launch_bounds__(kThreads) k_pair_pass(PairPassArgs a) {
       const bool live = (fl & kSegActive) && !(i < a.n_old && (fl & kSegSearched));
       if (live) {
         const double d2 =
-            fresh[k] ? pair_d2(key, px[k][0], px[k][1], px[k][2], px[k][3]) : dst[k];
+            (kCompute && fresh[k]) ? pair_d2(key, px[k][0], px[k][1], px[k][2], px[k][3]) : dst[k];
         keys[k] = key;
         d2s[k] = d2;
         vs[k] = make_int4(v[0], v[1], v[2], v[3]);
@@ -624,7 +629,11 @@ int launch_pair_pass(cc_solver* s, int64_t n_old, int64_t d_from, double dl2, bo
   // one scene and no removed scene's pairs left in P: the segment of a pair is known
   // without its vertex's segment id
   a.one_seg = single_live_seg(s) ? 0 : -1;
-  if (s->nP > 0) k_pair_pass<<<nblk(s->nP, kThreads * kPairsPerThread), kThreads, 0, st>>>(a);
+  if (s->nP > 0) {
+    const unsigned g = nblk(s->nP, kThreads * kPairsPerThread);
+    if (d_from > 0) k_pair_pass<true><<<g, kThreads, 0, st>>>(a);
+    else k_pair_pass<false><<<g, kThreads, 0, st>>>(a);
+  }
   CC_HIP(hipGetLastError());
   return CC_OK;
 }
