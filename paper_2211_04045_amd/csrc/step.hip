@@ -504,13 +504,18 @@ __global__ void __launch_bounds__(kThreads) k_pair_pass(PairPassArgs a) {
     fresh[k] = kCompute && i < a.d_from;
     if (fresh[k] && a.mvd)
       fresh[k] = (a.mvd[pv[k][0]] | a.mvd[pv[k][1]] | a.mvd[pv[k][2]] | a.mvd[pv[k][3]]) != 0;
-    if (kCompute && fresh[k]) {
+    if (kCompute && k == 0 && fresh[k]) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) px[k][q] = ld3(a.x, pv[k][q]);
     }
   }
 #pragma unroll
   for (int k = 0; k < kPairsPerThread; ++k) {
+    // the next pair's positions are loaded while this pair's distance is taken
+    if (kCompute && k + 1 < kPairsPerThread && fresh[k + 1]) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) px[k + 1][q] = ld3(a.x, pv[k + 1][q]);
+    }
     const int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
     const uint64_t key = keys[k];
     keys[k] = 0;
