@@ -1275,7 +1275,9 @@ int cc_solver_search(cc_solver* s, const double* x, double dmax, uint64_t* keys,
   // the static flags come from the last begin; without one every vertex counts as free
   if (!s->begun && nv) CC_HIP(hipMemsetAsync(s->stat, 0, nv, st));
   s->sel_host[0].seg = 0;
-  return lbvh_search(s, 1, x, dmax, keys, nullptr, keys ? cap : 0, n, st, false);
+  CC_TRY(lbvh_search(s, 1, x, dmax, keys, nullptr, keys ? cap : 0, n, st, false));
+  CC_HIP(hipStreamSynchronize(st));  // the keys are in place on return
+  return CC_OK;
 }
 
 int cc_solver_stats(cc_solver* s, cc_stats* out) {

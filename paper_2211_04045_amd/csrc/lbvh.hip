@@ -1633,7 +1633,9 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
         CC_TRY(launch_traverse(group, A, nq, st));
         timer_end(s, st);
         CC_HIP(hipMemcpyAsync(s->hstripe, s->stripe, kStripeBytes, hipMemcpyDeviceToHost, st));
+        CC_HIP(hipMemcpyAsync(s->hc, s->dc, sizeof(Counters), hipMemcpyDeviceToHost, st));
         CC_HIP(hipStreamSynchronize(st));
+        if (s->hc->err & 2ull) return CC_EOVERFLOW;  // a traversal stack overflowed
         unsigned long long mx = 0, mr = 0, tot = 0, nvis = 0;
         nruns = 0;
         for (int k = 0; k < kStripes; ++k) {
@@ -1663,10 +1665,8 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
       }
     }
   }
+  // (the gather is left queued on the stream: what follows is ordered after it)
   CC_HIP(hipGetLastError());
-  CC_HIP(hipMemcpyAsync(s->hc, s->dc, sizeof(Counters), hipMemcpyDeviceToHost, st));
-  CC_HIP(hipStreamSynchronize(st));
-  if (s->hc->err & 2ull) return CC_EOVERFLOW;
   *nfound = nfd;
   // tree quality: node records read by the traversal; a refitted tree whose
   // traversal reads 30 % more of them than right after its build is built anew at the
