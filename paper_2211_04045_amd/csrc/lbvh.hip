@@ -180,10 +180,14 @@ __global__ void k_morton(const float4* __restrict__ blo, const float4* __restric
     c[2] = (float)p.z;
     grp = 3u;
   }
+  // one scale for the three axes (the largest span): cubic Morton cells, so that a
+  // thin scene (a cloth a few layers thick) is split across its extent before its
+  // thickness and a node's box stays compact
+  float span = 0.f;
+  for (int k = 0; k < 3; ++k) span = fmaxf(span, ord2f(bounds[3 + k]) - ord2f(bounds[k]));
   uint32_t q[3];
   for (int k = 0; k < 3; ++k) {
-    float lo = ord2f(bounds[k]), hi = ord2f(bounds[3 + k]);
-    float span = hi - lo;
+    const float lo = ord2f(bounds[k]);
     float t = span > 0.f ? (c[k] - lo) / span : 0.f;
     float v = t * 1024.f;
     v = v < 0.f ? 0.f : (v > 1023.f ? 1023.f : v);
