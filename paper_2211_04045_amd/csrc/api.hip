@@ -200,6 +200,7 @@ void free_vertex_arrays(cc_solver* s) {
 }
 void free_edge_arrays(cc_solver* s) {
   dfree(s->edges); dfree(s->eseg); dfree(s->eg); dfree(s->einv); dfree(s->ecol); dfree(s->eorder);
+  dfree(s->eij);
   dfree(s->elist0); dfree(s->elist1); dfree(s->elist2); dfree(s->lamE);
   dfree(s->efail); dfree(s->epick);
 }
@@ -291,7 +292,9 @@ int resize_arrays(cc_solver* s, int32_t capV, int32_t capF, int32_t capE, hipStr
     CC_TRY(dregrow(&s->einv, capE, oE, st));
     CC_TRY(dregrow(&s->ecol, capE, oE, st));
     dfree(s->eorder); dfree(s->elist0); dfree(s->elist1); dfree(s->elist2); dfree(s->lamE);
+    dfree(s->eij);
     CC_TRY(dalloc(&s->eorder, capE));
+    CC_TRY(dalloc(&s->eij, capE));
     CC_TRY(dalloc(&s->elist0, capE));
     CC_TRY(dalloc(&s->elist1, capE));
     CC_TRY(dalloc(&s->elist2, capE));

@@ -235,6 +235,7 @@ struct cc_solver {
   double* einv = nullptr;
   int32_t* ecol = nullptr;
   int32_t* eorder = nullptr;
+  int2* eij = nullptr;      // per bucket position: the row's two vertices (with eorder)
   int32_t *elist0 = nullptr, *elist1 = nullptr, *elist2 = nullptr;
   double* lamE = nullptr;
   int32_t n_erows = 0, n_ecolors = 0;  // rows in the union buckets, their colours

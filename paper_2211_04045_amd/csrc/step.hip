@@ -1493,7 +1493,9 @@ __global__ void __launch_bounds__(kThreads) k_ebucket_scatter(const int32_t* __r
                                                               const int32_t* __restrict__ colors,
                                                               int32_t ne,
                                                               int32_t* __restrict__ cursor,
-                                                              int32_t* __restrict__ order) {
+                                                              int32_t* __restrict__ order,
+                                                              const int32_t* __restrict__ edges,
+                                                              int2* __restrict__ eij) {
   __shared__ int32_t h[kMaxColors];
   for (int c = threadIdx.x; c < kMaxColors; c += kThreads) h[c] = 0;
   __syncthreads();
@@ -1508,7 +1510,10 @@ __global__ void __launch_bounds__(kThreads) k_ebucket_scatter(const int32_t* __r
   for (int k = threadIdx.x; k < kMaxColors; k += kThreads)
     if (h[k]) h[k] = atomicAdd(&cursor[k], h[k]);
   __syncthreads();
-  if (live) order[h[c] + rank] = e;
+  if (live) {
+    order[h[c] + rank] = e;
+    eij[h[c] + rank] = make_int2(edges[2 * e], edges[2 * e + 1]);
+  }
 }
 
 int build_edge_buckets(cc_solver* s, hipStream_t st) {
@@ -1533,7 +1538,8 @@ int build_edge_buckets(cc_solver* s, hipStream_t st) {
   if (ncol == 0) return CC_OK;
   CC_HIP(hipMemcpyAsync(s->col_cnt, off.data(), sizeof(int32_t) * ncol, hipMemcpyHostToDevice, st));
   k_ebucket_scatter<<<nblk(s->ne), kThreads, 0, st>>>(s->eseg, s->seg_dev, s->einv, s->ecol,
-                                                       s->ne, s->col_cnt, s->eorder);
+                                                       s->ne, s->col_cnt, s->eorder, s->edges,
+                                                       s->eij);
   CC_HIP(hipMemcpyAsync(s->ecoff_dev, off.data(), sizeof(int32_t) * (ncol + 1),
                         hipMemcpyHostToDevice, st));
   CC_HIP(hipGetLastError());
@@ -1557,6 +1563,7 @@ static_assert(sizeof(RowRec) == 8 * kRowWords, "contact row record size");
 
 struct GsArgs {
   const int32_t* order;
+  const int2* eij;  // edge rows: the vertices of each bucket position (with order)
   int32_t cnt;
   const RowRec* rows;
   const unsigned long long* err;  // bit 0 set: the colouring failed, the step does nothing
@@ -1697,9 +1704,13 @@ __device__ __forceinline__ void gs_contact_update(const GsArgs& a, int32_t r) {
 
 // Edge-length row (Sec. 4.2), same projected update. Mixed precision: the part
 // sigma - g.(x_i - x_j) in FP64, the rest on y - x in FP32.
+// Edge row at bucket position t (its edge and two vertices read side by side, so the
+// vertices' loads do not wait on the edge's).
 template <bool kMixed>
-__device__ __forceinline__ void gs_edge_update(const GsArgs& a, int32_t e) {
-  int32_t i = a.edges[2 * e], j = a.edges[2 * e + 1];
+__device__ __forceinline__ void gs_edge_update(const GsArgs& a, int32_t t) {
+  const int32_t e = a.order[t];
+  const int2 ij = a.eij[t];
+  const int32_t i = ij.x, j = ij.y;
   V3 g = ld3(a.eg, e);
   const double wi = a.w[i], wj = a.w[j];
   if (kMixed) {
@@ -1752,7 +1763,7 @@ __global__ void __launch_bounds__(kThreads) k_gs_contact(GsArgs a) {
 template <bool kMixed>
 __global__ void __launch_bounds__(kThreads) k_gs_edge(GsArgs a) {
   int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < a.cnt && !gs_off(a)) gs_edge_update<kMixed>(a, a.order[t]);
+  if (t < a.cnt && !gs_off(a)) gs_edge_update<kMixed>(a, t);
 }
 
 // A run of small colours [c0, c1) in one block, colour after colour with a block
@@ -1768,7 +1779,7 @@ __global__ void __launch_bounds__(kGsTailThreads) k_gs_tail(GsArgs a, const int3
   for (int32_t c = c0; c < c1; ++c) {
     const int32_t b = off[c], e = off[c + 1];
     for (int32_t t = b + threadIdx.x; t < e; t += kGsTailThreads) {
-      if (is_edge) gs_edge_update<kMixed>(a, a.order[t]);
+      if (is_edge) gs_edge_update<kMixed>(a, t);
       else gs_contact_update<kMixed>(a, a.order[t]);
     }
     __syncthreads();
@@ -1808,14 +1819,16 @@ __global__ void __launch_bounds__(kGsTailThreads) k_gs_contact_small(
 }
 
 template <bool kMixed>
-static void gs_colours(const GsArgs& base, const int32_t* order, const std::vector<int32_t>& off,
-                       const int32_t* off_dev, int32_t ncol, bool edge, hipStream_t st) {
+static void gs_colours(const GsArgs& base, const int32_t* order, const int2* eij,
+                       const std::vector<int32_t>& off, const int32_t* off_dev, int32_t ncol,
+                       bool edge, hipStream_t st) {
   GsArgs a = base;
   int32_t c = 0;
   while (c < ncol) {
     int32_t cnt = off[c + 1] - off[c];
     if (cnt >= kGsTailRows) {
       a.order = order + off[c];
+      a.eij = eij ? eij + off[c] : nullptr;
       a.cnt = cnt;
       if (edge) k_gs_edge<kMixed><<<nblk(cnt), kThreads, 0, st>>>(a);
       else k_gs_contact<kMixed><<<nblk(cnt), kThreads, 0, st>>>(a);
@@ -1825,6 +1838,7 @@ static void gs_colours(const GsArgs& base, const int32_t* order, const std::vect
     int32_t c1 = c;
     while (c1 < ncol && off[c1 + 1] - off[c1] < kGsTailRows) ++c1;
     a.order = order;
+    a.eij = eij;
     a.cnt = 0;
     k_gs_tail<kMixed><<<1, kGsTailThreads, 0, st>>>(a, off_dev, c, c1, edge ? 1 : 0, nullptr);
     c = c1;
@@ -1844,16 +1858,17 @@ static void gs_sweeps(cc_solver* s, GsArgs a, hipStream_t st) {
         k_gs_contact_small<kMixed><<<1, kGsTailThreads, 0, st>>>(a, s->coff_dev, &s->dc->ncol,
                                                                   &s->dc->n_act);
     } else {
-      gs_colours<kMixed>(a, s->Aorder, s->col_off, s->coff_dev, s->n_colors, false, st);
+      gs_colours<kMixed>(a, s->Aorder, nullptr, s->col_off, s->coff_dev, s->n_colors, false, st);
     }
     a.lam = s->lamE;
     a.lamf = (float*)s->lamE;
-    gs_colours<kMixed>(a, s->eorder, s->ecol_off, s->ecoff_dev, s->n_ecolors, true, st);
+    gs_colours<kMixed>(a, s->eorder, s->eij, s->ecol_off, s->ecoff_dev, s->n_ecolors, true, st);
   }
 }
 
 int launch_gs(cc_solver* s, hipStream_t st) {
   GsArgs a;
+  a.eij = s->eij;
   a.Akeys = s->Akeys;
   a.Averts = s->Averts;
   a.rows = reinterpret_cast<const RowRec*>(s->Arow);
