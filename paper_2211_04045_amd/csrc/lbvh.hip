@@ -1132,18 +1132,17 @@ __global__ void __launch_bounds__(1024) k_wave_offsets(long long* w, int32_t n) 
 // The stripes' runs to out, wave by wave: P holds each wave's pairs together, in
 // the order the wave found them (a wave's 64 queries are neighbours in Morton order,
 // so the pairs of one pair-pass block share most of their vertices). One wave per
-// run; the run's stripe from the stripes' run counts (one wave's scan per block).
-__global__ void __launch_bounds__(64) k_stripe_gather(const unsigned long long* stripe,
-                                                      int64_t capS, int64_t capC,
-                                                      const int4* chunks,
-                                                      const long long* woff,
-                                                      const uint64_t* skeys,
-                                                      const double* sd2, uint64_t* out,
-                                                      double* outd) {
+// run, kGatherWaves runs per block; the run's stripe from the stripes' run counts
+// (one wave's scan per block).
+constexpr int kGatherWaves = 4;
+__global__ void __launch_bounds__(64 * kGatherWaves) k_stripe_gather(
+    const unsigned long long* stripe, int64_t capS, int64_t capC, const int4* chunks,
+    const long long* woff, const uint64_t* skeys, const double* sd2, uint64_t* out,
+    double* outd, int64_t nruns) {
   static_assert(kStripes == 64, "one lane per stripe");
   __shared__ long long off[kStripes + 1];
-  const int lane = threadIdx.x;
-  {
+  const int lane = threadIdx.x & 63;
+  if (threadIdx.x < 64) {
     const long long c = (long long)(stripe[lane * kStripeWords] >> kRunShift);
     long long incl = c;
     for (int o = 1; o < 64; o <<= 1) {
@@ -1154,7 +1153,8 @@ __global__ void __launch_bounds__(64) k_stripe_gather(const unsigned long long* 
     if (lane == 0) off[0] = 0;
   }
   __syncthreads();
-  const long long r = blockIdx.x;
+  const long long r = (long long)blockIdx.x * kGatherWaves + (threadIdx.x >> 6);
+  if (r >= nruns) return;
   int lo = 0, hi = kStripes;  // off[lo] <= r < off[hi]
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
@@ -1664,8 +1664,9 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
       }
       if (out && nfd > 0 && nfd <= cap) {
         k_wave_offsets<<<1, 1024, 0, st>>>(s->wtot, (int32_t)nwaves);
-        k_stripe_gather<<<(unsigned)nruns, 64, 0, st>>>(s->stripe, s->capS, s->capC, s->chunks,
-                                                       s->wtot, s->skeys, s->sd2, out, outd);
+        k_stripe_gather<<<(unsigned)((nruns + kGatherWaves - 1) / kGatherWaves), 64 * kGatherWaves,
+                          0, st>>>(s->stripe, s->capS, s->capC, s->chunks, s->wtot, s->skeys,
+                                   s->sd2, out, outd, nruns);
       }
     }
   }
