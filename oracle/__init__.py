@@ -82,6 +82,10 @@ def _load():
     lib.orc_search.restype = i64
     lib.orc_color_rows.argtypes = [vp, i64, vp, vp, vp]
     lib.orc_color_rows.restype = i32
+    lib.orc_color_rows_greedy.argtypes = [vp, i64, vp, vp, vp]
+    lib.orc_color_rows_greedy.restype = i32
+    lib.orc_greedy_prio.argtypes = [C.c_uint64, C.c_uint64]
+    lib.orc_greedy_prio.restype = C.c_uint64
     lib.orc_mix64.argtypes = [u64]
     lib.orc_mix64.restype = u64
     lib.orc_ccd_hit.argtypes = [vp, vp, C.c_int, d, P(d)]
@@ -280,6 +284,19 @@ class Scene:
         if nc < 0:
             raise RuntimeError("palette exhausted")
         return col, nc
+
+    def color_greedy(self, rows, keys):
+        """The edge-length rows' colouring: greedy in decreasing greedy_prio order."""
+        rows = np.ascontiguousarray(rows, dtype=np.int32).reshape(-1, 4)
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        col = np.zeros(len(rows), np.int32)
+        nc = self.lib.orc_color_rows_greedy(self.h, len(rows), _ptr(rows), _ptr(keys), _ptr(col))
+        if nc < 0:
+            raise RuntimeError("palette exhausted")
+        return col, nc
+
+    def greedy_prio(self, key, seed):
+        return int(self.lib.orc_greedy_prio(int(key), int(seed)))
 
 
 def collide_step(scene: dict, **over):

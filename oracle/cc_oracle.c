@@ -28,8 +28,10 @@
  *  - The multipliers start at zero in every backward step and y carries the
  *    accumulated effect (Sec. 4: y initialised with y^(l)).
  *  - Constraints are coloured on the graph "shares a vertex with w > 0" (Sec. 4.3
- *    colours constraints, not vertices) by a randomised palette colouring whose
- *    choices are hashes of the row key, the seed and the round (orc_color_rows);
+ *    colours constraints, not vertices): contact rows by a randomised palette
+ *    colouring whose choices are hashes of the row key, the seed and the round
+ *    (orc_color_rows), edge-length rows greedily in the order of a hash of their
+ *    key and the seed (orc_color_rows_greedy);
  *    the key of a contact is its pair key, the key of an edge-length row its
  *    input edge index. Contacts are swept colour by colour, then edge-length rows
  *    colour by colour.
@@ -1127,6 +1129,70 @@ int32_t orc_color_rows(const orc_scene* s, int64_t nrows, const int32_t* rv,
   return err ? -1 : ncol;
 }
 
+/* Greedy colouring in priority order, for the edge-length rows (colours kept for
+ * a scene's steps, so their number, which sets the sweeps per backward step, counts
+ * more than the time to find them): the rows are taken in decreasing priority,
+ * prio = (high 32 bits of mix64(key ^ seed)) << 32 | key (keys below 2^32, so no two
+ * rows tie), and each takes the smallest colour not used by an already coloured row
+ * at one of its free vertices. Returns the colour count, or -1 past max_colors. */
+typedef struct {
+  uint64_t prio;
+  int64_t row;
+} prio_row_t;
+
+static int cmp_prio_desc(const void* a, const void* b) {
+  const prio_row_t *x = (const prio_row_t*)a, *y = (const prio_row_t*)b;
+  if (x->prio != y->prio) return x->prio > y->prio ? -1 : 1;
+  return 0;
+}
+
+uint64_t orc_greedy_prio(uint64_t key, uint64_t seed) {
+  return (orc_mix64(key ^ seed) & 0xFFFFFFFF00000000ull) | (key & 0xFFFFFFFFull);
+}
+
+int32_t orc_color_rows_greedy(const orc_scene* s, int64_t nrows, const int32_t* rv,
+                              const uint64_t* keys, int32_t* colors) {
+  const int W = (s->p.max_colors + 63) / 64;
+  const size_t NR = (size_t)(nrows > 0 ? nrows : 1);
+  prio_row_t* order = (prio_row_t*)malloc(NR * sizeof(prio_row_t));
+  uint64_t* mask = (uint64_t*)calloc((size_t)s->n * (size_t)W, sizeof(uint64_t));
+  for (int64_t r = 0; r < nrows; ++r) {
+    order[r].prio = orc_greedy_prio(keys[r], s->p.seed);
+    order[r].row = r;
+    colors[r] = -1;
+  }
+  qsort(order, (size_t)nrows, sizeof(prio_row_t), cmp_prio_desc);
+  int32_t ncol = 0, err = 0;
+  for (int64_t i = 0; i < nrows && !err; ++i) {
+    const int64_t r = order[i].row;
+    int32_t c = -1;
+    for (int32_t q = 0; q < s->p.max_colors; ++q) {
+      int used = 0;
+      for (int k = 0; k < 4; ++k) {
+        const int32_t v = rv[4 * r + k];
+        if (free_vertex(s, v) && ((mask[(size_t)v * W + q / 64] >> (q % 64)) & 1ull)) used = 1;
+      }
+      if (!used) {
+        c = q;
+        break;
+      }
+    }
+    if (c < 0) {
+      err = 1;
+      break;
+    }
+    colors[r] = c;
+    if (c + 1 > ncol) ncol = c + 1;
+    for (int k = 0; k < 4; ++k) {
+      const int32_t v = rv[4 * r + k];
+      if (free_vertex(s, v)) mask[(size_t)v * W + c / 64] |= 1ull << (c % 64);
+    }
+  }
+  free(order);
+  free(mask);
+  return err ? -1 : ncol;
+}
+
 /* ------------------------------------------------------------- scene */
 
 orc_scene* orc_create(int32_t n, const double* w, const int32_t* tris, int32_t nt,
@@ -1229,7 +1295,7 @@ static int setup_edges(orc_scene* s) {
     rv[4 * r + 3] = -1;
     keys[r] = (uint64_t)s->er_e[r];
   }
-  int32_t nc = orc_color_rows(s, s->n_er, rv, keys, s->er_col);
+  int32_t nc = orc_color_rows_greedy(s, s->n_er, rv, keys, s->er_col);
   free(rv);
   free(keys);
   if (nc < 0) return -1;

@@ -113,6 +113,11 @@ int64_t orc_search(orc_scene* s, const double* x, double dmax, int brute,
  * number of colours, <0 on error. */
 int32_t orc_color_rows(const orc_scene* s, int64_t nrows, const int32_t* rv,
                        const uint64_t* keys, int32_t* colors);
+/* Greedy colouring of rows in decreasing orc_greedy_prio(key, seed) order (the
+ * edge-length rows' colouring); same arguments and result as orc_color_rows. */
+int32_t orc_color_rows_greedy(const orc_scene* s, int64_t nrows, const int32_t* rv,
+                              const uint64_t* keys, int32_t* colors);
+uint64_t orc_greedy_prio(uint64_t key, uint64_t seed);
 uint64_t orc_mix64(uint64_t z);
 /* Continuous test of a pair along q_k + t dq_k, t in [0,1] (q, dq: the points in
  * the contact-row order). kind 0: vertex-triangle (4 points), 1: edge-edge (4),

@@ -612,7 +612,7 @@ int seg_begin(cc_solver* s, const int32_t* sgs, int32_t k, const double* const* 
     const bool reuse = ec_try && s->hc->ecmis == 0 && s->n_newrows == ec.rows;
     if (!reuse) {
       timer_begin(s, CC_K_COLOR, st);
-      crc = color_rows(s, true, st);
+      crc = color_edges_greedy(s, st);
       timer_end(s, st);
       if (crc == CC_OK && lone) crc = ecache_store(s, st);
     }

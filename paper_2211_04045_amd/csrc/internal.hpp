@@ -364,6 +364,9 @@ int launch_pair_pass(cc_solver* s, int64_t n_old, int64_t d_from, double dl2, bo
                      bool in_place, hipStream_t st);
 // contacts: colour A; edges: colour the n_newrows rows listed in elist0
 int color_rows(cc_solver* s, bool edges, hipStream_t st);
+// the edge-length rows' colouring (greedy in priority order) of the n_newrows rows
+// listed in elist0
+int color_edges_greedy(cc_solver* s, hipStream_t st);
 // Edge colouring cache of a lone scene (segment 0 at offset 0): compare the inputs
 // with the cached ones (counted into dc->ecmis, cleared here), or store them.
 int ecache_compare(cc_solver* s, hipStream_t st);

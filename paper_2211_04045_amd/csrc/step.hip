@@ -1382,6 +1382,154 @@ int color_rows(cc_solver* s, bool edges, hipStream_t st) {
   return CC_OK;
 }
 
+// ------------------------------------------------------------- greedy colouring of edge rows
+
+// The edge-length rows' colouring: greedy in decreasing priority, prio = (high 32
+// bits of mix64(key ^ seed)) << 32 | key (distinct for distinct keys), each row
+// taking the smallest colour not used by an already coloured row at one of its free
+// vertices. Found by Jones-Plassmann rounds: a row whose priority is the largest
+// among the uncoloured rows at each of its free vertices takes its colour in the
+// round; two such rows share no free vertex, and every row with a higher priority
+// at its vertices is coloured by then, so the result is the greedy colouring.
+__device__ __forceinline__ uint64_t greedy_prio(uint64_t key, uint64_t seed) {
+  return (mix64(key ^ seed) & 0xFFFFFFFF00000000ull) | (key & 0xFFFFFFFFull);
+}
+
+// Round part 1: the largest priority of the uncoloured rows at each free vertex
+// (a.unc, zero between rounds).
+__global__ void __launch_bounds__(kThreads) k_jp_max(PcArgs a, const int32_t* list,
+                                                    const unsigned long long* nlist) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)*nlist) return;
+  uint64_t key;
+  int32_t v[4];
+  a.src.get(list[t], key, v);
+  const uint64_t p = greedy_prio(key, a.seed);
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (is_free(a.w, v[k])) atomicMax(&a.unc[v[k]], (unsigned long long)p);
+}
+
+// Round part 2: a row that holds the largest priority at each of its free vertices
+// takes the smallest colour free at them and marks it there (no other row taking a
+// colour in this round shares those vertices); the others go to list_out. The
+// largest colour taken raises c->ncol once per block.
+__global__ void __launch_bounds__(kThreads) k_jp_pick(PcArgs a, const int32_t* list,
+                                                     const unsigned long long* nlist,
+                                                     int32_t* list_out,
+                                                     unsigned long long* nout) {
+  __shared__ int s_max[kThreads / 64];
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = t < (int64_t)*nlist;
+  int32_t r = 0;
+  bool stay = false;
+  int col = -1;
+  if (valid) {
+    r = list[t];
+    uint64_t key;
+    int32_t v[4];
+    a.src.get(r, key, v);
+    const uint64_t p = greedy_prio(key, a.seed);
+    bool top = true;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (is_free(a.w, v[k]) && a.unc[v[k]] != (unsigned long long)p) top = false;
+    if (!top) {
+      stay = true;
+    } else {
+      const int words = (a.maxc + 63) / 64;
+      for (int wd = 0; wd < words && col < 0; ++wd) {
+        unsigned long long u = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (is_free(a.w, v[k])) u |= a.masks[(int64_t)v[k] * kMaskWords + wd];
+        if (~u) {
+          const int c = wd * 64 + __ffsll((long long)~u) - 1;
+          if (c < a.maxc) col = c;
+          else break;
+        }
+      }
+      if (col < 0) {
+        atomicOr(&a.c->err, 1ull);  // the palette limit: no colour left
+      } else {
+        a.colors[r] = col;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (is_free(a.w, v[k]))
+            atomicOr(&a.masks[(int64_t)v[k] * kMaskWords + col / 64], 1ull << (col % 64));
+      }
+    }
+  }
+  int nblock = 0;
+  const unsigned long long pos = block_append(stay, nout, &nblock);
+  if (stay) list_out[pos] = r;
+  for (int o = 32; o >= 1; o >>= 1) col = max(col, __shfl_xor(col, o));
+  if (__lane_id() == 0) s_max[threadIdx.x >> 6] = col;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int mx = s_max[0];
+    for (int w = 1; w < kThreads / 64; ++w) mx = max(mx, s_max[w]);
+    if (mx >= 0) atomicMax(&a.c->ncol, (unsigned long long)(mx + 1));
+  }
+}
+
+// Round part 3: the priorities of the round's rows cleared at their vertices.
+__global__ void __launch_bounds__(kThreads) k_jp_clear(PcArgs a, const int32_t* list,
+                                                      const unsigned long long* nlist) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)*nlist) return;
+  uint64_t key;
+  int32_t v[4];
+  a.src.get(list[t], key, v);
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (is_free(a.w, v[k])) a.unc[v[k]] = 0ull;
+}
+
+int color_edges_greedy(cc_solver* s, hipStream_t st) {
+  const int64_t nrows = s->n_newrows;
+  s->ecache.ok = false;  // the cached colours are overwritten from here on
+  if (nrows == 0) return CC_OK;
+  CC_HIP(hipMemcpyAsync(s->elist1, s->elist0, sizeof(int32_t) * nrows, hipMemcpyDeviceToDevice, st));
+  int32_t *cur = s->elist1, *nxt = s->elist2;
+  if (s->pc_dirty) {  // an aborted colouring left counts or claims behind
+    CC_HIP(hipMemsetAsync(s->vmax0, 0, sizeof(unsigned long long) * (size_t)s->capV, st));
+    CC_HIP(hipMemsetAsync(s->claims, 0, sizeof(unsigned long long) * (size_t)s->capV * 2 * kMaskWords,
+                          st));
+    s->pc_dirty = false;
+  }
+  CC_HIP(hipMemsetAsync(s->masks, 0, sizeof(unsigned long long) * s->n * kMaskWords, st));
+  CC_HIP(hipMemsetAsync(&s->dc->ncol, 0, sizeof(unsigned long long), st));
+  CC_HIP(hipMemsetAsync(&s->dc->err, 0, sizeof(unsigned long long), st));
+  CC_HIP(hipMemsetAsync(s->rcnt, 0, sizeof(unsigned long long) * (kMaxRounds + 1), st));
+  CC_TRY(launch_fill_u64(s->rcnt, 1, (unsigned long long)nrows, st));
+  const PcArgs a = pc_args(s, true);
+  int64_t known = nrows;  // upper bound of the current list length
+  int round = 0;
+  s->pc_dirty = true;  // until the rounds end with every priority cleared
+  while (known > 0) {
+    if (round + kRoundsPerSync > kMaxRounds) return CC_ECOLOR;
+    for (int b = 0; b < kRoundsPerSync; ++b) {
+      const unsigned g = nblk(known);
+      k_jp_max<<<g, kThreads, 0, st>>>(a, cur, s->rcnt + round);
+      k_jp_pick<<<g, kThreads, 0, st>>>(a, cur, s->rcnt + round, nxt, s->rcnt + round + 1);
+      k_jp_clear<<<g, kThreads, 0, st>>>(a, cur, s->rcnt + round);
+      std::swap(cur, nxt);
+      ++round;
+    }
+    CC_HIP(hipGetLastError());
+    CC_HIP(hipMemcpyAsync(&s->hc->n_left, s->rcnt + round, sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, st));
+    CC_HIP(hipMemcpyAsync(&s->hc->err, &s->dc->err, sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, st));
+    CC_HIP(hipStreamSynchronize(st));
+    if (s->hc->err & 1ull) return CC_ECOLOR;
+    known = (int64_t)s->hc->n_left;
+  }
+  s->pc_dirty = false;
+  return CC_OK;
+}
+
 // ------------------------------------------------------------- edge colouring cache
 
 __global__ void k_ecache(const int32_t* __restrict__ edges, const double* __restrict__ einv,

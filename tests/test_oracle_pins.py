@@ -390,6 +390,68 @@ def test_colouring_is_proper_and_independent_of_row_order():
         assert np.array_equal(col2, col[perm]) and nc2 == nc
 
 
+def _neighbours(rows, w):
+    at = {}
+    for r, vs in enumerate(rows):
+        for v in vs:
+            if v >= 0 and w[v] > 0:
+                at.setdefault(int(v), set()).add(r)
+    nb = [set() for _ in rows]
+    for rs in at.values():
+        for r in rs:
+            nb[r] |= rs - {r}
+    return nb
+
+
+def test_greedy_colouring_is_proper_first_fit_and_follows_its_order():
+    """The edge rows' colouring: proper; first fit (every colour below a row's own is
+    taken by a neighbour, the defining property of a greedy colouring); no more
+    colours than the largest neighbourhood plus one; a function of the row set; and
+    equal to a plain greedy pass, written here, over the rows in decreasing
+    priority."""
+    rng = np.random.default_rng(16)
+    n = 50
+    w = np.where(rng.uniform(size=n) < 0.8, 1.0, 0.0)
+    s = _scene(n, w=w)
+    seed = oracle.DEFAULTS["seed"]
+    for trial in range(20):
+        m = int(rng.integers(1, 300))
+        rows = _random_rows(rng, n, m)
+        keys = rng.choice(2 ** 31, size=m, replace=False).astype(np.uint64)
+        col, nc = s.color_greedy(rows, keys)
+        nb = _neighbours(rows, w)
+        assert _proper(rows, col, w)
+        assert nc == col.max() + 1
+        for r in range(m):
+            assert {int(col[q]) for q in nb[r]} >= set(range(int(col[r])))
+        assert nc <= max(len(x) for x in nb) + 1
+        perm = rng.permutation(m)
+        col2, nc2 = s.color_greedy(rows[perm], keys[perm])
+        assert np.array_equal(col2, col[perm]) and nc2 == nc
+        order = sorted(range(m), key=lambda r: -s.greedy_prio(int(keys[r]), seed))
+        want = [-1] * m
+        for r in order:
+            used = {want[q] for q in nb[r]}
+            c = 0
+            while c in used:
+                c += 1
+            want[r] = c
+        assert list(col) == want
+
+
+def test_greedy_priority_is_unique_and_seeded():
+    """The greedy order: distinct keys get distinct priorities (the key fills the low
+    32 bits), and another seed gives another order."""
+    s = _scene(4)
+    seed = oracle.DEFAULTS["seed"]
+    keys = list(range(5000))
+    p = [s.greedy_prio(k, seed) for k in keys]
+    assert len(set(p)) == len(keys)
+    assert all(pk & 0xFFFFFFFF == k for pk, k in zip(p, keys))
+    q = [s.greedy_prio(k, seed + 1) for k in keys]
+    assert np.argsort(p).tolist() != np.argsort(q).tolist()
+
+
 def test_colouring_small_cases():
     """Worked cases of the rule: a row alone, or at static vertices only, takes
     colour 0; k rows at one free vertex take k different colours; two rows at one
