@@ -910,8 +910,9 @@ __global__ void __launch_bounds__(kTailThreads) k_pc_tail(PcArgs a, int32_t* la,
 constexpr int kSmallPer = kSmallRows / kTailThreads;  // rows per thread
 // LDS layouts of the one-block colouring: kLocWords colour words per vertex (colours
 // below 64 kLocWords) for at most kLocCap distinct free vertices. One word holds 4096
-// vertices, two words 2048 (about 110 KB of LDS either way).
-constexpr int kLocCap1 = 4096, kLocCap2 = 2048;
+// vertices (about 116 KB of LDS), two words 2944 (about 154 KB; a block may take up
+// to 160 KB on gfx950).
+constexpr int kLocCap1 = 4096, kLocCap2 = 2944;
 static_assert(kSmallRows % kTailThreads == 0, "whole rows per thread");
 static_assert(kMaxColors == kTailThreads, "one thread per colour bucket in the scan");
 

@@ -851,11 +851,11 @@ def _particle_dimers(nd, seed, spacing=5e-3, gap=5e-4):
 
 
 @pytest.mark.parametrize("kind", ["cluster", "cluster_wide", "dimers_lds", "dimers_many",
-                                  "dimers_overflow"])
+                                  "dimers_overflow", "wide_overflow"])
 def test_small_contact_set_colouring_paths_lockstep(cc, ctx, kind):
     # Contact sets of at most 4096 rows are coloured by one block with the vertex state
     # in LDS: one colour word per vertex (64 colours) for up to 4096 vertices, or, after
-    # a colouring of more than 56 colours, two words (128 colours) for up to 2048. A set
+    # a colouring of more than 56 colours, two words (128 colours) for up to 2944. A set
     # that needs more colours than the words hold, or touches more free vertices than
     # fit, is finished by the same block with the global-memory rounds. The cases:
     # - cluster: 90 particles, about 136 colours: beyond both layouts;
@@ -864,11 +864,19 @@ def test_small_contact_set_colouring_paths_lockstep(cc, ctx, kind):
     # - dimers_lds, dimers_many: 900 and 1500 dimers (1800 and 3000 free vertices, one
     #   colour) complete in LDS with one word;
     # - dimers_overflow: 2100 dimers, 4200 free vertices: more than 4096 fit, so the block
-    #   colours them with the global-memory rounds.
+    #   colours them with the global-memory rounds;
+    # - wide_overflow: the 50-particle cluster 1 m from 1500 dimers: the later iterations
+    #   take two words (more than 56 colours) over 3050 free vertices, more than 2944
+    #   fit, so the block colours them with the global-memory rounds.
     if kind == "cluster":
         x, xt = _particle_cluster(90, 4.5e-4, 5)
     elif kind == "cluster_wide":
         x, xt = _particle_cluster(50, 4.5e-4, 5)
+    elif kind == "wide_overflow":
+        xc, xtc = _particle_cluster(50, 4.5e-4, 5)
+        xd, xtd = _particle_dimers(1500, 7)
+        x = np.concatenate([xc + 1.0, xd])
+        xt = np.concatenate([xtc + 1.0, xtd])
     else:
         nd = {"dimers_lds": 900, "dimers_many": 1500, "dimers_overflow": 2100}[kind]
         x, xt = _particle_dimers(nd, 7)
@@ -883,3 +891,6 @@ def test_small_contact_set_colouring_paths_lockstep(cc, ctx, kind):
         assert 64 < cols[0] <= 127 and all(56 < c <= 127 for c in cols[1:3])
     elif kind == "dimers_overflow":
         assert len(x) > 4096 and gpu.trace[0]["n_a"] <= 4096
+    elif kind == "wide_overflow":
+        assert len(x) > 2944 and all(56 < c <= 127 for c in cols[1:3])
+        assert all(t["n_a"] <= 4096 for t in gpu.trace)
