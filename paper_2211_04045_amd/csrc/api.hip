@@ -212,18 +212,19 @@ void solver_free(cc_solver* s) {
   free_pairs(s);
   free_active(s);
   dfree(s->col_cnt); dfree(s->rcnt); dfree(s->coff_dev); dfree(s->ecoff_dev);
-  dfree(s->seg_dev);
-  if (s->seg_host) (void)hipHostFree(s->seg_host);
-  s->seg_host = nullptr;
   bvh_free(s);
   if (s->sel_host) (void)hipHostFree(s->sel_host);
   s->sel_host = nullptr;
-  if (s->hstripe) (void)hipHostFree(s->hstripe);
-  s->hstripe = nullptr;
   ecache_free(s);
-  dfree(s->dc);
-  if (s->hc) (void)hipHostFree(s->hc);
+  dfree(s->mirror_dev);
+  if (s->mirror_host) (void)hipHostFree(s->mirror_host);
+  s->mirror_host = nullptr;
+  s->dc = nullptr;
   s->hc = nullptr;
+  s->seg_dev = nullptr;
+  s->seg_host = nullptr;
+  s->stripe = nullptr;
+  s->hstripe = nullptr;
   for (auto& t : s->timers) {
     (void)hipEventDestroy(t.a);
     (void)hipEventDestroy(t.b);
@@ -321,13 +322,21 @@ int solver_alloc(cc_solver* s, int32_t capV, int32_t capF, int32_t capE, hipStre
   CC_TRY(dalloc(&s->rcnt, kMaxRounds + 1));
   CC_TRY(dalloc(&s->coff_dev, kMaxColors + 1));
   CC_TRY(dalloc(&s->ecoff_dev, kMaxColors + 1));
-  CC_TRY(dalloc(&s->seg_dev, kMaxSeg));
-  if (hipHostMalloc((void**)&s->seg_host, sizeof(SegDev) * kMaxSeg, hipHostMallocDefault) != hipSuccess)
+  static_assert(sizeof(Counters) <= kMirrorSeg - kMirrorCounters, "counters fit their slot");
+  static_assert(kMirrorCounters >= 64 * 16 * sizeof(unsigned long long), "stripes fit theirs");
+  const size_t mbytes = kMirrorSeg + sizeof(SegDev) * kMaxSeg;
+  CC_TRY(dalloc(&s->mirror_dev, (int64_t)mbytes));
+  if (hipHostMalloc((void**)&s->mirror_host, mbytes, hipHostMallocDefault) != hipSuccess) {
+    s->mirror_host = nullptr;
     return CC_ENOMEM;
-  memset(s->seg_host, 0, sizeof(SegDev) * kMaxSeg);
-  CC_TRY(dalloc(&s->dc, 1));
-  if (hipHostMalloc((void**)&s->hc, sizeof(Counters), hipHostMallocDefault) != hipSuccess)
-    return CC_ENOMEM;
+  }
+  memset(s->mirror_host, 0, mbytes);
+  s->stripe = reinterpret_cast<unsigned long long*>(s->mirror_dev + kMirrorStripe);
+  s->hstripe = reinterpret_cast<unsigned long long*>(s->mirror_host + kMirrorStripe);
+  s->dc = reinterpret_cast<Counters*>(s->mirror_dev + kMirrorCounters);
+  s->hc = reinterpret_cast<Counters*>(s->mirror_host + kMirrorCounters);
+  s->seg_dev = reinterpret_cast<SegDev*>(s->mirror_dev + kMirrorSeg);
+  s->seg_host = reinterpret_cast<SegDev*>(s->mirror_host + kMirrorSeg);
   CC_TRY(resize_arrays(s, std::max(capV, 1), std::max(capF, 1), std::max(capE, 1), st));
   const int64_t cap = std::max<int64_t>(4096, 32 * ((int64_t)capV + capE));
   CC_TRY(alloc_pairs(s, cap, 0, st));
@@ -711,8 +720,9 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
     CC_TRY(launch_pair_pass(s, n_old, sel.empty() ? s->nP : n_old, p.delta * p.delta, trace,
                             in_place, st));
     timer_end(s, st);
-    CC_HIP(hipMemcpyAsync(s->hc, s->dc, sizeof(Counters), hipMemcpyDeviceToHost, st));
-    CC_HIP(hipMemcpyAsync(s->seg_host, s->seg_dev, sizeof(SegDev) * ns, hipMemcpyDeviceToHost, st));
+    // the counters and the segment records in one copy
+    CC_HIP(hipMemcpyAsync(s->hc, s->dc, kMirrorSeg - kMirrorCounters + sizeof(SegDev) * ns,
+                          hipMemcpyDeviceToHost, st));
     CC_HIP(hipStreamSynchronize(st));
     if ((int64_t)s->hc->n_act <= s->capA) break;
     if (attempt > 0) return CC_EOVERFLOW;
@@ -780,10 +790,12 @@ int engine_iterate(cc_solver* s, hipStream_t st) {
   timer_begin(s, CC_K_CERT, st);
   CC_TRY(launch_cert(s, ccd_step, st));
   timer_end(s, st);
-  CC_HIP(hipMemcpyAsync(s->seg_host, s->seg_dev, sizeof(SegDev) * ns, hipMemcpyDeviceToHost, st));
   const bool small = s->col_small;
-  if (trace || jacobi || small)
-    CC_HIP(hipMemcpyAsync(s->hc, s->dc, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  if (trace || jacobi || small)  // the counters and the segment records in one copy
+    CC_HIP(hipMemcpyAsync(s->hc, s->dc, kMirrorSeg - kMirrorCounters + sizeof(SegDev) * ns,
+                          hipMemcpyDeviceToHost, st));
+  else
+    CC_HIP(hipMemcpyAsync(s->seg_host, s->seg_dev, sizeof(SegDev) * ns, hipMemcpyDeviceToHost, st));
   CC_HIP(hipStreamSynchronize(st));
   // vertices of pieces the certificate did not clear go back to x^(l); that changes
   // the pieces of the pairs sharing them, so the certificate runs again until it

@@ -35,6 +35,8 @@ constexpr unsigned long long kQueueCertified = 1ull << 63;
 constexpr unsigned long long kOneBits = 0x3FF0000000000000ull;  // bits of 1.0
 constexpr int kStepPasses = 16;  // CCD-based step: passes that scale steps
 constexpr int kMaxSeg = 1024;      // scenes (segments) resident in one solver
+// the shared readback block: stripe counts (64 x 128 B), counters, segment records
+constexpr size_t kMirrorStripe = 0, kMirrorCounters = 8192, kMirrorSeg = 8192 + 256;
 constexpr int kSegBits = 10;       // bits of a segment's rank in a search's sort keys
 constexpr int32_t kMaxIds = 1 << 30;  // primitive ids of pair keys are 30-bit
 constexpr double kFreeTol = 1e-9;  // input check: closest allowed distance (m)
@@ -296,6 +298,11 @@ struct cc_solver {
   int64_t capC = 0;
   long long* wtot = nullptr;
   int64_t capW = 0;
+  // the search's stripe counts, the counters and the segment records share one device
+  // block and one pinned host mirror (kMirror* offsets), so that each host round trip
+  // reads back what it needs with one copy
+  unsigned char* mirror_dev = nullptr;
+  unsigned char* mirror_host = nullptr;
   // counters
   cc::Counters* dc = nullptr;
   cc::Counters* hc = nullptr;  // pinned host mirror

@@ -1347,13 +1347,6 @@ int bvh_alloc(cc_solver* s) {
     return CC_ENOMEM;
   CC_TRY(dalloc(&s->root_t, kMaxSeg));
   CC_TRY(dalloc(&s->root_e, kMaxSeg));
-  CC_TRY(dalloc(&s->stripe, kStripes * kStripeWords));
-  if (!s->hstripe && hipHostMalloc((void**)&s->hstripe,
-                                   sizeof(unsigned long long) * kStripes * kStripeWords,
-                                   hipHostMallocDefault) != hipSuccess) {
-    s->hstripe = nullptr;
-    return CC_ENOMEM;
-  }
   return CC_OK;
 }
 
@@ -1366,7 +1359,7 @@ void bvh_free(cc_solver* s) {
   dfree(s->ubox_lo); dfree(s->ubox_hi); dfree(s->gprim); dfree(s->rs_hist); dfree(s->bounds);
   dfree(s->bounds_part); dfree(s->vorder); dfree(s->vrank); dfree(s->erank); dfree(s->rs_total);
   dfree(s->sel_dev); dfree(s->root_t); dfree(s->root_e);
-  dfree(s->stripe); dfree(s->skeys); dfree(s->sd2); dfree(s->chunks); dfree(s->wtot);
+  dfree(s->skeys); dfree(s->sd2); dfree(s->chunks); dfree(s->wtot);
   s->capS = 0;
   s->capC = 0;
   s->capW = 0;
@@ -1636,8 +1629,10 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
         timer_begin(s, CC_K_SEARCH, st);
         CC_TRY(launch_traverse(group, A, nq, st));
         timer_end(s, st);
-        CC_HIP(hipMemcpyAsync(s->hstripe, s->stripe, kStripeBytes, hipMemcpyDeviceToHost, st));
-        CC_HIP(hipMemcpyAsync(s->hc, s->dc, sizeof(Counters), hipMemcpyDeviceToHost, st));
+        // the stripe counts and the counters after them in one copy
+        static_assert(kStripeBytes == kMirrorCounters - kMirrorStripe, "stripes, then counters");
+        CC_HIP(hipMemcpyAsync(s->hstripe, s->stripe, kStripeBytes + sizeof(Counters),
+                              hipMemcpyDeviceToHost, st));
         CC_HIP(hipStreamSynchronize(st));
         if (s->hc->err & 2ull) return CC_EOVERFLOW;  // a traversal stack overflowed
         unsigned long long mx = 0, mr = 0, tot = 0, nvis = 0;
