@@ -710,6 +710,7 @@ struct TravArgs {
   int4* chunks;                // per stripe capC runs: wave, offset in its output, length, start
   int64_t capC;
   long long* wtot;             // per wave: pairs found
+  int32_t xcd_chunk;           // blocks per run of consecutive blocks dealt to one XCD
   Counters* cnt;
 };
 
@@ -800,18 +801,32 @@ constexpr int kGroupDefault = 16;
 constexpr int kGStack = 100;                // stack entries per traversal (4-wide DFS)
 constexpr int kQueue = 128;                 // candidate ring per wave (two rounds of 64)
 constexpr int kOut = 192;                   // found pairs held per wave (flushed from 128)
+constexpr int kXcdChunk = 32;               // consecutive traversal blocks per XCD
 constexpr int kStripes = 64;                // output stripes of the search
 constexpr int kStripeWords = 16;            // their counters 128 B apart
 constexpr int kRunShift = 40;               // a stripe counter: runs << 40 | pairs
 constexpr unsigned long long kPairMask = (1ull << kRunShift) - 1ull;
 
-template <int G>
+// The block's place in query order. Blocks are dealt to the 8 XCDs round-robin
+// (block b runs on XCD b mod 8), and each XCD has an L2 of its own. Runs of c
+// consecutive blocks (neighbouring queries in Morton order, which reach the same
+// part of the tree and the same primitives) go to one XCD, and consecutive runs to
+// consecutive XCDs, so that an XCD's waves share what its L2 holds while each XCD
+// still takes an even share of dense and sparse regions. The last blocks past a
+// whole number of rounds (8 c blocks each) keep their order. c = 1 is the identity.
+__device__ __forceinline__ int32_t xcd_block(int32_t b, int32_t nb, int32_t c) {
+  const int32_t full = nb / (8 * c) * (8 * c);
+  if (c <= 1 || b >= full) return b;
+  const int32_t x = b & 7, j = b >> 3;
+  return ((j / c) * 8 + x) * c + j % c;
+}
+
+template <int G, int P>
 struct WaveLds {
   int32_t stack[kWaves][64 / G][kGStack];
-  float4 nrec[kWaves][64 / G][8];  // two-node steps: the second node's record
+  float4 nrec[kWaves][64 / G][8 * P];  // the records of the nodes a group takes in one step
   int32_t qlane[kWaves][kQueue];  // candidate: query lane ...
   int32_t qprim[kWaves][kQueue];  // ... and leaf primitive
-  double qx[kWaves][6][64];       // query positions per lane
   int32_t qi[kWaves][3][64];      // query id and its vertices per lane
   uint64_t okey[kWaves][kOut];    // found pairs not yet written out
   double od2[kWaves][kOut];
@@ -824,7 +839,7 @@ struct WaveLds {
 // stripes fill evenly. The run is recorded (wave, its offset in the wave's output,
 // length, start) so that the gather can lay out P wave by wave.
 template <class LT>
-__device__ __forceinline__ void flush_out(LT& L, int wv, int& no, unsigned& sidx,
+__device__ __forceinline__ void flush_out(LT& L, int wv, int32_t gw, int& no, unsigned& sidx,
                                           long long& wrun, const TravArgs& A) {
   const int lane = __lane_id();
   const unsigned sid = sidx & (kStripes - 1);
@@ -840,14 +855,14 @@ __device__ __forceinline__ void flush_out(LT& L, int wv, int& no, unsigned& sidx
     for (int j = lane; j < no; j += 64) {
       const int64_t pos = (int64_t)base + j;
       if (pos < A.capS) {
-        A.out[s0 + pos] = L.okey[wv][j];
-        if (A.outd) A.outd[s0 + pos] = L.od2[wv][j];
+        __builtin_nontemporal_store(L.okey[wv][j], &A.out[s0 + pos]);
+        if (A.outd) __builtin_nontemporal_store(L.od2[wv][j], &A.outd[s0 + pos]);
       }
     }
     const int64_t run = (int64_t)(old >> kRunShift);
     if (lane == 0 && run < A.capC)
       A.chunks[(int64_t)sid * A.capC + run] =
-          make_int4((int)(blockIdx.x * kWaves + wv), (int)wrun, no, (int)base);
+          make_int4((int)gw, (int)wrun, no, (int)base);
   }
   wrun += no;
   no = 0;
@@ -857,7 +872,7 @@ __device__ __forceinline__ void flush_out(LT& L, int wv, int& no, unsigned& sidx
 // The exact test of n <= 64 queued candidates, one per lane; found pairs join the
 // wave's held pairs (no, wave-uniform), written out from 128 on.
 template <class LT>
-__device__ __forceinline__ void drain(LT& L, int wv, int head, int n, int kind, int& no,
+__device__ __forceinline__ void drain(LT& L, int wv, int32_t gw, int head, int n, int kind, int& no,
                                       unsigned& sidx, long long& wrun, unsigned& ntested,
                                       const TravArgs& A) {
   ntested += (unsigned)n;
@@ -869,10 +884,11 @@ __device__ __forceinline__ void drain(LT& L, int wv, int head, int n, int kind, 
     const int e = (head + lane) & (kQueue - 1);
     const int ql = L.qlane[wv][e];
     const int32_t prim = L.qprim[wv][e];
-    const V3 qx0{L.qx[wv][0][ql], L.qx[wv][1][ql], L.qx[wv][2][ql]};
-    const V3 qx1{L.qx[wv][3][ql], L.qx[wv][4][ql], L.qx[wv][5][ql]};
-    found = candidate(A, kind, prim, L.qi[wv][0][ql], L.qi[wv][1][ql], L.qi[wv][2][ql], qx0, qx1,
-                      &key, &d2);
+    const int32_t qv0 = L.qi[wv][1][ql], qv1 = L.qi[wv][2][ql];
+    // the query's positions, gathered again (the same values its box was made from)
+    const V3 qx0 = ld3(A.x, qv0);
+    const V3 qx1 = kind == kQEE ? ld3(A.x, qv1) : qx0;
+    found = candidate(A, kind, prim, L.qi[wv][0][ql], qv0, qv1, qx0, qx1, &key, &d2);
   }
   __builtin_amdgcn_wave_barrier();
   const uint64_t m = __ballot(found);
@@ -883,7 +899,7 @@ __device__ __forceinline__ void drain(LT& L, int wv, int head, int n, int kind, 
   }
   no += __popcll(m);
   __builtin_amdgcn_wave_barrier();
-  if (no >= kOut - 64) flush_out(L, wv, no, sidx, wrun, A);
+  if (no >= kOut - 64) flush_out(L, wv, gw, no, sidx, wrun, A);
 }
 
 // Proximity search (Sec. 3.1). A wave takes 64 consecutive queries of one class
@@ -898,15 +914,20 @@ __device__ __forceinline__ void drain(LT& L, int wv, int head, int n, int kind, 
 // exactly the leaves its own box overlaps (their ancestors overlap it too), so
 // the pair set is that of independent per-query traversals, whatever kGroup is.
 // Lanes of different scenes in one group walk their own subtrees in turn.
-// (occupancy target: 4 waves per SIMD; 3 for 8-lane groups, whose LDS allows no more)
+// The records of the nodes a group takes in one step are staged in LDS (one float4
+// per lane) and their children tested in a loop that is not unrolled, so that the
+// exact tests are compiled once: the kernel's code stays within the instruction
+// cache. (occupancy target: 4 waves per SIMD)
 template <int kGroup, int kPop>
-__global__ void __launch_bounds__(kTravThreads, kGroup == 8 ? 3 : 4) k_traverse(TravArgs A) {
-  __shared__ WaveLds<kGroup> L;
+__global__ void __launch_bounds__(kTravThreads, 4) k_traverse(TravArgs A) {
+  __shared__ WaveLds<kGroup, kPop> L;
   // the wave index is uniform over the wave: held in a scalar register
   const int lane = __lane_id(), wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int grp = lane / kGroup, gl = lane % kGroup;
   const uint64_t gmask = (kGroup == 64 ? ~0ull : ((1ull << kGroup) - 1ull)) << (grp * kGroup);
-  const int32_t q0 = blockIdx.x * kTravThreads + wv * 64;  // the wave's first padded query
+  const int32_t lb = xcd_block(blockIdx.x, gridDim.x, A.xcd_chunk);
+  const int32_t gw = lb * kWaves + wv;                // the wave's place in query order
+  const int32_t q0 = gw * 64;                         // the wave's first padded query
   int kind;
   int32_t idx, ncl;
   if (q0 < A.mv_pad) {
@@ -957,18 +978,12 @@ __global__ void __launch_bounds__(kTravThreads, kGroup == 8 ? 3 : 4) k_traverse(
                         hi_out(fmax(qx0.z, qx1.z) + A.infl), 0.f);
     }
   }
-  L.qx[wv][0][lane] = qx0.x;
-  L.qx[wv][1][lane] = qx0.y;
-  L.qx[wv][2][lane] = qx0.z;
-  L.qx[wv][3][lane] = qx1.x;
-  L.qx[wv][4][lane] = qx1.y;
-  L.qx[wv][5][lane] = qx1.z;
   L.qi[wv][0][lane] = qid;
   L.qi[wv][1][lane] = qv0;
   L.qi[wv][2][lane] = qv1;
   int head = 0, qn = 0;  // candidate ring: first entry, entries queued (wave-uniform)
   int no = 0;            // found pairs held (wave-uniform)
-  unsigned sidx = blockIdx.x * kWaves + wv;  // the stripe of the wave's next flush
+  unsigned sidx = gw;  // the stripe of the wave's next flush
   long long wrun = 0;                         // pairs the wave has written out
   unsigned ntested = 0;  // candidates tested by the wave
   unsigned nvisit = 0;   // node records this lane's group read (counted by its first lane)
@@ -986,7 +1001,7 @@ __global__ void __launch_bounds__(kTravThreads, kGroup == 8 ? 3 : 4) k_traverse(
   }
   __builtin_amdgcn_wave_barrier();
   if (qn == 64) {
-    drain(L, wv, head, 64, kind, no, sidx, wrun, ntested, A);
+    drain(L, wv, gw, head, 64, kind, no, sidx, wrun, ntested, A);
     qn = 0;
     __builtin_amdgcn_wave_barrier();
   }
@@ -1019,52 +1034,38 @@ __global__ void __launch_bounds__(kTravThreads, kGroup == 8 ? 3 : 4) k_traverse(
     // kPop nodes leave the group's stack per step, their records loaded together so
     // that their latencies overlap (kPop = 2 halves the chain of dependent loads of a
     // deep walk; the set of nodes visited is the same)
-    bool valid[kPop];
+    unsigned vmask = 0;  // the nodes taken (uniform in the group)
     int32_t ni[kPop];
 #pragma unroll
     for (int k = 0; k < kPop; ++k) {
-      valid[k] = sp > 0;
       ni[k] = 0;
-      if (valid[k]) {
+      if (sp > 0) {
         --sp;
         ni[k] = L.stack[wv][grp][sp];
+        vmask |= 1u << k;
         if (gl == 0) ++nvisit;
       }
     }
-    // both records are loaded together; the second goes to LDS (each lane of the
-    // group stores one of its eight float4), so that registers hold one record while
-    // the first node's children are tested and candidates drained
-    float4 rb0[4], rb1[4];
+    // each lane of the group stages float4s of the records (8 per node) in LDS
 #pragma unroll
-    for (int slot = 0; slot < 4; ++slot) {
-      rb0[slot] = make_float4(0.f, 0.f, 0.f, 0.f);
-      rb1[slot] = rb0[slot];
-    }
-    if (valid[0]) {
-      const float4* rec = T.wide + 8 * (int64_t)ni[0];
+    for (int f0 = 0; f0 < 8 * kPop; f0 += kGroup) {
+      const int f = f0 + gl;
+      if (f < 8 * kPop) {
+        float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
+        int32_t nk = ni[0];
 #pragma unroll
-      for (int slot = 0; slot < 4; ++slot) {
-        rb0[slot] = rec[2 * slot];
-        rb1[slot] = rec[2 * slot + 1];
+        for (int k = 1; k < kPop; ++k)
+          if ((f >> 3) == k) nk = ni[k];
+        if ((vmask >> (f >> 3)) & 1u) r = T.wide[8 * (int64_t)nk + (f & 7)];
+        L.nrec[wv][grp][f] = r;
       }
     }
-    if (kPop > 1) {
-      float4 r2 = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (valid[kPop - 1] && gl < 8) r2 = T.wide[8 * (int64_t)ni[kPop - 1] + gl];
-      if (gl < 8) L.nrec[wv][grp][gl] = r2;
-      __builtin_amdgcn_wave_barrier();
-    }
-#pragma unroll
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll 1
     for (int slot = 0; slot < 4 * kPop; ++slot) {
-      float4 b0, b1;
-      if (slot < 4) {
-        b0 = rb0[slot];
-        b1 = rb1[slot];
-      } else {
-        b0 = L.nrec[wv][grp][2 * (slot - 4)];
-        b1 = L.nrec[wv][grp][2 * (slot - 4) + 1];
-      }
-      const bool ov = valid[slot / 4] && part &&
+      const float4 b0 = L.nrec[wv][grp][2 * slot];
+      const float4 b1 = L.nrec[wv][grp][2 * slot + 1];
+      const bool ov = ((vmask >> (slot >> 2)) & 1u) && part &&
                       overlap6(qlo, qhi, b0.x, b0.y, b0.z, b0.w, b1.x, b1.y) &&
                       __float_as_int(b1.w) > qpos &&
                       !far6(qlo, qhi, b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, A.fdmax, qr2);
@@ -1090,16 +1091,16 @@ __global__ void __launch_bounds__(kTravThreads, kGroup == 8 ? 3 : 4) k_traverse(
       qn += __popcll(ml);
       __builtin_amdgcn_wave_barrier();
       while (qn >= 64) {
-        drain(L, wv, head, 64, kind, no, sidx, wrun, ntested, A);
+        drain(L, wv, gw, head, 64, kind, no, sidx, wrun, ntested, A);
         head = (head + 64) & (kQueue - 1);
         qn -= 64;
         __builtin_amdgcn_wave_barrier();
       }
     }
   }
-  if (qn > 0) drain(L, wv, head, qn, kind, no, sidx, wrun, ntested, A);
-  if (no > 0) flush_out(L, wv, no, sidx, wrun, A);
-  if (A.out && lane == 0) A.wtot[blockIdx.x * kWaves + wv] = wrun;
+  if (qn > 0) drain(L, wv, gw, head, qn, kind, no, sidx, wrun, ntested, A);
+  if (no > 0) flush_out(L, wv, gw, no, sidx, wrun, A);
+  if (A.out && lane == 0) A.wtot[gw] = wrun;
   // node records read by the wave's groups: the measure of the tree's quality
   unsigned long long nv = nvisit;
   for (int o = 32; o >= 1; o >>= 1) nv += __shfl_xor(nv, o);
@@ -1573,6 +1574,7 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
     A.chunks = s->chunks;
     A.capC = s->capC;
     A.cnt = s->dc;
+    A.xcd_chunk = kXcdChunk;
     A.mv_pad = (A.mv + 63) & ~63;
     A.me_pad = (me + 63) & ~63;
     int64_t nq = (int64_t)A.mv_pad + A.me_pad + mp;
