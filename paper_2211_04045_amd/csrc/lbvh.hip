@@ -505,12 +505,21 @@ struct RefitView {
 
 // Refit, part 1 (one 256-leaf block): leaf boxes into their parents, prefix and
 // suffix unions inside the block, the block box, and every internal node whose
-// leaf range lies inside the block (range union read from LDS).
+// leaf range lies inside the block. Those nodes are formed bottom-up: each leaf
+// climbs from its parent, and of a node's two children the second to arrive
+// (an arrival count in LDS) forms the node's box from its own and its sibling's
+// and climbs on, so a thread does as many steps as its leaf is deep in the
+// block's part of the tree. (A Karras node's index lies in its leaf range, so
+// a node inside the block has its arrival count at its index minus the block's
+// first leaf.)
 __device__ void refit_block(const RefitView& T, int32_t b) {
   __shared__ float slo[3][kBlk], shi[3][kBlk];
+  __shared__ int arrive[kBlk];
+  __shared__ float cbox[kBlk][2][6];
   const int32_t B0 = b * kBlk;
   const int32_t cnt = T.n - B0 < kBlk ? T.n - B0 : kBlk;
   const int tid = threadIdx.x;
+  arrive[tid] = 0;
   Box6 mine = box_empty();
   if (tid < cnt) {
     float4 l = T.leaf_lo[B0 + tid], h = T.leaf_hi[B0 + tid];
@@ -564,24 +573,29 @@ __device__ void refit_block(const RefitView& T, int32_t b) {
     __syncthreads();
   }
   if (tid < cnt) box_st(T.suf + 2 * (B0 + tid), suf);
-  // leaves again for range unions
-  for (int k = 0; k < 3; ++k) {
-    slo[k][tid] = mine.lo[k];
-    shi[k][tid] = mine.hi[k];
-  }
-  __syncthreads();
-  const int32_t i = B0 + tid;
-  if (i < T.n - 1) {
-    int2 r = T.range[i];
-    if (r.x >= B0 && r.y < B0 + kBlk) {
-      Box6 u = box_empty();
-      for (int32_t j = r.x - B0; j <= r.y - B0; ++j)
-        for (int k = 0; k < 3; ++k) {
-          u.lo[k] = fminf(u.lo[k], slo[k][j]);
-          u.hi[k] = fmaxf(u.hi[k], shi[k][j]);
-        }
-      box_to_parent(T.node, T.root, T.parent[i], u);
+  if (tid >= cnt) return;
+  Box6 u = mine;
+  int32_t par = T.parent[T.n - 1 + B0 + tid];
+  while (par >= 0) {
+    const int32_t p = par >> 1, side = par & 1;
+    const int2 r = T.range[p];
+    if (r.x < B0 || r.y >= B0 + kBlk) break;  // crosses the block: part 2
+    const int slot = p - B0;
+    for (int k = 0; k < 3; ++k) {
+      cbox[slot][side][k] = u.lo[k];
+      cbox[slot][side][3 + k] = u.hi[k];
     }
+    __threadfence_block();
+    if (atomicAdd(&arrive[slot], 1) == 0) break;  // the sibling forms the node
+    __threadfence_block();
+    Box6 o;
+    for (int k = 0; k < 3; ++k) {
+      o.lo[k] = cbox[slot][side ^ 1][k];
+      o.hi[k] = cbox[slot][side ^ 1][3 + k];
+    }
+    u = box_union(u, o);
+    par = T.parent[p];
+    box_to_parent(T.node, T.root, par, u);
   }
 }
 
