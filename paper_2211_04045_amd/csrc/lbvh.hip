@@ -501,7 +501,37 @@ struct RefitView {
   float4* pre;  // 2 per leaf
   float4* suf;  // 2 per leaf
   float4* blk;  // 2 per block
+  float4* wide;     // the 4-wide records (8 float4 per internal node)
+  int wide_direct;  // a refit of built records: boxes go into them directly
 };
+
+// A box into one slot of a 4-wide record (the slot's first six floats; its
+// child id and last leaf position stay as the build wrote them).
+__device__ __forceinline__ void wide_slot_st(float4* wide, int32_t r, int slot, const Box6& b) {
+  float* f = (float*)(wide + 8 * (int64_t)r + 2 * slot);
+  f[0] = b.lo[0];
+  f[1] = b.lo[1];
+  f[2] = b.lo[2];
+  f[3] = b.hi[0];
+  f[4] = b.hi[1];
+  f[5] = b.hi[2];
+}
+
+// A node's (or leaf's) box to where the traversal reads it: the root box, or the
+// binary record of its parent (from which a build makes the 4-wide records); in
+// a refit of built 4-wide records, the wide record of its grandparent instead
+// (slot 2 x the parent's side + its own side), and for a leaf its parent's wide
+// record too (slot 2 x its side: a leaf child stays in place).
+__device__ __forceinline__ void put_box(const RefitView& T, int32_t par, bool leaf, const Box6& b) {
+  if (par < 0 || !T.wide_direct) {
+    box_to_parent(T.node, T.root, par, b);
+    return;
+  }
+  const int32_t p = par >> 1, side = par & 1;
+  if (leaf) wide_slot_st(T.wide, p, 2 * side, b);
+  const int32_t gp = T.parent[p];
+  if (gp >= 0) wide_slot_st(T.wide, gp >> 1, 2 * (gp & 1) + side, b);
+}
 
 // Refit, part 1 (one 256-leaf block): leaf boxes into their parents, prefix and
 // suffix unions inside the block, the block box, and every internal node whose
@@ -524,7 +554,7 @@ __device__ void refit_block(const RefitView& T, int32_t b) {
   if (tid < cnt) {
     float4 l = T.leaf_lo[B0 + tid], h = T.leaf_hi[B0 + tid];
     mine = Box6{{l.x, l.y, l.z}, {h.x, h.y, h.z}};
-    box_to_parent(T.node, T.root, T.parent[T.n - 1 + B0 + tid], mine);
+    put_box(T, T.parent[T.n - 1 + B0 + tid], true, mine);
   }
   for (int k = 0; k < 3; ++k) {
     slo[k][tid] = mine.lo[k];
@@ -595,7 +625,7 @@ __device__ void refit_block(const RefitView& T, int32_t b) {
     }
     u = box_union(u, o);
     par = T.parent[p];
-    box_to_parent(T.node, T.root, par, u);
+    put_box(T, par, false, u);
   }
 }
 
@@ -638,7 +668,7 @@ __device__ void refit_top(const RefitView& T, int32_t i) {
     const float4* lev = T.blk + (int64_t)2 * nb * k;
     u = box_union(u, box_union(box_ld(lev + 2 * lo), box_ld(lev + 2 * (hi - (1 << k) + 1))));
   }
-  box_to_parent(T.node, T.root, T.parent[i], u);
+  put_box(T, T.parent[i], false, u);
 }
 
 __global__ void k_refit_top(RefitView ta, RefitView tb) {
@@ -869,8 +899,8 @@ __device__ __forceinline__ void flush_out(LT& L, int wv, int32_t gw, int& no, un
     for (int j = lane; j < no; j += 64) {
       const int64_t pos = (int64_t)base + j;
       if (pos < A.capS) {
-        __builtin_nontemporal_store(L.okey[wv][j], &A.out[s0 + pos]);
-        if (A.outd) __builtin_nontemporal_store(L.od2[wv][j], &A.outd[s0 + pos]);
+        A.out[s0 + pos] = L.okey[wv][j];
+        if (A.outd) A.outd[s0 + pos] = L.od2[wv][j];
       }
     }
     const int64_t run = (int64_t)(old >> kRunShift);
@@ -1382,17 +1412,20 @@ void bvh_free(cc_solver* s) {
 
 static inline unsigned blocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-static RefitView refit_view(Bvh& b) {
-  return RefitView{b.n, b.leaf_lo, b.leaf_hi, b.parent, b.range, b.node, b.root,
-                   b.pre, b.suf, b.blk};
+static RefitView refit_view(Bvh& b, bool direct) {
+  return RefitView{b.n,   b.leaf_lo, b.leaf_hi, b.parent, b.range, b.node,
+                   b.root, b.pre,    b.suf,     b.blk,    b.wide,  direct ? 1 : 0};
 }
 
-// Node boxes from the leaf boxes (fence-free refit), then the 4-wide records.
-static int refit_and_widen(cc_solver* s, int32_t mt, int32_t me, int32_t mp, hipStream_t st) {
+// Node boxes from the leaf boxes (fence-free refit). After a build the 4-wide
+// records are then made from the binary ones; a refit of the same tree writes
+// the boxes into the built 4-wide records as it forms them.
+static int refit_and_widen(cc_solver* s, int32_t mt, int32_t me, int32_t mp, bool built,
+                           hipStream_t st) {
   Bvh& bt = s->tree_t;
   Bvh& be = s->tree_e;
   Bvh& bp = s->tree_p;
-  RefitView ra = refit_view(bt), rbv = refit_view(be);
+  RefitView ra = refit_view(bt, !built), rbv = refit_view(be, !built);
   if (mt < 2) ra.n = 0;
   if (me < 2) rbv.n = 0;
   const int32_t nba = (ra.n + kBlk - 1) / kBlk, nbb = (rbv.n + kBlk - 1) / kBlk;
@@ -1403,16 +1436,18 @@ static int refit_and_widen(cc_solver* s, int32_t mt, int32_t me, int32_t mp, hip
     k_refit_top<<<blocks(ninternal, 256), 256, 0, st>>>(ra, rbv);
   }
   if (mp > 1) {  // the particle tree, refit on its own
-    RefitView rc = refit_view(bp), rnone = refit_view(bp);
+    RefitView rc = refit_view(bp, !built), rnone = refit_view(bp, !built);
     rnone.n = 0;
     const int32_t nbc = (mp + kBlk - 1) / kBlk;
     k_refit_block<<<nbc, kBlk, 0, st>>>(rc, rnone, nbc);
     k_blk_sparse<<<1, 1024, 0, st>>>(rc, rnone);
     k_refit_top<<<blocks(mp - 1, 256), 256, 0, st>>>(rc, rnone);
   }
-  if (mt > 1) k_wide<<<blocks(mt - 1, 256), 256, 0, st>>>(bt.node, bt.wide, mt - 1);
-  if (me > 1) k_wide<<<blocks(me - 1, 256), 256, 0, st>>>(be.node, be.wide, me - 1);
-  if (mp > 1) k_wide<<<blocks(mp - 1, 256), 256, 0, st>>>(bp.node, bp.wide, mp - 1);
+  if (built) {
+    if (mt > 1) k_wide<<<blocks(mt - 1, 256), 256, 0, st>>>(bt.node, bt.wide, mt - 1);
+    if (me > 1) k_wide<<<blocks(me - 1, 256), 256, 0, st>>>(be.node, be.wide, me - 1);
+    if (mp > 1) k_wide<<<blocks(mp - 1, 256), 256, 0, st>>>(bp.node, bp.wide, mp - 1);
+  }
   CC_HIP(hipGetLastError());
   return CC_OK;
 }
@@ -1507,7 +1542,7 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
         x, s->tris, s->edges, mt, me, mp, infl, LeafOut{bt.leaf_lo, bt.leaf_hi, bt.leaf_prim, nullptr},
         LeafOut{be.leaf_lo, be.leaf_hi, be.leaf_prim, nullptr},
         LeafOut{bp.leaf_lo, bp.leaf_hi, bp.leaf_prim, nullptr});
-    CC_TRY(refit_and_widen(s, mt, me, mp, st));
+    CC_TRY(refit_and_widen(s, mt, me, mp, false, st));
   } else if (m > 0) {
     CC_HIP(hipMemcpyAsync(s->sel_dev, s->sel_host, sizeof(SelDev) * (nsel + 1),
                           hipMemcpyHostToDevice, st));
@@ -1550,7 +1585,7 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
     k_seg_roots<<<blocks(nsel, 256), 256, 0, st>>>(s->sel_dev, nsel, mt, me, mp, bt.range,
                                                    bt.leaf_prim, be.range, be.leaf_prim, bp.range,
                                                    bp.leaf_prim, s->root_t, s->root_e, s->root_p);
-    CC_TRY(refit_and_widen(s, mt, me, mp, st));
+    CC_TRY(refit_and_widen(s, mt, me, mp, true, st));
   }
   if (m > 0) {
     TravArgs A;
