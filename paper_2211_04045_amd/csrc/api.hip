@@ -160,7 +160,7 @@ void free_pairs(cc_solver* s) {
 void free_active(cc_solver* s) {
   dfree(s->Akeys); dfree(s->Averts); dfree(s->Acol); dfree(s->Aorder);
   dfree(s->list0); dfree(s->list1); dfree(s->lamA); dfree(s->afail); dfree(s->apick);
-  dfree(s->Arow);
+  dfree(s->Arow); dfree(s->Aslot); dfree(s->lvert);
 }
 
 // Pair buffers of capacity cap; the first `keep` keys of P survive.
@@ -188,6 +188,8 @@ int alloc_active(cc_solver* s, int64_t cap) {
   CC_TRY(dalloc(&s->afail, cap));
   CC_TRY(dalloc(&s->apick, cap));
   CC_TRY(dalloc(&s->Arow, cap * kRowWords));
+  CC_TRY(dalloc(&s->Aslot, cap));
+  CC_TRY(dalloc(&s->lvert, (int64_t)kLocCap1));
   return CC_OK;
 }
 

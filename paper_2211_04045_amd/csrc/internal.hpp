@@ -42,6 +42,8 @@ constexpr int32_t kMaxIds = 1 << 30;  // primitive ids of pair keys are 30-bit
 constexpr double kFreeTol = 1e-9;  // input check: closest allowed distance (m)
 constexpr int kRowWords = 20;      // one linearised contact row: ids, c0, 1/A, w[4], J[4]
 constexpr int kSmallRows = 4096;   // contact sets up to this size are coloured by one block
+// vertices a one-block colouring holds in LDS with one colour word each
+constexpr int kLocCap1 = 4096;
 constexpr int32_t kNoLoc = 0x7fffffff;  // vloc entry of a vertex no colouring block holds
 
 // Per-segment record on the device (one scene of a multi-scene solver). The host
@@ -86,6 +88,8 @@ struct Counters {
   unsigned long long et;        // input check: an edge meets a triangle
   unsigned long long ncert;     // certificate: pairs queued for the continuous test
   unsigned long long ecmis;     // edge colouring cache: inputs differing from the last
+  unsigned long long nloc;      // one-block colouring: free vertices given block-local
+                                // slots (above kLocCap1 when it coloured without them)
 };
 
 // Device buffers of a linear BVH over n leaves (n-1 internal nodes), allocated
@@ -226,6 +230,10 @@ struct cc_solver {
   int32_t *list0 = nullptr, *list1 = nullptr;
   double* lamA = nullptr;
   double* Arow = nullptr;  // contact rows linearised at x (kRowWords doubles each)
+  // one-block colouring: each row's four block-local vertex slots (16 bits each,
+  // 0xffff: none) and the vertex of each slot
+  unsigned long long* Aslot = nullptr;
+  int32_t* lvert = nullptr;
   int64_t nA = 0;
   int32_t n_colors = 0;
   std::vector<int32_t> col_off;  // host copy of colour bucket offsets (n_colors+1)

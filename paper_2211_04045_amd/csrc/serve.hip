@@ -263,7 +263,7 @@ size_t cc_scene_bytes(int32_t n, int32_t nt, int32_t ne) {
   const size_t per_prim = 32 + 4 + 64 + 128 + 8 + 8 + 64 + 32 + 2 * 12;
   const size_t per_e = 8 + 4 + 24 + 8 + 4 + 4 + 12 + 8 + 2;
   const size_t pair_cap = 32 * ((size_t)n + (size_t)ne);
-  const size_t pairs = pair_cap * 32 + (pair_cap / 8) * (8 + 16 + 4 + 4 + 8 + 8 + 8 * cc::kRowWords);
+  const size_t pairs = pair_cap * 32 + (pair_cap / 8) * (8 + 16 + 4 + 4 + 8 + 8 + 8 + 8 * cc::kRowWords);
   // particles (vertices in no triangle or edge): at least n - 3F - 2E of them, each a
   // leaf of the particle tree and a search key
   const int64_t np = std::max<int64_t>(0, (int64_t)n - 3 * (int64_t)nt - 2 * (int64_t)ne);

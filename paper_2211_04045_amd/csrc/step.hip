@@ -701,6 +701,8 @@ struct PcArgs {
   int maxc;
   int32_t* colors;
   Counters* c;
+  unsigned long long* lslot;  // one-block colouring of contact rows: each row's
+  int32_t* lvert;             // block-local vertex slots, and each slot's vertex
 };
 
 __device__ __forceinline__ bool is_free(const double* w, int32_t v) { return v >= 0 && w[v] > 0.0; }
@@ -912,7 +914,7 @@ constexpr int kSmallPer = kSmallRows / kTailThreads;  // rows per thread
 // below 64 kLocWords) for at most kLocCap distinct free vertices. One word holds 4096
 // vertices (about 116 KB of LDS), two words 2944 (about 154 KB; a block may take up
 // to 160 KB on gfx950).
-constexpr int kLocCap1 = 4096, kLocCap2 = 2944;
+constexpr int kLocCap2 = 2944;
 static_assert(kSmallRows % kTailThreads == 0, "whole rows per thread");
 static_assert(kMaxColors == kTailThreads, "one thread per colour bucket in the scan");
 
@@ -985,6 +987,7 @@ __global__ void __launch_bounds__(kTailThreads) k_pc_small(PcArgs a, int32_t nro
       if (__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != r * 4 + q) continue;
       const int32_t l = atomicAdd(&s_nloc, 1);
       if (l < kLocCap) {
+        if (a.lvert) a.lvert[l] = vid[k][q];
         s_unc[l] = 0u;
 #pragma unroll
         for (int wd = 0; wd < kLocWords; ++wd) s_mask[l][wd] = s_claim[l][wd] = s_clash[l][wd] = 0ull;
@@ -1166,6 +1169,8 @@ __global__ void __launch_bounds__(kTailThreads) k_pc_small(PcArgs a, int32_t nro
   off[tid] = ex;
   if (tid == kTailThreads - 1) off[kMaxColors] = ex + cv;
   if (tid == 0 && !global_rounds) a.c->ncol = (unsigned long long)s_ncol;
+  // the rows' block-local slots, for a projection that keeps y at them in LDS
+  if (tid == 0 && a.lslot) a.c->nloc = global_rounds ? ~0ull : (unsigned long long)s_nloc;
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kSmallPer; ++k) {
@@ -1173,6 +1178,13 @@ __global__ void __launch_bounds__(kTailThreads) k_pc_small(PcArgs a, int32_t nro
     if (r >= nrows) continue;
     order[s_cnt[col[k]] + rank[k]] = r;
     a.colors[r] = col[k];
+    if (a.lslot && !global_rounds) {
+      unsigned long long ps = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        ps |= (unsigned long long)(lid[k][q] >= 0 ? (uint32_t)lid[k][q] : 0xffffu) << (16 * q);
+      a.lslot[r] = ps;
+    }
   }
 }
 
@@ -1258,6 +1270,8 @@ static PcArgs pc_args(cc_solver* s, bool edges) {
   a.maxc = s->p.max_colors;
   a.colors = edges ? s->ecol : s->Acol;
   a.c = s->dc;
+  a.lslot = edges ? nullptr : s->Aslot;
+  a.lvert = edges ? nullptr : s->lvert;
   return a;
 }
 
@@ -1712,6 +1726,8 @@ static_assert(sizeof(RowRec) == 8 * kRowWords, "contact row record size");
 
 struct GsArgs {
   const int32_t* order;
+  const unsigned long long* lslot;  // small contact sets: the rows' block-local slots
+  const int32_t* lvert;             // and each slot's vertex (from the colouring)
   const int2* eij;  // edge rows: the vertices of each bucket position (with order)
   int32_t cnt;
   const RowRec* rows;
@@ -1940,11 +1956,17 @@ __global__ void __launch_bounds__(kGsTailThreads) k_gs_tail(GsArgs a, const int3
 // p mod kGsTailThreads; the thread of position p < kGsTailThreads holds that row's
 // record from the start, so a colour costs it only the loads of x and y at the row's
 // vertices and the stores. The bucket offsets are staged in LDS.
+// When every row has its own thread and the colouring gave the rows' free vertices
+// block-local slots (at most kLocCap1), y at those vertices stays in LDS for the
+// whole sweep (read once, written back once) and each thread holds x at its row's
+// vertices (y - x at its fixed ones, which the sweep does not move): a colour is
+// then LDS traffic only. The arithmetic is the same, in the same order.
 template <bool kMixed>
 __global__ void __launch_bounds__(kGsTailThreads) k_gs_contact_small(
     GsArgs a, const int32_t* __restrict__ off, const unsigned long long* ncolp,
-    const unsigned long long* nAp) {
+    const unsigned long long* nAp, const unsigned long long* nlocp) {
   __shared__ int32_t s_off[kMaxColors + 1];
+  __shared__ double s_y[kLocCap1][3];
   if (gs_off(a)) return;
   const int32_t ncol = (int32_t)*ncolp;
   const int32_t nA = (int32_t)*nAp;
@@ -1956,6 +1978,65 @@ __global__ void __launch_bounds__(kGsTailThreads) k_gs_contact_small(
     r0 = a.order[p0];
     R0 = a.rows[r0];
     if (!(R0.inv_a > 0.0)) r0 = -1;  // an inactive row does nothing
+  }
+  const unsigned long long nloc = a.lslot ? *nlocp : ~0ull;
+  if (!kMixed && nA <= kGsTailThreads && nloc <= (unsigned long long)kLocCap1) {
+    const int32_t U = (int32_t)nloc;
+    for (int32_t l = threadIdx.x; l < U; l += kGsTailThreads) {
+      const V3 yv = ld3(a.y, a.lvert[l]);
+      s_y[l][0] = yv.x;
+      s_y[l][1] = yv.y;
+      s_y[l][2] = yv.z;
+    }
+    int32_t sl[4] = {-1, -1, -1, -1};
+    V3 xc[4];  // x at a free vertex, y - x at a fixed one
+    double lam = 0.0;
+    const int32_t v[4] = {R0.v.x, R0.v.y, R0.v.z, R0.v.w};
+    const int nk = v[2] < 0 ? 2 : 4;
+    if (r0 >= 0) {
+      const unsigned long long ps = a.lslot[r0];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int32_t q = (int32_t)((ps >> (16 * k)) & 0xffffull);
+        sl[k] = q == 0xffff ? -1 : q;
+        xc[k] = V3{0.0, 0.0, 0.0};
+        if (k >= nk) continue;
+        const V3 xk = ld3(a.x, v[k]);
+        xc[k] = sl[k] >= 0 ? xk : vsub(ld3(a.y, v[k]), xk);
+      }
+      lam = a.lam[r0];
+    }
+    __syncthreads();
+    for (int32_t c = 0; c < ncol; ++c) {
+      if (r0 >= 0 && p0 >= s_off[c] && p0 < s_off[c + 1]) {
+        double wr = R0.c0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (k >= nk) continue;
+          const V3 dy = sl[k] >= 0 ? vsub(V3{s_y[sl[k]][0], s_y[sl[k]][1], s_y[sl[k]][2]}, xc[k])
+                                   : xc[k];
+          wr = wr + vdot(R0.J[k], dy);
+        }
+        double ln = lam - wr * R0.inv_a;
+        if (ln < 0.0) ln = 0.0;
+        const double dl = ln - lam;
+        lam = ln;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (k >= nk || sl[k] < 0 || !(R0.w[k] > 0.0)) continue;
+          const double co = R0.w[k] * dl;
+          double* yv = s_y[sl[k]];
+          yv[0] = yv[0] + co * R0.J[k].x;
+          yv[1] = yv[1] + co * R0.J[k].y;
+          yv[2] = yv[2] + co * R0.J[k].z;
+        }
+      }
+      __syncthreads();
+    }
+    if (r0 >= 0) a.lam[r0] = lam;
+    for (int32_t l = threadIdx.x; l < U; l += kGsTailThreads)
+      st3(a.y, a.lvert[l], V3{s_y[l][0], s_y[l][1], s_y[l][2]});
+    return;
   }
   __syncthreads();
   for (int32_t c = 0; c < ncol; ++c) {
@@ -2005,7 +2086,7 @@ static void gs_sweeps(cc_solver* s, GsArgs a, hipStream_t st) {
       a.cnt = 0;
       if (s->nA > 0)
         k_gs_contact_small<kMixed><<<1, kGsTailThreads, 0, st>>>(a, s->coff_dev, &s->dc->ncol,
-                                                                  &s->dc->n_act);
+                                                                  &s->dc->n_act, &s->dc->nloc);
     } else {
       gs_colours<kMixed>(a, s->Aorder, nullptr, s->col_off, s->coff_dev, s->n_colors, false, st);
     }
@@ -2017,6 +2098,8 @@ static void gs_sweeps(cc_solver* s, GsArgs a, hipStream_t st) {
 
 int launch_gs(cc_solver* s, hipStream_t st) {
   GsArgs a;
+  a.lslot = s->Aslot;
+  a.lvert = s->lvert;
   a.eij = s->eij;
   a.Akeys = s->Akeys;
   a.Averts = s->Averts;
@@ -2155,6 +2238,8 @@ __global__ void __launch_bounds__(kThreads) k_jacobi_apply(double* __restrict__ 
 
 int launch_jacobi(cc_solver* s, hipStream_t st) {
   GsArgs a;
+  a.lslot = nullptr;
+  a.lvert = nullptr;
   a.rows = nullptr;
   a.err = nullptr;
   a.Akeys = s->Akeys;
