@@ -755,6 +755,8 @@ struct TravArgs {
   int64_t capC;
   long long* wtot;             // per wave: pairs found
   int32_t xcd_chunk;           // blocks per run of consecutive blocks dealt to one XCD
+  int32_t nchunks;             // runs of 64 queries (a wave's worth each)
+  unsigned long long* next;    // runs taken past the launch's own (zero at the launch)
   Counters* cnt;
 };
 
@@ -970,8 +972,11 @@ __global__ void __launch_bounds__(kTravThreads, 4) k_traverse(TravArgs A) {
   const int grp = lane / kGroup, gl = lane % kGroup;
   const uint64_t gmask = (kGroup == 64 ? ~0ull : ((1ull << kGroup) - 1ull)) << (grp * kGroup);
   const int32_t lb = xcd_block(blockIdx.x, gridDim.x, A.xcd_chunk);
-  const int32_t gw = lb * kWaves + wv;                // the wave's place in query order
-  const int32_t q0 = gw * 64;                         // the wave's first padded query
+  unsigned nvisit = 0;  // node records this lane's group read (counted by its first lane)
+  // runs of 64 queries: first the wave's own (its place in query order), then, when
+  // the launch holds fewer waves than runs, the next run not yet taken
+  for (int32_t gw = lb * kWaves + wv; gw < A.nchunks;) {
+  const int32_t q0 = gw * 64;                         // the run's first padded query
   int kind;
   int32_t idx, ncl;
   if (q0 < A.mv_pad) {
@@ -1030,7 +1035,6 @@ __global__ void __launch_bounds__(kTravThreads, 4) k_traverse(TravArgs A) {
   unsigned sidx = gw;  // the stripe of the wave's next flush
   long long wrun = 0;                         // pairs the wave has written out
   unsigned ntested = 0;  // candidates tested by the wave
-  unsigned nvisit = 0;   // node records this lane's group read (counted by its first lane)
   // a scene with one triangle: its vertices meet the leaf itself (one edge or one
   // particle pairs with nothing)
   {
@@ -1145,10 +1149,15 @@ __global__ void __launch_bounds__(kTravThreads, 4) k_traverse(TravArgs A) {
   if (qn > 0) drain(L, wv, gw, head, qn, kind, no, sidx, wrun, ntested, A);
   if (no > 0) flush_out(L, wv, gw, no, sidx, wrun, A);
   if (A.out && lane == 0) A.wtot[gw] = wrun;
+  unsigned long long nx = 0;
+  if (lane == 0) nx = atomicAdd(A.next, 1ull);
+  gw = __builtin_amdgcn_readfirstlane((int32_t)(gridDim.x * kWaves) + (int32_t)__shfl(nx, 0));
+  }
   // node records read by the wave's groups: the measure of the tree's quality
   unsigned long long nv = nvisit;
   for (int o = 32; o >= 1; o >>= 1) nv += __shfl_xor(nv, o);
-  if (lane == 0 && nv) atomicAdd(&A.stripe[(sidx & (kStripes - 1)) * kStripeWords + 1], nv);
+  if (lane == 0 && nv)
+    atomicAdd(&A.stripe[((blockIdx.x * kWaves + wv) & (kStripes - 1)) * kStripeWords + 1], nv);
 }
 
 // Exclusive prefix sum of the waves' pair counts, in place (one block).
@@ -1472,15 +1481,42 @@ static int grow_stripes(cc_solver* s, int64_t capS, int64_t capC) {
 // runs of a stripe of capS pairs: all but a wave's last hold at least kOut - 64
 static inline int64_t runs_for(int64_t capS) { return capS / 64 + 1024; }
 
+// Blocks of a traversal variant the device holds at once (0 if unknown).
+template <int G, int P>
+static unsigned resident_blocks() {
+  int dev = 0, ncu = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_traverse<G, P>, kTravThreads, 0) !=
+          hipSuccess)
+    return 0;
+  return (unsigned)(ncu > 0 && per > 0 ? ncu * per : 0);
+}
+
+// The traversal over A.nchunks runs of 64 queries with at most as many blocks as the
+// device holds at once: the runs past the launch's own go to the waves that finish
+// first (A.next counts them from zero), so none waits for a whole block to end.
+template <int G, int P>
+static void traverse_variant(const TravArgs& A, hipStream_t st) {
+  static unsigned res[64] = {};  // per device (0: not asked yet)
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  unsigned& r = res[dev & 63];
+  if (r == 0) r = resident_blocks<G, P>();
+  unsigned nb = (unsigned)(A.nchunks / kWaves);
+  if (r > 0 && nb > r) nb = r;
+  k_traverse<G, P><<<nb, kTravThreads, 0, st>>>(A);
+}
+
 int launch_traverse(int group, const TravArgs& A, int64_t nq, hipStream_t st) {
-  const unsigned nb = blocks(nq, kTravThreads);
+  if ((int64_t)A.nchunks * 64 < nq || A.nchunks % kWaves != 0) return CC_EINVAL;
   switch (group) {
-    case 8: k_traverse<8, 1><<<nb, kTravThreads, 0, st>>>(A); break;
-    case 32: k_traverse<32, 1><<<nb, kTravThreads, 0, st>>>(A); break;
-    case 108: k_traverse<8, 2><<<nb, kTravThreads, 0, st>>>(A); break;
-    case 116: k_traverse<16, 2><<<nb, kTravThreads, 0, st>>>(A); break;
-    case 132: k_traverse<32, 2><<<nb, kTravThreads, 0, st>>>(A); break;
-    default: k_traverse<16, 1><<<nb, kTravThreads, 0, st>>>(A); break;
+    case 8: traverse_variant<8, 1>(A, st); break;
+    case 32: traverse_variant<32, 1>(A, st); break;
+    case 108: traverse_variant<8, 2>(A, st); break;
+    case 116: traverse_variant<16, 2>(A, st); break;
+    case 132: traverse_variant<32, 2>(A, st); break;
+    default: traverse_variant<16, 1>(A, st); break;
   }
   CC_HIP(hipGetLastError());
   return CC_OK;
@@ -1624,10 +1660,12 @@ int lbvh_search(cc_solver* s, int32_t nsel, const double* x, double dmax, uint64
     A.capC = s->capC;
     A.cnt = s->dc;
     A.xcd_chunk = kXcdChunk;
+    A.next = s->stripe + 2;  // a free word of the first stripe's counters (cleared with them)
     A.mv_pad = (A.mv + 63) & ~63;
     A.me_pad = (me + 63) & ~63;
     int64_t nq = (int64_t)A.mv_pad + A.me_pad + mp;
     const int64_t nwaves = (int64_t)blocks(nq, kTravThreads) * kWaves;
+    A.nchunks = (int32_t)nwaves;
     if (out && nwaves > s->capW) {
       dfree(s->wtot);
       s->capW = 0;
