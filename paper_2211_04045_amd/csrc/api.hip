@@ -198,7 +198,7 @@ void free_vertex_arrays(cc_solver* s) {
   dfree(s->rold); dfree(s->dyold); dfree(s->back); dfree(s->alph); dfree(s->scale);
   dfree(s->r); dfree(s->move2); dfree(s->mvd); dfree(s->Di); dfree(s->vseg); dfree(s->plist); dfree(s->dy);
   dfree(s->jacc);
-  dfree(s->vmax0); dfree(s->claims); dfree(s->masks); dfree(s->vloc);
+  dfree(s->vmax0); dfree(s->claims); dfree(s->masks);
 }
 void free_edge_arrays(cc_solver* s) {
   dfree(s->edges); dfree(s->eseg); dfree(s->eg); dfree(s->einv); dfree(s->ecol); dfree(s->eorder);
@@ -282,9 +282,6 @@ int resize_arrays(cc_solver* s, int32_t capV, int32_t capF, int32_t capE, hipStr
     CC_HIP(hipMemsetAsync(s->claims, 0, sizeof(unsigned long long) * (size_t)capV * 2 * kMaskWords, st));
     s->pc_dirty = false;
     CC_TRY(dalloc(&s->masks, (int64_t)capV * kMaskWords));
-    dfree(s->vloc);
-    CC_TRY(dalloc(&s->vloc, capV));
-    CC_TRY(launch_fill_i32(s->vloc, capV, kNoLoc, st));
   }
   if (capF != oF) CC_TRY(dregrow(&s->tris, 3 * (int64_t)capF, 3 * oF, st));
   if (capE != oE) {

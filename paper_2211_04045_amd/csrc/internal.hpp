@@ -44,7 +44,6 @@ constexpr int kRowWords = 20;      // one linearised contact row: ids, c0, 1/A, 
 constexpr int kSmallRows = 4096;   // contact sets up to this size are coloured by one block
 // vertices a one-block colouring holds in LDS with one colour word each
 constexpr int kLocCap1 = 4096;
-constexpr int32_t kNoLoc = 0x7fffffff;  // vloc entry of a vertex no colouring block holds
 
 // Per-segment record on the device (one scene of a multi-scene solver). The host
 // writes D, D2, bases and flags before an iteration and reads the reductions back.
@@ -239,7 +238,6 @@ struct cc_solver {
   std::vector<int32_t> col_off;  // host copy of colour bucket offsets (n_colors+1)
   bool col_small = false;  // this step's contact colours and buckets live on the device only
   bool pc_wide = false;    // the last one-block colouring used more than 56 colours
-  int32_t* vloc = nullptr;  // per vertex: kNoLoc, or a block-local slot while one block colours
   // edge-length rows (one per edge; inv_a = 0 marks an unused edge)
   double* eg = nullptr;     // 3 per edge
   double* einv = nullptr;

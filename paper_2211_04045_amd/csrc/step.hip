@@ -919,19 +919,25 @@ static_assert(kSmallRows % kTailThreads == 0, "whole rows per thread");
 static_assert(kMaxColors == kTailThreads, "one thread per colour bucket in the scan");
 
 // The same rounds (from round 1) over every contact row [0, nrows) in one block,
-// with the per-vertex state in LDS. The rows' free vertices get block-local slots:
-// each (row, corner) names its vertex in vloc with an atomic minimum of its index,
-// the corner that holds the minimum takes the next slot and writes it back (as
-// -(slot + 1)), every corner reads it, and vloc returns to kNoLoc before the
-// rounds. A thread keeps its rows (row t + k * kTailThreads) in registers. When
-// more than kLocCap vertices take part, or a pick would need a colour beyond the
-// kLocWords words in LDS, the block runs the global-memory rounds from round 1
-// instead, with the same result (the colours depend only on the row set). Then
-// the colour buckets: counts, their exclusive scan to off (kMaxColors + 1
-// entries), the rows in colour order to order; the colour count goes to c->ncol.
+// with the per-vertex state in LDS. The rows' free vertices get block-local slots
+// through an open-addressing table in LDS (kHashSize entries, linear probing; it
+// borrows the claim and clash words, which the rounds clear before use): each
+// (row, corner) enters its vertex with a compare-and-swap, each entry it creates
+// takes the next slot, and every corner reads its entry's slot. A thread keeps its
+// rows (row t + k * kTailThreads) in registers. When more than kLocCap vertices
+// take part (or a vertex finds no place within kHashProbes), or a pick would need
+// a colour beyond the kLocWords words in LDS, the block runs the global-memory
+// rounds from round 1 instead, with the same result (the colours depend only on
+// the row set). Then the colour buckets: counts, their exclusive scan to off
+// (kMaxColors + 1 entries), the rows in colour order to order; the colour count
+// goes to c->ncol.
+constexpr int kHashBits = 13, kHashSize = 1 << kHashBits;
+// probes before a vertex gives up its place (at most kLocCap1 = kHashSize / 2 vertices
+// fit the LDS state, so a table that holds them is at most half full)
+constexpr int kHashProbes = 64;
 template <int kLocWords, int kLocCap>
 __global__ void __launch_bounds__(kTailThreads) k_pc_small(PcArgs a, int32_t nrows, int32_t* la,
-                                                           int32_t* lb, int32_t* __restrict__ vloc,
+                                                           int32_t* lb,
                                                            int32_t* __restrict__ order,
                                                            int32_t* __restrict__ off,
                                                            uint64_t tmax) {
@@ -942,6 +948,11 @@ __global__ void __launch_bounds__(kTailThreads) k_pc_small(PcArgs a, int32_t nro
   __shared__ int32_t s_cnt[kMaxColors];
   __shared__ int32_t s_wsum[kTailThreads / 64];
   __shared__ int32_t s_nloc, s_live, s_next, s_ncol, s_over, ncur, nnext;
+  static_assert(sizeof(s_claim) >= sizeof(int32_t) * kHashSize &&
+                    sizeof(s_clash) >= sizeof(int32_t) * kHashSize,
+                "the vertex table fits the claim and clash words");
+  int32_t* const hkey = reinterpret_cast<int32_t*>(&s_claim[0][0]);   // vertex id, -1: empty
+  int32_t* const hslot = reinterpret_cast<int32_t*>(&s_clash[0][0]);  // its slot
   const int tid = threadIdx.x;
   if (tid == 0) {
     s_nloc = 0;
@@ -951,6 +962,7 @@ __global__ void __launch_bounds__(kTailThreads) k_pc_small(PcArgs a, int32_t nro
     s_over = 0;
   }
   s_cnt[tid] = 0;
+  for (int h = tid; h < kHashSize; h += kTailThreads) hkey[h] = -1;
   uint64_t hk[kSmallPer];
   int32_t vid[kSmallPer][4], lid[kSmallPer][4];
   int32_t fails[kSmallPer], pick[kSmallPer], col[kSmallPer];
@@ -969,46 +981,55 @@ __global__ void __launch_bounds__(kTailThreads) k_pc_small(PcArgs a, int32_t nro
       a.src.get(r, key, v);
       hk[k] = mix64(key ^ a.seed);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (!is_free(a.w, v[q])) continue;
-        vid[k][q] = v[q];
-        atomicMin(&vloc[v[q]], r * 4 + q);
-      }
+      for (int q = 0; q < 4; ++q)
+        if (is_free(a.w, v[q])) vid[k][q] = v[q];
     }
   }
   __syncthreads();
+  // every free corner enters its vertex; lid holds the table position for now
+  unsigned made = 0;  // bit 4k + q: this corner created its vertex's entry
 #pragma unroll
-  for (int k = 0; k < kSmallPer; ++k) {
-    const int32_t r = tid + k * kTailThreads;
+  for (int k = 0; k < kSmallPer; ++k)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      if (vid[k][q] < 0) continue;
-      int32_t* slot = &vloc[vid[k][q]];
-      if (__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != r * 4 + q) continue;
-      const int32_t l = atomicAdd(&s_nloc, 1);
-      if (l < kLocCap) {
-        if (a.lvert) a.lvert[l] = vid[k][q];
-        s_unc[l] = 0u;
-#pragma unroll
-        for (int wd = 0; wd < kLocWords; ++wd) s_mask[l][wd] = s_claim[l][wd] = s_clash[l][wd] = 0ull;
+      const int32_t v = vid[k][q];
+      if (v < 0) continue;
+      uint32_t h = ((uint32_t)v * 2654435761u) >> (32 - kHashBits);
+      int n = 0;
+      for (; n < kHashProbes; ++n, h = (h + 1) & (kHashSize - 1)) {
+        const int32_t old = atomicCAS(&hkey[h], -1, v);
+        if (old == -1) made |= 1u << (4 * k + q);
+        if (old == -1 || old == v) break;
       }
-      __hip_atomic_store(slot, -(l + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (n == kHashProbes) s_over = 1;  // a crowded table: the global rounds colour
+      lid[k][q] = (int32_t)h;
     }
-  }
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kSmallPer; ++k)
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (vid[k][q] >= 0)
-        lid[k][q] = -__hip_atomic_load(&vloc[vid[k][q]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - 1;
+    for (int q = 0; q < 4; ++q) {
+      if (!(made & (1u << (4 * k + q)))) continue;
+      const int32_t l = atomicAdd(&s_nloc, 1);
+      hslot[lid[k][q]] = l;
+      if (l < kLocCap && a.lvert) a.lvert[l] = vid[k][q];
+    }
   __syncthreads();
+  const bool in_lds = s_nloc <= kLocCap && !s_over;
 #pragma unroll
   for (int k = 0; k < kSmallPer; ++k)
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-      if (vid[k][q] >= 0) __hip_atomic_store(&vloc[vid[k][q]], kNoLoc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const bool in_lds = s_nloc <= kLocCap;
+      if (vid[k][q] >= 0) lid[k][q] = in_lds ? hslot[lid[k][q]] : -1;
+  __syncthreads();
+  // the slots' state starts clear (the table is done with)
+  if (in_lds)
+    for (int l = tid; l < s_nloc; l += kTailThreads) {
+      s_unc[l] = 0u;
+#pragma unroll
+      for (int wd = 0; wd < kLocWords; ++wd) s_mask[l][wd] = s_claim[l][wd] = s_clash[l][wd] = 0ull;
+    }
+  __syncthreads();
   const int W = (a.maxc + 63) / 64;
   if (in_lds) {
     for (uint64_t t = 1; s_live > 0; ++t) {
@@ -1292,11 +1313,11 @@ int color_small(cc_solver* s, hipStream_t st) {
   // colours; either way a set that does not fit is still coloured, by the global rounds
   if (s->pc_wide)
     k_pc_small<2, kLocCap2><<<1, kTailThreads, 0, st>>>(pc_args(s, false), (int32_t)s->nA,
-                                                        s->list0, s->list1, s->vloc, s->Aorder,
+                                                        s->list0, s->list1, s->Aorder,
                                                         s->coff_dev, (uint64_t)kMaxRounds);
   else
     k_pc_small<1, kLocCap1><<<1, kTailThreads, 0, st>>>(pc_args(s, false), (int32_t)s->nA,
-                                                        s->list0, s->list1, s->vloc, s->Aorder,
+                                                        s->list0, s->list1, s->Aorder,
                                                         s->coff_dev, (uint64_t)kMaxRounds);
   CC_HIP(hipGetLastError());
   return CC_OK;
