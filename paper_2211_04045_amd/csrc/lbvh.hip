@@ -1094,19 +1094,26 @@ __global__ void __launch_bounds__(kTravThreads, 4) k_traverse(TravArgs A) {
         if (gl == 0) ++nvisit;
       }
     }
-    // each lane of the group stages float4s of the records (8 per node) in LDS
+    // each lane of the group stages float4s of the records (8 per node) in LDS; all
+    // of a lane's loads are issued before the first is stored, so they overlap
+    constexpr int kPer = (8 * kPop + kGroup - 1) / kGroup;  // float4s per lane
+    float4 rv[kPer];
 #pragma unroll
-    for (int f0 = 0; f0 < 8 * kPop; f0 += kGroup) {
-      const int f = f0 + gl;
+    for (int i = 0; i < kPer; ++i) {
+      const int f = i * kGroup + gl;
+      rv[i] = make_float4(0.f, 0.f, 0.f, 0.f);
       if (f < 8 * kPop) {
-        float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
         int32_t nk = ni[0];
 #pragma unroll
         for (int k = 1; k < kPop; ++k)
           if ((f >> 3) == k) nk = ni[k];
-        if ((vmask >> (f >> 3)) & 1u) r = T.wide[8 * (int64_t)nk + (f & 7)];
-        L.nrec[wv][grp][f] = r;
+        if ((vmask >> (f >> 3)) & 1u) rv[i] = T.wide[8 * (int64_t)nk + (f & 7)];
       }
+    }
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int f = i * kGroup + gl;
+      if (f < 8 * kPop) L.nrec[wv][grp][f] = rv[i];
     }
     __builtin_amdgcn_wave_barrier();
 #pragma unroll 1
