@@ -768,16 +768,17 @@ __device__ __forceinline__ bool overlap6(float4 ql, float4 qh, float lx, float l
 // Boxes that overlap6 accepts but whose un-inflated boxes lie farther apart than
 // dmax in the Euclidean norm hold no pair within dmax (a primitive lies in its box,
 // and the FP32 boxes contain the FP64 ones). Both boxes carry half of dmax, so the
-// separation on an axis is max(0, gap + dmax); r2 is (dmax + m)^2 with m =
-// 1e-6 (1 + |query|_inf) m, far above the FP32 rounding of these few operations
-// (about 2.4e-7 |query|_inf + 1.5e-7 dmax), so a box is dropped only when the exact
-// FP64 test would reject every primitive in it.
-__device__ __forceinline__ bool far6(float4 ql, float4 qh, float lx, float ly, float lz, float hx,
-                                     float hy, float hz, float fdmax, float r2) {
-  const float sx = fmaxf(0.f, fmaxf(ql.x - hx, lx - qh.x) + fdmax);
-  const float sy = fmaxf(0.f, fmaxf(ql.y - hy, ly - qh.y) + fdmax);
-  const float sz = fmaxf(0.f, fmaxf(ql.z - hz, lz - qh.z) + fdmax);
-  return sx * sx + sy * sy + sz * sz > r2;
+// separation on an axis is max(0, gap + dmax), taken here as max(0, (ql + dmax) - h,
+// l - (qh - dmax)) with the query's bounds moved by dmax once per query (qlp, qhm);
+// r2 is (dmax + m)^2 with m = 1e-6 (1 + |query|_inf) m, far above the FP32 rounding of
+// these few operations (below 3e-7 |query|_inf + 2e-7 dmax), so a box is dropped only
+// when the exact FP64 test would reject every primitive in it.
+__device__ __forceinline__ bool far6(float4 qlp, float4 qhm, float lx, float ly, float lz,
+                                     float hx, float hy, float hz, float r2) {
+  const float sx = fmaxf(0.f, fmaxf(qlp.x - hx, lx - qhm.x));
+  const float sy = fmaxf(0.f, fmaxf(qlp.y - hy, ly - qhm.y));
+  const float sz = fmaxf(0.f, fmaxf(qlp.z - hz, lz - qhm.z));
+  return __builtin_fmaf(sz, sz, __builtin_fmaf(sy, sy, sx * sx)) > r2;
 }
 
 __device__ __forceinline__ uint64_t lanes_below_tr() {
@@ -865,6 +866,20 @@ __device__ __forceinline__ int32_t xcd_block(int32_t b, int32_t nb, int32_t c) {
   if (c <= 1 || b >= full) return b;
   const int32_t x = b & 7, j = b >> 3;
   return ((j / c) * 8 + x) * c + j % c;
+}
+
+// A lane mask with every lane of a group of G consecutive lanes set when any lane of
+// the group is set in m (scalar arithmetic on a wave-uniform mask).
+template <int G>
+__device__ __forceinline__ uint64_t group_any(uint64_t m) {
+  if (G == 64) return m ? ~0ull : 0ull;
+  uint64_t low = 1ull;  // the first lane of every group
+  for (int s = G; s < 64; s <<= 1) low |= low << s;
+  uint64_t t = m;
+  for (int s = 1; s < G; s <<= 1) t |= t >> s;
+  t &= low;
+  for (int s = 1; s < G; s <<= 1) t |= t << s;
+  return t;
 }
 
 template <int G, int P>
@@ -1061,6 +1076,8 @@ __global__ void __launch_bounds__(kTravThreads, 4) k_traverse(TravArgs A) {
     const float r = A.fdmax + 1e-6f * (1.f + qm);
     qr2 = r * r;
   }
+  const float4 qlp = make_float4(qlo.x + A.fdmax, qlo.y + A.fdmax, qlo.z + A.fdmax, 0.f);
+  const float4 qhm = make_float4(qhi.x - A.fdmax, qhi.y - A.fdmax, qhi.z - A.fdmax, 0.f);
   bool todo = active && root >= 0;  // this lane's subtree still to walk
   bool part = false;                // this lane takes part in its group's current walk
   int sp = 0;                       // the group's stack depth (uniform in the group)
@@ -1116,18 +1133,34 @@ __global__ void __launch_bounds__(kTravThreads, 4) k_traverse(TravArgs A) {
       if (f < 8 * kPop) L.nrec[wv][grp][f] = rv[i];
     }
     __builtin_amdgcn_wave_barrier();
+    // per node taken: the lanes that test its children (taken by their group, and
+    // taking part in the group's walk), as a lane mask
+    const uint64_t pm = __ballot(part);
+    uint64_t live[kPop];
+#pragma unroll
+    for (int k = 0; k < kPop; ++k) live[k] = __ballot(((vmask >> k) & 1u) != 0) & pm;
 #pragma unroll 1
     for (int slot = 0; slot < 4 * kPop; ++slot) {
+      uint64_t lv = live[0];
+#pragma unroll
+      for (int k = 1; k < kPop; ++k)
+        if ((slot >> 2) == k) lv = live[k];
       const float4 b0 = L.nrec[wv][grp][2 * slot];
       const float4 b1 = L.nrec[wv][grp][2 * slot + 1];
-      const bool ov = ((vmask >> (slot >> 2)) & 1u) && part &&
-                      overlap6(qlo, qhi, b0.x, b0.y, b0.z, b0.w, b1.x, b1.y) &&
-                      __float_as_int(b1.w) > qpos &&
-                      !far6(qlo, qhi, b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, A.fdmax, qr2);
-      const uint64_t m = __ballot(ov);
       const int32_t c = __float_as_int(b1.z);
+      bool ov = false;
+      if (__builtin_amdgcn_inverse_ballot_w64(lv))
+        ov = overlap6(qlo, qhi, b0.x, b0.y, b0.z, b0.w, b1.x, b1.y) &&
+             __float_as_int(b1.w) > qpos &&
+             !far6(qlp, qhm, b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, qr2);
+      // lane masks, kept in scalar registers: the lanes that overlap the child, the
+      // groups whose child is internal, the groups that enter it, the leaf candidates
+      const uint64_t m = __ballot(ov);
+      const uint64_t inner = __ballot(c >= 0);
+      const uint64_t enter = group_any<kGroup>(m) & inner;
+      const uint64_t ml = m & ~inner;
       // internal child: the group enters it
-      if ((m & gmask) && c >= 0) {
+      if (__builtin_amdgcn_inverse_ballot_w64(enter)) {
         if (sp < kGStack) {
           if (gl == 0) L.stack[wv][grp][sp] = c;
           ++sp;
@@ -1136,10 +1169,10 @@ __global__ void __launch_bounds__(kTravThreads, 4) k_traverse(TravArgs A) {
         }
       }
       // leaf child: one candidate per overlapping lane
-      const bool leaf = ov && c < 0;
-      const uint64_t ml = __ballot(leaf);
-      if (leaf) {
-        const int e = (head + qn + __popcll(ml & lanes_below_tr())) & (kQueue - 1);
+      if (__builtin_amdgcn_inverse_ballot_w64(ml)) {
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(ml >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)ml, 0u));
+        const int e = (head + qn + (int)below) & (kQueue - 1);
         L.qlane[wv][e] = lane;
         L.qprim[wv][e] = c & 0x7fffffff;
       }
