@@ -977,8 +977,9 @@ __device__ __forceinline__ void drain(LT& L, int wv, int32_t gw, int head, int n
 // Lanes of different scenes in one group walk their own subtrees in turn.
 // The records of the nodes a group takes in one step are staged in LDS (one float4
 // per lane) and their children tested in a loop that is not unrolled, so that the
-// exact tests are compiled once: the kernel's code stays within the instruction
-// cache. (occupancy target: 4 waves per SIMD)
+// exact tests are compiled once (a third of the code, fewer registers). The child
+// test is issue-bound, so its lane predicates are kept as scalar lane masks.
+// (occupancy target: 4 waves per SIMD)
 template <int kGroup, int kPop>
 __global__ void __launch_bounds__(kTravThreads, 4) k_traverse(TravArgs A) {
   __shared__ WaveLds<kGroup, kPop> L;
@@ -991,207 +992,212 @@ __global__ void __launch_bounds__(kTravThreads, 4) k_traverse(TravArgs A) {
   // runs of 64 queries: first the wave's own (its place in query order), then, when
   // the launch holds fewer waves than runs, the next run not yet taken
   for (int32_t gw = lb * kWaves + wv; gw < A.nchunks;) {
-  const int32_t q0 = gw * 64;                         // the run's first padded query
-  int kind;
-  int32_t idx, ncl;
-  if (q0 < A.mv_pad) {
-    kind = kQVT;
-    idx = q0 + lane;
-    ncl = A.mv;
-  } else if (q0 < A.mv_pad + A.me_pad) {
-    kind = kQEE;
-    idx = q0 - A.mv_pad + lane;
-    ncl = A.me;
-  } else {
-    kind = kQVV;
-    idx = q0 - A.mv_pad - A.me_pad + lane;
-    ncl = A.mp;
-  }
-  const bool active = idx < ncl;
-  const TravTree T = kind == kQVT ? A.tt : (kind == kQEE ? A.te : A.tp);
-  float4 qlo = make_float4(0.f, 0.f, 0.f, 0.f), qhi = qlo;
-  int32_t qv0 = 0, qv1 = 0, qid = 0, qpos = -1, root = -1;
-  V3 qx0{0, 0, 0}, qx1{0, 0, 0};
-  if (active) {
-    if (kind == kQVT) {
-      qid = A.vorder[idx];
-      root = A.root_t[A.vrank[idx]];
-      qv0 = qid;
-      qx0 = ld3(A.x, qid);
-      qlo = make_float4(lo_out(qx0.x - A.infl), lo_out(qx0.y - A.infl), lo_out(qx0.z - A.infl), 0.f);
-      qhi = make_float4(hi_out(qx0.x + A.infl), hi_out(qx0.y + A.infl), hi_out(qx0.z + A.infl), 0.f);
-    } else if (kind == kQVV) {
-      qpos = idx;  // sorted position of the query particle in its tree
-      qid = T.leaf_prim[qpos];
-      root = A.root_p[A.prank[qpos]];
-      qv0 = qid;
-      qx0 = ld3(A.x, qid);
-      qlo = make_float4(lo_out(qx0.x - A.infl), lo_out(qx0.y - A.infl), lo_out(qx0.z - A.infl), 0.f);
-      qhi = make_float4(hi_out(qx0.x + A.infl), hi_out(qx0.y + A.infl), hi_out(qx0.z + A.infl), 0.f);
+    const int32_t q0 = gw * 64;                         // the run's first padded query
+    int kind;
+    int32_t idx, ncl;
+    if (q0 < A.mv_pad) {
+      kind = kQVT;
+      idx = q0 + lane;
+      ncl = A.mv;
+    } else if (q0 < A.mv_pad + A.me_pad) {
+      kind = kQEE;
+      idx = q0 - A.mv_pad + lane;
+      ncl = A.me;
     } else {
-      qpos = idx;  // sorted position of the query edge in the edge tree
-      qid = T.leaf_prim[qpos];
-      root = A.root_e[A.erank[qpos]];
-      qv0 = A.edges[2 * qid];
-      qv1 = A.edges[2 * qid + 1];
-      qx0 = ld3(A.x, qv0);
-      qx1 = ld3(A.x, qv1);
-      qlo = make_float4(lo_out(fmin(qx0.x, qx1.x) - A.infl), lo_out(fmin(qx0.y, qx1.y) - A.infl),
-                        lo_out(fmin(qx0.z, qx1.z) - A.infl), 0.f);
-      qhi = make_float4(hi_out(fmax(qx0.x, qx1.x) + A.infl), hi_out(fmax(qx0.y, qx1.y) + A.infl),
-                        hi_out(fmax(qx0.z, qx1.z) + A.infl), 0.f);
+      kind = kQVV;
+      idx = q0 - A.mv_pad - A.me_pad + lane;
+      ncl = A.mp;
     }
-  }
-  L.qi[wv][0][lane] = qid;
-  L.qi[wv][1][lane] = qv0;
-  L.qi[wv][2][lane] = qv1;
-  int head = 0, qn = 0;  // candidate ring: first entry, entries queued (wave-uniform)
-  int no = 0;            // found pairs held (wave-uniform)
-  unsigned sidx = gw;  // the stripe of the wave's next flush
-  long long wrun = 0;                         // pairs the wave has written out
-  unsigned ntested = 0;  // candidates tested by the wave
-  // a scene with one triangle: its vertices meet the leaf itself (one edge or one
-  // particle pairs with nothing)
-  {
-    const bool single = active && kind == kQVT && root < -1;
-    const uint64_t m = __ballot(single);
-    if (single) {
-      const int e = __popcll(m & lanes_below_tr());
-      L.qlane[wv][e] = lane;
-      L.qprim[wv][e] = root & 0x7fffffff;
-    }
-    qn = __popcll(m);
-  }
-  __builtin_amdgcn_wave_barrier();
-  if (qn == 64) {
-    drain(L, wv, gw, head, 64, kind, no, sidx, wrun, ntested, A);
-    qn = 0;
-    __builtin_amdgcn_wave_barrier();
-  }
-  // (dmax + m)^2 of the Euclidean box test, m = 1e-6 (1 + |query|_inf)
-  float qr2;
-  {
-    const float qm = fmaxf(fmaxf(fmaxf(fabsf(qlo.x), fabsf(qhi.x)), fmaxf(fabsf(qlo.y), fabsf(qhi.y))),
-                           fmaxf(fabsf(qlo.z), fabsf(qhi.z)));
-    const float r = A.fdmax + 1e-6f * (1.f + qm);
-    qr2 = r * r;
-  }
-  const float4 qlp = make_float4(qlo.x + A.fdmax, qlo.y + A.fdmax, qlo.z + A.fdmax, 0.f);
-  const float4 qhm = make_float4(qhi.x - A.fdmax, qhi.y - A.fdmax, qhi.z - A.fdmax, 0.f);
-  bool todo = active && root >= 0;  // this lane's subtree still to walk
-  bool part = false;                // this lane takes part in its group's current walk
-  int sp = 0;                       // the group's stack depth (uniform in the group)
-  for (;;) {
-    // a group with an empty stack starts the next scene's subtree among its lanes
-    const uint64_t tm = __ballot(todo) & gmask;
-    if (sp == 0) {
-      part = false;
-      if (tm) {
-        const int32_t r = __shfl(root, __ffsll((long long)tm) - 1);
-        part = todo && root == r;
-        todo = todo && !part;
-        if (gl == 0) L.stack[wv][grp][0] = r;
-        sp = 1;
+    const bool active = idx < ncl;
+    const TravTree T = kind == kQVT ? A.tt : (kind == kQEE ? A.te : A.tp);
+    float4 qlo = make_float4(0.f, 0.f, 0.f, 0.f), qhi = qlo;
+    int32_t qv0 = 0, qv1 = 0, qid = 0, qpos = -1, root = -1;
+    V3 qx0{0, 0, 0}, qx1{0, 0, 0};
+    if (active) {
+      if (kind == kQVT) {
+        qid = A.vorder[idx];
+        root = A.root_t[A.vrank[idx]];
+        qv0 = qid;
+        qx0 = ld3(A.x, qid);
+        qlo = make_float4(lo_out(qx0.x - A.infl), lo_out(qx0.y - A.infl),
+                          lo_out(qx0.z - A.infl), 0.f);
+        qhi = make_float4(hi_out(qx0.x + A.infl), hi_out(qx0.y + A.infl),
+                          hi_out(qx0.z + A.infl), 0.f);
+      } else if (kind == kQVV) {
+        qpos = idx;  // sorted position of the query particle in its tree
+        qid = T.leaf_prim[qpos];
+        root = A.root_p[A.prank[qpos]];
+        qv0 = qid;
+        qx0 = ld3(A.x, qid);
+        qlo = make_float4(lo_out(qx0.x - A.infl), lo_out(qx0.y - A.infl),
+                          lo_out(qx0.z - A.infl), 0.f);
+        qhi = make_float4(hi_out(qx0.x + A.infl), hi_out(qx0.y + A.infl),
+                          hi_out(qx0.z + A.infl), 0.f);
+      } else {
+        qpos = idx;  // sorted position of the query edge in the edge tree
+        qid = T.leaf_prim[qpos];
+        root = A.root_e[A.erank[qpos]];
+        qv0 = A.edges[2 * qid];
+        qv1 = A.edges[2 * qid + 1];
+        qx0 = ld3(A.x, qv0);
+        qx1 = ld3(A.x, qv1);
+        qlo = make_float4(lo_out(fmin(qx0.x, qx1.x) - A.infl), lo_out(fmin(qx0.y, qx1.y) - A.infl),
+                          lo_out(fmin(qx0.z, qx1.z) - A.infl), 0.f);
+        qhi = make_float4(hi_out(fmax(qx0.x, qx1.x) + A.infl), hi_out(fmax(qx0.y, qx1.y) + A.infl),
+                          hi_out(fmax(qx0.z, qx1.z) + A.infl), 0.f);
       }
     }
-    if (!__any(sp > 0)) break;
-    __builtin_amdgcn_wave_barrier();
-    // kPop nodes leave the group's stack per step, their records loaded together so
-    // that their latencies overlap (kPop = 2 halves the chain of dependent loads of a
-    // deep walk; the set of nodes visited is the same)
-    unsigned vmask = 0;  // the nodes taken (uniform in the group)
-    int32_t ni[kPop];
-#pragma unroll
-    for (int k = 0; k < kPop; ++k) {
-      ni[k] = 0;
-      if (sp > 0) {
-        --sp;
-        ni[k] = L.stack[wv][grp][sp];
-        vmask |= 1u << k;
-        if (gl == 0) ++nvisit;
+    L.qi[wv][0][lane] = qid;
+    L.qi[wv][1][lane] = qv0;
+    L.qi[wv][2][lane] = qv1;
+    int head = 0, qn = 0;  // candidate ring: first entry, entries queued (wave-uniform)
+    int no = 0;            // found pairs held (wave-uniform)
+    unsigned sidx = gw;  // the stripe of the wave's next flush
+    long long wrun = 0;                         // pairs the wave has written out
+    unsigned ntested = 0;  // candidates tested by the wave
+    // a scene with one triangle: its vertices meet the leaf itself (one edge or one
+    // particle pairs with nothing)
+    {
+      const bool single = active && kind == kQVT && root < -1;
+      const uint64_t m = __ballot(single);
+      if (single) {
+        const int e = __popcll(m & lanes_below_tr());
+        L.qlane[wv][e] = lane;
+        L.qprim[wv][e] = root & 0x7fffffff;
       }
-    }
-    // each lane of the group stages float4s of the records (8 per node) in LDS; all
-    // of a lane's loads are issued before the first is stored, so they overlap
-    constexpr int kPer = (8 * kPop + kGroup - 1) / kGroup;  // float4s per lane
-    float4 rv[kPer];
-#pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-      const int f = i * kGroup + gl;
-      rv[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (f < 8 * kPop) {
-        int32_t nk = ni[0];
-#pragma unroll
-        for (int k = 1; k < kPop; ++k)
-          if ((f >> 3) == k) nk = ni[k];
-        if ((vmask >> (f >> 3)) & 1u) rv[i] = T.wide[8 * (int64_t)nk + (f & 7)];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-      const int f = i * kGroup + gl;
-      if (f < 8 * kPop) L.nrec[wv][grp][f] = rv[i];
+      qn = __popcll(m);
     }
     __builtin_amdgcn_wave_barrier();
-    // per node taken: the lanes that test its children (taken by their group, and
-    // taking part in the group's walk), as a lane mask
-    const uint64_t pm = __ballot(part);
-    uint64_t live[kPop];
-#pragma unroll
-    for (int k = 0; k < kPop; ++k) live[k] = __ballot(((vmask >> k) & 1u) != 0) & pm;
-#pragma unroll 1
-    for (int slot = 0; slot < 4 * kPop; ++slot) {
-      uint64_t lv = live[0];
-#pragma unroll
-      for (int k = 1; k < kPop; ++k)
-        if ((slot >> 2) == k) lv = live[k];
-      const float4 b0 = L.nrec[wv][grp][2 * slot];
-      const float4 b1 = L.nrec[wv][grp][2 * slot + 1];
-      const int32_t c = __float_as_int(b1.z);
-      bool ov = false;
-      if (__builtin_amdgcn_inverse_ballot_w64(lv))
-        ov = overlap6(qlo, qhi, b0.x, b0.y, b0.z, b0.w, b1.x, b1.y) &&
-             __float_as_int(b1.w) > qpos &&
-             !far6(qlp, qhm, b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, qr2);
-      // lane masks, kept in scalar registers: the lanes that overlap the child, the
-      // groups whose child is internal, the groups that enter it, the leaf candidates
-      const uint64_t m = __ballot(ov);
-      const uint64_t inner = __ballot(c >= 0);
-      const uint64_t enter = group_any<kGroup>(m) & inner;
-      const uint64_t ml = m & ~inner;
-      // internal child: the group enters it
-      if (__builtin_amdgcn_inverse_ballot_w64(enter)) {
-        if (sp < kGStack) {
-          if (gl == 0) L.stack[wv][grp][sp] = c;
-          ++sp;
-        } else if (gl == 0) {
-          atomicOr(&A.cnt->err, 2ull);
+    if (qn == 64) {
+      drain(L, wv, gw, head, 64, kind, no, sidx, wrun, ntested, A);
+      qn = 0;
+      __builtin_amdgcn_wave_barrier();
+    }
+    // (dmax + m)^2 of the Euclidean box test, m = 1e-6 (1 + |query|_inf)
+    float qr2;
+    {
+      const float qm = fmaxf(fmaxf(fmaxf(fabsf(qlo.x), fabsf(qhi.x)),
+                                   fmaxf(fabsf(qlo.y), fabsf(qhi.y))),
+                             fmaxf(fabsf(qlo.z), fabsf(qhi.z)));
+      const float r = A.fdmax + 1e-6f * (1.f + qm);
+      qr2 = r * r;
+    }
+    const float4 qlp = make_float4(qlo.x + A.fdmax, qlo.y + A.fdmax, qlo.z + A.fdmax, 0.f);
+    const float4 qhm = make_float4(qhi.x - A.fdmax, qhi.y - A.fdmax, qhi.z - A.fdmax, 0.f);
+    bool todo = active && root >= 0;  // this lane's subtree still to walk
+    bool part = false;                // this lane takes part in its group's current walk
+    int sp = 0;                       // the group's stack depth (uniform in the group)
+    for (;;) {
+      // a group with an empty stack starts the next scene's subtree among its lanes
+      const uint64_t tm = __ballot(todo) & gmask;
+      if (sp == 0) {
+        part = false;
+        if (tm) {
+          const int32_t r = __shfl(root, __ffsll((long long)tm) - 1);
+          part = todo && root == r;
+          todo = todo && !part;
+          if (gl == 0) L.stack[wv][grp][0] = r;
+          sp = 1;
         }
       }
-      // leaf child: one candidate per overlapping lane
-      if (__builtin_amdgcn_inverse_ballot_w64(ml)) {
-        const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(ml >> 32),
-                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)ml, 0u));
-        const int e = (head + qn + (int)below) & (kQueue - 1);
-        L.qlane[wv][e] = lane;
-        L.qprim[wv][e] = c & 0x7fffffff;
-      }
-      qn += __popcll(ml);
+      if (!__any(sp > 0)) break;
       __builtin_amdgcn_wave_barrier();
-      while (qn >= 64) {
-        drain(L, wv, gw, head, 64, kind, no, sidx, wrun, ntested, A);
-        head = (head + 64) & (kQueue - 1);
-        qn -= 64;
+      // kPop nodes leave the group's stack per step, their records loaded together so
+      // that their latencies overlap (kPop = 2 halves the chain of dependent loads of a
+      // deep walk; the set of nodes visited is the same)
+      unsigned vmask = 0;  // the nodes taken (uniform in the group)
+      int32_t ni[kPop];
+  #pragma unroll
+      for (int k = 0; k < kPop; ++k) {
+        ni[k] = 0;
+        if (sp > 0) {
+          --sp;
+          ni[k] = L.stack[wv][grp][sp];
+          vmask |= 1u << k;
+          if (gl == 0) ++nvisit;
+        }
+      }
+      // each lane of the group stages float4s of the records (8 per node) in LDS; all
+      // of a lane's loads are issued before the first is stored, so they overlap
+      constexpr int kPer = (8 * kPop + kGroup - 1) / kGroup;  // float4s per lane
+      float4 rv[kPer];
+  #pragma unroll
+      for (int i = 0; i < kPer; ++i) {
+        const int f = i * kGroup + gl;
+        rv[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (f < 8 * kPop) {
+          int32_t nk = ni[0];
+  #pragma unroll
+          for (int k = 1; k < kPop; ++k)
+            if ((f >> 3) == k) nk = ni[k];
+          if ((vmask >> (f >> 3)) & 1u) rv[i] = T.wide[8 * (int64_t)nk + (f & 7)];
+        }
+      }
+  #pragma unroll
+      for (int i = 0; i < kPer; ++i) {
+        const int f = i * kGroup + gl;
+        if (f < 8 * kPop) L.nrec[wv][grp][f] = rv[i];
+      }
+      __builtin_amdgcn_wave_barrier();
+      // per node taken: the lanes that test its children (taken by their group, and
+      // taking part in the group's walk), as a lane mask
+      const uint64_t pm = __ballot(part);
+      uint64_t live[kPop];
+  #pragma unroll
+      for (int k = 0; k < kPop; ++k) live[k] = __ballot(((vmask >> k) & 1u) != 0) & pm;
+  #pragma unroll 1
+      for (int slot = 0; slot < 4 * kPop; ++slot) {
+        uint64_t lv = live[0];
+  #pragma unroll
+        for (int k = 1; k < kPop; ++k)
+          if ((slot >> 2) == k) lv = live[k];
+        const float4 b0 = L.nrec[wv][grp][2 * slot];
+        const float4 b1 = L.nrec[wv][grp][2 * slot + 1];
+        const int32_t c = __float_as_int(b1.z);
+        bool ov = false;
+        if (__builtin_amdgcn_inverse_ballot_w64(lv))
+          ov = overlap6(qlo, qhi, b0.x, b0.y, b0.z, b0.w, b1.x, b1.y) &&
+               __float_as_int(b1.w) > qpos &&
+               !far6(qlp, qhm, b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, qr2);
+        // lane masks, kept in scalar registers: the lanes that overlap the child, the
+        // groups whose child is internal, the groups that enter it, the leaf candidates
+        const uint64_t m = __ballot(ov);
+        const uint64_t inner = __ballot(c >= 0);
+        const uint64_t enter = group_any<kGroup>(m) & inner;
+        const uint64_t ml = m & ~inner;
+        // internal child: the group enters it
+        if (__builtin_amdgcn_inverse_ballot_w64(enter)) {
+          if (sp < kGStack) {
+            if (gl == 0) L.stack[wv][grp][sp] = c;
+            ++sp;
+          } else if (gl == 0) {
+            atomicOr(&A.cnt->err, 2ull);
+          }
+        }
+        // leaf child: one candidate per overlapping lane
+        if (__builtin_amdgcn_inverse_ballot_w64(ml)) {
+          const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+              (uint32_t)(ml >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ml, 0u));
+          const int e = (head + qn + (int)below) & (kQueue - 1);
+          L.qlane[wv][e] = lane;
+          L.qprim[wv][e] = c & 0x7fffffff;
+        }
+        qn += __popcll(ml);
         __builtin_amdgcn_wave_barrier();
+        while (qn >= 64) {
+          drain(L, wv, gw, head, 64, kind, no, sidx, wrun, ntested, A);
+          head = (head + 64) & (kQueue - 1);
+          qn -= 64;
+          __builtin_amdgcn_wave_barrier();
+        }
       }
     }
-  }
-  if (qn > 0) drain(L, wv, gw, head, qn, kind, no, sidx, wrun, ntested, A);
-  if (no > 0) flush_out(L, wv, gw, no, sidx, wrun, A);
-  if (A.out && lane == 0) A.wtot[gw] = wrun;
-  unsigned long long nx = 0;
-  if (lane == 0) nx = atomicAdd(A.next, 1ull);
-  gw = __builtin_amdgcn_readfirstlane((int32_t)(gridDim.x * kWaves) + (int32_t)__shfl(nx, 0));
+    if (qn > 0) drain(L, wv, gw, head, qn, kind, no, sidx, wrun, ntested, A);
+    if (no > 0) flush_out(L, wv, gw, no, sidx, wrun, A);
+    if (A.out && lane == 0) A.wtot[gw] = wrun;
+    unsigned long long nx = 0;
+    if (lane == 0) nx = atomicAdd(A.next, 1ull);
+    gw = __builtin_amdgcn_readfirstlane((int32_t)(gridDim.x * kWaves) + (int32_t)__shfl(nx, 0));
   }
   // node records read by the wave's groups: the measure of the tree's quality
   unsigned long long nv = nvisit;
