@@ -931,6 +931,126 @@ static_assert(kMaxColors == kTailThreads, "one thread per colour bucket in the s
 // the row set). Then the colour buckets: counts, their exclusive scan to off
 // (kMaxColors + 1 entries), the rows in colour order to order; the colour count
 // goes to c->ncol.
+// The colouring rounds of the one-block colouring, from round 1, with the state of
+// each vertex slot in LDS: kW colour words (64 colours each) per slot. A pick beyond
+// kW words sets *s_over and abandons the rounds.
+template <int kW>
+__device__ __forceinline__ void lds_rounds(const PcArgs& a, int32_t nrows, uint64_t tmax,
+                                           unsigned* s_unc, unsigned long long (*s_mask)[kW],
+                                           unsigned long long (*s_claim)[kW],
+                                           unsigned long long (*s_clash)[kW], int32_t* s_live,
+                                           int32_t* s_next, int32_t* s_ncol, int32_t* s_over,
+                                           const uint64_t (&hk)[kSmallPer],
+                                           const int32_t (&lid)[kSmallPer][4],
+                                           int32_t (&fails)[kSmallPer], int32_t (&pick)[kSmallPer],
+                                           int32_t (&col)[kSmallPer]) {
+  const int tid = threadIdx.x;
+  const int W = (a.maxc + 63) / 64;
+  for (uint64_t t = 1; *s_live > 0; ++t) {
+    if (t > tmax) {
+      if (tid == 0) atomicOr(&a.c->err, 1ull);
+      break;
+    }
+    unsigned live = 0;
+#pragma unroll
+    for (int k = 0; k < kSmallPer; ++k) {
+      if (tid + k * kTailThreads >= nrows || col[k] >= 0) continue;
+      live |= 1u << k;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (lid[k][q] >= 0) atomicAdd(&s_unc[lid[k][q]], 1u);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSmallPer; ++k) {
+      if (!(live & (1u << k))) continue;
+      unsigned long long m = 1;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (lid[k][q] >= 0 && (unsigned long long)s_unc[lid[k][q]] > m) m = s_unc[lid[k][q]];
+      m += (unsigned long long)fails[k];
+      unsigned long long want = mix64(hk[k] + t * kPhi) % m;
+      int c = -1;
+      bool over = false;
+      for (int wd = 0; wd < W && c < 0; ++wd) {
+        if (wd >= kW) {
+          over = true;
+          break;
+        }
+        unsigned long long used = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (lid[k][q] >= 0) used |= s_mask[lid[k][q]][wd];
+        unsigned long long fr = ~used;
+        const int lim = a.maxc - 64 * wd;
+        if (lim < 64) fr &= (1ull << lim) - 1ull;
+        const unsigned long long cnt = (unsigned long long)__popcll(fr);
+        if (want >= cnt) {
+          want -= cnt;
+          continue;
+        }
+        for (unsigned long long z = 0; z < want; ++z) fr &= fr - 1ull;
+        c = 64 * wd + (__ffsll((long long)fr) - 1);
+      }
+      if (over) {
+        *s_over = 1;
+        c = 0;  // the round is abandoned
+      } else if (c < 0) {
+        atomicOr(&a.c->err, 1ull);
+        c = 0;
+      }
+      pick[k] = c;
+      const unsigned long long bit = 1ull << (c % 64);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (lid[k][q] < 0) continue;
+        const unsigned long long old = atomicOr(&s_claim[lid[k][q]][c / 64], bit);
+        if (old & bit) atomicOr(&s_clash[lid[k][q]][c / 64], bit);
+      }
+    }
+    __syncthreads();
+    if (*s_over) break;
+#pragma unroll
+    for (int k = 0; k < kSmallPer; ++k) {
+      if (!(live & (1u << k))) continue;
+      const int c = pick[k];
+      const unsigned long long bit = 1ull << (c % 64);
+      bool clash = false;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (lid[k][q] >= 0 && (s_clash[lid[k][q]][c / 64] & bit)) clash = true;
+      if (clash) {
+        fails[k] += 1;
+        atomicAdd(s_next, 1);
+        continue;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (lid[k][q] >= 0) atomicOr(&s_mask[lid[k][q]][c / 64], bit);
+      col[k] = c;
+      atomicMax(s_ncol, c + 1);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSmallPer; ++k) {
+      if (!(live & (1u << k))) continue;
+      const int wd = pick[k] / 64;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (lid[k][q] < 0) continue;
+        s_unc[lid[k][q]] = 0u;
+        s_claim[lid[k][q]][wd] = 0ull;
+        s_clash[lid[k][q]][wd] = 0ull;
+      }
+    }
+    if (tid == 0) {
+      *s_live = *s_next;
+      *s_next = 0;
+    }
+    __syncthreads();
+  }
+}
+
 constexpr int kHashBits = 13, kHashSize = 1 << kHashBits;
 // probes before a vertex gives up its place (at most kLocCap1 = kHashSize / 2 vertices
 // fit the LDS state, so a table that holds them is at most half full)
@@ -1030,110 +1150,36 @@ __global__ void __launch_bounds__(kTailThreads) k_pc_small(PcArgs a, int32_t nro
       for (int wd = 0; wd < kLocWords; ++wd) s_mask[l][wd] = s_claim[l][wd] = s_clash[l][wd] = 0ull;
     }
   __syncthreads();
-  const int W = (a.maxc + 63) / 64;
   if (in_lds) {
-    for (uint64_t t = 1; s_live > 0; ++t) {
-      if (t > tmax) {
-        if (tid == 0) atomicOr(&a.c->err, 1ull);
-        break;
-      }
-      unsigned live = 0;
-#pragma unroll
-      for (int k = 0; k < kSmallPer; ++k) {
-        if (tid + k * kTailThreads >= nrows || col[k] >= 0) continue;
-        live |= 1u << k;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (lid[k][q] >= 0) atomicAdd(&s_unc[lid[k][q]], 1u);
-      }
+    lds_rounds<kLocWords>(a, nrows, tmax, s_unc, s_mask, s_claim, s_clash, &s_live, &s_next,
+                          &s_ncol, &s_over, hk, lid, fails, pick, col);
+    // more colours than one word holds: the rounds start again from round 1 with two
+    // words per slot in the same LDS when the slots fit (half as many)
+    if (kLocWords == 1 && s_over && s_nloc <= kLocCap / 2) {
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < kSmallPer; ++k) {
-        if (!(live & (1u << k))) continue;
-        unsigned long long m = 1;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (lid[k][q] >= 0 && (unsigned long long)s_unc[lid[k][q]] > m) m = s_unc[lid[k][q]];
-        m += (unsigned long long)fails[k];
-        unsigned long long want = mix64(hk[k] + t * kPhi) % m;
-        int c = -1;
-        bool over = false;
-        for (int wd = 0; wd < W && c < 0; ++wd) {
-          if (wd >= kLocWords) {
-            over = true;
-            break;
-          }
-          unsigned long long used = 0;
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            if (lid[k][q] >= 0) used |= s_mask[lid[k][q]][wd];
-          unsigned long long fr = ~used;
-          const int lim = a.maxc - 64 * wd;
-          if (lim < 64) fr &= (1ull << lim) - 1ull;
-          const unsigned long long cnt = (unsigned long long)__popcll(fr);
-          if (want >= cnt) {
-            want -= cnt;
-            continue;
-          }
-          for (unsigned long long z = 0; z < want; ++z) fr &= fr - 1ull;
-          c = 64 * wd + (__ffsll((long long)fr) - 1);
-        }
-        if (over) {
-          s_over = 1;
-          c = 0;  // the round is abandoned
-        } else if (c < 0) {
-          atomicOr(&a.c->err, 1ull);
-          c = 0;
-        }
-        pick[k] = c;
-        const unsigned long long bit = 1ull << (c % 64);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (lid[k][q] < 0) continue;
-          const unsigned long long old = atomicOr(&s_claim[lid[k][q]][c / 64], bit);
-          if (old & bit) atomicOr(&s_clash[lid[k][q]][c / 64], bit);
-        }
+        col[k] = -1;
+        fails[k] = 0;
+        pick[k] = 0;
+      }
+      auto m2 = reinterpret_cast<unsigned long long(*)[2]>(&s_mask[0][0]);
+      auto c2 = reinterpret_cast<unsigned long long(*)[2]>(&s_claim[0][0]);
+      auto k2 = reinterpret_cast<unsigned long long(*)[2]>(&s_clash[0][0]);
+      for (int l = tid; l < s_nloc; l += kTailThreads) {
+        s_unc[l] = 0u;
+        m2[l][0] = m2[l][1] = c2[l][0] = c2[l][1] = k2[l][0] = k2[l][1] = 0ull;
       }
       __syncthreads();
-      if (s_over) break;
-#pragma unroll
-      for (int k = 0; k < kSmallPer; ++k) {
-        if (!(live & (1u << k))) continue;
-        const int c = pick[k];
-        const unsigned long long bit = 1ull << (c % 64);
-        bool clash = false;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (lid[k][q] >= 0 && (s_clash[lid[k][q]][c / 64] & bit)) clash = true;
-        if (clash) {
-          fails[k] += 1;
-          atomicAdd(&s_next, 1);
-          continue;
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (lid[k][q] >= 0) atomicOr(&s_mask[lid[k][q]][c / 64], bit);
-        col[k] = c;
-        atomicMax(&s_ncol, c + 1);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < kSmallPer; ++k) {
-        if (!(live & (1u << k))) continue;
-        const int wd = pick[k] / 64;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (lid[k][q] < 0) continue;
-          s_unc[lid[k][q]] = 0u;
-          s_claim[lid[k][q]][wd] = 0ull;
-          s_clash[lid[k][q]][wd] = 0ull;
-        }
-      }
       if (tid == 0) {
-        s_live = s_next;
+        s_live = nrows;
         s_next = 0;
+        s_ncol = 0;
+        s_over = 0;
       }
       __syncthreads();
+      lds_rounds<2>(a, nrows, tmax, s_unc, m2, c2, k2, &s_live, &s_next, &s_ncol, &s_over, hk,
+                    lid, fails, pick, col);
     }
   }
   const bool global_rounds = !in_lds || s_over;
