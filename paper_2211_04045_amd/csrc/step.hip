@@ -911,9 +911,10 @@ __global__ void __launch_bounds__(kTailThreads) k_pc_tail(PcArgs a, int32_t* la,
 
 constexpr int kSmallPer = kSmallRows / kTailThreads;  // rows per thread
 // LDS layouts of the one-block colouring: kLocWords colour words per vertex (colours
-// below 64 kLocWords) for at most kLocCap distinct free vertices. One word holds 4096
-// vertices (about 116 KB of LDS), two words 2944 (about 154 KB; a block may take up
-// to 160 KB on gfx950).
+// below 64 kLocWords) for at most kLocCap distinct free vertices: one word for 4096
+// vertices, two words for 2944. The colour words are sized for the larger of the two
+// (the one-word kernel can start again with two words): about 158 KB of LDS with the
+// rest of the block's state, within the 160 KB a block may take on gfx950.
 constexpr int kLocCap2 = 2944;
 static_assert(kSmallRows % kTailThreads == 0, "whole rows per thread");
 static_assert(kMaxColors == kTailThreads, "one thread per colour bucket in the scan");
@@ -1061,18 +1062,22 @@ __global__ void __launch_bounds__(kTailThreads) k_pc_small(PcArgs a, int32_t nro
                                                            int32_t* __restrict__ order,
                                                            int32_t* __restrict__ off,
                                                            uint64_t tmax) {
-  __shared__ unsigned s_unc[kLocCap];
-  __shared__ unsigned long long s_mask[kLocCap][kLocWords];
-  __shared__ unsigned long long s_claim[kLocCap][kLocWords];
-  __shared__ unsigned long long s_clash[kLocCap][kLocWords];
+  // the colour words of the slots, sized for either layout (kLocCap slots of kLocWords
+  // words, or kLocCap2 slots of two words for a restart)
+  constexpr int kWordsMax = kLocCap * kLocWords > 2 * kLocCap2 ? kLocCap * kLocWords : 2 * kLocCap2;
+  __shared__ unsigned s_unc[kLocCap > kLocCap2 ? kLocCap : kLocCap2];
+  __shared__ unsigned long long s_maskw[kWordsMax], s_claimw[kWordsMax], s_clashw[kWordsMax];
+  auto s_mask = reinterpret_cast<unsigned long long(*)[kLocWords]>(s_maskw);
+  auto s_claim = reinterpret_cast<unsigned long long(*)[kLocWords]>(s_claimw);
+  auto s_clash = reinterpret_cast<unsigned long long(*)[kLocWords]>(s_clashw);
   __shared__ int32_t s_cnt[kMaxColors];
   __shared__ int32_t s_wsum[kTailThreads / 64];
   __shared__ int32_t s_nloc, s_live, s_next, s_ncol, s_over, ncur, nnext;
-  static_assert(sizeof(s_claim) >= sizeof(int32_t) * kHashSize &&
-                    sizeof(s_clash) >= sizeof(int32_t) * kHashSize,
+  static_assert(sizeof(s_claimw) >= sizeof(int32_t) * kHashSize &&
+                    sizeof(s_clashw) >= sizeof(int32_t) * kHashSize,
                 "the vertex table fits the claim and clash words");
-  int32_t* const hkey = reinterpret_cast<int32_t*>(&s_claim[0][0]);   // vertex id, -1: empty
-  int32_t* const hslot = reinterpret_cast<int32_t*>(&s_clash[0][0]);  // its slot
+  int32_t* const hkey = reinterpret_cast<int32_t*>(s_claimw);   // vertex id, -1: empty
+  int32_t* const hslot = reinterpret_cast<int32_t*>(s_clashw);  // its slot
   const int tid = threadIdx.x;
   if (tid == 0) {
     s_nloc = 0;
@@ -1154,8 +1159,8 @@ __global__ void __launch_bounds__(kTailThreads) k_pc_small(PcArgs a, int32_t nro
     lds_rounds<kLocWords>(a, nrows, tmax, s_unc, s_mask, s_claim, s_clash, &s_live, &s_next,
                           &s_ncol, &s_over, hk, lid, fails, pick, col);
     // more colours than one word holds: the rounds start again from round 1 with two
-    // words per slot in the same LDS when the slots fit (half as many)
-    if (kLocWords == 1 && s_over && s_nloc <= kLocCap / 2) {
+    // words per slot in the same LDS when the slots fit (kLocCap2 of them)
+    if (kLocWords == 1 && s_over && s_nloc <= kLocCap2) {
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < kSmallPer; ++k) {
@@ -1163,9 +1168,9 @@ __global__ void __launch_bounds__(kTailThreads) k_pc_small(PcArgs a, int32_t nro
         fails[k] = 0;
         pick[k] = 0;
       }
-      auto m2 = reinterpret_cast<unsigned long long(*)[2]>(&s_mask[0][0]);
-      auto c2 = reinterpret_cast<unsigned long long(*)[2]>(&s_claim[0][0]);
-      auto k2 = reinterpret_cast<unsigned long long(*)[2]>(&s_clash[0][0]);
+      auto m2 = reinterpret_cast<unsigned long long(*)[2]>(s_maskw);
+      auto c2 = reinterpret_cast<unsigned long long(*)[2]>(s_claimw);
+      auto k2 = reinterpret_cast<unsigned long long(*)[2]>(s_clashw);
       for (int l = tid; l < s_nloc; l += kTailThreads) {
         s_unc[l] = 0u;
         m2[l][0] = m2[l][1] = c2[l][0] = c2[l][1] = k2[l][0] = k2[l][1] = 0ull;
